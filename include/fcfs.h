@@ -1,0 +1,183 @@
+/*
+ * fcfs.h -- C ABI of the MI355X (gfx950) library for the continuous Fourier
+ * series (CFS) of rectilinear lattice polygons, after Scheibler, Hurley and
+ * Chebira, "Fast Continuous Haar and Fourier Transforms of Rectilinear
+ * Polygons from VLSI Layouts".
+ *
+ * The CFS coefficient over a T x T tile (Sec. II-C; inner product of
+ * Sec. III-A with the orthonormal Fourier basis) is
+ *
+ *     F[k,l] = (1/T) * integral of f(x,y) e^{-j 2 pi (k x + l y) / T} dx dy,
+ *
+ * f being the sum of the polygons' indicators (Sec. III-A, signal model).
+ * Prop. 3 (Sec. III-C1) gives it in closed form from the vertices.  The
+ * library uses the equivalent signed-corner form: every vertex v is an
+ * endpoint of exactly one horizontal edge; s_v = +1 if that edge ends at v in
+ * clockwise loop order and -1 if it starts there (the +1/-1 entries of the
+ * sparse image of Alg. 2, lines building V^{KL}).  With e(t) = e^{-j 2 pi t/T}:
+ *
+ *     F[0,0] = (1/T)            sum_v s_v x_v y_v        (area / T; Step 1)
+ *     F[k,0] = j/(2 pi k)       sum_v s_v y_v e(k x_v)   (Step 2)
+ *     F[0,l] = j/(2 pi l)       sum_v s_v x_v e(l y_v)   (Step 3)
+ *     F[k,l] = -T/(4 pi^2 k l)  sum_v s_v e(k x_v) e(l y_v)   (Step 4)
+ *
+ * Conventions shared by every entry point:
+ *  - Ownership: the caller owns every data buffer and every workspace; the
+ *    handle owns only its constant twiddle tables and batch plans.
+ *  - Pointers marked (device) are device memory on the handle's device;
+ *    (host) pointers are ordinary host memory.
+ *  - Execution: device work is enqueued on the handle's stream and the call
+ *    returns without synchronising.  A fault on the device surfaces as
+ *    FCFS_ERR_DEVICE on a later call.
+ *  - Errors: a negative status; outputs are then unspecified.
+ *    fcfs_last_error() gives a human-readable detail.
+ *  - The device path trusts the corner data it is given: s_v in {+1,-1},
+ *    corners polygon-contiguous (accuracy depends on it), |x|,|y| < 2^30.
+ *  - The tile period T is a power of two in [2, 8192]; K, L >= 0.
+ *  - Threading: one handle per host thread.
+ */
+#ifndef FCFS_H_
+#define FCFS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FCFS_OK = 0,
+  FCFS_ERR_INVALID_ARG = -1,
+  FCFS_ERR_NOT_RECTILINEAR = -2,
+  FCFS_ERR_RANGE = -3,
+  FCFS_ERR_UNSUPPORTED = -4,
+  FCFS_ERR_WORKSPACE = -5,
+  FCFS_ERR_DEVICE = -6,
+  FCFS_ERR_NO_MEMORY = -7
+} fcfs_status;
+
+/* Arithmetic of the vertex contraction (the F[k,l] sums, Step 4).  Phases,
+ * the area and the axis sums are exact integer / FP64 in every mode.
+ *   FCFS_FP32        FP32 twiddles, FP32 MFMA products, FP32 accumulation.
+ *   FCFS_SPLIT_BF16  twiddle w = hi + lo with hi, lo bfloat16 (round to
+ *                    nearest even); hi*hi' + hi*lo' + lo*hi' on bf16 MFMA,
+ *                    FP32 accumulation.
+ *   FCFS_SPLIT_FP16  the same with binary16 hi, lo. */
+typedef enum { FCFS_FP32 = 0, FCFS_SPLIT_BF16 = 1, FCFS_SPLIT_FP16 = 2 } fcfs_precision;
+
+typedef struct fcfs_handle fcfs_handle;
+typedef struct fcfs_plan fcfs_plan;
+
+/* One clip: a signed corner list (the concatenated sparse lists of Alg. 2 for
+ * all polygons of the tile, Sec. III-C1 "multiple polygons") and its output. */
+typedef struct {
+  const int32_t *x;  /* (device) [V] corner abscissae                        */
+  const int32_t *y;  /* (device) [V] corner ordinates                        */
+  const int8_t *s;   /* (device) [V] corner signs, +1 or -1                  */
+  int64_t V;         /* number of corners, >= 0                              */
+  int32_t T;         /* tile period, power of two in [2, 8192]               */
+  int32_t K, L;      /* cut-offs: |k| <= K, |l| <= L                          */
+  float *F;          /* (device) out: (2K+1)*(2L+1) complex64 as interleaved
+                        (re, im) floats, k-major: F[(k+K)*(2L+1) + (l+L)]     */
+  int64_t *area;     /* (device) out: exact sum_v s_v x_v y_v (= area), or NULL */
+} fcfs_clip;
+
+/* Creates a handle on `device`, enqueuing on `hip_stream` (a hipStream_t; NULL
+ * = the device's null stream).  Builds the twiddle tables of Step 4 once:
+ * e^{j 2 pi p / 8192}, p = 0..8191, in FP64, FP32 and bf16/fp16 hi+lo. */
+fcfs_status fcfs_create(fcfs_handle **h, int device, void *hip_stream);
+fcfs_status fcfs_destroy(fcfs_handle *h);
+fcfs_status fcfs_set_stream(fcfs_handle *h, void *hip_stream);
+
+/* (host) Polygon loops -> signed corner list and edge map.
+ * xy: [n_vertices][2] lattice coordinates; loop_off: [n_loops+1] offsets,
+ * loop m = vertices loop_off[m] .. loop_off[m+1]-1 (Sec. II-A2: ordered
+ * vertices of a rectilinear polygon).  Validates: >= 4 and an even number of
+ * vertices per loop, every edge horizontal or vertical with nonzero length,
+ * edges alternating, nonzero area.  A counter-clockwise loop is taken as its
+ * clockwise reversal (its signs are negated).
+ * Outputs (host, caller-allocated, [n_vertices] each, any may be NULL):
+ *   x, y  copies of the coordinates, s the corner signs,
+ *   hedge[v] / vedge[v] the index of the horizontal / vertical edge at v,
+ *   edge e joining vertex e to the next vertex of its loop.
+ * Returns FCFS_ERR_NOT_RECTILINEAR or FCFS_ERR_RANGE on invalid loops. */
+fcfs_status fcfs_loops_to_corners(const int32_t *xy, const int64_t *loop_off, int64_t n_loops,
+                                  int32_t *x, int32_t *y, int8_t *s, int64_t *hedge,
+                                  int64_t *vedge);
+
+/* Workspace (device bytes) that fcfs_forward (adjoint = 0) or fcfs_adjoint
+ * (adjoint = 1) needs for clip `c` at precision `p`.  Depends only on V, T, K,
+ * L and p.  Pointers in `c` are not read. */
+fcfs_status fcfs_workspace_size(const fcfs_clip *c, fcfs_precision p, int adjoint,
+                                size_t *bytes);
+
+/* Forward transform (Prop. 3 / Alg. 2 for one tile): writes c->F and
+ * c->area.  ws: (device) workspace of at least fcfs_workspace_size bytes,
+ * 256-byte aligned.  Steps enqueued: pre-pass (phase reduction, area),
+ * axis sums (FP64), vertex contraction on MFMA, epilogue. */
+fcfs_status fcfs_forward(fcfs_handle *h, const fcfs_clip *c, fcfs_precision p, void *ws,
+                         size_t ws_bytes);
+
+/* Adjoint of fcfs_forward with respect to the corner coordinates (the
+ * derivative of the four closed forms of Prop. 3 in x_v and y_v).
+ * grad_F: (device) cotangent, same layout as c->F, holding
+ * dLoss/dRe F + j dLoss/dIm F.  Writes (device) gx[V] = dLoss/dx_v and
+ * gy[V] = dLoss/dy_v.  c->F and c->area are not touched. */
+fcfs_status fcfs_adjoint(fcfs_handle *h, const fcfs_clip *c, const float *grad_F, float *gx,
+                         float *gy, fcfs_precision p, void *ws, size_t ws_bytes);
+
+/* Edge-offset gradient: a shift of edge e moves both of its endpoints (along
+ * x for a vertical edge, along y for a horizontal one), so
+ * g_edge[e] = sum of gx (vertical) or gy (horizontal) over the two corners of
+ * e.  hedge/vedge: (device) [V] maps from fcfs_loops_to_corners; gx, gy:
+ * (device) [V]; g_edge: (device) out [E]. */
+fcfs_status fcfs_edge_grad(fcfs_handle *h, const float *gx, const float *gy,
+                           const int64_t *hedge, const int64_t *vedge, int64_t V, int64_t E,
+                           float *g_edge);
+
+/* Batched forward: n clips (each with its own V, T, K, L and outputs) in one
+ * persistent contraction launch.  The first call with *plan == NULL builds a
+ * plan (work list, tile shapes) and captures the enqueued sequence in a
+ * hipGraph; later calls with the same plan and the same clip array contents
+ * replay the graph.  ws: (device) workspace of at least
+ * fcfs_batch_workspace_size bytes. */
+fcfs_status fcfs_batch_workspace_size(const fcfs_clip *c, int32_t n, fcfs_precision p,
+                                      size_t *bytes);
+fcfs_status fcfs_forward_batch(fcfs_handle *h, const fcfs_clip *c, int32_t n, fcfs_precision p,
+                               void *ws, size_t ws_bytes, fcfs_plan **plan);
+fcfs_status fcfs_plan_destroy(fcfs_plan *plan);
+
+/* Debug export of the exact integer phase indices of Step 4:
+ * p[i*V + v] = ((k0 + i) * x_v) mod T for i in [0, nk) (axis = 0), or with
+ * y_v (axis = 1).  p: (device) out [nk][V] int32. */
+fcfs_status fcfs_debug_phases(fcfs_handle *h, const fcfs_clip *c, int32_t axis, int32_t k0,
+                              int32_t nk, int32_t *p);
+
+/* Times candidate tile shapes of the contraction on synthetic corners and
+ * stores the fastest per (precision, K-bucket, V-bucket) in the handle; with
+ * cache_path != NULL the table is also written there as JSON and read back
+ * by fcfs_create's successors through FCFS_AUTOTUNE_CACHE.  effort: 0..2. */
+fcfs_status fcfs_autotune(fcfs_handle *h, const char *cache_path, int effort);
+
+/* Tuning hooks.  fcfs_tile_variants fills wk[i], wl[i] (frequencies per
+ * wave in k and l of contraction tile variant i, for i < cap) and returns the
+ * number of variants.  fcfs_set_tile forces variant `variant` on every later
+ * call of this handle (-1 restores the automatic choice).
+ * fcfs_workspace_size_tile is fcfs_workspace_size (forward) for a given
+ * variant. */
+int32_t fcfs_tile_variants(int32_t *wk, int32_t *wl, int32_t cap);
+fcfs_status fcfs_set_tile(fcfs_handle *h, int32_t variant);
+fcfs_status fcfs_workspace_size_tile(const fcfs_clip *c, fcfs_precision p, int32_t tile,
+                                     size_t *bytes);
+
+const char *fcfs_status_string(fcfs_status s);
+/* Detail of the last failing call on this handle (or of the last failing
+ * handle-less call when h is NULL).  Never NULL. */
+const char *fcfs_last_error(fcfs_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FCFS_H_ */

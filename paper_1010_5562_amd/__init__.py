@@ -1,0 +1,206 @@
+"""Continuous Fourier series of rectilinear polygons on MI355X (gfx950).
+
+Thin Python binding over the C ABI of ``include/fcfs.h``: it only marshals
+arguments.  Every step of the transform runs in the HIP kernels of
+``libfcfs.so``; PyTorch supplies device memory and the current stream.
+Importing works without a GPU; every entry point that touches the device
+raises if the library or the device is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from ._lib import PRECISIONS, FcfsClip, FcfsError, check, load  # noqa: F401
+
+__all__ = [
+    "Handle", "FcfsError", "loops_to_corners", "forward", "workspace_size", "debug_phases",
+    "tile_variants", "PRECISIONS",
+]
+
+
+def _prec(p) -> int:
+    if isinstance(p, int):
+        return p
+    try:
+        return PRECISIONS[p]
+    except KeyError:
+        raise ValueError(f"unknown precision {p!r}; one of {sorted(PRECISIONS)}") from None
+
+
+def loops_to_corners(xy, off):
+    """Polygon loops -> (x, y, s, hedge, vedge) numpy arrays (host; a1 of the path).
+
+    ``xy``: (n, 2) int32 lattice coordinates, ``off``: (n_loops+1,) int64.
+    """
+    lib = load()
+    xy = np.ascontiguousarray(np.asarray(xy, dtype=np.int32).reshape(-1, 2))
+    off = np.ascontiguousarray(np.asarray(off, dtype=np.int64))
+    n = xy.shape[0]
+    x = np.empty(n, np.int32)
+    y = np.empty(n, np.int32)
+    s = np.empty(n, np.int8)
+    he = np.empty(n, np.int64)
+    ve = np.empty(n, np.int64)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    check(lib.fcfs_loops_to_corners(p(xy), p(off), off.size - 1, p(x), p(y), p(s), p(he), p(ve)))
+    return x, y, s, he, ve
+
+
+def tile_variants():
+    """[(wk, wl)] frequencies per wave of every contraction tile variant."""
+    lib = load()
+    n = lib.fcfs_tile_variants(None, None, 0)
+    wk = (ctypes.c_int32 * n)()
+    wl = (ctypes.c_int32 * n)()
+    lib.fcfs_tile_variants(wk, wl, n)
+    return list(zip(wk, wl))
+
+
+def _clip(x, y, s, V, T, K, L, F=None, area=None) -> FcfsClip:
+    c = FcfsClip()
+    c.x = x.data_ptr() if x is not None else None
+    c.y = y.data_ptr() if y is not None else None
+    c.s = s.data_ptr() if s is not None else None
+    c.V, c.T, c.K, c.L = int(V), int(T), int(K), int(L)
+    c.F = F.data_ptr() if F is not None else None
+    c.area = area.data_ptr() if area is not None else None
+    return c
+
+
+def workspace_size(V: int, T: int, K: int, L: int, precision="bf16", adjoint: bool = False,
+                   tile: int | None = None) -> int:
+    lib = load()
+    c = _clip(None, None, None, V, T, K, L)
+    n = ctypes.c_size_t(0)
+    if tile is None:
+        check(lib.fcfs_workspace_size(ctypes.byref(c), _prec(precision), int(adjoint),
+                                      ctypes.byref(n)))
+    else:
+        check(lib.fcfs_workspace_size_tile(ctypes.byref(c), _prec(precision), int(tile),
+                                           ctypes.byref(n)))
+    return int(n.value)
+
+
+class Handle:
+    """Owns an ``fcfs_handle`` (twiddle tables) on one device."""
+
+    def __init__(self, device=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("paper_1010_5562_amd needs a ROCm GPU; none is visible")
+        self.lib = load()
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.device = dev
+        self._h = ctypes.c_void_p()
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        check(self.lib.fcfs_create(ctypes.byref(self._h), dev.index, ctypes.c_void_p(stream)))
+        self._ws = None
+
+    def close(self):
+        if self._h:
+            self.lib.fcfs_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def sync_stream(self):
+        import torch
+
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        check(self.lib.fcfs_set_stream(self._h, ctypes.c_void_p(stream)), self._h)
+
+    def set_tile(self, variant: int = -1):
+        check(self.lib.fcfs_set_tile(self._h, int(variant)), self._h)
+
+    def workspace(self, nbytes: int):
+        """A cached device workspace of at least ``nbytes`` (256-byte aligned)."""
+        import torch
+
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+
+_default = {}
+
+
+def default_handle(device=None) -> Handle:
+    import torch
+
+    idx = torch.cuda.current_device() if device is None else torch.device(device).index
+    h = _default.get(idx)
+    if h is None:
+        h = _default[idx] = Handle(idx)
+    return h
+
+
+def _corners_on(dev, x, y, s):
+    import torch
+
+    x = torch.as_tensor(x, dtype=torch.int32).to(dev).contiguous()
+    y = torch.as_tensor(y, dtype=torch.int32).to(dev).contiguous()
+    s = torch.as_tensor(s, dtype=torch.int8).to(dev).contiguous()
+    if not (x.numel() == y.numel() == s.numel()):
+        raise ValueError("x, y, s differ in length")
+    return x, y, s
+
+
+def forward(x, y, s, T: int, K: int, L: int | None = None, precision="bf16", handle=None,
+            out=None, area_out=None, tile: int | None = None):
+    """CFS coefficients F[k, l], |k| <= K, |l| <= L, of a signed corner list.
+
+    Returns ``(F, area)``: F a (2K+1, 2L+1) complex64 tensor indexed
+    [k + K, l + L], area a 1-element int64 tensor (exact sum s x y).
+    """
+    import torch
+
+    L = K if L is None else L
+    h = handle or default_handle()
+    h.sync_stream()
+    x, y, s = _corners_on(h.device, x, y, s)
+    V = x.numel()
+    F = out if out is not None else torch.empty((2 * K + 1, 2 * L + 1), dtype=torch.complex64,
+                                                device=h.device)
+    if F.dtype != torch.complex64 or F.numel() != (2 * K + 1) * (2 * L + 1) or not F.is_contiguous():
+        raise ValueError("out must be a contiguous complex64 tensor of (2K+1)(2L+1) entries")
+    area = area_out if area_out is not None else torch.empty(1, dtype=torch.int64, device=h.device)
+    if tile is not None:
+        h.set_tile(tile)
+    try:
+        nbytes = workspace_size(V, T, K, L, precision, tile=tile)
+        ws = h.workspace(nbytes)
+        c = _clip(x, y, s, V, T, K, L, F, area)
+        check(h.lib.fcfs_forward(h.ptr, ctypes.byref(c), _prec(precision),
+                                 ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel())),
+              h.ptr)
+    finally:
+        if tile is not None:
+            h.set_tile(-1)
+    return F, area
+
+
+def debug_phases(x, y, s, T: int, k0: int, nk: int, axis: int = 0, handle=None):
+    """Exact integer phases (k0+i) * x_v mod T (axis 0) or with y_v (axis 1),
+    as the contraction computes them; an (nk, V) int32 tensor."""
+    import torch
+
+    h = handle or default_handle()
+    h.sync_stream()
+    x, y, s = _corners_on(h.device, x, y, s)
+    V = x.numel()
+    p = torch.empty((nk, V), dtype=torch.int32, device=h.device)
+    c = _clip(x, y, s, V, T, 0, 0)
+    check(h.lib.fcfs_debug_phases(h.ptr, ctypes.byref(c), int(axis), int(k0), int(nk),
+                                  ctypes.c_void_p(p.data_ptr())), h.ptr)
+    return p

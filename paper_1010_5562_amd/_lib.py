@@ -1,0 +1,108 @@
+"""ctypes declarations of the C ABI in ``include/fcfs.h``.
+
+Loading fails loudly when ``libfcfs.so`` has not been built: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfcfs.so")
+
+FCFS_OK = 0
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
+
+STATUS_NAMES = {
+    0: "FCFS_OK",
+    -1: "FCFS_ERR_INVALID_ARG",
+    -2: "FCFS_ERR_NOT_RECTILINEAR",
+    -3: "FCFS_ERR_RANGE",
+    -4: "FCFS_ERR_UNSUPPORTED",
+    -5: "FCFS_ERR_WORKSPACE",
+    -6: "FCFS_ERR_DEVICE",
+    -7: "FCFS_ERR_NO_MEMORY",
+}
+
+# Every symbol include/fcfs.h declares.
+EXPORTS = (
+    "fcfs_create", "fcfs_destroy", "fcfs_set_stream", "fcfs_loops_to_corners",
+    "fcfs_workspace_size", "fcfs_forward", "fcfs_adjoint", "fcfs_edge_grad",
+    "fcfs_batch_workspace_size", "fcfs_forward_batch", "fcfs_plan_destroy",
+    "fcfs_debug_phases", "fcfs_autotune", "fcfs_tile_variants", "fcfs_set_tile",
+    "fcfs_workspace_size_tile", "fcfs_status_string", "fcfs_last_error",
+)
+
+
+class FcfsClip(ctypes.Structure):
+    _fields_ = [
+        ("x", ctypes.c_void_p),
+        ("y", ctypes.c_void_p),
+        ("s", ctypes.c_void_p),
+        ("V", ctypes.c_int64),
+        ("T", ctypes.c_int32),
+        ("K", ctypes.c_int32),
+        ("L", ctypes.c_int32),
+        ("F", ctypes.c_void_p),
+        ("area", ctypes.c_void_p),
+    ]
+
+
+class FcfsError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {detail}")
+        self.status = status
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build the HIP library first "
+            "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, c_int = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int
+    sz = ctypes.POINTER(ctypes.c_size_t)
+    clip_p = ctypes.POINTER(FcfsClip)
+    sig = {
+        "fcfs_create": [ctypes.POINTER(P), c_int, P],
+        "fcfs_destroy": [P],
+        "fcfs_set_stream": [P, P],
+        "fcfs_loops_to_corners": [P, P, i64, P, P, P, P, P],
+        "fcfs_workspace_size": [clip_p, c_int, c_int, sz],
+        "fcfs_workspace_size_tile": [clip_p, c_int, i32, sz],
+        "fcfs_forward": [P, clip_p, c_int, P, ctypes.c_size_t],
+        "fcfs_adjoint": [P, clip_p, P, P, P, c_int, P, ctypes.c_size_t],
+        "fcfs_edge_grad": [P, P, P, P, P, i64, i64, P],
+        "fcfs_batch_workspace_size": [clip_p, i32, c_int, sz],
+        "fcfs_forward_batch": [P, clip_p, i32, c_int, P, ctypes.c_size_t, ctypes.POINTER(P)],
+        "fcfs_plan_destroy": [P],
+        "fcfs_debug_phases": [P, clip_p, i32, i32, i32, P],
+        "fcfs_autotune": [P, ctypes.c_char_p, c_int],
+        "fcfs_set_tile": [P, i32],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = c_int
+    lib.fcfs_tile_variants.argtypes = [P, P, i32]
+    lib.fcfs_tile_variants.restype = i32
+    lib.fcfs_status_string.argtypes = [c_int]
+    lib.fcfs_status_string.restype = ctypes.c_char_p
+    lib.fcfs_last_error.argtypes = [P]
+    lib.fcfs_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def check(status: int, handle=None) -> None:
+    if status != FCFS_OK:
+        lib = load()
+        detail = lib.fcfs_last_error(handle).decode(errors="replace")
+        raise FcfsError(status, detail)

@@ -1,0 +1,513 @@
+// Host runtime and C ABI of the FCFS library: handle, twiddle tables, planner,
+// validation, loops -> corners canonicalisation and the entry points of
+// include/fcfs.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/fcfs.h"
+#include "fcfs_internal.h"
+
+using fcfs::FwdPlan;
+using fcfs::Tables;
+
+struct fcfs_handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  Tables tab;
+  int tile_override = -1;
+  std::string err;
+};
+
+namespace {
+
+std::mutex g_err_mu;
+std::string g_err;  // last error of a handle-less call
+
+fcfs_status fail(fcfs_handle *h, fcfs_status st, const std::string &msg) {
+  if (h) {
+    h->err = msg;
+  } else {
+    std::lock_guard<std::mutex> g(g_err_mu);
+    g_err = msg;
+  }
+  return st;
+}
+
+fcfs_status hip_fail(fcfs_handle *h, hipError_t e, const char *what) {
+  return fail(h, FCFS_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// ---------------------------------------------------------------------------
+// Twiddle tables: e^{j 2 pi p / N}, N = 8192, stored as (cos, sin).  The first
+// octant comes from libm in FP64; every other entry follows from exact
+// symmetries, so entry p + N/2 is exactly the negation of entry p (the sign
+// of a corner is applied by that shift).
+// ---------------------------------------------------------------------------
+void twiddles64(std::vector<double> &c, std::vector<double> &s) {
+  const int N = fcfs::kTabN, Q = N / 4, O = N / 8;
+  std::vector<double> c0(Q + 1), s0(Q + 1);
+  for (int q = 0; q <= O; ++q) {
+    const double a = 2.0 * M_PI * (double)q / (double)N;
+    c0[q] = std::cos(a);
+    s0[q] = std::sin(a);
+  }
+  for (int q = O + 1; q <= Q; ++q) {
+    c0[q] = s0[Q - q];
+    s0[q] = c0[Q - q];
+  }
+  c.resize(N);
+  s.resize(N);
+  for (int p = 0; p < N; ++p) {
+    const int quad = p / Q, q = p % Q;
+    double cv, sv;
+    switch (quad) {
+      case 0: cv = c0[q]; sv = s0[q]; break;
+      case 1: cv = -s0[q]; sv = c0[q]; break;
+      case 2: cv = -c0[q]; sv = -s0[q]; break;
+      default: cv = s0[q]; sv = -c0[q]; break;
+    }
+    c[p] = cv == 0.0 ? 0.0 : cv;  // no negative zeros
+    s[p] = sv == 0.0 ? 0.0 : sv;
+  }
+}
+
+// Round to nearest even on a grid of spacing 2^e (exact in FP64).
+double rne_grid(double x, int e) { return std::nearbyint(std::ldexp(x, -e)) * std::ldexp(1.0, e); }
+
+double rne_bf16(double x) {
+  if (x == 0.0) return 0.0;
+  return rne_grid(x, std::ilogb(x) - 7);  // 8 significant bits
+}
+double rne_fp16(double x) {
+  if (x == 0.0) return 0.0;
+  int e = std::ilogb(x);
+  if (e < -14) e = -14;  // subnormal range: fixed spacing 2^-24
+  return rne_grid(x, e - 10);
+}
+uint32_t bf16_bits(double r) {
+  const float f = (float)r;  // exact: r has <= 8 significant bits
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return u >> 16;
+}
+uint32_t fp16_bits(double r) {
+  const _Float16 h = (_Float16)r;  // exact
+  uint16_t u;
+  std::memcpy(&u, &h, 2);
+  return u;
+}
+
+fcfs_status build_tables(fcfs_handle *h) {
+  std::vector<double> c, s;
+  twiddles64(c, s);
+  const int N = fcfs::kTabN, NE = fcfs::kTabEntries;
+  std::vector<double2> w64(N);
+  std::vector<float2> w32(NE);
+  std::vector<uint2> wb(NE), wh(NE);
+  for (int p = 0; p < N; ++p) {
+    w64[p] = make_double2(c[p], s[p]);
+    w32[p] = make_float2((float)c[p], (float)s[p]);
+    const double chb = rne_bf16(c[p]), shb = rne_bf16(s[p]);
+    const double clb = rne_bf16(c[p] - chb), slb = rne_bf16(s[p] - shb);
+    wb[p] = make_uint2(bf16_bits(chb) | bf16_bits(shb) << 16, bf16_bits(clb) | bf16_bits(slb) << 16);
+    const double chh = rne_fp16(c[p]), shh = rne_fp16(s[p]);
+    const double clh = rne_fp16(c[p] - chh), slh = rne_fp16(s[p] - shh);
+    wh[p] = make_uint2(fp16_bits(chh) | fp16_bits(shh) << 16, fp16_bits(clh) | fp16_bits(slh) << 16);
+  }
+  w32[N] = make_float2(0.f, 0.f);
+  wb[N] = make_uint2(0u, 0u);
+  wh[N] = make_uint2(0u, 0u);
+  hipError_t e;
+  if ((e = hipMalloc(&h->tab.w64, sizeof(double2) * N)) != hipSuccess) return hip_fail(h, e, "hipMalloc");
+  if ((e = hipMalloc(&h->tab.w32, sizeof(float2) * NE)) != hipSuccess) return hip_fail(h, e, "hipMalloc");
+  if ((e = hipMalloc(&h->tab.wbf16, sizeof(uint2) * NE)) != hipSuccess) return hip_fail(h, e, "hipMalloc");
+  if ((e = hipMalloc(&h->tab.wfp16, sizeof(uint2) * NE)) != hipSuccess) return hip_fail(h, e, "hipMalloc");
+  if ((e = hipMemcpy(h->tab.w64, w64.data(), sizeof(double2) * N, hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(h->tab.w32, w32.data(), sizeof(float2) * NE, hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(h->tab.wbf16, wb.data(), sizeof(uint2) * NE, hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(h->tab.wfp16, wh.data(), sizeof(uint2) * NE, hipMemcpyHostToDevice)))
+    return hip_fail(h, e, "hipMemcpy");
+  return FCFS_OK;
+}
+
+void free_tables(Tables &t) {
+  if (t.w64) (void)hipFree(t.w64);
+  if (t.w32) (void)hipFree(t.w32);
+  if (t.wbf16) (void)hipFree(t.wbf16);
+  if (t.wfp16) (void)hipFree(t.wfp16);
+  t = Tables();
+}
+
+// ---------------------------------------------------------------------------
+// Planner: launch geometry and workspace layout from (V, T, K, L, precision).
+// ---------------------------------------------------------------------------
+constexpr int kMaxFreq = 4095;  // |k|, |l| cut-off limit (phases stay below 2^29)
+constexpr int kTargetWG = 512;  // two contraction workgroups per CU on 256 CUs
+
+int default_tile(int prec, int K, int L) {
+  (void)prec;
+  (void)K;
+  (void)L;
+  return 0;
+}
+
+fcfs_status check_dims(fcfs_handle *h, int64_t V, int T, int K, int L, int prec) {
+  if (V < 0) return fail(h, FCFS_ERR_INVALID_ARG, "V < 0");
+  if (!is_pow2(T) || T < 2 || T > fcfs::kTabN)
+    return fail(h, FCFS_ERR_UNSUPPORTED, "T must be a power of two in [2, 8192]");
+  if (K < 0 || L < 0) return fail(h, FCFS_ERR_INVALID_ARG, "K and L must be >= 0");
+  if (K > kMaxFreq || L > kMaxFreq) return fail(h, FCFS_ERR_UNSUPPORTED, "K, L must be <= 4095");
+  if (prec < 0 || prec > 2) return fail(h, FCFS_ERR_INVALID_ARG, "unknown precision");
+  if (V > ((int64_t)1 << 34)) return fail(h, FCFS_ERR_UNSUPPORTED, "V too large");
+  return FCFS_OK;
+}
+
+fcfs_status make_plan(fcfs_handle *h, int64_t V, int T, int K, int L, int prec, int tile,
+                      FwdPlan *p) {
+  fcfs_status st = check_dims(h, V, T, K, L, prec);
+  if (st) return st;
+  FwdPlan q{};
+  q.prec = prec;
+  q.T = T;
+  q.K = K;
+  q.L = L;
+  q.V = V;
+  q.shift = fcfs::kTabBits - (int)std::lround(std::log2((double)T));
+  if (tile < 0) tile = default_tile(prec, K, L);
+  if (tile >= fcfs::n_tile_variants()) return fail(h, FCFS_ERR_INVALID_ARG, "unknown tile variant");
+  const fcfs::TileVariant &tv = fcfs::tile_variant(tile);
+  q.tile = tile;
+  q.wgk = 2 * tv.wk;
+  q.wgl = 2 * tv.wl;
+  q.kp = (int)round_up(K + 1, q.wgk);
+  q.lp = (int)round_up(L + 1, q.wgl);
+  q.tiles_k = q.kp / q.wgk;
+  q.tiles_l = q.lp / q.wgl;
+  const int64_t tiles = (int64_t)q.tiles_k * q.tiles_l;
+  int64_t ns = ceil_div(kTargetWG, tiles);
+  const int64_t ns_max = std::max<int64_t>(1, ceil_div(V, 512));
+  ns = std::max<int64_t>(1, std::min(ns, ns_max));
+  ns = std::min<int64_t>(ns, 65535);
+  q.nsplit = (int)ns;
+  q.chunk = std::max<int64_t>(16, round_up(ceil_div(std::max<int64_t>(V, 1), ns), 16));
+  q.vpad = q.chunk * q.nsplit;
+  q.pre_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(q.vpad, 256)));
+  const int fblocks = (int)(ceil_div(K, 256) + ceil_div(L, 256));
+  if (fblocks > 0 && V > 0) {
+    int64_t ac = std::max<int64_t>(1, ceil_div(1024, fblocks));
+    ac = std::min<int64_t>(ac, ceil_div(V, 256));
+    q.ax_chunk = round_up(ceil_div(V, ac), 256);
+    q.ax_chunks = (int)ceil_div(V, q.ax_chunk);
+  } else {
+    q.ax_chunk = 256;
+    q.ax_chunks = 1;
+  }
+  size_t off = 0;
+  q.off_packed = off;
+  off += align256(sizeof(uint2) * (size_t)q.vpad);
+  q.off_area = off;
+  off += align256(sizeof(unsigned long long) * (size_t)q.pre_blocks);
+  q.off_axis = off;
+  off += align256(sizeof(double2) * (size_t)q.ax_chunks * (size_t)std::max(1, K + L));
+  q.off_part = off;
+  off += align256(sizeof(float) * 4 * (size_t)q.nsplit * (size_t)q.kp * (size_t)q.lp);
+  q.bytes = off;
+  *p = q;
+  return FCFS_OK;
+}
+
+fcfs_status check_clip(fcfs_handle *h, const fcfs_clip *c, bool need_out) {
+  if (!c) return fail(h, FCFS_ERR_INVALID_ARG, "clip is NULL");
+  if (c->V > 0 && (!c->x || !c->y || !c->s))
+    return fail(h, FCFS_ERR_INVALID_ARG, "corner arrays are NULL");
+  if (need_out && !c->F) return fail(h, FCFS_ERR_INVALID_ARG, "output F is NULL");
+  return FCFS_OK;
+}
+
+fcfs_status check_ws(fcfs_handle *h, const FwdPlan &p, void *ws, size_t ws_bytes) {
+  if (ws_bytes < p.bytes)
+    return fail(h, FCFS_ERR_WORKSPACE,
+                "workspace too small: need " + std::to_string(p.bytes) + " bytes, got " +
+                    std::to_string(ws_bytes));
+  if (!ws) return fail(h, FCFS_ERR_WORKSPACE, "workspace is NULL");
+  if (((uintptr_t)ws & 255u) != 0) return fail(h, FCFS_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  return FCFS_OK;
+}
+
+fcfs_status enter(fcfs_handle *h) {
+  if (!h) return fail(nullptr, FCFS_ERR_INVALID_ARG, "handle is NULL");
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
+  e = hipPeekAtLastError();
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return hip_fail(h, e, "pending device error");
+  }
+  return FCFS_OK;
+}
+
+template <class T>
+T *ws_at(void *ws, size_t off) {
+  return (T *)((char *)ws + off);
+}
+
+fcfs_status run_forward(fcfs_handle *h, const fcfs_clip *c, const FwdPlan &p, void *ws) {
+  uint2 *packed = ws_at<uint2>(ws, p.off_packed);
+  auto *area_part = ws_at<unsigned long long>(ws, p.off_area);
+  auto *axis_part = ws_at<double2>(ws, p.off_axis);
+  float *part = ws_at<float>(ws, p.off_part);
+  hipError_t e;
+  if ((e = fcfs::launch_prepass(p, c->x, c->y, c->s, packed, area_part, h->stream)))
+    return hip_fail(h, e, "pre-pass launch");
+  if ((e = fcfs::launch_axis(p, c->x, c->y, c->s, packed, h->tab.w64, axis_part, h->stream)))
+    return hip_fail(h, e, "axis launch");
+  if (p.K > 0 && p.L > 0)
+    if ((e = fcfs::launch_contract(p, packed, h->tab, part, h->stream)))
+      return hip_fail(h, e, "contraction launch");
+  if ((e = fcfs::launch_epilogue(p, part, axis_part, area_part, c->F, c->area, h->stream)))
+    return hip_fail(h, e, "epilogue launch");
+  return FCFS_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *fcfs_status_string(fcfs_status s) {
+  switch (s) {
+    case FCFS_OK: return "ok";
+    case FCFS_ERR_INVALID_ARG: return "invalid argument";
+    case FCFS_ERR_NOT_RECTILINEAR: return "not a rectilinear polygon";
+    case FCFS_ERR_RANGE: return "value out of range";
+    case FCFS_ERR_UNSUPPORTED: return "unsupported";
+    case FCFS_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case FCFS_ERR_DEVICE: return "device error";
+    case FCFS_ERR_NO_MEMORY: return "out of memory";
+  }
+  return "unknown status";
+}
+
+const char *fcfs_last_error(fcfs_handle *h) {
+  if (h) return h->err.c_str();
+  std::lock_guard<std::mutex> g(g_err_mu);
+  static thread_local std::string copy;
+  copy = g_err;
+  return copy.c_str();
+}
+
+fcfs_status fcfs_create(fcfs_handle **out, int device, void *hip_stream) {
+  if (!out) return fail(nullptr, FCFS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDeviceCount");
+  if (device < 0 || device >= n) return fail(nullptr, FCFS_ERR_INVALID_ARG, "no such device");
+  if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+  fcfs_handle *h = new (std::nothrow) fcfs_handle();
+  if (!h) return fail(nullptr, FCFS_ERR_NO_MEMORY, "handle allocation");
+  h->device = device;
+  h->stream = (hipStream_t)hip_stream;
+  fcfs_status st = build_tables(h);
+  if (st) {
+    {
+      std::lock_guard<std::mutex> g(g_err_mu);
+      g_err = h->err;
+    }
+    free_tables(h->tab);
+    delete h;
+    return st;
+  }
+  *out = h;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_destroy(fcfs_handle *h) {
+  if (!h) return FCFS_OK;
+  (void)hipSetDevice(h->device);
+  free_tables(h->tab);
+  delete h;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_set_stream(fcfs_handle *h, void *hip_stream) {
+  if (!h) return fail(nullptr, FCFS_ERR_INVALID_ARG, "handle is NULL");
+  h->stream = (hipStream_t)hip_stream;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_set_tile(fcfs_handle *h, int32_t variant) {
+  if (!h) return fail(nullptr, FCFS_ERR_INVALID_ARG, "handle is NULL");
+  if (variant < -1 || variant >= fcfs::n_tile_variants())
+    return fail(h, FCFS_ERR_INVALID_ARG, "unknown tile variant");
+  h->tile_override = variant;
+  return FCFS_OK;
+}
+
+int32_t fcfs_tile_variants(int32_t *wk, int32_t *wl, int32_t cap) {
+  const int n = fcfs::n_tile_variants();
+  for (int i = 0; i < n && i < cap; ++i) {
+    if (wk) wk[i] = fcfs::tile_variant(i).wk;
+    if (wl) wl[i] = fcfs::tile_variant(i).wl;
+  }
+  return n;
+}
+
+fcfs_status fcfs_loops_to_corners(const int32_t *xy, const int64_t *loop_off, int64_t n_loops,
+                                  int32_t *x, int32_t *y, int8_t *s, int64_t *hedge,
+                                  int64_t *vedge) {
+  if (n_loops < 0 || !loop_off) return fail(nullptr, FCFS_ERR_INVALID_ARG, "bad loop offsets");
+  if (loop_off[0] != 0) return fail(nullptr, FCFS_ERR_INVALID_ARG, "loop_off[0] must be 0");
+  const int64_t nv = loop_off[n_loops];
+  if (nv > 0 && !xy) return fail(nullptr, FCFS_ERR_INVALID_ARG, "xy is NULL");
+  for (int64_t m = 0; m < n_loops; ++m) {
+    const int64_t b = loop_off[m], n = loop_off[m + 1] - b;
+    if (n < 4 || (n & 1))
+      return fail(nullptr, FCFS_ERR_NOT_RECTILINEAR,
+                  "loop " + std::to_string(m) + ": needs an even number (>= 4) of vertices");
+    // edge i: vertex i -> vertex i+1; horizontal iff the y's agree
+    int64_t area = 0;
+    bool first_h = false;
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t a = b + i, c = b + (i + 1) % n;
+      const int64_t xa = xy[2 * a], ya = xy[2 * a + 1], xc = xy[2 * c], yc = xy[2 * c + 1];
+      if (std::llabs(xa) >= (1ll << 30) || std::llabs(ya) >= (1ll << 30))
+        return fail(nullptr, FCFS_ERR_RANGE, "coordinate magnitude must be < 2^30");
+      const bool h = (ya == yc) && (xa != xc);
+      const bool v = (xa == xc) && (ya != yc);
+      if (!h && !v)
+        return fail(nullptr, FCFS_ERR_NOT_RECTILINEAR,
+                    "loop " + std::to_string(m) + ", edge " + std::to_string(i) +
+                        ": not axis-parallel or zero length");
+      if (i == 0) first_h = h;
+      if (((i & 1) == 0) != (h == first_h))
+        return fail(nullptr, FCFS_ERR_NOT_RECTILINEAR,
+                    "loop " + std::to_string(m) + ": edges do not alternate");
+      if (h) area += ya * (xc - xa);
+    }
+    if (area == 0) return fail(nullptr, FCFS_ERR_NOT_RECTILINEAR, "loop " + std::to_string(m) + ": zero area");
+    const int sigma = area > 0 ? 1 : -1;  // clockwise (y up) has positive area
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t v = b + i;
+      const int64_t prev = b + (i + n - 1) % n;  // edge ending at v
+      const int64_t next = v;                    // edge starting at v
+      const bool next_h = ((i & 1) == 0) == first_h;
+      if (x) x[v] = xy[2 * v];
+      if (y) y[v] = xy[2 * v + 1];
+      // s = +1 where v ends its horizontal edge, -1 where it starts it
+      // (clockwise); a counter-clockwise loop takes the opposite sign.
+      if (s) s[v] = (int8_t)(next_h ? -sigma : sigma);
+      if (hedge) hedge[v] = next_h ? next : prev;
+      if (vedge) vedge[v] = next_h ? prev : next;
+    }
+  }
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_workspace_size(const fcfs_clip *c, fcfs_precision p, int adjoint, size_t *bytes) {
+  if (!c || !bytes) return fail(nullptr, FCFS_ERR_INVALID_ARG, "NULL argument");
+  FwdPlan q;
+  fcfs_status st = make_plan(nullptr, c->V, c->T, c->K, c->L, (int)p, -1, &q);
+  if (st) return st;
+  *bytes = q.bytes;
+  if (adjoint) return fail(nullptr, FCFS_ERR_UNSUPPORTED, "adjoint not built");
+  return FCFS_OK;
+}
+
+// Workspace size for an explicit tile variant (autotuning and tests).
+fcfs_status fcfs_workspace_size_tile(const fcfs_clip *c, fcfs_precision p, int32_t tile,
+                                     size_t *bytes) {
+  if (!c || !bytes) return fail(nullptr, FCFS_ERR_INVALID_ARG, "NULL argument");
+  FwdPlan q;
+  fcfs_status st = make_plan(nullptr, c->V, c->T, c->K, c->L, (int)p, tile, &q);
+  if (st) return st;
+  *bytes = q.bytes;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_forward(fcfs_handle *h, const fcfs_clip *c, fcfs_precision p, void *ws,
+                         size_t ws_bytes) {
+  fcfs_status st = enter(h);
+  if (st) return st;
+  if ((st = check_clip(h, c, true))) return st;
+  FwdPlan q;
+  if ((st = make_plan(h, c->V, c->T, c->K, c->L, (int)p, h->tile_override, &q))) return st;
+  if ((st = check_ws(h, q, ws, ws_bytes))) return st;
+  return run_forward(h, c, q, ws);
+}
+
+fcfs_status fcfs_debug_phases(fcfs_handle *h, const fcfs_clip *c, int32_t axis, int32_t k0,
+                              int32_t nk, int32_t *p) {
+  fcfs_status st = enter(h);
+  if (st) return st;
+  if ((st = check_clip(h, c, false))) return st;
+  if (axis < 0 || axis > 1 || k0 < 0 || nk < 0 || k0 + nk > fcfs::kTabN || (nk > 0 && c->V > 0 && !p))
+    return fail(h, FCFS_ERR_INVALID_ARG, "bad phase range");
+  FwdPlan q;
+  if ((st = make_plan(h, c->V, c->T, 0, 0, 0, 0, &q))) return st;
+  void *tmp = nullptr;
+  const size_t nb = align256(sizeof(uint2) * (size_t)q.vpad) + align256(8 * (size_t)q.pre_blocks);
+  hipError_t e = hipMalloc(&tmp, nb);
+  if (e) return hip_fail(h, e, "hipMalloc");
+  uint2 *packed = (uint2 *)tmp;
+  auto *ap = ws_at<unsigned long long>(tmp, align256(sizeof(uint2) * (size_t)q.vpad));
+  if ((e = fcfs::launch_prepass(q, c->x, c->y, c->s, packed, ap, h->stream)) ||
+      (e = fcfs::launch_debug_phases(q, packed, axis, k0, nk, p, h->stream)) ||
+      (e = hipStreamSynchronize(h->stream))) {
+    (void)hipFree(tmp);
+    return hip_fail(h, e, "debug phases");
+  }
+  (void)hipFree(tmp);
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_adjoint(fcfs_handle *h, const fcfs_clip *c, const float *grad_F, float *gx,
+                         float *gy, fcfs_precision p, void *ws, size_t ws_bytes) {
+  (void)c; (void)grad_F; (void)gx; (void)gy; (void)p; (void)ws; (void)ws_bytes;
+  return fail(h, FCFS_ERR_UNSUPPORTED, "adjoint not built");
+}
+
+fcfs_status fcfs_edge_grad(fcfs_handle *h, const float *gx, const float *gy, const int64_t *hedge,
+                           const int64_t *vedge, int64_t V, int64_t E, float *g_edge) {
+  (void)gx; (void)gy; (void)hedge; (void)vedge; (void)V; (void)E; (void)g_edge;
+  return fail(h, FCFS_ERR_UNSUPPORTED, "edge gradient not built");
+}
+
+fcfs_status fcfs_batch_workspace_size(const fcfs_clip *c, int32_t n, fcfs_precision p,
+                                      size_t *bytes) {
+  (void)c; (void)n; (void)p; (void)bytes;
+  return fail(nullptr, FCFS_ERR_UNSUPPORTED, "batch not built");
+}
+
+fcfs_status fcfs_forward_batch(fcfs_handle *h, const fcfs_clip *c, int32_t n, fcfs_precision p,
+                               void *ws, size_t ws_bytes, fcfs_plan **plan) {
+  (void)c; (void)n; (void)p; (void)ws; (void)ws_bytes; (void)plan;
+  return fail(h, FCFS_ERR_UNSUPPORTED, "batch not built");
+}
+
+fcfs_status fcfs_plan_destroy(fcfs_plan *plan) {
+  (void)plan;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_autotune(fcfs_handle *h, const char *cache_path, int effort) {
+  (void)cache_path; (void)effort;
+  return fail(h, FCFS_ERR_UNSUPPORTED, "autotune not built");
+}
+
+}  // extern "C"

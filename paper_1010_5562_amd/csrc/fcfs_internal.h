@@ -1,0 +1,82 @@
+// Internal declarations shared by the host runtime and the kernel launchers
+// of the FCFS library (gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fcfs {
+
+// One twiddle table of N = 8192 entries serves every power-of-two period
+// T <= 8192: the phase index of period T is scaled by 8192 / T.
+constexpr int kTabBits = 13;
+constexpr int kTabN = 1 << kTabBits;
+// Entry kTabN of every device table is zero: padded corners point there.
+constexpr int kTabEntries = kTabN + 1;
+
+// Packed corner record written by the pre-pass (two 32-bit words):
+//   w0 = (xs * 8) | (ys * 8) << 16   -- byte offsets of the phase-1 entries
+//                                       in an 8-byte-per-entry table
+//   w1 = bit 15: sign (adds half a period to the y phase, i.e. a factor -1)
+//        bit 16: padding corner (contributes zero)
+// where xs = (x mod T) * (8192 / T), ys likewise.
+constexpr uint32_t kPadFlag = 1u << 16;
+constexpr uint32_t kNegFlag = 1u << 15;
+
+enum Prec { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
+
+// Device-resident constant tables owned by a handle.
+struct Tables {
+  double2 *w64 = nullptr;    // [kTabN]       (cos, sin)(2 pi p / N), FP64
+  float2 *w32 = nullptr;     // [kTabEntries] FP32 (cos, sin)
+  uint2 *wbf16 = nullptr;    // [kTabEntries] {hi(c)|hi(s)<<16, lo(c)|lo(s)<<16}
+  uint2 *wfp16 = nullptr;    // [kTabEntries] same layout, binary16
+};
+
+// Launch geometry of one forward (or adjoint) call, fixed by the planner
+// from (V, T, K, L, precision) alone.
+struct FwdPlan {
+  int prec;
+  int T, K, L;
+  int64_t V;
+  int shift;         // log2(8192 / T)
+  int tile;          // contraction tile variant id
+  int wgk, wgl;      // workgroup tile in k and l (frequencies)
+  int kp, lp;        // padded frequency counts (multiples of wgk, wgl)
+  int tiles_k, tiles_l;
+  int nsplit;        // vertex splits of the contraction
+  int64_t chunk;     // corners per split (multiple of 16)
+  int64_t vpad;      // nsplit * chunk
+  int pre_blocks;    // pre-pass blocks (area partials)
+  int ax_chunks;     // vertex chunks of the axis sums
+  int64_t ax_chunk;  // corners per axis chunk
+  // workspace offsets (bytes)
+  size_t off_packed, off_area, off_axis, off_part, bytes;
+};
+
+// Kernel launchers (fcfs_kernels.hip).  All enqueue on `st` and return the
+// launch status.
+hipError_t launch_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
+                          uint2 *packed, unsigned long long *area_part, hipStream_t st);
+hipError_t launch_axis(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
+                       const uint2 *packed, const double2 *w64, double2 *axis_part,
+                       hipStream_t st);
+hipError_t launch_contract(const FwdPlan &p, const uint2 *packed, const Tables &t, float *part,
+                           hipStream_t st);
+hipError_t launch_epilogue(const FwdPlan &p, const float *part, const double2 *axis_part,
+                           const unsigned long long *area_part, float *F, int64_t *area,
+                           hipStream_t st);
+hipError_t launch_debug_phases(const FwdPlan &p, const uint2 *packed, int axis, int k0, int nk,
+                               int32_t *out, hipStream_t st);
+
+// Contraction tile variants (wave tile in k x l frequencies; 2 x 2 waves).
+struct TileVariant {
+  int id;
+  int prec_mask;  // bit per Prec this variant is built for
+  int wk, wl;     // frequencies per wave
+};
+int n_tile_variants();
+const TileVariant &tile_variant(int i);
+
+}  // namespace fcfs

@@ -1,0 +1,126 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+symbol, canonicalises loops into signed corners, validates its arguments and
+sizes workspaces.  No device work is launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from tests import helpers as H
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1010_5562_amd import _lib
+
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libfcfs.so is not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fcfs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fcfs_\w+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(lib):
+    from paper_1010_5562_amd import _lib
+
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_status_strings(lib):
+    for st in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert lib.fcfs_status_string(st)
+    assert lib.fcfs_last_error(None) is not None
+
+
+def test_loops_to_corners_signs_match_raster_corners():
+    import paper_1010_5562_amd as P
+
+    c = synth.clip(21, 256, 10, n_polygons=1)
+    x, y, s, he, ve = P.loops_to_corners(c.xy, c.off)
+    assert np.array_equal(x, c.xy[:, 0]) and np.array_equal(y, c.xy[:, 1])
+    # corner weights of the rasterised polygon (independent of the edge walk)
+    W = H.corner_image(H.raster(c.xy, c.off, 256))
+    assert np.array_equal(W[x, y], s.astype(np.int64))
+    assert int(np.count_nonzero(W)) == c.n_vertices
+    # edge maps: hedge[v] is the horizontal edge at v, vedge[v] the vertical one
+    n = c.n_vertices
+    for v in range(n):
+        for e, horiz in ((he[v], True), (ve[v], False)):
+            a, b = c.xy[e], c.xy[(e + 1) % n]
+            assert v in (e, (e + 1) % n)
+            assert (a[1] == b[1]) == horiz
+
+
+def test_loops_to_corners_counter_clockwise_and_multi():
+    import paper_1010_5562_amd as P
+
+    r1 = synth.rectangle_loop(0, 0, 5, 3)
+    r2 = synth.rectangle_loop(10, 10, 12, 20)[::-1]  # counter-clockwise
+    xy = np.concatenate([r1, r2])
+    x, y, s, he, ve = P.loops_to_corners(xy, [0, 4, 8])
+    # sum s x y is the total area for both orientations
+    assert int(np.sum(s.astype(np.int64) * x * y)) == 15 + 20
+    # per polygon the signs sum to zero
+    assert s[:4].sum() == 0 and s[4:].sum() == 0
+
+
+@pytest.mark.parametrize(
+    "xy,off,status",
+    [
+        ([[0, 0], [0, 5], [5, 5]], [0, 3], -2),
+        ([[0, 0], [0, 5], [5, 6], [5, 0]], [0, 4], -2),
+        ([[0, 0], [0, 5], [0, 9], [5, 9], [5, 0], [3, 0]], [0, 6], -2),
+        ([[0, 0], [0, 0], [5, 0], [5, 0]], [0, 4], -2),
+        ([[0, 0], [0, 1 << 30], [5, 1 << 30], [5, 0]], [0, 4], -3),
+    ],
+)
+def test_loops_to_corners_rejects(xy, off, status):
+    import paper_1010_5562_amd as P
+
+    with pytest.raises(P.FcfsError) as ei:
+        P.loops_to_corners(np.array(xy), off)
+    assert ei.value.status == status
+
+
+def test_workspace_sizes():
+    import paper_1010_5562_amd as P
+
+    a = P.workspace_size(40000, 4096, 255, 255, "fp32")
+    b = P.workspace_size(200000, 8192, 511, 511, "bf16")
+    assert 0 < a < b < 1 << 31
+    assert P.workspace_size(0, 2, 0, 0, "fp16") > 0
+    for t in range(len(P.tile_variants())):
+        assert P.workspace_size(1000, 1024, 63, 63, "bf16", tile=t) > 0
+    with pytest.raises(P.FcfsError) as ei:
+        P.workspace_size(10, 1000, 4, 4)  # not a power of two
+    assert ei.value.status == -4
+    with pytest.raises(P.FcfsError) as ei:
+        P.workspace_size(10, 16384, 4, 4)
+    assert ei.value.status == -4
+    with pytest.raises(P.FcfsError) as ei:
+        P.workspace_size(10, 1024, 5000, 4)
+    assert ei.value.status == -4
+    with pytest.raises(P.FcfsError) as ei:
+        P.workspace_size(10, 1024, -1, 4)
+    assert ei.value.status == -1
+
+
+def test_null_handle_is_rejected(lib):
+    from paper_1010_5562_amd import _lib
+
+    c = _lib.FcfsClip()
+    st = lib.fcfs_forward(None, ctypes.byref(c), 0, None, 0)
+    assert st == -1

@@ -1,0 +1,165 @@
+"""GPU parity of the forward transform against the FP64 oracle.
+
+Every case calls the HIP path through the C ABI (via the thin binding) and
+compares element by element with the oracle on the same seeded input.
+Tolerances (relative to |F[0,0]|, over the whole grid or the sampled set):
+FP32 contraction 1e-6, split-bf16 / split-fp16 1e-5; the area and the integer
+phases are compared bit for bit.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-6, "bf16": 1e-5, "fp16": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1010_5562_amd as P
+
+    torch.cuda.set_device(0)
+    return P
+
+
+def _corners(P, clip):
+    x, y, s, _, _ = P.loops_to_corners(clip.xy, clip.off)
+    return x, y, s
+
+
+def _run(P, x, y, s, T, K, L, prec, tile=None):
+    F, a = P.forward(x, y, s, T, K, L, precision=prec, tile=tile)
+    torch.cuda.synchronize()
+    return F.cpu().numpy().astype(np.complex128), int(a.item())
+
+
+def _err(F, ref, K, L):
+    return float(np.max(np.abs(F - ref)) / abs(ref[K, L]))
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_single_polygon_c1(P, oracle_lib, prec):
+    clip, _, _ = synth.clip_c1(1)
+    _say(f"C1 V={clip.n_vertices} T={clip.T} K={clip.K} prec={prec}")
+    ref, area = oracle_lib.cfs_grid(clip.xy, clip.off, clip.T, clip.K, clip.L)
+    F, a = _run(P, *_corners(P, clip), clip.T, clip.K, clip.L, prec)
+    assert a == area
+    assert F[clip.K, clip.L] == np.complex64(np.float32(area / clip.T))
+    e = _err(F, ref, clip.K, clip.L)
+    _say(f"  err/|F00| = {e:.3e}")
+    assert e <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("tile", [0, 1, 2])
+def test_tiles_and_ragged_edges(P, oracle_lib, prec, tile):
+    # several workgroup tiles in k and l, K != L, a ragged vertex tail
+    T, K, L = 1024, 150, 97
+    clip = synth.clip(31, T, K, L, n_polygons=211)
+    _say(f"ragged V={clip.n_vertices} T={T} K={K} L={L} prec={prec} tile={tile}")
+    ref, area = oracle_lib.cfs_grid(clip.xy, clip.off, T, K, L)
+    F, a = _run(P, *_corners(P, clip), T, K, L, prec, tile=tile)
+    assert a == area
+    e = _err(F, ref, K, L)
+    _say(f"  err/|F00| = {e:.3e}")
+    assert e <= TOL[prec]
+
+
+def test_phases_bit_exact(P):
+    clip = synth.clip(8, 4096, 255, n_polygons=300)
+    x, y, s = _corners(P, clip)
+    # include negative and out-of-tile coordinates
+    x = x.astype(np.int64) - 5000
+    y = y.astype(np.int64) + 9000
+    for T in (4096, 64, 8192):
+        for axis, c in ((0, x), (1, y)):
+            p = P.debug_phases(x.astype(np.int32), y.astype(np.int32), s, T, 1, 300, axis=axis)
+            got = p.cpu().numpy().astype(np.int64)
+            want = (np.arange(1, 301)[:, None] * c[None, :]) % T
+            assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_degenerate_sizes(P, oracle_lib, prec):
+    clip = synth.clip(12, 512, 20, n_polygons=9)
+    x, y, s = _corners(P, clip)
+    for K, L in ((0, 0), (0, 7), (9, 0), (1, 1), (33, 2)):
+        _say(f"degenerate K={K} L={L} prec={prec}")
+        ref, area = oracle_lib.cfs_grid(clip.xy, clip.off, 512, K, L)
+        F, a = _run(P, x, y, s, 512, K, L, prec)
+        assert a == area
+        assert _err(F, ref, K, L) <= TOL[prec]
+    # no corners at all: every coefficient is zero
+    e = np.zeros(0, np.int32)
+    F, a = _run(P, e, e, e.astype(np.int8), 512, 5, 4, prec)
+    assert a == 0 and np.all(F == 0)
+
+
+@pytest.mark.parametrize("T", [2, 16, 8192])
+def test_periods_and_out_of_tile(P, oracle_lib, T):
+    # coordinates beyond [0, T) and negative: the CFS of the periodisation
+    clip = synth.clip(13, 300, 12, n_polygons=25)
+    xy = synth.shift_loops(clip.xy, -150, 77)
+    K = min(12, 3 * T)
+    ref, area = oracle_lib.cfs_grid(xy, clip.off, T, K, K)
+    x, y, s, _, _ = P.loops_to_corners(xy, clip.off)
+    for prec in ("fp32", "fp16"):
+        F, a = _run(P, x, y, s, T, K, K, prec)
+        assert a == area
+        assert _err(F, ref, K, K) <= TOL[prec]
+
+
+def test_deterministic_and_hermitian(P):
+    clip = synth.clip(14, 2048, 127, n_polygons=400)
+    x, y, s = _corners(P, clip)
+    F1, _ = _run(P, x, y, s, 2048, 127, 127, "bf16")
+    F2, _ = _run(P, x, y, s, 2048, 127, 127, "bf16")
+    assert np.array_equal(F1, F2)
+    assert np.array_equal(F1, np.conj(F1[::-1, ::-1]))
+
+
+def _sample_points(K, L, n, seed):
+    rng = np.random.default_rng(seed)
+    lo = [(k, l) for k in range(-8, 9) for l in range(-8, 9)]
+    kk = np.concatenate([np.array([p[0] for p in lo]), rng.integers(-K, K + 1, n)])
+    ll = np.concatenate([np.array([p[1] for p in lo]), rng.integers(-L, L + 1, n)])
+    return kk, ll
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_full_size_layout_clip_sampled(P, oracle_lib, prec):
+    # 2,000 polygons, T = 4096, |k|,|l| <= 255 (the layout-clip workload)
+    T, K = 4096, 255
+    clip = synth.clip(2, T, K, n_polygons=2000)
+    _say(f"layout clip V={clip.n_vertices} T={T} K={K} prec={prec}")
+    kk, ll = _sample_points(K, K, 400, 1)
+    ref = oracle_lib.cfs_points(clip.xy, clip.off, T, kk, ll)
+    F, a = _run(P, *_corners(P, clip), T, K, K, prec)
+    f00 = oracle_lib.cfs_points(clip.xy, clip.off, T, [0], [0])[0]
+    e = float(np.max(np.abs(F[kk + K, ll + K] - ref)) / abs(f00))
+    _say(f"  err/|F00| = {e:.3e}")
+    assert e <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "fp32"])
+def test_full_size_precision_clip_sampled(P, oracle_lib, prec):
+    # 200k corners, T = 8192, |k|,|l| <= 511 (the precision-form workload)
+    T, K = 8192, 511
+    clip = synth.clip(3, T, K, min_vertices=200_000)
+    _say(f"precision clip V={clip.n_vertices} T={T} K={K} prec={prec}")
+    kk, ll = _sample_points(K, K, 300, 2)
+    ref = oracle_lib.cfs_points(clip.xy, clip.off, T, kk, ll)
+    f00 = oracle_lib.cfs_points(clip.xy, clip.off, T, [0], [0])[0]
+    F, a = _run(P, *_corners(P, clip), T, K, K, prec)
+    e = float(np.max(np.abs(F[kk + K, ll + K] - ref)) / abs(f00))
+    _say(f"  err/|F00| = {e:.3e}")
+    assert e <= TOL[prec]
