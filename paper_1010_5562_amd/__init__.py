@@ -123,6 +123,19 @@ class Handle:
     def set_tile(self, variant: int = -1):
         check(self.lib.fcfs_set_tile(self._h, int(variant)), self._h)
 
+    PROFILE_KINDS = ("prepass", "axis", "contract", "epilogue", "adjoint", "batch")
+
+    def profile_begin(self):
+        check(self.lib.fcfs_profile_begin(self._h), self._h)
+
+    def profile_end(self):
+        """{kind: (total_ms, launches)} since profile_begin (waits for the events)."""
+        n = len(self.PROFILE_KINDS)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        check(self.lib.fcfs_profile_end(self._h, ms, cnt, n), self._h)
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(self.PROFILE_KINDS)}
+
     def workspace(self, nbytes: int):
         """A cached device workspace of at least ``nbytes`` (256-byte aligned)."""
         import torch

@@ -31,7 +31,8 @@ EXPORTS = (
     "fcfs_workspace_size", "fcfs_forward", "fcfs_adjoint", "fcfs_edge_grad",
     "fcfs_batch_workspace_size", "fcfs_forward_batch", "fcfs_plan_destroy",
     "fcfs_debug_phases", "fcfs_autotune", "fcfs_tile_variants", "fcfs_set_tile",
-    "fcfs_workspace_size_tile", "fcfs_status_string", "fcfs_last_error",
+    "fcfs_workspace_size_tile", "fcfs_profile_begin", "fcfs_profile_end",
+    "fcfs_status_string", "fcfs_last_error",
 )
 
 
@@ -86,6 +87,8 @@ def load() -> ctypes.CDLL:
         "fcfs_debug_phases": [P, clip_p, i32, i32, i32, P],
         "fcfs_autotune": [P, ctypes.c_char_p, c_int],
         "fcfs_set_tile": [P, i32],
+        "fcfs_profile_begin": [P],
+        "fcfs_profile_end": [P, P, P, i32],
     }
     for name, args in sig.items():
         f = getattr(lib, name)

@@ -17,12 +17,22 @@
 using fcfs::FwdPlan;
 using fcfs::Tables;
 
+// Kernel families timed by the profiling hooks.
+enum ProfKind { kProfPrepass = 0, kProfAxis, kProfContract, kProfEpilogue, kProfAdjoint,
+                kProfBatch, kProfKinds };
+
 struct fcfs_handle {
   int device = 0;
   hipStream_t stream = nullptr;
   Tables tab;
   int tile_override = -1;
   std::string err;
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[kProfKinds];
+  // side stream for work that overlaps the contraction (axis sums), joined
+  // back into `stream` with events; default priority like every stream here
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
@@ -157,11 +167,12 @@ void free_tables(Tables &t) {
 constexpr int kMaxFreq = 4095;  // |k|, |l| cut-off limit (phases stay below 2^29)
 constexpr int kTargetWG = 512;  // two contraction workgroups per CU on 256 CUs
 
+// Built-in choice when no tuned entry applies: the 64 x 32 wave tile, lean
+// two-waves-per-SIMD loop for the split forms.
 int default_tile(int prec, int K, int L) {
-  (void)prec;
   (void)K;
   (void)L;
-  return 0;
+  return prec == fcfs::kFP32 ? 1 : 4;
 }
 
 fcfs_status check_dims(fcfs_handle *h, int64_t V, int T, int K, int L, int prec) {
@@ -205,19 +216,22 @@ fcfs_status make_plan(fcfs_handle *h, int64_t V, int T, int K, int L, int prec, 
   q.chunk = std::max<int64_t>(16, round_up(ceil_div(std::max<int64_t>(V, 1), ns), 16));
   q.vpad = q.chunk * q.nsplit;
   q.pre_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(q.vpad, 256)));
-  const int fblocks = (int)(ceil_div(K, 256) + ceil_div(L, 256));
-  if (fblocks > 0 && V > 0) {
-    int64_t ac = std::max<int64_t>(1, ceil_div(1024, fblocks));
-    ac = std::min<int64_t>(ac, ceil_div(V, 256));
-    q.ax_chunk = round_up(ceil_div(V, ac), 256);
+  q.ax_groups_k = (int)ceil_div(K, 512);
+  q.ax_groups_l = (int)ceil_div(L, 512);
+  const int groups = q.ax_groups_k + q.ax_groups_l;
+  if (groups > 0 && V > 0) {
+    // staged chunks of at most 1024 corners, enough blocks to fill the chip
+    int64_t ac = std::max(ceil_div(kTargetWG, groups), ceil_div(V, 1024));
+    ac = std::max<int64_t>(1, std::min<int64_t>(ac, ceil_div(V, 64)));
+    q.ax_chunk = std::min<int64_t>(1024, ceil_div(V, ac));
     q.ax_chunks = (int)ceil_div(V, q.ax_chunk);
   } else {
-    q.ax_chunk = 256;
+    q.ax_chunk = 1;
     q.ax_chunks = 1;
   }
   size_t off = 0;
   q.off_packed = off;
-  off += align256(sizeof(uint2) * (size_t)q.vpad);
+  off += align256(sizeof(uint4) * (size_t)q.vpad);
   q.off_area = off;
   off += align256(sizeof(unsigned long long) * (size_t)q.pre_blocks);
   q.off_axis = off;
@@ -259,26 +273,65 @@ fcfs_status enter(fcfs_handle *h) {
   return FCFS_OK;
 }
 
+// Brackets one launch with events on the handle's stream when profiling.
+struct ProfScope {
+  fcfs_handle *h;
+  int kind;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(fcfs_handle *h_, int kind_, hipStream_t st_ = nullptr)
+      : h(h_), kind(kind_), st(st_ ? st_ : h_->stream) {
+    if (!h->prof) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      h->prof = false;
+      return;
+    }
+    (void)hipEventRecord(a, st);
+  }
+  ~ProfScope() {
+    if (!h->prof || !a) return;
+    (void)hipEventRecord(b, st);
+    h->prof_ev[kind].emplace_back(a, b);
+  }
+};
+
 template <class T>
 T *ws_at(void *ws, size_t off) {
   return (T *)((char *)ws + off);
 }
 
 fcfs_status run_forward(fcfs_handle *h, const fcfs_clip *c, const FwdPlan &p, void *ws) {
-  uint2 *packed = ws_at<uint2>(ws, p.off_packed);
+  uint4 *packed = ws_at<uint4>(ws, p.off_packed);
   auto *area_part = ws_at<unsigned long long>(ws, p.off_area);
   auto *axis_part = ws_at<double2>(ws, p.off_axis);
   float *part = ws_at<float>(ws, p.off_part);
   hipError_t e;
-  if ((e = fcfs::launch_prepass(p, c->x, c->y, c->s, packed, area_part, h->stream)))
-    return hip_fail(h, e, "pre-pass launch");
-  if ((e = fcfs::launch_axis(p, c->x, c->y, c->s, packed, h->tab.w64, axis_part, h->stream)))
-    return hip_fail(h, e, "axis launch");
-  if (p.K > 0 && p.L > 0)
+  {
+    ProfScope ps(h, kProfPrepass);
+    if ((e = fcfs::launch_prepass(p, c->x, c->y, c->s, packed, area_part, h->stream)))
+      return hip_fail(h, e, "pre-pass launch");
+  }
+  // the FP64 axis sums run on the side stream, overlapping the contraction
+  if ((e = hipEventRecord(h->ev_fork, h->stream)) ||
+      (e = hipStreamWaitEvent(h->side, h->ev_fork, 0)))
+    return hip_fail(h, e, "fork");
+  {
+    ProfScope ps(h, kProfAxis, h->side);
+    if ((e = fcfs::launch_axis(p, c->x, c->y, c->s, packed, h->tab.w64, axis_part, h->side)))
+      return hip_fail(h, e, "axis launch");
+  }
+  if ((e = hipEventRecord(h->ev_join, h->side))) return hip_fail(h, e, "join");
+  if (p.K > 0 && p.L > 0) {
+    ProfScope ps(h, kProfContract);
     if ((e = fcfs::launch_contract(p, packed, h->tab, part, h->stream)))
       return hip_fail(h, e, "contraction launch");
-  if ((e = fcfs::launch_epilogue(p, part, axis_part, area_part, c->F, c->area, h->stream)))
-    return hip_fail(h, e, "epilogue launch");
+  }
+  if ((e = hipStreamWaitEvent(h->stream, h->ev_join, 0))) return hip_fail(h, e, "join");
+  {
+    ProfScope ps(h, kProfEpilogue);
+    if ((e = fcfs::launch_epilogue(p, part, axis_part, area_part, c->F, c->area, h->stream)))
+      return hip_fail(h, e, "epilogue launch");
+  }
   return FCFS_OK;
 }
 
@@ -324,11 +377,21 @@ fcfs_status fcfs_create(fcfs_handle **out, int device, void *hip_stream) {
   h->device = device;
   h->stream = (hipStream_t)hip_stream;
   fcfs_status st = build_tables(h);
+  if (!st) {
+    hipError_t e2;
+    if ((e2 = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking)) ||
+        (e2 = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming)) ||
+        (e2 = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming)))
+      st = hip_fail(h, e2, "side stream");
+  }
   if (st) {
     {
       std::lock_guard<std::mutex> g(g_err_mu);
       g_err = h->err;
     }
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->side) (void)hipStreamDestroy(h->side);
     free_tables(h->tab);
     delete h;
     return st;
@@ -340,6 +403,17 @@ fcfs_status fcfs_create(fcfs_handle **out, int device, void *hip_stream) {
 fcfs_status fcfs_destroy(fcfs_handle *h) {
   if (!h) return FCFS_OK;
   (void)hipSetDevice(h->device);
+  for (auto &v : h->prof_ev)
+    for (auto &pr : v) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  if (h->side) {
+    (void)hipStreamSynchronize(h->side);
+    (void)hipStreamDestroy(h->side);
+  }
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   free_tables(h->tab);
   delete h;
   return FCFS_OK;
@@ -349,6 +423,42 @@ fcfs_status fcfs_set_stream(fcfs_handle *h, void *hip_stream) {
   if (!h) return fail(nullptr, FCFS_ERR_INVALID_ARG, "handle is NULL");
   h->stream = (hipStream_t)hip_stream;
   return FCFS_OK;
+}
+
+fcfs_status fcfs_profile_begin(fcfs_handle *h) {
+  if (!h) return fail(nullptr, FCFS_ERR_INVALID_ARG, "handle is NULL");
+  for (auto &v : h->prof_ev)
+    for (auto &pr : v) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  for (auto &v : h->prof_ev) v.clear();
+  h->prof = true;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_profile_end(fcfs_handle *h, double *ms, int64_t *count, int32_t nkinds) {
+  if (!h) return fail(nullptr, FCFS_ERR_INVALID_ARG, "handle is NULL");
+  h->prof = false;
+  fcfs_status st = FCFS_OK;
+  for (int k = 0; k < kProfKinds; ++k) {
+    double sum = 0.0;
+    for (auto &pr : h->prof_ev[k]) {
+      float t = 0.f;
+      hipError_t e = hipEventSynchronize(pr.second);
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, pr.first, pr.second);
+      if (e != hipSuccess) st = hip_fail(h, e, "profile events");
+      sum += t;
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+    if (k < nkinds) {
+      if (ms) ms[k] = sum;
+      if (count) count[k] = (int64_t)h->prof_ev[k].size();
+    }
+    h->prof_ev[k].clear();
+  }
+  return st;
 }
 
 fcfs_status fcfs_set_tile(fcfs_handle *h, int32_t variant) {
@@ -461,11 +571,11 @@ fcfs_status fcfs_debug_phases(fcfs_handle *h, const fcfs_clip *c, int32_t axis, 
   FwdPlan q;
   if ((st = make_plan(h, c->V, c->T, 0, 0, 0, 0, &q))) return st;
   void *tmp = nullptr;
-  const size_t nb = align256(sizeof(uint2) * (size_t)q.vpad) + align256(8 * (size_t)q.pre_blocks);
+  const size_t nb = align256(sizeof(uint4) * (size_t)q.vpad) + align256(8 * (size_t)q.pre_blocks);
   hipError_t e = hipMalloc(&tmp, nb);
   if (e) return hip_fail(h, e, "hipMalloc");
-  uint2 *packed = (uint2 *)tmp;
-  auto *ap = ws_at<unsigned long long>(tmp, align256(sizeof(uint2) * (size_t)q.vpad));
+  uint4 *packed = (uint4 *)tmp;
+  auto *ap = ws_at<unsigned long long>(tmp, align256(sizeof(uint4) * (size_t)q.vpad));
   if ((e = fcfs::launch_prepass(q, c->x, c->y, c->s, packed, ap, h->stream)) ||
       (e = fcfs::launch_debug_phases(q, packed, axis, k0, nk, p, h->stream)) ||
       (e = hipStreamSynchronize(h->stream))) {

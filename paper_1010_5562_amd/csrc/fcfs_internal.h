@@ -15,14 +15,13 @@ constexpr int kTabN = 1 << kTabBits;
 // Entry kTabN of every device table is zero: padded corners point there.
 constexpr int kTabEntries = kTabN + 1;
 
-// Packed corner record written by the pre-pass (two 32-bit words):
-//   w0 = (xs * 8) | (ys * 8) << 16   -- byte offsets of the phase-1 entries
-//                                       in an 8-byte-per-entry table
-//   w1 = bit 15: sign (adds half a period to the y phase, i.e. a factor -1)
-//        bit 16: padding corner (contributes zero)
-// where xs = (x mod T) * (8192 / T), ys likewise.
-constexpr uint32_t kPadFlag = 1u << 16;
-constexpr uint32_t kNegFlag = 1u << 15;
+// Corner record written by the pre-pass (uint4, 16 bytes), already decoded
+// for the inner loops (byte offsets into 8-byte-per-entry tables):
+//   .x = xs * 8, .y = ys * 8  with xs = (x mod T) * (8192 / T), ys likewise
+//   .z = 4096 * 8 if s = -1 else 0  (half a period: a factor -1 on the y side)
+//   .w = kTabN * 8 for padding records (points the y side at the zero entry)
+constexpr uint32_t kNegOff = (uint32_t)(kTabN / 2) * 8u;
+constexpr uint32_t kPadOff = (uint32_t)kTabN * 8u;
 
 enum Prec { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
 
@@ -49,6 +48,8 @@ struct FwdPlan {
   int64_t chunk;     // corners per split (multiple of 16)
   int64_t vpad;      // nsplit * chunk
   int pre_blocks;    // pre-pass blocks (area partials)
+  int ax_groups_k;   // 512-frequency groups of the x-axis sums
+  int ax_groups_l;   // and of the y-axis sums
   int ax_chunks;     // vertex chunks of the axis sums
   int64_t ax_chunk;  // corners per axis chunk
   // workspace offsets (bytes)
@@ -58,16 +59,16 @@ struct FwdPlan {
 // Kernel launchers (fcfs_kernels.hip).  All enqueue on `st` and return the
 // launch status.
 hipError_t launch_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
-                          uint2 *packed, unsigned long long *area_part, hipStream_t st);
+                          uint4 *packed, unsigned long long *area_part, hipStream_t st);
 hipError_t launch_axis(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
-                       const uint2 *packed, const double2 *w64, double2 *axis_part,
+                       const uint4 *packed, const double2 *w64, double2 *axis_part,
                        hipStream_t st);
-hipError_t launch_contract(const FwdPlan &p, const uint2 *packed, const Tables &t, float *part,
+hipError_t launch_contract(const FwdPlan &p, const uint4 *packed, const Tables &t, float *part,
                            hipStream_t st);
 hipError_t launch_epilogue(const FwdPlan &p, const float *part, const double2 *axis_part,
                            const unsigned long long *area_part, float *F, int64_t *area,
                            hipStream_t st);
-hipError_t launch_debug_phases(const FwdPlan &p, const uint2 *packed, int axis, int k0, int nk,
+hipError_t launch_debug_phases(const FwdPlan &p, const uint4 *packed, int axis, int k0, int nk,
                                int32_t *out, hipStream_t st);
 
 // Contraction tile variants (wave tile in k x l frequencies; 2 x 2 waves).
@@ -75,6 +76,7 @@ struct TileVariant {
   int id;
   int prec_mask;  // bit per Prec this variant is built for
   int wk, wl;     // frequencies per wave
+  int pipe;       // software-pipelined inner loop (one wave per SIMD) or lean
 };
 int n_tile_variants();
 const TileVariant &tile_variant(int i);

@@ -23,14 +23,24 @@ constexpr double kPi = 3.14159265358979323846264338327950288;
 // table of kTabN entries: offset = ((f * xs) mod 8192) * 8, computed exactly in
 // 32-bit integers (f < 2^13, xs*8 < 2^16).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t phase_x(uint32_t f, uint32_t w0) {
-  return __umul24(f, w0 & 0xFFFFu) & 0xFFF8u;
+// The multiplies are written as 24-bit integer ops (v_mul/v_mad_u32_u24, full
+// rate); plain 32-bit multiplies would become quarter-rate v_mul_lo_u32.
+// x side: (f * xs8) mod 65536, the product's high half dropped by the
+// sub-dword destination select.
+__device__ __forceinline__ uint32_t phase_x(uint32_t f, const uint4 &c) {
+  uint32_t r;
+  asm("v_mul_u32_u24_sdwa %0, %1, %2 dst_sel:WORD_0 dst_unused:UNUSED_PAD src0_sel:DWORD "
+      "src1_sel:DWORD"
+      : "=v"(r)
+      : "v"(f), "v"(c.x));
+  return r;
 }
-// y phase with the corner sign folded in (half a period = factor -1) and
-// padding corners redirected to the zero entry kTabN.
-__device__ __forceinline__ uint32_t phase_y(uint32_t f, uint32_t w0, uint32_t w1) {
-  return ((__umul24(f, w0 >> 16) + (w1 & kNegFlag)) & 0xFFF8u) |
-         (w1 & kPadFlag);
+// y side: (f * ys8 + sign offset) mod 65536; padding records are sent to the
+// zero entry kTabN.
+__device__ __forceinline__ uint32_t phase_y(uint32_t f, const uint4 &c) {
+  uint32_t t;
+  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(t) : "v"(f), "v"(c.y), "v"(c.z));
+  return (t & 0xFFFFu) | c.w;
 }
 
 // ---------------------------------------------------------------------------
@@ -42,23 +52,22 @@ __global__ __launch_bounds__(256) void k_prepass(const int32_t *__restrict__ x,
                                                  const int32_t *__restrict__ y,
                                                  const int8_t *__restrict__ s, int64_t V,
                                                  int64_t vpad, uint32_t tmask, int shift,
-                                                 uint2 *__restrict__ packed,
+                                                 uint4 *__restrict__ packed,
                                                  unsigned long long *__restrict__ area_part) {
   unsigned long long acc = 0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < vpad;
        i += (int64_t)gridDim.x * 256) {
-    uint2 w;
+    uint4 w;
     if (i < V) {
       const int32_t xv = x[i], yv = y[i];
       const int sv = s[i];
-      const uint32_t xs = ((uint32_t)xv & tmask) << shift;
-      const uint32_t ys = ((uint32_t)yv & tmask) << shift;
-      w.x = (xs << 3) | ((ys << 3) << 16);
-      w.y = sv < 0 ? kNegFlag : 0u;
+      w.x = (((uint32_t)xv & tmask) << shift) << 3;
+      w.y = (((uint32_t)yv & tmask) << shift) << 3;
+      w.z = sv < 0 ? kNegOff : 0u;
+      w.w = 0u;
       acc += (unsigned long long)((long long)sv * (long long)xv * (long long)yv);
     } else {
-      w.x = 0u;
-      w.y = kPadFlag;
+      w = make_uint4(0u, 0u, 0u, kPadOff);
     }
     packed[i] = w;
   }
@@ -71,7 +80,7 @@ __global__ __launch_bounds__(256) void k_prepass(const int32_t *__restrict__ x,
 }
 
 hipError_t launch_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
-                          uint2 *packed, unsigned long long *area_part, hipStream_t st) {
+                          uint4 *packed, unsigned long long *area_part, hipStream_t st) {
   hipLaunchKernelGGL(k_prepass, dim3(p.pre_blocks), dim3(256), 0, st, x, y, s, p.V, p.vpad,
                      (uint32_t)(p.T - 1), p.shift, packed, area_part);
   return hipGetLastError();
@@ -80,68 +89,108 @@ hipError_t launch_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y, 
 // ---------------------------------------------------------------------------
 // Axis sums (Steps 2 and 3): for f = 1..K,
 //   Sx[f] = sum_v s_v y_v e(f x_v),  and for f = 1..L,  Sy[f] = sum_v s_v x_v e(f y_v),
-// with raw (unreduced) coordinates as weights and FP64 twiddles indexed by the
-// exact integer phase.  Block (fb, c): 256 frequencies, one vertex chunk;
-// partial sums per chunk, reduced in fixed order by the epilogue.
+// with raw (unreduced) coordinates as weights, in FP64.  Each lane owns 8
+// consecutive frequencies f0..f0+7 of a 512-frequency group: e(f0 x) comes from
+// the FP64 table at the exact integer phase, the next seven from repeated
+// multiplication by e(x) (seven FP64 complex products, error ~1e-15).  The four
+// waves of a block take every fourth corner of the block's chunk and are
+// combined in a fixed order; one partial per (chunk, frequency) goes to the
+// epilogue.
 // ---------------------------------------------------------------------------
+constexpr int kAxR = 8;               // frequencies per lane
+constexpr int kAxGroup = 64 * kAxR;   // frequencies per group
+constexpr int kAxChunkMax = 1024;     // corners staged per block
+
 __global__ __launch_bounds__(256) void k_axis(const int32_t *__restrict__ x,
                                               const int32_t *__restrict__ y,
-                                              const uint2 *__restrict__ packed,
+                                              const uint4 *__restrict__ packed,
                                               const double2 *__restrict__ w64, int64_t V,
-                                              int64_t ax_chunk, int K, int L, int kblocks,
+                                              int64_t ax_chunk, int K, int L, int groups_k,
                                               double2 *__restrict__ axis_part) {
-  __shared__ uint32_t s_ph[256];
-  __shared__ double s_wt[256];
-  const int fb = blockIdx.x;
-  const bool xaxis = fb < kblocks;
-  const int f = 1 + (xaxis ? fb : fb - kblocks) * 256 + threadIdx.x;
+  __shared__ uint32_t s_ph[kAxChunkMax];
+  __shared__ double s_wt[kAxChunkMax];
+  __shared__ double2 s_e1[kAxChunkMax];
+  __shared__ double2 red[3][64][kAxR];
+  const int g = blockIdx.x;
+  const bool xaxis = g < groups_k;
+  const int gi = xaxis ? g : g - groups_k;
   const int nf = xaxis ? K : L;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t f0 = (uint32_t)(gi * kAxGroup + lane * kAxR + 1);
   const int64_t v0 = (int64_t)blockIdx.y * ax_chunk;
-  const int64_t v1 = min(V, v0 + ax_chunk);
-  double re = 0.0, im = 0.0;
-  for (int64_t vb = v0; vb < v1; vb += 256) {
-    const int64_t v = vb + threadIdx.x;
-    uint32_t ph = 0;
-    double wt = 0.0;
-    if (v < v1) {
-      const uint2 w = packed[v];
-      const double sg = (w.y & kNegFlag) ? -1.0 : 1.0;
-      if (xaxis) {
-        ph = (w.x & 0xFFFFu) >> 3;
-        wt = sg * (double)y[v];
-      } else {
-        ph = w.x >> 19;
-        wt = sg * (double)x[v];
-      }
+  const int n = (int)(min(V, v0 + ax_chunk) - v0);
+  // stage the chunk: phase index, signed weight and e^{j 2 pi ph / N}
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const int64_t v = v0 + i;
+    const uint4 c = packed[v];
+    const uint32_t ph = (xaxis ? c.x : c.y) >> 3;
+    const double coord = (double)(xaxis ? y[v] : x[v]);
+    s_ph[i] = ph;
+    s_wt[i] = c.z ? -coord : coord;
+    s_e1[i] = w64[ph];
+  }
+  __syncthreads();
+  double re[kAxR], im[kAxR];
+#pragma unroll
+  for (int r = 0; r < kAxR; ++r) re[r] = im[r] = 0.0;
+  // each wave takes every fourth staged corner, four at a time
+  constexpr int U = 4;
+  for (int jb = wave; jb < n; jb += 4 * U) {
+    double wt[U];
+    double2 e1[U], z[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = jb + 4 * u;
+      const bool ok = j < n;
+      const int jj = ok ? j : jb;
+      wt[u] = ok ? s_wt[jj] : 0.0;
+      e1[u] = s_e1[jj];
+      z[u] = w64[(f0 * s_ph[jj]) & (uint32_t)(kTabN - 1)];
     }
-    __syncthreads();
-    s_ph[threadIdx.x] = ph;
-    s_wt[threadIdx.x] = wt;
-    __syncthreads();
-    const int n = (int)min((int64_t)256, v1 - vb);
-    if (f <= nf) {
-      for (int j = 0; j < n; ++j) {
-        const uint32_t idx = ((uint32_t)f * s_ph[j]) & (kTabN - 1);
-        const double2 t = w64[idx];
-        re = fma(s_wt[j], t.x, re);
-        im = fma(-s_wt[j], t.y, im);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int r = 0; r < kAxR; ++r) {
+        // e(f x) = cos - j sin of the table angle
+        re[r] = fma(wt[u], z[u].x, re[r]);
+        im[r] = fma(-wt[u], z[u].y, im[r]);
+        if (r + 1 < kAxR) {
+          const double zx = fma(z[u].x, e1[u].x, -z[u].y * e1[u].y);
+          const double zy = fma(z[u].x, e1[u].y, z[u].y * e1[u].x);
+          z[u].x = zx;
+          z[u].y = zy;
+        }
       }
     }
   }
-  if (f <= nf) {
-    const int slot = xaxis ? f - 1 : K + f - 1;
-    axis_part[(size_t)blockIdx.y * (K + L) + slot] = make_double2(re, im);
+  if (wave > 0)
+#pragma unroll
+    for (int r = 0; r < kAxR; ++r) red[wave - 1][lane][r] = make_double2(re[r], im[r]);
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int r = 0; r < kAxR; ++r) {
+      double sr = re[r], si = im[r];
+      for (int w = 0; w < 3; ++w) {
+        sr += red[w][lane][r].x;
+        si += red[w][lane][r].y;
+      }
+      const int f = (int)f0 + r;
+      if (f <= nf) {
+        const int slot = xaxis ? f - 1 : K + f - 1;
+        axis_part[(size_t)blockIdx.y * (K + L) + slot] = make_double2(sr, si);
+      }
+    }
   }
 }
 
 hipError_t launch_axis(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
-                       const uint2 *packed, const double2 *w64, double2 *axis_part,
+                       const uint4 *packed, const double2 *w64, double2 *axis_part,
                        hipStream_t st) {
   (void)s;
-  if (p.K + p.L == 0 || p.ax_chunks == 0) return hipSuccess;
-  const int kblocks = (p.K + 255) / 256, lblocks = (p.L + 255) / 256;
-  hipLaunchKernelGGL(k_axis, dim3(kblocks + lblocks, p.ax_chunks), dim3(256), 0, st, x, y,
-                     packed, w64, p.V, p.ax_chunk, p.K, p.L, kblocks, axis_part);
+  if (p.K + p.L == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axis, dim3(p.ax_groups_k + p.ax_groups_l, p.ax_chunks), dim3(256), 0, st,
+                     x, y, packed, w64, p.V, p.ax_chunk, p.K, p.L, p.ax_groups_k, axis_part);
   return hipGetLastError();
 }
 
@@ -182,8 +231,96 @@ __device__ __forceinline__ void store_part(float *__restrict__ part, const f32x1
       }
 }
 
+// The 8 corners of this lane's half-wave for one 16-corner step.
+__device__ __forceinline__ void load_corners(uint4 (&c)[8], const uint4 *__restrict__ vp) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) c[j] = vp[j];
+}
+
+// Raw table entries of one step: a[kb][j] = W[k x_j], b[lb][j] = s_j W[l y_j].
+template <int NKB, int NLB>
+struct Raw {
+  uint2 a[NKB][8], b[NLB][8];
+};
+
+template <int NKB, int NLB>
+__device__ __forceinline__ void gather(Raw<NKB, NLB> &r, const uint2 *s_tab, const uint4 (&c)[8],
+                                       const uint32_t (&kf)[NKB], const uint32_t (&lf)[NLB]) {
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) r.a[kb][j] = lds_entry(s_tab, phase_x(kf[kb], c[j]));
+#pragma unroll
+  for (int lb = 0; lb < NLB; ++lb)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) r.b[lb][j] = lds_entry(s_tab, phase_y(lf[lb], c[j]));
+}
+
+// MFMA operand fragments of one step: 8 corners (the lane's k-slots), two
+// 16-bit values per register.  Table entry = {hi(c)|hi(s)<<16, lo(c)|lo(s)<<16}.
+template <int NKB, int NLB>
+struct Frag {
+  u32x4 ach[NKB], acl[NKB], ash[NKB], asl[NKB];
+  u32x4 bch[NLB], bcl[NLB], bsh[NLB], bsl[NLB];
+};
+
+__device__ __forceinline__ void pack4(const uint2 (&d)[8], u32x4 &ch, u32x4 &sh, u32x4 &cl,
+                                      u32x4 &sl) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    ch[j] = __builtin_amdgcn_perm(d[2 * j + 1].x, d[2 * j].x, 0x05040100u);
+    sh[j] = __builtin_amdgcn_perm(d[2 * j + 1].x, d[2 * j].x, 0x07060302u);
+    cl[j] = __builtin_amdgcn_perm(d[2 * j + 1].y, d[2 * j].y, 0x05040100u);
+    sl[j] = __builtin_amdgcn_perm(d[2 * j + 1].y, d[2 * j].y, 0x07060302u);
+  }
+}
+
+template <int NKB, int NLB>
+__device__ __forceinline__ void build(Frag<NKB, NLB> &f, const Raw<NKB, NLB> &r) {
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb) pack4(r.a[kb], f.ach[kb], f.ash[kb], f.acl[kb], f.asl[kb]);
+#pragma unroll
+  for (int lb = 0; lb < NLB; ++lb) pack4(r.b[lb], f.bch[lb], f.bsh[lb], f.bcl[lb], f.bsl[lb]);
+}
+
+template <int PREC>
+__device__ __forceinline__ f32x16 mfma16(const u32x4 &a, const u32x4 &b, const f32x16 &c) {
+  if constexpr (PREC == kBF16)
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
+                                                  __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+}
+
+// hi*hi' + hi*lo' + lo*hi' for the four quadrants of every (kb, lb) block.
 template <int PREC, int NKB, int NLB>
-__global__ __launch_bounds__(256) void k_contract_split(const uint2 *__restrict__ packed,
+__device__ __forceinline__ void mma(f32x16 (&acc)[NKB][NLB][4], const Frag<NKB, NLB> &f) {
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+    for (int lb = 0; lb < NLB; ++lb) {
+      acc[kb][lb][0] = mfma16<PREC>(f.ach[kb], f.bch[lb], acc[kb][lb][0]);
+      acc[kb][lb][1] = mfma16<PREC>(f.ach[kb], f.bsh[lb], acc[kb][lb][1]);
+      acc[kb][lb][2] = mfma16<PREC>(f.ash[kb], f.bch[lb], acc[kb][lb][2]);
+      acc[kb][lb][3] = mfma16<PREC>(f.ash[kb], f.bsh[lb], acc[kb][lb][3]);
+      acc[kb][lb][0] = mfma16<PREC>(f.ach[kb], f.bcl[lb], acc[kb][lb][0]);
+      acc[kb][lb][1] = mfma16<PREC>(f.ach[kb], f.bsl[lb], acc[kb][lb][1]);
+      acc[kb][lb][2] = mfma16<PREC>(f.ash[kb], f.bcl[lb], acc[kb][lb][2]);
+      acc[kb][lb][3] = mfma16<PREC>(f.ash[kb], f.bsl[lb], acc[kb][lb][3]);
+      acc[kb][lb][0] = mfma16<PREC>(f.acl[kb], f.bch[lb], acc[kb][lb][0]);
+      acc[kb][lb][1] = mfma16<PREC>(f.acl[kb], f.bsh[lb], acc[kb][lb][1]);
+      acc[kb][lb][2] = mfma16<PREC>(f.asl[kb], f.bch[lb], acc[kb][lb][2]);
+      acc[kb][lb][3] = mfma16<PREC>(f.asl[kb], f.bsh[lb], acc[kb][lb][3]);
+    }
+}
+
+// Split (hi + lo) contraction.  Software pipeline per 16-corner step s:
+// the table lookups of step s+1 are in flight and the corners of step s+2 are
+// being loaded while the MFMAs of step s run; operand fragments are double
+// buffered (two unrolled half-iterations swap their roles).
+template <int PREC, int NKB, int NLB>
+__global__ __launch_bounds__(256) void k_contract_split(const uint4 *__restrict__ packed,
                                                         const uint2 *__restrict__ tab,
                                                         int64_t chunk, int tiles_l, int kp,
                                                         int lp, float *__restrict__ part) {
@@ -214,84 +351,88 @@ __global__ __launch_bounds__(256) void k_contract_split(const uint2 *__restrict_
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[kb][lb][q][r] = 0.0f;
 
-  const u32x4 *vp = (const u32x4 *)(packed + (size_t)split * chunk + 8 * lh);
+  // corners of step s for this lane: vp + 16 s + j
+  const uint4 *vp = packed + (size_t)split * chunk + 8 * lh;
+  const int nsteps = (int)(chunk >> 4);
+  uint4 c[8];
+  Raw<NKB, NLB> raw;
+  Frag<NKB, NLB> f0, f1;
+  load_corners(c, vp);
+  gather(raw, s_tab, c, kf, lf);
+  build(f0, raw);
+  if (nsteps > 1) {
+    load_corners(c, vp + 16);
+    gather(raw, s_tab, c, kf, lf);
+  }
+  if (nsteps > 2) load_corners(c, vp + 32);
+  int s = 0;
+  // steady state: f0 = step s, raw = lookups of step s+1, c = corners of s+2
+  for (; s + 4 <= nsteps; s += 2) {
+    build(f1, raw);
+    gather(raw, s_tab, c, kf, lf);
+    load_corners(c, vp + 16 * (s + 3));
+    mma<PREC>(acc, f0);
+    build(f0, raw);
+    gather(raw, s_tab, c, kf, lf);
+    if (s + 4 < nsteps) load_corners(c, vp + 16 * (s + 4));
+    mma<PREC>(acc, f1);
+  }
+  // drain: at most three steps left (s, s+1, s+2)
+  for (; s < nsteps; ++s) {
+    if (s + 1 < nsteps) build(f1, raw);
+    if (s + 2 < nsteps) gather(raw, s_tab, c, kf, lf);
+    if (s + 3 < nsteps) load_corners(c, vp + 16 * (s + 3));
+    mma<PREC>(acc, f0);
+    f0 = f1;
+  }
+  store_part<NKB, NLB>(part, acc, split, kp, lp, k0, l0, li, lh);
+}
+
+// Lean form of the same contraction for two waves per SIMD: no software
+// pipeline inside the wave (lookups, fragment build and MFMAs of a step in
+// sequence); the second wave on the SIMD hides the latencies.
+template <int PREC, int NKB, int NLB>
+__global__ __launch_bounds__(256, 2) void k_contract_split_lean(const uint4 *__restrict__ packed,
+                                                                const uint2 *__restrict__ tab,
+                                                                int64_t chunk, int tiles_l,
+                                                                int kp, int lp,
+                                                                float *__restrict__ part) {
+  __shared__ uint2 s_tab[kTabEntries];
+  for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
+  __syncthreads();
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 31, lh = lane >> 5;
+  const int tk = blockIdx.x / tiles_l, tl = blockIdx.x % tiles_l;
+  const int split = blockIdx.y;
+  const int k0 = tk * (64 * NKB) + (wave >> 1) * (32 * NKB);
+  const int l0 = tl * (64 * NLB) + (wave & 1) * (32 * NLB);
+
+  uint32_t kf[NKB], lf[NLB];
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb) kf[kb] = (uint32_t)(k0 + 32 * kb + li);
+#pragma unroll
+  for (int lb = 0; lb < NLB; ++lb) lf[lb] = (uint32_t)(l0 + 32 * lb + li);
+
+  f32x16 acc[NKB][NLB][4];
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+    for (int lb = 0; lb < NLB; ++lb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[kb][lb][q][r] = 0.0f;
+
+  const uint4 *vp = packed + (size_t)split * chunk + 8 * lh;
   for (int64_t vb = 0; vb < chunk; vb += 16) {
-    // this lane's 8 corners: vb + 8*lh + j
-    uint32_t w0[8], w1[8];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const u32x4 q = vp[(vb >> 1) + j];
-      w0[2 * j] = q.x;
-      w1[2 * j] = q.y;
-      w0[2 * j + 1] = q.z;
-      w1[2 * j + 1] = q.w;
-    }
-    u32x4 ach[NKB], acl[NKB], ash[NKB], asl[NKB];
-#pragma unroll
-    for (int kb = 0; kb < NKB; ++kb) {
-      uint2 d[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) d[j] = lds_entry(s_tab, phase_x(kf[kb], w0[j]));
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        ach[kb][j] = __builtin_amdgcn_perm(d[2 * j + 1].x, d[2 * j].x, 0x05040100u);
-        ash[kb][j] = __builtin_amdgcn_perm(d[2 * j + 1].x, d[2 * j].x, 0x07060302u);
-        acl[kb][j] = __builtin_amdgcn_perm(d[2 * j + 1].y, d[2 * j].y, 0x05040100u);
-        asl[kb][j] = __builtin_amdgcn_perm(d[2 * j + 1].y, d[2 * j].y, 0x07060302u);
-      }
-    }
-    u32x4 bch[NLB], bcl[NLB], bsh[NLB], bsl[NLB];
-#pragma unroll
-    for (int lb = 0; lb < NLB; ++lb) {
-      uint2 d[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) d[j] = lds_entry(s_tab, phase_y(lf[lb], w0[j], w1[j]));
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        bch[lb][j] = __builtin_amdgcn_perm(d[2 * j + 1].x, d[2 * j].x, 0x05040100u);
-        bsh[lb][j] = __builtin_amdgcn_perm(d[2 * j + 1].x, d[2 * j].x, 0x07060302u);
-        bcl[lb][j] = __builtin_amdgcn_perm(d[2 * j + 1].y, d[2 * j].y, 0x05040100u);
-        bsl[lb][j] = __builtin_amdgcn_perm(d[2 * j + 1].y, d[2 * j].y, 0x07060302u);
-      }
-    }
-#pragma unroll
-    for (int kb = 0; kb < NKB; ++kb)
-#pragma unroll
-      for (int lb = 0; lb < NLB; ++lb) {
-        if constexpr (PREC == kBF16) {
-#define MF(A, B, C) \
-  C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, A), __builtin_bit_cast(bf16x8, B), C, 0, 0, 0)
-          MF(ach[kb], bch[lb], acc[kb][lb][0]);
-          MF(ach[kb], bcl[lb], acc[kb][lb][0]);
-          MF(acl[kb], bch[lb], acc[kb][lb][0]);
-          MF(ach[kb], bsh[lb], acc[kb][lb][1]);
-          MF(ach[kb], bsl[lb], acc[kb][lb][1]);
-          MF(acl[kb], bsh[lb], acc[kb][lb][1]);
-          MF(ash[kb], bch[lb], acc[kb][lb][2]);
-          MF(ash[kb], bcl[lb], acc[kb][lb][2]);
-          MF(asl[kb], bch[lb], acc[kb][lb][2]);
-          MF(ash[kb], bsh[lb], acc[kb][lb][3]);
-          MF(ash[kb], bsl[lb], acc[kb][lb][3]);
-          MF(asl[kb], bsh[lb], acc[kb][lb][3]);
-#undef MF
-        } else {
-#define MF(A, B, C) \
-  C = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, A), __builtin_bit_cast(f16x8, B), C, 0, 0, 0)
-          MF(ach[kb], bch[lb], acc[kb][lb][0]);
-          MF(ach[kb], bcl[lb], acc[kb][lb][0]);
-          MF(acl[kb], bch[lb], acc[kb][lb][0]);
-          MF(ach[kb], bsh[lb], acc[kb][lb][1]);
-          MF(ach[kb], bsl[lb], acc[kb][lb][1]);
-          MF(acl[kb], bsh[lb], acc[kb][lb][1]);
-          MF(ash[kb], bch[lb], acc[kb][lb][2]);
-          MF(ash[kb], bcl[lb], acc[kb][lb][2]);
-          MF(asl[kb], bch[lb], acc[kb][lb][2]);
-          MF(ash[kb], bsh[lb], acc[kb][lb][3]);
-          MF(ash[kb], bsl[lb], acc[kb][lb][3]);
-          MF(asl[kb], bsh[lb], acc[kb][lb][3]);
-#undef MF
-        }
-      }
+    uint4 c[8];
+    load_corners(c, vp + vb);
+    Raw<NKB, NLB> raw;
+    gather(raw, s_tab, c, kf, lf);
+    Frag<NKB, NLB> f;
+    build(f, raw);
+    mma<PREC>(acc, f);
   }
   store_part<NKB, NLB>(part, acc, split, kp, lp, k0, l0, li, lh);
 }
@@ -299,7 +440,7 @@ __global__ __launch_bounds__(256) void k_contract_split(const uint2 *__restrict_
 // FP32 form: v_mfma_f32_32x32x2_f32, two corners per product (lanes 0-31
 // carry corner j of the lane's group, lanes 32-63 corner 8 + j).
 template <int NKB, int NLB>
-__global__ __launch_bounds__(256) void k_contract_fp32(const uint2 *__restrict__ packed,
+__global__ __launch_bounds__(256) void k_contract_fp32(const uint4 *__restrict__ packed,
                                                        const float2 *__restrict__ tab,
                                                        int64_t chunk, int tiles_l, int kp, int lp,
                                                        float *__restrict__ part) {
@@ -330,26 +471,19 @@ __global__ __launch_bounds__(256) void k_contract_fp32(const uint2 *__restrict__
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[kb][lb][q][r] = 0.0f;
 
-  const u32x4 *vp = (const u32x4 *)(packed + (size_t)split * chunk + 8 * lh);
+  const uint4 *vp = packed + (size_t)split * chunk + 8 * lh;
   for (int64_t vb = 0; vb < chunk; vb += 16) {
-    uint32_t w0[8], w1[8];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const u32x4 q = vp[(vb >> 1) + j];
-      w0[2 * j] = q.x;
-      w1[2 * j] = q.y;
-      w0[2 * j + 1] = q.z;
-      w1[2 * j + 1] = q.w;
-    }
+    uint4 c[8];
+    load_corners(c, vp + vb);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       float2 a[NKB], b[NLB];
 #pragma unroll
       for (int kb = 0; kb < NKB; ++kb)
-        a[kb] = *(const float2 *)((const char *)s_tab + phase_x(kf[kb], w0[j]));
+        a[kb] = *(const float2 *)((const char *)s_tab + phase_x(kf[kb], c[j]));
 #pragma unroll
       for (int lb = 0; lb < NLB; ++lb)
-        b[lb] = *(const float2 *)((const char *)s_tab + phase_y(lf[lb], w0[j], w1[j]));
+        b[lb] = *(const float2 *)((const char *)s_tab + phase_y(lf[lb], c[j]));
 #pragma unroll
       for (int kb = 0; kb < NKB; ++kb)
 #pragma unroll
@@ -364,37 +498,50 @@ __global__ __launch_bounds__(256) void k_contract_fp32(const uint2 *__restrict__
   store_part<NKB, NLB>(part, acc, split, kp, lp, k0, l0, li, lh);
 }
 
-// Tile variants: (id, precision mask, k per wave, l per wave).
+// Tile variants: (id, precision mask, k per wave, l per wave, pipelined).
 static const TileVariant kVariants[] = {
-    {0, 0x7, 32, 32},
-    {1, 0x7, 64, 32},
-    {2, 0x7, 64, 64},
+    {0, 0x7, 32, 32, 1},
+    {1, 0x7, 64, 32, 1},
+    {2, 0x7, 64, 64, 1},
+    {3, 0x6, 32, 32, 0},
+    {4, 0x6, 64, 32, 0},
 };
 
 int n_tile_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 const TileVariant &tile_variant(int i) { return kVariants[i]; }
 
-template <int NKB, int NLB>
-static void launch_contract_t(const FwdPlan &p, const uint2 *packed, const Tables &t, float *part,
+template <int NKB, int NLB, bool PIPE>
+static void launch_contract_t(const FwdPlan &p, const uint4 *packed, const Tables &t, float *part,
                               hipStream_t st) {
   dim3 grid(p.tiles_k * p.tiles_l, p.nsplit), block(256);
-  if (p.prec == kFP32)
+  if (p.prec == kFP32) {
     hipLaunchKernelGGL((k_contract_fp32<NKB, NLB>), grid, block, 0, st, packed, t.w32, p.chunk,
                        p.tiles_l, p.kp, p.lp, part);
-  else if (p.prec == kBF16)
-    hipLaunchKernelGGL((k_contract_split<kBF16, NKB, NLB>), grid, block, 0, st, packed, t.wbf16,
-                       p.chunk, p.tiles_l, p.kp, p.lp, part);
-  else
-    hipLaunchKernelGGL((k_contract_split<kFP16, NKB, NLB>), grid, block, 0, st, packed, t.wfp16,
-                       p.chunk, p.tiles_l, p.kp, p.lp, part);
+  } else if constexpr (PIPE) {
+    if (p.prec == kBF16)
+      hipLaunchKernelGGL((k_contract_split<kBF16, NKB, NLB>), grid, block, 0, st, packed,
+                         t.wbf16, p.chunk, p.tiles_l, p.kp, p.lp, part);
+    else
+      hipLaunchKernelGGL((k_contract_split<kFP16, NKB, NLB>), grid, block, 0, st, packed,
+                         t.wfp16, p.chunk, p.tiles_l, p.kp, p.lp, part);
+  } else {
+    if (p.prec == kBF16)
+      hipLaunchKernelGGL((k_contract_split_lean<kBF16, NKB, NLB>), grid, block, 0, st, packed,
+                         t.wbf16, p.chunk, p.tiles_l, p.kp, p.lp, part);
+    else
+      hipLaunchKernelGGL((k_contract_split_lean<kFP16, NKB, NLB>), grid, block, 0, st, packed,
+                         t.wfp16, p.chunk, p.tiles_l, p.kp, p.lp, part);
+  }
 }
 
-hipError_t launch_contract(const FwdPlan &p, const uint2 *packed, const Tables &t, float *part,
+hipError_t launch_contract(const FwdPlan &p, const uint4 *packed, const Tables &t, float *part,
                            hipStream_t st) {
   switch (p.tile) {
-    case 0: launch_contract_t<1, 1>(p, packed, t, part, st); break;
-    case 1: launch_contract_t<2, 1>(p, packed, t, part, st); break;
-    case 2: launch_contract_t<2, 2>(p, packed, t, part, st); break;
+    case 0: launch_contract_t<1, 1, true>(p, packed, t, part, st); break;
+    case 1: launch_contract_t<2, 1, true>(p, packed, t, part, st); break;
+    case 2: launch_contract_t<2, 2, true>(p, packed, t, part, st); break;
+    case 3: launch_contract_t<1, 1, false>(p, packed, t, part, st); break;
+    case 4: launch_contract_t<2, 1, false>(p, packed, t, part, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -411,18 +558,31 @@ hipError_t launch_contract(const FwdPlan &p, const uint2 *packed, const Tables &
 __global__ __launch_bounds__(256) void k_epilogue(const float *__restrict__ part, int nsplit, int kp,
                                                   int lp, int K, int L, double T,
                                                   float2 *__restrict__ F) {
-  const int l = 1 + blockIdx.x * 256 + threadIdx.x;
+  // 64 consecutive l per block, 4 threads per l summing splits q, q+4, ...
+  __shared__ double4 red[4][64];
+  const int t = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int l = 1 + blockIdx.x * 64 + t;
   const int k = 1 + blockIdx.y;
-  if (l > L) return;
   const size_t plane = (size_t)kp * lp;
-  const size_t o = (size_t)k * lp + l;
   double P = 0.0, U = 0.0, R = 0.0, Q = 0.0;
-  for (int s = 0; s < nsplit; ++s) {
-    const float *b = part + (size_t)s * 4 * plane + o;
-    P += (double)b[0];
-    U += (double)b[plane];
-    R += (double)b[2 * plane];
-    Q += (double)b[3 * plane];
+  if (l <= L) {
+    const size_t o = (size_t)k * lp + l;
+    for (int s = q; s < nsplit; s += 4) {
+      const float *b = part + (size_t)s * 4 * plane + o;
+      P += (double)b[0];
+      U += (double)b[plane];
+      R += (double)b[2 * plane];
+      Q += (double)b[3 * plane];
+    }
+  }
+  red[q][t] = make_double4(P, U, R, Q);
+  __syncthreads();
+  if (q != 0 || l > L) return;
+  for (int w = 1; w < 4; ++w) {
+    P += red[w][t].x;
+    U += red[w][t].y;
+    R += red[w][t].z;
+    Q += red[w][t].w;
   }
   const double a = -T / (4.0 * kPi * kPi * (double)k * (double)l);
   const double pre = a * (P - Q), pim = -a * (R + U);  // F[k, l]
@@ -437,19 +597,31 @@ __global__ __launch_bounds__(256) void k_epilogue(const float *__restrict__ part
 // Axis entries (Steps 2, 3) and DC (Step 1):
 //   F[k,0] = j/(2 pi k) Sx[k],  F[-k,0] = conj F[k,0];  likewise F[0,l];
 //   F[0,0] = area / T.
+// Block: 16 frequency slots x 16 partial sums over the axis chunks (fixed
+// order: chunk c goes to sum c mod 16, the sums are added in order).
 __global__ __launch_bounds__(256) void k_epilogue_axes(const double2 *__restrict__ axis_part,
                                                        int ax_chunks, int K, int L, double T,
                                                        const unsigned long long *__restrict__ area_part,
                                                        int pre_blocks, float2 *__restrict__ F,
                                                        int64_t *__restrict__ area) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  __shared__ double2 red[16][16];
+  const int t = threadIdx.x & 15, q = threadIdx.x >> 4;
+  const int i = blockIdx.x * 16 + t;
   const size_t W = 2 * (size_t)L + 1;
-  if (i < K + L) {
-    double re = 0.0, im = 0.0;
-    for (int c = 0; c < ax_chunks; ++c) {
-      const double2 v = axis_part[(size_t)c * (K + L) + i];
+  const int nslot = K + L;
+  double re = 0.0, im = 0.0;
+  if (i < nslot)
+    for (int c = q; c < ax_chunks; c += 16) {
+      const double2 v = axis_part[(size_t)c * nslot + i];
       re += v.x;
       im += v.y;
+    }
+  red[q][t] = make_double2(re, im);
+  __syncthreads();
+  if (q == 0 && i < nslot) {
+    for (int w = 1; w < 16; ++w) {
+      re += red[w][t].x;
+      im += red[w][t].y;
     }
     const int f = i < K ? i + 1 : i - K + 1;
     const double sc = 1.0 / (2.0 * kPi * (double)f);
@@ -462,11 +634,12 @@ __global__ __launch_bounds__(256) void k_epilogue_axes(const double2 *__restrict
       F[(size_t)K * W + (L - f)] = make_float2(fre, -fim);
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x < 64) {
+  if (blockIdx.x == 0 && threadIdx.x >= 64 && threadIdx.x < 128) {
+    const int a0 = threadIdx.x - 64;
     unsigned long long a = 0;
-    for (int b = threadIdx.x; b < pre_blocks; b += 64) a += area_part[b];
+    for (int b = a0; b < pre_blocks; b += 64) a += area_part[b];
     for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-    if (threadIdx.x == 0) {
+    if (a0 == 0) {
       const long long A = (long long)a;
       F[(size_t)K * W + L] = make_float2((float)((double)A / T), 0.0f);
       if (area) *area = A;
@@ -478,11 +651,11 @@ hipError_t launch_epilogue(const FwdPlan &p, const float *part, const double2 *a
                            const unsigned long long *area_part, float *F, int64_t *area,
                            hipStream_t st) {
   float2 *F2 = (float2 *)F;
-  const int nax = (p.K + p.L + 255) / 256;
+  const int nax = (p.K + p.L + 15) / 16;
   hipLaunchKernelGGL(k_epilogue_axes, dim3(nax > 0 ? nax : 1), dim3(256), 0, st, axis_part,
                      p.ax_chunks, p.K, p.L, (double)p.T, area_part, p.pre_blocks, F2, area);
   if (p.K > 0 && p.L > 0)
-    hipLaunchKernelGGL(k_epilogue, dim3((p.L + 255) / 256, p.K), dim3(256), 0, st, part,
+    hipLaunchKernelGGL(k_epilogue, dim3((p.L + 63) / 64, p.K), dim3(256), 0, st, part,
                        p.nsplit, p.kp, p.lp, p.K, p.L, (double)p.T, F2);
   return hipGetLastError();
 }
@@ -492,18 +665,19 @@ hipError_t launch_epilogue(const FwdPlan &p, const float *part, const double2 *a
 // out[i*V + v] = ((k0+i) * x_v) mod T  (axis 0) or with y_v (axis 1, the
 // sign-free phase), recovered from the same byte offsets the kernels use.
 // ---------------------------------------------------------------------------
-__global__ void k_debug_phases(const uint2 *__restrict__ packed, int64_t V, int axis, int k0,
+__global__ void k_debug_phases(const uint4 *__restrict__ packed, int64_t V, int axis, int k0,
                                int nk, int shift, int32_t *__restrict__ out) {
   const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int i = blockIdx.y;
   if (v >= V || i >= nk) return;
-  const uint2 w = packed[v];
+  uint4 w = packed[v];
+  w.z = 0u;  // the sign-free y phase
   const uint32_t f = (uint32_t)(k0 + i);
-  const uint32_t b = axis == 0 ? phase_x(f, w.x) : phase_y(f, w.x, 0u);
+  const uint32_t b = axis == 0 ? phase_x(f, w) : phase_y(f, w);
   out[(size_t)i * V + v] = (int32_t)((b >> 3) >> shift);
 }
 
-hipError_t launch_debug_phases(const FwdPlan &p, const uint2 *packed, int axis, int k0, int nk,
+hipError_t launch_debug_phases(const FwdPlan &p, const uint4 *packed, int axis, int k0, int nk,
                                int32_t *out, hipStream_t st) {
   if (p.V == 0 || nk == 0) return hipSuccess;
   hipLaunchKernelGGL(k_debug_phases, dim3((unsigned)((p.V + 255) / 256), nk), dim3(256), 0, st,
