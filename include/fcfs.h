@@ -127,6 +127,14 @@ fcfs_status fcfs_forward(fcfs_handle *h, const fcfs_clip *c, fcfs_precision p, v
 fcfs_status fcfs_adjoint(fcfs_handle *h, const fcfs_clip *c, const float *grad_F, float *gx,
                          float *gy, fcfs_precision p, void *ws, size_t ws_bytes);
 
+/* fcfs_adjoint restricted to a band: the caller guarantees grad_F == 0 for
+ * |k| > kmax or |l| > lmax (e.g. a pupil of radius <= min(kmax, lmax)); the
+ * GEMM and the axis sums then cover only the band.  kmax, lmax are clamped to
+ * K, L.  The workspace of fcfs_workspace_size(adjoint = 1) always suffices. */
+fcfs_status fcfs_adjoint_band(fcfs_handle *h, const fcfs_clip *c, const float *grad_F,
+                              int32_t kmax, int32_t lmax, float *gx, float *gy, fcfs_precision p,
+                              void *ws, size_t ws_bytes);
+
 /* Edge-offset gradient: a shift of edge e moves both of its endpoints (along
  * x for a vertical edge, along y for a horizontal one), so
  * g_edge[e] = sum of gx (vertical) or gy (horizontal) over the two corners of
@@ -135,6 +143,15 @@ fcfs_status fcfs_adjoint(fcfs_handle *h, const fcfs_clip *c, const float *grad_F
 fcfs_status fcfs_edge_grad(fcfs_handle *h, const float *gx, const float *gy,
                            const int64_t *hedge, const int64_t *vedge, int64_t V, int64_t E,
                            float *g_edge);
+
+/* Corner coordinates after edge shifts (the parametrisation used for
+ * edge-moving optimisation): x[v] = base_x[v] + rint(offsets[vedge[v]]),
+ * y[v] = base_y[v] + rint(offsets[hedge[v]]).  All arrays (device); offsets
+ * has one entry per edge and should hold integers (the lattice of Sec.
+ * II-A2); fractional values are rounded to nearest. */
+fcfs_status fcfs_apply_edge_offsets(fcfs_handle *h, const int32_t *base_x, const int32_t *base_y,
+                                    const int64_t *hedge, const int64_t *vedge,
+                                    const float *offsets, int64_t V, int32_t *x, int32_t *y);
 
 /* Batched forward: n clips (each with its own V, T, K, L and outputs) in one
  * persistent contraction launch.  The first call with *plan == NULL builds a

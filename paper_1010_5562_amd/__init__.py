@@ -217,3 +217,122 @@ def debug_phases(x, y, s, T: int, k0: int, nk: int, axis: int = 0, handle=None):
     check(h.lib.fcfs_debug_phases(h.ptr, ctypes.byref(c), int(axis), int(k0), int(nk),
                                   ctypes.c_void_p(p.data_ptr())), h.ptr)
     return p
+
+
+def adjoint(x, y, s, T: int, K: int, L: int, grad_F, precision="bf16", band=None, handle=None):
+    """dLoss/dx_v and dLoss/dy_v for a cotangent grad_F = dLoss/dRe F + j dLoss/dIm F
+    ((2K+1, 2L+1) complex64).  band = (kmax, lmax) restricts the work to where
+    grad_F can be nonzero.  Returns (gx, gy) float32 tensors of length V."""
+    import torch
+
+    h = handle or default_handle()
+    h.sync_stream()
+    x, y, s = _corners_on(h.device, x, y, s)
+    V = x.numel()
+    G = torch.as_tensor(grad_F).to(h.device, torch.complex64).contiguous()
+    if G.numel() != (2 * K + 1) * (2 * L + 1):
+        raise ValueError("grad_F must have (2K+1)(2L+1) entries")
+    gx = torch.empty(V, dtype=torch.float32, device=h.device)
+    gy = torch.empty(V, dtype=torch.float32, device=h.device)
+    kmax, lmax = (K, L) if band is None else (int(band[0]), int(band[1]))
+    nbytes = workspace_size(V, T, K, L, precision, adjoint=True)
+    ws = h.workspace(nbytes)
+    c = _clip(x, y, s, V, T, K, L)
+    check(h.lib.fcfs_adjoint_band(h.ptr, ctypes.byref(c), ctypes.c_void_p(G.data_ptr()), kmax, lmax,
+                                  ctypes.c_void_p(gx.data_ptr()), ctypes.c_void_p(gy.data_ptr()),
+                                  _prec(precision), ctypes.c_void_p(ws.data_ptr()),
+                                  ctypes.c_size_t(ws.numel())), h.ptr)
+    return gx, gy
+
+
+def edge_grad(gx, gy, hedge, vedge, n_edges: int, handle=None):
+    """Edge-offset gradient: the sum over the two corners of each edge of gx
+    (vertical edges) or gy (horizontal edges)."""
+    import torch
+
+    h = handle or default_handle()
+    h.sync_stream()
+    dev = h.device
+    hedge = torch.as_tensor(hedge, dtype=torch.int64).to(dev).contiguous()
+    vedge = torch.as_tensor(vedge, dtype=torch.int64).to(dev).contiguous()
+    g = torch.empty(int(n_edges), dtype=torch.float32, device=dev)
+    check(h.lib.fcfs_edge_grad(h.ptr, ctypes.c_void_p(gx.data_ptr()), ctypes.c_void_p(gy.data_ptr()),
+                               ctypes.c_void_p(hedge.data_ptr()), ctypes.c_void_p(vedge.data_ptr()),
+                               gx.numel(), int(n_edges), ctypes.c_void_p(g.data_ptr())), h.ptr)
+    return g
+
+
+class Geometry:
+    """Device-resident polygon geometry for edge-moving optimisation: base
+    corner coordinates, corner signs and the corner -> edge maps."""
+
+    def __init__(self, xy, off, T: int, K: int, L: int | None = None, handle=None):
+        import torch
+
+        self.handle = handle or default_handle()
+        dev = self.handle.device
+        x, y, s, he, ve = loops_to_corners(xy, off)
+        self.T, self.K, self.L = int(T), int(K), int(K if L is None else L)
+        self.n_edges = int(x.size)
+        self.base_x = torch.as_tensor(x).to(dev)
+        self.base_y = torch.as_tensor(y).to(dev)
+        self.s = torch.as_tensor(s).to(dev)
+        self.hedge = torch.as_tensor(he).to(dev)
+        self.vedge = torch.as_tensor(ve).to(dev)
+
+    def corners(self, offsets):
+        """Corner coordinates for edge offsets (one per edge, integer valued)."""
+        import torch
+
+        h = self.handle
+        h.sync_stream()
+        off = offsets.detach().to(h.device, torch.float32).contiguous()
+        if off.numel() != self.n_edges:
+            raise ValueError("one offset per edge")
+        if not torch.equal(off, torch.round(off)):
+            raise FcfsError(-1, "edge offsets must be integers (lattice coordinates)")
+        V = self.base_x.numel()
+        x = torch.empty_like(self.base_x)
+        y = torch.empty_like(self.base_y)
+        check(h.lib.fcfs_apply_edge_offsets(
+            h.ptr, ctypes.c_void_p(self.base_x.data_ptr()), ctypes.c_void_p(self.base_y.data_ptr()),
+            ctypes.c_void_p(self.hedge.data_ptr()), ctypes.c_void_p(self.vedge.data_ptr()),
+            ctypes.c_void_p(off.data_ptr()), V, ctypes.c_void_p(x.data_ptr()),
+            ctypes.c_void_p(y.data_ptr())), h.ptr)
+        return x, y
+
+
+def _autograd_function():
+    import torch
+
+    class FCFSFunction(torch.autograd.Function):
+        """F = FCFS(geometry moved by integer edge offsets); backward runs the
+        adjoint kernels and the edge reduction."""
+
+        @staticmethod
+        def forward(ctx, offsets, geom, precision="bf16", band=None):
+            x, y = geom.corners(offsets)
+            F, _ = forward(x, y, geom.s, geom.T, geom.K, geom.L, precision=precision,
+                           handle=geom.handle)
+            ctx.geom, ctx.precision, ctx.band = geom, precision, band
+            ctx.save_for_backward(x, y)
+            return F
+
+        @staticmethod
+        def backward(ctx, grad_F):
+            x, y = ctx.saved_tensors
+            g = ctx.geom
+            gx, gy = adjoint(x, y, g.s, g.T, g.K, g.L, grad_F.contiguous(), ctx.precision,
+                             band=ctx.band, handle=g.handle)
+            ge = edge_grad(gx, gy, g.hedge, g.vedge, g.n_edges, handle=g.handle)
+            return ge, None, None, None
+
+    return FCFSFunction
+
+
+def __getattr__(name):
+    if name == "FCFSFunction":
+        f = _autograd_function()
+        globals()["FCFSFunction"] = f
+        return f
+    raise AttributeError(name)

@@ -1,0 +1,477 @@
+// Adjoint of the FCFS forward transform with respect to the corner
+// coordinates (gfx950).
+//
+// Differentiating the closed forms of Prop. 3 (Sec. III-C1), with
+// e(t) = e^{-j 2 pi t / T} and the torch cotangent G = dL/dRe F + j dL/dIm F,
+// dL/dtheta = Re sum conj(G[k,l]) dF[k,l]/dtheta:
+//  * F[k,l] = alpha s e(kx) e(ly) gives dF/dx_v = s_v (j/(2 pi l)) e(k x_v) e(l y_v)
+//    and dF/dy_v = s_v (j/(2 pi k)) e(k x_v) e(l y_v) (alpha (-j w k) = j/(2 pi l)).
+//    Folding (k,l) with (-k,-l) leaves k > 0; writing e = c - j s for both
+//    coordinates turns the sum into s_v X_v^T W Y_v with X_v = [cos; sin](k x_v),
+//    Y_v = [cos; sin](l y_v) and a real matrix W built from G: one GEMM
+//    (vertices x 2K) . (2K x 4L) for both gradients, whose rows are dotted
+//    with Y_v on the fly (never stored).
+//  * F[k,0] = (j/(2 pi k)) sum s y e(kx): dF/dx_v = s_v y_v e(k x_v)/T,
+//    dF/dy_v = s_v (j/(2 pi k)) e(k x_v); F[0,l] likewise; F[0,0] = area/T:
+//    dF/dx_v = s_v y_v / T, dF/dy_v = s_v x_v / T.  These are evaluated per
+//    corner in FP64.
+#include "fcfs_device.h"
+
+namespace fcfs {
+
+// ---------------------------------------------------------------------------
+// W from the cotangent.  For 1 <= k <= kb, 1 <= l <= lb (zero outside the
+// band), with M'[k,l] = M[k,l] + conj(M[-k,-l]) and a + jb = M'[k,l],
+// a'' + jb'' = M'[k,-l]:
+//   W(cos k, cos l) = a + a'',  W(cos k, sin l) = b - b'',
+//   W(sin k, cos l) = b + b'',  W(sin k, sin l) = a'' - a.
+// Columns: [x: cos l | x: sin l | y: cos l | y: sin l], each lb wide; rows:
+// [cos k | sin k], each kb long.  Stored transposed, Wf[n * R + r], FP32.
+// The largest |W| is folded into *wmax (float bits, non-negative).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_adj_w(const float2 *__restrict__ G, int K, int L, int kmax,
+                                               int lmax, int kb, int lb, float *__restrict__ Wf,
+                                               unsigned int *__restrict__ wmax) {
+  const int l = 1 + blockIdx.x * 256 + threadIdx.x;
+  const int k = 1 + blockIdx.y;
+  if (l > lb) return;
+  const int R = 2 * kb;
+  double Wcc = 0, Wcs = 0, Wsc = 0, Wss = 0, Ycc = 0, Ycs = 0, Ysc = 0, Yss = 0;
+  if (k <= kmax && l <= lmax) {
+    const size_t WL = 2 * (size_t)L + 1;
+    const float2 gpp = G[(size_t)(K + k) * WL + (L + l)];  // G[k, l]
+    const float2 gmm = G[(size_t)(K - k) * WL + (L - l)];  // G[-k, -l]
+    const float2 gpm = G[(size_t)(K + k) * WL + (L - l)];  // G[k, -l]
+    const float2 gmp = G[(size_t)(K - k) * WL + (L + l)];  // G[-k, l]
+    // conj(G) * j c = (c gi, c gr); folded with the conjugate of the mirror
+    const double cl = 1.0 / (2.0 * kPi * l), ck = 1.0 / (2.0 * kPi * k);
+    // x gradient: c = 1/(2 pi l) with the sign of l
+    double a = cl * ((double)gpp.y - gmm.y), b = cl * ((double)gpp.x + gmm.x);
+    double a2 = -cl * ((double)gpm.y - gmp.y), b2 = -cl * ((double)gpm.x + gmp.x);
+    Wcc = a + a2;
+    Wss = a2 - a;
+    Wsc = b + b2;
+    Wcs = b - b2;
+    // y gradient: c = 1/(2 pi k), k > 0 on both sides
+    a = ck * ((double)gpp.y - gmm.y);
+    b = ck * ((double)gpp.x + gmm.x);
+    a2 = ck * ((double)gpm.y - gmp.y);
+    b2 = ck * ((double)gpm.x + gmp.x);
+    Ycc = a + a2;
+    Yss = a2 - a;
+    Ysc = b + b2;
+    Ycs = b - b2;
+  }
+  const int rc = k - 1, rs = kb + k - 1;
+  const size_t nxc = (size_t)(l - 1), nxs = (size_t)(lb + l - 1);
+  const size_t nyc = (size_t)(2 * lb + l - 1), nys = (size_t)(3 * lb + l - 1);
+  const float v[8] = {(float)Wcc, (float)Wsc, (float)Wcs, (float)Wss,
+                      (float)Ycc, (float)Ysc, (float)Ycs, (float)Yss};
+  Wf[nxc * R + rc] = v[0];
+  Wf[nxc * R + rs] = v[1];
+  Wf[nxs * R + rc] = v[2];
+  Wf[nxs * R + rs] = v[3];
+  Wf[nyc * R + rc] = v[4];
+  Wf[nyc * R + rs] = v[5];
+  Wf[nys * R + rc] = v[6];
+  Wf[nys * R + rs] = v[7];
+  float m = 0.f;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) m = fmaxf(m, fabsf(v[i]));
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0 && m > 0.f) atomicMax(wmax, __float_as_uint(m));
+}
+
+// Split W into hi + lo 16-bit parts after scaling by 2^e, e chosen from the
+// largest |W| so that the binary16 range is never exceeded (bf16 uses the
+// same scale).  scale[0] = e (as int), written by block 0.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_adj_split(const float *__restrict__ Wf, int64_t n,
+                                                   const unsigned int *__restrict__ wmax,
+                                                   uint16_t *__restrict__ whi,
+                                                   uint16_t *__restrict__ wlo,
+                                                   int *__restrict__ scale) {
+  const float m = __uint_as_float(*wmax);
+  int e = 0;
+  if (m > 0.f) {
+    int ex;
+    frexpf(m, &ex);  // m < 2^ex
+    e = 14 - ex;     // m * 2^e < 2^14
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) scale[0] = e;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const float w = ldexpf(Wf[i], e);
+    if constexpr (PREC == kBF16) {
+      const __bf16 h = (__bf16)w;
+      const __bf16 lo = (__bf16)(w - (float)h);
+      whi[i] = __builtin_bit_cast(uint16_t, h);
+      wlo[i] = __builtin_bit_cast(uint16_t, lo);
+    } else {
+      const _Float16 h = (_Float16)w;
+      const _Float16 lo = (_Float16)(w - (float)h);
+      whi[i] = __builtin_bit_cast(uint16_t, h);
+      wlo[i] = __builtin_bit_cast(uint16_t, lo);
+    }
+  }
+}
+
+__global__ void k_fill_u32(unsigned int *p, int n, unsigned int v) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Axis and DC coefficients, folded over +-f:
+//   P_k = conj(G[k,0]) + G[-k,0],  Q_l = conj(G[0,l]) + G[0,-l],  G00 real part.
+// coef layout: [P_1..P_K | Q_1..Q_L] as double2, then Re G[0,0].
+__global__ void k_adj_axcoef(const float2 *__restrict__ G, int K, int L, int kmax, int lmax,
+                             double2 *__restrict__ coef) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const size_t WL = 2 * (size_t)L + 1;
+  if (i < K) {
+    const int k = i + 1;
+    double2 p = make_double2(0.0, 0.0);
+    if (k <= kmax) {
+      const float2 a = G[(size_t)(K + k) * WL + L], b = G[(size_t)(K - k) * WL + L];
+      p = make_double2((double)a.x + b.x, (double)b.y - a.y);
+    }
+    coef[i] = p;
+  } else if (i < K + L) {
+    const int l = i - K + 1;
+    double2 q = make_double2(0.0, 0.0);
+    if (l <= lmax) {
+      const float2 a = G[(size_t)K * WL + (L + l)], b = G[(size_t)K * WL + (L - l)];
+      q = make_double2((double)a.x + b.x, (double)b.y - a.y);
+    }
+    coef[i] = q;
+  } else if (i == K + L) {
+    coef[i] = make_double2((double)G[(size_t)K * WL + L].x, 0.0);
+  }
+}
+
+// Per corner, FP64: the axis and DC parts of gx, gy (written, not added).
+// sum_f Re[c_f e(f t)] with e(f t) = conj(w^f), w = e^{j 2 pi ts / N}: the
+// powers come from repeated multiplication, restarted from the exact table
+// every 32 steps.
+__global__ __launch_bounds__(256) void k_adj_axis(const int32_t *__restrict__ x,
+                                                  const int32_t *__restrict__ y,
+                                                  const uint4 *__restrict__ packed,
+                                                  const double2 *__restrict__ w64,
+                                                  const double2 *__restrict__ coef, int64_t V,
+                                                  int K, int L, int kmax, int lmax, double T,
+                                                  float *__restrict__ gx, float *__restrict__ gy) {
+  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (v >= V) return;
+  const uint4 c = packed[v];
+  const double sg = c.z ? -1.0 : 1.0;
+  const double xv = (double)x[v], yv = (double)y[v];
+  double sx1 = 0.0, sx2 = 0.0;  // sum Re[P e(kx)],  sum Re[P j/(2 pi k) e(kx)]
+  {
+    const uint32_t ph = c.x >> 3;
+    const double2 w1 = w64[ph];
+    double2 w = w1;
+    for (int k = 1; k <= kmax; ++k) {
+      if ((k & 31) == 0) w = w64[((uint32_t)k * ph) & (uint32_t)(kTabN - 1)];
+      const double2 p = coef[k - 1];
+      // e(kx) = w.x - j w.y
+      const double re = p.x * w.x + p.y * w.y;   // Re[P e]
+      const double im = p.y * w.x - p.x * w.y;   // Im[P e]
+      sx1 += re;
+      sx2 += -im / (2.0 * kPi * k);              // Re[j P e] / (2 pi k)
+      const double nx = w.x * w1.x - w.y * w1.y, ny = w.x * w1.y + w.y * w1.x;
+      w = make_double2(nx, ny);
+    }
+  }
+  double sy1 = 0.0, sy2 = 0.0;  // sum Re[Q e(ly)],  sum Re[Q j/(2 pi l) e(ly)]
+  {
+    const uint32_t ph = c.y >> 3;
+    const double2 w1 = w64[ph];
+    double2 w = w1;
+    for (int l = 1; l <= lmax; ++l) {
+      if ((l & 31) == 0) w = w64[((uint32_t)l * ph) & (uint32_t)(kTabN - 1)];
+      const double2 q = coef[K + l - 1];
+      const double re = q.x * w.x + q.y * w.y;
+      const double im = q.y * w.x - q.x * w.y;
+      sy1 += re;
+      sy2 += -im / (2.0 * kPi * l);
+      const double nx = w.x * w1.x - w.y * w1.y, ny = w.x * w1.y + w.y * w1.x;
+      w = make_double2(nx, ny);
+    }
+  }
+  const double g00 = coef[K + L].x;
+  gx[v] = (float)(sg * (yv / T * sx1 + sy2 + yv * g00 / T));
+  gy[v] = (float)(sg * (sx2 + xv / T * sy1 + xv * g00 / T));
+}
+
+// ---------------------------------------------------------------------------
+// Main term: t_v = X_v^T W on MFMA (rows = 32 corners per wave, inner = the
+// 2*kb frequencies, NB column blocks of 32 at a time), each finished column
+// block dotted with Y_v at once; the per-corner partial sums are reduced
+// across the 32 columns held by the lanes and added to gx, gy.
+// ---------------------------------------------------------------------------
+constexpr int kAdjNB = 4;
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_adj_gemm_split(const uint4 *__restrict__ packed,
+                                                        const uint2 *__restrict__ tab,
+                                                        const float2 *__restrict__ tab32,
+                                                        const uint16_t *__restrict__ whi,
+                                                        const uint16_t *__restrict__ wlo,
+                                                        const int *__restrict__ scale, int64_t V,
+                                                        int kb, int lb, float *__restrict__ gx,
+                                                        float *__restrict__ gy) {
+  __shared__ uint2 s_tab[kTabEntries];
+  for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 31, lh = lane >> 5;
+  const int64_t vbase = (int64_t)blockIdx.x * 128 + wave * 32;
+  const int R = 2 * kb, NC = 4 * lb;
+  const uint4 ca = packed[vbase + li];  // this lane's A row
+  // the 16 output rows this lane holds
+  uint32_t ys8[16];
+  bool neg[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const uint4 c = packed[vbase + 8 * (r >> 2) + 4 * lh + (r & 3)];
+    ys8[r] = c.y;
+    neg[r] = c.z != 0u;
+  }
+  float sx[16], sy[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) sx[r] = sy[r] = 0.f;
+  for (int cg = 0; cg < NC; cg += 32 * kAdjNB) {
+    f32x16 acc[kAdjNB];
+#pragma unroll
+    for (int nb = 0; nb < kAdjNB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[nb][r] = 0.f;
+    for (int ib = 0; ib < kb; ib += 16) {
+      uint2 d[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        d[j] = lds_entry(s_tab, phase_x((uint32_t)(1 + ib + 8 * lh + j), ca));
+      u32x4 ach, ash, acl, asl;
+      pack4(d, ach, ash, acl, asl);
+#pragma unroll
+      for (int nb = 0; nb < kAdjNB; ++nb) {
+        const size_t n = (size_t)(cg + 32 * nb + li);
+        const size_t oc = n * R + ib + 8 * lh, os = oc + kb;
+        const u32x4 bch = *(const u32x4 *)(whi + oc), bcl = *(const u32x4 *)(wlo + oc);
+        const u32x4 bsh = *(const u32x4 *)(whi + os), bsl = *(const u32x4 *)(wlo + os);
+        acc[nb] = mfma16<PREC>(ach, bch, acc[nb]);
+        acc[nb] = mfma16<PREC>(ach, bcl, acc[nb]);
+        acc[nb] = mfma16<PREC>(acl, bch, acc[nb]);
+        acc[nb] = mfma16<PREC>(ash, bsh, acc[nb]);
+        acc[nb] = mfma16<PREC>(ash, bsl, acc[nb]);
+        acc[nb] = mfma16<PREC>(asl, bsh, acc[nb]);
+      }
+    }
+    // dot the finished columns with Y_v: column n = (q, l), q = n / lb
+#pragma unroll
+    for (int nb = 0; nb < kAdjNB; ++nb) {
+      const int n0 = cg + 32 * nb;
+      const int q = n0 / lb;
+      const uint32_t l = (uint32_t)(n0 - q * lb + li + 1);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float2 w = tab32[(l * (ys8[r] >> 3)) & (uint32_t)(kTabN - 1)];
+        const float yv = (q & 1) ? w.y : w.x;
+        if (q < 2)
+          sx[r] = fmaf(acc[nb][r], yv, sx[r]);
+        else
+          sy[r] = fmaf(acc[nb][r], yv, sy[r]);
+      }
+    }
+  }
+  // sum over the 32 columns of each half-wave (fixed butterfly order)
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    for (int o = 1; o < 32; o <<= 1) {
+      sx[r] += __shfl_xor(sx[r], o, 64);
+      sy[r] += __shfl_xor(sy[r], o, 64);
+    }
+  const float inv = ldexpf(1.0f, -scale[0]);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    if (li != r) continue;
+    const int64_t v = vbase + 8 * (r >> 2) + 4 * lh + (r & 3);
+    if (v < V) {
+      const float sg = neg[r] ? -inv : inv;
+      gx[v] += sg * sx[r];
+      gy[v] += sg * sy[r];
+    }
+  }
+}
+
+// FP32 main term: v_mfma_f32_32x32x2_f32, two frequencies per product.
+__global__ __launch_bounds__(256) void k_adj_gemm_fp32(const uint4 *__restrict__ packed,
+                                                       const float2 *__restrict__ tab32g,
+                                                       const float *__restrict__ Wf, int64_t V,
+                                                       int kb, int lb, float *__restrict__ gx,
+                                                       float *__restrict__ gy) {
+  __shared__ float2 s_tab[kTabEntries];
+  for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab32g[i];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 31, lh = lane >> 5;
+  const int64_t vbase = (int64_t)blockIdx.x * 128 + wave * 32;
+  const int R = 2 * kb, NC = 4 * lb;
+  const uint4 ca = packed[vbase + li];
+  uint32_t ys8[16];
+  bool neg[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const uint4 c = packed[vbase + 8 * (r >> 2) + 4 * lh + (r & 3)];
+    ys8[r] = c.y;
+    neg[r] = c.z != 0u;
+  }
+  float sx[16], sy[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) sx[r] = sy[r] = 0.f;
+  for (int cg = 0; cg < NC; cg += 32 * kAdjNB) {
+    f32x16 acc[kAdjNB];
+#pragma unroll
+    for (int nb = 0; nb < kAdjNB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[nb][r] = 0.f;
+    for (int ib = 0; ib < kb; ib += 2) {
+      const float2 a = *(const float2 *)((const char *)s_tab + phase_x((uint32_t)(1 + ib + lh), ca));
+#pragma unroll
+      for (int nb = 0; nb < kAdjNB; ++nb) {
+        const size_t n = (size_t)(cg + 32 * nb + li);
+        const float bc = Wf[n * R + ib + lh], bs = Wf[n * R + kb + ib + lh];
+        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, bc, acc[nb], 0, 0, 0);
+        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, bs, acc[nb], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int nb = 0; nb < kAdjNB; ++nb) {
+      const int n0 = cg + 32 * nb;
+      const int q = n0 / lb;
+      const uint32_t l = (uint32_t)(n0 - q * lb + li + 1);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float2 w = s_tab[(l * (ys8[r] >> 3)) & (uint32_t)(kTabN - 1)];
+        const float yv = (q & 1) ? w.y : w.x;
+        if (q < 2)
+          sx[r] = fmaf(acc[nb][r], yv, sx[r]);
+        else
+          sy[r] = fmaf(acc[nb][r], yv, sy[r]);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    for (int o = 1; o < 32; o <<= 1) {
+      sx[r] += __shfl_xor(sx[r], o, 64);
+      sy[r] += __shfl_xor(sy[r], o, 64);
+    }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    if (li != r) continue;
+    const int64_t v = vbase + 8 * (r >> 2) + 4 * lh + (r & 3);
+    if (v < V) {
+      const float sg = neg[r] ? -1.f : 1.f;
+      gx[v] += sg * sx[r];
+      gy[v] += sg * sy[r];
+    }
+  }
+}
+
+hipError_t launch_adjoint(const AdjPlan &a, const int32_t *x, const int32_t *y, const int8_t *s,
+                          const float *gradF, const Tables &t, void *ws, float *gx, float *gy,
+                          hipStream_t st) {
+  char *w = (char *)ws;
+  const uint4 *packed = (const uint4 *)(w + a.off_packed);
+  double2 *coef = (double2 *)(w + a.off_coef);
+  float *Wf = (float *)(w + a.off_wf);
+  uint16_t *whi = (uint16_t *)(w + a.off_whi), *wlo = (uint16_t *)(w + a.off_wlo);
+  unsigned int *wmax = (unsigned int *)(w + a.off_scale);
+  int *scale = (int *)(w + a.off_scale + 64);
+  const float2 *G = (const float2 *)gradF;
+  (void)s;
+  // axis and DC parts first: they write gx, gy
+  hipLaunchKernelGGL(k_adj_axcoef, dim3((a.K + a.L + 1 + 255) / 256), dim3(256), 0, st, G, a.K,
+                     a.L, a.kmax, a.lmax, coef);
+  if (a.V > 0)
+    hipLaunchKernelGGL(k_adj_axis, dim3((unsigned)((a.V + 255) / 256)), dim3(256), 0, st, x, y,
+                       packed, t.w64, coef, a.V, a.K, a.L, a.kmax, a.lmax, (double)a.T, gx, gy);
+  if (a.kmax == 0 || a.lmax == 0 || a.V == 0) return hipGetLastError();
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, wmax, 1, 0u);
+  hipLaunchKernelGGL(k_adj_w, dim3((a.lb + 255) / 256, a.kb), dim3(256), 0, st, G, a.K, a.L,
+                     a.kmax, a.lmax, a.kb, a.lb, Wf, wmax);
+  const unsigned blocks = (unsigned)(a.vpad / 128);
+  if (a.prec == kFP32) {
+    hipLaunchKernelGGL(k_adj_gemm_fp32, dim3(blocks), dim3(256), 0, st, packed, t.w32, Wf, a.V,
+                       a.kb, a.lb, gx, gy);
+  } else {
+    const int64_t n = (int64_t)a.R * a.NC;
+    const unsigned sb = (unsigned)std::min<int64_t>(1024, (n + 255) / 256);
+    if (a.prec == kBF16) {
+      hipLaunchKernelGGL(k_adj_split<kBF16>, dim3(sb), dim3(256), 0, st, Wf, n, wmax, whi, wlo,
+                         scale);
+      hipLaunchKernelGGL(k_adj_gemm_split<kBF16>, dim3(blocks), dim3(256), 0, st, packed,
+                         t.wbf16, t.w32, whi, wlo, scale, a.V, a.kb, a.lb, gx, gy);
+    } else {
+      hipLaunchKernelGGL(k_adj_split<kFP16>, dim3(sb), dim3(256), 0, st, Wf, n, wmax, whi, wlo,
+                         scale);
+      hipLaunchKernelGGL(k_adj_gemm_split<kFP16>, dim3(blocks), dim3(256), 0, st, packed,
+                         t.wfp16, t.w32, whi, wlo, scale, a.V, a.kb, a.lb, gx, gy);
+    }
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Edge-offset gradient: each edge collects the gradient of its two corners
+// along its normal direction (x for vertical edges, y for horizontal).  Two
+// contributions per edge, so the atomic sum is order independent.
+// ---------------------------------------------------------------------------
+__global__ void k_zero_f32(float *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+}
+
+__global__ void k_edge_grad(const float *__restrict__ gx, const float *__restrict__ gy,
+                            const int64_t *__restrict__ hedge, const int64_t *__restrict__ vedge,
+                            int64_t V, int64_t E, float *__restrict__ g_edge) {
+  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (v >= V) return;
+  const int64_t h = hedge[v], e = vedge[v];
+  if (h >= 0 && h < E) atomicAdd(&g_edge[h], gy[v]);
+  if (e >= 0 && e < E) atomicAdd(&g_edge[e], gx[v]);
+}
+
+hipError_t launch_edge_grad(const float *gx, const float *gy, const int64_t *hedge,
+                            const int64_t *vedge, int64_t V, int64_t E, float *g_edge,
+                            hipStream_t st) {
+  if (E > 0)
+    hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, st, g_edge, E);
+  if (V > 0)
+    hipLaunchKernelGGL(k_edge_grad, dim3((unsigned)((V + 255) / 256)), dim3(256), 0, st, gx, gy,
+                       hedge, vedge, V, E, g_edge);
+  return hipGetLastError();
+}
+
+// Corner coordinates after edge shifts: a vertical edge moves its two corners
+// along x, a horizontal edge along y (offsets rounded to the lattice).
+__global__ void k_apply_offsets(const int32_t *__restrict__ bx, const int32_t *__restrict__ by,
+                                const int64_t *__restrict__ hedge, const int64_t *__restrict__ vedge,
+                                const float *__restrict__ off, int64_t V, int32_t *__restrict__ x,
+                                int32_t *__restrict__ y) {
+  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (v >= V) return;
+  x[v] = bx[v] + (int32_t)rintf(off[vedge[v]]);
+  y[v] = by[v] + (int32_t)rintf(off[hedge[v]]);
+}
+
+hipError_t launch_apply_offsets(const int32_t *bx, const int32_t *by, const int64_t *hedge,
+                                const int64_t *vedge, const float *off, int64_t V, int32_t *x,
+                                int32_t *y, hipStream_t st) {
+  if (V > 0)
+    hipLaunchKernelGGL(k_apply_offsets, dim3((unsigned)((V + 255) / 256)), dim3(256), 0, st, bx,
+                       by, hedge, vedge, off, V, x, y);
+  return hipGetLastError();
+}
+
+}  // namespace fcfs

@@ -243,6 +243,47 @@ fcfs_status make_plan(fcfs_handle *h, int64_t V, int T, int K, int L, int prec, 
   return FCFS_OK;
 }
 
+fcfs_status make_adj_plan(fcfs_handle *h, int64_t V, int T, int K, int L, int kmax, int lmax,
+                          int prec, fcfs::AdjPlan *p) {
+  fcfs_status st = check_dims(h, V, T, K, L, prec);
+  if (st) return st;
+  if (kmax < 0 || lmax < 0) return fail(h, FCFS_ERR_INVALID_ARG, "band must be >= 0");
+  fcfs::AdjPlan a{};
+  a.prec = prec;
+  a.T = T;
+  a.K = K;
+  a.L = L;
+  a.kmax = std::min(kmax, K);
+  a.lmax = std::min(lmax, L);
+  a.V = V;
+  a.shift = fcfs::kTabBits - (int)std::lround(std::log2((double)T));
+  a.kb = (int)round_up(std::max(a.kmax, 1), 16);
+  a.lb = (int)round_up(std::max(a.lmax, 1), 32);
+  a.R = 2 * a.kb;
+  a.NC = 4 * a.lb;
+  a.vpad = round_up(std::max<int64_t>(V, 1), 128);
+  a.pre_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(a.vpad, 256)));
+  size_t off = 0;
+  a.off_packed = off;
+  off += align256(sizeof(uint4) * (size_t)a.vpad);
+  a.off_area = off;
+  off += align256(sizeof(unsigned long long) * (size_t)a.pre_blocks);
+  a.off_coef = off;
+  off += align256(sizeof(double2) * (size_t)(K + L + 1));
+  const size_t nw = (size_t)a.R * a.NC;
+  a.off_wf = off;
+  off += align256(sizeof(float) * nw);
+  a.off_whi = off;
+  off += align256(2 * nw);
+  a.off_wlo = off;
+  off += align256(2 * nw);
+  a.off_scale = off;
+  off += 256;
+  a.bytes = off;
+  *p = a;
+  return FCFS_OK;
+}
+
 fcfs_status check_clip(fcfs_handle *h, const fcfs_clip *c, bool need_out) {
   if (!c) return fail(h, FCFS_ERR_INVALID_ARG, "clip is NULL");
   if (c->V > 0 && (!c->x || !c->y || !c->s))
@@ -535,7 +576,12 @@ fcfs_status fcfs_workspace_size(const fcfs_clip *c, fcfs_precision p, int adjoin
   fcfs_status st = make_plan(nullptr, c->V, c->T, c->K, c->L, (int)p, -1, &q);
   if (st) return st;
   *bytes = q.bytes;
-  if (adjoint) return fail(nullptr, FCFS_ERR_UNSUPPORTED, "adjoint not built");
+  if (adjoint) {
+    fcfs::AdjPlan a;
+    st = make_adj_plan(nullptr, c->V, c->T, c->K, c->L, c->K, c->L, (int)p, &a);
+    if (st) return st;
+    *bytes = a.bytes;
+  }
   return FCFS_OK;
 }
 
@@ -586,16 +632,67 @@ fcfs_status fcfs_debug_phases(fcfs_handle *h, const fcfs_clip *c, int32_t axis, 
   return FCFS_OK;
 }
 
+fcfs_status fcfs_adjoint_band(fcfs_handle *h, const fcfs_clip *c, const float *grad_F,
+                              int32_t kmax, int32_t lmax, float *gx, float *gy, fcfs_precision p,
+                              void *ws, size_t ws_bytes) {
+  fcfs_status st = enter(h);
+  if (st) return st;
+  if ((st = check_clip(h, c, false))) return st;
+  if (!grad_F) return fail(h, FCFS_ERR_INVALID_ARG, "grad_F is NULL");
+  if (c->V > 0 && (!gx || !gy)) return fail(h, FCFS_ERR_INVALID_ARG, "gx/gy are NULL");
+  fcfs::AdjPlan a;
+  if ((st = make_adj_plan(h, c->V, c->T, c->K, c->L, kmax, lmax, (int)p, &a))) return st;
+  if (ws_bytes < a.bytes)
+    return fail(h, FCFS_ERR_WORKSPACE,
+                "workspace too small: need " + std::to_string(a.bytes) + " bytes, got " +
+                    std::to_string(ws_bytes));
+  if (!ws || ((uintptr_t)ws & 255u)) return fail(h, FCFS_ERR_WORKSPACE, "workspace NULL or misaligned");
+  // pre-pass over the padded corner block (same records as the forward)
+  FwdPlan q{};
+  q.T = c->T;
+  q.V = c->V;
+  q.vpad = a.vpad;
+  q.shift = a.shift;
+  q.pre_blocks = a.pre_blocks;
+  hipError_t e;
+  ProfScope ps(h, kProfAdjoint);
+  if ((e = fcfs::launch_prepass(q, c->x, c->y, c->s, ws_at<uint4>(ws, a.off_packed),
+                                ws_at<unsigned long long>(ws, a.off_area), h->stream)))
+    return hip_fail(h, e, "pre-pass launch");
+  if ((e = fcfs::launch_adjoint(a, c->x, c->y, c->s, grad_F, h->tab, ws, gx, gy, h->stream)))
+    return hip_fail(h, e, "adjoint launch");
+  return FCFS_OK;
+}
+
 fcfs_status fcfs_adjoint(fcfs_handle *h, const fcfs_clip *c, const float *grad_F, float *gx,
                          float *gy, fcfs_precision p, void *ws, size_t ws_bytes) {
-  (void)c; (void)grad_F; (void)gx; (void)gy; (void)p; (void)ws; (void)ws_bytes;
-  return fail(h, FCFS_ERR_UNSUPPORTED, "adjoint not built");
+  if (!c) return fail(h, FCFS_ERR_INVALID_ARG, "clip is NULL");
+  return fcfs_adjoint_band(h, c, grad_F, c->K, c->L, gx, gy, p, ws, ws_bytes);
 }
 
 fcfs_status fcfs_edge_grad(fcfs_handle *h, const float *gx, const float *gy, const int64_t *hedge,
                            const int64_t *vedge, int64_t V, int64_t E, float *g_edge) {
-  (void)gx; (void)gy; (void)hedge; (void)vedge; (void)V; (void)E; (void)g_edge;
-  return fail(h, FCFS_ERR_UNSUPPORTED, "edge gradient not built");
+  fcfs_status st = enter(h);
+  if (st) return st;
+  if (V < 0 || E < 0) return fail(h, FCFS_ERR_INVALID_ARG, "negative size");
+  if ((V > 0 && (!gx || !gy || !hedge || !vedge)) || (E > 0 && !g_edge))
+    return fail(h, FCFS_ERR_INVALID_ARG, "NULL array");
+  hipError_t e = fcfs::launch_edge_grad(gx, gy, hedge, vedge, V, E, g_edge, h->stream);
+  if (e) return hip_fail(h, e, "edge gradient launch");
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_apply_edge_offsets(fcfs_handle *h, const int32_t *base_x, const int32_t *base_y,
+                                    const int64_t *hedge, const int64_t *vedge,
+                                    const float *offsets, int64_t V, int32_t *x, int32_t *y) {
+  fcfs_status st = enter(h);
+  if (st) return st;
+  if (V < 0) return fail(h, FCFS_ERR_INVALID_ARG, "negative size");
+  if (V > 0 && (!base_x || !base_y || !hedge || !vedge || !offsets || !x || !y))
+    return fail(h, FCFS_ERR_INVALID_ARG, "NULL array");
+  hipError_t e = fcfs::launch_apply_offsets(base_x, base_y, hedge, vedge, offsets, V, x, y, h->stream);
+  if (e) return hip_fail(h, e, "offset launch");
+  return FCFS_OK;
 }
 
 fcfs_status fcfs_batch_workspace_size(const fcfs_clip *c, int32_t n, fcfs_precision p,

@@ -71,6 +71,31 @@ hipError_t launch_epilogue(const FwdPlan &p, const float *part, const double2 *a
 hipError_t launch_debug_phases(const FwdPlan &p, const uint4 *packed, int axis, int k0, int nk,
                                int32_t *out, hipStream_t st);
 
+// Geometry of one adjoint call (Hermitian-folded real GEMM, vertices x
+// frequencies).  kmax, lmax: the band outside which the cotangent is zero.
+struct AdjPlan {
+  int prec;
+  int T, K, L, kmax, lmax;
+  int64_t V;
+  int shift;
+  int kb, lb;        // kmax, lmax padded to multiples of 16 and 32
+  int R, NC;         // GEMM inner rows 2*kb and columns 4*lb
+  int64_t vpad;      // V padded to the 128-corner block of the GEMM
+  int pre_blocks;
+  size_t off_packed, off_area, off_coef, off_wf, off_whi, off_wlo, off_scale, bytes;
+};
+
+hipError_t launch_adjoint(const AdjPlan &a, const int32_t *x, const int32_t *y, const int8_t *s,
+                          const float *gradF, const Tables &t, void *ws, float *gx, float *gy,
+                          hipStream_t st);
+hipError_t launch_edge_grad(const float *gx, const float *gy, const int64_t *hedge,
+                            const int64_t *vedge, int64_t V, int64_t E, float *g_edge,
+                            hipStream_t st);
+
+hipError_t launch_apply_offsets(const int32_t *bx, const int32_t *by, const int64_t *hedge,
+                                const int64_t *vedge, const float *off, int64_t V, int32_t *x,
+                                int32_t *y, hipStream_t st);
+
 // Contraction tile variants (wave tile in k x l frequencies; 2 x 2 waves).
 struct TileVariant {
   int id;

@@ -1,0 +1,133 @@
+"""GPU parity of the adjoint (edge-offset gradient) against the FP64 oracle.
+
+The oracle's analytic gradient is itself pinned to central finite differences
+(test_oracle_pins).  Tolerances relative to max |g|: FP32 contraction 1e-5,
+split-bf16 / split-fp16 1e-4.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GTOL = {"fp32": 1e-5, "bf16": 1e-4, "fp16": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1010_5562_amd as P
+
+    torch.cuda.set_device(0)
+    return P
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _gpu_edge_grad(P, clip, G, prec, band=None):
+    x, y, s, he, ve = P.loops_to_corners(clip.xy, clip.off)
+    Gd = torch.as_tensor(G.astype(np.complex64)).cuda()
+    gx, gy = P.adjoint(x, y, s, clip.T, clip.K, clip.L, Gd, precision=prec, band=band)
+    ge = P.edge_grad(gx, gy, he, ve, x.size)
+    torch.cuda.synchronize()
+    return ge.cpu().numpy().astype(np.float64)
+
+
+def _rand_G(K, L, seed):
+    rng = np.random.default_rng(seed)
+    return rng.normal(size=(2 * K + 1, 2 * L + 1)) + 1j * rng.normal(size=(2 * K + 1, 2 * L + 1))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_adjoint_random_cotangent(P, oracle_lib, prec):
+    # a linear loss Re sum conj(G) F with a dense random G: every (k, l),
+    # axes and DC included; K != L, several GEMM column groups, ragged corners
+    T, K, L = 512, 37, 150
+    clip = synth.clip(41, T, K, L, n_polygons=40)
+    _say(f"adjoint V={clip.n_vertices} T={T} K={K} L={L} prec={prec}")
+    G = _rand_G(K, L, 1)
+    want = oracle_lib.edge_grad(clip.xy, clip.off, T, K, L, G.astype(np.complex64))
+    got = _gpu_edge_grad(P, clip, G, prec)
+    e = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+    _say(f"  err/max|g| = {e:.3e}")
+    assert e <= GTOL[prec]
+
+
+def test_adjoint_band_matches_full(P):
+    T, K, L = 1024, 64, 64
+    clip = synth.clip(42, T, K, L, n_polygons=60)
+    G = _rand_G(K, L, 2)
+    kk, ll = np.meshgrid(np.arange(-K, K + 1), np.arange(-L, L + 1), indexing="ij")
+    G[(kk**2 + ll**2) > 20**2] = 0
+    full = _gpu_edge_grad(P, clip, G, "fp32")
+    band = _gpu_edge_grad(P, clip, G, "fp32", band=(20, 20))
+    assert np.max(np.abs(full - band)) <= 1e-5 * np.max(np.abs(full))
+
+
+def _pupil(K, L, r):
+    kk, ll = np.meshgrid(np.arange(-K, K + 1), np.arange(-L, L + 1), indexing="ij")
+    return (kk**2 + ll**2 <= r * r).astype(np.float64)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_pupil_loss_gradient(P, oracle_lib, prec):
+    # L = sum |H F - G_t|^2, H a circular pupil of radius 0.35 K, G_t the
+    # pupil-filtered spectrum of a second seeded clip (computed by the oracle).
+    T, K = 4096, 255
+    r = 0.35 * K
+    rb = int(np.floor(r))
+    clip = synth.clip(5, T, K, min_vertices=20_000)
+    clip2 = synth.clip(6, T, K, min_vertices=20_000)
+    _say(f"pupil loss V={clip.n_vertices} T={T} K={K} prec={prec}")
+    Hp = _pupil(K, K, r)
+    # oracle spectra on the band only (H is zero outside)
+    kk, ll = np.nonzero(Hp)
+    kb, lb = kk - K, ll - K
+    Gt = np.zeros_like(Hp, dtype=np.complex128)
+    Gt[kk, ll] = oracle_lib.cfs_points(clip2.xy, clip2.off, T, kb, lb)
+    Gt = Gt.astype(np.complex64).astype(np.complex128)
+    Fo = np.zeros_like(Gt)
+    Fo[kk, ll] = oracle_lib.cfs_points(clip.xy, clip.off, T, kb, lb)
+    Go = 2 * Hp * (Hp * Fo - Gt)
+    rng = np.random.default_rng(7)
+    edges = rng.choice(clip.n_vertices, 256, replace=False)
+    want = oracle_lib.edge_grad(clip.xy, clip.off, T, K, K, Go, edges=edges)
+    # GPU: forward, cotangent from the loss, adjoint restricted to the pupil band
+    x, y, s, he, ve = P.loops_to_corners(clip.xy, clip.off)
+    F, _ = P.forward(x, y, s, T, K, K, precision=prec)
+    Hd = torch.as_tensor(Hp, dtype=torch.float32).cuda()
+    Gtd = torch.as_tensor(Gt.astype(np.complex64)).cuda()
+    Gd = 2 * Hd * (Hd * F - Gtd)
+    gx, gy = P.adjoint(x, y, s, T, K, K, Gd, precision=prec, band=(rb, rb))
+    ge = P.edge_grad(gx, gy, he, ve, x.size).cpu().numpy().astype(np.float64)
+    e = float(np.max(np.abs(ge[edges] - want)) / np.max(np.abs(want)))
+    _say(f"  err/max|g| over {edges.size} edges = {e:.3e}")
+    assert e <= GTOL[prec]
+
+
+def test_autograd_function(P, oracle_lib):
+    T, K = 256, 24
+    clip = synth.clip(43, T, K, n_polygons=12)
+    geom = P.Geometry(clip.xy, clip.off, T, K)
+    off = torch.zeros(geom.n_edges, dtype=torch.float32, device="cuda", requires_grad=True)
+    F = P.FCFSFunction.apply(off, geom, "fp32")
+    Hp = torch.as_tensor(_pupil(K, K, 0.35 * K), dtype=torch.float32).cuda()
+    loss = ((Hp * F).abs() ** 2).sum()
+    loss.backward()
+    Fo, _ = oracle_lib.cfs_grid(clip.xy, clip.off, T, K, K)
+    Hn = _pupil(K, K, 0.35 * K)
+    want = oracle_lib.edge_grad(clip.xy, clip.off, T, K, K, 2 * Hn * Hn * Fo)
+    got = off.grad.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(got - want)) <= 1e-5 * np.max(np.abs(want))
+    # an integer shift of the edges moves the corners accordingly
+    shift = torch.zeros(geom.n_edges, device="cuda")
+    shift[0] = 3.0
+    x, y = geom.corners(shift)
+    assert int((x.cpu() - geom.base_x.cpu()).abs().sum() + (y.cpu() - geom.base_y.cpu()).abs().sum()) == 6
+    with pytest.raises(P.FcfsError):
+        geom.corners(shift + 0.5)
