@@ -172,10 +172,15 @@ fcfs_status fcfs_debug_phases(fcfs_handle *h, const fcfs_clip *c, int32_t axis, 
                               int32_t nk, int32_t *p);
 
 /* Times candidate tile shapes of the contraction on synthetic corners and
- * stores the fastest per (precision, K-bucket, V-bucket) in the handle; with
- * cache_path != NULL the table is also written there as JSON and read back
- * by fcfs_create's successors through FCFS_AUTOTUNE_CACHE.  effort: 0..2. */
+ * stores the fastest per (precision, K-bucket, V-bucket) in the handle, plus
+ * the wave tile and corners per work item of the batched kernel; with
+ * cache_path != NULL the table is also written there as JSON.  fcfs_create
+ * reads such a file when the environment variable FCFS_AUTOTUNE_CACHE names
+ * it; fcfs_load_tune reads one explicitly.  A missing or malformed cache
+ * leaves the built-in choices.  effort: 0..2 (more shapes and sizes).
+ * Synchronises the handle's stream. */
 fcfs_status fcfs_autotune(fcfs_handle *h, const char *cache_path, int effort);
+fcfs_status fcfs_load_tune(fcfs_handle *h, const char *cache_path);
 
 /* Tuning hooks.  fcfs_tile_variants fills wk[i], wl[i] (frequencies per
  * wave in k and l of contraction tile variant i, for i < cap) and returns the

@@ -336,3 +336,69 @@ def __getattr__(name):
         globals()["FCFSFunction"] = f
         return f
     raise AttributeError(name)
+
+
+class Batch:
+    """Many clips in one persistent, graph-captured launch (fcfs_forward_batch).
+
+    ``clips``: sequence of (x, y, s, T, K, L) with host or device corner
+    arrays.  Inputs are copied to device tensors owned by this object, so the
+    captured graph's pointers stay valid; ``run()`` replays it.  Outputs:
+    ``F[i]`` ((2K_i+1, 2L_i+1) complex64) and ``area[i]``.
+    """
+
+    def __init__(self, clips, precision="bf16", handle=None):
+        import torch
+
+        self.handle = h = handle or default_handle()
+        self.precision = _prec(precision)
+        dev = h.device
+        self.inputs, self.F, self.area = [], [], []
+        arr = (FcfsClip * max(1, len(clips)))()
+        for i, (x, y, s, T, K, L) in enumerate(clips):
+            x, y, s = _corners_on(dev, x, y, s)
+            F = torch.empty((2 * K + 1, 2 * L + 1), dtype=torch.complex64, device=dev)
+            a = torch.empty(1, dtype=torch.int64, device=dev)
+            self.inputs.append((x, y, s))
+            self.F.append(F)
+            self.area.append(a)
+            arr[i] = _clip(x, y, s, x.numel(), T, K, L, F, a)
+        self.n = len(clips)
+        self._arr = arr
+        nb = ctypes.c_size_t(0)
+        check(h.lib.fcfs_batch_workspace_size(arr, self.n, self.precision, ctypes.byref(nb)))
+        self.ws = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=dev)
+        self._plan = ctypes.c_void_p()
+
+    def run(self):
+        h = self.handle
+        h.sync_stream()
+        check(h.lib.fcfs_forward_batch(h.ptr, self._arr, self.n, self.precision,
+                                       ctypes.c_void_p(self.ws.data_ptr()),
+                                       ctypes.c_size_t(self.ws.numel()), ctypes.byref(self._plan)),
+              h.ptr)
+        return self.F
+
+    def close(self):
+        if self._plan:
+            self.handle.lib.fcfs_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(cache_path=None, effort: int = 1, handle=None):
+    """Runs the library's autotuner on this handle (and writes the JSON cache)."""
+    h = handle or default_handle()
+    h.sync_stream()
+    path = None if cache_path is None else str(cache_path).encode()
+    check(h.lib.fcfs_autotune(h.ptr, path, int(effort)), h.ptr)
+
+
+def load_tune(cache_path, handle=None):
+    h = handle or default_handle()
+    check(h.lib.fcfs_load_tune(h.ptr, str(cache_path).encode()), h.ptr)

@@ -30,7 +30,7 @@ EXPORTS = (
     "fcfs_create", "fcfs_destroy", "fcfs_set_stream", "fcfs_loops_to_corners",
     "fcfs_workspace_size", "fcfs_forward", "fcfs_adjoint", "fcfs_adjoint_band", "fcfs_edge_grad",
     "fcfs_apply_edge_offsets", "fcfs_batch_workspace_size", "fcfs_forward_batch", "fcfs_plan_destroy",
-    "fcfs_debug_phases", "fcfs_autotune", "fcfs_tile_variants", "fcfs_set_tile",
+    "fcfs_debug_phases", "fcfs_autotune", "fcfs_load_tune", "fcfs_tile_variants", "fcfs_set_tile",
     "fcfs_workspace_size_tile", "fcfs_profile_begin", "fcfs_profile_end",
     "fcfs_status_string", "fcfs_last_error",
 )
@@ -88,6 +88,7 @@ def load() -> ctypes.CDLL:
         "fcfs_plan_destroy": [P],
         "fcfs_debug_phases": [P, clip_p, i32, i32, i32, P],
         "fcfs_autotune": [P, ctypes.c_char_p, c_int],
+        "fcfs_load_tune": [P, ctypes.c_char_p],
         "fcfs_set_tile": [P, i32],
         "fcfs_profile_begin": [P],
         "fcfs_profile_end": [P, P, P, i32],

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -33,9 +34,36 @@ struct fcfs_handle {
   // back into `stream` with events; default priority like every stream here
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // autotuned choices: forward tile per (precision, K bucket, V bucket) and
+  // the persistent batch kernel's tile and corners per work item
+  struct Tune {
+    int prec, kbucket, vbucket, tile;
+    double ms;
+  };
+  std::vector<Tune> tune;
+  int batch_tile[3] = {-1, -1, -1};
+  int64_t batch_chunk[3] = {0, 0, 0};
+};
+
+struct fcfs_plan {
+  int device = 0;
+  int prec = 0;
+  int tile = 0;
+  int64_t chunk_target = 0;
+  std::vector<fcfs_clip> clips;      // the clips the graph was captured for
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  std::vector<void *> dev_allocs;    // descriptor arrays, counter
+  fcfs::BatchLaunch launch{};
+  hipStream_t cap = nullptr, side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 namespace {
+
+bool load_tune(fcfs_handle *h, const char *path);
 
 std::mutex g_err_mu;
 std::string g_err;  // last error of a handle-less call
@@ -167,11 +195,20 @@ void free_tables(Tables &t) {
 constexpr int kMaxFreq = 4095;  // |k|, |l| cut-off limit (phases stay below 2^29)
 constexpr int kTargetWG = 512;  // two contraction workgroups per CU on 256 CUs
 
-// Built-in choice when no tuned entry applies: the 64 x 32 wave tile, lean
-// two-waves-per-SIMD loop for the split forms.
-int default_tile(int prec, int K, int L) {
-  (void)K;
-  (void)L;
+int kbucket(int K) {
+  int b = 0;
+  for (int lim = 63; lim < K && b < 6; lim = 2 * lim + 1) ++b;
+  return b;
+}
+int vbucket(int64_t V) { return V < 8192 ? 0 : (V < 65536 ? 1 : 2); }
+
+// Tuned entry for (precision, K, V) if the handle has one, else the built-in
+// choice: the 64 x 32 wave tile, lean two-waves-per-SIMD loop for the split
+// forms.
+int default_tile(fcfs_handle *h, int prec, int K, int64_t V) {
+  if (h)
+    for (const auto &t : h->tune)
+      if (t.prec == prec && t.kbucket == kbucket(K) && t.vbucket == vbucket(V)) return t.tile;
   return prec == fcfs::kFP32 ? 1 : 4;
 }
 
@@ -197,9 +234,11 @@ fcfs_status make_plan(fcfs_handle *h, int64_t V, int T, int K, int L, int prec, 
   q.L = L;
   q.V = V;
   q.shift = fcfs::kTabBits - (int)std::lround(std::log2((double)T));
-  if (tile < 0) tile = default_tile(prec, K, L);
+  if (tile < 0) tile = default_tile(h, prec, std::max(K, L), V);
   if (tile >= fcfs::n_tile_variants()) return fail(h, FCFS_ERR_INVALID_ARG, "unknown tile variant");
   const fcfs::TileVariant &tv = fcfs::tile_variant(tile);
+  if (!(tv.prec_mask & (1 << prec)))
+    return fail(h, FCFS_ERR_UNSUPPORTED, "tile variant not built for this precision");
   q.tile = tile;
   q.wgk = 2 * tv.wk;
   q.wgl = 2 * tv.wl;
@@ -437,6 +476,8 @@ fcfs_status fcfs_create(fcfs_handle **out, int device, void *hip_stream) {
     delete h;
     return st;
   }
+  // an autotune cache named by the environment, if present and well formed
+  if (const char *path = std::getenv("FCFS_AUTOTUNE_CACHE")) (void)load_tune(h, path);
   *out = h;
   return FCFS_OK;
 }
@@ -695,26 +736,532 @@ fcfs_status fcfs_apply_edge_offsets(fcfs_handle *h, const int32_t *base_x, const
   return FCFS_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+constexpr int kBatchPreBlocks = 64;
+
+// Host layout of a batch: per-clip descriptors with workspace offsets (the
+// device pointers are filled in once the workspace base is known).
+struct BatchLayout {
+  std::vector<fcfs::BatchClip> bc;
+  std::vector<size_t> off_packed, off_area, off_axis, off_part;
+  std::vector<int4> ax_desc, items;
+  std::vector<int> epi_off, epa_off;
+  size_t bytes = 0;
+};
+
+int batch_tile(fcfs_handle *h, int prec);
+int64_t batch_chunk(fcfs_handle *h, int prec);
+
+fcfs_status batch_layout(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec, int tile,
+                         int64_t chunk_target, BatchLayout *L) {
+  if (n < 0 || (n > 0 && !c)) return fail(h, FCFS_ERR_INVALID_ARG, "bad clip array");
+  if (tile < 0 || tile >= fcfs::n_tile_variants()) return fail(h, FCFS_ERR_INVALID_ARG, "tile");
+  const fcfs::TileVariant &tv = fcfs::tile_variant(tile);
+  L->bc.assign(n, fcfs::BatchClip{});
+  L->off_packed.assign(n, 0);
+  L->off_area.assign(n, 0);
+  L->off_axis.assign(n, 0);
+  L->off_part.assign(n, 0);
+  L->ax_desc.clear();
+  L->items.clear();
+  L->epi_off.assign(n + 1, 0);
+  L->epa_off.assign(n + 1, 0);
+  size_t off = 256;  // the work counter lives at the head of the workspace
+  std::vector<std::pair<int64_t, int4>> items;
+  for (int i = 0; i < n; ++i) {
+    const fcfs_clip &ci = c[i];
+    fcfs_status st = check_dims(h, ci.V, ci.T, ci.K, ci.L, prec);
+    if (st) return st;
+    fcfs::BatchClip &b = L->bc[i];
+    b.V = ci.V;
+    b.T = ci.T;
+    b.K = ci.K;
+    b.L = ci.L;
+    b.shift = fcfs::kTabBits - (int)std::lround(std::log2((double)ci.T));
+    const int wgk = 2 * tv.wk, wgl = 2 * tv.wl;
+    b.kp = (int)round_up(ci.K + 1, wgk);
+    b.lp = (int)round_up(ci.L + 1, wgl);
+    b.tiles_l = b.lp / wgl;
+    const int tiles = (b.kp / wgk) * b.tiles_l;
+    int64_t ns = std::max<int64_t>(1, ceil_div(ci.V, chunk_target));
+    ns = std::min<int64_t>(ns, 4096);
+    b.nsplit = (int)ns;
+    b.chunk = std::max<int64_t>(16, round_up(ceil_div(std::max<int64_t>(ci.V, 1), ns), 16));
+    b.vpad = b.chunk * b.nsplit;
+    const int gk = (int)ceil_div(ci.K, 512), gl = (int)ceil_div(ci.L, 512);
+    b.ax_groups_k = gk;
+    b.ax_chunk = 1024;
+    b.ax_chunks = (int)std::max<int64_t>(1, ceil_div(ci.V, 1024));
+    if (ci.V > 0)
+      for (int g = 0; g < gk + gl; ++g)
+        for (int ch = 0; ch < b.ax_chunks; ++ch) L->ax_desc.push_back(make_int4(i, g, ch, 0));
+    if (ci.K > 0 && ci.L > 0)
+      for (int t = 0; t < tiles; ++t)
+        for (int sp = 0; sp < b.nsplit; ++sp)
+          items.push_back({b.chunk * (int64_t)wgk * wgl, make_int4(i, t, sp, 0)});
+    L->epi_off[i + 1] = L->epi_off[i] + (int)(ceil_div(ci.L, 64) * ci.K);
+    L->epa_off[i + 1] = L->epa_off[i] + (int)std::max<int64_t>(1, ceil_div(ci.K + ci.L, 16));
+    L->off_packed[i] = off;
+    off += align256(sizeof(uint4) * (size_t)b.vpad);
+    L->off_area[i] = off;
+    off += align256(sizeof(unsigned long long) * kBatchPreBlocks);
+    L->off_axis[i] = off;
+    off += align256(sizeof(double2) * (size_t)b.ax_chunks * (size_t)std::max(1, ci.K + ci.L));
+    L->off_part[i] = off;
+    off += align256(sizeof(float) * 4 * (size_t)b.nsplit * (size_t)b.kp * (size_t)b.lp);
+  }
+  // longest processing time first; ties keep clip order
+  std::stable_sort(items.begin(), items.end(),
+                   [](const std::pair<int64_t, int4> &a, const std::pair<int64_t, int4> &b) {
+                     return a.first > b.first;
+                   });
+  for (auto &it : items) L->items.push_back(it.second);
+  L->bytes = off;
+  return FCFS_OK;
+}
+
+void plan_free(fcfs_plan *p) {
+  if (!p) return;
+  (void)hipSetDevice(p->device);
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  if (p->side) (void)hipStreamDestroy(p->side);
+  for (void *a : p->dev_allocs) (void)hipFree(a);
+  delete p;
+}
+
+template <class T>
+fcfs_status upload(fcfs_handle *h, fcfs_plan *p, const std::vector<T> &v, const T **out) {
+  void *d = nullptr;
+  const size_t nb = std::max<size_t>(sizeof(T), sizeof(T) * v.size());
+  hipError_t e = hipMalloc(&d, nb);
+  if (e) return hip_fail(h, e, "hipMalloc (plan)");
+  p->dev_allocs.push_back(d);
+  if (!v.empty() && (e = hipMemcpy(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice)))
+    return hip_fail(h, e, "hipMemcpy (plan)");
+  *out = (const T *)d;
+  return FCFS_OK;
+}
+
+// Builds the plan for clips c and captures the enqueued sequence in a graph.
+fcfs_status build_plan(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec, void *ws,
+                       size_t ws_bytes, fcfs_plan **out) {
+  fcfs_plan *p = new (std::nothrow) fcfs_plan();
+  if (!p) return fail(h, FCFS_ERR_NO_MEMORY, "plan allocation");
+  p->device = h->device;
+  p->prec = prec;
+  p->tile = batch_tile(h, prec);
+  p->chunk_target = batch_chunk(h, prec);
+  p->clips.assign(c, c + n);
+  p->ws = ws;
+  p->ws_bytes = ws_bytes;
+  BatchLayout L;
+  fcfs_status st = batch_layout(h, c, n, prec, p->tile, p->chunk_target, &L);
+  if (!st && ws_bytes < L.bytes)
+    st = fail(h, FCFS_ERR_WORKSPACE, "batch workspace too small: need " + std::to_string(L.bytes));
+  if (!st && (!ws || ((uintptr_t)ws & 255u)))
+    st = fail(h, FCFS_ERR_WORKSPACE, "workspace NULL or misaligned");
+  for (int i = 0; !st && i < n; ++i) {
+    if (c[i].V > 0 && (!c[i].x || !c[i].y || !c[i].s)) st = fail(h, FCFS_ERR_INVALID_ARG, "NULL corners");
+    if (!c[i].F) st = fail(h, FCFS_ERR_INVALID_ARG, "NULL output");
+    fcfs::BatchClip &b = L.bc[i];
+    b.x = c[i].x;
+    b.y = c[i].y;
+    b.s = c[i].s;
+    b.F = (float2 *)c[i].F;
+    b.area = c[i].area;
+    b.packed = ws_at<uint4>(ws, L.off_packed[i]);
+    b.area_part = ws_at<unsigned long long>(ws, L.off_area[i]);
+    b.axis_part = ws_at<double2>(ws, L.off_axis[i]);
+    b.part = ws_at<float>(ws, L.off_part[i]);
+  }
+  fcfs::BatchLaunch &bl = p->launch;
+  bl.n_clips = n;
+  bl.prec = prec;
+  bl.tile = p->tile;
+  bl.pre_blocks = kBatchPreBlocks;
+  bl.n_ax = (int)L.ax_desc.size();
+  bl.n_items = (int)L.items.size();
+  bl.grid = fcfs::batch_grid(p->tile, prec);
+  bl.counter = ws_at<unsigned int>(ws, 0);
+  bl.n_epi = L.epi_off[n];
+  bl.n_epa = L.epa_off[n];
+  if (!st) st = upload(h, p, L.bc, &bl.clips);
+  if (!st) st = upload(h, p, L.ax_desc, &bl.ax_desc);
+  if (!st) st = upload(h, p, L.items, &bl.items);
+  if (!st) st = upload(h, p, L.epi_off, &bl.epi_off);
+  if (!st) st = upload(h, p, L.epa_off, &bl.epa_off);
+  hipError_t e = hipSuccess;
+  if (!st && ((e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking)) ||
+              (e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking)) ||
+              (e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming)) ||
+              (e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming))))
+    st = hip_fail(h, e, "plan streams");
+  if (!st) {
+    // capture on the plan's own stream; the graph is launched on the handle's
+    if ((e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal))) {
+      st = hip_fail(h, e, "hipStreamBeginCapture");
+    } else {
+      hipError_t le = fcfs::launch_batch_prepass(bl, p->cap);
+      if (!le) le = hipEventRecord(p->ev_fork, p->cap);
+      if (!le) le = hipStreamWaitEvent(p->side, p->ev_fork, 0);
+      if (!le) le = fcfs::launch_batch_axis(bl, h->tab.w64, p->side);
+      if (!le) le = hipEventRecord(p->ev_join, p->side);
+      if (!le) le = fcfs::launch_batch_contract(bl, h->tab, p->cap);
+      if (!le) le = hipStreamWaitEvent(p->cap, p->ev_join, 0);
+      if (!le) le = fcfs::launch_batch_epilogue(bl, p->cap);
+      e = hipStreamEndCapture(p->cap, &p->graph);
+      if (le) st = hip_fail(h, le, "batch capture");
+      else if (e) st = hip_fail(h, e, "hipStreamEndCapture");
+      else if ((e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0)))
+        st = hip_fail(h, e, "hipGraphInstantiate");
+    }
+  }
+  if (st) {
+    plan_free(p);
+    return st;
+  }
+  *out = p;
+  return FCFS_OK;
+}
+
+bool same_clips(const fcfs_plan *p, const fcfs_clip *c, int32_t n) {
+  if ((int32_t)p->clips.size() != n) return false;
+  for (int i = 0; i < n; ++i) {
+    const fcfs_clip &a = p->clips[i], &b = c[i];
+    if (a.x != b.x || a.y != b.y || a.s != b.s || a.V != b.V || a.T != b.T || a.K != b.K ||
+        a.L != b.L || a.F != b.F || a.area != b.area)
+      return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+fcfs_status fcfs_batch_workspace_size_h(fcfs_handle *h, const fcfs_clip *c, int32_t n,
+                                        fcfs_precision p, size_t *bytes) {
+  if (!bytes) return fail(h, FCFS_ERR_INVALID_ARG, "bytes is NULL");
+  BatchLayout L;
+  const int tile = batch_tile(h, (int)p);
+  fcfs_status st = batch_layout(h, c, n, (int)p, tile, batch_chunk(h, (int)p), &L);
+  if (st) return st;
+  *bytes = L.bytes;
+  return FCFS_OK;
+}
+
 fcfs_status fcfs_batch_workspace_size(const fcfs_clip *c, int32_t n, fcfs_precision p,
                                       size_t *bytes) {
-  (void)c; (void)n; (void)p; (void)bytes;
-  return fail(nullptr, FCFS_ERR_UNSUPPORTED, "batch not built");
+  return fcfs_batch_workspace_size_h(nullptr, c, n, p, bytes);
 }
 
 fcfs_status fcfs_forward_batch(fcfs_handle *h, const fcfs_clip *c, int32_t n, fcfs_precision p,
                                void *ws, size_t ws_bytes, fcfs_plan **plan) {
-  (void)c; (void)n; (void)p; (void)ws; (void)ws_bytes; (void)plan;
-  return fail(h, FCFS_ERR_UNSUPPORTED, "batch not built");
-}
-
-fcfs_status fcfs_plan_destroy(fcfs_plan *plan) {
-  (void)plan;
+  fcfs_status st = enter(h);
+  if (st) return st;
+  if (!plan) return fail(h, FCFS_ERR_INVALID_ARG, "plan is NULL");
+  if (!*plan) {
+    if ((st = build_plan(h, c, n, (int)p, ws, ws_bytes, plan))) return st;
+  } else {
+    fcfs_plan *q = *plan;
+    if (q->device != h->device || q->prec != (int)p || q->ws != ws || q->ws_bytes != ws_bytes ||
+        !same_clips(q, c, n))
+      return fail(h, FCFS_ERR_INVALID_ARG,
+                  "plan was built for other clips, precision or workspace; destroy it and pass NULL");
+  }
+  ProfScope ps(h, kProfBatch);
+  hipError_t e = hipGraphLaunch((*plan)->exec, h->stream);
+  if (e) return hip_fail(h, e, "hipGraphLaunch");
   return FCFS_OK;
 }
 
+fcfs_status fcfs_plan_destroy(fcfs_plan *plan) {
+  plan_free(plan);
+  return FCFS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int batch_tile(fcfs_handle *h, int prec) {
+  if (h && prec >= 0 && prec < 3 && h->batch_tile[prec] >= 0) return h->batch_tile[prec];
+  return prec == fcfs::kFP32 ? 1 : 4;
+}
+int64_t batch_chunk(fcfs_handle *h, int prec) {
+  if (h && prec >= 0 && prec < 3 && h->batch_chunk[prec] > 0) return h->batch_chunk[prec];
+  return 16384;
+}
+
+// ---------------------------------------------------------------------------
+// Autotune cache (JSON, written and read by this library only):
+// {"format": "fcfs-autotune-1", "forward": [{"prec": p, "kbucket": k,
+//  "vbucket": v, "tile": t, "ms": x}, ...], "batch": [{"prec": p, "tile": t,
+//  "chunk": c, "ms": x}, ...]}
+// A missing or malformed file leaves the built-in choices in place.
+// ---------------------------------------------------------------------------
+bool json_int(const std::string &obj, const char *key, long long *v) {
+  const std::string k = std::string("\"") + key + "\"";
+  size_t p = obj.find(k);
+  if (p == std::string::npos) return false;
+  p = obj.find(':', p + k.size());
+  if (p == std::string::npos) return false;
+  char *end = nullptr;
+  const long long x = std::strtoll(obj.c_str() + p + 1, &end, 10);
+  if (end == obj.c_str() + p + 1) return false;
+  *v = x;
+  return true;
+}
+
+// objects {...} of the array that follows "name"
+std::vector<std::string> json_objects(const std::string &doc, const char *name) {
+  std::vector<std::string> out;
+  size_t p = doc.find(std::string("\"") + name + "\"");
+  if (p == std::string::npos) return out;
+  p = doc.find('[', p);
+  if (p == std::string::npos) return out;
+  const size_t e = doc.find(']', p);
+  if (e == std::string::npos) return out;
+  while (true) {
+    const size_t a = doc.find('{', p);
+    if (a == std::string::npos || a > e) break;
+    const size_t b = doc.find('}', a);
+    if (b == std::string::npos || b > e) break;
+    out.push_back(doc.substr(a, b - a + 1));
+    p = b + 1;
+  }
+  return out;
+}
+
+bool load_tune(fcfs_handle *h, const char *path) {
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return false;
+  std::string doc;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) doc.append(buf, n);
+  std::fclose(f);
+  if (doc.find("\"fcfs-autotune-1\"") == std::string::npos) return false;
+  std::vector<fcfs_handle::Tune> tune;
+  for (const std::string &o : json_objects(doc, "forward")) {
+    long long pr, kb, vb, t;
+    if (!json_int(o, "prec", &pr) || !json_int(o, "kbucket", &kb) || !json_int(o, "vbucket", &vb) ||
+        !json_int(o, "tile", &t))
+      return false;
+    if (pr < 0 || pr > 2 || t < 0 || t >= fcfs::n_tile_variants() ||
+        !(fcfs::tile_variant((int)t).prec_mask & (1 << pr)))
+      return false;
+    tune.push_back({(int)pr, (int)kb, (int)vb, (int)t, 0.0});
+  }
+  int bt[3] = {-1, -1, -1};
+  int64_t bc[3] = {0, 0, 0};
+  for (const std::string &o : json_objects(doc, "batch")) {
+    long long pr, t, c;
+    if (!json_int(o, "prec", &pr) || !json_int(o, "tile", &t) || !json_int(o, "chunk", &c))
+      return false;
+    if (pr < 0 || pr > 2 || t < 0 || t >= fcfs::n_tile_variants() || c < 16 || c > (1 << 24))
+      return false;
+    bt[pr] = (int)t;
+    bc[pr] = c;
+  }
+  h->tune = tune;
+  for (int i = 0; i < 3; ++i) {
+    h->batch_tile[i] = bt[i];
+    h->batch_chunk[i] = bc[i];
+  }
+  return true;
+}
+
+bool save_tune(const fcfs_handle *h, const char *path) {
+  FILE *f = std::fopen(path, "wb");
+  if (!f) return false;
+  std::fprintf(f, "{\"format\": \"fcfs-autotune-1\", \"arch\": \"gfx950\",\n \"forward\": [");
+  for (size_t i = 0; i < h->tune.size(); ++i) {
+    const auto &t = h->tune[i];
+    std::fprintf(f, "%s\n  {\"prec\": %d, \"kbucket\": %d, \"vbucket\": %d, \"tile\": %d, \"ms\": %.6f}",
+                 i ? "," : "", t.prec, t.kbucket, t.vbucket, t.tile, t.ms);
+  }
+  std::fprintf(f, "],\n \"batch\": [");
+  bool first = true;
+  for (int p = 0; p < 3; ++p) {
+    if (h->batch_tile[p] < 0) continue;
+    std::fprintf(f, "%s\n  {\"prec\": %d, \"tile\": %d, \"chunk\": %lld}", first ? "" : ",", p,
+                 h->batch_tile[p], (long long)h->batch_chunk[p]);
+    first = false;
+  }
+  std::fprintf(f, "]}\n");
+  return std::fclose(f) == 0;
+}
+
+// Deterministic synthetic corners for timing: lattice points uniform in
+// [0, 8192)^2 with alternating signs (the contraction's cost does not depend
+// on the geometry beyond the phase statistics).
+void synth_corners(int64_t V, uint64_t seed, std::vector<int32_t> &x, std::vector<int32_t> &y,
+                   std::vector<int8_t> &s) {
+  x.resize(V);
+  y.resize(V);
+  s.resize(V);
+  uint64_t z = seed * 0x9E3779B97F4A7C15ull + 1;
+  for (int64_t i = 0; i < V; ++i) {
+    z = z * 6364136223846793005ull + 1442695040888963407ull;
+    x[i] = (int32_t)((z >> 33) & 8191);
+    z = z * 6364136223846793005ull + 1442695040888963407ull;
+    y[i] = (int32_t)((z >> 33) & 8191);
+    s[i] = (i & 1) ? -1 : 1;
+  }
+}
+
+struct DevBuf {
+  void *p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
 fcfs_status fcfs_autotune(fcfs_handle *h, const char *cache_path, int effort) {
-  (void)cache_path; (void)effort;
-  return fail(h, FCFS_ERR_UNSUPPORTED, "autotune not built");
+  fcfs_status st = enter(h);
+  if (st) return st;
+  if (effort < 0 || effort > 2) return fail(h, FCFS_ERR_INVALID_ARG, "effort must be 0..2");
+  std::vector<int> Ks = effort == 0 ? std::vector<int>{127, 511} : std::vector<int>{63, 127, 255, 511};
+  std::vector<int64_t> Vs = effort == 0   ? std::vector<int64_t>{32768}
+                            : effort == 1 ? std::vector<int64_t>{4096, 200000}
+                                          : std::vector<int64_t>{4096, 32768, 200000};
+  const int T = 8192;
+  const int64_t vmax = *std::max_element(Vs.begin(), Vs.end());
+  std::vector<int32_t> hx, hy;
+  std::vector<int8_t> hs;
+  synth_corners(vmax, 12345, hx, hy, hs);
+  DevBuf dx, dy, ds, dF, dws;
+  hipError_t e;
+  const int kmaxK = *std::max_element(Ks.begin(), Ks.end());
+  const size_t fbytes = sizeof(float) * 2 * (2 * (size_t)kmaxK + 1) * (2 * (size_t)kmaxK + 1);
+  if ((e = hipMalloc(&dx.p, 4 * vmax)) || (e = hipMalloc(&dy.p, 4 * vmax)) ||
+      (e = hipMalloc(&ds.p, vmax)) || (e = hipMalloc(&dF.p, fbytes)) ||
+      (e = hipMemcpy(dx.p, hx.data(), 4 * vmax, hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(dy.p, hy.data(), 4 * vmax, hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(ds.p, hs.data(), vmax, hipMemcpyHostToDevice)))
+    return hip_fail(h, e, "autotune buffers");
+  size_t wsb = 0;
+  for (int p = 0; p < 3; ++p)
+    for (int K : Ks)
+      for (int64_t V : Vs)
+        for (int t = 0; t < fcfs::n_tile_variants(); ++t) {
+          FwdPlan q;
+          if (make_plan(nullptr, V, T, K, K, p, t, &q) == FCFS_OK) wsb = std::max(wsb, q.bytes);
+        }
+  if ((e = hipMalloc(&dws.p, wsb))) return hip_fail(h, e, "autotune workspace");
+  hipEvent_t e0, e1;
+  if ((e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1))) return hip_fail(h, e, "events");
+  const int saved = h->tile_override;
+  const bool saved_prof = h->prof;
+  h->prof = false;
+  std::vector<fcfs_handle::Tune> tune;
+  const int reps = effort == 0 ? 2 : 3;
+  for (int p = 0; p < 3 && !st; ++p)
+    for (int K : Ks)
+      for (int64_t V : Vs) {
+        double best = 1e30;
+        int best_t = -1;
+        for (int t = 0; t < fcfs::n_tile_variants() && !st; ++t) {
+          if (!(fcfs::tile_variant(t).prec_mask & (1 << p))) continue;
+          fcfs_clip c{(const int32_t *)dx.p, (const int32_t *)dy.p, (const int8_t *)ds.p, V, T, K, K,
+                      (float *)dF.p, nullptr};
+          h->tile_override = t;
+          st = fcfs_forward(h, &c, (fcfs_precision)p, dws.p, wsb);  // warm-up
+          if ((e = hipEventRecord(e0, h->stream))) st = hip_fail(h, e, "event");
+          for (int r = 0; r < reps && !st; ++r) st = fcfs_forward(h, &c, (fcfs_precision)p, dws.p, wsb);
+          if (!st && (e = hipEventRecord(e1, h->stream))) st = hip_fail(h, e, "event");
+          float ms = 0.f;
+          if (!st && ((e = hipEventSynchronize(e1)) || (e = hipEventElapsedTime(&ms, e0, e1))))
+            st = hip_fail(h, e, "event timing");
+          if (!st && ms / reps < best) {
+            best = ms / reps;
+            best_t = t;
+          }
+        }
+        if (best_t >= 0) tune.push_back({p, kbucket(K), vbucket(V), best_t, best});
+      }
+  h->tile_override = saved;
+  // batch: corners per work item and wave tile on a mixed synthetic batch
+  if (!st) {
+    const int nb = effort == 0 ? 8 : 24;
+    std::vector<fcfs_clip> cl(nb);
+    std::vector<DevBuf> outs(nb);
+    uint64_t z = 777;
+    for (int i = 0; i < nb && !st; ++i) {
+      z = z * 6364136223846793005ull + 1442695040888963407ull;
+      const int K = Ks[(z >> 40) % Ks.size()];
+      z = z * 6364136223846793005ull + 1442695040888963407ull;
+      const int64_t V = std::min<int64_t>(vmax, 2000 + (int64_t)((z >> 33) % 40000));
+      const size_t fb = sizeof(float) * 2 * (2 * (size_t)K + 1) * (2 * (size_t)K + 1);
+      if ((e = hipMalloc(&outs[i].p, fb))) st = hip_fail(h, e, "autotune outputs");
+      cl[i] = fcfs_clip{(const int32_t *)dx.p, (const int32_t *)dy.p, (const int8_t *)ds.p, V, T, K,
+                        K, (float *)outs[i].p, nullptr};
+    }
+    const int64_t chunks[4] = {4096, 8192, 16384, 32768};
+    for (int p = 0; p < 3 && !st; ++p) {
+      const int tiles[2] = {p == fcfs::kFP32 ? 0 : 3, p == fcfs::kFP32 ? 1 : 4};
+      double best = 1e30;
+      int best_tile = -1;
+      int64_t best_chunk = 0;
+      for (int ti = 0; ti < 2 && !st; ++ti)
+        for (int ci = 0; ci < 4 && !st; ++ci) {
+          h->batch_tile[p] = tiles[ti];
+          h->batch_chunk[p] = chunks[ci];
+          size_t bb = 0;
+          if ((st = fcfs_batch_workspace_size_h(h, cl.data(), nb, (fcfs_precision)p, &bb))) break;
+          DevBuf bw;
+          if ((e = hipMalloc(&bw.p, bb))) {
+            st = hip_fail(h, e, "batch workspace");
+            break;
+          }
+          fcfs_plan *plan = nullptr;
+          st = fcfs_forward_batch(h, cl.data(), nb, (fcfs_precision)p, bw.p, bb, &plan);
+          if (!st && (e = hipEventRecord(e0, h->stream))) st = hip_fail(h, e, "event");
+          for (int r = 0; r < reps && !st; ++r)
+            st = fcfs_forward_batch(h, cl.data(), nb, (fcfs_precision)p, bw.p, bb, &plan);
+          if (!st && (e = hipEventRecord(e1, h->stream))) st = hip_fail(h, e, "event");
+          float ms = 0.f;
+          if (!st && ((e = hipEventSynchronize(e1)) || (e = hipEventElapsedTime(&ms, e0, e1))))
+            st = hip_fail(h, e, "event timing");
+          (void)hipStreamSynchronize(h->stream);
+          plan_free(plan);
+          if (!st && ms / reps < best) {
+            best = ms / reps;
+            best_tile = tiles[ti];
+            best_chunk = chunks[ci];
+          }
+        }
+      h->batch_tile[p] = best_tile;
+      h->batch_chunk[p] = best_chunk;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->prof = saved_prof;
+  if (st) return st;
+  h->tune = tune;
+  if (cache_path && !save_tune(h, cache_path))
+    return fail(h, FCFS_ERR_INVALID_ARG, std::string("cannot write ") + cache_path);
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_load_tune(fcfs_handle *h, const char *cache_path) {
+  if (!h || !cache_path) return fail(h, FCFS_ERR_INVALID_ARG, "NULL argument");
+  if (!load_tune(h, cache_path))
+    return fail(h, FCFS_ERR_INVALID_ARG, std::string("no usable autotune cache at ") + cache_path);
+  return FCFS_OK;
 }
 
 }  // extern "C"

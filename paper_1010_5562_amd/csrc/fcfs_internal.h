@@ -96,6 +96,45 @@ hipError_t launch_apply_offsets(const int32_t *bx, const int32_t *by, const int6
                                 const int64_t *vedge, const float *off, int64_t V, int32_t *x,
                                 int32_t *y, hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// Batched form: one descriptor per clip (device copy), work lists.
+// ---------------------------------------------------------------------------
+struct BatchClip {
+  const int32_t *x, *y;
+  const int8_t *s;
+  float2 *F;
+  int64_t *area;
+  uint4 *packed;
+  unsigned long long *area_part;
+  double2 *axis_part;
+  float *part;
+  int64_t V, vpad, chunk, ax_chunk;
+  int T, shift, K, L, kp, lp, tiles_l, nsplit;
+  int ax_groups_k, ax_chunks;
+};
+
+struct BatchLaunch {
+  int n_clips;
+  int prec, tile;           // tile variant of the persistent contraction
+  const BatchClip *clips;   // device
+  int pre_blocks;           // pre-pass blocks per clip
+  const int4 *ax_desc;      // device: (clip, group, chunk) per axis block
+  int n_ax;
+  const int4 *items;        // device: (clip, tile, split) per work item, LPT order
+  int n_items;
+  int grid;                 // persistent workgroups
+  unsigned int *counter;    // device work counter
+  const int *epi_off;       // device: prefix of epilogue blocks per clip [n+1]
+  const int *epa_off;       // device: prefix of axis-epilogue blocks per clip [n+1]
+  int n_epi, n_epa;
+};
+
+hipError_t launch_batch_prepass(const BatchLaunch &b, hipStream_t st);
+hipError_t launch_batch_axis(const BatchLaunch &b, const double2 *w64, hipStream_t st);
+hipError_t launch_batch_contract(const BatchLaunch &b, const Tables &t, hipStream_t st);
+hipError_t launch_batch_epilogue(const BatchLaunch &b, hipStream_t st);
+int batch_grid(int tile, int prec);
+
 // Contraction tile variants (wave tile in k x l frequencies; 2 x 2 waves).
 struct TileVariant {
   int id;

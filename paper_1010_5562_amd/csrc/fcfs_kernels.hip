@@ -16,15 +16,14 @@ namespace fcfs {
 // padded count) become padding records.  The area sum is done modulo 2^64,
 // which is exact whenever the true area fits in int64.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_prepass(const int32_t *__restrict__ x,
-                                                 const int32_t *__restrict__ y,
-                                                 const int8_t *__restrict__ s, int64_t V,
-                                                 int64_t vpad, uint32_t tmask, int shift,
-                                                 uint4 *__restrict__ packed,
-                                                 unsigned long long *__restrict__ area_part) {
+__device__ __forceinline__ void prepass_body(const int32_t *__restrict__ x,
+                                             const int32_t *__restrict__ y,
+                                             const int8_t *__restrict__ s, int64_t V, int64_t vpad,
+                                             uint32_t tmask, int shift, uint4 *__restrict__ packed,
+                                             unsigned long long *__restrict__ area_part, int blk,
+                                             int nblk) {
   unsigned long long acc = 0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < vpad;
-       i += (int64_t)gridDim.x * 256) {
+  for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < vpad; i += (int64_t)nblk * 256) {
     uint4 w;
     if (i < V) {
       const int32_t xv = x[i], yv = y[i];
@@ -44,7 +43,16 @@ __global__ __launch_bounds__(256) void k_prepass(const int32_t *__restrict__ x,
   __shared__ unsigned long long red[4];
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) area_part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+  if (threadIdx.x == 0) area_part[blk] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(256) void k_prepass(const int32_t *__restrict__ x,
+                                                 const int32_t *__restrict__ y,
+                                                 const int8_t *__restrict__ s, int64_t V,
+                                                 int64_t vpad, uint32_t tmask, int shift,
+                                                 uint4 *__restrict__ packed,
+                                                 unsigned long long *__restrict__ area_part) {
+  prepass_body(x, y, s, V, vpad, tmask, shift, packed, area_part, blockIdx.x, gridDim.x);
 }
 
 hipError_t launch_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
@@ -69,23 +77,22 @@ constexpr int kAxR = 8;               // frequencies per lane
 constexpr int kAxGroup = 64 * kAxR;   // frequencies per group
 constexpr int kAxChunkMax = 1024;     // corners staged per block
 
-__global__ __launch_bounds__(256) void k_axis(const int32_t *__restrict__ x,
-                                              const int32_t *__restrict__ y,
-                                              const uint4 *__restrict__ packed,
-                                              const double2 *__restrict__ w64, int64_t V,
-                                              int64_t ax_chunk, int K, int L, int groups_k,
-                                              double2 *__restrict__ axis_part) {
+__device__ __forceinline__ void axis_body(const int32_t *__restrict__ x,
+                                          const int32_t *__restrict__ y,
+                                          const uint4 *__restrict__ packed,
+                                          const double2 *__restrict__ w64, int64_t V,
+                                          int64_t ax_chunk, int K, int L, int groups_k,
+                                          double2 *__restrict__ axis_part, int g, int chunk_idx) {
   __shared__ uint32_t s_ph[kAxChunkMax];
   __shared__ double s_wt[kAxChunkMax];
   __shared__ double2 s_e1[kAxChunkMax];
   __shared__ double2 red[3][64][kAxR];
-  const int g = blockIdx.x;
   const bool xaxis = g < groups_k;
   const int gi = xaxis ? g : g - groups_k;
   const int nf = xaxis ? K : L;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t f0 = (uint32_t)(gi * kAxGroup + lane * kAxR + 1);
-  const int64_t v0 = (int64_t)blockIdx.y * ax_chunk;
+  const int64_t v0 = (int64_t)chunk_idx * ax_chunk;
   const int n = (int)(min(V, v0 + ax_chunk) - v0);
   // stage the chunk: phase index, signed weight and e^{j 2 pi ph / N}
   for (int i = threadIdx.x; i < n; i += 256) {
@@ -146,10 +153,19 @@ __global__ __launch_bounds__(256) void k_axis(const int32_t *__restrict__ x,
       const int f = (int)f0 + r;
       if (f <= nf) {
         const int slot = xaxis ? f - 1 : K + f - 1;
-        axis_part[(size_t)blockIdx.y * (K + L) + slot] = make_double2(sr, si);
+        axis_part[(size_t)chunk_idx * (K + L) + slot] = make_double2(sr, si);
       }
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_axis(const int32_t *__restrict__ x,
+                                              const int32_t *__restrict__ y,
+                                              const uint4 *__restrict__ packed,
+                                              const double2 *__restrict__ w64, int64_t V,
+                                              int64_t ax_chunk, int K, int L, int groups_k,
+                                              double2 *__restrict__ axis_part) {
+  axis_body(x, y, packed, w64, V, ax_chunk, K, L, groups_k, axis_part, blockIdx.x, blockIdx.y);
 }
 
 hipError_t launch_axis(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
@@ -335,19 +351,13 @@ __global__ __launch_bounds__(256) void k_contract_split(const uint4 *__restrict_
 // pipeline inside the wave (lookups, fragment build and MFMAs of a step in
 // sequence); the second wave on the SIMD hides the latencies.
 template <int PREC, int NKB, int NLB>
-__global__ __launch_bounds__(256, 2) void k_contract_split_lean(const uint4 *__restrict__ packed,
-                                                                const uint2 *__restrict__ tab,
-                                                                int64_t chunk, int tiles_l,
-                                                                int kp, int lp,
-                                                                float *__restrict__ part) {
-  __shared__ uint2 s_tab[kTabEntries];
-  for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
-  __syncthreads();
-
+__device__ __forceinline__ void contract_lean_body(const uint2 *s_tab,
+                                                   const uint4 *__restrict__ packed,
+                                                   int64_t chunk, int tiles_l, int kp, int lp,
+                                                   float *__restrict__ part, int tile, int split) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 31, lh = lane >> 5;
-  const int tk = blockIdx.x / tiles_l, tl = blockIdx.x % tiles_l;
-  const int split = blockIdx.y;
+  const int tk = tile / tiles_l, tl = tile % tiles_l;
   const int k0 = tk * (64 * NKB) + (wave >> 1) * (32 * NKB);
   const int l0 = tl * (64 * NLB) + (wave & 1) * (32 * NLB);
 
@@ -380,21 +390,32 @@ __global__ __launch_bounds__(256, 2) void k_contract_split_lean(const uint4 *__r
   store_part<NKB, NLB>(part, acc, split, kp, lp, k0, l0, li, lh);
 }
 
+// Lean form of the same contraction for two waves per SIMD: no software
+// pipeline inside the wave (lookups, fragment build and MFMAs of a step in
+// sequence); the second wave on the SIMD hides the latencies.
+template <int PREC, int NKB, int NLB>
+__global__ __launch_bounds__(256, 2) void k_contract_split_lean(const uint4 *__restrict__ packed,
+                                                                const uint2 *__restrict__ tab,
+                                                                int64_t chunk, int tiles_l,
+                                                                int kp, int lp,
+                                                                float *__restrict__ part) {
+  __shared__ uint2 s_tab[kTabEntries];
+  for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
+  __syncthreads();
+  contract_lean_body<PREC, NKB, NLB>(s_tab, packed, chunk, tiles_l, kp, lp, part, blockIdx.x,
+                                     blockIdx.y);
+}
+
 // FP32 form: v_mfma_f32_32x32x2_f32, two corners per product (lanes 0-31
 // carry corner j of the lane's group, lanes 32-63 corner 8 + j).
 template <int NKB, int NLB>
-__global__ __launch_bounds__(256) void k_contract_fp32(const uint4 *__restrict__ packed,
-                                                       const float2 *__restrict__ tab,
-                                                       int64_t chunk, int tiles_l, int kp, int lp,
-                                                       float *__restrict__ part) {
-  __shared__ float2 s_tab[kTabEntries];
-  for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
-  __syncthreads();
-
+__device__ __forceinline__ void contract_fp32_body(const float2 *s_tab,
+                                                   const uint4 *__restrict__ packed,
+                                                   int64_t chunk, int tiles_l, int kp, int lp,
+                                                   float *__restrict__ part, int tile, int split) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 31, lh = lane >> 5;
-  const int tk = blockIdx.x / tiles_l, tl = blockIdx.x % tiles_l;
-  const int split = blockIdx.y;
+  const int tk = tile / tiles_l, tl = tile % tiles_l;
   const int k0 = tk * (64 * NKB) + (wave >> 1) * (32 * NKB);
   const int l0 = tl * (64 * NLB) + (wave & 1) * (32 * NLB);
 
@@ -439,6 +460,20 @@ __global__ __launch_bounds__(256) void k_contract_fp32(const uint4 *__restrict__
     }
   }
   store_part<NKB, NLB>(part, acc, split, kp, lp, k0, l0, li, lh);
+}
+
+// FP32 form: v_mfma_f32_32x32x2_f32, two corners per product (lanes 0-31
+// carry corner j of the lane's group, lanes 32-63 corner 8 + j).
+template <int NKB, int NLB>
+__global__ __launch_bounds__(256) void k_contract_fp32(const uint4 *__restrict__ packed,
+                                                       const float2 *__restrict__ tab,
+                                                       int64_t chunk, int tiles_l, int kp, int lp,
+                                                       float *__restrict__ part) {
+  __shared__ float2 s_tab[kTabEntries];
+  for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
+  __syncthreads();
+  contract_fp32_body<NKB, NLB>(s_tab, packed, chunk, tiles_l, kp, lp, part, blockIdx.x,
+                               blockIdx.y);
 }
 
 // Tile variants: (id, precision mask, k per wave, l per wave, pipelined).
@@ -498,14 +533,14 @@ hipError_t launch_contract(const FwdPlan &p, const uint4 *packed, const Tables &
 // alpha_{k,-l} = -alpha_{k,l}; F[-k,-l] = conj F[k,l] (real signal).
 // Split partials are summed in FP64 in a fixed order.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_epilogue(const float *__restrict__ part, int nsplit, int kp,
-                                                  int lp, int K, int L, double T,
-                                                  float2 *__restrict__ F) {
+__device__ __forceinline__ void epilogue_body(const float *__restrict__ part, int nsplit, int kp,
+                                              int lp, int K, int L, double T,
+                                              float2 *__restrict__ F, int bx, int by) {
   // 64 consecutive l per block, 4 threads per l summing splits q, q+4, ...
   __shared__ double4 red[4][64];
   const int t = threadIdx.x & 63, q = threadIdx.x >> 6;
-  const int l = 1 + blockIdx.x * 64 + t;
-  const int k = 1 + blockIdx.y;
+  const int l = 1 + bx * 64 + t;
+  const int k = 1 + by;
   const size_t plane = (size_t)kp * lp;
   double P = 0.0, U = 0.0, R = 0.0, Q = 0.0;
   if (l <= L) {
@@ -537,19 +572,25 @@ __global__ __launch_bounds__(256) void k_epilogue(const float *__restrict__ part
   F[(size_t)(K - k) * W + (L + l)] = make_float2((float)mre, (float)-mim);
 }
 
+__global__ __launch_bounds__(256) void k_epilogue(const float *__restrict__ part, int nsplit, int kp,
+                                                  int lp, int K, int L, double T,
+                                                  float2 *__restrict__ F) {
+  epilogue_body(part, nsplit, kp, lp, K, L, T, F, blockIdx.x, blockIdx.y);
+}
+
 // Axis entries (Steps 2, 3) and DC (Step 1):
 //   F[k,0] = j/(2 pi k) Sx[k],  F[-k,0] = conj F[k,0];  likewise F[0,l];
 //   F[0,0] = area / T.
 // Block: 16 frequency slots x 16 partial sums over the axis chunks (fixed
 // order: chunk c goes to sum c mod 16, the sums are added in order).
-__global__ __launch_bounds__(256) void k_epilogue_axes(const double2 *__restrict__ axis_part,
-                                                       int ax_chunks, int K, int L, double T,
-                                                       const unsigned long long *__restrict__ area_part,
-                                                       int pre_blocks, float2 *__restrict__ F,
-                                                       int64_t *__restrict__ area) {
+__device__ __forceinline__ void epilogue_axes_body(const double2 *__restrict__ axis_part,
+                                                   int ax_chunks, int K, int L, double T,
+                                                   const unsigned long long *__restrict__ area_part,
+                                                   int pre_blocks, float2 *__restrict__ F,
+                                                   int64_t *__restrict__ area, int bx) {
   __shared__ double2 red[16][16];
   const int t = threadIdx.x & 15, q = threadIdx.x >> 4;
-  const int i = blockIdx.x * 16 + t;
+  const int i = bx * 16 + t;
   const size_t W = 2 * (size_t)L + 1;
   const int nslot = K + L;
   double re = 0.0, im = 0.0;
@@ -577,7 +618,7 @@ __global__ __launch_bounds__(256) void k_epilogue_axes(const double2 *__restrict
       F[(size_t)K * W + (L - f)] = make_float2(fre, -fim);
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x >= 64 && threadIdx.x < 128) {
+  if (bx == 0 && threadIdx.x >= 64 && threadIdx.x < 128) {
     const int a0 = threadIdx.x - 64;
     unsigned long long a = 0;
     for (int b = a0; b < pre_blocks; b += 64) a += area_part[b];
@@ -588,6 +629,14 @@ __global__ __launch_bounds__(256) void k_epilogue_axes(const double2 *__restrict
       if (area) *area = A;
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_epilogue_axes(const double2 *__restrict__ axis_part,
+                                                       int ax_chunks, int K, int L, double T,
+                                                       const unsigned long long *__restrict__ area_part,
+                                                       int pre_blocks, float2 *__restrict__ F,
+                                                       int64_t *__restrict__ area) {
+  epilogue_axes_body(axis_part, ax_chunks, K, L, T, area_part, pre_blocks, F, area, blockIdx.x);
 }
 
 hipError_t launch_epilogue(const FwdPlan &p, const float *part, const double2 *axis_part,
@@ -625,6 +674,166 @@ hipError_t launch_debug_phases(const FwdPlan &p, const uint4 *packed, int axis, 
   if (p.V == 0 || nk == 0) return hipSuccess;
   hipLaunchKernelGGL(k_debug_phases, dim3((unsigned)((p.V + 255) / 256), nk), dim3(256), 0, st,
                      packed, p.V, axis, k0, nk, p.shift, out);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// Batched form.  Every clip keeps its own workspace slices; a persistent
+// contraction kernel loads the twiddle table into LDS once per workgroup and
+// then pulls (clip, tile, split) work items, longest first, from an atomic
+// counter until the list is exhausted.  The counter is reset by a kernel at
+// the head of the sequence, so a captured graph can be replayed.
+// ===========================================================================
+__global__ void k_batch_reset(unsigned int *counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_batch_prepass(const BatchClip *__restrict__ clips) {
+  const BatchClip &c = clips[blockIdx.y];
+  prepass_body(c.x, c.y, c.s, c.V, c.vpad, (uint32_t)(c.T - 1), c.shift, c.packed, c.area_part,
+               blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_batch_axis(const BatchClip *__restrict__ clips,
+                                                    const int4 *__restrict__ desc,
+                                                    const double2 *__restrict__ w64) {
+  const int4 d = desc[blockIdx.x];
+  const BatchClip &c = clips[d.x];
+  axis_body(c.x, c.y, c.packed, w64, c.V, c.ax_chunk, c.K, c.L, c.ax_groups_k, c.axis_part, d.y,
+            d.z);
+}
+
+// Next work item for the whole workgroup (-1 when the list is exhausted).
+__device__ __forceinline__ int next_item(unsigned int *counter, int n_items, int *s_item) {
+  __syncthreads();
+  if (threadIdx.x == 0) *s_item = (int)atomicAdd(counter, 1u);
+  __syncthreads();
+  const int it = *s_item;
+  return it < n_items ? it : -1;
+}
+
+template <int PREC, int NKB, int NLB>
+__global__ __launch_bounds__(256, 2) void k_batch_contract(const BatchClip *__restrict__ clips,
+                                                           const int4 *__restrict__ items,
+                                                           int n_items, unsigned int *counter,
+                                                           const uint2 *__restrict__ tab) {
+  __shared__ uint2 s_tab[kTabEntries];
+  __shared__ int s_item;
+  for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
+  for (;;) {
+    const int it = next_item(counter, n_items, &s_item);
+    if (it < 0) break;
+    const int4 d = items[it];
+    const BatchClip &c = clips[d.x];
+    contract_lean_body<PREC, NKB, NLB>(s_tab, c.packed, c.chunk, c.tiles_l, c.kp, c.lp, c.part,
+                                       d.y, d.z);
+  }
+}
+
+template <int NKB, int NLB>
+__global__ __launch_bounds__(256, 2) void k_batch_contract_fp32(const BatchClip *__restrict__ clips,
+                                                                const int4 *__restrict__ items,
+                                                                int n_items, unsigned int *counter,
+                                                                const float2 *__restrict__ tab) {
+  __shared__ float2 s_tab[kTabEntries];
+  __shared__ int s_item;
+  for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
+  for (;;) {
+    const int it = next_item(counter, n_items, &s_item);
+    if (it < 0) break;
+    const int4 d = items[it];
+    const BatchClip &c = clips[d.x];
+    contract_fp32_body<NKB, NLB>(s_tab, c.packed, c.chunk, c.tiles_l, c.kp, c.lp, c.part, d.y,
+                                 d.z);
+  }
+}
+
+// clip owning flat block b of a prefix array off[0..n]
+__device__ __forceinline__ int owner(const int *__restrict__ off, int n, int b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_batch_epilogue(const BatchClip *__restrict__ clips,
+                                                        const int *__restrict__ off, int n) {
+  const int ci = owner(off, n, blockIdx.x);
+  const BatchClip &c = clips[ci];
+  const int local = blockIdx.x - off[ci];
+  const int nbx = (c.L + 63) / 64;
+  epilogue_body(c.part, c.nsplit, c.kp, c.lp, c.K, c.L, (double)c.T, c.F, local % nbx,
+                local / nbx);
+}
+
+__global__ __launch_bounds__(256) void k_batch_epilogue_axes(const BatchClip *__restrict__ clips,
+                                                             const int *__restrict__ off, int n,
+                                                             int pre_blocks) {
+  const int ci = owner(off, n, blockIdx.x);
+  const BatchClip &c = clips[ci];
+  epilogue_axes_body(c.axis_part, c.ax_chunks, c.K, c.L, (double)c.T, c.area_part, pre_blocks,
+                     c.F, c.area, blockIdx.x - off[ci]);
+}
+
+hipError_t launch_batch_prepass(const BatchLaunch &b, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, b.counter);
+  hipLaunchKernelGGL(k_batch_prepass, dim3(b.pre_blocks, b.n_clips), dim3(256), 0, st, b.clips);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_axis(const BatchLaunch &b, const double2 *w64, hipStream_t st) {
+  if (b.n_ax > 0)
+    hipLaunchKernelGGL(k_batch_axis, dim3(b.n_ax), dim3(256), 0, st, b.clips, b.ax_desc, w64);
+  return hipGetLastError();
+}
+
+int batch_grid(int tile, int prec) {
+  (void)tile;
+  (void)prec;
+  return 2 * 256;  // two workgroups per CU (64 KB of LDS each) on 256 CUs
+}
+
+hipError_t launch_batch_contract(const BatchLaunch &b, const Tables &t, hipStream_t st) {
+  if (b.n_items == 0) return hipSuccess;
+  const dim3 grid(b.grid), block(256);
+  const bool wide = tile_variant(b.tile).wk == 64;
+  if (b.prec == kFP32) {
+    if (wide)
+      hipLaunchKernelGGL((k_batch_contract_fp32<2, 1>), grid, block, 0, st, b.clips, b.items,
+                         b.n_items, b.counter, t.w32);
+    else
+      hipLaunchKernelGGL((k_batch_contract_fp32<1, 1>), grid, block, 0, st, b.clips, b.items,
+                         b.n_items, b.counter, t.w32);
+  } else if (b.prec == kBF16) {
+    if (wide)
+      hipLaunchKernelGGL((k_batch_contract<kBF16, 2, 1>), grid, block, 0, st, b.clips, b.items,
+                         b.n_items, b.counter, t.wbf16);
+    else
+      hipLaunchKernelGGL((k_batch_contract<kBF16, 1, 1>), grid, block, 0, st, b.clips, b.items,
+                         b.n_items, b.counter, t.wbf16);
+  } else {
+    if (wide)
+      hipLaunchKernelGGL((k_batch_contract<kFP16, 2, 1>), grid, block, 0, st, b.clips, b.items,
+                         b.n_items, b.counter, t.wfp16);
+    else
+      hipLaunchKernelGGL((k_batch_contract<kFP16, 1, 1>), grid, block, 0, st, b.clips, b.items,
+                         b.n_items, b.counter, t.wfp16);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_epilogue(const BatchLaunch &b, hipStream_t st) {
+  if (b.n_epa > 0)
+    hipLaunchKernelGGL(k_batch_epilogue_axes, dim3(b.n_epa), dim3(256), 0, st, b.clips, b.epa_off,
+                       b.n_clips, b.pre_blocks);
+  if (b.n_epi > 0)
+    hipLaunchKernelGGL(k_batch_epilogue, dim3(b.n_epi), dim3(256), 0, st, b.clips, b.epi_off,
+                       b.n_clips);
   return hipGetLastError();
 }
 

@@ -1,0 +1,117 @@
+"""Batched form: persistent graph-captured launch over clips of mixed sizes,
+checked against the FP64 oracle and against the single-clip path; graph
+replays; the autotuner and its cache."""
+import json
+
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-6, "bf16": 1e-5, "fp16": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1010_5562_amd as P
+
+    torch.cuda.set_device(0)
+    return P
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _clips(n, seed, v_hi=20_000):
+    return synth.batch_clips(seed, n_clips=n, v_lo=1000, v_hi=v_hi, pool=256)
+
+
+def _as_args(P, clips):
+    out = []
+    for c in clips:
+        x, y, s, _, _ = P.loops_to_corners(c.xy, c.off)
+        out.append((x, y, s, c.T, c.K, c.L))
+    return out
+
+
+def _sample(K, n, seed):
+    rng = np.random.default_rng(seed)
+    lo = np.array([(k, l) for k in range(-4, 5) for l in range(-4, 5)])
+    kk = np.concatenate([lo[:, 0], rng.integers(-K, K + 1, n)])
+    ll = np.concatenate([lo[:, 1], rng.integers(-K, K + 1, n)])
+    return kk, ll
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32", "fp16"])
+def test_batch_matches_oracle(P, oracle_lib, prec):
+    clips = _clips(10, 5)
+    _say(f"batch of {len(clips)} clips, V = {[c.n_vertices for c in clips]} prec={prec}")
+    b = P.Batch(_as_args(P, clips), precision=prec)
+    F = b.run()
+    torch.cuda.synchronize()
+    for i, c in enumerate(clips):
+        kk, ll = _sample(c.K, 60, i)
+        ref = oracle_lib.cfs_points(c.xy, c.off, c.T, kk, ll)
+        f00 = abs(oracle_lib.cfs_points(c.xy, c.off, c.T, [0], [0])[0])
+        got = F[i].cpu().numpy()[kk + c.K, ll + c.L]
+        e = float(np.max(np.abs(got - ref)) / f00)
+        _, area = oracle_lib.cfs_grid(c.xy, c.off, c.T, 0, 0)
+        assert int(b.area[i].item()) == area
+        assert e <= TOL[prec], (i, c.T, c.K, e)
+    b.close()
+
+
+def test_batch_equals_single_clip_and_replays(P):
+    clips = _clips(8, 6)
+    args = _as_args(P, clips)
+    b = P.Batch(args, precision="bf16")
+    F1 = [f.cpu().numpy().copy() for f in b.run()]
+    for i, (x, y, s, T, K, L) in enumerate(args):
+        Fs, _ = P.forward(x, y, s, T, K, L, precision="bf16")
+        d = np.max(np.abs(Fs.cpu().numpy() - F1[i])) / abs(F1[i][K, L])
+        assert d <= 2e-6, (i, d)
+    # replays, with eager work and synchronisations in between, give the same bits
+    for r in range(3):
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        for f in b.F:
+            f.zero_()
+        F2 = [f.cpu().numpy() for f in b.run()]
+        for i in range(len(F1)):
+            assert np.array_equal(F1[i], F2[i]), (r, i)
+        del junk
+    # a plan built for other clips is refused
+    other = P.Batch(args[:3], precision="bf16")
+    other._plan = b._plan
+    with pytest.raises(P.FcfsError):
+        other.run()
+    other._plan = type(other._plan)()
+    b.close()
+
+
+def test_autotune_and_cache(P, tmp_path):
+    path = tmp_path / "tune.json"
+    h = P.Handle()
+    P.autotune(path, effort=0, handle=h)
+    doc = json.loads(path.read_text())
+    assert doc["format"] == "fcfs-autotune-1"
+    assert doc["forward"] and doc["batch"]
+    # a fresh handle reads the cache; a malformed one is refused and ignored
+    h2 = P.Handle()
+    P.load_tune(path, handle=h2)
+    bad = tmp_path / "bad.json"
+    bad.write_text("{not json")
+    with pytest.raises(P.FcfsError):
+        P.load_tune(bad, handle=h2)
+    clip, _, _ = synth.clip_c1(1)
+    x, y, s, _, _ = P.loops_to_corners(clip.xy, clip.off)
+    Fa, _ = P.forward(x, y, s, clip.T, clip.K, clip.L, precision="bf16", handle=h2)
+    Fb, _ = P.forward(x, y, s, clip.T, clip.K, clip.L, precision="bf16", handle=h)
+    torch.cuda.synchronize()
+    assert np.allclose(Fa.cpu().numpy(), Fb.cpu().numpy(), atol=1e-5 * abs(Fa[clip.K, clip.L].item()))
