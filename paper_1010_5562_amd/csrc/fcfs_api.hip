@@ -255,28 +255,25 @@ fcfs_status make_plan(fcfs_handle *h, int64_t V, int T, int K, int L, int prec, 
   q.chunk = std::max<int64_t>(16, round_up(ceil_div(std::max<int64_t>(V, 1), ns), 16));
   q.vpad = q.chunk * q.nsplit;
   q.pre_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(q.vpad, 256)));
-  q.ax_groups_k = (int)ceil_div(K, 512);
-  q.ax_groups_l = (int)ceil_div(L, 512);
-  const int groups = q.ax_groups_k + q.ax_groups_l;
-  if (groups > 0 && V > 0) {
-    // staged chunks of at most 1024 corners, enough blocks to fill the chip
-    int64_t ac = std::max(ceil_div(kTargetWG, groups), ceil_div(V, 1024));
-    ac = std::max<int64_t>(1, std::min<int64_t>(ac, ceil_div(V, 64)));
-    q.ax_chunk = std::min<int64_t>(1024, ceil_div(V, ac));
-    q.ax_chunks = (int)ceil_div(V, q.ax_chunk);
-  } else {
-    q.ax_chunk = 1;
-    q.ax_chunks = 1;
-  }
+  q.ax_fb_k = (int)ceil_div(K, 256);
+  q.ax_fb_l = (int)ceil_div(L, 256);
+  q.ax_chunks = (int)ceil_div(T, 512);
   size_t off = 0;
   q.off_packed = off;
   off += align256(sizeof(uint4) * (size_t)q.vpad);
   q.off_area = off;
   off += align256(sizeof(unsigned long long) * (size_t)q.pre_blocks);
+  q.off_hist = off;
+  off += align256(sizeof(unsigned long long) * 2 * fcfs::kTabN);
   q.off_axis = off;
   off += align256(sizeof(double2) * (size_t)q.ax_chunks * (size_t)std::max(1, K + L));
   q.off_part = off;
   off += align256(sizeof(float) * 4 * (size_t)q.nsplit * (size_t)q.kp * (size_t)q.lp);
+  // at least 128 corners per guard block, at most 256 partials per pair
+  q.g_chunk = std::max<int64_t>(128, ceil_div(V, 256));
+  q.g_chunks = (int)std::max<int64_t>(1, ceil_div(V, q.g_chunk));
+  q.off_guard = off;
+  off += align256(sizeof(double2) * 128 * (size_t)q.g_chunks);
   q.bytes = off;
   *p = q;
   return FCFS_OK;
@@ -395,10 +392,14 @@ fcfs_status run_forward(fcfs_handle *h, const fcfs_clip *c, const FwdPlan &p, vo
   if ((e = hipEventRecord(h->ev_fork, h->stream)) ||
       (e = hipStreamWaitEvent(h->side, h->ev_fork, 0)))
     return hip_fail(h, e, "fork");
+  double2 *gpart = ws_at<double2>(ws, p.off_guard);
   {
     ProfScope ps(h, kProfAxis, h->side);
-    if ((e = fcfs::launch_axis(p, c->x, c->y, c->s, packed, h->tab.w64, axis_part, h->side)))
+    if ((e = fcfs::launch_axis(p, c->x, c->y, packed, h->tab.w64,
+                               ws_at<unsigned long long>(ws, p.off_hist), axis_part, h->side)))
       return hip_fail(h, e, "axis launch");
+    if ((e = fcfs::launch_guard(p, packed, h->tab.w64, gpart, h->side)))
+      return hip_fail(h, e, "guard launch");
   }
   if ((e = hipEventRecord(h->ev_join, h->side))) return hip_fail(h, e, "join");
   if (p.K > 0 && p.L > 0) {
@@ -411,6 +412,8 @@ fcfs_status run_forward(fcfs_handle *h, const fcfs_clip *c, const FwdPlan &p, vo
     ProfScope ps(h, kProfEpilogue);
     if ((e = fcfs::launch_epilogue(p, part, axis_part, area_part, c->F, c->area, h->stream)))
       return hip_fail(h, e, "epilogue launch");
+    if ((e = fcfs::launch_guard_epilogue(p, gpart, c->F, h->stream)))
+      return hip_fail(h, e, "guard epilogue launch");
   }
   return FCFS_OK;
 }
@@ -746,8 +749,8 @@ constexpr int kBatchPreBlocks = 64;
 // device pointers are filled in once the workspace base is known).
 struct BatchLayout {
   std::vector<fcfs::BatchClip> bc;
-  std::vector<size_t> off_packed, off_area, off_axis, off_part;
-  std::vector<int4> ax_desc, items;
+  std::vector<size_t> off_packed, off_area, off_hist, off_axis, off_part, off_guard;
+  std::vector<int4> ax_desc, items, g_desc;
   std::vector<int> epi_off, epa_off;
   size_t bytes = 0;
 };
@@ -765,6 +768,9 @@ fcfs_status batch_layout(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec
   L->off_area.assign(n, 0);
   L->off_axis.assign(n, 0);
   L->off_part.assign(n, 0);
+  L->off_guard.assign(n, 0);
+  L->off_hist.assign(n, 0);
+  L->g_desc.clear();
   L->ax_desc.clear();
   L->items.clear();
   L->epi_off.assign(n + 1, 0);
@@ -791,13 +797,15 @@ fcfs_status batch_layout(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec
     b.nsplit = (int)ns;
     b.chunk = std::max<int64_t>(16, round_up(ceil_div(std::max<int64_t>(ci.V, 1), ns), 16));
     b.vpad = b.chunk * b.nsplit;
-    const int gk = (int)ceil_div(ci.K, 512), gl = (int)ceil_div(ci.L, 512);
-    b.ax_groups_k = gk;
-    b.ax_chunk = 1024;
-    b.ax_chunks = (int)std::max<int64_t>(1, ceil_div(ci.V, 1024));
-    if (ci.V > 0)
-      for (int g = 0; g < gk + gl; ++g)
-        for (int ch = 0; ch < b.ax_chunks; ++ch) L->ax_desc.push_back(make_int4(i, g, ch, 0));
+    const int fk = (int)ceil_div(ci.K, 256), fl = (int)ceil_div(ci.L, 256);
+    b.ax_fb_k = fk;
+    b.ax_chunks = (int)ceil_div(ci.T, 512);
+    for (int fb = 0; fb < fk + fl; ++fb)
+      for (int ch = 0; ch < b.ax_chunks; ++ch) L->ax_desc.push_back(make_int4(i, fb, ch, 0));
+    b.g_chunk = std::max<int64_t>(128, ceil_div(ci.V, 256));
+    b.g_chunks = (int)std::max<int64_t>(1, ceil_div(ci.V, b.g_chunk));
+    if (ci.V > 0 && ci.K > 0 && ci.L > 0)
+      for (int ch = 0; ch < b.g_chunks; ++ch) L->g_desc.push_back(make_int4(i, ch, 0, 0));
     if (ci.K > 0 && ci.L > 0)
       for (int t = 0; t < tiles; ++t)
         for (int sp = 0; sp < b.nsplit; ++sp)
@@ -808,10 +816,14 @@ fcfs_status batch_layout(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec
     off += align256(sizeof(uint4) * (size_t)b.vpad);
     L->off_area[i] = off;
     off += align256(sizeof(unsigned long long) * kBatchPreBlocks);
+    L->off_hist[i] = off;
+    off += align256(sizeof(unsigned long long) * 2 * fcfs::kTabN);
     L->off_axis[i] = off;
     off += align256(sizeof(double2) * (size_t)b.ax_chunks * (size_t)std::max(1, ci.K + ci.L));
     L->off_part[i] = off;
     off += align256(sizeof(float) * 4 * (size_t)b.nsplit * (size_t)b.kp * (size_t)b.lp);
+    L->off_guard[i] = off;
+    off += align256(sizeof(double2) * 128 * (size_t)b.g_chunks);
   }
   // longest processing time first; ties keep clip order
   std::stable_sort(items.begin(), items.end(),
@@ -880,6 +892,8 @@ fcfs_status build_plan(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec, 
     b.area_part = ws_at<unsigned long long>(ws, L.off_area[i]);
     b.axis_part = ws_at<double2>(ws, L.off_axis[i]);
     b.part = ws_at<float>(ws, L.off_part[i]);
+    b.gpart = ws_at<double2>(ws, L.off_guard[i]);
+    b.hist = ws_at<unsigned long long>(ws, L.off_hist[i]);
   }
   fcfs::BatchLaunch &bl = p->launch;
   bl.n_clips = n;
@@ -894,6 +908,8 @@ fcfs_status build_plan(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec, 
   bl.n_epa = L.epa_off[n];
   if (!st) st = upload(h, p, L.bc, &bl.clips);
   if (!st) st = upload(h, p, L.ax_desc, &bl.ax_desc);
+  if (!st) st = upload(h, p, L.g_desc, &bl.g_desc);
+  bl.n_g = (int)L.g_desc.size();
   if (!st) st = upload(h, p, L.items, &bl.items);
   if (!st) st = upload(h, p, L.epi_off, &bl.epi_off);
   if (!st) st = upload(h, p, L.epa_off, &bl.epa_off);
@@ -912,6 +928,7 @@ fcfs_status build_plan(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec, 
       if (!le) le = hipEventRecord(p->ev_fork, p->cap);
       if (!le) le = hipStreamWaitEvent(p->side, p->ev_fork, 0);
       if (!le) le = fcfs::launch_batch_axis(bl, h->tab.w64, p->side);
+      if (!le) le = fcfs::launch_batch_guard(bl, h->tab.w64, p->side);
       if (!le) le = hipEventRecord(p->ev_join, p->side);
       if (!le) le = fcfs::launch_batch_contract(bl, h->tab, p->cap);
       if (!le) le = hipStreamWaitEvent(p->cap, p->ev_join, 0);

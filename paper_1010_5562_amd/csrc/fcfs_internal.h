@@ -48,26 +48,30 @@ struct FwdPlan {
   int64_t chunk;     // corners per split (multiple of 16)
   int64_t vpad;      // nsplit * chunk
   int pre_blocks;    // pre-pass blocks (area partials)
-  int ax_groups_k;   // 512-frequency groups of the x-axis sums
-  int ax_groups_l;   // and of the y-axis sums
-  int ax_chunks;     // vertex chunks of the axis sums
-  int64_t ax_chunk;  // corners per axis chunk
+  int ax_fb_k;       // 256-frequency blocks of the x-axis DFT
+  int ax_fb_l;       // and of the y-axis DFT
+  int ax_chunks;     // bin chunks of the axis DFTs (partials per frequency)
+  int g_chunks;      // vertex chunks of the FP64 low-frequency guard block
+  int64_t g_chunk;
   // workspace offsets (bytes)
-  size_t off_packed, off_area, off_axis, off_part, bytes;
+  size_t off_packed, off_area, off_hist, off_axis, off_part, off_guard, bytes;
 };
 
 // Kernel launchers (fcfs_kernels.hip).  All enqueue on `st` and return the
 // launch status.
 hipError_t launch_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
                           uint4 *packed, unsigned long long *area_part, hipStream_t st);
-hipError_t launch_axis(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
-                       const uint4 *packed, const double2 *w64, double2 *axis_part,
+hipError_t launch_axis(const FwdPlan &p, const int32_t *x, const int32_t *y, const uint4 *packed,
+                       const double2 *w64, unsigned long long *hist, double2 *axis_part,
                        hipStream_t st);
 hipError_t launch_contract(const FwdPlan &p, const uint4 *packed, const Tables &t, float *part,
                            hipStream_t st);
 hipError_t launch_epilogue(const FwdPlan &p, const float *part, const double2 *axis_part,
                            const unsigned long long *area_part, float *F, int64_t *area,
                            hipStream_t st);
+hipError_t launch_guard(const FwdPlan &p, const uint4 *packed, const double2 *w64, double2 *gpart,
+                        hipStream_t st);
+hipError_t launch_guard_epilogue(const FwdPlan &p, const double2 *gpart, float *F, hipStream_t st);
 hipError_t launch_debug_phases(const FwdPlan &p, const uint4 *packed, int axis, int k0, int nk,
                                int32_t *out, hipStream_t st);
 
@@ -108,9 +112,11 @@ struct BatchClip {
   unsigned long long *area_part;
   double2 *axis_part;
   float *part;
-  int64_t V, vpad, chunk, ax_chunk;
+  double2 *gpart;
+  unsigned long long *hist;
+  int64_t V, vpad, chunk, g_chunk;
   int T, shift, K, L, kp, lp, tiles_l, nsplit;
-  int ax_groups_k, ax_chunks;
+  int ax_fb_k, ax_chunks, g_chunks;
 };
 
 struct BatchLaunch {
@@ -118,8 +124,10 @@ struct BatchLaunch {
   int prec, tile;           // tile variant of the persistent contraction
   const BatchClip *clips;   // device
   int pre_blocks;           // pre-pass blocks per clip
-  const int4 *ax_desc;      // device: (clip, group, chunk) per axis block
+  const int4 *ax_desc;      // device: (clip, frequency block, bin chunk) per axis block
   int n_ax;
+  const int4 *g_desc;       // device: (clip, chunk) per guard block
+  int n_g;
   const int4 *items;        // device: (clip, tile, split) per work item, LPT order
   int n_items;
   int grid;                 // persistent workgroups
@@ -131,6 +139,7 @@ struct BatchLaunch {
 
 hipError_t launch_batch_prepass(const BatchLaunch &b, hipStream_t st);
 hipError_t launch_batch_axis(const BatchLaunch &b, const double2 *w64, hipStream_t st);
+hipError_t launch_batch_guard(const BatchLaunch &b, const double2 *w64, hipStream_t st);
 hipError_t launch_batch_contract(const BatchLaunch &b, const Tables &t, hipStream_t st);
 hipError_t launch_batch_epilogue(const BatchLaunch &b, hipStream_t st);
 int batch_grid(int tile, int prec);

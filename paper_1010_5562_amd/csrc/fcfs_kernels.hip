@@ -63,118 +63,228 @@ hipError_t launch_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y, 
 }
 
 // ---------------------------------------------------------------------------
-// Axis sums (Steps 2 and 3): for f = 1..K,
-//   Sx[f] = sum_v s_v y_v e(f x_v),  and for f = 1..L,  Sy[f] = sum_v s_v x_v e(f y_v),
-// with raw (unreduced) coordinates as weights, in FP64.  Each lane owns 8
-// consecutive frequencies f0..f0+7 of a 512-frequency group: e(f0 x) comes from
-// the FP64 table at the exact integer phase, the next seven from repeated
-// multiplication by e(x) (seven FP64 complex products, error ~1e-15).  The four
-// waves of a block take every fourth corner of the block's chunk and are
-// combined in a fixed order; one partial per (chunk, frequency) goes to the
-// epilogue.
+// Axis sums (Steps 2 and 3):
+//   Sx[f] = sum_v s_v y_v e(f x_v), f = 1..K,   Sy[f] = sum_v s_v x_v e(f y_v), f = 1..L,
+// taken, as in the paper's Steps 2 and 3, as 1-D DFTs of sparse images: the
+// weights s_v y_v are binned by x_v mod T into Hx (the signed vertical edge
+// lengths at each abscissa) and s_v x_v by y_v mod T into Hy, in exact int64
+// arithmetic (the order of the atomic adds cannot change the result); then
+//   Sx[f] = sum_{q < T} Hx[q] e(f q)
+// in FP64.  Cost O(V + (K + L) T) instead of O(V (K + L)).
 // ---------------------------------------------------------------------------
-constexpr int kAxR = 8;               // frequencies per lane
-constexpr int kAxGroup = 64 * kAxR;   // frequencies per group
-constexpr int kAxChunkMax = 1024;     // corners staged per block
+constexpr int kHistN = kTabN;   // bins per axis (T <= 8192)
+constexpr int kAxQChunk = 512;  // bins per DFT block
 
-__device__ __forceinline__ void axis_body(const int32_t *__restrict__ x,
+// Bins of one clip; hist = [Hx | Hy], kHistN int64 each, zeroed beforehand.
+__device__ __forceinline__ void hist_body(const int32_t *__restrict__ x,
                                           const int32_t *__restrict__ y,
-                                          const uint4 *__restrict__ packed,
-                                          const double2 *__restrict__ w64, int64_t V,
-                                          int64_t ax_chunk, int K, int L, int groups_k,
-                                          double2 *__restrict__ axis_part, int g, int chunk_idx) {
-  __shared__ uint32_t s_ph[kAxChunkMax];
-  __shared__ double s_wt[kAxChunkMax];
-  __shared__ double2 s_e1[kAxChunkMax];
-  __shared__ double2 red[3][64][kAxR];
-  const bool xaxis = g < groups_k;
-  const int gi = xaxis ? g : g - groups_k;
-  const int nf = xaxis ? K : L;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint32_t f0 = (uint32_t)(gi * kAxGroup + lane * kAxR + 1);
-  const int64_t v0 = (int64_t)chunk_idx * ax_chunk;
-  const int n = (int)(min(V, v0 + ax_chunk) - v0);
-  // stage the chunk: phase index, signed weight and e^{j 2 pi ph / N}
-  for (int i = threadIdx.x; i < n; i += 256) {
-    const int64_t v = v0 + i;
+                                          const uint4 *__restrict__ packed, int64_t V, int shift,
+                                          unsigned long long *__restrict__ hist, int blk,
+                                          int nblk) {
+  for (int64_t v = (int64_t)blk * 256 + threadIdx.x; v < V; v += (int64_t)nblk * 256) {
     const uint4 c = packed[v];
-    const uint32_t ph = (xaxis ? c.x : c.y) >> 3;
-    const double coord = (double)(xaxis ? y[v] : x[v]);
-    s_ph[i] = ph;
-    s_wt[i] = c.z ? -coord : coord;
-    s_e1[i] = w64[ph];
-  }
-  __syncthreads();
-  double re[kAxR], im[kAxR];
-#pragma unroll
-  for (int r = 0; r < kAxR; ++r) re[r] = im[r] = 0.0;
-  // each wave takes every fourth staged corner, four at a time
-  constexpr int U = 4;
-  for (int jb = wave; jb < n; jb += 4 * U) {
-    double wt[U];
-    double2 e1[U], z[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int j = jb + 4 * u;
-      const bool ok = j < n;
-      const int jj = ok ? j : jb;
-      wt[u] = ok ? s_wt[jj] : 0.0;
-      e1[u] = s_e1[jj];
-      z[u] = w64[(f0 * s_ph[jj]) & (uint32_t)(kTabN - 1)];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-#pragma unroll
-      for (int r = 0; r < kAxR; ++r) {
-        // e(f x) = cos - j sin of the table angle
-        re[r] = fma(wt[u], z[u].x, re[r]);
-        im[r] = fma(-wt[u], z[u].y, im[r]);
-        if (r + 1 < kAxR) {
-          const double zx = fma(z[u].x, e1[u].x, -z[u].y * e1[u].y);
-          const double zy = fma(z[u].x, e1[u].y, z[u].y * e1[u].x);
-          z[u].x = zx;
-          z[u].y = zy;
-        }
-      }
-    }
-  }
-  if (wave > 0)
-#pragma unroll
-    for (int r = 0; r < kAxR; ++r) red[wave - 1][lane][r] = make_double2(re[r], im[r]);
-  __syncthreads();
-  if (wave == 0) {
-#pragma unroll
-    for (int r = 0; r < kAxR; ++r) {
-      double sr = re[r], si = im[r];
-      for (int w = 0; w < 3; ++w) {
-        sr += red[w][lane][r].x;
-        si += red[w][lane][r].y;
-      }
-      const int f = (int)f0 + r;
-      if (f <= nf) {
-        const int slot = xaxis ? f - 1 : K + f - 1;
-        axis_part[(size_t)chunk_idx * (K + L) + slot] = make_double2(sr, si);
-      }
-    }
+    const long long sg = c.z ? -1 : 1;
+    const uint32_t qx = (c.x >> 3) >> shift, qy = (c.y >> 3) >> shift;
+    atomicAdd(&hist[qx], (unsigned long long)(sg * (long long)y[v]));
+    atomicAdd(&hist[kHistN + qy], (unsigned long long)(sg * (long long)x[v]));
   }
 }
 
-__global__ __launch_bounds__(256) void k_axis(const int32_t *__restrict__ x,
+__device__ __forceinline__ void zero_hist_body(unsigned long long *__restrict__ hist, int blk,
+                                               int nblk) {
+  for (int i = blk * 256 + threadIdx.x; i < 2 * kHistN; i += nblk * 256) hist[i] = 0ull;
+}
+
+// Block (fb, chunk): 256 frequencies f = 1 + 256 fb' + t of one axis against
+// the bins q in [chunk * kAxQChunk, ...) < T.  e(f q) from the exact table at
+// the first bin of every 32 and FP64 complex products in between.
+__device__ __forceinline__ void dft_body(const unsigned long long *__restrict__ hist,
+                                         const double2 *__restrict__ w64, int T, int shift, int K,
+                                         int L, int fb_k, double2 *__restrict__ axis_part, int fb,
+                                         int chunk) {
+  __shared__ double s_h[kAxQChunk];
+  const bool xaxis = fb < fb_k;
+  const int f = 1 + (xaxis ? fb : fb - fb_k) * 256 + threadIdx.x;
+  const int nf = xaxis ? K : L;
+  const unsigned long long *H = hist + (xaxis ? 0 : kHistN);
+  const int q0 = chunk * kAxQChunk;
+  const int n = min(kAxQChunk, T - q0);
+  for (int i = threadIdx.x; i < n; i += 256) s_h[i] = (double)(long long)H[q0 + i];
+  __syncthreads();
+  double re = 0.0, im = 0.0;
+  const uint32_t uf = (uint32_t)f, mask = (uint32_t)(kTabN - 1);
+  const double2 w1 = w64[(uf << shift) & mask];
+  double2 w = make_double2(1.0, 0.0);
+  for (int i = 0; i < n; ++i) {
+    if ((i & 31) == 0) w = w64[((uf * (uint32_t)(q0 + i)) << shift) & mask];
+    const double h = s_h[i];
+    re = fma(h, w.x, re);  // e(f q) = conj(w)
+    im = fma(-h, w.y, im);
+    const double nx = w.x * w1.x - w.y * w1.y, ny = w.x * w1.y + w.y * w1.x;
+    w = make_double2(nx, ny);
+  }
+  if (f <= nf) {
+    const int slot = xaxis ? f - 1 : K + f - 1;
+    axis_part[(size_t)chunk * (K + L) + slot] = make_double2(re, im);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_zero_hist(unsigned long long *__restrict__ hist) {
+  zero_hist_body(hist, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_hist(const int32_t *__restrict__ x,
                                               const int32_t *__restrict__ y,
-                                              const uint4 *__restrict__ packed,
-                                              const double2 *__restrict__ w64, int64_t V,
-                                              int64_t ax_chunk, int K, int L, int groups_k,
-                                              double2 *__restrict__ axis_part) {
-  axis_body(x, y, packed, w64, V, ax_chunk, K, L, groups_k, axis_part, blockIdx.x, blockIdx.y);
+                                              const uint4 *__restrict__ packed, int64_t V,
+                                              int shift, unsigned long long *__restrict__ hist) {
+  hist_body(x, y, packed, V, shift, hist, blockIdx.x, gridDim.x);
 }
 
-hipError_t launch_axis(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
-                       const uint4 *packed, const double2 *w64, double2 *axis_part,
+__global__ __launch_bounds__(256) void k_axis_dft(const unsigned long long *__restrict__ hist,
+                                                  const double2 *__restrict__ w64, int T, int shift,
+                                                  int K, int L, int fb_k,
+                                                  double2 *__restrict__ axis_part) {
+  dft_body(hist, w64, T, shift, K, L, fb_k, axis_part, blockIdx.x, blockIdx.y);
+}
+
+hipError_t launch_axis(const FwdPlan &p, const int32_t *x, const int32_t *y, const uint4 *packed,
+                       const double2 *w64, unsigned long long *hist, double2 *axis_part,
                        hipStream_t st) {
-  (void)s;
   if (p.K + p.L == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_axis, dim3(p.ax_groups_k + p.ax_groups_l, p.ax_chunks), dim3(256), 0, st,
-                     x, y, packed, w64, p.V, p.ax_chunk, p.K, p.L, p.ax_groups_k, axis_part);
+  hipLaunchKernelGGL(k_zero_hist, dim3(16), dim3(256), 0, st, hist);
+  if (p.V > 0)
+    hipLaunchKernelGGL(k_hist, dim3((unsigned)std::min<int64_t>(1024, (p.V + 255) / 256)),
+                       dim3(256), 0, st, x, y, packed, p.V, p.shift, hist);
+  hipLaunchKernelGGL(k_axis_dft, dim3(p.ax_fb_k + p.ax_fb_l, p.ax_chunks), dim3(256), 0, st, hist,
+                     w64, p.T, p.shift, p.K, p.L, p.ax_fb_k, axis_part);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Low-frequency guard block: S(k, l) = sum_v s_v e(k x_v) e(l y_v) for
+// 1 <= k <= gk, 1 <= |l| <= gl (gk, gl <= 8) in FP64, replacing the MFMA
+// values there.  The 1/(k l) factor of alpha_{k,l} amplifies any error of the
+// contraction most at these frequencies.  Thread t of the first 128 owns the
+// pair (k, l) = (1 + t/16, l(t%16)), l(j) = j+1 for j < 8, -(j-7) otherwise;
+// threads 128..255 take the odd corners of the same pairs.  Per staged corner
+// the block tabulates e(k x), e(l y), k, l = 1..8: the exact FP64 table value
+// at k = 1, the higher powers by FP64 complex products (error ~1e-15).
+// ---------------------------------------------------------------------------
+constexpr int kGuard = 8;
+constexpr int kGuardPairs = kGuard * 2 * kGuard;  // 128
+constexpr int kGuardStage = 64;                   // corners staged at a time
+
+__device__ __forceinline__ void guard_body(const uint4 *__restrict__ packed,
+                                           const double2 *__restrict__ w64, int64_t V,
+                                           int64_t g_chunk, double2 *__restrict__ gpart,
+                                           int chunk_idx) {
+  __shared__ double2 s_ex[kGuardStage][kGuard];  // e^{+j k theta_x}
+  __shared__ double2 s_ey[kGuardStage][kGuard];  // e^{+j l theta_y}
+  __shared__ double s_sg[kGuardStage];
+  __shared__ double2 red[kGuardPairs];
+  const int t = threadIdx.x & (kGuardPairs - 1), half = threadIdx.x >> 7;
+  const int k = 1 + t / (2 * kGuard);
+  const int j = t % (2 * kGuard);
+  const int la = j < kGuard ? j + 1 : j - kGuard + 1;  // |l|
+  const bool lneg = j >= kGuard;
+  const int64_t v0 = (int64_t)chunk_idx * g_chunk;
+  const int64_t v1 = min(V, v0 + g_chunk);
+  double re = 0.0, im = 0.0;
+  for (int64_t vb = v0; vb < v1; vb += kGuardStage) {
+    const int n = (int)min((int64_t)kGuardStage, v1 - vb);
+    __syncthreads();
+    // threads 0..127 tabulate the x powers of corner i, 128..255 the y powers:
+    // one exact table value e^{j theta}, then seven FP64 complex products
+    {
+      const int i = threadIdx.x & 127;
+      if (i < n) {
+        const uint4 c = packed[vb + i];
+        const double2 w1 = w64[(half ? c.y : c.x) >> 3];
+        double2 w = w1;
+        double2(*dst)[kGuard] = half ? s_ey : s_ex;
+#pragma unroll
+        for (int f = 0; f < kGuard; ++f) {
+          dst[i][f] = w;
+          const double nx = w.x * w1.x - w.y * w1.y, ny = w.x * w1.y + w.y * w1.x;
+          w = make_double2(nx, ny);
+        }
+        if (!half) s_sg[i] = c.z ? -1.0 : 1.0;
+      }
+    }
+    __syncthreads();
+    for (int vi = half; vi < n; vi += 2) {
+      const double2 a = s_ex[vi][k - 1];
+      double2 b = s_ey[vi][la - 1];
+      if (lneg) b.y = -b.y;
+      // e(kx) e(ly) = conj(a b) with a, b the e^{+j...} table values
+      const double pr = a.x * b.x - a.y * b.y, pi = a.x * b.y + a.y * b.x;
+      re = fma(s_sg[vi], pr, re);
+      im = fma(-s_sg[vi], pi, im);
+    }
+  }
+  __syncthreads();
+  if (half == 1) red[t] = make_double2(re, im);
+  __syncthreads();
+  if (half == 0) gpart[(size_t)chunk_idx * kGuardPairs + t] = make_double2(re + red[t].x, im + red[t].y);
+}
+
+__global__ __launch_bounds__(256) void k_guard(const uint4 *__restrict__ packed,
+                                               const double2 *__restrict__ w64, int64_t V,
+                                               int64_t g_chunk, double2 *__restrict__ gpart) {
+  guard_body(packed, w64, V, g_chunk, gpart, blockIdx.x);
+}
+
+// F[k, l] = alpha_{k,l} S(k, l) on the guard block, F[-k, -l] its conjugate;
+// chunk partials summed in order.
+__device__ __forceinline__ void guard_epilogue_body(const double2 *__restrict__ gpart,
+                                                    int g_chunks, int K, int L, double T,
+                                                    float2 *__restrict__ F) {
+  // 1024 threads: pair t = tid % 128 sums the chunks c = q, q+8, ... with
+  // q = tid / 128; the eight sums are added in order
+  __shared__ double2 red[8][kGuardPairs];
+  const int t = threadIdx.x & (kGuardPairs - 1), q = threadIdx.x >> 7;
+  double re = 0.0, im = 0.0;
+  for (int c = q; c < g_chunks; c += 8) {
+    const double2 v = gpart[(size_t)c * kGuardPairs + t];
+    re += v.x;
+    im += v.y;
+  }
+  red[q][t] = make_double2(re, im);
+  __syncthreads();
+  if (q != 0) return;
+  for (int w = 1; w < 8; ++w) {
+    re += red[w][t].x;
+    im += red[w][t].y;
+  }
+  const int k = 1 + t / (2 * kGuard);
+  const int j = t % (2 * kGuard);
+  const int l = j < kGuard ? j + 1 : -(j - kGuard + 1);
+  if (k > K || abs(l) > L) return;
+  const double a = -T / (4.0 * kPi * kPi * (double)k * (double)l);
+  const size_t W = 2 * (size_t)L + 1;
+  F[(size_t)(K + k) * W + (L + l)] = make_float2((float)(a * re), (float)(a * im));
+  F[(size_t)(K - k) * W + (L - l)] = make_float2((float)(a * re), (float)(-a * im));
+}
+
+__global__ __launch_bounds__(1024) void k_guard_epilogue(const double2 *__restrict__ gpart,
+                                                         int g_chunks, int K, int L, double T,
+                                                         float2 *__restrict__ F) {
+  guard_epilogue_body(gpart, g_chunks, K, L, T, F);
+}
+
+hipError_t launch_guard(const FwdPlan &p, const uint4 *packed, const double2 *w64, double2 *gpart,
+                        hipStream_t st) {
+  if (p.K == 0 || p.L == 0 || p.V == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_guard, dim3(p.g_chunks), dim3(256), 0, st, packed, w64, p.V, p.g_chunk,
+                     gpart);
+  return hipGetLastError();
+}
+
+hipError_t launch_guard_epilogue(const FwdPlan &p, const double2 *gpart, float *F, hipStream_t st) {
+  if (p.K == 0 || p.L == 0) return hipSuccess;
+  if (p.V == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_guard_epilogue, dim3(1), dim3(8 * kGuardPairs), 0, st, gpart, p.g_chunks,
+                     p.K, p.L, (double)p.T, (float2 *)F);
   return hipGetLastError();
 }
 
@@ -692,6 +802,12 @@ __global__ __launch_bounds__(256) void k_batch_prepass(const BatchClip *__restri
   const BatchClip &c = clips[blockIdx.y];
   prepass_body(c.x, c.y, c.s, c.V, c.vpad, (uint32_t)(c.T - 1), c.shift, c.packed, c.area_part,
                blockIdx.x, gridDim.x);
+  zero_hist_body(c.hist, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_batch_hist(const BatchClip *__restrict__ clips) {
+  const BatchClip &c = clips[blockIdx.y];
+  hist_body(c.x, c.y, c.packed, c.V, c.shift, c.hist, blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(256) void k_batch_axis(const BatchClip *__restrict__ clips,
@@ -699,8 +815,27 @@ __global__ __launch_bounds__(256) void k_batch_axis(const BatchClip *__restrict_
                                                     const double2 *__restrict__ w64) {
   const int4 d = desc[blockIdx.x];
   const BatchClip &c = clips[d.x];
-  axis_body(c.x, c.y, c.packed, w64, c.V, c.ax_chunk, c.K, c.L, c.ax_groups_k, c.axis_part, d.y,
-            d.z);
+  dft_body(c.hist, w64, c.T, c.shift, c.K, c.L, c.ax_fb_k, c.axis_part, d.y, d.z);
+}
+
+__global__ __launch_bounds__(256) void k_batch_guard(const BatchClip *__restrict__ clips,
+                                                     const int4 *__restrict__ desc,
+                                                     const double2 *__restrict__ w64) {
+  const int4 d = desc[blockIdx.x];
+  const BatchClip &c = clips[d.x];
+  guard_body(c.packed, w64, c.V, c.g_chunk, c.gpart, d.y);
+}
+
+__global__ __launch_bounds__(1024) void k_batch_guard_epilogue(const BatchClip *__restrict__ clips) {
+  const BatchClip &c = clips[blockIdx.x];
+  if (c.K == 0 || c.L == 0 || c.V == 0) return;
+  guard_epilogue_body(c.gpart, c.g_chunks, c.K, c.L, (double)c.T, c.F);
+}
+
+hipError_t launch_batch_guard(const BatchLaunch &b, const double2 *w64, hipStream_t st) {
+  if (b.n_g > 0)
+    hipLaunchKernelGGL(k_batch_guard, dim3(b.n_g), dim3(256), 0, st, b.clips, b.g_desc, w64);
+  return hipGetLastError();
 }
 
 // Next work item for the whole workgroup (-1 when the list is exhausted).
@@ -787,6 +922,8 @@ hipError_t launch_batch_prepass(const BatchLaunch &b, hipStream_t st) {
 }
 
 hipError_t launch_batch_axis(const BatchLaunch &b, const double2 *w64, hipStream_t st) {
+  if (b.n_clips > 0)
+    hipLaunchKernelGGL(k_batch_hist, dim3(b.pre_blocks, b.n_clips), dim3(256), 0, st, b.clips);
   if (b.n_ax > 0)
     hipLaunchKernelGGL(k_batch_axis, dim3(b.n_ax), dim3(256), 0, st, b.clips, b.ax_desc, w64);
   return hipGetLastError();
@@ -834,6 +971,9 @@ hipError_t launch_batch_epilogue(const BatchLaunch &b, hipStream_t st) {
   if (b.n_epi > 0)
     hipLaunchKernelGGL(k_batch_epilogue, dim3(b.n_epi), dim3(256), 0, st, b.clips, b.epi_off,
                        b.n_clips);
+  if (b.n_clips > 0)
+    hipLaunchKernelGGL(k_batch_guard_epilogue, dim3(b.n_clips), dim3(8 * kGuardPairs), 0, st,
+                       b.clips);
   return hipGetLastError();
 }
 

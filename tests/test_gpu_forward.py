@@ -163,3 +163,19 @@ def test_full_size_precision_clip_sampled(P, oracle_lib, prec):
     e = float(np.max(np.abs(F[kk + K, ll + K] - ref)) / abs(f00))
     _say(f"  err/|F00| = {e:.3e}")
     assert e <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "fp32"])
+def test_disjoint_low_fill_clip(P, oracle_lib, prec):
+    # polygons confined to disjoint cells (fill factor well below one, as in a
+    # real layer): the hardest case for an error bound relative to |F[0,0]|
+    T, K = 8192, 511
+    clip = synth.clip(33, T, K, min_vertices=200_000, disjoint=True)
+    _say(f"disjoint clip V={clip.n_vertices} T={T} K={K} prec={prec}")
+    kk, ll = _sample_points(K, K, 300, 3)
+    ref = oracle_lib.cfs_points(clip.xy, clip.off, T, kk, ll)
+    f00 = oracle_lib.cfs_points(clip.xy, clip.off, T, [0], [0])[0]
+    F, a = _run(P, *_corners(P, clip), T, K, K, prec)
+    e = float(np.max(np.abs(F[kk + K, ll + K] - ref)) / abs(f00))
+    _say(f"  fill {abs(f00) * T / T**2:.3f}, err/|F00| = {e:.3e}")
+    assert e <= TOL[prec]
