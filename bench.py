@@ -60,14 +60,17 @@ def traffic_for(key: str):
     return None if e is None else e.get("bytes_per_launch")
 
 
-def timed(fn, steps: int, warmup: int, handle):
-    """Runs fn warmup + steps times; returns (ms per step, per-kernel events)."""
+def timed(fn, steps: int, warmup: int, handle, kinds=("contract",)):
+    """Runs fn warmup + steps times; returns (ms per step, per-kernel events).
+
+    Only the launches of ``kinds`` are bracketed by events inside the timed
+    region (two event records per launch on the launch's own stream)."""
     import torch
 
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    handle.profile_begin()
+    handle.profile_begin(kinds)
     t_a = time.perf_counter()
     for _ in range(steps):
         fn()
@@ -75,6 +78,20 @@ def timed(fn, steps: int, warmup: int, handle):
     t_b = time.perf_counter()
     prof = handle.profile_end()
     return (t_b - t_a) * 1e3 / steps, prof
+
+
+def breakdown(fn, steps: int, handle):
+    """Per-kind average kernel times from extra, untimed steps with events
+    around every launch."""
+    import torch
+
+    torch.cuda.synchronize()
+    handle.profile_begin()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    prof = handle.profile_end()
+    return {k: kavg(prof, k) for k in ("prepass", "axis", "contract", "epilogue")}
 
 
 def kavg(prof, kind):
@@ -147,6 +164,10 @@ def main() -> int:
                                            area_out=area), args.steps, args.warmup, h)
         legs[prec] = {"ms": ms, "prof": prof, "F": F.cpu().numpy().astype(np.complex128),
                       "area": int(area.item())}
+        if prec == "bf16":
+            legs[prec]["breakdown"] = breakdown(
+                lambda: P.forward(xd, yd, sd, T, K, L, precision=prec, out=F, area_out=area),
+                max(3, args.steps // 2), h)
         log(f"{prec}: {ms:.3f} ms/step  {pairs / ms * 1e3:.4g} pairs/s  "
             f"contract {kavg(prof, 'contract'):.3f} ms")
 
@@ -226,8 +247,9 @@ def main() -> int:
             "flops_per_launch": flops,
         },
         "cpu_baseline": cpu,
-        "kernels_ms": {k: kavg(main_leg["prof"], k) for k in ("prepass", "axis", "contract",
-                                                              "epilogue")},
+        # per-kind kernel times from separate steps with events on every launch
+        # (the side-stream figure spans the histograms, guard block and axis DFTs)
+        "kernels_ms": main_leg["breakdown"],
         "area_exact": main_leg["area"],
     }
     for prec in ("fp32", "fp16"):
@@ -287,7 +309,7 @@ def main() -> int:
     log(f"batch: 256 clips, {nvb} corners, {bpairs:.3e} pairs (generated in "
         f"{time.time() - t0:.1f}s)")
     batch = P.Batch(bargs, precision="bf16")
-    msb, profb = timed(batch.run, max(3, args.steps // 4), 1, h)
+    msb, profb = timed(batch.run, max(3, args.steps // 4), 1, h, kinds=("batch",))
     # error on the four smallest clips and four random ones, sampled points
     order = np.argsort([int(a[0].size) for a in bargs])
     pick = list(order[:4]) + list(rng.choice(order[4:], 4, replace=False))
@@ -342,7 +364,8 @@ def main() -> int:
         loss = ((Hd * Fv - Gt).abs() ** 2).sum()
         loss.backward()
 
-    ms5, prof5 = timed(step5, max(3, args.steps // 4), 1, h)
+    ms5, prof5 = timed(step5, max(3, args.steps // 4), 1, h,
+                       kinds=("prepass", "contract", "epilogue", "adjoint"))
     V5 = int(geom.base_x.numel())
     adj = {
         "workload": (f"adjoint: {V5} corners, T={T5}, |k|,|l|<={K5}, loss sum |H F - G|^2 with a "

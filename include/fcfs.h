@@ -193,13 +193,15 @@ fcfs_status fcfs_set_tile(fcfs_handle *h, int32_t variant);
 fcfs_status fcfs_workspace_size_tile(const fcfs_clip *c, fcfs_precision p, int32_t tile,
                                      size_t *bytes);
 
-/* Per-kernel timing with hipEvents on the handle's stream.  After
- * fcfs_profile_begin every launch is bracketed by two events;
- * fcfs_profile_end waits for them and writes, for kind i < nkinds, the summed
- * milliseconds ms[i] and the launch count count[i], then stops recording.
- * Kinds: 0 pre-pass, 1 axis sums, 2 contraction, 3 epilogue, 4 adjoint
- * kernels, 5 batched contraction. */
-fcfs_status fcfs_profile_begin(fcfs_handle *h);
+/* Per-kernel timing with hipEvents on the stream each kernel runs on.  After
+ * fcfs_profile_begin every launch of a kind whose bit is set in `kinds` (0:
+ * every kind) is bracketed by two events; fcfs_profile_end waits for them and
+ * writes, for kind i < nkinds, the summed milliseconds ms[i] and the launch
+ * count count[i], then stops recording.  Kinds: 0 pre-pass, 1 side-stream
+ * work (histograms, guard block, axis DFTs), 2 contraction, 3 epilogue,
+ * 4 adjoint kernels, 5 batched graph.  Each bracketed launch adds two event
+ * records to its stream. */
+fcfs_status fcfs_profile_begin(fcfs_handle *h, uint32_t kinds);
 fcfs_status fcfs_profile_end(fcfs_handle *h, double *ms, int64_t *count, int32_t nkinds);
 
 const char *fcfs_status_string(fcfs_status s);

@@ -125,8 +125,12 @@ class Handle:
 
     PROFILE_KINDS = ("prepass", "axis", "contract", "epilogue", "adjoint", "batch")
 
-    def profile_begin(self):
-        check(self.lib.fcfs_profile_begin(self._h), self._h)
+    def profile_begin(self, kinds=None):
+        """Starts event timing of the named kinds (all kinds when None)."""
+        mask = 0
+        for k in kinds or ():
+            mask |= 1 << self.PROFILE_KINDS.index(k)
+        check(self.lib.fcfs_profile_begin(self._h, mask), self._h)
 
     def profile_end(self):
         """{kind: (total_ms, launches)} since profile_begin (waits for the events)."""

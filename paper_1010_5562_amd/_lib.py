@@ -69,6 +69,7 @@ def load() -> ctypes.CDLL:
             "(python -c 'import __graft_entry__ as g; g.build()')")
     lib = ctypes.CDLL(LIB_PATH)
     P, i32, i64, c_int = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int
+    u32 = ctypes.c_uint32
     sz = ctypes.POINTER(ctypes.c_size_t)
     clip_p = ctypes.POINTER(FcfsClip)
     sig = {
@@ -90,7 +91,7 @@ def load() -> ctypes.CDLL:
         "fcfs_autotune": [P, ctypes.c_char_p, c_int],
         "fcfs_load_tune": [P, ctypes.c_char_p],
         "fcfs_set_tile": [P, i32],
-        "fcfs_profile_begin": [P],
+        "fcfs_profile_begin": [P, u32],
         "fcfs_profile_end": [P, P, P, i32],
     }
     for name, args in sig.items():

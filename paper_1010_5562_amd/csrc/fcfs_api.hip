@@ -29,6 +29,7 @@ struct fcfs_handle {
   int tile_override = -1;
   std::string err;
   bool prof = false;
+  uint32_t prof_mask = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[kProfKinds];
   // side stream for work that overlaps the contraction (axis sums), joined
   // back into `stream` with events; default priority like every stream here
@@ -194,6 +195,7 @@ void free_tables(Tables &t) {
 // ---------------------------------------------------------------------------
 constexpr int kMaxFreq = 4095;  // |k|, |l| cut-off limit (phases stay below 2^29)
 constexpr int kTargetWG = 512;  // two contraction workgroups per CU on 256 CUs
+constexpr int kGuardBlocks = 64;  // most blocks of the guard block's corner split
 
 int kbucket(int K) {
   int b = 0;
@@ -255,25 +257,30 @@ fcfs_status make_plan(fcfs_handle *h, int64_t V, int T, int K, int L, int prec, 
   q.chunk = std::max<int64_t>(16, round_up(ceil_div(std::max<int64_t>(V, 1), ns), 16));
   q.vpad = q.chunk * q.nsplit;
   q.pre_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(q.vpad, 256)));
+  q.hist_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(256, ceil_div(V, 1024)));
   q.ax_fb_k = (int)ceil_div(K, 256);
   q.ax_fb_l = (int)ceil_div(L, 256);
-  q.ax_chunks = (int)ceil_div(T, 512);
+  q.ax_chunks = (int)ceil_div(T, fcfs::kAxisBins);
+  // guard block: at most kGuardBlocks blocks of at least 512 corners
+  q.g_chunk = std::max<int64_t>(512, round_up(ceil_div(V, kGuardBlocks), 64));
+  q.g_chunks = (int)std::max<int64_t>(1, ceil_div(V, q.g_chunk));
   size_t off = 0;
   q.off_packed = off;
   off += align256(sizeof(uint4) * (size_t)q.vpad);
   q.off_area = off;
-  off += align256(sizeof(unsigned long long) * (size_t)q.pre_blocks);
+  off += align256(sizeof(unsigned long long) * q.pre_blocks);
   q.off_hist = off;
   off += align256(sizeof(unsigned long long) * 2 * fcfs::kTabN);
   q.off_axis = off;
   off += align256(sizeof(double2) * (size_t)q.ax_chunks * (size_t)std::max(1, K + L));
   q.off_part = off;
   off += align256(sizeof(float) * 4 * (size_t)q.nsplit * (size_t)q.kp * (size_t)q.lp);
-  // at least 128 corners per guard block, at most 256 partials per pair
-  q.g_chunk = std::max<int64_t>(128, ceil_div(V, 256));
-  q.g_chunks = (int)std::max<int64_t>(1, ceil_div(V, q.g_chunk));
   q.off_guard = off;
-  off += align256(sizeof(double2) * 128 * (size_t)q.g_chunks);
+  off += align256(sizeof(double) * fcfs::kGuardD * (size_t)q.g_chunks);
+  q.off_gfinal = off;
+  off += align256(sizeof(double) * fcfs::kGuardD);
+  q.off_gcount = off;
+  off += 256;
   q.bytes = off;
   *p = q;
   return FCFS_OK;
@@ -358,7 +365,7 @@ struct ProfScope {
   hipEvent_t a = nullptr, b = nullptr;
   ProfScope(fcfs_handle *h_, int kind_, hipStream_t st_ = nullptr)
       : h(h_), kind(kind_), st(st_ ? st_ : h_->stream) {
-    if (!h->prof) return;
+    if (!h->prof || !((h->prof_mask >> kind) & 1u)) return;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
       h->prof = false;
       return;
@@ -378,42 +385,41 @@ T *ws_at(void *ws, size_t off) {
 }
 
 fcfs_status run_forward(fcfs_handle *h, const fcfs_clip *c, const FwdPlan &p, void *ws) {
-  uint4 *packed = ws_at<uint4>(ws, p.off_packed);
-  auto *area_part = ws_at<unsigned long long>(ws, p.off_area);
-  auto *axis_part = ws_at<double2>(ws, p.off_axis);
-  float *part = ws_at<float>(ws, p.off_part);
   hipError_t e;
+  const bool grid2d = p.K > 0 && p.L > 0, side = p.K + p.L > 0;
   {
     ProfScope ps(h, kProfPrepass);
-    if ((e = fcfs::launch_prepass(p, c->x, c->y, c->s, packed, area_part, h->stream)))
+    if ((e = fcfs::launch_prepass(p, c->x, c->y, c->s, ws_at<uint4>(ws, p.off_packed),
+                                  ws_at<unsigned long long>(ws, p.off_area),
+                                  ws_at<unsigned long long>(ws, p.off_hist),
+                                  ws_at<unsigned int>(ws, p.off_gcount), h->stream)))
       return hip_fail(h, e, "pre-pass launch");
   }
-  // the FP64 axis sums run on the side stream, overlapping the contraction
-  if ((e = hipEventRecord(h->ev_fork, h->stream)) ||
-      (e = hipStreamWaitEvent(h->side, h->ev_fork, 0)))
-    return hip_fail(h, e, "fork");
-  double2 *gpart = ws_at<double2>(ws, p.off_guard);
-  {
-    ProfScope ps(h, kProfAxis, h->side);
-    if ((e = fcfs::launch_axis(p, c->x, c->y, packed, h->tab.w64,
-                               ws_at<unsigned long long>(ws, p.off_hist), axis_part, h->side)))
-      return hip_fail(h, e, "axis launch");
-    if ((e = fcfs::launch_guard(p, packed, h->tab.w64, gpart, h->side)))
-      return hip_fail(h, e, "guard launch");
-  }
-  if ((e = hipEventRecord(h->ev_join, h->side))) return hip_fail(h, e, "join");
-  if (p.K > 0 && p.L > 0) {
+  if (side && (e = hipEventRecord(h->ev_fork, h->stream))) return hip_fail(h, e, "fork");
+  // the contraction is enqueued first so that it starts right after the
+  // pre-pass; the histograms, guard block and axis DFTs run beside it on the
+  // side stream
+  if (grid2d) {
     ProfScope ps(h, kProfContract);
-    if ((e = fcfs::launch_contract(p, packed, h->tab, part, h->stream)))
+    if ((e = fcfs::launch_contract(p, ws_at<uint4>(ws, p.off_packed), h->tab,
+                                   ws_at<float>(ws, p.off_part), h->stream)))
       return hip_fail(h, e, "contraction launch");
   }
-  if ((e = hipStreamWaitEvent(h->stream, h->ev_join, 0))) return hip_fail(h, e, "join");
+  if (side) {
+    if ((e = hipStreamWaitEvent(h->side, h->ev_fork, 0))) return hip_fail(h, e, "fork");
+    {
+      ProfScope ps(h, kProfAxis, h->side);
+      if ((e = fcfs::launch_side(p, c->x, c->y, h->tab.w64, ws, h->side)))
+        return hip_fail(h, e, "side launch");
+    }
+    if ((e = hipEventRecord(h->ev_join, h->side)) ||
+        (e = hipStreamWaitEvent(h->stream, h->ev_join, 0)))
+      return hip_fail(h, e, "join");
+  }
   {
     ProfScope ps(h, kProfEpilogue);
-    if ((e = fcfs::launch_epilogue(p, part, axis_part, area_part, c->F, c->area, h->stream)))
+    if ((e = fcfs::launch_epilogue(p, ws, c->F, c->area, h->stream)))
       return hip_fail(h, e, "epilogue launch");
-    if ((e = fcfs::launch_guard_epilogue(p, gpart, c->F, h->stream)))
-      return hip_fail(h, e, "guard epilogue launch");
   }
   return FCFS_OK;
 }
@@ -510,7 +516,7 @@ fcfs_status fcfs_set_stream(fcfs_handle *h, void *hip_stream) {
   return FCFS_OK;
 }
 
-fcfs_status fcfs_profile_begin(fcfs_handle *h) {
+fcfs_status fcfs_profile_begin(fcfs_handle *h, uint32_t kinds) {
   if (!h) return fail(nullptr, FCFS_ERR_INVALID_ARG, "handle is NULL");
   for (auto &v : h->prof_ev)
     for (auto &pr : v) {
@@ -519,6 +525,7 @@ fcfs_status fcfs_profile_begin(fcfs_handle *h) {
     }
   for (auto &v : h->prof_ev) v.clear();
   h->prof = true;
+  h->prof_mask = kinds ? kinds : ~0u;
   return FCFS_OK;
 }
 
@@ -666,7 +673,7 @@ fcfs_status fcfs_debug_phases(fcfs_handle *h, const fcfs_clip *c, int32_t axis, 
   if (e) return hip_fail(h, e, "hipMalloc");
   uint4 *packed = (uint4 *)tmp;
   auto *ap = ws_at<unsigned long long>(tmp, align256(sizeof(uint4) * (size_t)q.vpad));
-  if ((e = fcfs::launch_prepass(q, c->x, c->y, c->s, packed, ap, h->stream)) ||
+  if ((e = fcfs::launch_prepass(q, c->x, c->y, c->s, packed, ap, nullptr, nullptr, h->stream)) ||
       (e = fcfs::launch_debug_phases(q, packed, axis, k0, nk, p, h->stream)) ||
       (e = hipStreamSynchronize(h->stream))) {
     (void)hipFree(tmp);
@@ -701,7 +708,8 @@ fcfs_status fcfs_adjoint_band(fcfs_handle *h, const fcfs_clip *c, const float *g
   hipError_t e;
   ProfScope ps(h, kProfAdjoint);
   if ((e = fcfs::launch_prepass(q, c->x, c->y, c->s, ws_at<uint4>(ws, a.off_packed),
-                                ws_at<unsigned long long>(ws, a.off_area), h->stream)))
+                                ws_at<unsigned long long>(ws, a.off_area), nullptr, nullptr,
+                                h->stream)))
     return hip_fail(h, e, "pre-pass launch");
   if ((e = fcfs::launch_adjoint(a, c->x, c->y, c->s, grad_F, h->tab, ws, gx, gy, h->stream)))
     return hip_fail(h, e, "adjoint launch");
@@ -749,9 +757,10 @@ constexpr int kBatchPreBlocks = 64;
 // device pointers are filled in once the workspace base is known).
 struct BatchLayout {
   std::vector<fcfs::BatchClip> bc;
-  std::vector<size_t> off_packed, off_area, off_hist, off_axis, off_part, off_guard;
-  std::vector<int4> ax_desc, items, g_desc;
-  std::vector<int> epi_off, epa_off;
+  std::vector<size_t> off_packed, off_area, off_hist, off_axis, off_part, off_guard, off_gfinal,
+      off_gcount;
+  std::vector<int4> ax_desc, items, side_desc;
+  std::vector<int> epi_off;
   size_t bytes = 0;
 };
 
@@ -769,12 +778,13 @@ fcfs_status batch_layout(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec
   L->off_axis.assign(n, 0);
   L->off_part.assign(n, 0);
   L->off_guard.assign(n, 0);
+  L->off_gfinal.assign(n, 0);
+  L->off_gcount.assign(n, 0);
   L->off_hist.assign(n, 0);
-  L->g_desc.clear();
+  L->side_desc.clear();
   L->ax_desc.clear();
   L->items.clear();
   L->epi_off.assign(n + 1, 0);
-  L->epa_off.assign(n + 1, 0);
   size_t off = 256;  // the work counter lives at the head of the workspace
   std::vector<std::pair<int64_t, int4>> items;
   for (int i = 0; i < n; ++i) {
@@ -799,19 +809,21 @@ fcfs_status batch_layout(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec
     b.vpad = b.chunk * b.nsplit;
     const int fk = (int)ceil_div(ci.K, 256), fl = (int)ceil_div(ci.L, 256);
     b.ax_fb_k = fk;
-    b.ax_chunks = (int)ceil_div(ci.T, 512);
+    b.ax_chunks = (int)ceil_div(ci.T, fcfs::kAxisBins);
     for (int fb = 0; fb < fk + fl; ++fb)
       for (int ch = 0; ch < b.ax_chunks; ++ch) L->ax_desc.push_back(make_int4(i, fb, ch, 0));
-    b.g_chunk = std::max<int64_t>(128, ceil_div(ci.V, 256));
+    b.g_chunk = std::max<int64_t>(512, round_up(ceil_div(ci.V, kGuardBlocks), 64));
     b.g_chunks = (int)std::max<int64_t>(1, ceil_div(ci.V, b.g_chunk));
-    if (ci.V > 0 && ci.K > 0 && ci.L > 0)
-      for (int ch = 0; ch < b.g_chunks; ++ch) L->g_desc.push_back(make_int4(i, ch, 0, 0));
+    b.hist_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(64, ceil_div(ci.V, 1024)));
+    if (ci.K > 0 && ci.L > 0)
+      for (int ch = 0; ch < b.g_chunks; ++ch) L->side_desc.push_back(make_int4(i, 1, ch, 0));
+    if (ci.K + ci.L > 0)
+      for (int hb = 0; hb < b.hist_blocks; ++hb) L->side_desc.push_back(make_int4(i, 0, hb, 0));
     if (ci.K > 0 && ci.L > 0)
       for (int t = 0; t < tiles; ++t)
         for (int sp = 0; sp < b.nsplit; ++sp)
           items.push_back({b.chunk * (int64_t)wgk * wgl, make_int4(i, t, sp, 0)});
-    L->epi_off[i + 1] = L->epi_off[i] + (int)(ceil_div(ci.L, 64) * ci.K);
-    L->epa_off[i + 1] = L->epa_off[i] + (int)std::max<int64_t>(1, ceil_div(ci.K + ci.L, 16));
+    L->epi_off[i + 1] = L->epi_off[i] + fcfs::epilogue_block_count(ci.K, ci.L);
     L->off_packed[i] = off;
     off += align256(sizeof(uint4) * (size_t)b.vpad);
     L->off_area[i] = off;
@@ -823,7 +835,11 @@ fcfs_status batch_layout(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec
     L->off_part[i] = off;
     off += align256(sizeof(float) * 4 * (size_t)b.nsplit * (size_t)b.kp * (size_t)b.lp);
     L->off_guard[i] = off;
-    off += align256(sizeof(double2) * 128 * (size_t)b.g_chunks);
+    off += align256(sizeof(double) * fcfs::kGuardD * (size_t)b.g_chunks);
+    L->off_gfinal[i] = off;
+    off += align256(sizeof(double) * fcfs::kGuardD);
+    L->off_gcount[i] = off;
+    off += 256;
   }
   // longest processing time first; ties keep clip order
   std::stable_sort(items.begin(), items.end(),
@@ -892,7 +908,9 @@ fcfs_status build_plan(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec, 
     b.area_part = ws_at<unsigned long long>(ws, L.off_area[i]);
     b.axis_part = ws_at<double2>(ws, L.off_axis[i]);
     b.part = ws_at<float>(ws, L.off_part[i]);
-    b.gpart = ws_at<double2>(ws, L.off_guard[i]);
+    b.gpart = ws_at<double>(ws, L.off_guard[i]);
+    b.gfinal = ws_at<double>(ws, L.off_gfinal[i]);
+    b.gcount = ws_at<unsigned int>(ws, L.off_gcount[i]);
     b.hist = ws_at<unsigned long long>(ws, L.off_hist[i]);
   }
   fcfs::BatchLaunch &bl = p->launch;
@@ -905,14 +923,12 @@ fcfs_status build_plan(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec, 
   bl.grid = fcfs::batch_grid(p->tile, prec);
   bl.counter = ws_at<unsigned int>(ws, 0);
   bl.n_epi = L.epi_off[n];
-  bl.n_epa = L.epa_off[n];
   if (!st) st = upload(h, p, L.bc, &bl.clips);
   if (!st) st = upload(h, p, L.ax_desc, &bl.ax_desc);
-  if (!st) st = upload(h, p, L.g_desc, &bl.g_desc);
-  bl.n_g = (int)L.g_desc.size();
+  if (!st) st = upload(h, p, L.side_desc, &bl.side_desc);
+  bl.n_side = (int)L.side_desc.size();
   if (!st) st = upload(h, p, L.items, &bl.items);
   if (!st) st = upload(h, p, L.epi_off, &bl.epi_off);
-  if (!st) st = upload(h, p, L.epa_off, &bl.epa_off);
   hipError_t e = hipSuccess;
   if (!st && ((e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking)) ||
               (e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking)) ||
@@ -926,11 +942,10 @@ fcfs_status build_plan(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec, 
     } else {
       hipError_t le = fcfs::launch_batch_prepass(bl, p->cap);
       if (!le) le = hipEventRecord(p->ev_fork, p->cap);
-      if (!le) le = hipStreamWaitEvent(p->side, p->ev_fork, 0);
-      if (!le) le = fcfs::launch_batch_axis(bl, h->tab.w64, p->side);
-      if (!le) le = fcfs::launch_batch_guard(bl, h->tab.w64, p->side);
-      if (!le) le = hipEventRecord(p->ev_join, p->side);
       if (!le) le = fcfs::launch_batch_contract(bl, h->tab, p->cap);
+      if (!le) le = hipStreamWaitEvent(p->side, p->ev_fork, 0);
+      if (!le) le = fcfs::launch_batch_side(bl, h->tab.w64, p->side);
+      if (!le) le = hipEventRecord(p->ev_join, p->side);
       if (!le) le = hipStreamWaitEvent(p->cap, p->ev_join, 0);
       if (!le) le = fcfs::launch_batch_epilogue(bl, p->cap);
       e = hipStreamEndCapture(p->cap, &p->graph);

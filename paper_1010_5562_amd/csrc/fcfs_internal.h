@@ -25,6 +25,11 @@ constexpr uint32_t kPadOff = (uint32_t)kTabN * 8u;
 
 enum Prec { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
 
+// Histogram bins per block of the axis DFTs (partials per frequency: T / kAxisBins).
+constexpr int kAxisBins = 128;
+// The FP64 low-frequency guard block: 16 x 16 sums ([cos; sin] for k, l = 1..8).
+constexpr int kGuardD = 256;
+
 // Device-resident constant tables owned by a handle.
 struct Tables {
   double2 *w64 = nullptr;    // [kTabN]       (cos, sin)(2 pi p / N), FP64
@@ -48,30 +53,30 @@ struct FwdPlan {
   int64_t chunk;     // corners per split (multiple of 16)
   int64_t vpad;      // nsplit * chunk
   int pre_blocks;    // pre-pass blocks (area partials)
+  int hist_blocks;   // histogram blocks of the side kernel
   int ax_fb_k;       // 256-frequency blocks of the x-axis DFT
   int ax_fb_l;       // and of the y-axis DFT
   int ax_chunks;     // bin chunks of the axis DFTs (partials per frequency)
-  int g_chunks;      // vertex chunks of the FP64 low-frequency guard block
+  int g_chunks;      // corner chunks (blocks) of the FP64 low-frequency guard block
   int64_t g_chunk;
   // workspace offsets (bytes)
-  size_t off_packed, off_area, off_hist, off_axis, off_part, off_guard, bytes;
+  size_t off_packed, off_area, off_hist, off_axis, off_part, off_guard, off_gfinal, off_gcount,
+      bytes;
 };
 
 // Kernel launchers (fcfs_kernels.hip).  All enqueue on `st` and return the
-// launch status.
+// launch status; `ws` is the workspace laid out by the plan.  The pre-pass
+// also clears the histograms and the guard counter when they are non-NULL.
 hipError_t launch_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
-                          uint4 *packed, unsigned long long *area_part, hipStream_t st);
-hipError_t launch_axis(const FwdPlan &p, const int32_t *x, const int32_t *y, const uint4 *packed,
-                       const double2 *w64, unsigned long long *hist, double2 *axis_part,
-                       hipStream_t st);
+                          uint4 *packed, unsigned long long *area_part,
+                          unsigned long long *hist, unsigned int *gcount, hipStream_t st);
+// histograms + guard block, then the axis DFTs (side stream)
+hipError_t launch_side(const FwdPlan &p, const int32_t *x, const int32_t *y, const double2 *w64,
+                       void *ws, hipStream_t st);
 hipError_t launch_contract(const FwdPlan &p, const uint4 *packed, const Tables &t, float *part,
                            hipStream_t st);
-hipError_t launch_epilogue(const FwdPlan &p, const float *part, const double2 *axis_part,
-                           const unsigned long long *area_part, float *F, int64_t *area,
+hipError_t launch_epilogue(const FwdPlan &p, const void *ws, float *F, int64_t *area,
                            hipStream_t st);
-hipError_t launch_guard(const FwdPlan &p, const uint4 *packed, const double2 *w64, double2 *gpart,
-                        hipStream_t st);
-hipError_t launch_guard_epilogue(const FwdPlan &p, const double2 *gpart, float *F, hipStream_t st);
 hipError_t launch_debug_phases(const FwdPlan &p, const uint4 *packed, int axis, int k0, int nk,
                                int32_t *out, hipStream_t st);
 
@@ -112,11 +117,12 @@ struct BatchClip {
   unsigned long long *area_part;
   double2 *axis_part;
   float *part;
-  double2 *gpart;
+  double *gpart, *gfinal;
+  unsigned int *gcount;
   unsigned long long *hist;
   int64_t V, vpad, chunk, g_chunk;
   int T, shift, K, L, kp, lp, tiles_l, nsplit;
-  int ax_fb_k, ax_chunks, g_chunks;
+  int ax_fb_k, ax_chunks, g_chunks, hist_blocks;
 };
 
 struct BatchLaunch {
@@ -124,25 +130,25 @@ struct BatchLaunch {
   int prec, tile;           // tile variant of the persistent contraction
   const BatchClip *clips;   // device
   int pre_blocks;           // pre-pass blocks per clip
+  const int4 *side_desc;    // device: (clip, 0 = histogram | 1 = guard, block) per side block
+  int n_side;
   const int4 *ax_desc;      // device: (clip, frequency block, bin chunk) per axis block
   int n_ax;
-  const int4 *g_desc;       // device: (clip, chunk) per guard block
-  int n_g;
   const int4 *items;        // device: (clip, tile, split) per work item, LPT order
   int n_items;
   int grid;                 // persistent workgroups
   unsigned int *counter;    // device work counter
   const int *epi_off;       // device: prefix of epilogue blocks per clip [n+1]
-  const int *epa_off;       // device: prefix of axis-epilogue blocks per clip [n+1]
-  int n_epi, n_epa;
+  int n_epi;
 };
 
 hipError_t launch_batch_prepass(const BatchLaunch &b, hipStream_t st);
-hipError_t launch_batch_axis(const BatchLaunch &b, const double2 *w64, hipStream_t st);
-hipError_t launch_batch_guard(const BatchLaunch &b, const double2 *w64, hipStream_t st);
+hipError_t launch_batch_side(const BatchLaunch &b, const double2 *w64, hipStream_t st);
 hipError_t launch_batch_contract(const BatchLaunch &b, const Tables &t, hipStream_t st);
 hipError_t launch_batch_epilogue(const BatchLaunch &b, hipStream_t st);
 int batch_grid(int tile, int prec);
+// blocks of the epilogue launch of one clip
+int epilogue_block_count(int K, int L);
 
 // Contraction tile variants (wave tile in k x l frequencies; 2 x 2 waves).
 struct TileVariant {

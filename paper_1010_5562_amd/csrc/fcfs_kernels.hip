@@ -14,14 +14,21 @@ namespace fcfs {
 // ---------------------------------------------------------------------------
 // Pre-pass: pack corners, exact area.  Corners with index >= V (up to the
 // padded count) become padding records.  The area sum is done modulo 2^64,
-// which is exact whenever the true area fits in int64.
+// which is exact whenever the true area fits in int64.  The same launch
+// clears the axis histograms (the 2T bins in use) and the guard block's
+// completion counter for the side-stream kernels that follow.
 // ---------------------------------------------------------------------------
+constexpr int kHistN = kTabN;  // bins per axis histogram (T <= 8192)
+
 __device__ __forceinline__ void prepass_body(const int32_t *__restrict__ x,
                                              const int32_t *__restrict__ y,
                                              const int8_t *__restrict__ s, int64_t V, int64_t vpad,
-                                             uint32_t tmask, int shift, uint4 *__restrict__ packed,
-                                             unsigned long long *__restrict__ area_part, int blk,
+                                             int T, int shift, uint4 *__restrict__ packed,
+                                             unsigned long long *__restrict__ area_part,
+                                             unsigned long long *__restrict__ hist,
+                                             unsigned int *__restrict__ gcount, int blk,
                                              int nblk) {
+  const uint32_t tmask = (uint32_t)(T - 1);
   unsigned long long acc = 0;
   for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < vpad; i += (int64_t)nblk * 256) {
     uint4 w;
@@ -38,6 +45,10 @@ __device__ __forceinline__ void prepass_body(const int32_t *__restrict__ x,
     }
     packed[i] = w;
   }
+  if (hist)
+    for (int i = blk * 256 + threadIdx.x; i < 2 * T; i += nblk * 256)
+      hist[i < T ? i : kHistN + (i - T)] = 0ull;
+  if (gcount && blk == 0 && threadIdx.x == 0) *gcount = 0u;
   // fixed-order block reduction (integer, exact)
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
   __shared__ unsigned long long red[4];
@@ -49,16 +60,20 @@ __device__ __forceinline__ void prepass_body(const int32_t *__restrict__ x,
 __global__ __launch_bounds__(256) void k_prepass(const int32_t *__restrict__ x,
                                                  const int32_t *__restrict__ y,
                                                  const int8_t *__restrict__ s, int64_t V,
-                                                 int64_t vpad, uint32_t tmask, int shift,
+                                                 int64_t vpad, int T, int shift,
                                                  uint4 *__restrict__ packed,
-                                                 unsigned long long *__restrict__ area_part) {
-  prepass_body(x, y, s, V, vpad, tmask, shift, packed, area_part, blockIdx.x, gridDim.x);
+                                                 unsigned long long *__restrict__ area_part,
+                                                 unsigned long long *__restrict__ hist,
+                                                 unsigned int *__restrict__ gcount) {
+  prepass_body(x, y, s, V, vpad, T, shift, packed, area_part, hist, gcount, blockIdx.x,
+               gridDim.x);
 }
 
 hipError_t launch_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
-                          uint4 *packed, unsigned long long *area_part, hipStream_t st) {
-  hipLaunchKernelGGL(k_prepass, dim3(p.pre_blocks), dim3(256), 0, st, x, y, s, p.V, p.vpad,
-                     (uint32_t)(p.T - 1), p.shift, packed, area_part);
+                          uint4 *packed, unsigned long long *area_part,
+                          unsigned long long *hist, unsigned int *gcount, hipStream_t st) {
+  hipLaunchKernelGGL(k_prepass, dim3(p.pre_blocks), dim3(256), 0, st, x, y, s, p.V, p.vpad, p.T,
+                     p.shift, packed, area_part, hist, gcount);
   return hipGetLastError();
 }
 
@@ -72,10 +87,8 @@ hipError_t launch_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y, 
 //   Sx[f] = sum_{q < T} Hx[q] e(f q)
 // in FP64.  Cost O(V + (K + L) T) instead of O(V (K + L)).
 // ---------------------------------------------------------------------------
-constexpr int kHistN = kTabN;   // bins per axis (T <= 8192)
-constexpr int kAxQChunk = 512;  // bins per DFT block
 
-// Bins of one clip; hist = [Hx | Hy], kHistN int64 each, zeroed beforehand.
+// Bins of one clip; hist = [Hx | Hy], kHistN int64 each, cleared beforehand.
 __device__ __forceinline__ void hist_body(const int32_t *__restrict__ x,
                                           const int32_t *__restrict__ y,
                                           const uint4 *__restrict__ packed, int64_t V, int shift,
@@ -90,25 +103,20 @@ __device__ __forceinline__ void hist_body(const int32_t *__restrict__ x,
   }
 }
 
-__device__ __forceinline__ void zero_hist_body(unsigned long long *__restrict__ hist, int blk,
-                                               int nblk) {
-  for (int i = blk * 256 + threadIdx.x; i < 2 * kHistN; i += nblk * 256) hist[i] = 0ull;
-}
-
 // Block (fb, chunk): 256 frequencies f = 1 + 256 fb' + t of one axis against
-// the bins q in [chunk * kAxQChunk, ...) < T.  e(f q) from the exact table at
+// the bins q in [chunk * kAxisBins, ...) < T.  e(f q) from the exact table at
 // the first bin of every 32 and FP64 complex products in between.
 __device__ __forceinline__ void dft_body(const unsigned long long *__restrict__ hist,
                                          const double2 *__restrict__ w64, int T, int shift, int K,
                                          int L, int fb_k, double2 *__restrict__ axis_part, int fb,
                                          int chunk) {
-  __shared__ double s_h[kAxQChunk];
+  __shared__ double s_h[kAxisBins];
   const bool xaxis = fb < fb_k;
   const int f = 1 + (xaxis ? fb : fb - fb_k) * 256 + threadIdx.x;
   const int nf = xaxis ? K : L;
   const unsigned long long *H = hist + (xaxis ? 0 : kHistN);
-  const int q0 = chunk * kAxQChunk;
-  const int n = min(kAxQChunk, T - q0);
+  const int q0 = chunk * kAxisBins;
+  const int n = min(kAxisBins, T - q0);
   for (int i = threadIdx.x; i < n; i += 256) s_h[i] = (double)(long long)H[q0 + i];
   __syncthreads();
   double re = 0.0, im = 0.0;
@@ -129,17 +137,6 @@ __device__ __forceinline__ void dft_body(const unsigned long long *__restrict__ 
   }
 }
 
-__global__ __launch_bounds__(256) void k_zero_hist(unsigned long long *__restrict__ hist) {
-  zero_hist_body(hist, blockIdx.x, gridDim.x);
-}
-
-__global__ __launch_bounds__(256) void k_hist(const int32_t *__restrict__ x,
-                                              const int32_t *__restrict__ y,
-                                              const uint4 *__restrict__ packed, int64_t V,
-                                              int shift, unsigned long long *__restrict__ hist) {
-  hist_body(x, y, packed, V, shift, hist, blockIdx.x, gridDim.x);
-}
-
 __global__ __launch_bounds__(256) void k_axis_dft(const unsigned long long *__restrict__ hist,
                                                   const double2 *__restrict__ w64, int T, int shift,
                                                   int K, int L, int fb_k,
@@ -147,144 +144,109 @@ __global__ __launch_bounds__(256) void k_axis_dft(const unsigned long long *__re
   dft_body(hist, w64, T, shift, K, L, fb_k, axis_part, blockIdx.x, blockIdx.y);
 }
 
-hipError_t launch_axis(const FwdPlan &p, const int32_t *x, const int32_t *y, const uint4 *packed,
-                       const double2 *w64, unsigned long long *hist, double2 *axis_part,
-                       hipStream_t st) {
-  if (p.K + p.L == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero_hist, dim3(16), dim3(256), 0, st, hist);
-  if (p.V > 0)
-    hipLaunchKernelGGL(k_hist, dim3((unsigned)std::min<int64_t>(1024, (p.V + 255) / 256)),
-                       dim3(256), 0, st, x, y, packed, p.V, p.shift, hist);
-  hipLaunchKernelGGL(k_axis_dft, dim3(p.ax_fb_k + p.ax_fb_l, p.ax_chunks), dim3(256), 0, st, hist,
-                     w64, p.T, p.shift, p.K, p.L, p.ax_fb_k, axis_part);
-  return hipGetLastError();
-}
-
 // ---------------------------------------------------------------------------
 // Low-frequency guard block: S(k, l) = sum_v s_v e(k x_v) e(l y_v) for
-// 1 <= k <= gk, 1 <= |l| <= gl (gk, gl <= 8) in FP64, replacing the MFMA
-// values there.  The 1/(k l) factor of alpha_{k,l} amplifies any error of the
-// contraction most at these frequencies.  Thread t of the first 128 owns the
-// pair (k, l) = (1 + t/16, l(t%16)), l(j) = j+1 for j < 8, -(j-7) otherwise;
-// threads 128..255 take the odd corners of the same pairs.  Per staged corner
-// the block tabulates e(k x), e(l y), k, l = 1..8: the exact FP64 table value
-// at k = 1, the higher powers by FP64 complex products (error ~1e-15).
+// 1 <= k <= 8, 1 <= |l| <= 8 in FP64, replacing the MFMA values there.  The
+// 1/(k l) factor of alpha_{k,l} amplifies any error of the contraction most
+// at these frequencies.
+// It is the same real-trigonometric GEMM as the contraction, restricted to a
+// 16 x 16 block and run on the FP64 matrix cores: rows a_i = cos((i+1) th_x)
+// for i < 8 and sin((i-7) th_x) for i >= 8, columns b_j likewise in th_y with
+// the sign s_v, every value an exact entry of the FP64 table (integer phase).
+// v_mfma_f64_16x16x4_f64 takes 4 corners per instruction: lane i + 16 q holds
+// A[i][q] = a_i(v_q) and B[q][i] = s b_i(v_q); D[i][j] is element i / 4 of
+// lane j + 16 (i % 4).
+// Each 256-thread block reduces its corner range to a 16 x 16 partial in a
+// fixed order; the last block to finish (completion counter) adds the block
+// partials in block order, so the result does not depend on scheduling.
 // ---------------------------------------------------------------------------
-constexpr int kGuard = 8;
-constexpr int kGuardPairs = kGuard * 2 * kGuard;  // 128
-constexpr int kGuardStage = 64;                   // corners staged at a time
+constexpr int kGuard = 8;     // |k|, |l| <= kGuard
+constexpr int kGuardUnroll = 8;
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void guard_body(const uint4 *__restrict__ packed,
-                                           const double2 *__restrict__ w64, int64_t V,
-                                           int64_t g_chunk, double2 *__restrict__ gpart,
-                                           int chunk_idx) {
-  __shared__ double2 s_ex[kGuardStage][kGuard];  // e^{+j k theta_x}
-  __shared__ double2 s_ey[kGuardStage][kGuard];  // e^{+j l theta_y}
-  __shared__ double s_sg[kGuardStage];
-  __shared__ double2 red[kGuardPairs];
-  const int t = threadIdx.x & (kGuardPairs - 1), half = threadIdx.x >> 7;
-  const int k = 1 + t / (2 * kGuard);
-  const int j = t % (2 * kGuard);
-  const int la = j < kGuard ? j + 1 : j - kGuard + 1;  // |l|
-  const bool lneg = j >= kGuard;
-  const int64_t v0 = (int64_t)chunk_idx * g_chunk;
+                                           const double *__restrict__ w64, int64_t V,
+                                           int64_t g_chunk, int nblk, int blk,
+                                           double *__restrict__ gpart, double *__restrict__ gfinal,
+                                           unsigned int *__restrict__ gcount) {
+  __shared__ double red[4][kGuardD];
+  __shared__ int s_last;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, q = lane >> 4;
+  const uint32_t f = (uint32_t)(i & 7) + 1u;
+  const int sc = i >> 3;  // 0: cos, 1: sin
+  const int64_t v0 = (int64_t)blk * g_chunk;
   const int64_t v1 = min(V, v0 + g_chunk);
-  double re = 0.0, im = 0.0;
-  for (int64_t vb = v0; vb < v1; vb += kGuardStage) {
-    const int n = (int)min((int64_t)kGuardStage, v1 - vb);
-    __syncthreads();
-    // threads 0..127 tabulate the x powers of corner i, 128..255 the y powers:
-    // one exact table value e^{j theta}, then seven FP64 complex products
-    {
-      const int i = threadIdx.x & 127;
-      if (i < n) {
-        const uint4 c = packed[vb + i];
-        const double2 w1 = w64[(half ? c.y : c.x) >> 3];
-        double2 w = w1;
-        double2(*dst)[kGuard] = half ? s_ey : s_ex;
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t base = v0 + 4 * wave; base < v1; base += 16 * kGuardUnroll) {
+    double a[kGuardUnroll], b[kGuardUnroll];
 #pragma unroll
-        for (int f = 0; f < kGuard; ++f) {
-          dst[i][f] = w;
-          const double nx = w.x * w1.x - w.y * w1.y, ny = w.x * w1.y + w.y * w1.x;
-          w = make_double2(nx, ny);
-        }
-        if (!half) s_sg[i] = c.z ? -1.0 : 1.0;
+    for (int u = 0; u < kGuardUnroll; ++u) {
+      const int64_t v = base + 16 * u + q;
+      a[u] = 0.0;
+      b[u] = 0.0;
+      if (v < v1) {
+        const uint4 c = packed[v];
+        const uint32_t px = __umul24(f, c.x >> 3) & (uint32_t)(kTabN - 1);
+        const uint32_t py = __umul24(f, c.y >> 3) & (uint32_t)(kTabN - 1);
+        a[u] = w64[2 * px + sc];
+        const double t = w64[2 * py + sc];
+        b[u] = c.z ? -t : t;
       }
     }
-    __syncthreads();
-    for (int vi = half; vi < n; vi += 2) {
-      const double2 a = s_ex[vi][k - 1];
-      double2 b = s_ey[vi][la - 1];
-      if (lneg) b.y = -b.y;
-      // e(kx) e(ly) = conj(a b) with a, b the e^{+j...} table values
-      const double pr = a.x * b.x - a.y * b.y, pi = a.x * b.y + a.y * b.x;
-      re = fma(s_sg[vi], pr, re);
-      im = fma(-s_sg[vi], pi, im);
-    }
+#pragma unroll
+    for (int u = 0; u < kGuardUnroll; ++u)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
   }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) red[wave][(q + 4 * r) * 16 + i] = acc[r];
   __syncthreads();
-  if (half == 1) red[t] = make_double2(re, im);
+  const int t = threadIdx.x;
+  gpart[(size_t)blk * kGuardD + t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+  __threadfence();
   __syncthreads();
-  if (half == 0) gpart[(size_t)chunk_idx * kGuardPairs + t] = make_double2(re + red[t].x, im + red[t].y);
-}
-
-__global__ __launch_bounds__(256) void k_guard(const uint4 *__restrict__ packed,
-                                               const double2 *__restrict__ w64, int64_t V,
-                                               int64_t g_chunk, double2 *__restrict__ gpart) {
-  guard_body(packed, w64, V, g_chunk, gpart, blockIdx.x);
-}
-
-// F[k, l] = alpha_{k,l} S(k, l) on the guard block, F[-k, -l] its conjugate;
-// chunk partials summed in order.
-__device__ __forceinline__ void guard_epilogue_body(const double2 *__restrict__ gpart,
-                                                    int g_chunks, int K, int L, double T,
-                                                    float2 *__restrict__ F) {
-  // 1024 threads: pair t = tid % 128 sums the chunks c = q, q+8, ... with
-  // q = tid / 128; the eight sums are added in order
-  __shared__ double2 red[8][kGuardPairs];
-  const int t = threadIdx.x & (kGuardPairs - 1), q = threadIdx.x >> 7;
-  double re = 0.0, im = 0.0;
-  for (int c = q; c < g_chunks; c += 8) {
-    const double2 v = gpart[(size_t)c * kGuardPairs + t];
-    re += v.x;
-    im += v.y;
-  }
-  red[q][t] = make_double2(re, im);
+  if (t == 0) s_last = atomicAdd(gcount, 1u) == (unsigned int)(nblk - 1);
   __syncthreads();
-  if (q != 0) return;
-  for (int w = 1; w < 8; ++w) {
-    re += red[w][t].x;
-    im += red[w][t].y;
-  }
-  const int k = 1 + t / (2 * kGuard);
-  const int j = t % (2 * kGuard);
-  const int l = j < kGuard ? j + 1 : -(j - kGuard + 1);
-  if (k > K || abs(l) > L) return;
-  const double a = -T / (4.0 * kPi * kPi * (double)k * (double)l);
-  const size_t W = 2 * (size_t)L + 1;
-  F[(size_t)(K + k) * W + (L + l)] = make_float2((float)(a * re), (float)(a * im));
-  F[(size_t)(K - k) * W + (L - l)] = make_float2((float)(a * re), (float)(-a * im));
+  if (!s_last) return;
+  __threadfence();
+  double sum = 0.0;
+  for (int bb = 0; bb < nblk; ++bb) sum += gpart[(size_t)bb * kGuardD + t];
+  gfinal[t] = sum;
 }
 
-__global__ __launch_bounds__(1024) void k_guard_epilogue(const double2 *__restrict__ gpart,
-                                                         int g_chunks, int K, int L, double T,
-                                                         float2 *__restrict__ F) {
-  guard_epilogue_body(gpart, g_chunks, K, L, T, F);
+// Side-stream kernel of one clip: blocks [0, nh) bin the axis histograms,
+// blocks [nh, nh + g_chunks) compute the guard block.
+__global__ __launch_bounds__(256) void k_side(const int32_t *__restrict__ x,
+                                              const int32_t *__restrict__ y,
+                                              const uint4 *__restrict__ packed, int64_t V,
+                                              int shift, unsigned long long *__restrict__ hist,
+                                              int nh, const double *__restrict__ w64,
+                                              int64_t g_chunk, int g_chunks,
+                                              double *__restrict__ gpart,
+                                              double *__restrict__ gfinal,
+                                              unsigned int *__restrict__ gcount) {
+  if ((int)blockIdx.x < nh)
+    hist_body(x, y, packed, V, shift, hist, blockIdx.x, nh);
+  else
+    guard_body(packed, w64, V, g_chunk, g_chunks, blockIdx.x - nh, gpart, gfinal, gcount);
 }
 
-hipError_t launch_guard(const FwdPlan &p, const uint4 *packed, const double2 *w64, double2 *gpart,
-                        hipStream_t st) {
-  if (p.K == 0 || p.L == 0 || p.V == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_guard, dim3(p.g_chunks), dim3(256), 0, st, packed, w64, p.V, p.g_chunk,
-                     gpart);
-  return hipGetLastError();
-}
-
-hipError_t launch_guard_epilogue(const FwdPlan &p, const double2 *gpart, float *F, hipStream_t st) {
-  if (p.K == 0 || p.L == 0) return hipSuccess;
-  if (p.V == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_guard_epilogue, dim3(1), dim3(8 * kGuardPairs), 0, st, gpart, p.g_chunks,
-                     p.K, p.L, (double)p.T, (float2 *)F);
+hipError_t launch_side(const FwdPlan &p, const int32_t *x, const int32_t *y, const double2 *w64,
+                       void *ws, hipStream_t st) {
+  char *w = (char *)ws;
+  const uint4 *packed = (const uint4 *)(w + p.off_packed);
+  auto *hist = (unsigned long long *)(w + p.off_hist);
+  const int nh = p.K + p.L > 0 ? p.hist_blocks : 0;
+  const int ng = p.K > 0 && p.L > 0 ? p.g_chunks : 0;
+  if (nh + ng > 0)
+    hipLaunchKernelGGL(k_side, dim3(nh + ng), dim3(256), 0, st, x, y, packed, p.V, p.shift, hist,
+                       nh, (const double *)w64, p.g_chunk, p.g_chunks,
+                       (double *)(w + p.off_guard), (double *)(w + p.off_gfinal),
+                       (unsigned int *)(w + p.off_gcount));
+  if (p.K + p.L > 0)
+    hipLaunchKernelGGL(k_axis_dft, dim3(p.ax_fb_k + p.ax_fb_l, p.ax_chunks), dim3(256), 0, st,
+                       hist, w64, p.T, p.shift, p.K, p.L, p.ax_fb_k,
+                       (double2 *)(w + p.off_axis));
   return hipGetLastError();
 }
 
@@ -641,8 +603,22 @@ hipError_t launch_contract(const FwdPlan &p, const uint4 *packed, const Tables &
 //   S(k, -l) = (P + Q) - j (R - U)
 // F[k, l] = alpha_{k,l} S(k, l) with alpha_{k,l} = -T / (4 pi^2 k l) (Prop. 3),
 // alpha_{k,-l} = -alpha_{k,l}; F[-k,-l] = conj F[k,l] (real signal).
-// Split partials are summed in FP64 in a fixed order.
+// Split partials are summed in FP64 in a fixed order.  One launch covers the
+// contraction grid (blocks [0, nmain), the guard block's entries excepted),
+// the axes and DC (the next nax blocks) and the guard block (the last one).
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void store_quad(float2 *__restrict__ F, int K, int L, int k, int l,
+                                           double T, double P, double U, double R, double Q) {
+  const double a = -T / (4.0 * kPi * kPi * (double)k * (double)l);
+  const double pre = a * (P - Q), pim = -a * (R + U);  // F[k, l]
+  const double mre = -a * (P + Q), mim = a * (R - U);  // F[k, -l]
+  const size_t W = 2 * (size_t)L + 1;
+  F[(size_t)(K + k) * W + (L + l)] = make_float2((float)pre, (float)pim);
+  F[(size_t)(K - k) * W + (L - l)] = make_float2((float)pre, (float)-pim);
+  F[(size_t)(K + k) * W + (L - l)] = make_float2((float)mre, (float)mim);
+  F[(size_t)(K - k) * W + (L + l)] = make_float2((float)mre, (float)-mim);
+}
+
 __device__ __forceinline__ void epilogue_body(const float *__restrict__ part, int nsplit, int kp,
                                               int lp, int K, int L, double T,
                                               float2 *__restrict__ F, int bx, int by) {
@@ -665,27 +641,27 @@ __device__ __forceinline__ void epilogue_body(const float *__restrict__ part, in
   }
   red[q][t] = make_double4(P, U, R, Q);
   __syncthreads();
-  if (q != 0 || l > L) return;
+  if (q != 0 || l > L || (k <= kGuard && l <= kGuard)) return;
   for (int w = 1; w < 4; ++w) {
     P += red[w][t].x;
     U += red[w][t].y;
     R += red[w][t].z;
     Q += red[w][t].w;
   }
-  const double a = -T / (4.0 * kPi * kPi * (double)k * (double)l);
-  const double pre = a * (P - Q), pim = -a * (R + U);  // F[k, l]
-  const double mre = -a * (P + Q), mim = a * (R - U);  // F[k, -l]
-  const size_t W = 2 * (size_t)L + 1;
-  F[(size_t)(K + k) * W + (L + l)] = make_float2((float)pre, (float)pim);
-  F[(size_t)(K - k) * W + (L - l)] = make_float2((float)pre, (float)-pim);
-  F[(size_t)(K + k) * W + (L - l)] = make_float2((float)mre, (float)mim);
-  F[(size_t)(K - k) * W + (L + l)] = make_float2((float)mre, (float)-mim);
+  store_quad(F, K, L, k, l, T, P, U, R, Q);
 }
 
-__global__ __launch_bounds__(256) void k_epilogue(const float *__restrict__ part, int nsplit, int kp,
-                                                  int lp, int K, int L, double T,
-                                                  float2 *__restrict__ F) {
-  epilogue_body(part, nsplit, kp, lp, K, L, T, F, blockIdx.x, blockIdx.y);
+// Guard block entries from the final 16 x 16 sums D (row-major):
+// P = D[k-1][l-1], U = D[k-1][8+l-1], R = D[8+k-1][l-1], Q = D[8+k-1][8+l-1].
+__device__ __forceinline__ void guard_store(const double *__restrict__ gfinal, int K, int L,
+                                            double T, float2 *__restrict__ F) {
+  const int t = threadIdx.x;
+  if (t >= kGuard * kGuard) return;
+  const int k = 1 + t / kGuard, l = 1 + t % kGuard;
+  if (k > K || l > L) return;
+  const double *d = gfinal;
+  store_quad(F, K, L, k, l, T, d[(k - 1) * 16 + (l - 1)], d[(k - 1) * 16 + 8 + (l - 1)],
+             d[(8 + k - 1) * 16 + (l - 1)], d[(8 + k - 1) * 16 + 8 + (l - 1)]);
 }
 
 // Axis entries (Steps 2, 3) and DC (Step 1):
@@ -741,24 +717,54 @@ __device__ __forceinline__ void epilogue_axes_body(const double2 *__restrict__ a
   }
 }
 
-__global__ __launch_bounds__(256) void k_epilogue_axes(const double2 *__restrict__ axis_part,
-                                                       int ax_chunks, int K, int L, double T,
-                                                       const unsigned long long *__restrict__ area_part,
-                                                       int pre_blocks, float2 *__restrict__ F,
-                                                       int64_t *__restrict__ area) {
-  epilogue_axes_body(axis_part, ax_chunks, K, L, T, area_part, pre_blocks, F, area, blockIdx.x);
+// Block b of the epilogue launch of one clip (block-uniform branch).
+__device__ __forceinline__ void epilogue_block(const float *__restrict__ part, int nsplit, int kp,
+                                               int lp, int K, int L, double T,
+                                               const double2 *__restrict__ axis_part,
+                                               int ax_chunks,
+                                               const unsigned long long *__restrict__ area_part,
+                                               int pre_blocks, const double *__restrict__ gfinal,
+                                               float2 *__restrict__ F, int64_t *__restrict__ area,
+                                               int b) {
+  const bool grid2d = K > 0 && L > 0;
+  const int nbx = (L + 63) / 64;
+  const int nmain = grid2d ? nbx * K : 0;
+  const int nax = max(1, (K + L + 15) / 16);
+  if (b < nmain)
+    epilogue_body(part, nsplit, kp, lp, K, L, T, F, b % nbx, b / nbx);
+  else if (b < nmain + nax)
+    epilogue_axes_body(axis_part, ax_chunks, K, L, T, area_part, pre_blocks, F, area, b - nmain);
+  else if (grid2d)
+    guard_store(gfinal, K, L, T, F);
 }
 
-hipError_t launch_epilogue(const FwdPlan &p, const float *part, const double2 *axis_part,
-                           const unsigned long long *area_part, float *F, int64_t *area,
+int epilogue_block_count(int K, int L) {
+  const int nmain = K > 0 && L > 0 ? ((L + 63) / 64) * K : 0;
+  const int nax = std::max(1, (K + L + 15) / 16);
+  return nmain + nax + (K > 0 && L > 0 ? 1 : 0);
+}
+
+__global__ __launch_bounds__(256) void k_epilogue(const float *__restrict__ part, int nsplit,
+                                                  int kp, int lp, int K, int L, double T,
+                                                  const double2 *__restrict__ axis_part,
+                                                  int ax_chunks,
+                                                  const unsigned long long *__restrict__ area_part,
+                                                  int pre_blocks,
+                                                  const double *__restrict__ gfinal,
+                                                  float2 *__restrict__ F,
+                                                  int64_t *__restrict__ area) {
+  epilogue_block(part, nsplit, kp, lp, K, L, T, axis_part, ax_chunks, area_part, pre_blocks,
+                 gfinal, F, area, blockIdx.x);
+}
+
+hipError_t launch_epilogue(const FwdPlan &p, const void *ws, float *F, int64_t *area,
                            hipStream_t st) {
-  float2 *F2 = (float2 *)F;
-  const int nax = (p.K + p.L + 15) / 16;
-  hipLaunchKernelGGL(k_epilogue_axes, dim3(nax > 0 ? nax : 1), dim3(256), 0, st, axis_part,
-                     p.ax_chunks, p.K, p.L, (double)p.T, area_part, p.pre_blocks, F2, area);
-  if (p.K > 0 && p.L > 0)
-    hipLaunchKernelGGL(k_epilogue, dim3((p.L + 63) / 64, p.K), dim3(256), 0, st, part,
-                       p.nsplit, p.kp, p.lp, p.K, p.L, (double)p.T, F2);
+  const char *w = (const char *)ws;
+  hipLaunchKernelGGL(k_epilogue, dim3(epilogue_block_count(p.K, p.L)), dim3(256), 0, st,
+                     (const float *)(w + p.off_part), p.nsplit, p.kp, p.lp, p.K, p.L, (double)p.T,
+                     (const double2 *)(w + p.off_axis), p.ax_chunks,
+                     (const unsigned long long *)(w + p.off_area), p.pre_blocks,
+                     (const double *)(w + p.off_gfinal), (float2 *)F, area);
   return hipGetLastError();
 }
 
@@ -800,14 +806,21 @@ __global__ void k_batch_reset(unsigned int *counter) {
 
 __global__ __launch_bounds__(256) void k_batch_prepass(const BatchClip *__restrict__ clips) {
   const BatchClip &c = clips[blockIdx.y];
-  prepass_body(c.x, c.y, c.s, c.V, c.vpad, (uint32_t)(c.T - 1), c.shift, c.packed, c.area_part,
+  prepass_body(c.x, c.y, c.s, c.V, c.vpad, c.T, c.shift, c.packed, c.area_part, c.hist, c.gcount,
                blockIdx.x, gridDim.x);
-  zero_hist_body(c.hist, blockIdx.x, gridDim.x);
 }
 
-__global__ __launch_bounds__(256) void k_batch_hist(const BatchClip *__restrict__ clips) {
-  const BatchClip &c = clips[blockIdx.y];
-  hist_body(c.x, c.y, c.packed, c.V, c.shift, c.hist, blockIdx.x, gridDim.x);
+// Side-stream blocks of a batch, one descriptor each: (clip, 0, b) bins
+// histogram block b of the clip, (clip, 1, b) computes its guard block b.
+__global__ __launch_bounds__(256) void k_batch_side(const BatchClip *__restrict__ clips,
+                                                    const int4 *__restrict__ desc,
+                                                    const double *__restrict__ w64) {
+  const int4 d = desc[blockIdx.x];
+  const BatchClip &c = clips[d.x];
+  if (d.y == 0)
+    hist_body(c.x, c.y, c.packed, c.V, c.shift, c.hist, d.z, c.hist_blocks);
+  else
+    guard_body(c.packed, w64, c.V, c.g_chunk, c.g_chunks, d.z, c.gpart, c.gfinal, c.gcount);
 }
 
 __global__ __launch_bounds__(256) void k_batch_axis(const BatchClip *__restrict__ clips,
@@ -816,26 +829,6 @@ __global__ __launch_bounds__(256) void k_batch_axis(const BatchClip *__restrict_
   const int4 d = desc[blockIdx.x];
   const BatchClip &c = clips[d.x];
   dft_body(c.hist, w64, c.T, c.shift, c.K, c.L, c.ax_fb_k, c.axis_part, d.y, d.z);
-}
-
-__global__ __launch_bounds__(256) void k_batch_guard(const BatchClip *__restrict__ clips,
-                                                     const int4 *__restrict__ desc,
-                                                     const double2 *__restrict__ w64) {
-  const int4 d = desc[blockIdx.x];
-  const BatchClip &c = clips[d.x];
-  guard_body(c.packed, w64, c.V, c.g_chunk, c.gpart, d.y);
-}
-
-__global__ __launch_bounds__(1024) void k_batch_guard_epilogue(const BatchClip *__restrict__ clips) {
-  const BatchClip &c = clips[blockIdx.x];
-  if (c.K == 0 || c.L == 0 || c.V == 0) return;
-  guard_epilogue_body(c.gpart, c.g_chunks, c.K, c.L, (double)c.T, c.F);
-}
-
-hipError_t launch_batch_guard(const BatchLaunch &b, const double2 *w64, hipStream_t st) {
-  if (b.n_g > 0)
-    hipLaunchKernelGGL(k_batch_guard, dim3(b.n_g), dim3(256), 0, st, b.clips, b.g_desc, w64);
-  return hipGetLastError();
 }
 
 // Next work item for the whole workgroup (-1 when the list is exhausted).
@@ -897,22 +890,12 @@ __device__ __forceinline__ int owner(const int *__restrict__ off, int n, int b) 
 }
 
 __global__ __launch_bounds__(256) void k_batch_epilogue(const BatchClip *__restrict__ clips,
-                                                        const int *__restrict__ off, int n) {
+                                                        const int *__restrict__ off, int n,
+                                                        int pre_blocks) {
   const int ci = owner(off, n, blockIdx.x);
   const BatchClip &c = clips[ci];
-  const int local = blockIdx.x - off[ci];
-  const int nbx = (c.L + 63) / 64;
-  epilogue_body(c.part, c.nsplit, c.kp, c.lp, c.K, c.L, (double)c.T, c.F, local % nbx,
-                local / nbx);
-}
-
-__global__ __launch_bounds__(256) void k_batch_epilogue_axes(const BatchClip *__restrict__ clips,
-                                                             const int *__restrict__ off, int n,
-                                                             int pre_blocks) {
-  const int ci = owner(off, n, blockIdx.x);
-  const BatchClip &c = clips[ci];
-  epilogue_axes_body(c.axis_part, c.ax_chunks, c.K, c.L, (double)c.T, c.area_part, pre_blocks,
-                     c.F, c.area, blockIdx.x - off[ci]);
+  epilogue_block(c.part, c.nsplit, c.kp, c.lp, c.K, c.L, (double)c.T, c.axis_part, c.ax_chunks,
+                 c.area_part, pre_blocks, c.gfinal, c.F, c.area, blockIdx.x - off[ci]);
 }
 
 hipError_t launch_batch_prepass(const BatchLaunch &b, hipStream_t st) {
@@ -921,9 +904,10 @@ hipError_t launch_batch_prepass(const BatchLaunch &b, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_batch_axis(const BatchLaunch &b, const double2 *w64, hipStream_t st) {
-  if (b.n_clips > 0)
-    hipLaunchKernelGGL(k_batch_hist, dim3(b.pre_blocks, b.n_clips), dim3(256), 0, st, b.clips);
+hipError_t launch_batch_side(const BatchLaunch &b, const double2 *w64, hipStream_t st) {
+  if (b.n_side > 0)
+    hipLaunchKernelGGL(k_batch_side, dim3(b.n_side), dim3(256), 0, st, b.clips, b.side_desc,
+                       (const double *)w64);
   if (b.n_ax > 0)
     hipLaunchKernelGGL(k_batch_axis, dim3(b.n_ax), dim3(256), 0, st, b.clips, b.ax_desc, w64);
   return hipGetLastError();
@@ -965,15 +949,9 @@ hipError_t launch_batch_contract(const BatchLaunch &b, const Tables &t, hipStrea
 }
 
 hipError_t launch_batch_epilogue(const BatchLaunch &b, hipStream_t st) {
-  if (b.n_epa > 0)
-    hipLaunchKernelGGL(k_batch_epilogue_axes, dim3(b.n_epa), dim3(256), 0, st, b.clips, b.epa_off,
-                       b.n_clips, b.pre_blocks);
   if (b.n_epi > 0)
     hipLaunchKernelGGL(k_batch_epilogue, dim3(b.n_epi), dim3(256), 0, st, b.clips, b.epi_off,
-                       b.n_clips);
-  if (b.n_clips > 0)
-    hipLaunchKernelGGL(k_batch_guard_epilogue, dim3(b.n_clips), dim3(8 * kGuardPairs), 0, st,
-                       b.clips);
+                       b.n_clips, b.pre_blocks);
   return hipGetLastError();
 }
 
