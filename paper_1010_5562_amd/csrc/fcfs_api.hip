@@ -194,7 +194,7 @@ void free_tables(Tables &t) {
 // Planner: launch geometry and workspace layout from (V, T, K, L, precision).
 // ---------------------------------------------------------------------------
 constexpr int kMaxFreq = 4095;  // |k|, |l| cut-off limit (phases stay below 2^29)
-constexpr int kTargetWG = 512;  // two contraction workgroups per CU on 256 CUs
+constexpr int kCUs = 256;  // compute units of the target GPU (MI355X)
 constexpr int kGuardBlocks = 64;  // most blocks of the guard block's corner split
 
 int kbucket(int K) {
@@ -205,13 +205,15 @@ int kbucket(int K) {
 int vbucket(int64_t V) { return V < 8192 ? 0 : (V < 65536 ? 1 : 2); }
 
 // Tuned entry for (precision, K, V) if the handle has one, else the built-in
-// choice: the 64 x 32 wave tile, lean two-waves-per-SIMD loop for the split
-// forms.
+// choice: for the split forms the interleaved 64 x 64 wave tile (one wave per
+// SIMD) from K = 127 on, where its 128-frequency workgroup tile wastes little,
+// and the lean 64 x 32 tile below; the double-buffered 64 x 32 tile for FP32.
 int default_tile(fcfs_handle *h, int prec, int K, int64_t V) {
   if (h)
     for (const auto &t : h->tune)
       if (t.prec == prec && t.kbucket == kbucket(K) && t.vbucket == vbucket(V)) return t.tile;
-  return prec == fcfs::kFP32 ? 1 : 4;
+  if (prec == fcfs::kFP32) return 1;
+  return K >= 127 ? 5 : 4;
 }
 
 fcfs_status check_dims(fcfs_handle *h, int64_t V, int T, int K, int L, int prec) {
@@ -249,12 +251,14 @@ fcfs_status make_plan(fcfs_handle *h, int64_t V, int T, int K, int L, int prec, 
   q.tiles_k = q.kp / q.wgk;
   q.tiles_l = q.lp / q.wgl;
   const int64_t tiles = (int64_t)q.tiles_k * q.tiles_l;
-  int64_t ns = ceil_div(kTargetWG, tiles);
+  // one wave of workgroups over the CUs, but at least 512 corners per split
+  int64_t ns = ceil_div((int64_t)kCUs * tv.wg_per_cu, tiles);
   const int64_t ns_max = std::max<int64_t>(1, ceil_div(V, 512));
   ns = std::max<int64_t>(1, std::min(ns, ns_max));
   ns = std::min<int64_t>(ns, 65535);
   q.nsplit = (int)ns;
-  q.chunk = std::max<int64_t>(16, round_up(ceil_div(std::max<int64_t>(V, 1), ns), 16));
+  const int cm = tv.chunk_mult;
+  q.chunk = std::max<int64_t>(cm, round_up(ceil_div(std::max<int64_t>(V, 1), ns), cm));
   q.vpad = q.chunk * q.nsplit;
   q.pre_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(q.vpad, 256)));
   q.hist_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(256, ceil_div(V, 1024)));
@@ -805,7 +809,8 @@ fcfs_status batch_layout(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec
     int64_t ns = std::max<int64_t>(1, ceil_div(ci.V, chunk_target));
     ns = std::min<int64_t>(ns, 4096);
     b.nsplit = (int)ns;
-    b.chunk = std::max<int64_t>(16, round_up(ceil_div(std::max<int64_t>(ci.V, 1), ns), 16));
+    b.chunk = std::max<int64_t>(tv.chunk_mult,
+                                round_up(ceil_div(std::max<int64_t>(ci.V, 1), ns), tv.chunk_mult));
     b.vpad = b.chunk * b.nsplit;
     const int fk = (int)ceil_div(ci.K, 256), fl = (int)ceil_div(ci.L, 256);
     b.ax_fb_k = fk;
@@ -1025,7 +1030,7 @@ namespace {
 
 int batch_tile(fcfs_handle *h, int prec) {
   if (h && prec >= 0 && prec < 3 && h->batch_tile[prec] >= 0) return h->batch_tile[prec];
-  return prec == fcfs::kFP32 ? 1 : 4;
+  return prec == fcfs::kFP32 ? 1 : 5;
 }
 int64_t batch_chunk(fcfs_handle *h, int prec) {
   if (h && prec >= 0 && prec < 3 && h->batch_chunk[prec] > 0) return h->batch_chunk[prec];
@@ -1243,11 +1248,12 @@ fcfs_status fcfs_autotune(fcfs_handle *h, const char *cache_path, int effort) {
     }
     const int64_t chunks[4] = {4096, 8192, 16384, 32768};
     for (int p = 0; p < 3 && !st; ++p) {
-      const int tiles[2] = {p == fcfs::kFP32 ? 0 : 3, p == fcfs::kFP32 ? 1 : 4};
+      const int tiles[3] = {p == fcfs::kFP32 ? 0 : 3, p == fcfs::kFP32 ? 1 : 4, 5};
+      const int ntiles = p == fcfs::kFP32 ? 2 : 3;
       double best = 1e30;
       int best_tile = -1;
       int64_t best_chunk = 0;
-      for (int ti = 0; ti < 2 && !st; ++ti)
+      for (int ti = 0; ti < ntiles && !st; ++ti)
         for (int ci = 0; ci < 4 && !st; ++ci) {
           h->batch_tile[p] = tiles[ti];
           h->batch_chunk[p] = chunks[ci];

@@ -153,9 +153,11 @@ int epilogue_block_count(int K, int L);
 // Contraction tile variants (wave tile in k x l frequencies; 2 x 2 waves).
 struct TileVariant {
   int id;
-  int prec_mask;  // bit per Prec this variant is built for
-  int wk, wl;     // frequencies per wave
-  int pipe;       // software-pipelined inner loop (one wave per SIMD) or lean
+  int prec_mask;   // bit per Prec this variant is built for
+  int wk, wl;      // frequencies per wave
+  int pipe;        // loop form: 0 lean, 1 double-buffered, 2 interleaved (one wave per SIMD)
+  int wg_per_cu;   // resident workgroups per CU the launch is sized for
+  int chunk_mult;  // corners per split are a multiple of this
 };
 int n_tile_variants();
 const TileVariant &tile_variant(int i);

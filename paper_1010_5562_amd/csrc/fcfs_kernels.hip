@@ -478,6 +478,95 @@ __global__ __launch_bounds__(256, 2) void k_contract_split_lean(const uint4 *__r
                                      blockIdx.y);
 }
 
+// Software-pipelined form for one wave per SIMD: the MFMAs of step s are
+// interleaved with the table lookups and operand packing of step s+1 and the
+// corner loads of step s+2.  Each half-iteration of the loop is one basic
+// block (the look-ahead loads clamp their step index instead of branching), so
+// the scheduling groups can interleave the whole step: per MFMA one group of
+// VALU work, with the LDS lookups front-loaded so that their results are back
+// before the packing needs them.  chunk must be a multiple of 32 corners.
+template <int NKB, int NLB>
+__device__ __forceinline__ void pipe_schedule() {
+  constexpr int NM = 12 * NKB * NLB;                          // MFMAs per step
+  constexpr int ND = 8 * (NKB + NLB);                         // LDS lookups per step
+  constexpr int NV = 8 * NKB + 16 * NLB + 16 * (NKB + NLB);   // phase and packing VALU
+#pragma unroll
+  for (int i = 0; i < NM; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                   // MFMA
+    if (i % 6 == 0) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // corner load
+    if (i < ND / 2) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);   // LDS lookups
+    __builtin_amdgcn_sched_group_barrier(0x002, (NV + NM - 1) / NM, 0);  // VALU
+  }
+}
+
+template <int PREC, int NKB, int NLB>
+__device__ __forceinline__ void contract_pipe_body(const uint2 *s_tab,
+                                                   const uint4 *__restrict__ packed,
+                                                   int64_t chunk, int tiles_l, int kp, int lp,
+                                                   float *__restrict__ part, int tile, int split) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 31, lh = lane >> 5;
+  const int tk = tile / tiles_l, tl = tile % tiles_l;
+  const int k0 = tk * (64 * NKB) + (wave >> 1) * (32 * NKB);
+  const int l0 = tl * (64 * NLB) + (wave & 1) * (32 * NLB);
+
+  uint32_t kf[NKB], lf[NLB];
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb) kf[kb] = (uint32_t)(k0 + 32 * kb + li);
+#pragma unroll
+  for (int lb = 0; lb < NLB; ++lb) lf[lb] = (uint32_t)(l0 + 32 * lb + li);
+
+  f32x16 acc[NKB][NLB][4];
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+    for (int lb = 0; lb < NLB; ++lb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[kb][lb][q][r] = 0.0f;
+
+  const uint4 *vp = packed + (size_t)split * chunk + 8 * lh;
+  const int nsteps = (int)(chunk >> 4);  // even
+  const int last = nsteps - 1;
+  uint4 c0[8], c1[8];
+  Raw<NKB, NLB> raw;
+  Frag<NKB, NLB> fa, fb;
+  load_corners(c0, vp);
+  gather(raw, s_tab, c0, kf, lf);
+  build(fa, raw);
+  load_corners(c1, vp + 16);
+  for (int s = 0; s < nsteps; s += 2) {
+    // fa: operands of step s; c1: corners of step s+1
+    load_corners(c0, vp + 16 * min(s + 2, last));
+    gather(raw, s_tab, c1, kf, lf);
+    build(fb, raw);
+    mma<PREC>(acc, fa);
+    pipe_schedule<NKB, NLB>();
+    // fb: operands of step s+1; c0: corners of step s+2 (the last iteration
+    // prepares a step that is never multiplied)
+    load_corners(c1, vp + 16 * min(s + 3, last));
+    gather(raw, s_tab, c0, kf, lf);
+    build(fa, raw);
+    mma<PREC>(acc, fb);
+    pipe_schedule<NKB, NLB>();
+  }
+  store_part<NKB, NLB>(part, acc, split, kp, lp, k0, l0, li, lh);
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256, 1) void k_contract_split_pipe(const uint4 *__restrict__ packed,
+                                                                const uint2 *__restrict__ tab,
+                                                                int64_t chunk, int tiles_l,
+                                                                int kp, int lp,
+                                                                float *__restrict__ part) {
+  __shared__ uint2 s_tab[kTabEntries];
+  for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
+  __syncthreads();
+  contract_pipe_body<PREC, 2, 2>(s_tab, packed, chunk, tiles_l, kp, lp, part, blockIdx.x,
+                                 blockIdx.y);
+}
+
 // FP32 form: v_mfma_f32_32x32x2_f32, two corners per product (lanes 0-31
 // carry corner j of the lane's group, lanes 32-63 corner 8 + j).
 template <int NKB, int NLB>
@@ -548,13 +637,15 @@ __global__ __launch_bounds__(256) void k_contract_fp32(const uint4 *__restrict__
                                blockIdx.y);
 }
 
-// Tile variants: (id, precision mask, k per wave, l per wave, pipelined).
+// Tile variants: (id, precision mask, k per wave, l per wave, loop form,
+// workgroups per CU, corners per split a multiple of).
 static const TileVariant kVariants[] = {
-    {0, 0x7, 32, 32, 1},
-    {1, 0x7, 64, 32, 1},
-    {2, 0x7, 64, 64, 1},
-    {3, 0x6, 32, 32, 0},
-    {4, 0x6, 64, 32, 0},
+    {0, 0x7, 32, 32, 1, 2, 16},
+    {1, 0x7, 64, 32, 1, 2, 16},
+    {2, 0x7, 64, 64, 1, 2, 16},
+    {3, 0x6, 32, 32, 0, 2, 16},
+    {4, 0x6, 64, 32, 0, 2, 16},
+    {5, 0x6, 64, 64, 2, 1, 32},
 };
 
 int n_tile_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
@@ -592,6 +683,18 @@ hipError_t launch_contract(const FwdPlan &p, const uint4 *packed, const Tables &
     case 2: launch_contract_t<2, 2, true>(p, packed, t, part, st); break;
     case 3: launch_contract_t<1, 1, false>(p, packed, t, part, st); break;
     case 4: launch_contract_t<2, 1, false>(p, packed, t, part, st); break;
+    case 5: {
+      const dim3 grid(p.tiles_k * p.tiles_l, p.nsplit), block(256);
+      if (p.prec == kBF16)
+        hipLaunchKernelGGL(k_contract_split_pipe<kBF16>, grid, block, 0, st, packed, t.wbf16,
+                           p.chunk, p.tiles_l, p.kp, p.lp, part);
+      else if (p.prec == kFP16)
+        hipLaunchKernelGGL(k_contract_split_pipe<kFP16>, grid, block, 0, st, packed, t.wfp16,
+                           p.chunk, p.tiles_l, p.kp, p.lp, part);
+      else
+        return hipErrorInvalidValue;
+      break;
+    }
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -858,6 +961,25 @@ __global__ __launch_bounds__(256, 2) void k_batch_contract(const BatchClip *__re
   }
 }
 
+template <int PREC>
+__global__ __launch_bounds__(256, 1) void k_batch_contract_pipe(const BatchClip *__restrict__ clips,
+                                                                const int4 *__restrict__ items,
+                                                                int n_items,
+                                                                unsigned int *counter,
+                                                                const uint2 *__restrict__ tab) {
+  __shared__ uint2 s_tab[kTabEntries];
+  __shared__ int s_item;
+  for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
+  for (;;) {
+    const int it = next_item(counter, n_items, &s_item);
+    if (it < 0) break;
+    const int4 d = items[it];
+    const BatchClip &c = clips[d.x];
+    contract_pipe_body<PREC, 2, 2>(s_tab, c.packed, c.chunk, c.tiles_l, c.kp, c.lp, c.part, d.y,
+                                   d.z);
+  }
+}
+
 template <int NKB, int NLB>
 __global__ __launch_bounds__(256, 2) void k_batch_contract_fp32(const BatchClip *__restrict__ clips,
                                                                 const int4 *__restrict__ items,
@@ -914,9 +1036,8 @@ hipError_t launch_batch_side(const BatchLaunch &b, const double2 *w64, hipStream
 }
 
 int batch_grid(int tile, int prec) {
-  (void)tile;
   (void)prec;
-  return 2 * 256;  // two workgroups per CU (64 KB of LDS each) on 256 CUs
+  return tile_variant(tile).wg_per_cu * 256;  // persistent workgroups on 256 CUs
 }
 
 hipError_t launch_batch_contract(const BatchLaunch &b, const Tables &t, hipStream_t st) {
@@ -930,6 +1051,13 @@ hipError_t launch_batch_contract(const BatchLaunch &b, const Tables &t, hipStrea
     else
       hipLaunchKernelGGL((k_batch_contract_fp32<1, 1>), grid, block, 0, st, b.clips, b.items,
                          b.n_items, b.counter, t.w32);
+  } else if (b.tile == 5) {
+    if (b.prec == kBF16)
+      hipLaunchKernelGGL(k_batch_contract_pipe<kBF16>, grid, block, 0, st, b.clips, b.items,
+                         b.n_items, b.counter, t.wbf16);
+    else
+      hipLaunchKernelGGL(k_batch_contract_pipe<kFP16>, grid, block, 0, st, b.clips, b.items,
+                         b.n_items, b.counter, t.wfp16);
   } else if (b.prec == kBF16) {
     if (wide)
       hipLaunchKernelGGL((k_batch_contract<kBF16, 2, 1>), grid, block, 0, st, b.clips, b.items,

@@ -60,9 +60,12 @@ def test_single_polygon_c1(P, oracle_lib, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
-@pytest.mark.parametrize("tile", [0, 1, 2])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5])
 def test_tiles_and_ragged_edges(P, oracle_lib, prec, tile):
-    # several workgroup tiles in k and l, K != L, a ragged vertex tail
+    # several workgroup tiles in k and l, K != L, a ragged vertex tail; tile
+    # variants 3-5 exist for the split forms only
+    if prec == "fp32" and tile >= 3:
+        pytest.skip("split-only tile variant")
     T, K, L = 1024, 150, 97
     clip = synth.clip(31, T, K, L, n_polygons=211)
     _say(f"ragged V={clip.n_vertices} T={T} K={K} L={L} prec={prec} tile={tile}")
