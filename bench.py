@@ -237,7 +237,7 @@ def main() -> int:
         "err_rel_f00": errs.get("bf16"),
         "roofline": {
             "bound": "mfma",
-            "kernel": "k_contract_split_lean<bf16,2,1>",
+            "kernel": "k_contract_split_pipe<bf16> (64x64 frequencies per wave, one wave per SIMD)",
             "achieved": achieved,
             "peak": PEAK_TFLOPS["bf16"],
             "unit": "TFLOP/s",
