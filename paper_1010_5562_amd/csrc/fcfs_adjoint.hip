@@ -19,6 +19,13 @@
 
 namespace fcfs {
 
+// Position of W[row r][column n] in the MFMA operand records (see k_adj_split).
+__device__ __forceinline__ size_t rec_index(int n, int r, int lb, int ncb) {
+  const int q = n / lb, lm = n - q * lb;
+  const int kstep = r >> 4, h = (r >> 3) & 1, j = r & 7, cb = (lm >> 5) * 4 + q, li = lm & 31;
+  return ((((size_t)kstep * ncb + cb) * 64) + li + 32 * h) * 8 + j;
+}
+
 // ---------------------------------------------------------------------------
 // W from the cotangent.  For 1 <= k <= kb, 1 <= l <= lb (zero outside the
 // band), with M'[k,l] = M[k,l] + conj(M[-k,-l]) and a + jb = M'[k,l],
@@ -29,15 +36,20 @@ namespace fcfs {
 // [cos k | sin k], each kb long.  Stored transposed, Wf[n * R + r], FP32.
 // The largest |W| is folded into *wmax (float bits, non-negative).
 // ---------------------------------------------------------------------------
+template <bool DIRECT>
 __global__ __launch_bounds__(256) void k_adj_w(const float2 *__restrict__ G, int K, int L, int kmax,
                                                int lmax, int kb, int lb, float *__restrict__ Wf,
-                                               unsigned int *__restrict__ wmax) {
+                                               unsigned int *__restrict__ wmax,
+                                               uint16_t *__restrict__ whi,
+                                               uint16_t *__restrict__ wlo,
+                                               int *__restrict__ scale) {
   const int l = 1 + blockIdx.x * 256 + threadIdx.x;
   const int k = 1 + blockIdx.y;
-  if (l > lb) return;
+  // lanes past lb stay active (with zeros) for the wave-wide maximum below
+  const bool live = l <= lb;
   const int R = 2 * kb;
   double Wcc = 0, Wcs = 0, Wsc = 0, Wss = 0, Ycc = 0, Ycs = 0, Ysc = 0, Yss = 0;
-  if (k <= kmax && l <= lmax) {
+  if (live && k <= kmax && l <= lmax) {
     const size_t WL = 2 * (size_t)L + 1;
     const float2 gpp = G[(size_t)(K + k) * WL + (L + l)];  // G[k, l]
     const float2 gmm = G[(size_t)(K - k) * WL + (L - l)];  // G[-k, -l]
@@ -67,14 +79,33 @@ __global__ __launch_bounds__(256) void k_adj_w(const float2 *__restrict__ G, int
   const size_t nyc = (size_t)(2 * lb + l - 1), nys = (size_t)(3 * lb + l - 1);
   const float v[8] = {(float)Wcc, (float)Wsc, (float)Wcs, (float)Wss,
                       (float)Ycc, (float)Ysc, (float)Ycs, (float)Yss};
-  Wf[nxc * R + rc] = v[0];
-  Wf[nxc * R + rs] = v[1];
-  Wf[nxs * R + rc] = v[2];
-  Wf[nxs * R + rs] = v[3];
-  Wf[nyc * R + rc] = v[4];
-  Wf[nyc * R + rs] = v[5];
-  Wf[nys * R + rc] = v[6];
-  Wf[nys * R + rs] = v[7];
+  if constexpr (DIRECT) {
+    // split-bf16: hi + lo records written here, scale 2^0
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) scale[0] = 0;
+    if (!live) return;
+    const int ncb = lb / 8;  // NC / 32 with NC = 4 lb
+    const int nn[8] = {(int)nxc, (int)nxc, (int)nxs, (int)nxs, (int)nyc, (int)nyc, (int)nys, (int)nys};
+    const int rr[8] = {rc, rs, rc, rs, rc, rs, rc, rs};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const __bf16 hi = (__bf16)v[i];
+      const __bf16 lo = (__bf16)(v[i] - (float)hi);
+      const size_t o = rec_index(nn[i], rr[i], lb, ncb);
+      whi[o] = __builtin_bit_cast(uint16_t, hi);
+      wlo[o] = __builtin_bit_cast(uint16_t, lo);
+    }
+    return;
+  }
+  if (live) {
+    Wf[nxc * R + rc] = v[0];
+    Wf[nxc * R + rs] = v[1];
+    Wf[nxs * R + rc] = v[2];
+    Wf[nxs * R + rs] = v[3];
+    Wf[nyc * R + rc] = v[4];
+    Wf[nyc * R + rs] = v[5];
+    Wf[nys * R + rc] = v[6];
+    Wf[nys * R + rs] = v[7];
+  }
   float m = 0.f;
 #pragma unroll
   for (int i = 0; i < 8; ++i) m = fmaxf(m, fabsf(v[i]));
@@ -85,8 +116,14 @@ __global__ __launch_bounds__(256) void k_adj_w(const float2 *__restrict__ G, int
 // Split W into hi + lo 16-bit parts after scaling by 2^e, e chosen from the
 // largest |W| so that the binary16 range is never exceeded (bf16 uses the
 // same scale).  scale[0] = e (as int), written by block 0.
+// The parts are stored in MFMA operand order: the 16 x 32 block (rows
+// 16 kstep .. +15, columns of block cb) is one 1 KB record of 64 lanes x 8
+// values, lane li + 32 h holding rows 16 kstep + 8 h .. +7 of the block's
+// column li, so that a wave loads its B operand with one contiguous read.
+// Block cb = 4 lblk + q holds the columns (q, l = 32 lblk + 1 .. 32 lblk + 32).
 template <int PREC>
-__global__ __launch_bounds__(256) void k_adj_split(const float *__restrict__ Wf, int64_t n,
+__global__ __launch_bounds__(256) void k_adj_split(const float *__restrict__ Wf, int R, int NC,
+                                                   int lb,
                                                    const unsigned int *__restrict__ wmax,
                                                    uint16_t *__restrict__ whi,
                                                    uint16_t *__restrict__ wlo,
@@ -99,18 +136,23 @@ __global__ __launch_bounds__(256) void k_adj_split(const float *__restrict__ Wf,
     e = 14 - ex;     // m * 2^e < 2^14
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) scale[0] = e;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+  const int64_t n_all = (int64_t)R * NC;
+  const int ncb = NC / 32;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n_all;
+       i += (int64_t)gridDim.x * 256) {
+    const int n = (int)(i / R), r = (int)(i % R);
     const float w = ldexpf(Wf[i], e);
+    const size_t o = rec_index(n, r, lb, ncb);
     if constexpr (PREC == kBF16) {
-      const __bf16 h = (__bf16)w;
-      const __bf16 lo = (__bf16)(w - (float)h);
-      whi[i] = __builtin_bit_cast(uint16_t, h);
-      wlo[i] = __builtin_bit_cast(uint16_t, lo);
+      const __bf16 hi = (__bf16)w;
+      const __bf16 lo = (__bf16)(w - (float)hi);
+      whi[o] = __builtin_bit_cast(uint16_t, hi);
+      wlo[o] = __builtin_bit_cast(uint16_t, lo);
     } else {
-      const _Float16 h = (_Float16)w;
-      const _Float16 lo = (_Float16)(w - (float)h);
-      whi[i] = __builtin_bit_cast(uint16_t, h);
-      wlo[i] = __builtin_bit_cast(uint16_t, lo);
+      const _Float16 hi = (_Float16)w;
+      const _Float16 lo = (_Float16)(w - (float)hi);
+      whi[o] = __builtin_bit_cast(uint16_t, hi);
+      wlo[o] = __builtin_bit_cast(uint16_t, lo);
     }
   }
 }
@@ -122,30 +164,37 @@ __global__ void k_fill_u32(unsigned int *p, int n, unsigned int v) {
 
 // Axis and DC coefficients, folded over +-f:
 //   P_k = conj(G[k,0]) + G[-k,0],  Q_l = conj(G[0,l]) + G[0,-l],  G00 real part.
-// coef layout: [P_1..P_K | Q_1..Q_L] as double2, then Re G[0,0].
+// coef layout: [P_1..P_K | Q_1..Q_L | Re G00 | P_k/(2 pi k) | Q_l/(2 pi l)] as
+// double2 (the scaled copies spare the per-corner loop a division).
 __global__ void k_adj_axcoef(const float2 *__restrict__ G, int K, int L, int kmax, int lmax,
                              double2 *__restrict__ coef) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   const size_t WL = 2 * (size_t)L + 1;
+  double2 v = make_double2(0.0, 0.0);
+  int f = 0;
   if (i < K) {
     const int k = i + 1;
-    double2 p = make_double2(0.0, 0.0);
+    f = k;
     if (k <= kmax) {
       const float2 a = G[(size_t)(K + k) * WL + L], b = G[(size_t)(K - k) * WL + L];
-      p = make_double2((double)a.x + b.x, (double)b.y - a.y);
+      v = make_double2((double)a.x + b.x, (double)b.y - a.y);
     }
-    coef[i] = p;
   } else if (i < K + L) {
     const int l = i - K + 1;
-    double2 q = make_double2(0.0, 0.0);
+    f = l;
     if (l <= lmax) {
       const float2 a = G[(size_t)K * WL + (L + l)], b = G[(size_t)K * WL + (L - l)];
-      q = make_double2((double)a.x + b.x, (double)b.y - a.y);
+      v = make_double2((double)a.x + b.x, (double)b.y - a.y);
     }
-    coef[i] = q;
   } else if (i == K + L) {
     coef[i] = make_double2((double)G[(size_t)K * WL + L].x, 0.0);
+    return;
+  } else {
+    return;
   }
+  coef[i] = v;
+  const double sc = 1.0 / (2.0 * kPi * (double)f);
+  coef[K + L + 1 + i] = make_double2(v.x * sc, v.y * sc);
 }
 
 // Per corner, FP64: the axis and DC parts of gx, gy (written, not added).
@@ -164,19 +213,20 @@ __global__ __launch_bounds__(256) void k_adj_axis(const int32_t *__restrict__ x,
   const uint4 c = packed[v];
   const double sg = c.z ? -1.0 : 1.0;
   const double xv = (double)x[v], yv = (double)y[v];
+  const double2 *coef_s = coef + (K + L + 1);  // scaled by 1/(2 pi f)
   double sx1 = 0.0, sx2 = 0.0;  // sum Re[P e(kx)],  sum Re[P j/(2 pi k) e(kx)]
   {
     const uint32_t ph = c.x >> 3;
     const double2 w1 = w64[ph];
     double2 w = w1;
+    // unrolled so that the uniform coefficient loads of 8 steps are issued together
+#pragma unroll 8
     for (int k = 1; k <= kmax; ++k) {
       if ((k & 31) == 0) w = w64[((uint32_t)k * ph) & (uint32_t)(kTabN - 1)];
-      const double2 p = coef[k - 1];
-      // e(kx) = w.x - j w.y
-      const double re = p.x * w.x + p.y * w.y;   // Re[P e]
-      const double im = p.y * w.x - p.x * w.y;   // Im[P e]
-      sx1 += re;
-      sx2 += -im / (2.0 * kPi * k);              // Re[j P e] / (2 pi k)
+      const double2 p = coef[k - 1], ps = coef_s[k - 1];
+      // e(kx) = w.x - j w.y;  Re[j z] = -Im z
+      sx1 += p.x * w.x + p.y * w.y;
+      sx2 -= ps.y * w.x - ps.x * w.y;
       const double nx = w.x * w1.x - w.y * w1.y, ny = w.x * w1.y + w.y * w1.x;
       w = make_double2(nx, ny);
     }
@@ -186,13 +236,12 @@ __global__ __launch_bounds__(256) void k_adj_axis(const int32_t *__restrict__ x,
     const uint32_t ph = c.y >> 3;
     const double2 w1 = w64[ph];
     double2 w = w1;
+#pragma unroll 8
     for (int l = 1; l <= lmax; ++l) {
       if ((l & 31) == 0) w = w64[((uint32_t)l * ph) & (uint32_t)(kTabN - 1)];
-      const double2 q = coef[K + l - 1];
-      const double re = q.x * w.x + q.y * w.y;
-      const double im = q.y * w.x - q.x * w.y;
-      sy1 += re;
-      sy2 += -im / (2.0 * kPi * l);
+      const double2 q = coef[K + l - 1], qs = coef_s[K + l - 1];
+      sy1 += q.x * w.x + q.y * w.y;
+      sy2 -= qs.y * w.x - qs.x * w.y;
       const double nx = w.x * w1.x - w.y * w1.y, ny = w.x * w1.y + w.y * w1.x;
       w = make_double2(nx, ny);
     }
@@ -204,28 +253,50 @@ __global__ __launch_bounds__(256) void k_adj_axis(const int32_t *__restrict__ x,
 
 // ---------------------------------------------------------------------------
 // Main term: t_v = X_v^T W on MFMA (rows = 32 corners per wave, inner = the
-// 2*kb frequencies, NB column blocks of 32 at a time), each finished column
+// 2*kb frequencies, four column blocks of 32 at a time), each finished column
 // block dotted with Y_v at once; the per-corner partial sums are reduced
 // across the 32 columns held by the lanes and added to gx, gy.
+// The eight waves of a workgroup (256 corners) share the W operand records:
+// per 16-frequency step the workgroup copies the 16 records it needs (4 column
+// blocks x cos/sin rows x hi/lo, 16 KB) into one of two LDS buffers, then every
+// wave reads them from there.  The step index runs on across column groups so
+// that consecutive steps always alternate buffers: one barrier per step keeps
+// a buffer from being refilled while a slower wave still reads it.
 // ---------------------------------------------------------------------------
 constexpr int kAdjNB = 4;
+constexpr int kAdjWaves = 8;
 
 template <int PREC>
-__global__ __launch_bounds__(256) void k_adj_gemm_split(const uint4 *__restrict__ packed,
-                                                        const uint2 *__restrict__ tab,
-                                                        const float2 *__restrict__ tab32,
-                                                        const uint16_t *__restrict__ whi,
-                                                        const uint16_t *__restrict__ wlo,
-                                                        const int *__restrict__ scale, int64_t V,
-                                                        int kb, int lb, float *__restrict__ gx,
-                                                        float *__restrict__ gy) {
+__global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_split(
+    const uint4 *__restrict__ packed, const uint2 *__restrict__ tab,
+    const float2 *__restrict__ tab32, const uint16_t *__restrict__ whi,
+    const uint16_t *__restrict__ wlo, const int *__restrict__ scale, int64_t V, int kb, int lb,
+    float *__restrict__ gx, float *__restrict__ gy) {
   __shared__ uint2 s_tab[kTabEntries];
-  for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
-  __syncthreads();
+  __shared__ u32x4 s_w[2][4 * kAdjNB][64];
+  for (int i = threadIdx.x; i < kTabEntries; i += 64 * kAdjWaves) s_tab[i] = tab[i];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 31, lh = lane >> 5;
-  const int64_t vbase = (int64_t)blockIdx.x * 128 + wave * 32;
-  const int R = 2 * kb, NC = 4 * lb;
+  const int64_t vbase = (int64_t)blockIdx.x * (32 * kAdjWaves) + wave * 32;
+  const int NC = 4 * lb, ncb = NC / 32, nks = kb / 16;
+  const int nsteps = (NC / (32 * kAdjNB)) * nks;
+  // operand record q of flat step it: column block nb = q & 3, sin rows if
+  // q & 4, lo part if q & 8 (layout of k_adj_split)
+  auto record = [&](int it, int q) -> const u32x4 * {
+    const int cgi = it / nks, t = it - cgi * nks;
+    const int kstep = (q & 4) ? nks + t : t;
+    const size_t cb = (size_t)(cgi * kAdjNB + (q & 3));
+    const uint16_t *base = (q & 8) ? wlo : whi;
+    return (const u32x4 *)(base + ((((size_t)kstep * ncb + cb) * 64) * 8));
+  };
+  // this thread's share of a step's 16 records: entries idx = tid + 512 u
+  constexpr int kPer = 4 * kAdjNB * 64 / (64 * kAdjWaves);
+  u32x4 pre[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int idx = threadIdx.x + 64 * kAdjWaves * u;
+    pre[u] = record(0, idx >> 6)[idx & 63];
+  }
   const uint4 ca = packed[vbase + li];  // this lane's A row
   // the 16 output rows this lane holds
   uint32_t ys8[16];
@@ -239,13 +310,28 @@ __global__ __launch_bounds__(256) void k_adj_gemm_split(const uint4 *__restrict_
   float sx[16], sy[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) sx[r] = sy[r] = 0.f;
+  int it = 0;
   for (int cg = 0; cg < NC; cg += 32 * kAdjNB) {
     f32x16 acc[kAdjNB];
 #pragma unroll
     for (int nb = 0; nb < kAdjNB; ++nb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[nb][r] = 0.f;
-    for (int ib = 0; ib < kb; ib += 16) {
+    for (int ib = 0; ib < kb; ib += 16, ++it) {
+      const int buf = it & 1;
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int idx = threadIdx.x + 64 * kAdjWaves * u;
+        s_w[buf][idx >> 6][idx & 63] = pre[u];
+      }
+      __syncthreads();
+      if (it + 1 < nsteps) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+          const int idx = threadIdx.x + 64 * kAdjWaves * u;
+          pre[u] = record(it + 1, idx >> 6)[idx & 63];
+        }
+      }
       uint2 d[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j)
@@ -254,10 +340,8 @@ __global__ __launch_bounds__(256) void k_adj_gemm_split(const uint4 *__restrict_
       pack4(d, ach, ash, acl, asl);
 #pragma unroll
       for (int nb = 0; nb < kAdjNB; ++nb) {
-        const size_t n = (size_t)(cg + 32 * nb + li);
-        const size_t oc = n * R + ib + 8 * lh, os = oc + kb;
-        const u32x4 bch = *(const u32x4 *)(whi + oc), bcl = *(const u32x4 *)(wlo + oc);
-        const u32x4 bsh = *(const u32x4 *)(whi + os), bsl = *(const u32x4 *)(wlo + os);
+        const u32x4 bch = s_w[buf][nb][lane], bsh = s_w[buf][4 + nb][lane];
+        const u32x4 bcl = s_w[buf][8 + nb][lane], bsl = s_w[buf][12 + nb][lane];
         acc[nb] = mfma16<PREC>(ach, bch, acc[nb]);
         acc[nb] = mfma16<PREC>(ach, bcl, acc[nb]);
         acc[nb] = mfma16<PREC>(acl, bch, acc[nb]);
@@ -266,20 +350,25 @@ __global__ __launch_bounds__(256) void k_adj_gemm_split(const uint4 *__restrict_
         acc[nb] = mfma16<PREC>(asl, bsh, acc[nb]);
       }
     }
-    // dot the finished columns with Y_v: column n = (q, l), q = n / lb
-#pragma unroll
-    for (int nb = 0; nb < kAdjNB; ++nb) {
-      const int n0 = cg + 32 * nb;
-      const int q = n0 / lb;
-      const uint32_t l = (uint32_t)(n0 - q * lb + li + 1);
+    // dot with Y_v: this lane's four accumulators hold the columns (q, l) of
+    // one frequency l; (cos, sin)(l y) = hi + lo from the split table
+    {
+      const uint32_t l = (uint32_t)((cg >> 2) + li + 1);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const float2 w = tab32[(l * (ys8[r] >> 3)) & (uint32_t)(kTabN - 1)];
-        const float yv = (q & 1) ? w.y : w.x;
-        if (q < 2)
-          sx[r] = fmaf(acc[nb][r], yv, sx[r]);
-        else
-          sy[r] = fmaf(acc[nb][r], yv, sy[r]);
+        const uint2 e = lds_entry(s_tab, phase_x(l, make_uint4(ys8[r], 0u, 0u, 0u)));
+        float yc, ys;
+        if constexpr (PREC == kBF16) {
+          yc = __uint_as_float(e.x << 16) + __uint_as_float(e.y << 16);
+          ys = __uint_as_float(e.x & 0xFFFF0000u) + __uint_as_float(e.y & 0xFFFF0000u);
+        } else {
+          yc = (float)__builtin_bit_cast(_Float16, (uint16_t)(e.x & 0xFFFFu)) +
+               (float)__builtin_bit_cast(_Float16, (uint16_t)(e.y & 0xFFFFu));
+          ys = (float)__builtin_bit_cast(_Float16, (uint16_t)(e.x >> 16)) +
+               (float)__builtin_bit_cast(_Float16, (uint16_t)(e.y >> 16));
+        }
+        sx[r] = fmaf(acc[0][r], yc, fmaf(acc[1][r], ys, sx[r]));
+        sy[r] = fmaf(acc[2][r], yc, fmaf(acc[3][r], ys, sy[r]));
       }
     }
   }
@@ -397,10 +486,17 @@ hipError_t launch_adjoint(const AdjPlan &a, const int32_t *x, const int32_t *y, 
     hipLaunchKernelGGL(k_adj_axis, dim3((unsigned)((a.V + 255) / 256)), dim3(256), 0, st, x, y,
                        packed, t.w64, coef, a.V, a.K, a.L, a.kmax, a.lmax, (double)a.T, gx, gy);
   if (a.kmax == 0 || a.lmax == 0 || a.V == 0) return hipGetLastError();
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, wmax, 1, 0u);
-  hipLaunchKernelGGL(k_adj_w, dim3((a.lb + 255) / 256, a.kb), dim3(256), 0, st, G, a.K, a.L,
-                     a.kmax, a.lmax, a.kb, a.lb, Wf, wmax);
-  const unsigned blocks = (unsigned)(a.vpad / 128);
+  const dim3 wgrid((a.lb + 255) / 256, a.kb);
+  if (a.prec == kBF16) {
+    hipLaunchKernelGGL(k_adj_w<true>, wgrid, dim3(256), 0, st, G, a.K, a.L, a.kmax, a.lmax, a.kb,
+                       a.lb, Wf, wmax, whi, wlo, scale);
+  } else {
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, wmax, 1, 0u);
+    hipLaunchKernelGGL(k_adj_w<false>, wgrid, dim3(256), 0, st, G, a.K, a.L, a.kmax, a.lmax,
+                       a.kb, a.lb, Wf, wmax, whi, wlo, scale);
+  }
+  const unsigned blocks = (unsigned)(a.vpad / 128);                     // FP32 form
+  const unsigned sblocks = (unsigned)(a.vpad / (32 * kAdjWaves));      // split forms
   if (a.prec == kFP32) {
     hipLaunchKernelGGL(k_adj_gemm_fp32, dim3(blocks), dim3(256), 0, st, packed, t.w32, Wf, a.V,
                        a.kb, a.lb, gx, gy);
@@ -408,14 +504,12 @@ hipError_t launch_adjoint(const AdjPlan &a, const int32_t *x, const int32_t *y, 
     const int64_t n = (int64_t)a.R * a.NC;
     const unsigned sb = (unsigned)std::min<int64_t>(1024, (n + 255) / 256);
     if (a.prec == kBF16) {
-      hipLaunchKernelGGL(k_adj_split<kBF16>, dim3(sb), dim3(256), 0, st, Wf, n, wmax, whi, wlo,
-                         scale);
-      hipLaunchKernelGGL(k_adj_gemm_split<kBF16>, dim3(blocks), dim3(256), 0, st, packed,
+      hipLaunchKernelGGL(k_adj_gemm_split<kBF16>, dim3(sblocks), dim3(64 * kAdjWaves), 0, st, packed,
                          t.wbf16, t.w32, whi, wlo, scale, a.V, a.kb, a.lb, gx, gy);
     } else {
-      hipLaunchKernelGGL(k_adj_split<kFP16>, dim3(sb), dim3(256), 0, st, Wf, n, wmax, whi, wlo,
-                         scale);
-      hipLaunchKernelGGL(k_adj_gemm_split<kFP16>, dim3(blocks), dim3(256), 0, st, packed,
+      hipLaunchKernelGGL(k_adj_split<kFP16>, dim3(sb), dim3(256), 0, st, Wf, a.R, a.NC, a.lb,
+                         wmax, whi, wlo, scale);
+      hipLaunchKernelGGL(k_adj_gemm_split<kFP16>, dim3(sblocks), dim3(64 * kAdjWaves), 0, st, packed,
                          t.wfp16, t.w32, whi, wlo, scale, a.V, a.kb, a.lb, gx, gy);
     }
   }

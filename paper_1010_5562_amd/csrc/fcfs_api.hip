@@ -308,7 +308,7 @@ fcfs_status make_adj_plan(fcfs_handle *h, int64_t V, int T, int K, int L, int km
   a.lb = (int)round_up(std::max(a.lmax, 1), 32);
   a.R = 2 * a.kb;
   a.NC = 4 * a.lb;
-  a.vpad = round_up(std::max<int64_t>(V, 1), 128);
+  a.vpad = round_up(std::max<int64_t>(V, 1), 256);  // 256-corner blocks of the split GEMM
   a.pre_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(a.vpad, 256)));
   size_t off = 0;
   a.off_packed = off;
@@ -316,7 +316,7 @@ fcfs_status make_adj_plan(fcfs_handle *h, int64_t V, int T, int K, int L, int km
   a.off_area = off;
   off += align256(sizeof(unsigned long long) * (size_t)a.pre_blocks);
   a.off_coef = off;
-  off += align256(sizeof(double2) * (size_t)(K + L + 1));
+  off += align256(sizeof(double2) * (size_t)(2 * (K + L) + 1));
   const size_t nw = (size_t)a.R * a.NC;
   a.off_wf = off;
   off += align256(sizeof(float) * nw);

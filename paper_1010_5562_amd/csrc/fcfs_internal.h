@@ -89,7 +89,7 @@ struct AdjPlan {
   int shift;
   int kb, lb;        // kmax, lmax padded to multiples of 16 and 32
   int R, NC;         // GEMM inner rows 2*kb and columns 4*lb
-  int64_t vpad;      // V padded to the 128-corner block of the GEMM
+  int64_t vpad;      // V padded to the 256-corner block of the split GEMM
   int pre_blocks;
   size_t off_packed, off_area, off_coef, off_wf, off_whi, off_wlo, off_scale, bytes;
 };
