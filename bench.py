@@ -360,7 +360,8 @@ def main() -> int:
 
     def step5():
         off.grad = None
-        Fv = P.FCFSFunction.apply(off, geom, "bf16", (rb, rb))
+        # low-pass forward and its adjoint: only the pupil's band and disc
+        Fv = P.FCFSFunction.apply(off, geom, "bf16", (rb, rb), r5)
         loss = ((Hd * Fv - Gt).abs() ** 2).sum()
         loss.backward()
 
@@ -369,7 +370,8 @@ def main() -> int:
     V5 = int(geom.base_x.numel())
     adj = {
         "workload": (f"adjoint: {V5} corners, T={T5}, |k|,|l|<={K5}, loss sum |H F - G|^2 with a "
-                     f"circular pupil of radius {r5:.2f}; forward + backward, split-bf16"),
+                     f"circular pupil of radius {r5:.2f}; low-pass forward + backward over the "
+                     "pupil, split-bf16"),
         "ms_per_step": ms5,
         "forward_ms": sum(kavg(prof5, k) or 0.0 for k in ("prepass", "contract", "epilogue")),
         "adjoint_ms": kavg(prof5, "adjoint"),

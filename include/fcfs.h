@@ -119,6 +119,20 @@ fcfs_status fcfs_workspace_size(const fcfs_clip *c, fcfs_precision p, int adjoin
 fcfs_status fcfs_forward(fcfs_handle *h, const fcfs_clip *c, fcfs_precision p, void *ws,
                          size_t ws_bytes);
 
+/* Low-pass forward: fcfs_forward restricted to the band |k| <= kmax,
+ * |l| <= lmax (clamped to K, L) and, when radius >= 0, to the disc
+ * k^2 + l^2 <= radius^2 (a circular pupil, as needed by lithography models,
+ * Sec. I and the outlook of Sec. V).  c->F keeps its full (2K+1) x (2L+1)
+ * layout: the entries inside the band (and disc) equal those of fcfs_forward
+ * up to rounding, every other entry is written as zero.  Contraction tiles
+ * wholly outside the disc are skipped.  ws: at least fcfs_band_workspace_size
+ * bytes (same arguments), 256-byte aligned.  FCFS_ERR_INVALID_ARG for a
+ * negative kmax or lmax or a NaN radius. */
+fcfs_status fcfs_band_workspace_size(const fcfs_clip *c, int32_t kmax, int32_t lmax,
+                                     double radius, fcfs_precision p, size_t *bytes);
+fcfs_status fcfs_forward_band(fcfs_handle *h, const fcfs_clip *c, int32_t kmax, int32_t lmax,
+                              double radius, fcfs_precision p, void *ws, size_t ws_bytes);
+
 /* Adjoint of fcfs_forward with respect to the corner coordinates (the
  * derivative of the four closed forms of Prop. 3 in x_v and y_v).
  * grad_F: (device) cotangent, same layout as c->F, holding
@@ -127,13 +141,16 @@ fcfs_status fcfs_forward(fcfs_handle *h, const fcfs_clip *c, fcfs_precision p, v
 fcfs_status fcfs_adjoint(fcfs_handle *h, const fcfs_clip *c, const float *grad_F, float *gx,
                          float *gy, fcfs_precision p, void *ws, size_t ws_bytes);
 
-/* fcfs_adjoint restricted to a band: the caller guarantees grad_F == 0 for
- * |k| > kmax or |l| > lmax (e.g. a pupil of radius <= min(kmax, lmax)); the
- * GEMM and the axis sums then cover only the band.  kmax, lmax are clamped to
- * K, L.  The workspace of fcfs_workspace_size(adjoint = 1) always suffices. */
+/* Adjoint of fcfs_forward_band with the same kmax, lmax, radius: only the
+ * entries of grad_F with |k| <= kmax, |l| <= lmax (clamped to K, L) and, when
+ * radius >= 0, k^2 + l^2 <= radius^2 are used; the GEMM and the axis sums then
+ * cover only that band.  It is also the adjoint of fcfs_forward whenever
+ * grad_F vanishes outside the band (e.g. a loss behind a pupil).  The
+ * workspace of fcfs_workspace_size(adjoint = 1) always suffices.
+ * FCFS_ERR_INVALID_ARG for a negative kmax or lmax or a NaN radius. */
 fcfs_status fcfs_adjoint_band(fcfs_handle *h, const fcfs_clip *c, const float *grad_F,
-                              int32_t kmax, int32_t lmax, float *gx, float *gy, fcfs_precision p,
-                              void *ws, size_t ws_bytes);
+                              int32_t kmax, int32_t lmax, double radius, float *gx, float *gy,
+                              fcfs_precision p, void *ws, size_t ws_bytes);
 
 /* Edge-offset gradient: a shift of edge e moves both of its endpoints (along
  * x for a vertical edge, along y for a horizontal one), so

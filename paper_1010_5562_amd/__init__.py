@@ -174,11 +174,14 @@ def _corners_on(dev, x, y, s):
 
 
 def forward(x, y, s, T: int, K: int, L: int | None = None, precision="bf16", handle=None,
-            out=None, area_out=None, tile: int | None = None):
+            out=None, area_out=None, tile: int | None = None, band=None, radius=None):
     """CFS coefficients F[k, l], |k| <= K, |l| <= L, of a signed corner list.
 
     Returns ``(F, area)``: F a (2K+1, 2L+1) complex64 tensor indexed
     [k + K, l + L], area a 1-element int64 tensor (exact sum s x y).
+    ``band=(kmax, lmax)`` and/or ``radius`` restrict the computation to
+    |k| <= kmax, |l| <= lmax and k^2 + l^2 <= radius^2 (``fcfs_forward_band``);
+    the other entries of F are zero.
     """
     import torch
 
@@ -195,12 +198,23 @@ def forward(x, y, s, T: int, K: int, L: int | None = None, precision="bf16", han
     if tile is not None:
         h.set_tile(tile)
     try:
-        nbytes = workspace_size(V, T, K, L, precision, tile=tile)
-        ws = h.workspace(nbytes)
         c = _clip(x, y, s, V, T, K, L, F, area)
-        check(h.lib.fcfs_forward(h.ptr, ctypes.byref(c), _prec(precision),
-                                 ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel())),
-              h.ptr)
+        if band is None and radius is None:
+            nbytes = workspace_size(V, T, K, L, precision, tile=tile)
+            ws = h.workspace(nbytes)
+            check(h.lib.fcfs_forward(h.ptr, ctypes.byref(c), _prec(precision),
+                                     ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel())),
+                  h.ptr)
+        else:
+            kmax, lmax = (K, L) if band is None else (int(band[0]), int(band[1]))
+            rad = -1.0 if radius is None else float(radius)
+            nb = ctypes.c_size_t(0)
+            check(h.lib.fcfs_band_workspace_size(ctypes.byref(c), kmax, lmax, rad,
+                                                 _prec(precision), ctypes.byref(nb)))
+            ws = h.workspace(nb.value)
+            check(h.lib.fcfs_forward_band(h.ptr, ctypes.byref(c), kmax, lmax, rad,
+                                          _prec(precision), ctypes.c_void_p(ws.data_ptr()),
+                                          ctypes.c_size_t(ws.numel())), h.ptr)
     finally:
         if tile is not None:
             h.set_tile(-1)
@@ -223,10 +237,13 @@ def debug_phases(x, y, s, T: int, k0: int, nk: int, axis: int = 0, handle=None):
     return p
 
 
-def adjoint(x, y, s, T: int, K: int, L: int, grad_F, precision="bf16", band=None, handle=None):
+def adjoint(x, y, s, T: int, K: int, L: int, grad_F, precision="bf16", band=None, handle=None,
+            radius=None):
     """dLoss/dx_v and dLoss/dy_v for a cotangent grad_F = dLoss/dRe F + j dLoss/dIm F
-    ((2K+1, 2L+1) complex64).  band = (kmax, lmax) restricts the work to where
-    grad_F can be nonzero.  Returns (gx, gy) float32 tensors of length V."""
+    ((2K+1, 2L+1) complex64).  band = (kmax, lmax) and radius restrict the work
+    (and the entries of grad_F used) to |k| <= kmax, |l| <= lmax,
+    k^2 + l^2 <= radius^2: the adjoint of ``forward`` with the same band and
+    radius.  Returns (gx, gy) float32 tensors of length V."""
     import torch
 
     h = handle or default_handle()
@@ -242,8 +259,9 @@ def adjoint(x, y, s, T: int, K: int, L: int, grad_F, precision="bf16", band=None
     nbytes = workspace_size(V, T, K, L, precision, adjoint=True)
     ws = h.workspace(nbytes)
     c = _clip(x, y, s, V, T, K, L)
+    rad = -1.0 if radius is None else float(radius)
     check(h.lib.fcfs_adjoint_band(h.ptr, ctypes.byref(c), ctypes.c_void_p(G.data_ptr()), kmax, lmax,
-                                  ctypes.c_void_p(gx.data_ptr()), ctypes.c_void_p(gy.data_ptr()),
+                                  rad, ctypes.c_void_p(gx.data_ptr()), ctypes.c_void_p(gy.data_ptr()),
                                   _prec(precision), ctypes.c_void_p(ws.data_ptr()),
                                   ctypes.c_size_t(ws.numel())), h.ptr)
     return gx, gy
@@ -311,14 +329,17 @@ def _autograd_function():
 
     class FCFSFunction(torch.autograd.Function):
         """F = FCFS(geometry moved by integer edge offsets); backward runs the
-        adjoint kernels and the edge reduction."""
+        adjoint kernels and the edge reduction.  With ``band`` and/or
+        ``radius`` the forward returns the low-pass spectrum (zero outside
+        |k| <= kmax, |l| <= lmax, k^2 + l^2 <= radius^2) and the backward is
+        its exact adjoint."""
 
         @staticmethod
-        def forward(ctx, offsets, geom, precision="bf16", band=None):
+        def forward(ctx, offsets, geom, precision="bf16", band=None, radius=None):
             x, y = geom.corners(offsets)
             F, _ = forward(x, y, geom.s, geom.T, geom.K, geom.L, precision=precision,
-                           handle=geom.handle)
-            ctx.geom, ctx.precision, ctx.band = geom, precision, band
+                           handle=geom.handle, band=band, radius=radius)
+            ctx.geom, ctx.precision, ctx.band, ctx.radius = geom, precision, band, radius
             ctx.save_for_backward(x, y)
             return F
 
@@ -327,9 +348,9 @@ def _autograd_function():
             x, y = ctx.saved_tensors
             g = ctx.geom
             gx, gy = adjoint(x, y, g.s, g.T, g.K, g.L, grad_F.contiguous(), ctx.precision,
-                             band=ctx.band, handle=g.handle)
+                             band=ctx.band, handle=g.handle, radius=ctx.radius)
             ge = edge_grad(gx, gy, g.hedge, g.vedge, g.n_edges, handle=g.handle)
-            return ge, None, None, None
+            return ge, None, None, None, None
 
     return FCFSFunction
 

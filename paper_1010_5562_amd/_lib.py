@@ -28,7 +28,8 @@ STATUS_NAMES = {
 # Every symbol include/fcfs.h declares.
 EXPORTS = (
     "fcfs_create", "fcfs_destroy", "fcfs_set_stream", "fcfs_loops_to_corners",
-    "fcfs_workspace_size", "fcfs_forward", "fcfs_adjoint", "fcfs_adjoint_band", "fcfs_edge_grad",
+    "fcfs_workspace_size", "fcfs_forward", "fcfs_band_workspace_size", "fcfs_forward_band",
+    "fcfs_adjoint", "fcfs_adjoint_band", "fcfs_edge_grad",
     "fcfs_apply_edge_offsets", "fcfs_batch_workspace_size", "fcfs_forward_batch", "fcfs_plan_destroy",
     "fcfs_debug_phases", "fcfs_autotune", "fcfs_load_tune", "fcfs_tile_variants", "fcfs_set_tile",
     "fcfs_workspace_size_tile", "fcfs_profile_begin", "fcfs_profile_end",
@@ -80,8 +81,11 @@ def load() -> ctypes.CDLL:
         "fcfs_workspace_size": [clip_p, c_int, c_int, sz],
         "fcfs_workspace_size_tile": [clip_p, c_int, i32, sz],
         "fcfs_forward": [P, clip_p, c_int, P, ctypes.c_size_t],
+        "fcfs_band_workspace_size": [clip_p, i32, i32, ctypes.c_double, c_int, sz],
+        "fcfs_forward_band": [P, clip_p, i32, i32, ctypes.c_double, c_int, P, ctypes.c_size_t],
         "fcfs_adjoint": [P, clip_p, P, P, P, c_int, P, ctypes.c_size_t],
-        "fcfs_adjoint_band": [P, clip_p, P, i32, i32, P, P, c_int, P, ctypes.c_size_t],
+        "fcfs_adjoint_band": [P, clip_p, P, i32, i32, ctypes.c_double, P, P, c_int, P,
+                              ctypes.c_size_t],
         "fcfs_edge_grad": [P, P, P, P, P, i64, i64, P],
         "fcfs_apply_edge_offsets": [P, P, P, P, P, P, i64, P, P],
         "fcfs_batch_workspace_size": [clip_p, i32, c_int, sz],

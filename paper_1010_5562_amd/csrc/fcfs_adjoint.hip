@@ -38,7 +38,8 @@ __device__ __forceinline__ size_t rec_index(int n, int r, int lb, int ncb) {
 // ---------------------------------------------------------------------------
 template <bool DIRECT>
 __global__ __launch_bounds__(256) void k_adj_w(const float2 *__restrict__ G, int K, int L, int kmax,
-                                               int lmax, int kb, int lb, float *__restrict__ Wf,
+                                               int lmax, double r2, int kb, int lb,
+                                               float *__restrict__ Wf,
                                                unsigned int *__restrict__ wmax,
                                                uint16_t *__restrict__ whi,
                                                uint16_t *__restrict__ wlo,
@@ -49,7 +50,7 @@ __global__ __launch_bounds__(256) void k_adj_w(const float2 *__restrict__ G, int
   const bool live = l <= lb;
   const int R = 2 * kb;
   double Wcc = 0, Wcs = 0, Wsc = 0, Wss = 0, Ycc = 0, Ycs = 0, Ysc = 0, Yss = 0;
-  if (live && k <= kmax && l <= lmax) {
+  if (live && k <= kmax && l <= lmax && (r2 < 0.0 || (double)k * k + (double)l * l <= r2)) {
     const size_t WL = 2 * (size_t)L + 1;
     const float2 gpp = G[(size_t)(K + k) * WL + (L + l)];  // G[k, l]
     const float2 gmm = G[(size_t)(K - k) * WL + (L - l)];  // G[-k, -l]
@@ -488,12 +489,12 @@ hipError_t launch_adjoint(const AdjPlan &a, const int32_t *x, const int32_t *y, 
   if (a.kmax == 0 || a.lmax == 0 || a.V == 0) return hipGetLastError();
   const dim3 wgrid((a.lb + 255) / 256, a.kb);
   if (a.prec == kBF16) {
-    hipLaunchKernelGGL(k_adj_w<true>, wgrid, dim3(256), 0, st, G, a.K, a.L, a.kmax, a.lmax, a.kb,
-                       a.lb, Wf, wmax, whi, wlo, scale);
+    hipLaunchKernelGGL(k_adj_w<true>, wgrid, dim3(256), 0, st, G, a.K, a.L, a.kmax, a.lmax, a.r2,
+                       a.kb, a.lb, Wf, wmax, whi, wlo, scale);
   } else {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, wmax, 1, 0u);
     hipLaunchKernelGGL(k_adj_w<false>, wgrid, dim3(256), 0, st, G, a.K, a.L, a.kmax, a.lmax,
-                       a.kb, a.lb, Wf, wmax, whi, wlo, scale);
+                       a.r2, a.kb, a.lb, Wf, wmax, whi, wlo, scale);
   }
   const unsigned blocks = (unsigned)(a.vpad / 128);                     // FP32 form
   const unsigned sblocks = (unsigned)(a.vpad / (32 * kAdjWaves));      // split forms

@@ -227,8 +227,10 @@ fcfs_status check_dims(fcfs_handle *h, int64_t V, int T, int K, int L, int prec)
   return FCFS_OK;
 }
 
+// r2 >= 0: only the pupil k^2 + l^2 <= r2 is kept (tiles wholly outside it
+// are skipped and the split count is sized for the remaining ones).
 fcfs_status make_plan(fcfs_handle *h, int64_t V, int T, int K, int L, int prec, int tile,
-                      FwdPlan *p) {
+                      FwdPlan *p, double r2 = -1.0) {
   fcfs_status st = check_dims(h, V, T, K, L, prec);
   if (st) return st;
   FwdPlan q{};
@@ -236,6 +238,9 @@ fcfs_status make_plan(fcfs_handle *h, int64_t V, int T, int K, int L, int prec, 
   q.T = T;
   q.K = K;
   q.L = L;
+  q.KO = K;
+  q.LO = L;
+  q.r2 = r2;
   q.V = V;
   q.shift = fcfs::kTabBits - (int)std::lround(std::log2((double)T));
   if (tile < 0) tile = default_tile(h, prec, std::max(K, L), V);
@@ -250,7 +255,16 @@ fcfs_status make_plan(fcfs_handle *h, int64_t V, int T, int K, int L, int prec, 
   q.lp = (int)round_up(L + 1, q.wgl);
   q.tiles_k = q.kp / q.wgk;
   q.tiles_l = q.lp / q.wgl;
-  const int64_t tiles = (int64_t)q.tiles_k * q.tiles_l;
+  int64_t tiles = (int64_t)q.tiles_k * q.tiles_l;
+  if (r2 >= 0.0) {  // tiles the pupil reaches (same test as the kernels)
+    int64_t active = 0;
+    for (int tk = 0; tk < q.tiles_k; ++tk)
+      for (int tl = 0; tl < q.tiles_l; ++tl) {
+        const double k0 = (double)tk * q.wgk, l0 = (double)tl * q.wgl;
+        active += k0 * k0 + l0 * l0 <= r2;
+      }
+    tiles = std::max<int64_t>(1, active);
+  }
   // one wave of workgroups over the CUs, but at least 512 corners per split
   int64_t ns = ceil_div((int64_t)kCUs * tv.wg_per_cu, tiles);
   const int64_t ns_max = std::max<int64_t>(1, ceil_div(V, 512));
@@ -296,6 +310,7 @@ fcfs_status make_adj_plan(fcfs_handle *h, int64_t V, int T, int K, int L, int km
   if (st) return st;
   if (kmax < 0 || lmax < 0) return fail(h, FCFS_ERR_INVALID_ARG, "band must be >= 0");
   fcfs::AdjPlan a{};
+  a.r2 = -1.0;
   a.prec = prec;
   a.T = T;
   a.K = K;
@@ -662,6 +677,42 @@ fcfs_status fcfs_forward(fcfs_handle *h, const fcfs_clip *c, fcfs_precision p, v
   return run_forward(h, c, q, ws);
 }
 
+namespace {
+fcfs_status make_band_plan(fcfs_handle *h, const fcfs_clip *c, int32_t kmax, int32_t lmax,
+                           double radius, int prec, int tile, FwdPlan *q) {
+  if (kmax < 0 || lmax < 0) return fail(h, FCFS_ERR_INVALID_ARG, "band must be >= 0");
+  if (!(radius == radius)) return fail(h, FCFS_ERR_INVALID_ARG, "radius is NaN");
+  const int kb = std::min(kmax, c->K), lb = std::min(lmax, c->L);
+  const double r2 = radius >= 0.0 ? radius * radius : -1.0;
+  fcfs_status st = make_plan(h, c->V, c->T, kb, lb, prec, tile, q, r2);
+  if (st) return st;
+  q->KO = c->K;
+  q->LO = c->L;
+  return FCFS_OK;
+}
+}  // namespace
+
+fcfs_status fcfs_band_workspace_size(const fcfs_clip *c, int32_t kmax, int32_t lmax,
+                                     double radius, fcfs_precision p, size_t *bytes) {
+  if (!c || !bytes) return fail(nullptr, FCFS_ERR_INVALID_ARG, "NULL argument");
+  FwdPlan q;
+  fcfs_status st = make_band_plan(nullptr, c, kmax, lmax, radius, (int)p, -1, &q);
+  if (st) return st;
+  *bytes = q.bytes;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_forward_band(fcfs_handle *h, const fcfs_clip *c, int32_t kmax, int32_t lmax,
+                              double radius, fcfs_precision p, void *ws, size_t ws_bytes) {
+  fcfs_status st = enter(h);
+  if (st) return st;
+  if ((st = check_clip(h, c, true))) return st;
+  FwdPlan q;
+  if ((st = make_band_plan(h, c, kmax, lmax, radius, (int)p, h->tile_override, &q))) return st;
+  if ((st = check_ws(h, q, ws, ws_bytes))) return st;
+  return run_forward(h, c, q, ws);
+}
+
 fcfs_status fcfs_debug_phases(fcfs_handle *h, const fcfs_clip *c, int32_t axis, int32_t k0,
                               int32_t nk, int32_t *p) {
   fcfs_status st = enter(h);
@@ -688,15 +739,22 @@ fcfs_status fcfs_debug_phases(fcfs_handle *h, const fcfs_clip *c, int32_t axis, 
 }
 
 fcfs_status fcfs_adjoint_band(fcfs_handle *h, const fcfs_clip *c, const float *grad_F,
-                              int32_t kmax, int32_t lmax, float *gx, float *gy, fcfs_precision p,
-                              void *ws, size_t ws_bytes) {
+                              int32_t kmax, int32_t lmax, double radius, float *gx, float *gy,
+                              fcfs_precision p, void *ws, size_t ws_bytes) {
   fcfs_status st = enter(h);
   if (st) return st;
   if ((st = check_clip(h, c, false))) return st;
   if (!grad_F) return fail(h, FCFS_ERR_INVALID_ARG, "grad_F is NULL");
   if (c->V > 0 && (!gx || !gy)) return fail(h, FCFS_ERR_INVALID_ARG, "gx/gy are NULL");
+  if (!(radius == radius)) return fail(h, FCFS_ERR_INVALID_ARG, "radius is NaN");
+  if (radius >= 0.0) {  // the disc also bounds the band
+    const double rf = std::floor(radius);
+    kmax = (int32_t)std::min<double>(kmax, rf);
+    lmax = (int32_t)std::min<double>(lmax, rf);
+  }
   fcfs::AdjPlan a;
   if ((st = make_adj_plan(h, c->V, c->T, c->K, c->L, kmax, lmax, (int)p, &a))) return st;
+  a.r2 = radius >= 0.0 ? radius * radius : -1.0;
   if (ws_bytes < a.bytes)
     return fail(h, FCFS_ERR_WORKSPACE,
                 "workspace too small: need " + std::to_string(a.bytes) + " bytes, got " +
@@ -723,7 +781,7 @@ fcfs_status fcfs_adjoint_band(fcfs_handle *h, const fcfs_clip *c, const float *g
 fcfs_status fcfs_adjoint(fcfs_handle *h, const fcfs_clip *c, const float *grad_F, float *gx,
                          float *gy, fcfs_precision p, void *ws, size_t ws_bytes) {
   if (!c) return fail(h, FCFS_ERR_INVALID_ARG, "clip is NULL");
-  return fcfs_adjoint_band(h, c, grad_F, c->K, c->L, gx, gy, p, ws, ws_bytes);
+  return fcfs_adjoint_band(h, c, grad_F, c->K, c->L, -1.0, gx, gy, p, ws, ws_bytes);
 }
 
 fcfs_status fcfs_edge_grad(fcfs_handle *h, const float *gx, const float *gy, const int64_t *hedge,

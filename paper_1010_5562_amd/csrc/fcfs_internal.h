@@ -42,7 +42,9 @@ struct Tables {
 // from (V, T, K, L, precision) alone.
 struct FwdPlan {
   int prec;
-  int T, K, L;
+  int T, K, L;       // period and computed band |k| <= K, |l| <= L
+  int KO, LO;        // output grid (2 KO + 1) x (2 LO + 1), KO >= K, LO >= L
+  double r2;         // pupil: entries with k^2 + l^2 > r2 written as zero (< 0: none)
   int64_t V;
   int shift;         // log2(8192 / T)
   int tile;          // contraction tile variant id
@@ -85,6 +87,7 @@ hipError_t launch_debug_phases(const FwdPlan &p, const uint4 *packed, int axis, 
 struct AdjPlan {
   int prec;
   int T, K, L, kmax, lmax;
+  double r2;         // pupil k^2 + l^2 <= r2 (< 0: none)
   int64_t V;
   int shift;
   int kb, lb;        // kmax, lmax padded to multiples of 16 and 32

@@ -250,6 +250,15 @@ hipError_t launch_side(const FwdPlan &p, const int32_t *x, const int32_t *y, con
   return hipGetLastError();
 }
 
+// A frequency tile whose corner nearest the origin lies outside the pupil
+// k^2 + l^2 <= r2 (r2 >= 0) holds only coefficients the epilogue writes as zero:
+// its workgroups return at once.
+__device__ __forceinline__ bool tile_outside(int tile, int tiles_l, int wgk, int wgl, double r2) {
+  if (r2 < 0.0) return false;
+  const double k0 = (double)(tile / tiles_l) * wgk, l0 = (double)(tile % tiles_l) * wgl;
+  return k0 * k0 + l0 * l0 > r2;
+}
+
 // ---------------------------------------------------------------------------
 // Vertex contraction (Step 4) in real-trigonometric form:
 //   Z = X diag(s) Y^T,  X = [cos; sin](2 pi k x_v / T), Y likewise in l,
@@ -354,7 +363,8 @@ template <int PREC, int NKB, int NLB>
 __global__ __launch_bounds__(256) void k_contract_split(const uint4 *__restrict__ packed,
                                                         const uint2 *__restrict__ tab,
                                                         int64_t chunk, int tiles_l, int kp,
-                                                        int lp, float *__restrict__ part) {
+                                                        int lp, float *__restrict__ part, double r2) {
+  if (tile_outside(blockIdx.x, tiles_l, 64 * NKB, 64 * NLB, r2)) return;
   __shared__ uint2 s_tab[kTabEntries];
   for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
   __syncthreads();
@@ -470,7 +480,8 @@ __global__ __launch_bounds__(256, 2) void k_contract_split_lean(const uint4 *__r
                                                                 const uint2 *__restrict__ tab,
                                                                 int64_t chunk, int tiles_l,
                                                                 int kp, int lp,
-                                                                float *__restrict__ part) {
+                                                                float *__restrict__ part, double r2) {
+  if (tile_outside(blockIdx.x, tiles_l, 64 * NKB, 64 * NLB, r2)) return;
   __shared__ uint2 s_tab[kTabEntries];
   for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
   __syncthreads();
@@ -559,7 +570,8 @@ __global__ __launch_bounds__(256, 1) void k_contract_split_pipe(const uint4 *__r
                                                                 const uint2 *__restrict__ tab,
                                                                 int64_t chunk, int tiles_l,
                                                                 int kp, int lp,
-                                                                float *__restrict__ part) {
+                                                                float *__restrict__ part, double r2) {
+  if (tile_outside(blockIdx.x, tiles_l, 128, 128, r2)) return;
   __shared__ uint2 s_tab[kTabEntries];
   for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
   __syncthreads();
@@ -629,7 +641,8 @@ template <int NKB, int NLB>
 __global__ __launch_bounds__(256) void k_contract_fp32(const uint4 *__restrict__ packed,
                                                        const float2 *__restrict__ tab,
                                                        int64_t chunk, int tiles_l, int kp, int lp,
-                                                       float *__restrict__ part) {
+                                                       float *__restrict__ part, double r2) {
+  if (tile_outside(blockIdx.x, tiles_l, 64 * NKB, 64 * NLB, r2)) return;
   __shared__ float2 s_tab[kTabEntries];
   for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
   __syncthreads();
@@ -657,21 +670,21 @@ static void launch_contract_t(const FwdPlan &p, const uint4 *packed, const Table
   dim3 grid(p.tiles_k * p.tiles_l, p.nsplit), block(256);
   if (p.prec == kFP32) {
     hipLaunchKernelGGL((k_contract_fp32<NKB, NLB>), grid, block, 0, st, packed, t.w32, p.chunk,
-                       p.tiles_l, p.kp, p.lp, part);
+                       p.tiles_l, p.kp, p.lp, part, p.r2);
   } else if constexpr (PIPE) {
     if (p.prec == kBF16)
       hipLaunchKernelGGL((k_contract_split<kBF16, NKB, NLB>), grid, block, 0, st, packed,
-                         t.wbf16, p.chunk, p.tiles_l, p.kp, p.lp, part);
+                         t.wbf16, p.chunk, p.tiles_l, p.kp, p.lp, part, p.r2);
     else
       hipLaunchKernelGGL((k_contract_split<kFP16, NKB, NLB>), grid, block, 0, st, packed,
-                         t.wfp16, p.chunk, p.tiles_l, p.kp, p.lp, part);
+                         t.wfp16, p.chunk, p.tiles_l, p.kp, p.lp, part, p.r2);
   } else {
     if (p.prec == kBF16)
       hipLaunchKernelGGL((k_contract_split_lean<kBF16, NKB, NLB>), grid, block, 0, st, packed,
-                         t.wbf16, p.chunk, p.tiles_l, p.kp, p.lp, part);
+                         t.wbf16, p.chunk, p.tiles_l, p.kp, p.lp, part, p.r2);
     else
       hipLaunchKernelGGL((k_contract_split_lean<kFP16, NKB, NLB>), grid, block, 0, st, packed,
-                         t.wfp16, p.chunk, p.tiles_l, p.kp, p.lp, part);
+                         t.wfp16, p.chunk, p.tiles_l, p.kp, p.lp, part, p.r2);
   }
 }
 
@@ -687,10 +700,10 @@ hipError_t launch_contract(const FwdPlan &p, const uint4 *packed, const Tables &
       const dim3 grid(p.tiles_k * p.tiles_l, p.nsplit), block(256);
       if (p.prec == kBF16)
         hipLaunchKernelGGL(k_contract_split_pipe<kBF16>, grid, block, 0, st, packed, t.wbf16,
-                           p.chunk, p.tiles_l, p.kp, p.lp, part);
+                           p.chunk, p.tiles_l, p.kp, p.lp, part, p.r2);
       else if (p.prec == kFP16)
         hipLaunchKernelGGL(k_contract_split_pipe<kFP16>, grid, block, 0, st, packed, t.wfp16,
-                           p.chunk, p.tiles_l, p.kp, p.lp, part);
+                           p.chunk, p.tiles_l, p.kp, p.lp, part, p.r2);
       else
         return hipErrorInvalidValue;
       break;
@@ -710,21 +723,35 @@ hipError_t launch_contract(const FwdPlan &p, const uint4 *packed, const Tables &
 // contraction grid (blocks [0, nmain), the guard block's entries excepted),
 // the axes and DC (the next nax blocks) and the guard block (the last one).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void store_quad(float2 *__restrict__ F, int K, int L, int k, int l,
-                                           double T, double P, double U, double R, double Q) {
+// Output grid of one clip: F holds (2 KO + 1) x (2 LO + 1) coefficients,
+// k-major, index (KO + k)(2 LO + 1) + (LO + l).  It may be larger than the
+// computed band |k| <= K, |l| <= L (the rest is cleared beforehand); with
+// r2 >= 0 the entries with k^2 + l^2 > r2 are written as zero (a pupil).
+struct OutGrid {
+  float2 *F;
+  int KO, LO;
+  double r2;
+};
+
+__device__ __forceinline__ void put(const OutGrid &o, int k, int l, float re, float im) {
+  if (o.r2 >= 0.0 && (double)k * k + (double)l * l > o.r2) re = im = 0.0f;
+  o.F[(size_t)(o.KO + k) * (2 * (size_t)o.LO + 1) + (o.LO + l)] = make_float2(re, im);
+}
+
+__device__ __forceinline__ void store_quad(const OutGrid &o, int k, int l, double T, double P,
+                                           double U, double R, double Q) {
   const double a = -T / (4.0 * kPi * kPi * (double)k * (double)l);
   const double pre = a * (P - Q), pim = -a * (R + U);  // F[k, l]
   const double mre = -a * (P + Q), mim = a * (R - U);  // F[k, -l]
-  const size_t W = 2 * (size_t)L + 1;
-  F[(size_t)(K + k) * W + (L + l)] = make_float2((float)pre, (float)pim);
-  F[(size_t)(K - k) * W + (L - l)] = make_float2((float)pre, (float)-pim);
-  F[(size_t)(K + k) * W + (L - l)] = make_float2((float)mre, (float)mim);
-  F[(size_t)(K - k) * W + (L + l)] = make_float2((float)mre, (float)-mim);
+  put(o, k, l, (float)pre, (float)pim);
+  put(o, -k, -l, (float)pre, (float)-pim);
+  put(o, k, -l, (float)mre, (float)mim);
+  put(o, -k, l, (float)mre, (float)-mim);
 }
 
 __device__ __forceinline__ void epilogue_body(const float *__restrict__ part, int nsplit, int kp,
-                                              int lp, int K, int L, double T,
-                                              float2 *__restrict__ F, int bx, int by) {
+                                              int lp, int K, int L, double T, const OutGrid &o,
+                                              int bx, int by) {
   // 64 consecutive l per block, 4 threads per l summing splits q, q+4, ...
   __shared__ double4 red[4][64];
   const int t = threadIdx.x & 63, q = threadIdx.x >> 6;
@@ -751,19 +778,19 @@ __device__ __forceinline__ void epilogue_body(const float *__restrict__ part, in
     R += red[w][t].z;
     Q += red[w][t].w;
   }
-  store_quad(F, K, L, k, l, T, P, U, R, Q);
+  store_quad(o, k, l, T, P, U, R, Q);
 }
 
 // Guard block entries from the final 16 x 16 sums D (row-major):
 // P = D[k-1][l-1], U = D[k-1][8+l-1], R = D[8+k-1][l-1], Q = D[8+k-1][8+l-1].
 __device__ __forceinline__ void guard_store(const double *__restrict__ gfinal, int K, int L,
-                                            double T, float2 *__restrict__ F) {
+                                            double T, const OutGrid &o) {
   const int t = threadIdx.x;
   if (t >= kGuard * kGuard) return;
   const int k = 1 + t / kGuard, l = 1 + t % kGuard;
   if (k > K || l > L) return;
   const double *d = gfinal;
-  store_quad(F, K, L, k, l, T, d[(k - 1) * 16 + (l - 1)], d[(k - 1) * 16 + 8 + (l - 1)],
+  store_quad(o, k, l, T, d[(k - 1) * 16 + (l - 1)], d[(k - 1) * 16 + 8 + (l - 1)],
              d[(8 + k - 1) * 16 + (l - 1)], d[(8 + k - 1) * 16 + 8 + (l - 1)]);
 }
 
@@ -775,12 +802,11 @@ __device__ __forceinline__ void guard_store(const double *__restrict__ gfinal, i
 __device__ __forceinline__ void epilogue_axes_body(const double2 *__restrict__ axis_part,
                                                    int ax_chunks, int K, int L, double T,
                                                    const unsigned long long *__restrict__ area_part,
-                                                   int pre_blocks, float2 *__restrict__ F,
+                                                   int pre_blocks, const OutGrid &o,
                                                    int64_t *__restrict__ area, int bx) {
   __shared__ double2 red[16][16];
   const int t = threadIdx.x & 15, q = threadIdx.x >> 4;
   const int i = bx * 16 + t;
-  const size_t W = 2 * (size_t)L + 1;
   const int nslot = K + L;
   double re = 0.0, im = 0.0;
   if (i < nslot)
@@ -800,11 +826,11 @@ __device__ __forceinline__ void epilogue_axes_body(const double2 *__restrict__ a
     const double sc = 1.0 / (2.0 * kPi * (double)f);
     const float fre = (float)(-im * sc), fim = (float)(re * sc);
     if (i < K) {
-      F[(size_t)(K + f) * W + L] = make_float2(fre, fim);
-      F[(size_t)(K - f) * W + L] = make_float2(fre, -fim);
+      put(o, f, 0, fre, fim);
+      put(o, -f, 0, fre, -fim);
     } else {
-      F[(size_t)K * W + (L + f)] = make_float2(fre, fim);
-      F[(size_t)K * W + (L - f)] = make_float2(fre, -fim);
+      put(o, 0, f, fre, fim);
+      put(o, 0, -f, fre, -fim);
     }
   }
   if (bx == 0 && threadIdx.x >= 64 && threadIdx.x < 128) {
@@ -814,7 +840,7 @@ __device__ __forceinline__ void epilogue_axes_body(const double2 *__restrict__ a
     for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
     if (a0 == 0) {
       const long long A = (long long)a;
-      F[(size_t)K * W + L] = make_float2((float)((double)A / T), 0.0f);
+      put(o, 0, 0, (float)((double)A / T), 0.0f);
       if (area) *area = A;
     }
   }
@@ -827,18 +853,18 @@ __device__ __forceinline__ void epilogue_block(const float *__restrict__ part, i
                                                int ax_chunks,
                                                const unsigned long long *__restrict__ area_part,
                                                int pre_blocks, const double *__restrict__ gfinal,
-                                               float2 *__restrict__ F, int64_t *__restrict__ area,
+                                               const OutGrid &o, int64_t *__restrict__ area,
                                                int b) {
   const bool grid2d = K > 0 && L > 0;
   const int nbx = (L + 63) / 64;
   const int nmain = grid2d ? nbx * K : 0;
   const int nax = max(1, (K + L + 15) / 16);
   if (b < nmain)
-    epilogue_body(part, nsplit, kp, lp, K, L, T, F, b % nbx, b / nbx);
+    epilogue_body(part, nsplit, kp, lp, K, L, T, o, b % nbx, b / nbx);
   else if (b < nmain + nax)
-    epilogue_axes_body(axis_part, ax_chunks, K, L, T, area_part, pre_blocks, F, area, b - nmain);
+    epilogue_axes_body(axis_part, ax_chunks, K, L, T, area_part, pre_blocks, o, area, b - nmain);
   else if (grid2d)
-    guard_store(gfinal, K, L, T, F);
+    guard_store(gfinal, K, L, T, o);
 }
 
 int epilogue_block_count(int K, int L) {
@@ -854,20 +880,31 @@ __global__ __launch_bounds__(256) void k_epilogue(const float *__restrict__ part
                                                   const unsigned long long *__restrict__ area_part,
                                                   int pre_blocks,
                                                   const double *__restrict__ gfinal,
-                                                  float2 *__restrict__ F,
-                                                  int64_t *__restrict__ area) {
+                                                  OutGrid o, int64_t *__restrict__ area) {
   epilogue_block(part, nsplit, kp, lp, K, L, T, axis_part, ax_chunks, area_part, pre_blocks,
-                 gfinal, F, area, blockIdx.x);
+                 gfinal, o, area, blockIdx.x);
+}
+
+// Clears the output grid (band forward: entries outside the computed band).
+__global__ __launch_bounds__(256) void k_zero_grid(float2 *__restrict__ F, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    F[i] = make_float2(0.0f, 0.0f);
 }
 
 hipError_t launch_epilogue(const FwdPlan &p, const void *ws, float *F, int64_t *area,
                            hipStream_t st) {
   const char *w = (const char *)ws;
+  const OutGrid o{(float2 *)F, p.KO, p.LO, p.r2};
+  if (p.KO > p.K || p.LO > p.L) {
+    const int64_t n = (2 * (int64_t)p.KO + 1) * (2 * (int64_t)p.LO + 1);
+    hipLaunchKernelGGL(k_zero_grid, dim3((unsigned)std::min<int64_t>(2048, (n + 255) / 256)),
+                       dim3(256), 0, st, (float2 *)F, n);
+  }
   hipLaunchKernelGGL(k_epilogue, dim3(epilogue_block_count(p.K, p.L)), dim3(256), 0, st,
                      (const float *)(w + p.off_part), p.nsplit, p.kp, p.lp, p.K, p.L, (double)p.T,
                      (const double2 *)(w + p.off_axis), p.ax_chunks,
                      (const unsigned long long *)(w + p.off_area), p.pre_blocks,
-                     (const double *)(w + p.off_gfinal), (float2 *)F, area);
+                     (const double *)(w + p.off_gfinal), o, area);
   return hipGetLastError();
 }
 
@@ -1016,8 +1053,9 @@ __global__ __launch_bounds__(256) void k_batch_epilogue(const BatchClip *__restr
                                                         int pre_blocks) {
   const int ci = owner(off, n, blockIdx.x);
   const BatchClip &c = clips[ci];
+  const OutGrid o{c.F, c.K, c.L, -1.0};
   epilogue_block(c.part, c.nsplit, c.kp, c.lp, c.K, c.L, (double)c.T, c.axis_part, c.ax_chunks,
-                 c.area_part, pre_blocks, c.gfinal, c.F, c.area, blockIdx.x - off[ci]);
+                 c.area_part, pre_blocks, c.gfinal, o, c.area, blockIdx.x - off[ci]);
 }
 
 hipError_t launch_batch_prepass(const BatchLaunch &b, hipStream_t st) {

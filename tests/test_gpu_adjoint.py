@@ -131,3 +131,28 @@ def test_autograd_function(P, oracle_lib):
     assert int((x.cpu() - geom.base_x.cpu()).abs().sum() + (y.cpu() - geom.base_y.cpu()).abs().sum()) == 6
     with pytest.raises(P.FcfsError):
         geom.corners(shift + 0.5)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_autograd_low_pass(P, oracle_lib, prec):
+    # FCFSFunction with a band and a disc: F is the low-pass spectrum M F and
+    # the gradient of sum |M F|^2 is the adjoint of M (2 M F)
+    T, K = 512, 40
+    r = 17.5
+    clip = synth.clip(44, T, K, n_polygons=30)
+    geom = P.Geometry(clip.xy, clip.off, T, K)
+    off = torch.zeros(geom.n_edges, dtype=torch.float32, device="cuda", requires_grad=True)
+    F = P.FCFSFunction.apply(off, geom, prec, (20, 20), r)
+    loss = (F.abs() ** 2).sum()
+    loss.backward()
+    Fo, _ = oracle_lib.cfs_grid(clip.xy, clip.off, T, K, K)
+    kk, ll = np.meshgrid(np.arange(-K, K + 1), np.arange(-K, K + 1), indexing="ij")
+    M = ((kk ** 2 + ll ** 2 <= r * r) & (np.abs(kk) <= 20) & (np.abs(ll) <= 20)).astype(np.float64)
+    Fm = F.detach().cpu().numpy().astype(np.complex128)
+    assert np.all(Fm[M == 0] == 0)
+    assert np.max(np.abs(Fm - M * Fo)) <= (1e-6 if prec == "fp32" else 1e-5) * abs(Fo[K, K])
+    want = oracle_lib.edge_grad(clip.xy, clip.off, T, K, K, 2 * M * Fo)
+    got = off.grad.cpu().numpy().astype(np.float64)
+    e = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+    _say(f"low-pass autograd {prec}: err/max|g| = {e:.3e}")
+    assert e <= GTOL[prec]

@@ -182,3 +182,47 @@ def test_disjoint_low_fill_clip(P, oracle_lib, prec):
     e = float(np.max(np.abs(F[kk + K, ll + K] - ref)) / abs(f00))
     _say(f"  fill {abs(f00) * T / T**2:.3f}, err/|F00| = {e:.3e}")
     assert e <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_band_forward(P, oracle_lib, prec):
+    # low-pass forward: |k| <= kmax, |l| <= lmax, optionally k^2 + l^2 <= r^2;
+    # the rest of the (2K+1)(2L+1) grid is zero
+    T, K, L = 1024, 150, 97
+    clip = synth.clip(31, T, K, L, n_polygons=211)
+    x, y, s = _corners(P, clip)
+    ref, _ = oracle_lib.cfs_grid(clip.xy, clip.off, T, K, L)
+    kk, ll = np.meshgrid(np.arange(-K, K + 1), np.arange(-L, L + 1), indexing="ij")
+    for band, radius in (((40, 70), None), ((K, L), 35.5), ((20, 60), 50.0), ((0, 30), None)):
+        _say(f"band {band} radius {radius} prec={prec}")
+        F, a = P.forward(x, y, s, T, K, L, precision=prec, band=band, radius=radius)
+        torch.cuda.synchronize()
+        F = F.cpu().numpy().astype(np.complex128)
+        inside = (np.abs(kk) <= band[0]) & (np.abs(ll) <= band[1])
+        if radius is not None:
+            inside &= kk ** 2 + ll ** 2 <= radius ** 2
+        assert np.all(F[~inside] == 0)
+        e = float(np.max(np.abs(F[inside] - ref[inside])) / abs(ref[K, L]))
+        _say(f"  err/|F00| = {e:.3e}")
+        assert e <= TOL[prec]
+
+
+def test_band_forward_skips_tiles_full_size(P, oracle_lib):
+    # precision clip with a disc of radius 200: the tiles beyond it are skipped
+    T, K = 8192, 511
+    clip = synth.clip(3, T, K, min_vertices=200_000)
+    x, y, s = _corners(P, clip)
+    r = 200.0
+    F, _ = P.forward(x, y, s, T, K, K, precision="bf16", radius=r)
+    torch.cuda.synchronize()
+    F = F.cpu().numpy()
+    kk, ll = _sample_points(K, K, 300, 4)
+    inside = kk ** 2 + ll ** 2 <= r * r
+    ref = oracle_lib.cfs_points(clip.xy, clip.off, T, kk[inside], ll[inside])
+    f00 = oracle_lib.cfs_points(clip.xy, clip.off, T, [0], [0])[0]
+    e = float(np.max(np.abs(F[kk[inside] + K, ll[inside] + K] - ref)) / abs(f00))
+    _say(f"disc r={r}: {int(inside.sum())} points inside, err/|F00| = {e:.3e}")
+    assert e <= TOL["bf16"]
+    assert np.all(F[kk[~inside] + K, ll[~inside] + K] == 0)
+    k2, l2 = np.meshgrid(np.arange(-K, K + 1), np.arange(-K, K + 1), indexing="ij")
+    assert np.all(F[k2 ** 2 + l2 ** 2 > r * r] == 0)
