@@ -133,6 +133,17 @@ fcfs_status fcfs_band_workspace_size(const fcfs_clip *c, int32_t kmax, int32_t l
 fcfs_status fcfs_forward_band(fcfs_handle *h, const fcfs_clip *c, int32_t kmax, int32_t lmax,
                               double radius, fcfs_precision p, void *ws, size_t ws_bytes);
 
+/* Lattice (FFT) form of the forward transform: the same coefficients as
+ * fcfs_forward, computed in FP64 from the corner image on the T x T lattice
+ * (Sec. III-C1, Step 4: a 2-D DFT of the image of corner signs) instead of
+ * the vertex contraction: a sparse DFT along y of every x-row's exact integer
+ * image for l = 1..L, then a radix-2 FFT of length T along x per l, cropped to
+ * |k| <= K; the axes and F[0,0] as in fcfs_forward.  Cost O(V L + L T log T),
+ * independent of the precision forms.  ws: at least fcfs_fft_workspace_size
+ * bytes (16 T L + 4 V + ... : ~68 MB at T = 8192, L = 511), 256-byte aligned. */
+fcfs_status fcfs_fft_workspace_size(const fcfs_clip *c, size_t *bytes);
+fcfs_status fcfs_forward_fft(fcfs_handle *h, const fcfs_clip *c, void *ws, size_t ws_bytes);
+
 /* Adjoint of fcfs_forward with respect to the corner coordinates (the
  * derivative of the four closed forms of Prop. 3 in x_v and y_v).
  * grad_F: (device) cotangent, same layout as c->F, holding

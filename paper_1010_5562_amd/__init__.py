@@ -123,7 +123,7 @@ class Handle:
     def set_tile(self, variant: int = -1):
         check(self.lib.fcfs_set_tile(self._h, int(variant)), self._h)
 
-    PROFILE_KINDS = ("prepass", "axis", "contract", "epilogue", "adjoint", "batch")
+    PROFILE_KINDS = ("prepass", "axis", "contract", "epilogue", "adjoint", "batch", "fft")
 
     def profile_begin(self, kinds=None):
         """Starts event timing of the named kinds (all kinds when None)."""
@@ -218,6 +218,31 @@ def forward(x, y, s, T: int, K: int, L: int | None = None, precision="bf16", han
     finally:
         if tile is not None:
             h.set_tile(-1)
+    return F, area
+
+
+def forward_fft(x, y, s, T: int, K: int, L: int | None = None, handle=None, out=None,
+                area_out=None):
+    """The same coefficients as ``forward`` from the lattice (FFT) form in FP64
+    (``fcfs_forward_fft``).  Returns ``(F, area)``."""
+    import torch
+
+    L = K if L is None else L
+    h = handle or default_handle()
+    h.sync_stream()
+    x, y, s = _corners_on(h.device, x, y, s)
+    V = x.numel()
+    F = out if out is not None else torch.empty((2 * K + 1, 2 * L + 1), dtype=torch.complex64,
+                                                device=h.device)
+    if F.dtype != torch.complex64 or F.numel() != (2 * K + 1) * (2 * L + 1) or not F.is_contiguous():
+        raise ValueError("out must be a contiguous complex64 tensor of (2K+1)(2L+1) entries")
+    area = area_out if area_out is not None else torch.empty(1, dtype=torch.int64, device=h.device)
+    c = _clip(x, y, s, V, T, K, L, F, area)
+    nb = ctypes.c_size_t(0)
+    check(h.lib.fcfs_fft_workspace_size(ctypes.byref(c), ctypes.byref(nb)))
+    ws = h.workspace(nb.value)
+    check(h.lib.fcfs_forward_fft(h.ptr, ctypes.byref(c), ctypes.c_void_p(ws.data_ptr()),
+                                 ctypes.c_size_t(ws.numel())), h.ptr)
     return F, area
 
 

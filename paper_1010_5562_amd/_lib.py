@@ -29,6 +29,7 @@ STATUS_NAMES = {
 EXPORTS = (
     "fcfs_create", "fcfs_destroy", "fcfs_set_stream", "fcfs_loops_to_corners",
     "fcfs_workspace_size", "fcfs_forward", "fcfs_band_workspace_size", "fcfs_forward_band",
+    "fcfs_fft_workspace_size", "fcfs_forward_fft",
     "fcfs_adjoint", "fcfs_adjoint_band", "fcfs_edge_grad",
     "fcfs_apply_edge_offsets", "fcfs_batch_workspace_size", "fcfs_forward_batch", "fcfs_plan_destroy",
     "fcfs_debug_phases", "fcfs_autotune", "fcfs_load_tune", "fcfs_tile_variants", "fcfs_set_tile",
@@ -83,6 +84,8 @@ def load() -> ctypes.CDLL:
         "fcfs_forward": [P, clip_p, c_int, P, ctypes.c_size_t],
         "fcfs_band_workspace_size": [clip_p, i32, i32, ctypes.c_double, c_int, sz],
         "fcfs_forward_band": [P, clip_p, i32, i32, ctypes.c_double, c_int, P, ctypes.c_size_t],
+        "fcfs_fft_workspace_size": [clip_p, sz],
+        "fcfs_forward_fft": [P, clip_p, P, ctypes.c_size_t],
         "fcfs_adjoint": [P, clip_p, P, P, P, c_int, P, ctypes.c_size_t],
         "fcfs_adjoint_band": [P, clip_p, P, i32, i32, ctypes.c_double, P, P, c_int, P,
                               ctypes.c_size_t],

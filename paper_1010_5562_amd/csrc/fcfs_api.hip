@@ -20,7 +20,7 @@ using fcfs::Tables;
 
 // Kernel families timed by the profiling hooks.
 enum ProfKind { kProfPrepass = 0, kProfAxis, kProfContract, kProfEpilogue, kProfAdjoint,
-                kProfBatch, kProfKinds };
+                kProfBatch, kProfFft, kProfKinds };
 
 struct fcfs_handle {
   int device = 0;
@@ -229,8 +229,10 @@ fcfs_status check_dims(fcfs_handle *h, int64_t V, int T, int K, int L, int prec)
 
 // r2 >= 0: only the pupil k^2 + l^2 <= r2 is kept (tiles wholly outside it
 // are skipped and the split count is sized for the remaining ones).
+// lattice: the plan of the lattice (FFT) form: no contraction partials or
+// guard block, but the bin counters, corner list and row transforms.
 fcfs_status make_plan(fcfs_handle *h, int64_t V, int T, int K, int L, int prec, int tile,
-                      FwdPlan *p, double r2 = -1.0) {
+                      FwdPlan *p, double r2 = -1.0, bool lattice = false) {
   fcfs_status st = check_dims(h, V, T, K, L, prec);
   if (st) return st;
   FwdPlan q{};
@@ -292,13 +294,22 @@ fcfs_status make_plan(fcfs_handle *h, int64_t V, int T, int K, int L, int prec, 
   q.off_axis = off;
   off += align256(sizeof(double2) * (size_t)q.ax_chunks * (size_t)std::max(1, K + L));
   q.off_part = off;
-  off += align256(sizeof(float) * 4 * (size_t)q.nsplit * (size_t)q.kp * (size_t)q.lp);
+  if (!lattice) off += align256(sizeof(float) * 4 * (size_t)q.nsplit * (size_t)q.kp * (size_t)q.lp);
   q.off_guard = off;
-  off += align256(sizeof(double) * fcfs::kGuardD * (size_t)q.g_chunks);
+  if (!lattice) off += align256(sizeof(double) * fcfs::kGuardD * (size_t)q.g_chunks);
   q.off_gfinal = off;
-  off += align256(sizeof(double) * fcfs::kGuardD);
+  if (!lattice) off += align256(sizeof(double) * fcfs::kGuardD);
   q.off_gcount = off;
   off += 256;
+  q.off_fcnt = q.off_flist = q.off_fd = off;
+  if (lattice) {
+    q.off_fcnt = off;
+    off += align256(sizeof(int) * (4 * (size_t)T + 2));  // counts, cursors, offsets, overflow
+    q.off_flist = off;
+    off += align256(sizeof(uint32_t) * (size_t)std::max<int64_t>(V, 1));
+    q.off_fd = off;
+    off += align256(sizeof(double2) * (size_t)T * (size_t)std::max(L, 1));
+  }
   q.bytes = off;
   *p = q;
   return FCFS_OK;
@@ -711,6 +722,50 @@ fcfs_status fcfs_forward_band(fcfs_handle *h, const fcfs_clip *c, int32_t kmax, 
   if ((st = make_band_plan(h, c, kmax, lmax, radius, (int)p, h->tile_override, &q))) return st;
   if ((st = check_ws(h, q, ws, ws_bytes))) return st;
   return run_forward(h, c, q, ws);
+}
+
+fcfs_status fcfs_fft_workspace_size(const fcfs_clip *c, size_t *bytes) {
+  if (!c || !bytes) return fail(nullptr, FCFS_ERR_INVALID_ARG, "NULL argument");
+  FwdPlan q;
+  fcfs_status st = make_plan(nullptr, c->V, c->T, c->K, c->L, fcfs::kFP32, -1, &q, -1.0, true);
+  if (st) return st;
+  *bytes = q.bytes;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_forward_fft(fcfs_handle *h, const fcfs_clip *c, void *ws, size_t ws_bytes) {
+  fcfs_status st = enter(h);
+  if (st) return st;
+  if ((st = check_clip(h, c, true))) return st;
+  FwdPlan q;
+  if ((st = make_plan(h, c->V, c->T, c->K, c->L, fcfs::kFP32, -1, &q, -1.0, true))) return st;
+  if ((st = check_ws(h, q, ws, ws_bytes))) return st;
+  hipError_t e;
+  {
+    ProfScope ps(h, kProfPrepass);
+    if ((e = fcfs::launch_prepass(q, c->x, c->y, c->s, ws_at<uint4>(ws, q.off_packed),
+                                  ws_at<unsigned long long>(ws, q.off_area),
+                                  ws_at<unsigned long long>(ws, q.off_hist),
+                                  ws_at<unsigned int>(ws, q.off_gcount), h->stream)))
+      return hip_fail(h, e, "pre-pass launch");
+  }
+  {
+    ProfScope ps(h, kProfAxis);
+    if (q.K + q.L > 0 &&
+        (e = fcfs::launch_side(q, c->x, c->y, h->tab.w64, ws, h->stream, false)))
+      return hip_fail(h, e, "axis launch");
+  }
+  if (q.K > 0 && q.L > 0) {
+    ProfScope ps(h, kProfFft);
+    if ((e = fcfs::launch_fft(q, c->x, c->y, c->s, h->tab.w64, ws, c->F, h->stream)))
+      return hip_fail(h, e, "lattice-form launch");
+  }
+  {
+    ProfScope ps(h, kProfEpilogue);
+    if ((e = fcfs::launch_epilogue_axes(q, ws, c->F, c->area, h->stream)))
+      return hip_fail(h, e, "epilogue launch");
+  }
+  return FCFS_OK;
 }
 
 fcfs_status fcfs_debug_phases(fcfs_handle *h, const fcfs_clip *c, int32_t axis, int32_t k0,

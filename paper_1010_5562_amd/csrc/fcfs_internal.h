@@ -64,6 +64,8 @@ struct FwdPlan {
   // workspace offsets (bytes)
   size_t off_packed, off_area, off_hist, off_axis, off_part, off_guard, off_gfinal, off_gcount,
       bytes;
+  // lattice (FFT) form only: bin counters, corner list, row transforms
+  size_t off_fcnt, off_flist, off_fd;
 };
 
 // Kernel launchers (fcfs_kernels.hip).  All enqueue on `st` and return the
@@ -72,13 +74,19 @@ struct FwdPlan {
 hipError_t launch_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
                           uint4 *packed, unsigned long long *area_part,
                           unsigned long long *hist, unsigned int *gcount, hipStream_t st);
-// histograms + guard block, then the axis DFTs (side stream)
+// histograms + guard block (unless guard is false), then the axis DFTs
 hipError_t launch_side(const FwdPlan &p, const int32_t *x, const int32_t *y, const double2 *w64,
-                       void *ws, hipStream_t st);
+                       void *ws, hipStream_t st, bool guard = true);
 hipError_t launch_contract(const FwdPlan &p, const uint4 *packed, const Tables &t, float *part,
                            hipStream_t st);
 hipError_t launch_epilogue(const FwdPlan &p, const void *ws, float *F, int64_t *area,
                            hipStream_t st);
+// the axes and DC entries only (lattice form)
+hipError_t launch_epilogue_axes(const FwdPlan &p, const void *ws, float *F, int64_t *area,
+                                hipStream_t st);
+// lattice form of the general term (fcfs_fft.hip): writes F for k, l != 0
+hipError_t launch_fft(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
+                      const double2 *w64, void *ws, float *F, hipStream_t st);
 hipError_t launch_debug_phases(const FwdPlan &p, const uint4 *packed, int axis, int k0, int nk,
                                int32_t *out, hipStream_t st);
 

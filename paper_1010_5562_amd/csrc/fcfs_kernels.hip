@@ -232,12 +232,12 @@ __global__ __launch_bounds__(256) void k_side(const int32_t *__restrict__ x,
 }
 
 hipError_t launch_side(const FwdPlan &p, const int32_t *x, const int32_t *y, const double2 *w64,
-                       void *ws, hipStream_t st) {
+                       void *ws, hipStream_t st, bool guard) {
   char *w = (char *)ws;
   const uint4 *packed = (const uint4 *)(w + p.off_packed);
   auto *hist = (unsigned long long *)(w + p.off_hist);
   const int nh = p.K + p.L > 0 ? p.hist_blocks : 0;
-  const int ng = p.K > 0 && p.L > 0 ? p.g_chunks : 0;
+  const int ng = guard && p.K > 0 && p.L > 0 ? p.g_chunks : 0;
   if (nh + ng > 0)
     hipLaunchKernelGGL(k_side, dim3(nh + ng), dim3(256), 0, st, x, y, packed, p.V, p.shift, hist,
                        nh, (const double *)w64, p.g_chunk, p.g_chunks,
@@ -885,6 +885,14 @@ __global__ __launch_bounds__(256) void k_epilogue(const float *__restrict__ part
                  gfinal, o, area, blockIdx.x);
 }
 
+__global__ __launch_bounds__(256) void k_epilogue_axes(const double2 *__restrict__ axis_part,
+                                                       int ax_chunks, int K, int L, double T,
+                                                       const unsigned long long *__restrict__ area_part,
+                                                       int pre_blocks, OutGrid o,
+                                                       int64_t *__restrict__ area) {
+  epilogue_axes_body(axis_part, ax_chunks, K, L, T, area_part, pre_blocks, o, area, blockIdx.x);
+}
+
 // Clears the output grid (band forward: entries outside the computed band).
 __global__ __launch_bounds__(256) void k_zero_grid(float2 *__restrict__ F, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
@@ -905,6 +913,16 @@ hipError_t launch_epilogue(const FwdPlan &p, const void *ws, float *F, int64_t *
                      (const double2 *)(w + p.off_axis), p.ax_chunks,
                      (const unsigned long long *)(w + p.off_area), p.pre_blocks,
                      (const double *)(w + p.off_gfinal), o, area);
+  return hipGetLastError();
+}
+
+hipError_t launch_epilogue_axes(const FwdPlan &p, const void *ws, float *F, int64_t *area,
+                                hipStream_t st) {
+  const char *w = (const char *)ws;
+  const OutGrid o{(float2 *)F, p.KO, p.LO, p.r2};
+  hipLaunchKernelGGL(k_epilogue_axes, dim3(std::max(1, (p.K + p.L + 15) / 16)), dim3(256), 0, st,
+                     (const double2 *)(w + p.off_axis), p.ax_chunks, p.K, p.L, (double)p.T,
+                     (const unsigned long long *)(w + p.off_area), p.pre_blocks, o, area);
   return hipGetLastError();
 }
 
