@@ -270,6 +270,26 @@ def main() -> int:
     if args.quick:
         print(json.dumps(out))
         return 0
+
+    # ------------------------------------------------- lattice (FFT) form, C3
+    # The same coefficients from the FP64 lattice form: reported as a separate
+    # leg (a different algorithm, not the metric's MFMA contraction), and used
+    # as the full-grid reference of the contraction forms.
+    Ff = torch.empty_like(F)
+    msf, proff = timed(lambda: P.forward_fft(xd, yd, sd, T, K, L, out=Ff), args.steps,
+                       args.warmup, h, kinds=("fft",))
+    Ff_np = Ff.cpu().numpy().astype(np.complex128)
+    ef = float(np.max(np.abs(Ff_np[kk + K, ll + L] - ref)) / f00)
+    lattice = {
+        "precision_clip": {"value": pairs / (msf * 1e-3), "ms_per_step": msf,
+                           "err_rel_f00": ef, "kernels_ms": kavg(proff, "fft")},
+    }
+    for prec, leg in legs.items():
+        out.setdefault("err_full_grid_vs_lattice", {})[prec] = float(
+            np.max(np.abs(leg["F"] - Ff_np)) / f00)
+    log(f"lattice form: {msf:.3f} ms/step  {pairs / msf * 1e3:.4g} pairs/s  err {ef:.2e}; "
+        f"full-grid error of the contraction forms against it: "
+        f"{out['err_full_grid_vs_lattice']}")
     del legs
 
     # ------------------------------------------------------------------ C2
@@ -295,6 +315,13 @@ def main() -> int:
                      "contract_ms": kavg(prof2, "contract")}
         log(f"layout clip {prec}: {ms2:.3f} ms  {p2 / ms2 * 1e3:.4g} pairs/s  err {e2:.2e}")
     forms["layout_clip"] = lay
+    F2f = torch.empty((2 * K2 + 1, 2 * K2 + 1), dtype=torch.complex64, device=dev)
+    ms2f, _ = timed(lambda: P.forward_fft(x2d, y2d, s2d, T2, K2, K2, out=F2f), args.steps,
+                    args.warmup, h, kinds=("fft",))
+    e2f = float(np.max(np.abs(F2f.cpu().numpy()[kk2 + K2, ll2 + K2] - ref2)) / f002)
+    lattice["layout_clip"] = {"value": p2 / (ms2f * 1e-3), "ms_per_step": ms2f, "err_rel_f00": e2f}
+    log(f"layout clip lattice form: {ms2f:.3f} ms  {p2 / ms2f * 1e3:.4g} pairs/s  err {e2f:.2e}")
+    forms["lattice_form"] = lattice
 
     # ------------------------------------------------------------------ C4
     t0 = time.time()
