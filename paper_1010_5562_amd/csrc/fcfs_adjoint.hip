@@ -26,6 +26,16 @@ __device__ __forceinline__ size_t rec_index(int n, int r, int lb, int ncb) {
   return ((((size_t)kstep * ncb + cb) * 64) + li + 32 * h) * 8 + j;
 }
 
+// Position of W[row r][column n] in the FP32 operand records: per 16-row step
+// and column block (the blocks of rec_index), 8 sub-steps of two rows, each a
+// 64-lane B operand of v_mfma_f32_32x32x2_f32 (lane li + 32 h: row 2 u + h,
+// column li of the block).
+__device__ __forceinline__ size_t rec_index_f32(int n, int r, int lb, int ncb) {
+  const int q = n / lb, lm = n - q * lb;
+  const int kstep = r >> 4, u = (r >> 1) & 7, h = r & 1, cb = (lm >> 5) * 4 + q, li = lm & 31;
+  return ((((size_t)kstep * ncb + cb) * 8 + u) * 64) + li + 32 * h;
+}
+
 // ---------------------------------------------------------------------------
 // W from the cotangent.  For 1 <= k <= kb, 1 <= l <= lb (zero outside the
 // band), with M'[k,l] = M[k,l] + conj(M[-k,-l]) and a + jb = M'[k,l],
@@ -36,7 +46,10 @@ __device__ __forceinline__ size_t rec_index(int n, int r, int lb, int ncb) {
 // [cos k | sin k], each kb long.  Stored transposed, Wf[n * R + r], FP32.
 // The largest |W| is folded into *wmax (float bits, non-negative).
 // ---------------------------------------------------------------------------
-template <bool DIRECT>
+// MODE 0: FP32 matrix Wf (transposed) and its largest |W| (the split-fp16
+// path scales from it); 1: split-bf16 operand records; 2: FP32 operand
+// records (rec_index_f32).
+template <int MODE>
 __global__ __launch_bounds__(256) void k_adj_w(const float2 *__restrict__ G, int K, int L, int kmax,
                                                int lmax, double r2, int kb, int lb,
                                                float *__restrict__ Wf,
@@ -80,7 +93,16 @@ __global__ __launch_bounds__(256) void k_adj_w(const float2 *__restrict__ G, int
   const size_t nyc = (size_t)(2 * lb + l - 1), nys = (size_t)(3 * lb + l - 1);
   const float v[8] = {(float)Wcc, (float)Wsc, (float)Wcs, (float)Wss,
                       (float)Ycc, (float)Ysc, (float)Ycs, (float)Yss};
-  if constexpr (DIRECT) {
+  if constexpr (MODE == 2) {
+    if (!live) return;
+    const int ncb = lb / 8;
+    const int nn[8] = {(int)nxc, (int)nxc, (int)nxs, (int)nxs, (int)nyc, (int)nyc, (int)nys, (int)nys};
+    const int rr[8] = {rc, rs, rc, rs, rc, rs, rc, rs};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) Wf[rec_index_f32(nn[i], rr[i], lb, ncb)] = v[i];
+    return;
+  }
+  if constexpr (MODE == 1) {
     // split-bf16: hi + lo records written here, scale 2^0
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) scale[0] = 0;
     if (!live) return;
@@ -393,19 +415,36 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_split(
   }
 }
 
-// FP32 main term: v_mfma_f32_32x32x2_f32, two frequencies per product.
-__global__ __launch_bounds__(256) void k_adj_gemm_fp32(const uint4 *__restrict__ packed,
-                                                       const float2 *__restrict__ tab32g,
-                                                       const float *__restrict__ Wf, int64_t V,
-                                                       int kb, int lb, float *__restrict__ gx,
-                                                       float *__restrict__ gy) {
+// FP32 main term: v_mfma_f32_32x32x2_f32, two frequencies per product, with
+// the operand records of rec_index_f32 shared through LDS as in the split form
+// (eight waves, 256 corners per workgroup, double-buffered 16-row steps).
+__global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_fp32(
+    const uint4 *__restrict__ packed, const float2 *__restrict__ tab32g,
+    const float *__restrict__ Wr, int64_t V, int kb, int lb, float *__restrict__ gx,
+    float *__restrict__ gy) {
   __shared__ float2 s_tab[kTabEntries];
-  for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab32g[i];
-  __syncthreads();
+  __shared__ float s_w[2][2 * kAdjNB][8][64];
+  for (int i = threadIdx.x; i < kTabEntries; i += 64 * kAdjWaves) s_tab[i] = tab32g[i];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 31, lh = lane >> 5;
-  const int64_t vbase = (int64_t)blockIdx.x * 128 + wave * 32;
-  const int R = 2 * kb, NC = 4 * lb;
+  const int64_t vbase = (int64_t)blockIdx.x * (32 * kAdjWaves) + wave * 32;
+  const int NC = 4 * lb, ncb = NC / 32, nks = kb / 16;
+  const int nsteps = (NC / (32 * kAdjNB)) * nks;
+  // block q of flat step it: column block nb = q & 3, sin rows if q & 4
+  auto record = [&](int it, int q) -> const float4 * {
+    const int cgi = it / nks, t = it - cgi * nks;
+    const int kstep = (q & 4) ? nks + t : t;
+    const size_t cb = (size_t)(cgi * kAdjNB + (q & 3));
+    return (const float4 *)(Wr + (((size_t)kstep * ncb + cb) * 8) * 64);
+  };
+  // a step is 8 blocks x 512 floats = 1024 float4: two per thread
+  constexpr int kPer = 2 * kAdjNB * 8 * 64 / 4 / (64 * kAdjWaves);
+  float4 pre[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int idx = threadIdx.x + 64 * kAdjWaves * u;
+    pre[u] = record(0, idx >> 7)[idx & 127];
+  }
   const uint4 ca = packed[vbase + li];
   uint32_t ys8[16];
   bool neg[16];
@@ -418,35 +457,50 @@ __global__ __launch_bounds__(256) void k_adj_gemm_fp32(const uint4 *__restrict__
   float sx[16], sy[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) sx[r] = sy[r] = 0.f;
+  int it = 0;
   for (int cg = 0; cg < NC; cg += 32 * kAdjNB) {
     f32x16 acc[kAdjNB];
 #pragma unroll
     for (int nb = 0; nb < kAdjNB; ++nb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[nb][r] = 0.f;
-    for (int ib = 0; ib < kb; ib += 2) {
-      const float2 a = *(const float2 *)((const char *)s_tab + phase_x((uint32_t)(1 + ib + lh), ca));
+    for (int ib = 0; ib < kb; ib += 16, ++it) {
+      const int buf = it & 1;
 #pragma unroll
-      for (int nb = 0; nb < kAdjNB; ++nb) {
-        const size_t n = (size_t)(cg + 32 * nb + li);
-        const float bc = Wf[n * R + ib + lh], bs = Wf[n * R + kb + ib + lh];
-        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, bc, acc[nb], 0, 0, 0);
-        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, bs, acc[nb], 0, 0, 0);
+      for (int u = 0; u < kPer; ++u) {
+        const int idx = threadIdx.x + 64 * kAdjWaves * u;
+        *(float4 *)&s_w[buf][idx >> 7][(idx & 127) >> 4][(idx & 15) * 4] = pre[u];
+      }
+      __syncthreads();
+      if (it + 1 < nsteps) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+          const int idx = threadIdx.x + 64 * kAdjWaves * u;
+          pre[u] = record(it + 1, idx >> 7)[idx & 127];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const float2 a = *(const float2 *)((const char *)s_tab +
+                                           phase_x((uint32_t)(1 + ib + 2 * u + lh), ca));
+#pragma unroll
+        for (int nb = 0; nb < kAdjNB; ++nb) {
+          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, s_w[buf][nb][u][lane], acc[nb], 0,
+                                                         0, 0);
+          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, s_w[buf][4 + nb][u][lane],
+                                                         acc[nb], 0, 0, 0);
+        }
       }
     }
-#pragma unroll
-    for (int nb = 0; nb < kAdjNB; ++nb) {
-      const int n0 = cg + 32 * nb;
-      const int q = n0 / lb;
-      const uint32_t l = (uint32_t)(n0 - q * lb + li + 1);
+    // dot with Y_v: one (cos, sin)(l y) per row serves the four accumulators
+    {
+      const uint32_t l = (uint32_t)((cg >> 2) + li + 1);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const float2 w = s_tab[(l * (ys8[r] >> 3)) & (uint32_t)(kTabN - 1)];
-        const float yv = (q & 1) ? w.y : w.x;
-        if (q < 2)
-          sx[r] = fmaf(acc[nb][r], yv, sx[r]);
-        else
-          sy[r] = fmaf(acc[nb][r], yv, sy[r]);
+        const float2 w = *(const float2 *)((const char *)s_tab +
+                                           phase_x(l, make_uint4(ys8[r], 0u, 0u, 0u)));
+        sx[r] = fmaf(acc[0][r], w.x, fmaf(acc[1][r], w.y, sx[r]));
+        sy[r] = fmaf(acc[2][r], w.x, fmaf(acc[3][r], w.y, sy[r]));
       }
     }
   }
@@ -489,18 +543,20 @@ hipError_t launch_adjoint(const AdjPlan &a, const int32_t *x, const int32_t *y, 
   if (a.kmax == 0 || a.lmax == 0 || a.V == 0) return hipGetLastError();
   const dim3 wgrid((a.lb + 255) / 256, a.kb);
   if (a.prec == kBF16) {
-    hipLaunchKernelGGL(k_adj_w<true>, wgrid, dim3(256), 0, st, G, a.K, a.L, a.kmax, a.lmax, a.r2,
+    hipLaunchKernelGGL(k_adj_w<1>, wgrid, dim3(256), 0, st, G, a.K, a.L, a.kmax, a.lmax, a.r2,
+                       a.kb, a.lb, Wf, wmax, whi, wlo, scale);
+  } else if (a.prec == kFP32) {
+    hipLaunchKernelGGL(k_adj_w<2>, wgrid, dim3(256), 0, st, G, a.K, a.L, a.kmax, a.lmax, a.r2,
                        a.kb, a.lb, Wf, wmax, whi, wlo, scale);
   } else {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, wmax, 1, 0u);
-    hipLaunchKernelGGL(k_adj_w<false>, wgrid, dim3(256), 0, st, G, a.K, a.L, a.kmax, a.lmax,
-                       a.r2, a.kb, a.lb, Wf, wmax, whi, wlo, scale);
+    hipLaunchKernelGGL(k_adj_w<0>, wgrid, dim3(256), 0, st, G, a.K, a.L, a.kmax, a.lmax, a.r2,
+                       a.kb, a.lb, Wf, wmax, whi, wlo, scale);
   }
-  const unsigned blocks = (unsigned)(a.vpad / 128);                     // FP32 form
-  const unsigned sblocks = (unsigned)(a.vpad / (32 * kAdjWaves));      // split forms
+  const unsigned sblocks = (unsigned)(a.vpad / (32 * kAdjWaves));
   if (a.prec == kFP32) {
-    hipLaunchKernelGGL(k_adj_gemm_fp32, dim3(blocks), dim3(256), 0, st, packed, t.w32, Wf, a.V,
-                       a.kb, a.lb, gx, gy);
+    hipLaunchKernelGGL(k_adj_gemm_fp32, dim3(sblocks), dim3(64 * kAdjWaves), 0, st, packed, t.w32,
+                       Wf, a.V, a.kb, a.lb, gx, gy);
   } else {
     const int64_t n = (int64_t)a.R * a.NC;
     const unsigned sb = (unsigned)std::min<int64_t>(1024, (n + 255) / 256);
