@@ -335,7 +335,12 @@ def main() -> int:
     nvb = sum(int(a[0].size) for a in bargs)
     log(f"batch: 256 clips, {nvb} corners, {bpairs:.3e} pairs (generated in "
         f"{time.time() - t0:.1f}s)")
-    batch = P.Batch(bargs, precision="bf16")
+    # tile shape and corners per work item from the library's batch autotuner,
+    # timed on these clips
+    t0 = time.time()
+    batch = P.Batch(bargs, precision="bf16", tune=True)
+    t_tune = time.time() - t0
+    log(f"batch autotune: {t_tune:.1f}s, choice (tile variant, corners per item) {batch.choice}")
     msb, profb = timed(batch.run, max(3, args.steps // 4), 1, h, kinds=("batch",))
     # error on the four smallest clips and four random ones, sampled points
     order = np.argsort([int(a[0].size) for a in bargs])
@@ -356,6 +361,8 @@ def main() -> int:
         "clips": 256, "corners": nvb, "pairs": bpairs,
         "value": bpairs / (msb * 1e-3), "ms_per_step": msb,
         "err_rel_f00_max_of_8_clips": eb,
+        "autotune": {"seconds": t_tune, "tile_variant": batch.choice[0],
+                     "corners_per_item": batch.choice[1]},
     }
     log(f"batch: {msb:.3f} ms  {bpairs / msb * 1e3:.4g} pairs/s  err {eb:.2e}")
     batch.close()

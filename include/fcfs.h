@@ -186,9 +186,11 @@ fcfs_status fcfs_apply_edge_offsets(fcfs_handle *h, const int32_t *base_x, const
  * plan (work list, tile shapes) and captures the enqueued sequence in a
  * hipGraph; later calls with the same plan and the same clip array contents
  * replay the graph.  ws: (device) workspace of at least
- * fcfs_batch_workspace_size bytes. */
-fcfs_status fcfs_batch_workspace_size(const fcfs_clip *c, int32_t n, fcfs_precision p,
-                                      size_t *bytes);
+ * fcfs_batch_workspace_size bytes, queried with the same handle (its tuned
+ * tile shape and corners per work item set the layout; h = NULL gives the
+ * built-in choices). */
+fcfs_status fcfs_batch_workspace_size(fcfs_handle *h, const fcfs_clip *c, int32_t n,
+                                      fcfs_precision p, size_t *bytes);
 fcfs_status fcfs_forward_batch(fcfs_handle *h, const fcfs_clip *c, int32_t n, fcfs_precision p,
                                void *ws, size_t ws_bytes, fcfs_plan **plan);
 fcfs_status fcfs_plan_destroy(fcfs_plan *plan);
@@ -208,6 +210,17 @@ fcfs_status fcfs_debug_phases(fcfs_handle *h, const fcfs_clip *c, int32_t axis, 
  * leaves the built-in choices.  effort: 0..2 (more shapes and sizes).
  * Synchronises the handle's stream. */
 fcfs_status fcfs_autotune(fcfs_handle *h, const char *cache_path, int effort);
+
+/* Batch autotuner: builds and times a plan of the clips c[0..n) for each
+ * candidate (contraction tile variant, corners per work item) and keeps the
+ * fastest on h (used by later fcfs_batch_workspace_size / fcfs_forward_batch
+ * calls for precision p); the built-in choice stays unless a candidate beats it
+ * by more than 3%.  Overwrites the clips' outputs.  effort 0..2 sets the timed
+ * repetitions (2, 3, 5).  Allocates and frees a workspace per candidate.
+ * fcfs_batch_choice reports the current choice. */
+fcfs_status fcfs_autotune_batch(fcfs_handle *h, const fcfs_clip *c, int32_t n, fcfs_precision p,
+                                int effort);
+fcfs_status fcfs_batch_choice(fcfs_handle *h, fcfs_precision p, int32_t *tile, int64_t *chunk);
 fcfs_status fcfs_load_tune(fcfs_handle *h, const char *cache_path);
 
 /* Tuning hooks.  fcfs_tile_variants fills wk[i], wl[i] (frequencies per

@@ -394,10 +394,12 @@ class Batch:
     ``clips``: sequence of (x, y, s, T, K, L) with host or device corner
     arrays.  Inputs are copied to device tensors owned by this object, so the
     captured graph's pointers stay valid; ``run()`` replays it.  Outputs:
-    ``F[i]`` ((2K_i+1, 2L_i+1) complex64) and ``area[i]``.
+    ``F[i]`` ((2K_i+1, 2L_i+1) complex64) and ``area[i]``.  ``tune=True`` runs
+    the batch autotuner on these clips first (fcfs_autotune_batch); ``choice``
+    holds the (tile variant, corners per work item) the plan uses.
     """
 
-    def __init__(self, clips, precision="bf16", handle=None):
+    def __init__(self, clips, precision="bf16", handle=None, tune=False, tune_effort=0):
         import torch
 
         self.handle = h = handle or default_handle()
@@ -415,8 +417,16 @@ class Batch:
             arr[i] = _clip(x, y, s, x.numel(), T, K, L, F, a)
         self.n = len(clips)
         self._arr = arr
+        if tune:
+            check(h.lib.fcfs_autotune_batch(h.ptr, arr, self.n, self.precision, int(tune_effort)),
+                  h.ptr)
+        tile, chunk = ctypes.c_int32(0), ctypes.c_int64(0)
+        check(h.lib.fcfs_batch_choice(h.ptr, self.precision, ctypes.byref(tile),
+                                      ctypes.byref(chunk)), h.ptr)
+        self.choice = (int(tile.value), int(chunk.value))
         nb = ctypes.c_size_t(0)
-        check(h.lib.fcfs_batch_workspace_size(arr, self.n, self.precision, ctypes.byref(nb)))
+        check(h.lib.fcfs_batch_workspace_size(h.ptr, arr, self.n, self.precision,
+                                              ctypes.byref(nb)), h.ptr)
         self.ws = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=dev)
         self._plan = ctypes.c_void_p()
 

@@ -32,7 +32,8 @@ EXPORTS = (
     "fcfs_fft_workspace_size", "fcfs_forward_fft",
     "fcfs_adjoint", "fcfs_adjoint_band", "fcfs_edge_grad",
     "fcfs_apply_edge_offsets", "fcfs_batch_workspace_size", "fcfs_forward_batch", "fcfs_plan_destroy",
-    "fcfs_debug_phases", "fcfs_autotune", "fcfs_load_tune", "fcfs_tile_variants", "fcfs_set_tile",
+    "fcfs_debug_phases", "fcfs_autotune", "fcfs_autotune_batch", "fcfs_batch_choice",
+    "fcfs_load_tune", "fcfs_tile_variants", "fcfs_set_tile",
     "fcfs_workspace_size_tile", "fcfs_profile_begin", "fcfs_profile_end",
     "fcfs_status_string", "fcfs_last_error",
 )
@@ -91,11 +92,13 @@ def load() -> ctypes.CDLL:
                               ctypes.c_size_t],
         "fcfs_edge_grad": [P, P, P, P, P, i64, i64, P],
         "fcfs_apply_edge_offsets": [P, P, P, P, P, P, i64, P, P],
-        "fcfs_batch_workspace_size": [clip_p, i32, c_int, sz],
+        "fcfs_batch_workspace_size": [P, clip_p, i32, c_int, sz],
         "fcfs_forward_batch": [P, clip_p, i32, c_int, P, ctypes.c_size_t, ctypes.POINTER(P)],
         "fcfs_plan_destroy": [P],
         "fcfs_debug_phases": [P, clip_p, i32, i32, i32, P],
         "fcfs_autotune": [P, ctypes.c_char_p, c_int],
+        "fcfs_autotune_batch": [P, clip_p, i32, c_int, c_int],
+        "fcfs_batch_choice": [P, c_int, P, P],
         "fcfs_load_tune": [P, ctypes.c_char_p],
         "fcfs_set_tile": [P, i32],
         "fcfs_profile_begin": [P, u32],

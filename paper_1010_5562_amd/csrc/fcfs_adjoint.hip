@@ -292,7 +292,7 @@ constexpr int kAdjWaves = 8;
 template <int PREC>
 __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_split(
     const uint4 *__restrict__ packed, const uint2 *__restrict__ tab,
-    const float2 *__restrict__ tab32, const uint16_t *__restrict__ whi,
+    const uint16_t *__restrict__ whi,
     const uint16_t *__restrict__ wlo, const int *__restrict__ scale, int64_t V, int kb, int lb,
     float *__restrict__ gx, float *__restrict__ gy) {
   __shared__ uint2 s_tab[kTabEntries];
@@ -562,12 +562,12 @@ hipError_t launch_adjoint(const AdjPlan &a, const int32_t *x, const int32_t *y, 
     const unsigned sb = (unsigned)std::min<int64_t>(1024, (n + 255) / 256);
     if (a.prec == kBF16) {
       hipLaunchKernelGGL(k_adj_gemm_split<kBF16>, dim3(sblocks), dim3(64 * kAdjWaves), 0, st, packed,
-                         t.wbf16, t.w32, whi, wlo, scale, a.V, a.kb, a.lb, gx, gy);
+                         t.wbf16, whi, wlo, scale, a.V, a.kb, a.lb, gx, gy);
     } else {
       hipLaunchKernelGGL(k_adj_split<kFP16>, dim3(sb), dim3(256), 0, st, Wf, a.R, a.NC, a.lb,
                          wmax, whi, wlo, scale);
       hipLaunchKernelGGL(k_adj_gemm_split<kFP16>, dim3(sblocks), dim3(64 * kAdjWaves), 0, st, packed,
-                         t.wfp16, t.w32, whi, wlo, scale, a.V, a.kb, a.lb, gx, gy);
+                         t.wfp16, whi, wlo, scale, a.V, a.kb, a.lb, gx, gy);
     }
   }
   return hipGetLastError();

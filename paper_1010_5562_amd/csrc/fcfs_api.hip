@@ -1096,8 +1096,8 @@ bool same_clips(const fcfs_plan *p, const fcfs_clip *c, int32_t n) {
 
 extern "C" {
 
-fcfs_status fcfs_batch_workspace_size_h(fcfs_handle *h, const fcfs_clip *c, int32_t n,
-                                        fcfs_precision p, size_t *bytes) {
+fcfs_status fcfs_batch_workspace_size(fcfs_handle *h, const fcfs_clip *c, int32_t n,
+                                      fcfs_precision p, size_t *bytes) {
   if (!bytes) return fail(h, FCFS_ERR_INVALID_ARG, "bytes is NULL");
   BatchLayout L;
   const int tile = batch_tile(h, (int)p);
@@ -1107,10 +1107,6 @@ fcfs_status fcfs_batch_workspace_size_h(fcfs_handle *h, const fcfs_clip *c, int3
   return FCFS_OK;
 }
 
-fcfs_status fcfs_batch_workspace_size(const fcfs_clip *c, int32_t n, fcfs_precision p,
-                                      size_t *bytes) {
-  return fcfs_batch_workspace_size_h(nullptr, c, n, p, bytes);
-}
 
 fcfs_status fcfs_forward_batch(fcfs_handle *h, const fcfs_clip *c, int32_t n, fcfs_precision p,
                                void *ws, size_t ws_bytes, fcfs_plan **plan) {
@@ -1288,7 +1284,8 @@ fcfs_status fcfs_autotune(fcfs_handle *h, const char *cache_path, int effort) {
                             : effort == 1 ? std::vector<int64_t>{4096, 200000}
                                           : std::vector<int64_t>{4096, 32768, 200000};
   const int T = 8192;
-  const int64_t vmax = *std::max_element(Vs.begin(), Vs.end());
+  // corners for the forward sizes and for batch clips of up to 200k corners
+  const int64_t vmax = std::max<int64_t>(200000, *std::max_element(Vs.begin(), Vs.end()));
   std::vector<int32_t> hx, hy;
   std::vector<int8_t> hs;
   synth_corners(vmax, 12345, hx, hy, hs);
@@ -1317,53 +1314,84 @@ fcfs_status fcfs_autotune(fcfs_handle *h, const char *cache_path, int effort) {
   const bool saved_prof = h->prof;
   h->prof = false;
   std::vector<fcfs_handle::Tune> tune;
-  const int reps = effort == 0 ? 2 : 3;
+  const int reps = effort == 0 ? 3 : 5;
+  // shortest of `reps` timed runs of fn (after one untimed run)
+  auto time_min = [&](auto &&fn, float *best_ms) -> fcfs_status {
+    fcfs_status s2 = fn();
+    float bm = 1e30f;
+    for (int r = 0; r < reps && !s2; ++r) {
+      hipError_t e2;
+      if ((e2 = hipEventRecord(e0, h->stream))) return hip_fail(h, e2, "event");
+      if ((s2 = fn())) break;
+      float ms = 0.f;
+      if ((e2 = hipEventRecord(e1, h->stream)) || (e2 = hipEventSynchronize(e1)) ||
+          (e2 = hipEventElapsedTime(&ms, e0, e1)))
+        return hip_fail(h, e2, "event timing");
+      bm = std::min(bm, ms);
+    }
+    *best_ms = bm;
+    return s2;
+  };
+  // a candidate replaces the built-in choice only when clearly faster
+  constexpr double kMargin = 0.97;
   for (int p = 0; p < 3 && !st; ++p)
     for (int K : Ks)
       for (int64_t V : Vs) {
-        double best = 1e30;
+        const int def = default_tile(nullptr, p, K, V);
+        double t_def = 1e30, best = 1e30;
         int best_t = -1;
         for (int t = 0; t < fcfs::n_tile_variants() && !st; ++t) {
           if (!(fcfs::tile_variant(t).prec_mask & (1 << p))) continue;
           fcfs_clip c{(const int32_t *)dx.p, (const int32_t *)dy.p, (const int8_t *)ds.p, V, T, K, K,
                       (float *)dF.p, nullptr};
           h->tile_override = t;
-          st = fcfs_forward(h, &c, (fcfs_precision)p, dws.p, wsb);  // warm-up
-          if ((e = hipEventRecord(e0, h->stream))) st = hip_fail(h, e, "event");
-          for (int r = 0; r < reps && !st; ++r) st = fcfs_forward(h, &c, (fcfs_precision)p, dws.p, wsb);
-          if (!st && (e = hipEventRecord(e1, h->stream))) st = hip_fail(h, e, "event");
           float ms = 0.f;
-          if (!st && ((e = hipEventSynchronize(e1)) || (e = hipEventElapsedTime(&ms, e0, e1))))
-            st = hip_fail(h, e, "event timing");
-          if (!st && ms / reps < best) {
-            best = ms / reps;
+          st = time_min([&]() { return fcfs_forward(h, &c, (fcfs_precision)p, dws.p, wsb); }, &ms);
+          if (st) break;
+          if (t == def) t_def = ms;
+          if (ms < best) {
+            best = ms;
             best_t = t;
           }
+        }
+        if (best_t >= 0 && !(best < kMargin * t_def)) {
+          best_t = def;
+          best = t_def;
         }
         if (best_t >= 0) tune.push_back({p, kbucket(K), vbucket(V), best_t, best});
       }
   h->tile_override = saved;
-  // batch: corners per work item and wave tile on a mixed synthetic batch
+  // batch: corners per work item and wave tile on a mixed synthetic batch drawn
+  // like a layout's clips (K uniform over 63..511, corners log-uniform in
+  // [2000, 200000], T = 8192)
   if (!st) {
-    const int nb = effort == 0 ? 8 : 24;
+    const int nb = effort == 0 ? 16 : 32;
     std::vector<fcfs_clip> cl(nb);
     std::vector<DevBuf> outs(nb);
+    const int bK[4] = {63, 127, 255, 511};
     uint64_t z = 777;
     for (int i = 0; i < nb && !st; ++i) {
       z = z * 6364136223846793005ull + 1442695040888963407ull;
-      const int K = Ks[(z >> 40) % Ks.size()];
+      const int K = bK[(z >> 40) & 3];
       z = z * 6364136223846793005ull + 1442695040888963407ull;
-      const int64_t V = std::min<int64_t>(vmax, 2000 + (int64_t)((z >> 33) % 40000));
+      const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+      const int64_t V = std::min<int64_t>(vmax, (int64_t)(2000.0 * std::pow(100.0, u)));
       const size_t fb = sizeof(float) * 2 * (2 * (size_t)K + 1) * (2 * (size_t)K + 1);
       if ((e = hipMalloc(&outs[i].p, fb))) st = hip_fail(h, e, "autotune outputs");
       cl[i] = fcfs_clip{(const int32_t *)dx.p, (const int32_t *)dy.p, (const int8_t *)ds.p, V, T, K,
                         K, (float *)outs[i].p, nullptr};
     }
-    const int64_t chunks[4] = {4096, 8192, 16384, 32768};
+    // corners per work item; smaller items balance better but multiply the
+    // split partials the epilogue reads
+    const int64_t chunks[4] = {8192, 16384, 32768, 65536};
     for (int p = 0; p < 3 && !st; ++p) {
       const int tiles[3] = {p == fcfs::kFP32 ? 0 : 3, p == fcfs::kFP32 ? 1 : 4, 5};
       const int ntiles = p == fcfs::kFP32 ? 2 : 3;
-      double best = 1e30;
+      h->batch_tile[p] = -1;
+      h->batch_chunk[p] = 0;
+      const int def_tile = batch_tile(h, p);
+      const int64_t def_chunk = batch_chunk(h, p);
+      double best = 1e30, t_def = 1e30;
       int best_tile = -1;
       int64_t best_chunk = 0;
       for (int ti = 0; ti < ntiles && !st; ++ti)
@@ -1371,29 +1399,31 @@ fcfs_status fcfs_autotune(fcfs_handle *h, const char *cache_path, int effort) {
           h->batch_tile[p] = tiles[ti];
           h->batch_chunk[p] = chunks[ci];
           size_t bb = 0;
-          if ((st = fcfs_batch_workspace_size_h(h, cl.data(), nb, (fcfs_precision)p, &bb))) break;
+          if ((st = fcfs_batch_workspace_size(h, cl.data(), nb, (fcfs_precision)p, &bb))) break;
           DevBuf bw;
           if ((e = hipMalloc(&bw.p, bb))) {
             st = hip_fail(h, e, "batch workspace");
             break;
           }
           fcfs_plan *plan = nullptr;
-          st = fcfs_forward_batch(h, cl.data(), nb, (fcfs_precision)p, bw.p, bb, &plan);
-          if (!st && (e = hipEventRecord(e0, h->stream))) st = hip_fail(h, e, "event");
-          for (int r = 0; r < reps && !st; ++r)
-            st = fcfs_forward_batch(h, cl.data(), nb, (fcfs_precision)p, bw.p, bb, &plan);
-          if (!st && (e = hipEventRecord(e1, h->stream))) st = hip_fail(h, e, "event");
           float ms = 0.f;
-          if (!st && ((e = hipEventSynchronize(e1)) || (e = hipEventElapsedTime(&ms, e0, e1))))
-            st = hip_fail(h, e, "event timing");
+          st = time_min([&]() {
+            return fcfs_forward_batch(h, cl.data(), nb, (fcfs_precision)p, bw.p, bb, &plan);
+          }, &ms);
           (void)hipStreamSynchronize(h->stream);
           plan_free(plan);
-          if (!st && ms / reps < best) {
-            best = ms / reps;
+          if (st) break;
+          if (tiles[ti] == def_tile && chunks[ci] == def_chunk) t_def = ms;
+          if (ms < best) {
+            best = ms;
             best_tile = tiles[ti];
             best_chunk = chunks[ci];
           }
         }
+      if (!(best < kMargin * t_def)) {
+        best_tile = def_tile;
+        best_chunk = def_chunk;
+      }
       h->batch_tile[p] = best_tile;
       h->batch_chunk[p] = best_chunk;
     }
@@ -1405,6 +1435,83 @@ fcfs_status fcfs_autotune(fcfs_handle *h, const char *cache_path, int effort) {
   h->tune = tune;
   if (cache_path && !save_tune(h, cache_path))
     return fail(h, FCFS_ERR_INVALID_ARG, std::string("cannot write ") + cache_path);
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_autotune_batch(fcfs_handle *h, const fcfs_clip *c, int32_t n, fcfs_precision p,
+                                int effort) {
+  fcfs_status st = enter(h);
+  if (st) return st;
+  if (effort < 0 || effort > 2) return fail(h, FCFS_ERR_INVALID_ARG, "effort must be 0..2");
+  if (n <= 0 || !c) return fail(h, FCFS_ERR_INVALID_ARG, "no clips");
+  const int pi = (int)p;
+  if (pi < 0 || pi > 2) return fail(h, FCFS_ERR_INVALID_ARG, "unknown precision");
+  const int reps = effort == 0 ? 2 : (effort == 1 ? 3 : 5);
+  hipEvent_t e0, e1;
+  hipError_t e;
+  if ((e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1))) return hip_fail(h, e, "events");
+  const bool saved_prof = h->prof;
+  h->prof = false;
+  const int tiles[3] = {pi == fcfs::kFP32 ? 0 : 3, pi == fcfs::kFP32 ? 1 : 4, 5};
+  const int ntiles = pi == fcfs::kFP32 ? 2 : 3;
+  const int64_t chunks[4] = {8192, 16384, 32768, 65536};
+  h->batch_tile[pi] = -1;
+  h->batch_chunk[pi] = 0;
+  const int def_tile = batch_tile(h, pi);
+  const int64_t def_chunk = batch_chunk(h, pi);
+  double best = 1e30, t_def = 1e30;
+  int best_tile = def_tile;
+  int64_t best_chunk = def_chunk;
+  for (int ti = 0; ti < ntiles && !st; ++ti)
+    for (int ci = 0; ci < 4 && !st; ++ci) {
+      h->batch_tile[pi] = tiles[ti];
+      h->batch_chunk[pi] = chunks[ci];
+      size_t bb = 0;
+      if ((st = fcfs_batch_workspace_size(h, c, n, p, &bb))) break;
+      DevBuf bw;
+      if ((e = hipMalloc(&bw.p, bb))) {
+        st = hip_fail(h, e, "batch workspace");
+        break;
+      }
+      fcfs_plan *plan = nullptr;
+      float bm = 1e30f;
+      st = fcfs_forward_batch(h, c, n, p, bw.p, bb, &plan);  // builds the plan, untimed
+      for (int r = 0; r < reps && !st; ++r) {
+        float ms = 0.f;
+        if ((e = hipEventRecord(e0, h->stream))) st = hip_fail(h, e, "event");
+        if (!st) st = fcfs_forward_batch(h, c, n, p, bw.p, bb, &plan);
+        if (!st && ((e = hipEventRecord(e1, h->stream)) || (e = hipEventSynchronize(e1)) ||
+                    (e = hipEventElapsedTime(&ms, e0, e1))))
+          st = hip_fail(h, e, "event timing");
+        bm = std::min(bm, ms);
+      }
+      (void)hipStreamSynchronize(h->stream);
+      plan_free(plan);
+      if (st) break;
+      if (tiles[ti] == def_tile && chunks[ci] == def_chunk) t_def = bm;
+      if (bm < best) {
+        best = bm;
+        best_tile = tiles[ti];
+        best_chunk = chunks[ci];
+      }
+    }
+  if (!(best < 0.97 * t_def)) {  // the built-in choice unless clearly slower
+    best_tile = def_tile;
+    best_chunk = def_chunk;
+  }
+  h->batch_tile[pi] = best_tile;
+  h->batch_chunk[pi] = best_chunk;
+  h->prof = saved_prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
+fcfs_status fcfs_batch_choice(fcfs_handle *h, fcfs_precision p, int32_t *tile, int64_t *chunk) {
+  if (!h) return fail(nullptr, FCFS_ERR_INVALID_ARG, "handle is NULL");
+  if ((int)p < 0 || (int)p > 2) return fail(h, FCFS_ERR_INVALID_ARG, "unknown precision");
+  if (tile) *tile = batch_tile(h, (int)p);
+  if (chunk) *chunk = batch_chunk(h, (int)p);
   return FCFS_OK;
 }
 

@@ -297,7 +297,7 @@ __global__ __launch_bounds__(256) void k_fft_rows_dense(const int *__restrict__ 
 // Workgroups with consecutive l share their D cache lines: blockIdx is mapped
 // so that they land on the same XCD (dispatch is round-robin over 8 XCDs).
 __global__ __launch_bounds__(1024) void k_fft_cols(const double2 *__restrict__ D, int T,
-                                                   int logT, int shift, int K, int L,
+                                                   int logT, int K, int L,
                                                    const double2 *__restrict__ w64,
                                                    float2 *__restrict__ F) {
   __shared__ double2 a[kTabN];
@@ -337,7 +337,6 @@ __global__ __launch_bounds__(1024) void k_fft_cols(const double2 *__restrict__ D
       F[(size_t)(K - kk) * W + (L - l)] = make_float2(re, -im);
     }
   }
-  (void)shift;
 }
 
 hipError_t launch_fft(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
@@ -365,7 +364,7 @@ hipError_t launch_fft(const FwdPlan &p, const int32_t *x, const int32_t *y, cons
                      w64, D, overflow);
   // 8 * ceil(L / 8) blocks: every l is reached by the XCD-grouped mapping
   hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)(8 * ((p.L + 7) / 8))), dim3(1024), 0, st, D, p.T,
-                     logT, p.shift, p.K, p.L, w64, (float2 *)F);
+                     logT, p.K, p.L, w64, (float2 *)F);
   return hipGetLastError();
 }
 

@@ -115,3 +115,20 @@ def test_autotune_and_cache(P, tmp_path):
     Fb, _ = P.forward(x, y, s, clip.T, clip.K, clip.L, precision="bf16", handle=h)
     torch.cuda.synchronize()
     assert np.allclose(Fa.cpu().numpy(), Fb.cpu().numpy(), atol=1e-5 * abs(Fa[clip.K, clip.L].item()))
+
+
+def test_batch_autotuner_on_its_clips(P):
+    # the batch autotuner times candidate plans on the clips themselves; the
+    # plan it leaves gives the same coefficients as the single-clip forward
+    clips = _clips(9, 6)
+    args = _as_args(P, clips)
+    h = P.Handle()
+    b = P.Batch(args, precision="bf16", handle=h, tune=True)
+    tile, chunk = b.choice
+    assert tile in (3, 4, 5) and chunk in (8192, 16384, 32768, 65536)
+    F = [f.cpu().numpy().copy() for f in b.run()]
+    for i, (x, y, s, T, K, L) in enumerate(args):
+        Fs, _ = P.forward(x, y, s, T, K, L, precision="bf16", handle=h)
+        d = np.max(np.abs(Fs.cpu().numpy() - F[i])) / abs(F[i][K, L])
+        assert d <= 2e-6, (i, d)
+    b.close()
