@@ -328,10 +328,12 @@ def main() -> int:
     bclips = synth.batch_clips(4, n_clips=256)
     bargs = []
     bpairs = 0
+    bflops = 0
     for c in bclips:
         bx, by, bs, _, _ = P.loops_to_corners(c.xy, c.off)
         bargs.append((bx, by, bs, c.T, c.K, c.L))
         bpairs += int(bx.size) * (2 * c.K + 1) * (2 * c.L + 1)
+        bflops += 3 * 8 * (c.K + 1) * (c.L + 1) * int(bx.size)
     nvb = sum(int(a[0].size) for a in bargs)
     log(f"batch: 256 clips, {nvb} corners, {bpairs:.3e} pairs (generated in "
         f"{time.time() - t0:.1f}s)")
@@ -361,6 +363,11 @@ def main() -> int:
         "clips": 256, "corners": nvb, "pairs": bpairs,
         "value": bpairs / (msb * 1e-3), "ms_per_step": msb,
         "err_rel_f00_max_of_8_clips": eb,
+        # algorithmic split-bf16 flops of all clips over the whole graph replay
+        # (every kernel of the batch counted in the time)
+        "roofline": {"bound": "mfma", "achieved": bflops / (msb * 1e-3) / 1e12,
+                     "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
+                     "frac": bflops / (msb * 1e-3) / 1e12 / PEAK_TFLOPS["bf16"]},
         "autotune": {"seconds": t_tune, "tile_variant": batch.choice[0],
                      "corners_per_item": batch.choice[1]},
     }
@@ -411,6 +418,14 @@ def main() -> int:
         "adjoint_ms": kavg(prof5, "adjoint"),
         "value": V5 * (2 * K5 + 1) ** 2 / (ms5 * 1e-3),
     }
+    # adjoint GEMM work inside the pupil band (three split products of the
+    # 2 kmax x 4 lmax folded cotangent per corner) over all adjoint kernels
+    aflops = 3 * 2 * (2 * rb) * (4 * rb) * V5
+    if adj["adjoint_ms"]:
+        adj["roofline"] = {"bound": "mfma",
+                           "achieved": aflops / (adj["adjoint_ms"] * 1e-3) / 1e12,
+                           "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
+                           "frac": aflops / (adj["adjoint_ms"] * 1e-3) / 1e12 / PEAK_TFLOPS["bf16"]}
     if args.check_adjoint:
         # gradient check on sampled edges against the FP64 oracle
         Fo = np.zeros(Hp.shape, np.complex128)
