@@ -10,6 +10,9 @@ is also run with the FP32 contraction (the comparison form) and split-fp16.
 
 Further forms, reported beside the headline:
   layout clip   2,000 polygons, T = 4096, |k|,|l| <= 255, FP32 and split-bf16
+  lattice form  the FP64 lattice (FFT) form on the precision and layout clips
+  single        one 64-corner polygon, T = 2048, |k|,|l| <= 64: microseconds
+                per direct call and per one-clip graph replay
   batch         256 clips, corners log-uniform in [1k, 200k], (T, K) in
                 {(1024,63), (2048,127), (4096,255), (8192,511)}, one replayed
                 graph, split-bf16
@@ -322,6 +325,37 @@ def main() -> int:
     lattice["layout_clip"] = {"value": p2 / (ms2f * 1e-3), "ms_per_step": ms2f, "err_rel_f00": e2f}
     log(f"layout clip lattice form: {ms2f:.3f} ms  {p2 / ms2f * 1e3:.4g} pairs/s  err {e2f:.2e}")
     forms["lattice_form"] = lattice
+
+    # ------------------------------------------------------------------ C1
+    # One 64-corner polygon, T = 2048, |k|,|l| <= 64: a latency case (a few
+    # microseconds of work).  The direct call and a one-clip captured graph
+    # are timed; the error is over the whole 129 x 129 grid.
+    c1, _, _ = synth.clip_c1(1)
+    x1, y1, s1, _, _ = P.loops_to_corners(c1.xy, c1.off)
+    x1d, y1d, s1d = (torch.as_tensor(a).to(dev) for a in (x1, y1, s1))
+    ref1, area1 = oracle.cfs_grid(c1.xy, c1.off, c1.T, c1.K, c1.L)
+    f001 = abs(ref1[c1.K, c1.L])
+    p1 = int(x1.size) * (2 * c1.K + 1) * (2 * c1.L + 1)
+    single = {"workload": (f"single polygon: {x1.size} corners (union of rectangles), "
+                           f"T={c1.T}, |k|,|l|<={c1.K}"), "area": int(area1)}
+    n1 = max(50, args.steps * 5)
+    for prec in ("fp32", "bf16"):
+        F1 = torch.empty((2 * c1.K + 1, 2 * c1.L + 1), dtype=torch.complex64, device=dev)
+        a1 = torch.empty(1, dtype=torch.int64, device=dev)
+        ms1, _ = timed(lambda: P.forward(x1d, y1d, s1d, c1.T, c1.K, c1.L, precision=prec,
+                                         out=F1, area_out=a1), n1, 5, h)
+        e1 = float(np.max(np.abs(F1.cpu().numpy().astype(np.complex128) - ref1)) / f001)
+        b1 = P.Batch([(x1d, y1d, s1d, c1.T, c1.K, c1.L)], precision=prec)
+        msg, _ = timed(b1.run, n1, 5, h, kinds=("batch",))
+        eg = float(np.max(np.abs(b1.F[0].cpu().numpy().astype(np.complex128) - ref1)) / f001)
+        single[prec] = {"us_per_call": ms1 * 1e3, "us_per_graph_replay": msg * 1e3,
+                        "value": p1 / (ms1 * 1e-3), "err_rel_f00": max(e1, eg),
+                        "area_exact": int(a1.item()) == int(area1)
+                        and int(b1.area[0].item()) == int(area1)}
+        b1.close()
+        log(f"single polygon {prec}: {ms1 * 1e3:.1f} us per call, {msg * 1e3:.1f} us per "
+            f"graph replay, err {max(e1, eg):.2e}")
+    forms["single_polygon"] = single
 
     # ------------------------------------------------------------------ C4
     t0 = time.time()

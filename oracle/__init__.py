@@ -1,13 +1,15 @@
-"""FP64 CPU oracle for the continuous Fourier series of rectilinear polygons.
+"""CPU oracles for the continuous Fourier series (FP64) and the pruned
+continuous Haar transform (exact integer areas) of rectilinear polygons.
 
 TEST INFRASTRUCTURE ONLY.  Only the tests, ``__graft_entry__.smoke()`` and the
 benchmark's CPU-baseline leg may import this package.  It shares no code with
 the HIP library (``paper_1010_5562_amd``) and imports nothing from it.
 
-The arithmetic lives in ``fcfs_oracle.c`` (plain C, FP64, optional OpenMP);
-this module only compiles it with gcc and marshals numpy arrays through ctypes.
-See the header of ``fcfs_oracle.c`` for the formulas and their sources in the
-paper (Prop. 3 of Sec. III-C1, edge form).
+The arithmetic lives in ``fcfs_oracle.c`` (plain C, FP64, optional OpenMP)
+and ``pcht_oracle.c`` (plain C, int64 areas); this module only compiles them
+with gcc and marshals numpy arrays through ctypes.  See the headers of the C
+files for the formulas and their sources in the paper (Prop. 3 of Sec.
+III-C1, edge form; Sec. III-B1 and Algorithm 1 for the Haar transform).
 
 Polygons are passed as loops: ``xy`` is an ``(n_vertices, 2)`` array of
 coordinates, ``off`` an ``(n_loops + 1,)`` int64 array of loop offsets.  Edge
@@ -22,7 +24,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "fcfs_oracle.c")
+_SRCS = [os.path.join(_HERE, "fcfs_oracle.c"), os.path.join(_HERE, "pcht_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle_fcfs.so")
 
 _lib = None
@@ -33,7 +35,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.run(
-            ["gcc", "-O2", "-fopenmp", "-Wall", "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"],
+            ["gcc", "-O2", "-fopenmp", "-Wall", "-shared", "-fPIC", *_SRCS, "-o", tmp, "-lm"],
             check=True,
         )
         os.replace(tmp, _LIB)
@@ -54,6 +56,8 @@ def _load():
     lib.fo_edge_grad.argtypes = [P, P, i64, i64, i32, i32, c_int, P, P, i64, c_int, P]
     lib.fo_loop_areas.argtypes = [P, P, i64, P]
     lib.fo_threads.argtypes = [c_int]
+    lib.po_pcht.argtypes = [P, P, i64, i64, i64, c_int, P, P, P]
+    lib.po_pcht.restype = ctypes.c_int
     for f in (lib.fo_cfs_grid, lib.fo_cfs_points, lib.fo_edge_grad, lib.fo_loop_areas,
               lib.fo_threads):
         f.restype = ctypes.c_int
@@ -144,3 +148,20 @@ def loop_areas(xy, off):
     a = np.zeros(max(off.size - 1, 1), dtype=np.int64)
     _check(lib.fo_loop_areas(_ptr(xy), _ptr(off), off.size - 1, _ptr(a)), "fo_loop_areas")
     return a[: off.size - 1]
+
+
+def pcht(xy, off, Nx: int, Ny: int, J: int):
+    """Pruned continuous Haar transform of the polygons over [0,Nx) x [0,Ny)
+    with J levels of wavelets.  Returns ``(U, W, nodes)``: U the 2^J x 2^J
+    int64 pyramid of integer area sums, W the coefficients (float64), nodes
+    the number of non-terminating recursive calls."""
+    lib = _load()
+    xy, off = _loops(xy, off)
+    side = 1 << int(J)
+    U = np.zeros(side * side, dtype=np.int64)
+    W = np.zeros(side * side, dtype=np.float64)
+    nodes = np.zeros(1, dtype=np.int64)
+    st = lib.po_pcht(_ptr(xy), _ptr(off), off.size - 1, int(Nx), int(Ny), int(J), _ptr(U),
+                     _ptr(W), _ptr(nodes))
+    _check(st, "po_pcht")
+    return U.reshape(side, side), W.reshape(side, side), int(nodes[0])
