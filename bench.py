@@ -11,6 +11,8 @@ is also run with the FP32 contraction (the comparison form) and split-fp16.
 Further forms, reported beside the headline:
   layout clip   2,000 polygons, T = 4096, |k|,|l| <= 255, FP32 and split-bf16
   lattice form  the FP64 lattice (FFT) form on the precision and layout clips
+  pcht          the pruned continuous Haar transform of the layout clip, 12
+                levels over its 4096 tile, bit-exact against the oracle
   single        one 64-corner polygon, T = 2048, |k|,|l| <= 64: microseconds
                 per direct call and per one-clip graph replay
   batch         256 clips, corners log-uniform in [1k, 200k], (T, K) in
@@ -325,6 +327,53 @@ def main() -> int:
     lattice["layout_clip"] = {"value": p2 / (ms2f * 1e-3), "ms_per_step": ms2f, "err_rel_f00": e2f}
     log(f"layout clip lattice form: {ms2f:.3f} ms  {p2 / ms2f * 1e3:.4g} pairs/s  err {e2f:.2e}")
     forms["lattice_form"] = lattice
+
+    # ------------------------------------------------- pruned Haar transform
+    # The PCHT of the same layout clip over its 4096 tile, all 12 wavelet
+    # levels (a 4096 x 4096 pyramid of int64 sums and float64 coefficients).
+    # Checked bit for bit against the oracle; the oracle's single-threaded
+    # time on the whole clip is reported beside it.
+    Jh = 12
+    off2d = torch.as_tensor(c2.off).to(dev)
+    Uh = torch.empty((1 << Jh, 1 << Jh), dtype=torch.int64, device=dev)
+    Wh = torch.empty((1 << Jh, 1 << Jh), dtype=torch.float64, device=dev)
+    msh, profh = timed(lambda: P.haar(x2d, y2d, s2d, off2d, T2, T2, Jh, out_U=Uh, out_W=Wh),
+                       args.steps, args.warmup, h, kinds=("prepass", "haar", "epilogue"))
+    _, _, sth = P.haar(x2d, y2d, s2d, off2d, T2, T2, Jh, out_U=Uh, out_W=Wh, stats=True)
+    cells, pairs_h = (int(v) for v in sth.cpu().numpy())
+    tc = time.perf_counter()
+    Uo, Wo, nodes_o = oracle.pcht(c2.xy, c2.off, T2, T2, Jh)
+    t_or = time.perf_counter() - tc
+    exact = bool(np.array_equal(Uh.cpu().numpy(), Uo)) and cells == nodes_o
+    exact_w = bool(np.array_equal(Wh.cpu().numpy(), Wo))
+    walk_ms = kavg(profh, "haar")
+    # 14 integer operations per (cell, horizontal edge): two clamped widths
+    # and two clamped heights (six med3, four subtractions) and four
+    # multiply-adds; a loop has one horizontal edge per two corners
+    ops = 7 * pairs_h
+    peak_alu = 256 * 4 * 16 * 2.4e9 / 1e12  # 32-bit integer VALU, T ops/s
+    pyr_bytes = (1 << (2 * Jh)) * 8
+    forms["pcht"] = {
+        "workload": (f"pruned continuous Haar transform of the layout clip ({c2.n_loops} polygons, "
+                     f"{V2} corners), tile {T2} x {T2}, J={Jh} (full {1 << Jh} x {1 << Jh} "
+                     "pyramid, int64 sums and float64 coefficients)"),
+        "ms_per_step": msh, "cells_visited": cells, "cell_corner_pairs": pairs_h,
+        "nonzero_coefficients": int(np.count_nonzero(Uo)),
+        "bit_exact_vs_oracle": exact, "coefficients_bit_exact": exact_w,
+        "kernels_ms": {"clear_and_plan": kavg(profh, "prepass"), "walk": walk_ms,
+                       "scale": kavg(profh, "epilogue")},
+        "roofline": {"bound": "alu", "kernel": "k_haar_walk",
+                     "achieved": ops / (walk_ms * 1e-3) / 1e12 if walk_ms else None,
+                     "peak": peak_alu, "unit": "Tops/s",
+                     "frac": ops / (walk_ms * 1e-3) / 1e12 / peak_alu if walk_ms else None},
+        "pyramid_passes_GBps": {
+            "clear": pyr_bytes / (kavg(profh, "prepass") * 1e-3) / 1e9,
+            "scale": 2 * pyr_bytes / (kavg(profh, "epilogue") * 1e-3) / 1e9},
+        "cpu_oracle": {"seconds": t_or, "cores": 1, "kind": "oracle",
+                       "sample": "the whole clip, all levels"},
+    }
+    log(f"PCHT: {msh:.3f} ms/step (walk {walk_ms:.3f} ms), {cells} cells, exact {exact}/{exact_w}, "
+        f"oracle {t_or:.2f} s")
 
     # ------------------------------------------------------------------ C1
     # One 64-corner polygon, T = 2048, |k|,|l| <= 64: a latency case (a few

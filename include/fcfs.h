@@ -144,6 +144,46 @@ fcfs_status fcfs_forward_band(fcfs_handle *h, const fcfs_clip *c, int32_t kmax, 
 fcfs_status fcfs_fft_workspace_size(const fcfs_clip *c, size_t *bytes);
 fcfs_status fcfs_forward_fft(fcfs_handle *h, const fcfs_clip *c, void *ws, size_t ws_bytes);
 
+/* Pruned continuous Haar transform (PCHT, Sec. III-B1) of the polygons of one
+ * tile [0,Nx) x [0,Ny): the inner products of the sum of polygon indicators
+ * with the 2-D Haar basis of Sec. II-B (scaling function phi_{0,0,0} and the
+ * wavelets psi^{hg}, psi^{gh}, psi^{hh} of levels j = 0..J-1, positions
+ * kx, ky < 2^j; psi^{ab} = sum_{n,m} a_n b_m phi_{j+1,2kx+n,2ky+m} with
+ * g = (1,1)/sqrt2, h = (1,-1)/sqrt2, n along x, m along y).  Per polygon the
+ * quadtree is refined where a cell meets the polygon's boundary; intersection
+ * areas are exact integers.  Polygons may extend past the tile (clipped).
+ * Output: a 2^J x 2^J row-major pyramid.  [0][0] holds the scaling
+ * coefficient; with p = 2^j, level j has hg at [ky][p+kx], gh at [p+ky][kx]
+ * and hh at [p+ky][p+kx].  U gets the integer sums (the coefficient times
+ * sqrt(Nx Ny) / 2^j, i.e. signed sums of child areas), W the coefficients.
+ * Requirements: 1 <= Nx, Ny <= 8192, 0 <= J <= 13, 2^J divides Nx and Ny.
+ * Polygon offsets must be nondecreasing (they are clamped to [0, V]). */
+typedef struct {
+  const int32_t *x;         /* (device) [V] corner abscissae, loop order       */
+  const int32_t *y;         /* (device) [V] corner ordinates                   */
+  const int8_t *s;          /* (device) [V] corner signs (fcfs_loops_to_corners) */
+  const int64_t *poly_off;  /* (device) [M+1] polygon m = corners
+                               poly_off[m] .. poly_off[m+1]-1                  */
+  int64_t V;                /* corners                                        */
+  int64_t M;                /* polygons                                       */
+  int32_t Nx, Ny;           /* tile size (lattice units)                      */
+  int32_t J;                /* wavelet levels                                 */
+  int64_t *U;               /* (device) out: [4^J] int64 integer sums          */
+  double *W;                /* (device) out: [4^J] coefficients, or NULL       */
+  int64_t *stats;           /* (device) out: [2] cells visited (calls that
+                               split a cell) and cell-corner pairs, or NULL    */
+} fcfs_haar_clip;
+
+/* Workspace of fcfs_haar (depends on M only: control words, per-polygon task
+ * counts and the task list of large polygons split over several waves; about
+ * 4 M + 8 max(M, 4096) bytes), 256-byte aligned.  FCFS_ERR_UNSUPPORTED /
+ * FCFS_ERR_INVALID_ARG for sizes outside the limits. */
+fcfs_status fcfs_haar_workspace_size(const fcfs_haar_clip *c, size_t *bytes);
+/* Enqueues the transform on the handle's stream: clears U (a fill kernel),
+ * walks every polygon's quadtree (one wave per polygon), then scales U into
+ * W when W is not NULL.  Calls that overlap on one workspace race. */
+fcfs_status fcfs_haar(fcfs_handle *h, const fcfs_haar_clip *c, void *ws, size_t ws_bytes);
+
 /* Adjoint of fcfs_forward with respect to the corner coordinates (the
  * derivative of the four closed forms of Prop. 3 in x_v and y_v).
  * grad_F: (device) cotangent, same layout as c->F, holding
@@ -240,8 +280,10 @@ fcfs_status fcfs_workspace_size_tile(const fcfs_clip *c, fcfs_precision p, int32
  * writes, for kind i < nkinds, the summed milliseconds ms[i] and the launch
  * count count[i], then stops recording.  Kinds: 0 pre-pass, 1 side-stream
  * work (histograms, guard block, axis DFTs), 2 contraction, 3 epilogue,
- * 4 adjoint kernels, 5 batched graph.  Each bracketed launch adds two event
- * records to its stream. */
+ * 4 adjoint kernels, 5 batched graph, 6 lattice form, 7 Haar quadtree walk
+ * (the Haar transform's clear-and-plan launches count as pre-pass, its
+ * scaling pass as epilogue).
+ * Each bracketed launch adds two event records to its stream. */
 fcfs_status fcfs_profile_begin(fcfs_handle *h, uint32_t kinds);
 fcfs_status fcfs_profile_end(fcfs_handle *h, double *ms, int64_t *count, int32_t nkinds);
 

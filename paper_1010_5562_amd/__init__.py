@@ -12,11 +12,11 @@ import ctypes
 
 import numpy as np
 
-from ._lib import PRECISIONS, FcfsClip, FcfsError, check, load  # noqa: F401
+from ._lib import PRECISIONS, FcfsClip, FcfsError, FcfsHaarClip, check, load  # noqa: F401
 
 __all__ = [
     "Handle", "FcfsError", "loops_to_corners", "forward", "workspace_size", "debug_phases",
-    "tile_variants", "PRECISIONS",
+    "tile_variants", "PRECISIONS", "haar",
 ]
 
 
@@ -123,7 +123,8 @@ class Handle:
     def set_tile(self, variant: int = -1):
         check(self.lib.fcfs_set_tile(self._h, int(variant)), self._h)
 
-    PROFILE_KINDS = ("prepass", "axis", "contract", "epilogue", "adjoint", "batch", "fft")
+    PROFILE_KINDS = ("prepass", "axis", "contract", "epilogue", "adjoint", "batch", "fft",
+                     "haar")
 
     def profile_begin(self, kinds=None):
         """Starts event timing of the named kinds (all kinds when None)."""
@@ -244,6 +245,45 @@ def forward_fft(x, y, s, T: int, K: int, L: int | None = None, handle=None, out=
     check(h.lib.fcfs_forward_fft(h.ptr, ctypes.byref(c), ctypes.c_void_p(ws.data_ptr()),
                                  ctypes.c_size_t(ws.numel())), h.ptr)
     return F, area
+
+
+def haar(x, y, s, poly_off, Nx: int, Ny: int, J: int, handle=None, out_U=None, out_W=None,
+         coefficients: bool = True, stats: bool = False):
+    """Pruned continuous Haar transform of one tile (``fcfs_haar``).
+
+    x, y, s: corners in loop order (``loops_to_corners``); poly_off: the
+    (M + 1,) int64 polygon offsets into them.  Returns ``(U, W, st)``: U the
+    2^J x 2^J int64 pyramid of integer sums, W the float64 coefficients (None
+    unless ``coefficients``), st a 2-element int64 tensor (cells visited,
+    cell-corner pairs) or None."""
+    import torch
+
+    h = handle or default_handle()
+    h.sync_stream()
+    x, y, s = _corners_on(h.device, x, y, s)
+    off = torch.as_tensor(poly_off, dtype=torch.int64).to(h.device).contiguous()
+    side = 1 << int(J)
+    U = out_U if out_U is not None else torch.empty((side, side), dtype=torch.int64,
+                                                    device=h.device)
+    if U.dtype != torch.int64 or U.numel() != side * side or not U.is_contiguous():
+        raise ValueError("out_U must be a contiguous int64 tensor of 4^J entries")
+    W = None
+    if coefficients:
+        W = out_W if out_W is not None else torch.empty((side, side), dtype=torch.float64,
+                                                        device=h.device)
+        if W.dtype != torch.float64 or W.numel() != side * side or not W.is_contiguous():
+            raise ValueError("out_W must be a contiguous float64 tensor of 4^J entries")
+    st = torch.empty(2, dtype=torch.int64, device=h.device) if stats else None
+    c = FcfsHaarClip(x.data_ptr(), y.data_ptr(), s.data_ptr(), off.data_ptr(), x.numel(),
+                     max(0, off.numel() - 1), int(Nx), int(Ny), int(J), U.data_ptr(),
+                     W.data_ptr() if W is not None else None,
+                     st.data_ptr() if st is not None else None)
+    nb = ctypes.c_size_t(0)
+    check(h.lib.fcfs_haar_workspace_size(ctypes.byref(c), ctypes.byref(nb)))
+    ws = h.workspace(nb.value)
+    check(h.lib.fcfs_haar(h.ptr, ctypes.byref(c), ctypes.c_void_p(ws.data_ptr()),
+                          ctypes.c_size_t(ws.numel())), h.ptr)
+    return U, W, st
 
 
 def debug_phases(x, y, s, T: int, k0: int, nk: int, axis: int = 0, handle=None):

@@ -20,7 +20,7 @@ using fcfs::Tables;
 
 // Kernel families timed by the profiling hooks.
 enum ProfKind { kProfPrepass = 0, kProfAxis, kProfContract, kProfEpilogue, kProfAdjoint,
-                kProfBatch, kProfFft, kProfKinds };
+                kProfBatch, kProfFft, kProfHaar, kProfKinds };
 
 struct fcfs_handle {
   int device = 0;
@@ -764,6 +764,62 @@ fcfs_status fcfs_forward_fft(fcfs_handle *h, const fcfs_clip *c, void *ws, size_
     ProfScope ps(h, kProfEpilogue);
     if ((e = fcfs::launch_epilogue_axes(q, ws, c->F, c->area, h->stream)))
       return hip_fail(h, e, "epilogue launch");
+  }
+  return FCFS_OK;
+}
+
+namespace {
+fcfs_status check_haar(fcfs_handle *h, const fcfs_haar_clip *c, bool pointers) {
+  if (!c) return fail(h, FCFS_ERR_INVALID_ARG, "clip is NULL");
+  if (c->V < 0 || c->M < 0) return fail(h, FCFS_ERR_INVALID_ARG, "V and M must be >= 0");
+  if (c->M >= ((int64_t)1 << 31) || c->V >= ((int64_t)1 << 40))
+    return fail(h, FCFS_ERR_UNSUPPORTED, "V or M too large");
+  if (c->J < 0 || c->J > fcfs::kHaarMaxJ)
+    return fail(h, FCFS_ERR_UNSUPPORTED, "J must be in [0, 13]");
+  if (c->Nx < 1 || c->Ny < 1 || c->Nx > fcfs::kHaarMaxSide || c->Ny > fcfs::kHaarMaxSide)
+    return fail(h, FCFS_ERR_UNSUPPORTED, "Nx, Ny must be in [1, 8192]");
+  if ((c->Nx & ((1 << c->J) - 1)) || (c->Ny & ((1 << c->J) - 1)))
+    return fail(h, FCFS_ERR_INVALID_ARG, "2^J must divide Nx and Ny");
+  if (pointers) {
+    if (!c->U) return fail(h, FCFS_ERR_INVALID_ARG, "U is NULL");
+    if (c->M > 0 && (!c->poly_off || (c->V > 0 && (!c->x || !c->y || !c->s))))
+      return fail(h, FCFS_ERR_INVALID_ARG, "NULL corner or offset array");
+  }
+  return FCFS_OK;
+}
+}  // namespace
+
+fcfs_status fcfs_haar_workspace_size(const fcfs_haar_clip *c, size_t *bytes) {
+  if (!bytes) return fail(nullptr, FCFS_ERR_INVALID_ARG, "NULL argument");
+  fcfs_status st = check_haar(nullptr, c, false);
+  if (st) return st;
+  *bytes = fcfs::haar_workspace_bytes(c->M);
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_haar(fcfs_handle *h, const fcfs_haar_clip *c, void *ws, size_t ws_bytes) {
+  fcfs_status st = enter(h);
+  if (st) return st;
+  if ((st = check_haar(h, c, true))) return st;
+  const size_t need = fcfs::haar_workspace_bytes(c->M);
+  if (ws_bytes < need || !ws)
+    return fail(h, FCFS_ERR_WORKSPACE,
+                "workspace too small or NULL: need " + std::to_string(need) + " bytes");
+  if (((uintptr_t)ws & 255u) != 0) return fail(h, FCFS_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  fcfs::HaarArgs a{c->x, c->y, c->s, c->poly_off, c->M, c->V, c->Nx, c->Ny, c->J,
+                   c->U, c->W, c->stats};
+  hipError_t e;
+  {
+    ProfScope ps(h, kProfPrepass);
+    if ((e = fcfs::launch_haar_prep(a, ws, h->stream))) return hip_fail(h, e, "PCHT pre-pass launch");
+  }
+  {
+    ProfScope ps(h, kProfHaar);
+    if ((e = fcfs::launch_haar_walk(a, ws, h->stream))) return hip_fail(h, e, "PCHT walk launch");
+  }
+  {
+    ProfScope ps(h, kProfEpilogue);
+    if ((e = fcfs::launch_haar_scale(a, h->stream))) return hip_fail(h, e, "PCHT scale launch");
   }
   return FCFS_OK;
 }

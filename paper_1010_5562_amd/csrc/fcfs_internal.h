@@ -3,6 +3,9 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -172,5 +175,28 @@ struct TileVariant {
 };
 int n_tile_variants();
 const TileVariant &tile_variant(int i);
+
+// Pruned continuous Haar transform of one tile (Sec. III-B1).
+constexpr int kHaarMaxJ = 13;      // deepest pyramid (tiles up to 8192 units)
+constexpr int kHaarMaxSide = 8192; // largest Nx, Ny
+struct HaarArgs {
+  const int32_t *x, *y;  // corners, loop order
+  const int8_t *s;       // corner signs
+  const int64_t *off;    // polygon offsets [M + 1]
+  int64_t M, V;
+  int Nx, Ny, J;
+  int64_t *U;            // [4^J] integer sums
+  double *W;             // [4^J] coefficients, or nullptr
+  int64_t *stats;        // [2] cells visited, cell-corner pairs; or nullptr
+};
+// Workspace of the Haar launches for M polygons (control words, task counts
+// and the list of extra tasks of split polygons).
+size_t haar_workspace_bytes(int64_t M);
+// clears U and the control words, plans the split of large polygons
+hipError_t launch_haar_prep(const HaarArgs &a, void *ws, hipStream_t st);
+// the quadtree walk (coefficients into U)
+hipError_t launch_haar_walk(const HaarArgs &a, void *ws, hipStream_t st);
+// W from U (no-op when W is null)
+hipError_t launch_haar_scale(const HaarArgs &a, hipStream_t st);
 
 }  // namespace fcfs
