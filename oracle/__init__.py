@@ -57,6 +57,8 @@ def _load():
     lib.fo_loop_areas.argtypes = [P, P, i64, P]
     lib.fo_threads.argtypes = [c_int]
     lib.po_pcht.argtypes = [P, P, i64, i64, i64, c_int, P, P, P]
+    lib.fo_cfs_grid_general.argtypes = [P, P, i64, i64, i64, i32, i32, i32, c_int, P, P]
+    lib.fo_cfs_grid_general.restype = ctypes.c_int
     lib.po_pcht.restype = ctypes.c_int
     for f in (lib.fo_cfs_grid, lib.fo_cfs_points, lib.fo_edge_grad, lib.fo_loop_areas,
               lib.fo_threads):
@@ -101,6 +103,23 @@ def cfs_grid(xy, off, T: int, K: int, L: int, lattice: bool = True, nthreads: in
     st = lib.fo_cfs_grid(_ptr(xy), _ptr(off), off.size - 1, int(T), int(K), int(L),
                          int(bool(lattice)), int(nthreads), _ptr(F), _ptr(area))
     _check(st, "fo_cfs_grid")
+    return F.view(np.complex128).reshape(2 * K + 1, 2 * L + 1), int(area[0])
+
+
+def cfs_grid_general(xy, off, Nx: int, Ny: int, K: int, L: int, frac_bits: int = 0,
+                     nthreads: int = 0):
+    """Coefficients over an Nx x Ny tile (Prop. 3 with its general factors) for
+    vertices on the grid of step 2^-frac_bits (``xy`` holds the true
+    coordinates).  Returns ``(F, area)``, F (2K+1, 2L+1) complex128 indexed
+    [k + K, l + L] and area = the signed area times 4^frac_bits (exact)."""
+    lib = _load()
+    xy, off = _loops(xy, off)
+    F = np.zeros((2 * K + 1) * (2 * L + 1) * 2, dtype=np.float64)
+    area = np.zeros(1, dtype=np.int64)
+    st = lib.fo_cfs_grid_general(_ptr(xy), _ptr(off), off.size - 1, int(Nx), int(Ny),
+                                 int(frac_bits), int(K), int(L), int(nthreads), _ptr(F),
+                                 _ptr(area))
+    _check(st, "fo_cfs_grid_general")
     return F.view(np.complex128).reshape(2 * K + 1, 2 * L + 1), int(area[0])
 
 

@@ -266,6 +266,136 @@ int fo_cfs_grid(const double *xy, const int64_t *off, int64_t n_loops, int64_t T
   return FO_OK;
 }
 
+/* ---------------------------------------------------------------------------
+ * General tile: periods Nx along x and Ny along y (any positive integers, Sec.
+ * II-C), vertices on the grid of step 2^-F (F = frac_bits >= 0; F = 0 is the
+ * integer lattice of Sec. II-A2).  Prop. 3 with its general factors:
+ *
+ *   alpha_00 = 1 / sqrt(Nx Ny),              alpha_k0 = j/(2 pi k) sqrt(Nx/Ny),
+ *   alpha_0l = j/(2 pi l) sqrt(Ny/Nx),       alpha_kl = -sqrt(Nx Ny) / (4 pi^2 k l),
+ *
+ * and phases w_x k x = 2 pi k x / Nx reduced exactly: with X = x 2^F (an
+ * integer) and Mx = Nx 2^F, k x / Nx = (k X mod Mx) / Mx + an integer.
+ * --------------------------------------------------------------------------- */
+typedef struct {
+  int64_t M;
+  fo_c *tab; /* e^{-j 2 pi r / M}, r = 0..M-1 */
+} fo_period;
+
+static int period_init(fo_period *p, int64_t M) {
+  p->M = M;
+  p->tab = (fo_c *)malloc(sizeof(fo_c) * (size_t)M);
+  if (!p->tab) return FO_ERR_NOMEM;
+  for (int64_t r = 0; r < M; ++r) {
+    double ang = 2.0 * FO_PI * (double)r / (double)M;
+    p->tab[r].re = cos(ang);
+    p->tab[r].im = -sin(ang);
+  }
+  return FO_OK;
+}
+
+/* e^{-j 2 pi k X / M} for an integer X (the coordinate times 2^F). */
+static fo_c period_expo(const fo_period *p, int64_t k, int64_t X) {
+  int64_t xr = ((X % p->M) + p->M) % p->M;
+  int64_t r = ((k % p->M) * xr) % p->M;
+  if (r < 0) r += p->M;
+  return p->tab[r];
+}
+
+static fo_c coef_general(const fo_period *px, const fo_period *py, double Nx, double Ny,
+                         double scale, const fo_edge *E, int64_t n, int64_t k, int64_t l) {
+  fo_c acc = {0.0, 0.0};
+  if (k == 0 && l == 0) {
+    for (int64_t e = 0; e < n; ++e)
+      if (E[e].horizontal) acc.re += E[e].sigma * E[e].ya * (E[e].xb - E[e].xa);
+    acc.re /= sqrt(Nx * Ny);
+    return acc;
+  }
+  if (l == 0) {
+    for (int64_t e = 0; e < n; ++e) {
+      if (E[e].horizontal) continue;
+      fo_c w = period_expo(px, k, (int64_t)llround(E[e].xa * scale));
+      double len = E[e].sigma * (E[e].ya - E[e].yb);
+      acc.re += len * w.re;
+      acc.im += len * w.im;
+    }
+    double sc = sqrt(Nx / Ny) / (2.0 * FO_PI * (double)k);
+    fo_c r = {-acc.im * sc, acc.re * sc};
+    return r;
+  }
+  if (k == 0) {
+    for (int64_t e = 0; e < n; ++e) {
+      if (!E[e].horizontal) continue;
+      fo_c w = period_expo(py, l, (int64_t)llround(E[e].ya * scale));
+      double len = E[e].sigma * (E[e].xb - E[e].xa);
+      acc.re += len * w.re;
+      acc.im += len * w.im;
+    }
+    double sc = sqrt(Ny / Nx) / (2.0 * FO_PI * (double)l);
+    fo_c r = {-acc.im * sc, acc.re * sc};
+    return r;
+  }
+  for (int64_t e = 0; e < n; ++e) {
+    if (!E[e].horizontal) continue;
+    fo_c wy = period_expo(py, l, (int64_t)llround(E[e].ya * scale));
+    fo_c wb = period_expo(px, k, (int64_t)llround(E[e].xb * scale));
+    fo_c wa = period_expo(px, k, (int64_t)llround(E[e].xa * scale));
+    fo_c d = {wb.re - wa.re, wb.im - wa.im};
+    fo_c t = cmul(wy, d);
+    acc.re += E[e].sigma * t.re;
+    acc.im += E[e].sigma * t.im;
+  }
+  double a = -sqrt(Nx * Ny) / (4.0 * FO_PI * FO_PI * (double)k * (double)l);
+  acc.re *= a;
+  acc.im *= a;
+  return acc;
+}
+
+/* Full centred grid for the general tile; layout as fo_cfs_grid.  xy holds the
+ * true coordinates (multiples of 2^-F).  area_out: sum over loops of the
+ * signed area times 4^F (an integer). */
+int fo_cfs_grid_general(const double *xy, const int64_t *off, int64_t n_loops, int64_t Nx,
+                        int64_t Ny, int32_t frac_bits, int32_t K, int32_t L, int nthreads,
+                        double *F, int64_t *area_out) {
+  if (Nx < 1 || Ny < 1 || frac_bits < 0 || frac_bits > 20 || K < 0 || L < 0 || !F)
+    return FO_ERR_ARG;
+  const double scale = ldexp(1.0, frac_bits);
+  const int64_t nv = off[n_loops];
+  for (int64_t i = 0; i < 2 * nv; ++i) {
+    double X = xy[i] * scale;
+    if (X != floor(X) || fabs(X) > 1073741823.0) return FO_ERR_RANGE;
+  }
+  fo_edge *E = NULL;
+  int64_t n = 0;
+  int st = build_edges(xy, off, n_loops, 0, &E, &n);
+  if (st) return st;
+  fo_period px, py;
+  if (period_init(&px, Nx << frac_bits)) { free(E); return FO_ERR_NOMEM; }
+  if (period_init(&py, Ny << frac_bits)) { free(px.tab); free(E); return FO_ERR_NOMEM; }
+  set_threads(nthreads);
+  const int64_t W = 2 * (int64_t)L + 1;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t k = -K; k <= K; ++k)
+    for (int64_t l = -L; l <= L; ++l) {
+      fo_c v = coef_general(&px, &py, (double)Nx, (double)Ny, scale, E, n, k, l);
+      int64_t idx = (k + K) * W + (l + L);
+      F[2 * idx] = v.re;
+      F[2 * idx + 1] = v.im;
+    }
+  if (area_out) {
+    int64_t A = 0;
+    for (int64_t e = 0; e < n; ++e)
+      if (E[e].horizontal)
+        A += (int64_t)E[e].sigma * llround(E[e].ya * scale) *
+             (llround(E[e].xb * scale) - llround(E[e].xa * scale));
+    *area_out = A;
+  }
+  free(px.tab);
+  free(py.tab);
+  free(E);
+  return FO_OK;
+}
+
 /* A list of single coefficients (k[i], l[i]); out interleaved (re, im). */
 int fo_cfs_points(const double *xy, const int64_t *off, int64_t n_loops, int64_t T, int lattice,
                   int64_t npts, const int32_t *kk, const int32_t *ll, int nthreads, double *F) {
