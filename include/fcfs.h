@@ -144,6 +144,38 @@ fcfs_status fcfs_forward_band(fcfs_handle *h, const fcfs_clip *c, int32_t kmax, 
 fcfs_status fcfs_fft_workspace_size(const fcfs_clip *c, size_t *bytes);
 fcfs_status fcfs_forward_fft(fcfs_handle *h, const fcfs_clip *c, void *ws, size_t ws_bytes);
 
+/* General tile (Prop. 3 for any periods): the tile is Nx x Ny lattice units
+ * (any positive integers, Nx != Ny allowed, Sec. II-C with w_x = 2 pi / Nx,
+ * w_y = 2 pi / Ny), and corners may sit on the finer grid of step 2^-F
+ * (F = frac_bits; F = 0 is the integer lattice of Sec. II-A2): x[v], y[v] are
+ * the coordinates times 2^F.  The phases k x / Nx are reduced exactly modulo
+ * Mx = Nx 2^F (likewise My); Mx and My must lie in [2, 8192].  Output as
+ * fcfs_forward with alpha_{k,l} = -sqrt(Nx Ny)/(4 pi^2 k l),
+ * alpha_{k,0} = j sqrt(Nx/Ny)/(2 pi k), alpha_{0,l} = j sqrt(Ny/Nx)/(2 pi l),
+ * F[0,0] = area / sqrt(Nx Ny); `area` receives sum_v s_v x[v] y[v] (the area
+ * times 4^F).  The contraction uses per-period tables that the handle builds
+ * on the first call with a period (a synchronous upload) and caches. */
+typedef struct {
+  const int32_t *x;   /* (device) [V] corner abscissae, times 2^frac_bits      */
+  const int32_t *y;   /* (device) [V] corner ordinates, times 2^frac_bits      */
+  const int8_t *s;    /* (device) [V] corner signs                             */
+  int64_t V;
+  int32_t Nx, Ny;     /* tile periods, lattice units                          */
+  int32_t frac_bits;  /* F in [0, 13]                                         */
+  int32_t K, L;       /* cut-offs, <= 4095                                    */
+  float *F;           /* (device) out: (2K+1)(2L+1) complex64, as fcfs_forward */
+  int64_t *area;      /* (device) out: sum s x y in grid units, or NULL        */
+} fcfs_gclip;
+
+/* Workspace of fcfs_forward_general (256-byte aligned).  FCFS_ERR_UNSUPPORTED
+ * when Nx 2^F or Ny 2^F is outside [2, 8192], F > 13 or K, L > 4095. */
+fcfs_status fcfs_general_workspace_size(const fcfs_gclip *c, fcfs_precision p, size_t *bytes);
+/* Forward transform of a general tile: pre-pass (residues, area), axis sums
+ * and FP64 low-frequency block on the side stream, MFMA contraction with
+ * exact phases (f x) mod M, epilogue with the alpha factors above. */
+fcfs_status fcfs_forward_general(fcfs_handle *h, const fcfs_gclip *c, fcfs_precision p, void *ws,
+                                 size_t ws_bytes);
+
 /* Pruned continuous Haar transform (PCHT, Sec. III-B1) of the polygons of one
  * tile [0,Nx) x [0,Ny): the inner products of the sum of polygon indicators
  * with the 2-D Haar basis of Sec. II-B (scaling function phi_{0,0,0} and the

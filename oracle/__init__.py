@@ -59,6 +59,8 @@ def _load():
     lib.po_pcht.argtypes = [P, P, i64, i64, i64, c_int, P, P, P]
     lib.fo_cfs_grid_general.argtypes = [P, P, i64, i64, i64, i32, i32, i32, c_int, P, P]
     lib.fo_cfs_grid_general.restype = ctypes.c_int
+    lib.fo_cfs_points_general.argtypes = [P, P, i64, i64, i64, i32, i64, P, P, c_int, P]
+    lib.fo_cfs_points_general.restype = ctypes.c_int
     lib.po_pcht.restype = ctypes.c_int
     for f in (lib.fo_cfs_grid, lib.fo_cfs_points, lib.fo_edge_grad, lib.fo_loop_areas,
               lib.fo_threads):
@@ -121,6 +123,23 @@ def cfs_grid_general(xy, off, Nx: int, Ny: int, K: int, L: int, frac_bits: int =
                                  _ptr(area))
     _check(st, "fo_cfs_grid_general")
     return F.view(np.complex128).reshape(2 * K + 1, 2 * L + 1), int(area[0])
+
+
+def cfs_points_general(xy, off, Nx: int, Ny: int, k, l, frac_bits: int = 0, nthreads: int = 0):
+    """Single coefficients F[k[i], l[i]] of a general tile (as
+    ``cfs_grid_general``), a complex128 vector."""
+    lib = _load()
+    xy, off = _loops(xy, off)
+    k = np.ascontiguousarray(np.asarray(k, dtype=np.int32).ravel())
+    l = np.ascontiguousarray(np.asarray(l, dtype=np.int32).ravel())
+    if k.size != l.size:
+        raise OracleError("k and l differ in length")
+    F = np.zeros(k.size * 2, dtype=np.float64)
+    st = lib.fo_cfs_points_general(_ptr(xy), _ptr(off), off.size - 1, int(Nx), int(Ny),
+                                   int(frac_bits), k.size, _ptr(k), _ptr(l), int(nthreads),
+                                   _ptr(F))
+    _check(st, "fo_cfs_points_general")
+    return F.view(np.complex128)
 
 
 def cfs_points(xy, off, T: int, k, l, lattice: bool = True, nthreads: int = 0):

@@ -396,6 +396,39 @@ int fo_cfs_grid_general(const double *xy, const int64_t *off, int64_t n_loops, i
   return FO_OK;
 }
 
+/* Single coefficients (k[i], l[i]) of a general tile; out interleaved. */
+int fo_cfs_points_general(const double *xy, const int64_t *off, int64_t n_loops, int64_t Nx,
+                          int64_t Ny, int32_t frac_bits, int64_t npts, const int32_t *kk,
+                          const int32_t *ll, int nthreads, double *F) {
+  if (Nx < 1 || Ny < 1 || frac_bits < 0 || frac_bits > 20 || npts < 0 || !F ||
+      (npts > 0 && (!kk || !ll)))
+    return FO_ERR_ARG;
+  const double scale = ldexp(1.0, frac_bits);
+  const int64_t nv = off[n_loops];
+  for (int64_t i = 0; i < 2 * nv; ++i) {
+    double X = xy[i] * scale;
+    if (X != floor(X) || fabs(X) > 1073741823.0) return FO_ERR_RANGE;
+  }
+  fo_edge *E = NULL;
+  int64_t n = 0;
+  int st = build_edges(xy, off, n_loops, 0, &E, &n);
+  if (st) return st;
+  fo_period px, py;
+  if (period_init(&px, Nx << frac_bits)) { free(E); return FO_ERR_NOMEM; }
+  if (period_init(&py, Ny << frac_bits)) { free(px.tab); free(E); return FO_ERR_NOMEM; }
+  set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < npts; ++i) {
+    fo_c v = coef_general(&px, &py, (double)Nx, (double)Ny, scale, E, n, kk[i], ll[i]);
+    F[2 * i] = v.re;
+    F[2 * i + 1] = v.im;
+  }
+  free(px.tab);
+  free(py.tab);
+  free(E);
+  return FO_OK;
+}
+
 /* A list of single coefficients (k[i], l[i]); out interleaved (re, im). */
 int fo_cfs_points(const double *xy, const int64_t *off, int64_t n_loops, int64_t T, int lattice,
                   int64_t npts, const int32_t *kk, const int32_t *ll, int nthreads, double *F) {

@@ -12,11 +12,12 @@ import ctypes
 
 import numpy as np
 
-from ._lib import PRECISIONS, FcfsClip, FcfsError, FcfsHaarClip, check, load  # noqa: F401
+from ._lib import (PRECISIONS, FcfsClip, FcfsError, FcfsGClip, FcfsHaarClip, check,  # noqa: F401
+                   load)
 
 __all__ = [
     "Handle", "FcfsError", "loops_to_corners", "forward", "workspace_size", "debug_phases",
-    "tile_variants", "PRECISIONS", "haar",
+    "tile_variants", "PRECISIONS", "haar", "forward_general",
 ]
 
 
@@ -244,6 +245,35 @@ def forward_fft(x, y, s, T: int, K: int, L: int | None = None, handle=None, out=
     ws = h.workspace(nb.value)
     check(h.lib.fcfs_forward_fft(h.ptr, ctypes.byref(c), ctypes.c_void_p(ws.data_ptr()),
                                  ctypes.c_size_t(ws.numel())), h.ptr)
+    return F, area
+
+
+def forward_general(x, y, s, Nx: int, Ny: int, K: int, L: int | None = None, frac_bits: int = 0,
+                    precision="bf16", handle=None, out=None, area_out=None):
+    """Coefficients of a general tile (``fcfs_forward_general``): periods Nx,
+    Ny (any integers), corners on the grid of step 2^-frac_bits given as
+    integers (true coordinate times 2^frac_bits).  Returns ``(F, area)`` as
+    ``forward``; area is sum s x y in grid units (the area times
+    4^frac_bits)."""
+    import torch
+
+    L = K if L is None else L
+    h = handle or default_handle()
+    h.sync_stream()
+    x, y, s = _corners_on(h.device, x, y, s)
+    F = out if out is not None else torch.empty((2 * K + 1, 2 * L + 1), dtype=torch.complex64,
+                                                device=h.device)
+    if F.dtype != torch.complex64 or F.numel() != (2 * K + 1) * (2 * L + 1) or not F.is_contiguous():
+        raise ValueError("out must be a contiguous complex64 tensor of (2K+1)(2L+1) entries")
+    area = area_out if area_out is not None else torch.empty(1, dtype=torch.int64, device=h.device)
+    c = FcfsGClip(x.data_ptr(), y.data_ptr(), s.data_ptr(), x.numel(), int(Nx), int(Ny),
+                  int(frac_bits), int(K), int(L), F.data_ptr(), area.data_ptr())
+    nb = ctypes.c_size_t(0)
+    check(h.lib.fcfs_general_workspace_size(ctypes.byref(c), _prec(precision), ctypes.byref(nb)))
+    ws = h.workspace(nb.value)
+    check(h.lib.fcfs_forward_general(h.ptr, ctypes.byref(c), _prec(precision),
+                                     ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel())),
+          h.ptr)
     return F, area
 
 

@@ -30,6 +30,7 @@ EXPORTS = (
     "fcfs_create", "fcfs_destroy", "fcfs_set_stream", "fcfs_loops_to_corners",
     "fcfs_workspace_size", "fcfs_forward", "fcfs_band_workspace_size", "fcfs_forward_band",
     "fcfs_fft_workspace_size", "fcfs_forward_fft", "fcfs_haar_workspace_size", "fcfs_haar",
+    "fcfs_general_workspace_size", "fcfs_forward_general",
     "fcfs_adjoint", "fcfs_adjoint_band", "fcfs_edge_grad",
     "fcfs_apply_edge_offsets", "fcfs_batch_workspace_size", "fcfs_forward_batch", "fcfs_plan_destroy",
     "fcfs_debug_phases", "fcfs_autotune", "fcfs_autotune_batch", "fcfs_batch_choice",
@@ -46,6 +47,22 @@ class FcfsClip(ctypes.Structure):
         ("s", ctypes.c_void_p),
         ("V", ctypes.c_int64),
         ("T", ctypes.c_int32),
+        ("K", ctypes.c_int32),
+        ("L", ctypes.c_int32),
+        ("F", ctypes.c_void_p),
+        ("area", ctypes.c_void_p),
+    ]
+
+
+class FcfsGClip(ctypes.Structure):
+    _fields_ = [
+        ("x", ctypes.c_void_p),
+        ("y", ctypes.c_void_p),
+        ("s", ctypes.c_void_p),
+        ("V", ctypes.c_int64),
+        ("Nx", ctypes.c_int32),
+        ("Ny", ctypes.c_int32),
+        ("frac_bits", ctypes.c_int32),
         ("K", ctypes.c_int32),
         ("L", ctypes.c_int32),
         ("F", ctypes.c_void_p),
@@ -105,6 +122,8 @@ def load() -> ctypes.CDLL:
         "fcfs_fft_workspace_size": [clip_p, sz],
         "fcfs_forward_fft": [P, clip_p, P, ctypes.c_size_t],
         "fcfs_haar_workspace_size": [ctypes.POINTER(FcfsHaarClip), sz],
+        "fcfs_general_workspace_size": [ctypes.POINTER(FcfsGClip), c_int, sz],
+        "fcfs_forward_general": [P, ctypes.POINTER(FcfsGClip), c_int, P, ctypes.c_size_t],
         "fcfs_haar": [P, ctypes.POINTER(FcfsHaarClip), P, ctypes.c_size_t],
         "fcfs_adjoint": [P, clip_p, P, P, P, c_int, P, ctypes.c_size_t],
         "fcfs_adjoint_band": [P, clip_p, P, i32, i32, ctypes.c_double, P, P, c_int, P,

@@ -42,6 +42,14 @@ struct fcfs_handle {
     double ms;
   };
   std::vector<Tune> tune;
+  // per-period tables of the general-tile path, built on first use
+  struct GenTab {
+    int N = 0;
+    double2 *w64 = nullptr;
+    float2 *w32 = nullptr;
+    uint2 *wbf16 = nullptr, *wfp16 = nullptr;
+  };
+  std::vector<GenTab> gen_tabs;
   int batch_tile[3] = {-1, -1, -1};
   int64_t batch_chunk[3] = {0, 0, 0};
 };
@@ -227,6 +235,59 @@ fcfs_status check_dims(fcfs_handle *h, int64_t V, int T, int K, int L, int prec)
   return FCFS_OK;
 }
 
+// Split count, chunk and workspace layout of a forward plan whose tile grid
+// (kp, lp, tiles_k, tiles_l) is set: one wave of workgroups over the CUs, but
+// at least 512 corners per split.
+void finish_plan(FwdPlan &q, int64_t tiles, int wg_per_cu, int chunk_mult, bool lattice) {
+  const int64_t V = q.V;
+  const int K = q.K, L = q.L;
+  const int Tmax = std::max(q.Mx, q.My);
+  int64_t ns = ceil_div((int64_t)kCUs * wg_per_cu, tiles);
+  const int64_t ns_max = std::max<int64_t>(1, ceil_div(V, 512));
+  ns = std::max<int64_t>(1, std::min(ns, ns_max));
+  ns = std::min<int64_t>(ns, 65535);
+  q.nsplit = (int)ns;
+  const int cm = chunk_mult;
+  q.chunk = std::max<int64_t>(cm, round_up(ceil_div(std::max<int64_t>(V, 1), ns), cm));
+  q.vpad = q.chunk * q.nsplit;
+  q.pre_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(q.vpad, 256)));
+  q.hist_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(256, ceil_div(V, 1024)));
+  q.ax_fb_k = (int)ceil_div(K, 256);
+  q.ax_fb_l = (int)ceil_div(L, 256);
+  q.ax_chunks = (int)ceil_div(Tmax, fcfs::kAxisBins);
+  // guard block: at most kGuardBlocks blocks of at least 512 corners
+  q.g_chunk = std::max<int64_t>(512, round_up(ceil_div(V, kGuardBlocks), 64));
+  q.g_chunks = (int)std::max<int64_t>(1, ceil_div(V, q.g_chunk));
+  size_t off = 0;
+  q.off_packed = off;
+  off += align256(sizeof(uint4) * (size_t)q.vpad);
+  q.off_area = off;
+  off += align256(sizeof(unsigned long long) * q.pre_blocks);
+  q.off_hist = off;
+  off += align256(sizeof(unsigned long long) * 2 * fcfs::kTabN);
+  q.off_axis = off;
+  off += align256(sizeof(double2) * (size_t)q.ax_chunks * (size_t)std::max(1, K + L));
+  q.off_part = off;
+  if (!lattice) off += align256(sizeof(float) * 4 * (size_t)q.nsplit * (size_t)q.kp * (size_t)q.lp);
+  q.off_guard = off;
+  if (!lattice) off += align256(sizeof(double) * fcfs::kGuardD * (size_t)q.g_chunks);
+  q.off_gfinal = off;
+  if (!lattice) off += align256(sizeof(double) * fcfs::kGuardD);
+  q.off_gcount = off;
+  off += 256;
+  q.off_fcnt = q.off_flist = q.off_fd = off;
+  if (lattice) {
+    const int T = q.T;
+    q.off_fcnt = off;
+    off += align256(sizeof(int) * (4 * (size_t)T + 2));  // counts, cursors, offsets, overflow
+    q.off_flist = off;
+    off += align256(sizeof(uint32_t) * (size_t)std::max<int64_t>(V, 1));
+    q.off_fd = off;
+    off += align256(sizeof(double2) * (size_t)T * (size_t)std::max(L, 1));
+  }
+  q.bytes = off;
+}
+
 // r2 >= 0: only the pupil k^2 + l^2 <= r2 is kept (tiles wholly outside it
 // are skipped and the split count is sized for the remaining ones).
 // lattice: the plan of the lattice (FFT) form: no contraction partials or
@@ -243,6 +304,10 @@ fcfs_status make_plan(fcfs_handle *h, int64_t V, int T, int K, int L, int prec, 
   q.KO = K;
   q.LO = L;
   q.r2 = r2;
+  q.eg = (double)T;
+  q.eax = q.eay = 1.0;
+  q.edc = 1.0 / (double)T;
+  q.Mx = q.My = T;
   q.V = V;
   q.shift = fcfs::kTabBits - (int)std::lround(std::log2((double)T));
   if (tile < 0) tile = default_tile(h, prec, std::max(K, L), V);
@@ -267,50 +332,7 @@ fcfs_status make_plan(fcfs_handle *h, int64_t V, int T, int K, int L, int prec, 
       }
     tiles = std::max<int64_t>(1, active);
   }
-  // one wave of workgroups over the CUs, but at least 512 corners per split
-  int64_t ns = ceil_div((int64_t)kCUs * tv.wg_per_cu, tiles);
-  const int64_t ns_max = std::max<int64_t>(1, ceil_div(V, 512));
-  ns = std::max<int64_t>(1, std::min(ns, ns_max));
-  ns = std::min<int64_t>(ns, 65535);
-  q.nsplit = (int)ns;
-  const int cm = tv.chunk_mult;
-  q.chunk = std::max<int64_t>(cm, round_up(ceil_div(std::max<int64_t>(V, 1), ns), cm));
-  q.vpad = q.chunk * q.nsplit;
-  q.pre_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(q.vpad, 256)));
-  q.hist_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(256, ceil_div(V, 1024)));
-  q.ax_fb_k = (int)ceil_div(K, 256);
-  q.ax_fb_l = (int)ceil_div(L, 256);
-  q.ax_chunks = (int)ceil_div(T, fcfs::kAxisBins);
-  // guard block: at most kGuardBlocks blocks of at least 512 corners
-  q.g_chunk = std::max<int64_t>(512, round_up(ceil_div(V, kGuardBlocks), 64));
-  q.g_chunks = (int)std::max<int64_t>(1, ceil_div(V, q.g_chunk));
-  size_t off = 0;
-  q.off_packed = off;
-  off += align256(sizeof(uint4) * (size_t)q.vpad);
-  q.off_area = off;
-  off += align256(sizeof(unsigned long long) * q.pre_blocks);
-  q.off_hist = off;
-  off += align256(sizeof(unsigned long long) * 2 * fcfs::kTabN);
-  q.off_axis = off;
-  off += align256(sizeof(double2) * (size_t)q.ax_chunks * (size_t)std::max(1, K + L));
-  q.off_part = off;
-  if (!lattice) off += align256(sizeof(float) * 4 * (size_t)q.nsplit * (size_t)q.kp * (size_t)q.lp);
-  q.off_guard = off;
-  if (!lattice) off += align256(sizeof(double) * fcfs::kGuardD * (size_t)q.g_chunks);
-  q.off_gfinal = off;
-  if (!lattice) off += align256(sizeof(double) * fcfs::kGuardD);
-  q.off_gcount = off;
-  off += 256;
-  q.off_fcnt = q.off_flist = q.off_fd = off;
-  if (lattice) {
-    q.off_fcnt = off;
-    off += align256(sizeof(int) * (4 * (size_t)T + 2));  // counts, cursors, offsets, overflow
-    q.off_flist = off;
-    off += align256(sizeof(uint32_t) * (size_t)std::max<int64_t>(V, 1));
-    q.off_fd = off;
-    off += align256(sizeof(double2) * (size_t)T * (size_t)std::max(L, 1));
-  }
-  q.bytes = off;
+  finish_plan(q, tiles, tv.wg_per_cu, tv.chunk_mult, lattice);
   *p = q;
   return FCFS_OK;
 }
@@ -454,6 +476,184 @@ fcfs_status run_forward(fcfs_handle *h, const fcfs_clip *c, const FwdPlan &p, vo
   return FCFS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// General tile: periods Mx = Nx 2^F, My = Ny 2^F on the grid of step 2^-F.
+// ---------------------------------------------------------------------------
+constexpr int kGenMaxTabs = 16;  // periods whose tables a handle keeps
+
+// Tables of one period N (FP64, FP32, split bf16 and fp16 entries of
+// (cos, sin)(2 pi p / N), FP64 from libm, hi = RNE(w), lo = RNE(w - hi)); the
+// operand tables have a zero entry at index N.  Built on first use.
+fcfs_status build_gen_table(fcfs_handle *h, int N, fcfs_handle::GenTab *out) {
+  std::vector<double2> w64(N);
+  std::vector<float2> w32(N + 1);
+  std::vector<uint2> wb(N + 1), wh(N + 1);
+  for (int p = 0; p < N; ++p) {
+    const double a = 2.0 * M_PI * (double)p / (double)N;
+    double c = std::cos(a), sn = std::sin(a);
+    c = c == 0.0 ? 0.0 : c;
+    sn = sn == 0.0 ? 0.0 : sn;
+    w64[p] = make_double2(c, sn);
+    w32[p] = make_float2((float)c, (float)sn);
+    const double chb = rne_bf16(c), shb = rne_bf16(sn);
+    const double clb = rne_bf16(c - chb), slb = rne_bf16(sn - shb);
+    wb[p] = make_uint2(bf16_bits(chb) | bf16_bits(shb) << 16, bf16_bits(clb) | bf16_bits(slb) << 16);
+    const double chh = rne_fp16(c), shh = rne_fp16(sn);
+    const double clh = rne_fp16(c - chh), slh = rne_fp16(sn - shh);
+    wh[p] = make_uint2(fp16_bits(chh) | fp16_bits(shh) << 16, fp16_bits(clh) | fp16_bits(slh) << 16);
+  }
+  w32[N] = make_float2(0.f, 0.f);
+  wb[N] = wh[N] = make_uint2(0u, 0u);
+  fcfs_handle::GenTab t;
+  t.N = N;
+  hipError_t e;
+  auto release = [&t]() {
+    (void)hipFree(t.w64);
+    (void)hipFree(t.w32);
+    (void)hipFree(t.wbf16);
+    (void)hipFree(t.wfp16);
+  };
+  if ((e = hipMalloc(&t.w64, sizeof(double2) * N)) || (e = hipMalloc(&t.w32, sizeof(float2) * (N + 1))) ||
+      (e = hipMalloc(&t.wbf16, sizeof(uint2) * (N + 1))) ||
+      (e = hipMalloc(&t.wfp16, sizeof(uint2) * (N + 1)))) {
+    release();
+    return hip_fail(h, e, "hipMalloc");
+  }
+  if ((e = hipMemcpy(t.w64, w64.data(), sizeof(double2) * N, hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(t.w32, w32.data(), sizeof(float2) * (N + 1), hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(t.wbf16, wb.data(), sizeof(uint2) * (N + 1), hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(t.wfp16, wh.data(), sizeof(uint2) * (N + 1), hipMemcpyHostToDevice))) {
+    release();
+    return hip_fail(h, e, "hipMemcpy");
+  }
+  *out = t;
+  return FCFS_OK;
+}
+
+// The tables of both periods of a call (copies of the cache entries).  When
+// the cache is full, the oldest entry that this call does not use is dropped,
+// after the device has drained.
+fcfs_status gen_tables(fcfs_handle *h, int Mx, int My, fcfs_handle::GenTab *tx,
+                       fcfs_handle::GenTab *ty) {
+  for (int N : {Mx, My}) {
+    bool have = false;
+    for (const auto &t : h->gen_tabs) have = have || t.N == N;
+    if (have) continue;
+    if ((int)h->gen_tabs.size() >= kGenMaxTabs) {
+      hipError_t e = hipDeviceSynchronize();
+      if (e) return hip_fail(h, e, "hipDeviceSynchronize");
+      for (size_t i = 0; i < h->gen_tabs.size(); ++i) {
+        auto &t = h->gen_tabs[i];
+        if (t.N == Mx || t.N == My) continue;
+        (void)hipFree(t.w64);
+        (void)hipFree(t.w32);
+        (void)hipFree(t.wbf16);
+        (void)hipFree(t.wfp16);
+        h->gen_tabs.erase(h->gen_tabs.begin() + (long)i);
+        break;
+      }
+    }
+    fcfs_handle::GenTab t;
+    fcfs_status st = build_gen_table(h, N, &t);
+    if (st) return st;
+    h->gen_tabs.push_back(t);
+  }
+  for (const auto &t : h->gen_tabs) {
+    if (t.N == Mx) *tx = t;
+    if (t.N == My) *ty = t;
+  }
+  return FCFS_OK;
+}
+
+fcfs_status make_plan_general(fcfs_handle *h, const fcfs_gclip *c, int prec, FwdPlan *p) {
+  if (!c) return fail(h, FCFS_ERR_INVALID_ARG, "clip is NULL");
+  if (c->V < 0) return fail(h, FCFS_ERR_INVALID_ARG, "V < 0");
+  if (c->V > ((int64_t)1 << 34)) return fail(h, FCFS_ERR_UNSUPPORTED, "V too large");
+  if (c->frac_bits < 0 || c->frac_bits > 13)
+    return fail(h, FCFS_ERR_UNSUPPORTED, "frac_bits must be in [0, 13]");
+  if (c->Nx < 1 || c->Ny < 1) return fail(h, FCFS_ERR_INVALID_ARG, "Nx, Ny must be >= 1");
+  const int64_t Mx = (int64_t)c->Nx << c->frac_bits, My = (int64_t)c->Ny << c->frac_bits;
+  if (Mx < 2 || My < 2 || Mx > fcfs::kTabN || My > fcfs::kTabN)
+    return fail(h, FCFS_ERR_UNSUPPORTED, "Nx 2^frac_bits and Ny 2^frac_bits must be in [2, 8192]");
+  if (c->K < 0 || c->L < 0) return fail(h, FCFS_ERR_INVALID_ARG, "K and L must be >= 0");
+  if (c->K > kMaxFreq || c->L > kMaxFreq) return fail(h, FCFS_ERR_UNSUPPORTED, "K, L must be <= 4095");
+  if (prec < 0 || prec > 2) return fail(h, FCFS_ERR_INVALID_ARG, "unknown precision");
+  FwdPlan q{};
+  q.prec = prec;
+  q.T = (int)Mx;
+  q.Mx = (int)Mx;
+  q.My = (int)My;
+  q.K = q.KO = c->K;
+  q.L = q.LO = c->L;
+  q.r2 = -1.0;
+  q.V = c->V;
+  q.shift = 0;
+  q.tile = -1;
+  // alpha of Prop. 3 for the tile Nx x Ny, with sums taken in grid units
+  // (coordinates 2^F times the true ones, periods Mx, My): 2^-F sqrt(Mx My)
+  // = sqrt(Nx Ny) and so on
+  const double sc = std::ldexp(1.0, -c->frac_bits);
+  q.eg = sc * std::sqrt((double)Mx * (double)My);
+  q.eax = sc * std::sqrt((double)Mx / (double)My);
+  q.eay = sc * std::sqrt((double)My / (double)Mx);
+  q.edc = sc / std::sqrt((double)Mx * (double)My);
+  q.wgk = q.wgl = 128;
+  q.kp = (int)round_up(c->K + 1, 128);
+  q.lp = (int)round_up(c->L + 1, 128);
+  q.tiles_k = q.kp / 128;
+  q.tiles_l = q.lp / 128;
+  // one workgroup of 8 waves per CU when both tables fill the LDS, else two
+  const int wpc = (Mx + 1 + (Mx == My ? 0 : My)) * 8 <= 80 * 1024 ? 2 : 1;
+  finish_plan(q, (int64_t)q.tiles_k * q.tiles_l, wpc, 16, false);
+  *p = q;
+  return FCFS_OK;
+}
+
+fcfs_status run_forward_general(fcfs_handle *h, const fcfs_gclip *c, const FwdPlan &p, void *ws) {
+  fcfs_handle::GenTab gx, gy;
+  fcfs_status st = gen_tables(h, p.Mx, p.My, &gx, &gy);
+  if (st) return st;
+  const fcfs_handle::GenTab *tx = &gx, *ty = &gy;
+  hipError_t e;
+  const bool grid2d = p.K > 0 && p.L > 0, side = p.K + p.L > 0;
+  const uint32_t smask = p.prec == fcfs::kFP32 ? 0x80000000u : 0x80008000u;
+  {
+    ProfScope ps(h, kProfPrepass);
+    if ((e = fcfs::launch_gen_prepass(p, c->x, c->y, c->s, smask, ws, h->stream)))
+      return hip_fail(h, e, "pre-pass launch");
+  }
+  if (side && (e = hipEventRecord(h->ev_fork, h->stream))) return hip_fail(h, e, "fork");
+  if (grid2d) {
+    const void *ox, *oy;
+    switch (p.prec) {
+      case fcfs::kFP32: ox = tx->w32; oy = ty->w32; break;
+      case fcfs::kBF16: ox = tx->wbf16; oy = ty->wbf16; break;
+      default: ox = tx->wfp16; oy = ty->wfp16; break;
+    }
+    ProfScope ps(h, kProfContract);
+    if ((e = fcfs::launch_gen_contract(p, ws_at<uint4>(ws, p.off_packed), ox, oy,
+                                       ws_at<float>(ws, p.off_part), h->stream)))
+      return hip_fail(h, e, "contraction launch");
+  }
+  if (side) {
+    if ((e = hipStreamWaitEvent(h->side, h->ev_fork, 0))) return hip_fail(h, e, "fork");
+    {
+      ProfScope ps(h, kProfAxis, h->side);
+      if ((e = fcfs::launch_gen_side(p, c->x, c->y, tx->w64, ty->w64, ws, h->side)))
+        return hip_fail(h, e, "side launch");
+    }
+    if ((e = hipEventRecord(h->ev_join, h->side)) ||
+        (e = hipStreamWaitEvent(h->stream, h->ev_join, 0)))
+      return hip_fail(h, e, "join");
+  }
+  {
+    ProfScope ps(h, kProfEpilogue);
+    if ((e = fcfs::launch_epilogue(p, ws, c->F, c->area, h->stream)))
+      return hip_fail(h, e, "epilogue launch");
+  }
+  return FCFS_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -536,6 +736,12 @@ fcfs_status fcfs_destroy(fcfs_handle *h) {
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   free_tables(h->tab);
+  for (auto &t : h->gen_tabs) {
+    (void)hipFree(t.w64);
+    (void)hipFree(t.w32);
+    (void)hipFree(t.wbf16);
+    (void)hipFree(t.wfp16);
+  }
   delete h;
   return FCFS_OK;
 }
@@ -822,6 +1028,28 @@ fcfs_status fcfs_haar(fcfs_handle *h, const fcfs_haar_clip *c, void *ws, size_t 
     if ((e = fcfs::launch_haar_scale(a, h->stream))) return hip_fail(h, e, "PCHT scale launch");
   }
   return FCFS_OK;
+}
+
+fcfs_status fcfs_general_workspace_size(const fcfs_gclip *c, fcfs_precision p, size_t *bytes) {
+  if (!bytes) return fail(nullptr, FCFS_ERR_INVALID_ARG, "NULL argument");
+  FwdPlan q;
+  fcfs_status st = make_plan_general(nullptr, c, (int)p, &q);
+  if (st) return st;
+  *bytes = q.bytes;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_forward_general(fcfs_handle *h, const fcfs_gclip *c, fcfs_precision p, void *ws,
+                                 size_t ws_bytes) {
+  fcfs_status st = enter(h);
+  if (st) return st;
+  FwdPlan q;
+  if ((st = make_plan_general(h, c, (int)p, &q))) return st;
+  if (c->V > 0 && (!c->x || !c->y || !c->s))
+    return fail(h, FCFS_ERR_INVALID_ARG, "corner arrays are NULL");
+  if (!c->F) return fail(h, FCFS_ERR_INVALID_ARG, "output F is NULL");
+  if ((st = check_ws(h, q, ws, ws_bytes))) return st;
+  return run_forward_general(h, c, q, ws);
 }
 
 fcfs_status fcfs_debug_phases(fcfs_handle *h, const fcfs_clip *c, int32_t axis, int32_t k0,

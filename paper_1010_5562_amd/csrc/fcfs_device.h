@@ -66,4 +66,79 @@ __device__ __forceinline__ f32x16 mfma16(const u32x4 &a, const u32x4 &b, const f
                                                   __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
 }
 
+
+// ---------------------------------------------------------------------------
+// Contraction building blocks shared by the power-of-two and general-period
+// kernels: partial stores, corner loads, raw table entries, MFMA fragments.
+// ---------------------------------------------------------------------------
+template <int NKB, int NLB>
+__device__ __forceinline__ void store_part(float *__restrict__ part, const f32x16 (&acc)[NKB][NLB][4],
+                                           int split, int kp, int lp, int k0, int l0, int li,
+                                           int lh) {
+  const size_t plane = (size_t)kp * lp;
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+    for (int lb = 0; lb < NLB; ++lb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float *base = part + ((size_t)split * 4 + q) * plane + (size_t)(l0 + 32 * lb + li);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = k0 + 32 * kb + 8 * (r >> 2) + 4 * lh + (r & 3);
+          base[(size_t)row * lp] = acc[kb][lb][q][r];
+        }
+      }
+}
+
+// The 8 corners of this lane's half-wave for one 16-corner step.
+__device__ __forceinline__ void load_corners(uint4 (&c)[8], const uint4 *__restrict__ vp) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) c[j] = vp[j];
+}
+
+// Raw table entries of one step: a[kb][j] = W[k x_j], b[lb][j] = s_j W[l y_j].
+template <int NKB, int NLB>
+struct Raw {
+  uint2 a[NKB][8], b[NLB][8];
+};
+
+// MFMA operand fragments of one step: 8 corners (the lane's k-slots), two
+// 16-bit values per register.  Table entry = {hi(c)|hi(s)<<16, lo(c)|lo(s)<<16}.
+template <int NKB, int NLB>
+struct Frag {
+  u32x4 ach[NKB], acl[NKB], ash[NKB], asl[NKB];
+  u32x4 bch[NLB], bcl[NLB], bsh[NLB], bsl[NLB];
+};
+
+template <int NKB, int NLB>
+__device__ __forceinline__ void build(Frag<NKB, NLB> &f, const Raw<NKB, NLB> &r) {
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb) pack4(r.a[kb], f.ach[kb], f.ash[kb], f.acl[kb], f.asl[kb]);
+#pragma unroll
+  for (int lb = 0; lb < NLB; ++lb) pack4(r.b[lb], f.bch[lb], f.bsh[lb], f.bcl[lb], f.bsl[lb]);
+}
+
+// hi*hi' + hi*lo' + lo*hi' for the four quadrants of every (kb, lb) block.
+template <int PREC, int NKB, int NLB>
+__device__ __forceinline__ void mma(f32x16 (&acc)[NKB][NLB][4], const Frag<NKB, NLB> &f) {
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+    for (int lb = 0; lb < NLB; ++lb) {
+      acc[kb][lb][0] = mfma16<PREC>(f.ach[kb], f.bch[lb], acc[kb][lb][0]);
+      acc[kb][lb][1] = mfma16<PREC>(f.ach[kb], f.bsh[lb], acc[kb][lb][1]);
+      acc[kb][lb][2] = mfma16<PREC>(f.ash[kb], f.bch[lb], acc[kb][lb][2]);
+      acc[kb][lb][3] = mfma16<PREC>(f.ash[kb], f.bsh[lb], acc[kb][lb][3]);
+      acc[kb][lb][0] = mfma16<PREC>(f.ach[kb], f.bcl[lb], acc[kb][lb][0]);
+      acc[kb][lb][1] = mfma16<PREC>(f.ach[kb], f.bsl[lb], acc[kb][lb][1]);
+      acc[kb][lb][2] = mfma16<PREC>(f.ash[kb], f.bcl[lb], acc[kb][lb][2]);
+      acc[kb][lb][3] = mfma16<PREC>(f.ash[kb], f.bsl[lb], acc[kb][lb][3]);
+      acc[kb][lb][0] = mfma16<PREC>(f.acl[kb], f.bch[lb], acc[kb][lb][0]);
+      acc[kb][lb][1] = mfma16<PREC>(f.acl[kb], f.bsh[lb], acc[kb][lb][1]);
+      acc[kb][lb][2] = mfma16<PREC>(f.asl[kb], f.bch[lb], acc[kb][lb][2]);
+      acc[kb][lb][3] = mfma16<PREC>(f.asl[kb], f.bsh[lb], acc[kb][lb][3]);
+    }
+}
+
 }  // namespace fcfs

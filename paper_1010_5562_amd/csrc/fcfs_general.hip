@@ -1,0 +1,167 @@
+// Vertex contraction (Step 4 of Sec. III-C1) for a general tile: periods Mx
+// along x and My along y, any integers in [2, 8192], not only powers of two,
+// and not necessarily equal (Prop. 3 with w_x = 2 pi / Nx, w_y = 2 pi / Ny;
+// vertices on a finer grid are handled by scaling the periods, see the API).
+//
+// The same real-trigonometric GEMM as the power-of-two kernels: per (k, l)
+// the four sums P, U, R, Q of s_v (cos, sin)(2 pi k x_v / Mx) x
+// (cos, sin)(2 pi l y_v / My) on MFMA, operands gathered from per-period
+// tables in LDS.  What differs is the exact phase reduction: (f x) mod M for
+// x < M and a lane-constant frequency f is
+//     f' x - floor(x m / 2^32) M,   f' = f mod M,  m = ceil(f' 2^32 / M),
+// exact because x M < 2^32 (the error term x (m - f' 2^32 / M) / 2^32 is below
+// x / 2^32 < 1 / M).  The sign s_v flips the sign bits of the y-side entry
+// (record field z) and padding records send the x-side lookup to the zero
+// entry (record field w = Mx).
+//
+// Workgroup: 8 waves (2 in k x 4 in l), each 64 k x 32 l, so a 128 x 128
+// frequency tile; one or two workgroups per CU depending on the table sizes
+// (at most (8193 + 8192) 8-byte entries of LDS), i.e. two waves per SIMD or more.
+#include "fcfs_device.h"
+
+namespace fcfs {
+namespace {
+
+constexpr int kGenWaves = 8;
+constexpr int kGenNKB = 2, kGenNLB = 1;
+
+__device__ __forceinline__ uint32_t gen_magic(uint32_t fr, uint32_t M) {
+  return (uint32_t)((((uint64_t)fr << 32) + M - 1u) / M);
+}
+
+// (f x) mod M with fr = f mod M and m = gen_magic(fr, M), for x < M <= 8192.
+__device__ __forceinline__ uint32_t gen_phase(uint32_t fr, uint32_t m, uint32_t x, uint32_t M) {
+  return __umul24(fr, x) - __umul24(__umulhi(x, m), M);
+}
+
+struct GenLane {
+  uint32_t kr[kGenNKB], km[kGenNKB], lr[kGenNLB], lm[kGenNLB];
+};
+
+// Entries of one 16-corner step: a[kb][j] = Wx[(k x_j) mod Mx] (zero for
+// padding), b[lb][j] = s_j Wy[(l y_j) mod My].
+template <typename E>
+__device__ __forceinline__ E flip(E e, uint32_t m) {
+  uint2 u = __builtin_bit_cast(uint2, e);
+  u.x ^= m;
+  u.y ^= m;
+  return __builtin_bit_cast(E, u);
+}
+
+template <typename E>
+__device__ __forceinline__ void gen_gather(E (&a)[kGenNKB][8], E (&b)[kGenNLB][8], const E *tx,
+                                           const E *ty, const uint4 (&c)[8], const GenLane &g,
+                                           uint32_t Mx, uint32_t My) {
+#pragma unroll
+  for (int kb = 0; kb < kGenNKB; ++kb)
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      a[kb][j] = tx[min(gen_phase(g.kr[kb], g.km[kb], c[j].x, Mx) + c[j].w, Mx)];
+#pragma unroll
+  for (int lb = 0; lb < kGenNLB; ++lb)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) b[lb][j] = flip(ty[gen_phase(g.lr[lb], g.lm[lb], c[j].y, My)], c[j].z);
+}
+
+// PREC: kBF16 / kFP16 (E = uint2 split entries) or kFP32 (E = float2).
+template <int PREC>
+__global__ __launch_bounds__(64 * kGenWaves) void k_contract_gen(
+    const uint4 *__restrict__ packed, const void *__restrict__ tabx, const void *__restrict__ taby,
+    int Mx, int My, int64_t chunk, int tiles_l, int kp, int lp, float *__restrict__ part) {
+  using E = typename std::conditional<PREC == kFP32, float2, uint2>::type;
+  extern __shared__ uint2 lds[];
+  E *tx = reinterpret_cast<E *>(lds);
+  E *ty = tabx == taby ? tx : tx + (Mx + 1);
+  for (int i = threadIdx.x; i <= Mx; i += 64 * kGenWaves) tx[i] = static_cast<const E *>(tabx)[i];
+  if (tabx != taby)
+    for (int i = threadIdx.x; i < My; i += 64 * kGenWaves) ty[i] = static_cast<const E *>(taby)[i];
+  __syncthreads();
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 31, lh = lane >> 5;
+  const int tk = blockIdx.x / tiles_l, tl = blockIdx.x % tiles_l;
+  const int split = blockIdx.y;
+  const int k0 = tk * 128 + (wave >> 2) * 64;
+  const int l0 = tl * 128 + (wave & 3) * 32;
+  const uint32_t ux = (uint32_t)Mx, uy = (uint32_t)My;
+  GenLane g;
+#pragma unroll
+  for (int kb = 0; kb < kGenNKB; ++kb) {
+    g.kr[kb] = (uint32_t)(k0 + 32 * kb + li) % ux;
+    g.km[kb] = gen_magic(g.kr[kb], ux);
+  }
+#pragma unroll
+  for (int lb = 0; lb < kGenNLB; ++lb) {
+    g.lr[lb] = (uint32_t)(l0 + 32 * lb + li) % uy;
+    g.lm[lb] = gen_magic(g.lr[lb], uy);
+  }
+
+  f32x16 acc[kGenNKB][kGenNLB][4];
+#pragma unroll
+  for (int kb = 0; kb < kGenNKB; ++kb)
+#pragma unroll
+    for (int lb = 0; lb < kGenNLB; ++lb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[kb][lb][q][r] = 0.0f;
+
+  const uint4 *vp = packed + (size_t)split * chunk + 8 * lh;
+  for (int64_t vb = 0; vb < chunk; vb += 16) {
+    uint4 c[8];
+    load_corners(c, vp + vb);
+    if constexpr (PREC == kFP32) {
+      float2 a[kGenNKB][8], b[kGenNLB][8];
+      gen_gather(a, b, tx, ty, c, g, ux, uy);
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int kb = 0; kb < kGenNKB; ++kb)
+#pragma unroll
+          for (int lb = 0; lb < kGenNLB; ++lb) {
+            acc[kb][lb][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[kb][j].x, b[lb][j].x, acc[kb][lb][0], 0, 0, 0);
+            acc[kb][lb][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[kb][j].x, b[lb][j].y, acc[kb][lb][1], 0, 0, 0);
+            acc[kb][lb][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[kb][j].y, b[lb][j].x, acc[kb][lb][2], 0, 0, 0);
+            acc[kb][lb][3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[kb][j].y, b[lb][j].y, acc[kb][lb][3], 0, 0, 0);
+          }
+    } else {
+      Raw<kGenNKB, kGenNLB> raw;
+      gen_gather(raw.a, raw.b, tx, ty, c, g, ux, uy);
+      Frag<kGenNKB, kGenNLB> f;
+      build(f, raw);
+      mma<PREC>(acc, f);
+    }
+  }
+  store_part<kGenNKB, kGenNLB>(part, acc, split, kp, lp, k0, l0, li, lh);
+}
+
+template <int PREC>
+hipError_t launch_gen_t(const FwdPlan &p, const uint4 *packed, const void *tx, const void *ty,
+                        float *part, hipStream_t st) {
+  const size_t lds = sizeof(uint2) * ((size_t)p.Mx + 1 + (tx == ty ? 0 : (size_t)p.My));
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_contract_gen<PREC>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(sizeof(uint2) * (2 * kTabN + 1)));
+    if (e) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_contract_gen<PREC>, dim3(p.tiles_k * p.tiles_l, p.nsplit),
+                     dim3(64 * kGenWaves), lds, st, packed, tx, ty, p.Mx, p.My, p.chunk, p.tiles_l,
+                     p.kp, p.lp, part);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gen_contract(const FwdPlan &p, const uint4 *packed, const void *tx,
+                               const void *ty, float *part, hipStream_t st) {
+  switch (p.prec) {
+    case kFP32: return launch_gen_t<kFP32>(p, packed, tx, ty, part, st);
+    case kBF16: return launch_gen_t<kBF16>(p, packed, tx, ty, part, st);
+    default: return launch_gen_t<kFP16>(p, packed, tx, ty, part, st);
+  }
+}
+
+}  // namespace fcfs

@@ -48,6 +48,8 @@ struct FwdPlan {
   int T, K, L;       // period and computed band |k| <= K, |l| <= L
   int KO, LO;        // output grid (2 KO + 1) x (2 LO + 1), KO >= K, LO >= L
   double r2;         // pupil: entries with k^2 + l^2 > r2 written as zero (< 0: none)
+  double eg, eax, eay, edc;  // epilogue factors of alpha (square tile: T, 1, 1, 1/T)
+  int Mx, My;        // periods of the phase reduction (square tile: T, T)
   int64_t V;
   int shift;         // log2(8192 / T)
   int tile;          // contraction tile variant id
@@ -88,6 +90,17 @@ hipError_t launch_epilogue(const FwdPlan &p, const void *ws, float *F, int64_t *
 hipError_t launch_epilogue_axes(const FwdPlan &p, const void *ws, float *F, int64_t *area,
                                 hipStream_t st);
 // lattice form of the general term (fcfs_fft.hip): writes F for k, l != 0
+// General tile (periods Mx, My in [2, 8192], any integers): pre-pass into
+// residue records, side-stream work (histograms, FP64 guard block, axis DFTs
+// with the per-period FP64 tables wx, wy) and the MFMA contraction with the
+// per-period operand tables tx, ty (split or FP32 entries; tx has Mx + 1
+// entries, the last zero).
+hipError_t launch_gen_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y,
+                              const int8_t *s, uint32_t smask, void *ws, hipStream_t st);
+hipError_t launch_gen_side(const FwdPlan &p, const int32_t *x, const int32_t *y,
+                           const double2 *wx, const double2 *wy, void *ws, hipStream_t st);
+hipError_t launch_gen_contract(const FwdPlan &p, const uint4 *packed, const void *tx,
+                               const void *ty, float *part, hipStream_t st);
 hipError_t launch_fft(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
                       const double2 *w64, void *ws, float *F, hipStream_t st);
 hipError_t launch_debug_phases(const FwdPlan &p, const uint4 *packed, int axis, int k0, int nk,

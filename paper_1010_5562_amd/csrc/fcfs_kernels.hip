@@ -77,6 +77,58 @@ hipError_t launch_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y, 
   return hipGetLastError();
 }
 
+// General tile (periods Mx, My: any integers in [2, 8192], coordinates in
+// units of the grid): records {x mod Mx, y mod My, sign mask, pad}.  The sign
+// mask flips the sign bits of a y-side table entry (smask = 0x80008000 for the
+// packed 16-bit split entries, 0x80000000 for FP32 pairs); padding records
+// carry pad = Mx, which sends the x-side lookup to the zero entry Mx.  Bins
+// of the axis histograms are the residues themselves.
+__global__ __launch_bounds__(256) void k_gen_prepass(const int32_t *__restrict__ x,
+                                                     const int32_t *__restrict__ y,
+                                                     const int8_t *__restrict__ s, int64_t V,
+                                                     int64_t vpad, int Mx, int My, uint32_t smask,
+                                                     uint4 *__restrict__ packed,
+                                                     unsigned long long *__restrict__ area_part,
+                                                     unsigned long long *__restrict__ hist,
+                                                     unsigned int *__restrict__ gcount) {
+  const int blk = blockIdx.x, nblk = gridDim.x;
+  unsigned long long acc = 0;
+  for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < vpad; i += (int64_t)nblk * 256) {
+    uint4 w;
+    if (i < V) {
+      const int32_t xv = x[i], yv = y[i];
+      const int sv = s[i];
+      const int xm = xv % Mx, ym = yv % My;
+      w.x = (uint32_t)(xm < 0 ? xm + Mx : xm);
+      w.y = (uint32_t)(ym < 0 ? ym + My : ym);
+      w.z = sv < 0 ? smask : 0u;
+      w.w = 0u;
+      acc += (unsigned long long)((long long)sv * (long long)xv * (long long)yv);
+    } else {
+      w = make_uint4(0u, 0u, 0u, (uint32_t)Mx);
+    }
+    packed[i] = w;
+  }
+  for (int i = blk * 256 + threadIdx.x; i < Mx + My; i += nblk * 256)
+    hist[i < Mx ? i : kHistN + (i - Mx)] = 0ull;
+  if (blk == 0 && threadIdx.x == 0) *gcount = 0u;
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  __shared__ unsigned long long red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) area_part[blk] = red[0] + red[1] + red[2] + red[3];
+}
+
+hipError_t launch_gen_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y,
+                              const int8_t *s, uint32_t smask, void *ws, hipStream_t st) {
+  char *w = (char *)ws;
+  hipLaunchKernelGGL(k_gen_prepass, dim3(p.pre_blocks), dim3(256), 0, st, x, y, s, p.V, p.vpad,
+                     p.Mx, p.My, smask, (uint4 *)(w + p.off_packed),
+                     (unsigned long long *)(w + p.off_area), (unsigned long long *)(w + p.off_hist),
+                     (unsigned int *)(w + p.off_gcount));
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Axis sums (Steps 2 and 3):
 //   Sx[f] = sum_v s_v y_v e(f x_v), f = 1..K,   Sy[f] = sum_v s_v x_v e(f y_v), f = 1..L,
@@ -89,6 +141,8 @@ hipError_t launch_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y, 
 // ---------------------------------------------------------------------------
 
 // Bins of one clip; hist = [Hx | Hy], kHistN int64 each, cleared beforehand.
+// GEN: general-tile records (the residues are the bins).
+template <bool GEN = false>
 __device__ __forceinline__ void hist_body(const int32_t *__restrict__ x,
                                           const int32_t *__restrict__ y,
                                           const uint4 *__restrict__ packed, int64_t V, int shift,
@@ -97,7 +151,7 @@ __device__ __forceinline__ void hist_body(const int32_t *__restrict__ x,
   for (int64_t v = (int64_t)blk * 256 + threadIdx.x; v < V; v += (int64_t)nblk * 256) {
     const uint4 c = packed[v];
     const long long sg = c.z ? -1 : 1;
-    const uint32_t qx = (c.x >> 3) >> shift, qy = (c.y >> 3) >> shift;
+    const uint32_t qx = GEN ? c.x : (c.x >> 3) >> shift, qy = GEN ? c.y : (c.y >> 3) >> shift;
     atomicAdd(&hist[qx], (unsigned long long)(sg * (long long)y[v]));
     atomicAdd(&hist[kHistN + qy], (unsigned long long)(sg * (long long)x[v]));
   }
@@ -106,25 +160,33 @@ __device__ __forceinline__ void hist_body(const int32_t *__restrict__ x,
 // Block (fb, chunk): 256 frequencies f = 1 + 256 fb' + t of one axis against
 // the bins q in [chunk * kAxisBins, ...) < T.  e(f q) from the exact table at
 // the first bin of every 32 and FP64 complex products in between.
+// GEN: the axis has its own period (Mx or My) and table, and the table index
+// is (f q) mod M; chunks past the axis's period write zero partials.
+template <bool GEN = false>
 __device__ __forceinline__ void dft_body(const unsigned long long *__restrict__ hist,
                                          const double2 *__restrict__ w64, int T, int shift, int K,
                                          int L, int fb_k, double2 *__restrict__ axis_part, int fb,
-                                         int chunk) {
+                                         int chunk, const double2 *__restrict__ w64y = nullptr,
+                                         int My = 0) {
   __shared__ double s_h[kAxisBins];
   const bool xaxis = fb < fb_k;
   const int f = 1 + (xaxis ? fb : fb - fb_k) * 256 + threadIdx.x;
   const int nf = xaxis ? K : L;
   const unsigned long long *H = hist + (xaxis ? 0 : kHistN);
+  const int M = GEN && !xaxis ? My : T;
+  const double2 *W = GEN && !xaxis ? w64y : w64;
   const int q0 = chunk * kAxisBins;
-  const int n = min(kAxisBins, T - q0);
+  const int n = max(0, min(kAxisBins, M - q0));
   for (int i = threadIdx.x; i < n; i += 256) s_h[i] = (double)(long long)H[q0 + i];
   __syncthreads();
   double re = 0.0, im = 0.0;
   const uint32_t uf = (uint32_t)f, mask = (uint32_t)(kTabN - 1);
-  const double2 w1 = w64[(uf << shift) & mask];
+  const uint32_t um = (uint32_t)M, fr = GEN ? uf % um : 0u;
+  const double2 w1 = GEN ? W[fr] : W[(uf << shift) & mask];
   double2 w = make_double2(1.0, 0.0);
   for (int i = 0; i < n; ++i) {
-    if ((i & 31) == 0) w = w64[((uf * (uint32_t)(q0 + i)) << shift) & mask];
+    if ((i & 31) == 0)
+      w = GEN ? W[(fr * (uint32_t)(q0 + i)) % um] : W[((uf * (uint32_t)(q0 + i)) << shift) & mask];
     const double h = s_h[i];
     re = fma(h, w.x, re);  // e(f q) = conj(w)
     im = fma(-h, w.y, im);
@@ -164,11 +226,15 @@ constexpr int kGuard = 8;     // |k|, |l| <= kGuard
 constexpr int kGuardUnroll = 8;
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+// GEN: general-tile records; x phases (f x) mod Mx index wx, y phases wy.
+template <bool GEN = false>
 __device__ __forceinline__ void guard_body(const uint4 *__restrict__ packed,
                                            const double *__restrict__ w64, int64_t V,
                                            int64_t g_chunk, int nblk, int blk,
                                            double *__restrict__ gpart, double *__restrict__ gfinal,
-                                           unsigned int *__restrict__ gcount) {
+                                           unsigned int *__restrict__ gcount,
+                                           const double *__restrict__ wy = nullptr, int Mx = 0,
+                                           int My = 0) {
   __shared__ double red[4][kGuardD];
   __shared__ int s_last;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -187,10 +253,16 @@ __device__ __forceinline__ void guard_body(const uint4 *__restrict__ packed,
       b[u] = 0.0;
       if (v < v1) {
         const uint4 c = packed[v];
-        const uint32_t px = __umul24(f, c.x >> 3) & (uint32_t)(kTabN - 1);
-        const uint32_t py = __umul24(f, c.y >> 3) & (uint32_t)(kTabN - 1);
+        uint32_t px, py;
+        if constexpr (GEN) {
+          px = (f * c.x) % (uint32_t)Mx;
+          py = (f * c.y) % (uint32_t)My;
+        } else {
+          px = __umul24(f, c.x >> 3) & (uint32_t)(kTabN - 1);
+          py = __umul24(f, c.y >> 3) & (uint32_t)(kTabN - 1);
+        }
         a[u] = w64[2 * px + sc];
-        const double t = w64[2 * py + sc];
+        const double t = GEN ? wy[2 * py + sc] : w64[2 * py + sc];
         b[u] = c.z ? -t : t;
       }
     }
@@ -250,6 +322,51 @@ hipError_t launch_side(const FwdPlan &p, const int32_t *x, const int32_t *y, con
   return hipGetLastError();
 }
 
+// General-tile side-stream work: histogram blocks, guard blocks, then the
+// axis DFTs of both periods.
+__global__ __launch_bounds__(256) void k_gen_side(const int32_t *__restrict__ x,
+                                                  const int32_t *__restrict__ y,
+                                                  const uint4 *__restrict__ packed, int64_t V,
+                                                  unsigned long long *__restrict__ hist, int nh,
+                                                  const double *__restrict__ wx,
+                                                  const double *__restrict__ wy, int Mx, int My,
+                                                  int64_t g_chunk, int g_chunks,
+                                                  double *__restrict__ gpart,
+                                                  double *__restrict__ gfinal,
+                                                  unsigned int *__restrict__ gcount) {
+  if ((int)blockIdx.x < nh)
+    hist_body<true>(x, y, packed, V, 0, hist, blockIdx.x, nh);
+  else
+    guard_body<true>(packed, wx, V, g_chunk, g_chunks, blockIdx.x - nh, gpart, gfinal, gcount, wy,
+                     Mx, My);
+}
+
+__global__ __launch_bounds__(256) void k_gen_axis_dft(const unsigned long long *__restrict__ hist,
+                                                      const double2 *__restrict__ wx,
+                                                      const double2 *__restrict__ wy, int Mx,
+                                                      int My, int K, int L, int fb_k,
+                                                      double2 *__restrict__ axis_part) {
+  dft_body<true>(hist, wx, Mx, 0, K, L, fb_k, axis_part, blockIdx.x, blockIdx.y, wy, My);
+}
+
+hipError_t launch_gen_side(const FwdPlan &p, const int32_t *x, const int32_t *y,
+                           const double2 *wx, const double2 *wy, void *ws, hipStream_t st) {
+  char *w = (char *)ws;
+  const uint4 *packed = (const uint4 *)(w + p.off_packed);
+  auto *hist = (unsigned long long *)(w + p.off_hist);
+  const int nh = p.K + p.L > 0 ? p.hist_blocks : 0;
+  const int ng = p.K > 0 && p.L > 0 ? p.g_chunks : 0;
+  if (nh + ng > 0)
+    hipLaunchKernelGGL(k_gen_side, dim3(nh + ng), dim3(256), 0, st, x, y, packed, p.V, hist, nh,
+                       (const double *)wx, (const double *)wy, p.Mx, p.My, p.g_chunk, p.g_chunks,
+                       (double *)(w + p.off_guard), (double *)(w + p.off_gfinal),
+                       (unsigned int *)(w + p.off_gcount));
+  if (p.K + p.L > 0)
+    hipLaunchKernelGGL(k_gen_axis_dft, dim3(p.ax_fb_k + p.ax_fb_l, p.ax_chunks), dim3(256), 0, st,
+                       hist, wx, wy, p.Mx, p.My, p.K, p.L, p.ax_fb_k, (double2 *)(w + p.off_axis));
+  return hipGetLastError();
+}
+
 // A frequency tile whose corner nearest the origin lies outside the pupil
 // k^2 + l^2 <= r2 (r2 >= 0) holds only coefficients the epilogue writes as zero:
 // its workgroups return at once.
@@ -273,38 +390,6 @@ __device__ __forceinline__ bool tile_outside(int tile, int tiles_l, int wgk, int
 // row 8*(r/4) + 4*h + (r%4), column i.
 // ---------------------------------------------------------------------------
 template <int NKB, int NLB>
-__device__ __forceinline__ void store_part(float *__restrict__ part, const f32x16 (&acc)[NKB][NLB][4],
-                                           int split, int kp, int lp, int k0, int l0, int li,
-                                           int lh) {
-  const size_t plane = (size_t)kp * lp;
-#pragma unroll
-  for (int kb = 0; kb < NKB; ++kb)
-#pragma unroll
-    for (int lb = 0; lb < NLB; ++lb)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        float *base = part + ((size_t)split * 4 + q) * plane + (size_t)(l0 + 32 * lb + li);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int row = k0 + 32 * kb + 8 * (r >> 2) + 4 * lh + (r & 3);
-          base[(size_t)row * lp] = acc[kb][lb][q][r];
-        }
-      }
-}
-
-// The 8 corners of this lane's half-wave for one 16-corner step.
-__device__ __forceinline__ void load_corners(uint4 (&c)[8], const uint4 *__restrict__ vp) {
-#pragma unroll
-  for (int j = 0; j < 8; ++j) c[j] = vp[j];
-}
-
-// Raw table entries of one step: a[kb][j] = W[k x_j], b[lb][j] = s_j W[l y_j].
-template <int NKB, int NLB>
-struct Raw {
-  uint2 a[NKB][8], b[NLB][8];
-};
-
-template <int NKB, int NLB>
 __device__ __forceinline__ void gather(Raw<NKB, NLB> &r, const uint2 *s_tab, const uint4 (&c)[8],
                                        const uint32_t (&kf)[NKB], const uint32_t (&lf)[NLB]) {
 #pragma unroll
@@ -315,44 +400,6 @@ __device__ __forceinline__ void gather(Raw<NKB, NLB> &r, const uint2 *s_tab, con
   for (int lb = 0; lb < NLB; ++lb)
 #pragma unroll
     for (int j = 0; j < 8; ++j) r.b[lb][j] = lds_entry(s_tab, phase_y(lf[lb], c[j]));
-}
-
-// MFMA operand fragments of one step: 8 corners (the lane's k-slots), two
-// 16-bit values per register.  Table entry = {hi(c)|hi(s)<<16, lo(c)|lo(s)<<16}.
-template <int NKB, int NLB>
-struct Frag {
-  u32x4 ach[NKB], acl[NKB], ash[NKB], asl[NKB];
-  u32x4 bch[NLB], bcl[NLB], bsh[NLB], bsl[NLB];
-};
-
-template <int NKB, int NLB>
-__device__ __forceinline__ void build(Frag<NKB, NLB> &f, const Raw<NKB, NLB> &r) {
-#pragma unroll
-  for (int kb = 0; kb < NKB; ++kb) pack4(r.a[kb], f.ach[kb], f.ash[kb], f.acl[kb], f.asl[kb]);
-#pragma unroll
-  for (int lb = 0; lb < NLB; ++lb) pack4(r.b[lb], f.bch[lb], f.bsh[lb], f.bcl[lb], f.bsl[lb]);
-}
-
-// hi*hi' + hi*lo' + lo*hi' for the four quadrants of every (kb, lb) block.
-template <int PREC, int NKB, int NLB>
-__device__ __forceinline__ void mma(f32x16 (&acc)[NKB][NLB][4], const Frag<NKB, NLB> &f) {
-#pragma unroll
-  for (int kb = 0; kb < NKB; ++kb)
-#pragma unroll
-    for (int lb = 0; lb < NLB; ++lb) {
-      acc[kb][lb][0] = mfma16<PREC>(f.ach[kb], f.bch[lb], acc[kb][lb][0]);
-      acc[kb][lb][1] = mfma16<PREC>(f.ach[kb], f.bsh[lb], acc[kb][lb][1]);
-      acc[kb][lb][2] = mfma16<PREC>(f.ash[kb], f.bch[lb], acc[kb][lb][2]);
-      acc[kb][lb][3] = mfma16<PREC>(f.ash[kb], f.bsh[lb], acc[kb][lb][3]);
-      acc[kb][lb][0] = mfma16<PREC>(f.ach[kb], f.bcl[lb], acc[kb][lb][0]);
-      acc[kb][lb][1] = mfma16<PREC>(f.ach[kb], f.bsl[lb], acc[kb][lb][1]);
-      acc[kb][lb][2] = mfma16<PREC>(f.ash[kb], f.bcl[lb], acc[kb][lb][2]);
-      acc[kb][lb][3] = mfma16<PREC>(f.ash[kb], f.bsl[lb], acc[kb][lb][3]);
-      acc[kb][lb][0] = mfma16<PREC>(f.acl[kb], f.bch[lb], acc[kb][lb][0]);
-      acc[kb][lb][1] = mfma16<PREC>(f.acl[kb], f.bsh[lb], acc[kb][lb][1]);
-      acc[kb][lb][2] = mfma16<PREC>(f.asl[kb], f.bch[lb], acc[kb][lb][2]);
-      acc[kb][lb][3] = mfma16<PREC>(f.asl[kb], f.bsh[lb], acc[kb][lb][3]);
-    }
 }
 
 // Split (hi + lo) contraction.  Software pipeline per 16-corner step s:
@@ -727,10 +774,15 @@ hipError_t launch_contract(const FwdPlan &p, const uint4 *packed, const Tables &
 // k-major, index (KO + k)(2 LO + 1) + (LO + l).  It may be larger than the
 // computed band |k| <= K, |l| <= L (the rest is cleared beforehand); with
 // r2 >= 0 the entries with k^2 + l^2 > r2 are written as zero (a pupil).
+// The factors of alpha_{k,l} (Prop. 3) come with the grid: alpha_{k,l} =
+// -g / (4 pi^2 k l), alpha_{k,0} = j ax / (2 pi k), alpha_{0,l} = j ay / (2 pi l),
+// F[0,0] = dc * area.  A square tile of period T has g = T, ax = ay = 1,
+// dc = 1 / T; a general one carries the sqrt(Nx/Ny)-type factors.
 struct OutGrid {
   float2 *F;
   int KO, LO;
   double r2;
+  double g, ax, ay, dc;
 };
 
 __device__ __forceinline__ void put(const OutGrid &o, int k, int l, float re, float im) {
@@ -740,7 +792,8 @@ __device__ __forceinline__ void put(const OutGrid &o, int k, int l, float re, fl
 
 __device__ __forceinline__ void store_quad(const OutGrid &o, int k, int l, double T, double P,
                                            double U, double R, double Q) {
-  const double a = -T / (4.0 * kPi * kPi * (double)k * (double)l);
+  (void)T;
+  const double a = -o.g / (4.0 * kPi * kPi * (double)k * (double)l);
   const double pre = a * (P - Q), pim = -a * (R + U);  // F[k, l]
   const double mre = -a * (P + Q), mim = a * (R - U);  // F[k, -l]
   put(o, k, l, (float)pre, (float)pim);
@@ -823,7 +876,7 @@ __device__ __forceinline__ void epilogue_axes_body(const double2 *__restrict__ a
       im += red[w][t].y;
     }
     const int f = i < K ? i + 1 : i - K + 1;
-    const double sc = 1.0 / (2.0 * kPi * (double)f);
+    const double sc = (i < K ? o.ax : o.ay) / (2.0 * kPi * (double)f);
     const float fre = (float)(-im * sc), fim = (float)(re * sc);
     if (i < K) {
       put(o, f, 0, fre, fim);
@@ -840,7 +893,7 @@ __device__ __forceinline__ void epilogue_axes_body(const double2 *__restrict__ a
     for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
     if (a0 == 0) {
       const long long A = (long long)a;
-      put(o, 0, 0, (float)((double)A / T), 0.0f);
+      put(o, 0, 0, (float)((double)A * o.dc), 0.0f);
       if (area) *area = A;
     }
   }
@@ -902,7 +955,7 @@ __global__ __launch_bounds__(256) void k_zero_grid(float2 *__restrict__ F, int64
 hipError_t launch_epilogue(const FwdPlan &p, const void *ws, float *F, int64_t *area,
                            hipStream_t st) {
   const char *w = (const char *)ws;
-  const OutGrid o{(float2 *)F, p.KO, p.LO, p.r2};
+  const OutGrid o{(float2 *)F, p.KO, p.LO, p.r2, p.eg, p.eax, p.eay, p.edc};
   if (p.KO > p.K || p.LO > p.L) {
     const int64_t n = (2 * (int64_t)p.KO + 1) * (2 * (int64_t)p.LO + 1);
     hipLaunchKernelGGL(k_zero_grid, dim3((unsigned)std::min<int64_t>(2048, (n + 255) / 256)),
@@ -919,7 +972,7 @@ hipError_t launch_epilogue(const FwdPlan &p, const void *ws, float *F, int64_t *
 hipError_t launch_epilogue_axes(const FwdPlan &p, const void *ws, float *F, int64_t *area,
                                 hipStream_t st) {
   const char *w = (const char *)ws;
-  const OutGrid o{(float2 *)F, p.KO, p.LO, p.r2};
+  const OutGrid o{(float2 *)F, p.KO, p.LO, p.r2, p.eg, p.eax, p.eay, p.edc};
   hipLaunchKernelGGL(k_epilogue_axes, dim3(std::max(1, (p.K + p.L + 15) / 16)), dim3(256), 0, st,
                      (const double2 *)(w + p.off_axis), p.ax_chunks, p.K, p.L, (double)p.T,
                      (const unsigned long long *)(w + p.off_area), p.pre_blocks, o, area);
@@ -1071,7 +1124,7 @@ __global__ __launch_bounds__(256) void k_batch_epilogue(const BatchClip *__restr
                                                         int pre_blocks) {
   const int ci = owner(off, n, blockIdx.x);
   const BatchClip &c = clips[ci];
-  const OutGrid o{c.F, c.K, c.L, -1.0};
+  const OutGrid o{c.F, c.K, c.L, -1.0, (double)c.T, 1.0, 1.0, 1.0 / (double)c.T};
   epilogue_block(c.part, c.nsplit, c.kp, c.lp, c.K, c.L, (double)c.T, c.axis_part, c.ax_chunks,
                  c.area_part, pre_blocks, c.gfinal, o, c.area, blockIdx.x - off[ci]);
 }

@@ -1,0 +1,111 @@
+"""GPU parity of the general-tile forward transform (fcfs_forward_general:
+periods Nx != Ny, not powers of two, corners on a 2^-F grid) against the
+general-tile oracle.
+
+Tolerances as for the square tile: FP32 1e-6 |F[0,0]|, split 1e-5 |F[0,0]|;
+the area (sum s x y in grid units) is exact."""
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-6, "bf16": 1e-5, "fp16": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1010_5562_amd as P
+
+    torch.cuda.set_device(0)
+    return P
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _gpu(P, xy, off, Nx, Ny, K, L, F, prec):
+    x, y, s, _, _ = P.loops_to_corners(xy, off)
+    Fg, a = P.forward_general(x, y, s, Nx, Ny, K, L, frac_bits=F, precision=prec)
+    torch.cuda.synchronize()
+    return Fg.cpu().numpy().astype(np.complex128), int(a.item())
+
+
+@pytest.mark.parametrize("Nx,Ny,F,K,L,npol,seed", [
+    (3000, 2000, 0, 40, 33, 150, 21),     # non-square, not powers of two
+    (750, 1000, 2, 37, 45, 150, 22),      # quarter-unit grid: periods 3000 x 4000
+    (1000, 1000, 0, 70, 70, 200, 23),     # equal periods (one shared table)
+    (7, 5, 3, 30, 29, 6, 24),             # tiny odd tile, frequencies past the period
+    (2048, 1536, 1, 3, 0, 60, 25),        # L = 0: axes only
+])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_general_full_grid(P, oracle_lib, Nx, Ny, F, K, L, npol, seed, prec):
+    Mx, My = Nx << F, Ny << F
+    clip = synth.clip(seed, max(Mx, My), K, L, n_polygons=npol)  # grid units
+    xy = clip.xy.astype(np.float64) / 2 ** F
+    ref, area = oracle_lib.cfs_grid_general(xy, clip.off, Nx, Ny, K, L, frac_bits=F)
+    Fg, a = _gpu(P, clip.xy, clip.off, Nx, Ny, K, L, F, prec)
+    assert a == area
+    e = float(np.max(np.abs(Fg - ref)) / abs(ref[K, L]))
+    _say(f"general {Nx}x{Ny} F={F} K={K} L={L} {prec}: err/|F00| = {e:.3e}")
+    assert e <= TOL[prec]
+
+
+def test_general_negative_and_outside_coordinates(P, oracle_lib):
+    clip = synth.clip(26, 900, 20, n_polygons=40)
+    xy = synth.shift_loops(clip.xy, -523, 1777)
+    ref, area = oracle_lib.cfs_grid_general(xy.astype(float) / 2, clip.off, 450, 300, 20, 18,
+                                           frac_bits=1)
+    for prec in ("fp32", "bf16"):
+        Fg, a = _gpu(P, xy, clip.off, 450, 300, 20, 18, 1, prec)
+        assert a == area
+        assert float(np.max(np.abs(Fg - ref)) / abs(ref[20, 18])) <= TOL[prec]
+
+
+def test_general_square_power_of_two_matches_fast_path(P, oracle_lib):
+    clip = synth.clip(27, 1024, 100, n_polygons=300)
+    x, y, s, _, _ = P.loops_to_corners(clip.xy, clip.off)
+    ref, _ = oracle_lib.cfs_grid(clip.xy, clip.off, 1024, 100, 100)
+    for prec in ("fp32", "bf16"):
+        Fg, _ = P.forward_general(x, y, s, 1024, 1024, 100, 100, precision=prec)
+        Ff, _ = P.forward(x, y, s, 1024, 100, 100, precision=prec)
+        torch.cuda.synchronize()
+        for F_ in (Fg, Ff):
+            e = float(np.max(np.abs(F_.cpu().numpy().astype(np.complex128) - ref)) / abs(ref[100, 100]))
+            assert e <= TOL[prec]
+
+
+def test_general_layout_clip_sampled(P, oracle_lib):
+    # 2,000 polygons on a 4000 x 3000 tile with half-unit corners (periods
+    # 8000 x 6000 in grid units), |k|, |l| <= 255: sampled coefficients
+    Nx, Ny, F, K = 4000, 3000, 1, 255
+    clip = synth.clip(2, 8000, K, n_polygons=2000)
+    xy = clip.xy.astype(np.float64) / 2
+    rng = np.random.default_rng(8)
+    lo = np.array([(k, l) for k in range(-8, 9) for l in range(-8, 9)])
+    kk = np.concatenate([lo[:, 0], rng.integers(-K, K + 1, 300)])
+    ll = np.concatenate([lo[:, 1], rng.integers(-K, K + 1, 300)])
+    ref = oracle_lib.cfs_points_general(xy, clip.off, Nx, Ny, kk, ll, frac_bits=F)
+    f00 = abs(oracle_lib.cfs_points_general(xy, clip.off, Nx, Ny, [0], [0], frac_bits=F)[0])
+    for prec in ("fp32", "bf16"):
+        Fg, _ = _gpu(P, clip.xy, clip.off, Nx, Ny, K, K, F, prec)
+        e = float(np.max(np.abs(Fg[kk + K, ll + K] - ref)) / f00)
+        _say(f"general layout clip {prec}: err/|F00| = {e:.3e} over {kk.size} points")
+        assert e <= TOL[prec]
+
+
+def test_general_empty_and_errors(P):
+    e = np.zeros(0, np.int32)
+    Fg, a = P.forward_general(e, e, e.astype(np.int8), 300, 200, 5, 4)
+    torch.cuda.synchronize()
+    assert int(a.item()) == 0 and bool((Fg == 0).all())
+    sq = synth.rectangle_loop(0, 0, 3, 3)
+    x, y, s, _, _ = P.loops_to_corners(sq, np.array([0, 4]))
+    for Nx, Ny, F in ((9000, 100, 0), (100, 100, 14), (3000, 100, 2), (1, 1, 0)):
+        with pytest.raises(P.FcfsError):
+            P.forward_general(x, y, s, Nx, Ny, 4, 4, frac_bits=F)

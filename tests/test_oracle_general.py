@@ -100,3 +100,14 @@ def test_general_rejects_off_grid_coordinates(oracle_lib):
     xy, off = _loop(0.25, 0, 3, 2)
     with pytest.raises(oracle_lib.OracleError):
         oracle_lib.cfs_grid_general(xy, off, 16, 16, 2, 2, frac_bits=1)
+
+
+def test_general_points_match_grid(oracle_lib):
+    clip = synth.clip(14, 300, 12, n_polygons=10)
+    xy = clip.xy.astype(float) / 4
+    G, _ = oracle_lib.cfs_grid_general(xy, clip.off, 75, 50, 12, 9, frac_bits=2)
+    rng = np.random.default_rng(3)
+    k = rng.integers(-12, 13, 40)
+    l = rng.integers(-9, 10, 40)
+    P = oracle_lib.cfs_points_general(xy, clip.off, 75, 50, k, l, frac_bits=2)
+    assert np.array_equal(P, G[k + 12, l + 9])
