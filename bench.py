@@ -11,6 +11,8 @@ is also run with the FP32 contraction (the comparison form) and split-fp16.
 Further forms, reported beside the headline:
   layout clip   2,000 polygons, T = 4096, |k|,|l| <= 255, FP32 and split-bf16
   lattice form  the FP64 lattice (FFT) form on the precision and layout clips
+  general tile  the precision clip on an 8000 x 6000 tile, the layout clip on
+                half units over 4000 x 3000 (periods not powers of two)
   pcht          the pruned continuous Haar transform of the layout clip, 12
                 levels over its 4096 tile, bit-exact against the oracle
   single        one 64-corner polygon, T = 2048, |k|,|l| <= 64: microseconds
@@ -405,6 +407,42 @@ def main() -> int:
         log(f"single polygon {prec}: {ms1 * 1e3:.1f} us per call, {msg * 1e3:.1f} us per "
             f"graph replay, err {max(e1, eg):.2e}")
     forms["single_polygon"] = single
+
+    # ------------------------------------------------------------- general tile
+    # Periods that are neither equal nor powers of two, and a finer corner
+    # grid: the precision clip on an 8000 x 6000 tile (K = L = 511, same
+    # corners and coefficient count as the headline), and the layout clip drawn
+    # on half units over a 4000 x 3000 tile (periods 8000 x 6000 grid units).
+    gen = {}
+    for name, gclip, gx, gy, gs, Ng, Mg, Fb, Kg in (
+            ("precision_clip_8000x6000", clip, xd, yd, sd, 8000, 6000, 0, K),
+            ("layout_clip_half_units_4000x3000", c2, x2d, y2d, s2d, 4000, 3000, 1, K2)):
+        Vg = int(gx.numel())
+        pg = Vg * (2 * Kg + 1) ** 2
+        kq = np.concatenate([kk[:289] if Kg >= 8 else kk, rng.integers(-Kg, Kg + 1, 200)])
+        lq = np.concatenate([ll[:289] if Kg >= 8 else ll, rng.integers(-Kg, Kg + 1, 200)])
+        xyg = gclip.xy.astype(np.float64) / 2 ** Fb
+        refg = oracle.cfs_points_general(xyg, gclip.off, Ng, Mg, kq, lq, frac_bits=Fb)
+        f00g = abs(oracle.cfs_points_general(xyg, gclip.off, Ng, Mg, [0], [0], frac_bits=Fb)[0])
+        entry = {"workload": (f"{Vg} corners, tile {Ng} x {Mg}, corners on a 2^-{Fb} grid "
+                              f"(periods {Ng << Fb} x {Mg << Fb} grid units), |k|,|l|<={Kg}")}
+        Fgen = torch.empty((2 * Kg + 1, 2 * Kg + 1), dtype=torch.complex64, device=dev)
+        for prec in ("fp32", "bf16"):
+            msg, profg = timed(lambda: P.forward_general(gx, gy, gs, Ng, Mg, Kg, Kg, frac_bits=Fb,
+                                                         precision=prec, out=Fgen),
+                               args.steps, args.warmup, h)
+            eg = float(np.max(np.abs(Fgen.cpu().numpy()[kq + Kg, lq + Kg] - refg)) / f00g)
+            cms = kavg(profg, "contract")
+            fl = (3 if prec != "fp32" else 1) * 8 * (Kg + 1) ** 2 * Vg
+            entry[prec] = {"value": pg / (msg * 1e-3), "ms_per_step": msg, "err_rel_f00": eg,
+                           "contract_ms": cms,
+                           "roofline": {"bound": "mfma", "achieved": fl / (cms * 1e-3) / 1e12,
+                                        "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                                        "frac": fl / (cms * 1e-3) / 1e12 / PEAK_TFLOPS[prec]}}
+            log(f"general tile {name} {prec}: {msg:.3f} ms  {pg / msg * 1e3:.4g} pairs/s  "
+                f"err {eg:.2e}  contract {cms:.3f} ms")
+        gen[name] = entry
+    forms["general_tile"] = gen
 
     # ------------------------------------------------------------------ C4
     t0 = time.time()

@@ -61,6 +61,8 @@ def _load():
     lib.fo_cfs_grid_general.restype = ctypes.c_int
     lib.fo_cfs_points_general.argtypes = [P, P, i64, i64, i64, i32, i64, P, P, c_int, P]
     lib.fo_cfs_points_general.restype = ctypes.c_int
+    lib.fo_edge_grad_general.argtypes = [P, P, i64, i64, i64, i32, i32, i32, P, P, i64, c_int, P]
+    lib.fo_edge_grad_general.restype = ctypes.c_int
     lib.po_pcht.restype = ctypes.c_int
     for f in (lib.fo_cfs_grid, lib.fo_cfs_points, lib.fo_edge_grad, lib.fo_loop_areas,
               lib.fo_threads):
@@ -176,6 +178,28 @@ def edge_grad(xy, off, T: int, K: int, L: int, G, edges=None, lattice: bool = Tr
                           int(bool(lattice)), _ptr(Gf), None if sel is None else _ptr(sel),
                           0 if sel is None else sel.size, int(nthreads), _ptr(g))
     _check(st, "fo_edge_grad")
+    return g[:n]
+
+
+def edge_grad_general(xy, off, Nx: int, Ny: int, K: int, L: int, G, frac_bits: int = 0,
+                      edges=None, nthreads: int = 0):
+    """dLoss/d(edge offset), true units, for a general tile; as ``edge_grad``."""
+    lib = _load()
+    xy, off = _loops(xy, off)
+    G = np.ascontiguousarray(np.asarray(G, dtype=np.complex128).reshape(2 * K + 1, 2 * L + 1))
+    Gf = G.view(np.float64).ravel()
+    if edges is None:
+        n = int(off[-1])
+        sel = None
+    else:
+        sel = np.ascontiguousarray(np.asarray(edges, dtype=np.int64).ravel())
+        n = sel.size
+    g = np.zeros(max(n, 1), dtype=np.float64)
+    st = lib.fo_edge_grad_general(_ptr(xy), _ptr(off), off.size - 1, int(Nx), int(Ny),
+                                  int(frac_bits), int(K), int(L), _ptr(Gf),
+                                  None if sel is None else _ptr(sel), 0 if sel is None else sel.size,
+                                  int(nthreads), _ptr(g))
+    _check(st, "fo_edge_grad_general")
     return g[:n]
 
 

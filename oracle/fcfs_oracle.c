@@ -560,6 +560,116 @@ int fo_edge_grad(const double *xy, const int64_t *off, int64_t n_loops, int64_t 
   return FO_OK;
 }
 
+/* Derivative of F[k,l] of a general tile (Prop. 3 with its general factors)
+ * with respect to the shift of edge e, in true units; the same four closed
+ * forms as dcoef, with w_x = 2 pi / Nx, w_y = 2 pi / Ny and the alphas of
+ * coef_general. */
+static fo_c dcoef_general(const fo_period *px, const fo_period *py, double Nx, double Ny,
+                          double scale, const fo_edge *e, int64_t k, int64_t l) {
+  fo_c r = {0.0, 0.0};
+  const double sg = e->sigma, rn = 1.0 / sqrt(Nx * Ny);
+  const double wx = 2.0 * FO_PI / Nx, wy = 2.0 * FO_PI / Ny;
+  if (!e->horizontal) {
+    const double ya = e->ya, yb = e->yb;
+    const int64_t Xg = llround(e->xa * scale);
+    if (k == 0 && l == 0) {
+      r.re = sg * (ya - yb) * rn;
+    } else if (l == 0) {
+      /* alpha_k0 (y_a - y_b) (-j w_x k) e(kX) = (y_a - y_b) e(kX) / sqrt(Nx Ny) */
+      fo_c ex = period_expo(px, k, Xg);
+      r.re = sg * (ya - yb) * rn * ex.re;
+      r.im = sg * (ya - yb) * rn * ex.im;
+    } else if (k == 0) {
+      /* alpha_0l (e(l y_a) - e(l y_b)) */
+      fo_c ea = period_expo(py, l, llround(ya * scale)), eb = period_expo(py, l, llround(yb * scale));
+      double s = sg * sqrt(Ny / Nx) / (2.0 * FO_PI * (double)l);
+      r.re = -(ea.im - eb.im) * s;
+      r.im = (ea.re - eb.re) * s;
+    } else {
+      /* alpha_kl (-j w_x k) e(kX) (e(l y_a) - e(l y_b)) */
+      fo_c ex = period_expo(px, k, Xg);
+      fo_c ea = period_expo(py, l, llround(ya * scale)), eb = period_expo(py, l, llround(yb * scale));
+      fo_c d = {ea.re - eb.re, ea.im - eb.im};
+      fo_c t = cmul(ex, d);
+      double a = -sqrt(Nx * Ny) / (4.0 * FO_PI * FO_PI * (double)k * (double)l);
+      double m = sg * a * wx * (double)k; /* times -j */
+      r.re = m * t.im;
+      r.im = -m * t.re;
+    }
+  } else {
+    const double xa = e->xa, xb = e->xb;
+    const int64_t Yg = llround(e->ya * scale);
+    if (k == 0 && l == 0) {
+      r.re = sg * (xb - xa) * rn;
+    } else if (l == 0) {
+      /* alpha_k0 (e(k x_b) - e(k x_a)) */
+      fo_c ea = period_expo(px, k, llround(xa * scale)), eb = period_expo(px, k, llround(xb * scale));
+      double s = sg * sqrt(Nx / Ny) / (2.0 * FO_PI * (double)k);
+      r.re = -(eb.im - ea.im) * s;
+      r.im = (eb.re - ea.re) * s;
+    } else if (k == 0) {
+      /* alpha_0l (x_b - x_a) (-j w_y l) e(lY) = (x_b - x_a) e(lY) / sqrt(Nx Ny) */
+      fo_c ey = period_expo(py, l, Yg);
+      r.re = sg * (xb - xa) * rn * ey.re;
+      r.im = sg * (xb - xa) * rn * ey.im;
+    } else {
+      /* alpha_kl (-j w_y l) e(lY) (e(k x_b) - e(k x_a)) */
+      fo_c ey = period_expo(py, l, Yg);
+      fo_c ea = period_expo(px, k, llround(xa * scale)), eb = period_expo(px, k, llround(xb * scale));
+      fo_c d = {eb.re - ea.re, eb.im - ea.im};
+      fo_c t = cmul(ey, d);
+      double a = -sqrt(Nx * Ny) / (4.0 * FO_PI * FO_PI * (double)k * (double)l);
+      double m = sg * a * wy * (double)l;
+      r.re = m * t.im;
+      r.im = -m * t.re;
+    }
+  }
+  return r;
+}
+
+/* Gradient of a real loss with respect to edge offsets (true units) for a
+ * general tile; arguments as fo_edge_grad plus Nx, Ny and frac_bits. */
+int fo_edge_grad_general(const double *xy, const int64_t *off, int64_t n_loops, int64_t Nx,
+                         int64_t Ny, int32_t frac_bits, int32_t K, int32_t L, const double *G,
+                         const int64_t *edge_idx, int64_t n_sel, int nthreads, double *g) {
+  if (Nx < 1 || Ny < 1 || frac_bits < 0 || frac_bits > 20 || K < 0 || L < 0 || !G || !g)
+    return FO_ERR_ARG;
+  const double scale = ldexp(1.0, frac_bits);
+  const int64_t nv = off[n_loops];
+  for (int64_t i = 0; i < 2 * nv; ++i) {
+    double X = xy[i] * scale;
+    if (X != floor(X) || fabs(X) > 1073741823.0) return FO_ERR_RANGE;
+  }
+  fo_edge *E = NULL;
+  int64_t n = 0;
+  int st = build_edges(xy, off, n_loops, 0, &E, &n);
+  if (st) return st;
+  int64_t cnt = edge_idx ? n_sel : n;
+  for (int64_t i = 0; i < cnt; ++i)
+    if (edge_idx && (edge_idx[i] < 0 || edge_idx[i] >= n)) { free(E); return FO_ERR_ARG; }
+  fo_period px, py;
+  if (period_init(&px, Nx << frac_bits)) { free(E); return FO_ERR_NOMEM; }
+  if (period_init(&py, Ny << frac_bits)) { free(px.tab); free(E); return FO_ERR_NOMEM; }
+  set_threads(nthreads);
+  const int64_t W = 2 * (int64_t)L + 1;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < cnt; ++i) {
+    const fo_edge *e = &E[edge_idx ? edge_idx[i] : i];
+    double acc = 0.0;
+    for (int64_t k = -K; k <= K; ++k)
+      for (int64_t l = -L; l <= L; ++l) {
+        int64_t idx = (k + K) * W + (l + L);
+        fo_c d = dcoef_general(&px, &py, (double)Nx, (double)Ny, scale, e, k, l);
+        acc += G[2 * idx] * d.re + G[2 * idx + 1] * d.im;
+      }
+    g[i] = acc;
+  }
+  free(px.tab);
+  free(py.tab);
+  free(E);
+  return FO_OK;
+}
+
 /* Exact edge-form area of every loop (lattice coordinates), sign kept. */
 int fo_loop_areas(const double *xy, const int64_t *off, int64_t n_loops, int64_t *areas) {
   fo_edge *E = NULL;

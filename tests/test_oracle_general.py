@@ -111,3 +111,45 @@ def test_general_points_match_grid(oracle_lib):
     l = rng.integers(-9, 10, 40)
     P = oracle_lib.cfs_points_general(xy, clip.off, 75, 50, k, l, frac_bits=2)
     assert np.array_equal(P, G[k + 12, l + 9])
+
+
+def _shift_edge(xy, off, e, h):
+    """Loops with edge e (joining vertex e to the next of its loop) moved by h
+    along its normal: +x for a vertical edge, +y for a horizontal one."""
+    xy = np.array(xy, dtype=np.float64)
+    m = int(np.searchsorted(off, e, side="right") - 1)
+    a, b = e, off[m] + (e - off[m] + 1) % (off[m + 1] - off[m])
+    axis = 0 if xy[a, 0] == xy[b, 0] else 1
+    xy[a, axis] += h
+    xy[b, axis] += h
+    return xy
+
+
+@pytest.mark.parametrize("Nx,Ny,F", [(40, 28, 0), (30, 44, 3)])
+def test_general_edge_grad_against_central_differences(oracle_lib, Nx, Ny, F):
+    # linear loss Re sum conj(G) F with a fixed random G; both endpoints of an
+    # edge move together; step h = 2^-10 keeps the corners on a 2^-12 grid
+    clip = synth.clip(31, min(Nx, Ny), 6, n_polygons=3)
+    Fg = 12
+    xy = clip.xy.astype(np.float64) / 2 ** F
+    K, L = 6, 5
+    rng = np.random.default_rng(4)
+    G = rng.normal(size=(2 * K + 1, 2 * L + 1)) + 1j * rng.normal(size=(2 * K + 1, 2 * L + 1))
+    g = oracle_lib.edge_grad_general(xy, clip.off, Nx, Ny, K, L, G, frac_bits=F)
+    h = 2.0 ** -10
+    for e in rng.choice(int(clip.off[-1]), 8, replace=False):
+        Fp, _ = oracle_lib.cfs_grid_general(_shift_edge(xy, clip.off, e, h), clip.off, Nx, Ny, K, L,
+                                            frac_bits=Fg)
+        Fm, _ = oracle_lib.cfs_grid_general(_shift_edge(xy, clip.off, e, -h), clip.off, Nx, Ny,
+                                            K, L, frac_bits=Fg)
+        fd = float(np.real(np.sum(np.conj(G) * (Fp - Fm)))) / (2 * h)
+        assert abs(fd - g[e]) <= 1e-6 * np.max(np.abs(g)) + 1e-9
+
+
+def test_general_edge_grad_square_tile_matches_square_oracle(oracle_lib):
+    clip = synth.clip(32, 64, 6, n_polygons=4)
+    rng = np.random.default_rng(6)
+    G = rng.normal(size=(13, 11)) + 1j * rng.normal(size=(13, 11))
+    g1 = oracle_lib.edge_grad_general(clip.xy.astype(float), clip.off, 64, 64, 6, 5, G)
+    g2 = oracle_lib.edge_grad(clip.xy, clip.off, 64, 6, 5, G)
+    assert np.max(np.abs(g1 - g2)) <= 1e-12 * np.max(np.abs(g2))
