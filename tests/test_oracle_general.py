@@ -129,7 +129,7 @@ def _shift_edge(xy, off, e, h):
 def test_general_edge_grad_against_central_differences(oracle_lib, Nx, Ny, F):
     # linear loss Re sum conj(G) F with a fixed random G; both endpoints of an
     # edge move together; step h = 2^-10 keeps the corners on a 2^-12 grid
-    clip = synth.clip(31, min(Nx, Ny), 6, n_polygons=3)
+    clip = synth.clip(31, 400, 6, n_polygons=3)  # larger than the tile: periodic
     Fg = 12
     xy = clip.xy.astype(np.float64) / 2 ** F
     K, L = 6, 5
