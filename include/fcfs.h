@@ -176,6 +176,19 @@ fcfs_status fcfs_general_workspace_size(const fcfs_gclip *c, fcfs_precision p, s
 fcfs_status fcfs_forward_general(fcfs_handle *h, const fcfs_gclip *c, fcfs_precision p, void *ws,
                                  size_t ws_bytes);
 
+/* Adjoint of fcfs_forward_general with respect to the corner coordinates, in
+ * lattice units (the derivative of the general closed forms of Prop. 3):
+ * gx[v] = dLoss/dx_v, gy[v] = dLoss/dy_v for the true coordinates
+ * x[v] / 2^frac_bits.  grad_F, band (kmax, lmax) and radius as in
+ * fcfs_adjoint_band.  ws: at least fcfs_general_adjoint_workspace_size bytes,
+ * 256-byte aligned.  Uses the per-period tables of the handle (built on first
+ * use, as for the forward). */
+fcfs_status fcfs_general_adjoint_workspace_size(const fcfs_gclip *c, fcfs_precision p,
+                                                size_t *bytes);
+fcfs_status fcfs_adjoint_general(fcfs_handle *h, const fcfs_gclip *c, const float *grad_F,
+                                 int32_t kmax, int32_t lmax, double radius, float *gx, float *gy,
+                                 fcfs_precision p, void *ws, size_t ws_bytes);
+
 /* Pruned continuous Haar transform (PCHT, Sec. III-B1) of the polygons of one
  * tile [0,Nx) x [0,Ny): the inner products of the sum of polygon indicators
  * with the 2-D Haar basis of Sec. II-B (scaling function phi_{0,0,0} and the
@@ -252,6 +265,13 @@ fcfs_status fcfs_edge_grad(fcfs_handle *h, const float *gx, const float *gy,
 fcfs_status fcfs_apply_edge_offsets(fcfs_handle *h, const int32_t *base_x, const int32_t *base_y,
                                     const int64_t *hedge, const int64_t *vedge,
                                     const float *offsets, int64_t V, int32_t *x, int32_t *y);
+/* The same on a grid of step 2^-frac_bits: base_x, base_y, x, y in grid units
+ * (coordinates times 2^frac_bits), offsets in lattice units; each corner moves
+ * by rint(offset 2^frac_bits) grid steps.  frac_bits in [0, 13]. */
+fcfs_status fcfs_apply_edge_offsets_grid(fcfs_handle *h, const int32_t *base_x,
+                                         const int32_t *base_y, const int64_t *hedge,
+                                         const int64_t *vedge, const float *offsets, int64_t V,
+                                         int32_t frac_bits, int32_t *x, int32_t *y);
 
 /* Batched forward: n clips (each with its own V, T, K, L and outputs) in one
  * persistent contraction launch.  The first call with *plan == NULL builds a

@@ -17,7 +17,7 @@ from ._lib import (PRECISIONS, FcfsClip, FcfsError, FcfsGClip, FcfsHaarClip, che
 
 __all__ = [
     "Handle", "FcfsError", "loops_to_corners", "forward", "workspace_size", "debug_phases",
-    "tile_variants", "PRECISIONS", "haar", "forward_general",
+    "tile_variants", "PRECISIONS", "haar", "forward_general", "adjoint_general",
 ]
 
 
@@ -277,6 +277,37 @@ def forward_general(x, y, s, Nx: int, Ny: int, K: int, L: int | None = None, fra
     return F, area
 
 
+def adjoint_general(x, y, s, Nx: int, Ny: int, K: int, L: int, grad_F, frac_bits: int = 0,
+                    precision="bf16", band=None, radius=None, handle=None):
+    """dLoss/dx_v, dLoss/dy_v (lattice units) of a general tile
+    (``fcfs_adjoint_general``); x, y in grid units as for
+    ``forward_general``, band and radius as for ``adjoint``."""
+    import torch
+
+    h = handle or default_handle()
+    h.sync_stream()
+    x, y, s = _corners_on(h.device, x, y, s)
+    V = x.numel()
+    G = torch.as_tensor(grad_F).to(h.device, torch.complex64).contiguous()
+    if G.numel() != (2 * K + 1) * (2 * L + 1):
+        raise ValueError("grad_F must have (2K+1)(2L+1) entries")
+    gx = torch.empty(V, dtype=torch.float32, device=h.device)
+    gy = torch.empty(V, dtype=torch.float32, device=h.device)
+    kmax, lmax = (K, L) if band is None else (int(band[0]), int(band[1]))
+    c = FcfsGClip(x.data_ptr(), y.data_ptr(), s.data_ptr(), V, int(Nx), int(Ny), int(frac_bits),
+                  int(K), int(L), None, None)
+    nb = ctypes.c_size_t(0)
+    check(h.lib.fcfs_general_adjoint_workspace_size(ctypes.byref(c), _prec(precision),
+                                                    ctypes.byref(nb)))
+    ws = h.workspace(nb.value)
+    check(h.lib.fcfs_adjoint_general(h.ptr, ctypes.byref(c), ctypes.c_void_p(G.data_ptr()), kmax,
+                                     lmax, -1.0 if radius is None else float(radius),
+                                     ctypes.c_void_p(gx.data_ptr()), ctypes.c_void_p(gy.data_ptr()),
+                                     _prec(precision), ctypes.c_void_p(ws.data_ptr()),
+                                     ctypes.c_size_t(ws.numel())), h.ptr)
+    return gx, gy
+
+
 def haar(x, y, s, poly_off, Nx: int, Ny: int, J: int, handle=None, out_U=None, out_W=None,
          coefficients: bool = True, stats: bool = False):
     """Pruned continuous Haar transform of one tile (``fcfs_haar``).
@@ -381,15 +412,28 @@ def edge_grad(gx, gy, hedge, vedge, n_edges: int, handle=None):
 
 class Geometry:
     """Device-resident polygon geometry for edge-moving optimisation: base
-    corner coordinates, corner signs and the corner -> edge maps."""
+    corner coordinates, corner signs and the corner -> edge maps.
 
-    def __init__(self, xy, off, T: int, K: int, L: int | None = None, handle=None):
+    Square tile: period T (a power of two), integer corners, integer edge
+    offsets.  General tile (``Ny`` given, T not a power of two, or
+    ``frac_bits`` > 0): periods T x Ny and corners on the grid of step
+    2^-frac_bits (``xy`` holds the true coordinates); edge offsets are then
+    multiples of 2^-frac_bits."""
+
+    def __init__(self, xy, off, T: int, K: int, L: int | None = None, handle=None,
+                 Ny: int | None = None, frac_bits: int = 0):
         import torch
 
         self.handle = handle or default_handle()
         dev = self.handle.device
-        x, y, s, he, ve = loops_to_corners(xy, off)
+        self.frac_bits = int(frac_bits)
         self.T, self.K, self.L = int(T), int(K), int(K if L is None else L)
+        self.Ny = int(T if Ny is None else Ny)
+        self.general = (Ny is not None or self.frac_bits > 0 or self.T & (self.T - 1) != 0)
+        xyg = np.asarray(xy, dtype=np.float64) * (1 << self.frac_bits)
+        if not np.array_equal(xyg, np.round(xyg)):
+            raise ValueError("corners must lie on the grid of step 2^-frac_bits")
+        x, y, s, he, ve = loops_to_corners(np.round(xyg).astype(np.int32), off)
         self.n_edges = int(x.size)
         self.base_x = torch.as_tensor(x).to(dev)
         self.base_y = torch.as_tensor(y).to(dev)
@@ -398,7 +442,8 @@ class Geometry:
         self.vedge = torch.as_tensor(ve).to(dev)
 
     def corners(self, offsets):
-        """Corner coordinates for edge offsets (one per edge, integer valued)."""
+        """Corner coordinates (grid units) for edge offsets (one per edge, on
+        the grid of step 2^-frac_bits)."""
         import torch
 
         h = self.handle
@@ -406,16 +451,22 @@ class Geometry:
         off = offsets.detach().to(h.device, torch.float32).contiguous()
         if off.numel() != self.n_edges:
             raise ValueError("one offset per edge")
-        if not torch.equal(off, torch.round(off)):
-            raise FcfsError(-1, "edge offsets must be integers (lattice coordinates)")
+        sc = float(1 << self.frac_bits)
+        if not torch.equal(off * sc, torch.round(off * sc)):
+            raise FcfsError(-1, "edge offsets must be multiples of 2^-frac_bits")
         V = self.base_x.numel()
         x = torch.empty_like(self.base_x)
         y = torch.empty_like(self.base_y)
-        check(h.lib.fcfs_apply_edge_offsets(
-            h.ptr, ctypes.c_void_p(self.base_x.data_ptr()), ctypes.c_void_p(self.base_y.data_ptr()),
-            ctypes.c_void_p(self.hedge.data_ptr()), ctypes.c_void_p(self.vedge.data_ptr()),
-            ctypes.c_void_p(off.data_ptr()), V, ctypes.c_void_p(x.data_ptr()),
-            ctypes.c_void_p(y.data_ptr())), h.ptr)
+        args = (ctypes.c_void_p(self.base_x.data_ptr()), ctypes.c_void_p(self.base_y.data_ptr()),
+                ctypes.c_void_p(self.hedge.data_ptr()), ctypes.c_void_p(self.vedge.data_ptr()),
+                ctypes.c_void_p(off.data_ptr()), V)
+        if self.general:
+            check(h.lib.fcfs_apply_edge_offsets_grid(h.ptr, *args, self.frac_bits,
+                                                     ctypes.c_void_p(x.data_ptr()),
+                                                     ctypes.c_void_p(y.data_ptr())), h.ptr)
+        else:
+            check(h.lib.fcfs_apply_edge_offsets(h.ptr, *args, ctypes.c_void_p(x.data_ptr()),
+                                                ctypes.c_void_p(y.data_ptr())), h.ptr)
         return x, y
 
 
@@ -423,7 +474,8 @@ def _autograd_function():
     import torch
 
     class FCFSFunction(torch.autograd.Function):
-        """F = FCFS(geometry moved by integer edge offsets); backward runs the
+        """F = FCFS(geometry moved by edge offsets: integers on a square tile,
+        multiples of 2^-frac_bits on a general one); backward runs the
         adjoint kernels and the edge reduction.  With ``band`` and/or
         ``radius`` the forward returns the low-pass spectrum (zero outside
         |k| <= kmax, |l| <= lmax, k^2 + l^2 <= radius^2) and the backward is
@@ -432,8 +484,15 @@ def _autograd_function():
         @staticmethod
         def forward(ctx, offsets, geom, precision="bf16", band=None, radius=None):
             x, y = geom.corners(offsets)
-            F, _ = forward(x, y, geom.s, geom.T, geom.K, geom.L, precision=precision,
-                           handle=geom.handle, band=band, radius=radius)
+            if geom.general:
+                if band is not None or radius is not None:
+                    raise NotImplementedError("no low-pass forward for general tiles")
+                F, _ = forward_general(x, y, geom.s, geom.T, geom.Ny, geom.K, geom.L,
+                                       frac_bits=geom.frac_bits, precision=precision,
+                                       handle=geom.handle)
+            else:
+                F, _ = forward(x, y, geom.s, geom.T, geom.K, geom.L, precision=precision,
+                               handle=geom.handle, band=band, radius=radius)
             ctx.geom, ctx.precision, ctx.band, ctx.radius = geom, precision, band, radius
             ctx.save_for_backward(x, y)
             return F
@@ -442,8 +501,13 @@ def _autograd_function():
         def backward(ctx, grad_F):
             x, y = ctx.saved_tensors
             g = ctx.geom
-            gx, gy = adjoint(x, y, g.s, g.T, g.K, g.L, grad_F.contiguous(), ctx.precision,
-                             band=ctx.band, handle=g.handle, radius=ctx.radius)
+            if g.general:
+                gx, gy = adjoint_general(x, y, g.s, g.T, g.Ny, g.K, g.L, grad_F.contiguous(),
+                                         frac_bits=g.frac_bits, precision=ctx.precision,
+                                         handle=g.handle)
+            else:
+                gx, gy = adjoint(x, y, g.s, g.T, g.K, g.L, grad_F.contiguous(), ctx.precision,
+                                 band=ctx.band, handle=g.handle, radius=ctx.radius)
             ge = edge_grad(gx, gy, g.hedge, g.vedge, g.n_edges, handle=g.handle)
             return ge, None, None, None, None
 

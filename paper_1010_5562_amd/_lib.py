@@ -31,6 +31,7 @@ EXPORTS = (
     "fcfs_workspace_size", "fcfs_forward", "fcfs_band_workspace_size", "fcfs_forward_band",
     "fcfs_fft_workspace_size", "fcfs_forward_fft", "fcfs_haar_workspace_size", "fcfs_haar",
     "fcfs_general_workspace_size", "fcfs_forward_general",
+    "fcfs_general_adjoint_workspace_size", "fcfs_adjoint_general", "fcfs_apply_edge_offsets_grid",
     "fcfs_adjoint", "fcfs_adjoint_band", "fcfs_edge_grad",
     "fcfs_apply_edge_offsets", "fcfs_batch_workspace_size", "fcfs_forward_batch", "fcfs_plan_destroy",
     "fcfs_debug_phases", "fcfs_autotune", "fcfs_autotune_batch", "fcfs_batch_choice",
@@ -124,6 +125,10 @@ def load() -> ctypes.CDLL:
         "fcfs_haar_workspace_size": [ctypes.POINTER(FcfsHaarClip), sz],
         "fcfs_general_workspace_size": [ctypes.POINTER(FcfsGClip), c_int, sz],
         "fcfs_forward_general": [P, ctypes.POINTER(FcfsGClip), c_int, P, ctypes.c_size_t],
+        "fcfs_general_adjoint_workspace_size": [ctypes.POINTER(FcfsGClip), c_int, sz],
+        "fcfs_adjoint_general": [P, ctypes.POINTER(FcfsGClip), P, i32, i32, ctypes.c_double, P, P,
+                                 c_int, P, ctypes.c_size_t],
+        "fcfs_apply_edge_offsets_grid": [P, P, P, P, P, P, i64, i32, P, P],
         "fcfs_haar": [P, ctypes.POINTER(FcfsHaarClip), P, ctypes.c_size_t],
         "fcfs_adjoint": [P, clip_p, P, P, P, c_int, P, ctypes.c_size_t],
         "fcfs_adjoint_band": [P, clip_p, P, i32, i32, ctypes.c_double, P, P, c_int, P,

@@ -15,6 +15,11 @@
 //    dF/dy_v = s_v (j/(2 pi k)) e(k x_v); F[0,l] likewise; F[0,0] = area/T:
 //    dF/dx_v = s_v y_v / T, dF/dy_v = s_v x_v / T.  These are evaluated per
 //    corner in FP64.
+//  * General tile (periods Nx, Ny, corners on a 2^-F grid): the same forms
+//    with alpha of Prop. 3 for Nx x Ny; the coefficients j/(2 pi l) of the x
+//    gradient gain sqrt(Ny/Nx), those of the y gradient sqrt(Nx/Ny), and 1/T
+//    becomes 2^-F / sqrt(Nx Ny) (coordinates in grid units); phases are
+//    reduced modulo Mx = Nx 2^F, My = Ny 2^F with per-period tables.
 #include "fcfs_device.h"
 
 namespace fcfs {
@@ -51,8 +56,8 @@ __device__ __forceinline__ size_t rec_index_f32(int n, int r, int lb, int ncb) {
 // records (rec_index_f32).
 template <int MODE>
 __global__ __launch_bounds__(256) void k_adj_w(const float2 *__restrict__ G, int K, int L, int kmax,
-                                               int lmax, double r2, int kb, int lb,
-                                               float *__restrict__ Wf,
+                                               int lmax, double r2, int kb, int lb, double rx,
+                                               double ry, float *__restrict__ Wf,
                                                unsigned int *__restrict__ wmax,
                                                uint16_t *__restrict__ whi,
                                                uint16_t *__restrict__ wlo,
@@ -70,7 +75,7 @@ __global__ __launch_bounds__(256) void k_adj_w(const float2 *__restrict__ G, int
     const float2 gpm = G[(size_t)(K + k) * WL + (L - l)];  // G[k, -l]
     const float2 gmp = G[(size_t)(K - k) * WL + (L + l)];  // G[-k, l]
     // conj(G) * j c = (c gi, c gr); folded with the conjugate of the mirror
-    const double cl = 1.0 / (2.0 * kPi * l), ck = 1.0 / (2.0 * kPi * k);
+    const double cl = rx / (2.0 * kPi * l), ck = ry / (2.0 * kPi * k);
     // x gradient: c = 1/(2 pi l) with the sign of l
     double a = cl * ((double)gpp.y - gmm.y), b = cl * ((double)gpp.x + gmm.x);
     double a2 = -cl * ((double)gpm.y - gmp.y), b2 = -cl * ((double)gpm.x + gmp.x);
@@ -190,7 +195,7 @@ __global__ void k_fill_u32(unsigned int *p, int n, unsigned int v) {
 // coef layout: [P_1..P_K | Q_1..Q_L | Re G00 | P_k/(2 pi k) | Q_l/(2 pi l)] as
 // double2 (the scaled copies spare the per-corner loop a division).
 __global__ void k_adj_axcoef(const float2 *__restrict__ G, int K, int L, int kmax, int lmax,
-                             double2 *__restrict__ coef) {
+                             double rx, double ry, double2 *__restrict__ coef) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   const size_t WL = 2 * (size_t)L + 1;
   double2 v = make_double2(0.0, 0.0);
@@ -216,7 +221,8 @@ __global__ void k_adj_axcoef(const float2 *__restrict__ G, int K, int L, int kma
     return;
   }
   coef[i] = v;
-  const double sc = 1.0 / (2.0 * kPi * (double)f);
+  // P_k enters the y gradient (sqrt(Nx/Ny)), Q_l the x gradient (sqrt(Ny/Nx))
+  const double sc = (i < K ? ry : rx) / (2.0 * kPi * (double)f);
   coef[K + L + 1 + i] = make_double2(v.x * sc, v.y * sc);
 }
 
@@ -224,13 +230,17 @@ __global__ void k_adj_axcoef(const float2 *__restrict__ G, int K, int L, int kma
 // sum_f Re[c_f e(f t)] with e(f t) = conj(w^f), w = e^{j 2 pi ts / N}: the
 // powers come from repeated multiplication, restarted from the exact table
 // every 32 steps.
+// GEN: residue records of a general tile, tables wx (period Mx) and wy (My).
+template <bool GEN>
 __global__ __launch_bounds__(256) void k_adj_axis(const int32_t *__restrict__ x,
                                                   const int32_t *__restrict__ y,
                                                   const uint4 *__restrict__ packed,
                                                   const double2 *__restrict__ w64,
                                                   const double2 *__restrict__ coef, int64_t V,
-                                                  int K, int L, int kmax, int lmax, double T,
-                                                  float *__restrict__ gx, float *__restrict__ gy) {
+                                                  int K, int L, int kmax, int lmax, double dcf,
+                                                  float *__restrict__ gx, float *__restrict__ gy,
+                                                  const double2 *__restrict__ wy = nullptr,
+                                                  int Mx = 0, int My = 0) {
   const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (v >= V) return;
   const uint4 c = packed[v];
@@ -239,13 +249,15 @@ __global__ __launch_bounds__(256) void k_adj_axis(const int32_t *__restrict__ x,
   const double2 *coef_s = coef + (K + L + 1);  // scaled by 1/(2 pi f)
   double sx1 = 0.0, sx2 = 0.0;  // sum Re[P e(kx)],  sum Re[P j/(2 pi k) e(kx)]
   {
-    const uint32_t ph = c.x >> 3;
+    const uint32_t ph = GEN ? c.x : c.x >> 3;
     const double2 w1 = w64[ph];
     double2 w = w1;
     // unrolled so that the uniform coefficient loads of 8 steps are issued together
 #pragma unroll 8
     for (int k = 1; k <= kmax; ++k) {
-      if ((k & 31) == 0) w = w64[((uint32_t)k * ph) & (uint32_t)(kTabN - 1)];
+      if ((k & 31) == 0)
+        w = GEN ? w64[((uint32_t)k * ph) % (uint32_t)Mx]
+                : w64[((uint32_t)k * ph) & (uint32_t)(kTabN - 1)];
       const double2 p = coef[k - 1], ps = coef_s[k - 1];
       // e(kx) = w.x - j w.y;  Re[j z] = -Im z
       sx1 += p.x * w.x + p.y * w.y;
@@ -256,12 +268,15 @@ __global__ __launch_bounds__(256) void k_adj_axis(const int32_t *__restrict__ x,
   }
   double sy1 = 0.0, sy2 = 0.0;  // sum Re[Q e(ly)],  sum Re[Q j/(2 pi l) e(ly)]
   {
-    const uint32_t ph = c.y >> 3;
-    const double2 w1 = w64[ph];
+    const double2 *W = GEN ? wy : w64;
+    const uint32_t ph = GEN ? c.y : c.y >> 3;
+    const double2 w1 = W[ph];
     double2 w = w1;
 #pragma unroll 8
     for (int l = 1; l <= lmax; ++l) {
-      if ((l & 31) == 0) w = w64[((uint32_t)l * ph) & (uint32_t)(kTabN - 1)];
+      if ((l & 31) == 0)
+        w = GEN ? W[((uint32_t)l * ph) % (uint32_t)My]
+                : W[((uint32_t)l * ph) & (uint32_t)(kTabN - 1)];
       const double2 q = coef[K + l - 1], qs = coef_s[K + l - 1];
       sy1 += q.x * w.x + q.y * w.y;
       sy2 -= qs.y * w.x - qs.x * w.y;
@@ -270,8 +285,8 @@ __global__ __launch_bounds__(256) void k_adj_axis(const int32_t *__restrict__ x,
     }
   }
   const double g00 = coef[K + L].x;
-  gx[v] = (float)(sg * (yv / T * sx1 + sy2 + yv * g00 / T));
-  gy[v] = (float)(sg * (sx2 + xv / T * sy1 + xv * g00 / T));
+  gx[v] = (float)(sg * (yv * dcf * sx1 + sy2 + yv * g00 * dcf));
+  gy[v] = (float)(sg * (sx2 + xv * dcf * sy1 + xv * g00 * dcf));
 }
 
 // ---------------------------------------------------------------------------
@@ -289,15 +304,47 @@ __global__ __launch_bounds__(256) void k_adj_axis(const int32_t *__restrict__ x,
 constexpr int kAdjNB = 4;
 constexpr int kAdjWaves = 8;
 
-template <int PREC>
+// Exact (f t) mod M for a lane-constant t < M <= 8192 and f < 2^19, with
+// m = ceil(t 2^32 / M): floor(f t / M) = floor(f m / 2^32) because the error
+// f (m - t 2^32 / M) / 2^32 < 2^-13 <= 1 / M.
+__device__ __forceinline__ uint32_t adj_magic(uint32_t t, uint32_t M) {
+  return (uint32_t)((((uint64_t)t << 32) + M - 1u) / M);
+}
+__device__ __forceinline__ uint32_t adj_phase(uint32_t f, uint32_t t, uint32_t m, uint32_t M) {
+  return __umul24(f, t) - __umul24(__umulhi(f, m), M);
+}
+
+// Operand tables of a general tile in dynamic LDS: x entries [0, Mx), then y
+// entries [Mx, Mx + My) unless the periods are equal (one table).
+template <typename E>
+__device__ __forceinline__ void stage_period_tables(E *dyn, const void *tx, const void *ty, int Mx,
+                                                    int My, const E *&px, const E *&py) {
+  for (int i = threadIdx.x; i < Mx; i += 64 * kAdjWaves) dyn[i] = static_cast<const E *>(tx)[i];
+  if (tx != ty)
+    for (int i = threadIdx.x; i < My; i += 64 * kAdjWaves) dyn[Mx + i] = static_cast<const E *>(ty)[i];
+  px = dyn;
+  py = tx != ty ? dyn + Mx : dyn;
+}
+
+// GEN: a general tile (residue records, per-period tables tab / taby in
+// dynamic LDS, exact phases by adj_phase).
+template <int PREC, bool GEN>
 __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_split(
     const uint4 *__restrict__ packed, const uint2 *__restrict__ tab,
     const uint16_t *__restrict__ whi,
     const uint16_t *__restrict__ wlo, const int *__restrict__ scale, int64_t V, int kb, int lb,
-    float *__restrict__ gx, float *__restrict__ gy) {
-  __shared__ uint2 s_tab[kTabEntries];
+    float *__restrict__ gx, float *__restrict__ gy, const uint2 *__restrict__ taby = nullptr,
+    int Mx = 0, int My = 0) {
   __shared__ u32x4 s_w[2][4 * kAdjNB][64];
-  for (int i = threadIdx.x; i < kTabEntries; i += 64 * kAdjWaves) s_tab[i] = tab[i];
+  const uint2 *s_tab, *s_taby;
+  if constexpr (GEN) {
+    extern __shared__ uint2 s_dyn[];
+    stage_period_tables<uint2>(s_dyn, tab, taby, Mx, My, s_tab, s_taby);
+  } else {
+    __shared__ uint2 s_fix[kTabEntries];
+    for (int i = threadIdx.x; i < kTabEntries; i += 64 * kAdjWaves) s_fix[i] = tab[i];
+    s_tab = s_taby = s_fix;
+  }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 31, lh = lane >> 5;
   const int64_t vbase = (int64_t)blockIdx.x * (32 * kAdjWaves) + wave * 32;
@@ -322,14 +369,16 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_split(
   }
   const uint4 ca = packed[vbase + li];  // this lane's A row
   // the 16 output rows this lane holds
-  uint32_t ys8[16];
+  uint32_t ys8[16], ym[16];
   bool neg[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const uint4 c = packed[vbase + 8 * (r >> 2) + 4 * lh + (r & 3)];
     ys8[r] = c.y;
+    ym[r] = GEN ? adj_magic(c.y, (uint32_t)My) : 0u;
     neg[r] = c.z != 0u;
   }
+  const uint32_t xm = GEN ? adj_magic(ca.x, (uint32_t)Mx) : 0u;
   float sx[16], sy[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) sx[r] = sy[r] = 0.f;
@@ -357,8 +406,10 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_split(
       }
       uint2 d[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
-        d[j] = lds_entry(s_tab, phase_x((uint32_t)(1 + ib + 8 * lh + j), ca));
+      for (int j = 0; j < 8; ++j) {
+        const uint32_t f = (uint32_t)(1 + ib + 8 * lh + j);
+        d[j] = GEN ? s_tab[adj_phase(f, ca.x, xm, (uint32_t)Mx)] : lds_entry(s_tab, phase_x(f, ca));
+      }
       u32x4 ach, ash, acl, asl;
       pack4(d, ach, ash, acl, asl);
 #pragma unroll
@@ -379,7 +430,8 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_split(
       const uint32_t l = (uint32_t)((cg >> 2) + li + 1);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const uint2 e = lds_entry(s_tab, phase_x(l, make_uint4(ys8[r], 0u, 0u, 0u)));
+        const uint2 e = GEN ? s_taby[adj_phase(l, ys8[r], ym[r], (uint32_t)My)]
+                            : lds_entry(s_taby, phase_x(l, make_uint4(ys8[r], 0u, 0u, 0u)));
         float yc, ys;
         if constexpr (PREC == kBF16) {
           yc = __uint_as_float(e.x << 16) + __uint_as_float(e.y << 16);
@@ -418,13 +470,21 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_split(
 // FP32 main term: v_mfma_f32_32x32x2_f32, two frequencies per product, with
 // the operand records of rec_index_f32 shared through LDS as in the split form
 // (eight waves, 256 corners per workgroup, double-buffered 16-row steps).
+template <bool GEN>
 __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_fp32(
     const uint4 *__restrict__ packed, const float2 *__restrict__ tab32g,
     const float *__restrict__ Wr, int64_t V, int kb, int lb, float *__restrict__ gx,
-    float *__restrict__ gy) {
-  __shared__ float2 s_tab[kTabEntries];
+    float *__restrict__ gy, const float2 *__restrict__ taby = nullptr, int Mx = 0, int My = 0) {
   __shared__ float s_w[2][2 * kAdjNB][8][64];
-  for (int i = threadIdx.x; i < kTabEntries; i += 64 * kAdjWaves) s_tab[i] = tab32g[i];
+  const float2 *s_tab, *s_taby;
+  if constexpr (GEN) {
+    extern __shared__ float2 s_dynf[];
+    stage_period_tables<float2>(s_dynf, tab32g, taby, Mx, My, s_tab, s_taby);
+  } else {
+    __shared__ float2 s_fix[kTabEntries];
+    for (int i = threadIdx.x; i < kTabEntries; i += 64 * kAdjWaves) s_fix[i] = tab32g[i];
+    s_tab = s_taby = s_fix;
+  }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 31, lh = lane >> 5;
   const int64_t vbase = (int64_t)blockIdx.x * (32 * kAdjWaves) + wave * 32;
@@ -446,14 +506,16 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_fp32(
     pre[u] = record(0, idx >> 7)[idx & 127];
   }
   const uint4 ca = packed[vbase + li];
-  uint32_t ys8[16];
+  uint32_t ys8[16], ym[16];
   bool neg[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const uint4 c = packed[vbase + 8 * (r >> 2) + 4 * lh + (r & 3)];
     ys8[r] = c.y;
+    ym[r] = GEN ? adj_magic(c.y, (uint32_t)My) : 0u;
     neg[r] = c.z != 0u;
   }
+  const uint32_t xm = GEN ? adj_magic(ca.x, (uint32_t)Mx) : 0u;
   float sx[16], sy[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) sx[r] = sy[r] = 0.f;
@@ -481,8 +543,9 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_fp32(
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const float2 a = *(const float2 *)((const char *)s_tab +
-                                           phase_x((uint32_t)(1 + ib + 2 * u + lh), ca));
+        const uint32_t f = (uint32_t)(1 + ib + 2 * u + lh);
+        const float2 a = GEN ? s_tab[adj_phase(f, ca.x, xm, (uint32_t)Mx)]
+                             : *(const float2 *)((const char *)s_tab + phase_x(f, ca));
 #pragma unroll
         for (int nb = 0; nb < kAdjNB; ++nb) {
           acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, s_w[buf][nb][u][lane], acc[nb], 0,
@@ -497,8 +560,9 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_fp32(
       const uint32_t l = (uint32_t)((cg >> 2) + li + 1);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const float2 w = *(const float2 *)((const char *)s_tab +
-                                           phase_x(l, make_uint4(ys8[r], 0u, 0u, 0u)));
+        const float2 w = GEN ? s_taby[adj_phase(l, ys8[r], ym[r], (uint32_t)My)]
+                             : *(const float2 *)((const char *)s_taby +
+                                                 phase_x(l, make_uint4(ys8[r], 0u, 0u, 0u)));
         sx[r] = fmaf(acc[0][r], w.x, fmaf(acc[1][r], w.y, sx[r]));
         sy[r] = fmaf(acc[2][r], w.x, fmaf(acc[3][r], w.y, sy[r]));
       }
@@ -522,9 +586,20 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_fp32(
   }
 }
 
+namespace {
+template <typename KernelT>
+hipError_t allow_big_lds(KernelT k, bool &done) {
+  if (done) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)(sizeof(uint2) * 2 * kTabN));
+  done = e == hipSuccess;
+  return e;
+}
+}  // namespace
+
 hipError_t launch_adjoint(const AdjPlan &a, const int32_t *x, const int32_t *y, const int8_t *s,
                           const float *gradF, const Tables &t, void *ws, float *gx, float *gy,
-                          hipStream_t st) {
+                          hipStream_t st, const PeriodTables *gtab) {
   char *w = (char *)ws;
   const uint4 *packed = (const uint4 *)(w + a.off_packed);
   double2 *coef = (double2 *)(w + a.off_coef);
@@ -533,41 +608,77 @@ hipError_t launch_adjoint(const AdjPlan &a, const int32_t *x, const int32_t *y, 
   unsigned int *wmax = (unsigned int *)(w + a.off_scale);
   int *scale = (int *)(w + a.off_scale + 64);
   const float2 *G = (const float2 *)gradF;
+  const bool gen = a.gen && gtab;
+  if (a.gen && !gtab) return hipErrorInvalidValue;
   (void)s;
   // axis and DC parts first: they write gx, gy
   hipLaunchKernelGGL(k_adj_axcoef, dim3((a.K + a.L + 1 + 255) / 256), dim3(256), 0, st, G, a.K,
-                     a.L, a.kmax, a.lmax, coef);
-  if (a.V > 0)
-    hipLaunchKernelGGL(k_adj_axis, dim3((unsigned)((a.V + 255) / 256)), dim3(256), 0, st, x, y,
-                       packed, t.w64, coef, a.V, a.K, a.L, a.kmax, a.lmax, (double)a.T, gx, gy);
+                     a.L, a.kmax, a.lmax, a.rx, a.ry, coef);
+  if (a.V > 0) {
+    if (gen)
+      hipLaunchKernelGGL(k_adj_axis<true>, dim3((unsigned)((a.V + 255) / 256)), dim3(256), 0, st,
+                         x, y, packed, gtab->w64x, coef, a.V, a.K, a.L, a.kmax, a.lmax, a.dcf, gx,
+                         gy, gtab->w64y, a.Mx, a.My);
+    else
+      hipLaunchKernelGGL(k_adj_axis<false>, dim3((unsigned)((a.V + 255) / 256)), dim3(256), 0, st,
+                         x, y, packed, t.w64, coef, a.V, a.K, a.L, a.kmax, a.lmax, a.dcf, gx, gy,
+                         nullptr, 0, 0);
+  }
   if (a.kmax == 0 || a.lmax == 0 || a.V == 0) return hipGetLastError();
   const dim3 wgrid((a.lb + 255) / 256, a.kb);
   if (a.prec == kBF16) {
     hipLaunchKernelGGL(k_adj_w<1>, wgrid, dim3(256), 0, st, G, a.K, a.L, a.kmax, a.lmax, a.r2,
-                       a.kb, a.lb, Wf, wmax, whi, wlo, scale);
+                       a.kb, a.lb, a.rx, a.ry, Wf, wmax, whi, wlo, scale);
   } else if (a.prec == kFP32) {
     hipLaunchKernelGGL(k_adj_w<2>, wgrid, dim3(256), 0, st, G, a.K, a.L, a.kmax, a.lmax, a.r2,
-                       a.kb, a.lb, Wf, wmax, whi, wlo, scale);
+                       a.kb, a.lb, a.rx, a.ry, Wf, wmax, whi, wlo, scale);
   } else {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, wmax, 1, 0u);
     hipLaunchKernelGGL(k_adj_w<0>, wgrid, dim3(256), 0, st, G, a.K, a.L, a.kmax, a.lmax, a.r2,
-                       a.kb, a.lb, Wf, wmax, whi, wlo, scale);
+                       a.kb, a.lb, a.rx, a.ry, Wf, wmax, whi, wlo, scale);
   }
   const unsigned sblocks = (unsigned)(a.vpad / (32 * kAdjWaves));
+  // general tile: both period tables in dynamic LDS
+  const size_t glds = gen ? sizeof(uint2) * ((size_t)a.Mx + (gtab->opx == gtab->opy ? 0 : a.My)) : 0;
+  hipError_t e;
   if (a.prec == kFP32) {
-    hipLaunchKernelGGL(k_adj_gemm_fp32, dim3(sblocks), dim3(64 * kAdjWaves), 0, st, packed, t.w32,
-                       Wf, a.V, a.kb, a.lb, gx, gy);
+    if (gen) {
+      static bool done = false;
+      if ((e = allow_big_lds(k_adj_gemm_fp32<true>, done))) return e;
+      hipLaunchKernelGGL(k_adj_gemm_fp32<true>, dim3(sblocks), dim3(64 * kAdjWaves), glds, st,
+                         packed, (const float2 *)gtab->opx, Wf, a.V, a.kb, a.lb, gx, gy,
+                         (const float2 *)gtab->opy, a.Mx, a.My);
+    } else {
+      hipLaunchKernelGGL(k_adj_gemm_fp32<false>, dim3(sblocks), dim3(64 * kAdjWaves), 0, st,
+                         packed, t.w32, Wf, a.V, a.kb, a.lb, gx, gy, nullptr, 0, 0);
+    }
   } else {
     const int64_t n = (int64_t)a.R * a.NC;
     const unsigned sb = (unsigned)std::min<int64_t>(1024, (n + 255) / 256);
-    if (a.prec == kBF16) {
-      hipLaunchKernelGGL(k_adj_gemm_split<kBF16>, dim3(sblocks), dim3(64 * kAdjWaves), 0, st, packed,
-                         t.wbf16, whi, wlo, scale, a.V, a.kb, a.lb, gx, gy);
-    } else {
+    if (a.prec == kFP16)
       hipLaunchKernelGGL(k_adj_split<kFP16>, dim3(sb), dim3(256), 0, st, Wf, a.R, a.NC, a.lb,
                          wmax, whi, wlo, scale);
-      hipLaunchKernelGGL(k_adj_gemm_split<kFP16>, dim3(sblocks), dim3(64 * kAdjWaves), 0, st, packed,
-                         t.wfp16, whi, wlo, scale, a.V, a.kb, a.lb, gx, gy);
+    const uint2 *tb = a.prec == kBF16 ? t.wbf16 : t.wfp16;
+    if (gen) {
+      if (a.prec == kBF16) {
+        static bool done = false;
+        if ((e = allow_big_lds(k_adj_gemm_split<kBF16, true>, done))) return e;
+        hipLaunchKernelGGL((k_adj_gemm_split<kBF16, true>), dim3(sblocks), dim3(64 * kAdjWaves),
+                           glds, st, packed, (const uint2 *)gtab->opx, whi, wlo, scale, a.V, a.kb,
+                           a.lb, gx, gy, (const uint2 *)gtab->opy, a.Mx, a.My);
+      } else {
+        static bool done = false;
+        if ((e = allow_big_lds(k_adj_gemm_split<kFP16, true>, done))) return e;
+        hipLaunchKernelGGL((k_adj_gemm_split<kFP16, true>), dim3(sblocks), dim3(64 * kAdjWaves),
+                           glds, st, packed, (const uint2 *)gtab->opx, whi, wlo, scale, a.V, a.kb,
+                           a.lb, gx, gy, (const uint2 *)gtab->opy, a.Mx, a.My);
+      }
+    } else if (a.prec == kBF16) {
+      hipLaunchKernelGGL((k_adj_gemm_split<kBF16, false>), dim3(sblocks), dim3(64 * kAdjWaves), 0,
+                         st, packed, tb, whi, wlo, scale, a.V, a.kb, a.lb, gx, gy, nullptr, 0, 0);
+    } else {
+      hipLaunchKernelGGL((k_adj_gemm_split<kFP16, false>), dim3(sblocks), dim3(64 * kAdjWaves), 0,
+                         st, packed, tb, whi, wlo, scale, a.V, a.kb, a.lb, gx, gy, nullptr, 0, 0);
     }
   }
   return hipGetLastError();
@@ -605,23 +716,24 @@ hipError_t launch_edge_grad(const float *gx, const float *gy, const int64_t *hed
 }
 
 // Corner coordinates after edge shifts: a vertical edge moves its two corners
-// along x, a horizontal edge along y (offsets rounded to the lattice).
+// along x, a horizontal edge along y.  Coordinates are in units of 2^-F
+// (grid), offsets in lattice units: the shift is rint(offset 2^F) grid steps.
 __global__ void k_apply_offsets(const int32_t *__restrict__ bx, const int32_t *__restrict__ by,
                                 const int64_t *__restrict__ hedge, const int64_t *__restrict__ vedge,
-                                const float *__restrict__ off, int64_t V, int32_t *__restrict__ x,
-                                int32_t *__restrict__ y) {
+                                const float *__restrict__ off, int64_t V, float scale,
+                                int32_t *__restrict__ x, int32_t *__restrict__ y) {
   const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (v >= V) return;
-  x[v] = bx[v] + (int32_t)rintf(off[vedge[v]]);
-  y[v] = by[v] + (int32_t)rintf(off[hedge[v]]);
+  x[v] = bx[v] + (int32_t)rintf(off[vedge[v]] * scale);
+  y[v] = by[v] + (int32_t)rintf(off[hedge[v]] * scale);
 }
 
 hipError_t launch_apply_offsets(const int32_t *bx, const int32_t *by, const int64_t *hedge,
                                 const int64_t *vedge, const float *off, int64_t V, int32_t *x,
-                                int32_t *y, hipStream_t st) {
+                                int32_t *y, hipStream_t st, int frac_bits) {
   if (V > 0)
     hipLaunchKernelGGL(k_apply_offsets, dim3((unsigned)((V + 255) / 256)), dim3(256), 0, st, bx,
-                       by, hedge, vedge, off, V, x, y);
+                       by, hedge, vedge, off, V, ldexpf(1.0f, frac_bits), x, y);
   return hipGetLastError();
 }
 

@@ -356,6 +356,10 @@ fcfs_status make_adj_plan(fcfs_handle *h, int64_t V, int T, int K, int L, int km
   a.lb = (int)round_up(std::max(a.lmax, 1), 32);
   a.R = 2 * a.kb;
   a.NC = 4 * a.lb;
+  a.gen = false;
+  a.Mx = a.My = T;
+  a.rx = a.ry = 1.0;
+  a.dcf = 1.0 / (double)T;
   a.vpad = round_up(std::max<int64_t>(V, 1), 256);  // 256-corner blocks of the split GEMM
   a.pre_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(a.vpad, 256)));
   size_t off = 0;
@@ -1145,6 +1149,89 @@ fcfs_status fcfs_apply_edge_offsets(fcfs_handle *h, const int32_t *base_x, const
     return fail(h, FCFS_ERR_INVALID_ARG, "NULL array");
   hipError_t e = fcfs::launch_apply_offsets(base_x, base_y, hedge, vedge, offsets, V, x, y, h->stream);
   if (e) return hip_fail(h, e, "offset launch");
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_apply_edge_offsets_grid(fcfs_handle *h, const int32_t *base_x,
+                                         const int32_t *base_y, const int64_t *hedge,
+                                         const int64_t *vedge, const float *offsets, int64_t V,
+                                         int32_t frac_bits, int32_t *x, int32_t *y) {
+  fcfs_status st = enter(h);
+  if (st) return st;
+  if (V < 0) return fail(h, FCFS_ERR_INVALID_ARG, "negative size");
+  if (frac_bits < 0 || frac_bits > 13) return fail(h, FCFS_ERR_UNSUPPORTED, "frac_bits must be in [0, 13]");
+  if (V > 0 && (!base_x || !base_y || !hedge || !vedge || !offsets || !x || !y))
+    return fail(h, FCFS_ERR_INVALID_ARG, "NULL array");
+  hipError_t e = fcfs::launch_apply_offsets(base_x, base_y, hedge, vedge, offsets, V, x, y,
+                                            h->stream, frac_bits);
+  if (e) return hip_fail(h, e, "offset launch");
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_general_adjoint_workspace_size(const fcfs_gclip *c, fcfs_precision p,
+                                                size_t *bytes) {
+  if (!bytes) return fail(nullptr, FCFS_ERR_INVALID_ARG, "NULL argument");
+  FwdPlan q;
+  fcfs_status st = make_plan_general(nullptr, c, (int)p, &q);
+  if (st) return st;
+  fcfs::AdjPlan a;
+  if ((st = make_adj_plan(nullptr, c->V, fcfs::kTabN, c->K, c->L, c->K, c->L, (int)p, &a)))
+    return st;
+  *bytes = a.bytes;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_adjoint_general(fcfs_handle *h, const fcfs_gclip *c, const float *grad_F,
+                                 int32_t kmax, int32_t lmax, double radius, float *gx, float *gy,
+                                 fcfs_precision p, void *ws, size_t ws_bytes) {
+  fcfs_status st = enter(h);
+  if (st) return st;
+  FwdPlan q;
+  if ((st = make_plan_general(h, c, (int)p, &q))) return st;
+  if (c->V > 0 && (!c->x || !c->y || !c->s))
+    return fail(h, FCFS_ERR_INVALID_ARG, "corner arrays are NULL");
+  if (!grad_F) return fail(h, FCFS_ERR_INVALID_ARG, "grad_F is NULL");
+  if (c->V > 0 && (!gx || !gy)) return fail(h, FCFS_ERR_INVALID_ARG, "gx/gy are NULL");
+  if (!(radius == radius)) return fail(h, FCFS_ERR_INVALID_ARG, "radius is NaN");
+  if (radius >= 0.0) {
+    const double rf = std::floor(radius);
+    kmax = (int32_t)std::min<double>(kmax, rf);
+    lmax = (int32_t)std::min<double>(lmax, rf);
+  }
+  fcfs::AdjPlan a;
+  if ((st = make_adj_plan(h, c->V, fcfs::kTabN, c->K, c->L, kmax, lmax, (int)p, &a))) return st;
+  a.r2 = radius >= 0.0 ? radius * radius : -1.0;
+  a.gen = true;
+  a.T = q.Mx;
+  a.Mx = q.Mx;
+  a.My = q.My;
+  // derivative factors of the general alpha (see fcfs_forward_general)
+  a.rx = std::sqrt((double)q.My / (double)q.Mx);
+  a.ry = std::sqrt((double)q.Mx / (double)q.My);
+  a.dcf = std::ldexp(1.0, -c->frac_bits) / std::sqrt((double)c->Nx * (double)c->Ny);
+  if (ws_bytes < a.bytes)
+    return fail(h, FCFS_ERR_WORKSPACE,
+                "workspace too small: need " + std::to_string(a.bytes) + " bytes, got " +
+                    std::to_string(ws_bytes));
+  if (!ws || ((uintptr_t)ws & 255u)) return fail(h, FCFS_ERR_WORKSPACE, "workspace NULL or misaligned");
+  fcfs_handle::GenTab tx, ty;
+  if ((st = gen_tables(h, q.Mx, q.My, &tx, &ty))) return st;
+  fcfs::PeriodTables pt;
+  pt.w64x = tx.w64;
+  pt.w64y = ty.w64;
+  switch (a.prec) {
+    case fcfs::kFP32: pt.opx = tx.w32; pt.opy = ty.w32; break;
+    case fcfs::kBF16: pt.opx = tx.wbf16; pt.opy = ty.wbf16; break;
+    default: pt.opx = tx.wfp16; pt.opy = ty.wfp16; break;
+  }
+  hipError_t e;
+  ProfScope ps(h, kProfAdjoint);
+  if ((e = fcfs::launch_gen_prepass_records(c->x, c->y, c->s, c->V, a.vpad, q.Mx, q.My,
+                                            a.pre_blocks, ws_at<uint4>(ws, a.off_packed),
+                                            ws_at<unsigned long long>(ws, a.off_area), h->stream)))
+    return hip_fail(h, e, "pre-pass launch");
+  if ((e = fcfs::launch_adjoint(a, c->x, c->y, c->s, grad_F, h->tab, ws, gx, gy, h->stream, &pt)))
+    return hip_fail(h, e, "adjoint launch");
   return FCFS_OK;
 }
 

@@ -97,6 +97,11 @@ hipError_t launch_epilogue_axes(const FwdPlan &p, const void *ws, float *F, int6
 // entries, the last zero).
 hipError_t launch_gen_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y,
                               const int8_t *s, uint32_t smask, void *ws, hipStream_t st);
+// residue records only (no histograms), for the adjoint of a general tile
+hipError_t launch_gen_prepass_records(const int32_t *x, const int32_t *y, const int8_t *s,
+                                      int64_t V, int64_t vpad, int Mx, int My, int pre_blocks,
+                                      uint4 *packed, unsigned long long *area_part,
+                                      hipStream_t st);
 hipError_t launch_gen_side(const FwdPlan &p, const int32_t *x, const int32_t *y,
                            const double2 *wx, const double2 *wy, void *ws, hipStream_t st);
 hipError_t launch_gen_contract(const FwdPlan &p, const uint4 *packed, const void *tx,
@@ -119,18 +124,34 @@ struct AdjPlan {
   int64_t vpad;      // V padded to the 256-corner block of the split GEMM
   int pre_blocks;
   size_t off_packed, off_area, off_coef, off_wf, off_whi, off_wlo, off_scale, bytes;
+  // general tile: periods Mx, My of the phase reduction and the factors of
+  // the derivatives (square tile: T, T, 1, 1, 1/T): rx = sqrt(Ny/Nx) and
+  // ry = sqrt(Nx/Ny) scale the x- and y-gradient coefficients j/(2 pi f),
+  // dcf = 2^-F / sqrt(Nx Ny) replaces 1/T in the axis and DC terms
+  bool gen;
+  int Mx, My;
+  double rx, ry, dcf;
 };
 
+// Per-period tables of a general tile for the adjoint: FP64 (cos, sin) for
+// the axis terms and the operand entries of the plan's precision (split or
+// FP32 pairs) for the GEMM, one set per axis.
+struct PeriodTables {
+  const double2 *w64x, *w64y;
+  const void *opx, *opy;
+};
+
+// gtab: non-null for a general tile (a.gen), else the square-tile tables t.
 hipError_t launch_adjoint(const AdjPlan &a, const int32_t *x, const int32_t *y, const int8_t *s,
                           const float *gradF, const Tables &t, void *ws, float *gx, float *gy,
-                          hipStream_t st);
+                          hipStream_t st, const PeriodTables *gtab = nullptr);
 hipError_t launch_edge_grad(const float *gx, const float *gy, const int64_t *hedge,
                             const int64_t *vedge, int64_t V, int64_t E, float *g_edge,
                             hipStream_t st);
 
 hipError_t launch_apply_offsets(const int32_t *bx, const int32_t *by, const int64_t *hedge,
                                 const int64_t *vedge, const float *off, int64_t V, int32_t *x,
-                                int32_t *y, hipStream_t st);
+                                int32_t *y, hipStream_t st, int frac_bits = 0);
 
 // ---------------------------------------------------------------------------
 // Batched form: one descriptor per clip (device copy), work lists.

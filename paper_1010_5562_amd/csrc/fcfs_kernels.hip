@@ -109,9 +109,10 @@ __global__ __launch_bounds__(256) void k_gen_prepass(const int32_t *__restrict__
     }
     packed[i] = w;
   }
-  for (int i = blk * 256 + threadIdx.x; i < Mx + My; i += nblk * 256)
-    hist[i < Mx ? i : kHistN + (i - Mx)] = 0ull;
-  if (blk == 0 && threadIdx.x == 0) *gcount = 0u;
+  if (hist)
+    for (int i = blk * 256 + threadIdx.x; i < Mx + My; i += nblk * 256)
+      hist[i < Mx ? i : kHistN + (i - Mx)] = 0ull;
+  if (gcount && blk == 0 && threadIdx.x == 0) *gcount = 0u;
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
   __shared__ unsigned long long red[4];
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -126,6 +127,15 @@ hipError_t launch_gen_prepass(const FwdPlan &p, const int32_t *x, const int32_t 
                      p.Mx, p.My, smask, (uint4 *)(w + p.off_packed),
                      (unsigned long long *)(w + p.off_area), (unsigned long long *)(w + p.off_hist),
                      (unsigned int *)(w + p.off_gcount));
+  return hipGetLastError();
+}
+
+hipError_t launch_gen_prepass_records(const int32_t *x, const int32_t *y, const int8_t *s,
+                                      int64_t V, int64_t vpad, int Mx, int My, int pre_blocks,
+                                      uint4 *packed, unsigned long long *area_part,
+                                      hipStream_t st) {
+  hipLaunchKernelGGL(k_gen_prepass, dim3(pre_blocks), dim3(256), 0, st, x, y, s, V, vpad, Mx, My,
+                     0x80008000u, packed, area_part, nullptr, nullptr);
   return hipGetLastError();
 }
 

@@ -109,3 +109,84 @@ def test_general_empty_and_errors(P):
     for Nx, Ny, F in ((9000, 100, 0), (100, 100, 14), (3000, 100, 2), (1, 1, 0)):
         with pytest.raises(P.FcfsError):
             P.forward_general(x, y, s, Nx, Ny, 4, 4, frac_bits=F)
+
+
+# ---------------------------------------------------------------- adjoint
+GTOL = {"fp32": 1e-5, "bf16": 1e-4, "fp16": 1e-4}
+
+
+def _rand_G(K, L, seed):
+    rng = np.random.default_rng(seed)
+    return rng.normal(size=(2 * K + 1, 2 * L + 1)) + 1j * rng.normal(size=(2 * K + 1, 2 * L + 1))
+
+
+@pytest.mark.parametrize("Nx,Ny,F,K,L,seed", [
+    (3000, 2000, 0, 37, 70, 51),      # several GEMM column groups, K != L
+    (750, 1000, 2, 40, 33, 52),       # quarter-unit grid, periods 3000 x 4000
+    (8192, 8000, 0, 20, 20, 53),      # both tables at their largest (LDS full)
+])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_general_adjoint_random_cotangent(P, oracle_lib, Nx, Ny, F, K, L, seed, prec):
+    Mx, My = Nx << F, Ny << F
+    clip = synth.clip(seed, max(Mx, My), K, L, n_polygons=40)
+    xy = clip.xy.astype(np.float64) / 2 ** F
+    G = _rand_G(K, L, seed)
+    want = oracle_lib.edge_grad_general(xy, clip.off, Nx, Ny, K, L, G.astype(np.complex64),
+                                        frac_bits=F)
+    x, y, s, he, ve = P.loops_to_corners(clip.xy, clip.off)
+    Gd = torch.as_tensor(G.astype(np.complex64)).cuda()
+    gx, gy = P.adjoint_general(x, y, s, Nx, Ny, K, L, Gd, frac_bits=F, precision=prec)
+    got = P.edge_grad(gx, gy, he, ve, x.size).cpu().numpy().astype(np.float64)
+    e = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+    _say(f"general adjoint {Nx}x{Ny} F={F} {prec}: err/max|g| = {e:.3e}")
+    assert e <= GTOL[prec]
+
+
+def test_general_adjoint_band_and_disc(P, oracle_lib):
+    Nx, Ny, F, K, L = 1500, 1100, 1, 48, 48
+    clip = synth.clip(54, 3000, K, L, n_polygons=60)
+    xy = clip.xy.astype(np.float64) / 2
+    G = _rand_G(K, L, 5)
+    kk, ll = np.meshgrid(np.arange(-K, K + 1), np.arange(-L, L + 1), indexing="ij")
+    G[(kk ** 2 + ll ** 2) > 17.5 ** 2] = 0
+    want = oracle_lib.edge_grad_general(xy, clip.off, Nx, Ny, K, L, G.astype(np.complex64),
+                                        frac_bits=F)
+    x, y, s, he, ve = P.loops_to_corners(clip.xy, clip.off)
+    Gd = torch.as_tensor(G.astype(np.complex64)).cuda()
+    gx, gy = P.adjoint_general(x, y, s, Nx, Ny, K, L, Gd, frac_bits=F, precision="fp32",
+                               band=(20, 20), radius=17.5)
+    got = P.edge_grad(gx, gy, he, ve, x.size).cpu().numpy().astype(np.float64)
+    assert float(np.max(np.abs(got - want)) / np.max(np.abs(want))) <= GTOL["fp32"]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_general_autograd_fractional_offsets(P, oracle_lib, prec):
+    # edges moved by multiples of a quarter unit on a 600 x 420 tile; loss
+    # sum |F|^2: forward against the oracle at the moved corners, gradient
+    # against the oracle's analytic gradient there (cotangent 2 F)
+    Nx, Ny, F, K = 600, 420, 2, 24
+    clip = synth.clip(55, 420, K, n_polygons=12)
+    geom = P.Geometry(clip.xy, clip.off, Nx, K, Ny=Ny, frac_bits=F)
+    rng = np.random.default_rng(9)
+    offs = rng.integers(-3, 4, geom.n_edges) / 4.0
+    off = torch.tensor(offs, dtype=torch.float32, device="cuda", requires_grad=True)
+    Fv = P.FCFSFunction.apply(off, geom, prec)
+    (Fv.abs() ** 2).sum().backward()
+    torch.cuda.synchronize()
+    # the moved loops (true units) for the oracle
+    xy = clip.xy.astype(np.float64).copy()
+    for m in range(clip.off.size - 1):
+        a0, a1 = clip.off[m], clip.off[m + 1]
+        for e in range(a0, a1):
+            b = a0 + (e - a0 + 1) % (a1 - a0)
+            axis = 0 if clip.xy[e, 0] == clip.xy[b, 0] else 1
+            xy[e, axis] += offs[e]
+            xy[b, axis] += offs[e]
+    ref, _ = oracle_lib.cfs_grid_general(xy, clip.off, Nx, Ny, K, K, frac_bits=F)
+    Fg = Fv.detach().cpu().numpy().astype(np.complex128)
+    assert float(np.max(np.abs(Fg - ref)) / abs(ref[K, K])) <= TOL[prec]
+    want = oracle_lib.edge_grad_general(xy, clip.off, Nx, Ny, K, K, 2 * ref, frac_bits=F)
+    got = off.grad.cpu().numpy().astype(np.float64)
+    e = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+    _say(f"general autograd {prec}: err/max|g| = {e:.3e}")
+    assert e <= GTOL[prec]
