@@ -189,6 +189,20 @@ fcfs_status fcfs_adjoint_general(fcfs_handle *h, const fcfs_gclip *c, const floa
                                  int32_t kmax, int32_t lmax, double radius, float *gx, float *gy,
                                  fcfs_precision p, void *ws, size_t ws_bytes);
 
+/* The loss of the edge-moving optimisation behind a pupil (the low-pass need
+ * of lithography models, Sec. I): loss = sum_{k,l} |H[k,l] F[k,l] - G[k,l]|^2
+ * and its cotangent grad = dLoss/dRe F + j dLoss/dIm F = 2 H (H F - G), for
+ * the backward of fcfs_adjoint / fcfs_adjoint_band.  F, G, grad: (device)
+ * (2K+1)(2L+1) complex64, layout of fcfs_clip.F; H: (device) real weights in
+ * the same layout, or NULL for the indicator of the disc k^2 + l^2 <= radius^2
+ * (radius < 0: H = 1).  loss: (device) one double.  Sums in FP64 in a fixed
+ * order (deterministic).  ws: fcfs_pupil_loss_workspace_size bytes, 256-byte
+ * aligned. */
+fcfs_status fcfs_pupil_loss_workspace_size(size_t *bytes);
+fcfs_status fcfs_pupil_loss(fcfs_handle *h, const float *F, const float *G, const float *H,
+                            int32_t K, int32_t L, double radius, double *loss, float *grad,
+                            void *ws, size_t ws_bytes);
+
 /* Pruned continuous Haar transform (PCHT, Sec. III-B1) of the polygons of one
  * tile [0,Nx) x [0,Ny): the inner products of the sum of polygon indicators
  * with the 2-D Haar basis of Sec. II-B (scaling function phi_{0,0,0} and the
@@ -334,7 +348,7 @@ fcfs_status fcfs_workspace_size_tile(const fcfs_clip *c, fcfs_precision p, int32
  * work (histograms, guard block, axis DFTs), 2 contraction, 3 epilogue,
  * 4 adjoint kernels, 5 batched graph, 6 lattice form, 7 Haar quadtree walk
  * (the Haar transform's clear-and-plan launches count as pre-pass, its
- * scaling pass as epilogue).
+ * scaling pass as epilogue), 8 pupil loss.
  * Each bracketed launch adds two event records to its stream. */
 fcfs_status fcfs_profile_begin(fcfs_handle *h, uint32_t kinds);
 fcfs_status fcfs_profile_end(fcfs_handle *h, double *ms, int64_t *count, int32_t nkinds);

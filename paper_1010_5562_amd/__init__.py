@@ -125,7 +125,7 @@ class Handle:
         check(self.lib.fcfs_set_tile(self._h, int(variant)), self._h)
 
     PROFILE_KINDS = ("prepass", "axis", "contract", "epilogue", "adjoint", "batch", "fft",
-                     "haar")
+                     "haar", "loss")
 
     def profile_begin(self, kinds=None):
         """Starts event timing of the named kinds (all kinds when None)."""
@@ -511,14 +511,48 @@ def _autograd_function():
             ge = edge_grad(gx, gy, g.hedge, g.vedge, g.n_edges, handle=g.handle)
             return ge, None, None, None, None
 
-    return FCFSFunction
+    class PupilLoss(torch.autograd.Function):
+        """loss = sum |H F - G|^2 (``fcfs_pupil_loss``), H the indicator of the
+        disc k^2 + l^2 <= radius^2 (radius None: 1) or the real weights ``H``;
+        one kernel computes the value (FP64, fixed order) and the cotangent
+        2 H (H F - G) that the backward returns."""
+
+        @staticmethod
+        def forward(ctx, F, G, radius=None, H=None, handle=None):
+            h = handle or default_handle()
+            h.sync_stream()
+            F = F.detach().contiguous()
+            G = torch.as_tensor(G).to(h.device, torch.complex64).contiguous()
+            K2, L2 = F.shape
+            grad = torch.empty_like(F)
+            loss = torch.empty((), dtype=torch.float64, device=h.device)
+            Hc = None if H is None else torch.as_tensor(H).to(h.device, torch.float32).contiguous()
+            nb = ctypes.c_size_t(0)
+            check(h.lib.fcfs_pupil_loss_workspace_size(ctypes.byref(nb)))
+            ws = h.workspace(nb.value)
+            check(h.lib.fcfs_pupil_loss(
+                h.ptr, ctypes.c_void_p(F.data_ptr()), ctypes.c_void_p(G.data_ptr()),
+                None if Hc is None else ctypes.c_void_p(Hc.data_ptr()), (K2 - 1) // 2, (L2 - 1) // 2,
+                -1.0 if radius is None else float(radius), ctypes.c_void_p(loss.data_ptr()),
+                ctypes.c_void_p(grad.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                ctypes.c_size_t(ws.numel())), h.ptr)
+            ctx.save_for_backward(grad)
+            return loss
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (grad,) = ctx.saved_tensors
+            return grad * grad_out.to(grad.real.dtype), None, None, None, None
+
+    return FCFSFunction, PupilLoss
 
 
 def __getattr__(name):
-    if name == "FCFSFunction":
-        f = _autograd_function()
+    if name in ("FCFSFunction", "PupilLoss"):
+        f, pl = _autograd_function()
         globals()["FCFSFunction"] = f
-        return f
+        globals()["PupilLoss"] = pl
+        return globals()[name]
     raise AttributeError(name)
 
 

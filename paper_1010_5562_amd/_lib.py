@@ -32,6 +32,7 @@ EXPORTS = (
     "fcfs_fft_workspace_size", "fcfs_forward_fft", "fcfs_haar_workspace_size", "fcfs_haar",
     "fcfs_general_workspace_size", "fcfs_forward_general",
     "fcfs_general_adjoint_workspace_size", "fcfs_adjoint_general", "fcfs_apply_edge_offsets_grid",
+    "fcfs_pupil_loss_workspace_size", "fcfs_pupil_loss",
     "fcfs_adjoint", "fcfs_adjoint_band", "fcfs_edge_grad",
     "fcfs_apply_edge_offsets", "fcfs_batch_workspace_size", "fcfs_forward_batch", "fcfs_plan_destroy",
     "fcfs_debug_phases", "fcfs_autotune", "fcfs_autotune_batch", "fcfs_batch_choice",
@@ -129,6 +130,8 @@ def load() -> ctypes.CDLL:
         "fcfs_adjoint_general": [P, ctypes.POINTER(FcfsGClip), P, i32, i32, ctypes.c_double, P, P,
                                  c_int, P, ctypes.c_size_t],
         "fcfs_apply_edge_offsets_grid": [P, P, P, P, P, P, i64, i32, P, P],
+        "fcfs_pupil_loss_workspace_size": [sz],
+        "fcfs_pupil_loss": [P, P, P, P, i32, i32, ctypes.c_double, P, P, P, ctypes.c_size_t],
         "fcfs_haar": [P, ctypes.POINTER(FcfsHaarClip), P, ctypes.c_size_t],
         "fcfs_adjoint": [P, clip_p, P, P, P, c_int, P, ctypes.c_size_t],
         "fcfs_adjoint_band": [P, clip_p, P, i32, i32, ctypes.c_double, P, P, c_int, P,

@@ -685,6 +685,73 @@ hipError_t launch_adjoint(const AdjPlan &a, const int32_t *x, const int32_t *y, 
 }
 
 // ---------------------------------------------------------------------------
+// Pupil loss of the edge-moving optimisation: L = sum |H F - G|^2 over the
+// grid, H a real weight (an array, or the indicator of the disc
+// k^2 + l^2 <= r2), and its cotangent dL/dRe F + j dL/dIm F = 2 H (H F - G),
+// written in the layout of F.  Each block sums its range in FP64 in a fixed
+// order; the block partials are added in block order by one more block, so
+// the value does not depend on scheduling.
+// ---------------------------------------------------------------------------
+constexpr int kLossBlocks = 512;
+
+__global__ __launch_bounds__(256) void k_pupil_loss(const float2 *__restrict__ F,
+                                                    const float2 *__restrict__ G,
+                                                    const float *__restrict__ H, int K, int L,
+                                                    double r2, float2 *__restrict__ grad,
+                                                    double *__restrict__ part) {
+  const int64_t n = (2 * (int64_t)K + 1) * (2 * (int64_t)L + 1);
+  const int W = 2 * L + 1;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    double h;
+    if (H) {
+      h = (double)H[i];
+    } else {
+      const int k = (int)(i / W) - K, l = (int)(i % W) - L;
+      h = r2 < 0.0 || (double)k * k + (double)l * l <= r2 ? 1.0 : 0.0;
+    }
+    const float2 f = F[i], g = G[i];
+    const double dr = h * f.x - g.x, di = h * f.y - g.y;
+    acc += dr * dr + di * di;
+    grad[i] = make_float2((float)(2.0 * h * dr), (float)(2.0 * h * di));
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_parts(const double *__restrict__ part, int n,
+                                                   double *__restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += part[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+size_t pupil_loss_workspace_bytes() { return sizeof(double) * kLossBlocks; }
+
+hipError_t launch_pupil_loss(const float *F, const float *G, const float *H, int K, int L, double r2,
+                             double *loss, float *grad, void *ws, hipStream_t st) {
+  const int64_t n = (2 * (int64_t)K + 1) * (2 * (int64_t)L + 1);
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kLossBlocks, (n + 255) / 256));
+  hipLaunchKernelGGL(k_pupil_loss, dim3(nb), dim3(256), 0, st, (const float2 *)F, (const float2 *)G,
+                     H, K, L, r2, (float2 *)grad, (double *)ws);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, (const double *)ws, nb, loss);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Edge-offset gradient: each edge collects the gradient of its two corners
 // along its normal direction (x for vertical edges, y for horizontal).  Two
 // contributions per edge, so the atomic sum is order independent.

@@ -20,7 +20,7 @@ using fcfs::Tables;
 
 // Kernel families timed by the profiling hooks.
 enum ProfKind { kProfPrepass = 0, kProfAxis, kProfContract, kProfEpilogue, kProfAdjoint,
-                kProfBatch, kProfFft, kProfHaar, kProfKinds };
+                kProfBatch, kProfFft, kProfHaar, kProfLoss, kProfKinds };
 
 struct fcfs_handle {
   int device = 0;
@@ -1165,6 +1165,29 @@ fcfs_status fcfs_apply_edge_offsets_grid(fcfs_handle *h, const int32_t *base_x,
   hipError_t e = fcfs::launch_apply_offsets(base_x, base_y, hedge, vedge, offsets, V, x, y,
                                             h->stream, frac_bits);
   if (e) return hip_fail(h, e, "offset launch");
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_pupil_loss_workspace_size(size_t *bytes) {
+  if (!bytes) return fail(nullptr, FCFS_ERR_INVALID_ARG, "NULL argument");
+  *bytes = fcfs::pupil_loss_workspace_bytes();
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_pupil_loss(fcfs_handle *h, const float *F, const float *G, const float *H,
+                            int32_t K, int32_t L, double radius, double *loss, float *grad,
+                            void *ws, size_t ws_bytes) {
+  fcfs_status st = enter(h);
+  if (st) return st;
+  if (K < 0 || L < 0) return fail(h, FCFS_ERR_INVALID_ARG, "K and L must be >= 0");
+  if (!F || !G || !loss || !grad) return fail(h, FCFS_ERR_INVALID_ARG, "NULL array");
+  if (!(radius == radius)) return fail(h, FCFS_ERR_INVALID_ARG, "radius is NaN");
+  if (ws_bytes < fcfs::pupil_loss_workspace_bytes() || !ws || ((uintptr_t)ws & 255u))
+    return fail(h, FCFS_ERR_WORKSPACE, "workspace too small, NULL or misaligned");
+  ProfScope ps(h, kProfLoss);
+  hipError_t e = fcfs::launch_pupil_loss(F, G, H, K, L, radius >= 0.0 ? radius * radius : -1.0,
+                                         loss, grad, ws, h->stream);
+  if (e) return hip_fail(h, e, "loss launch");
   return FCFS_OK;
 }
 

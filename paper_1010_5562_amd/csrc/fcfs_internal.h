@@ -149,6 +149,10 @@ hipError_t launch_edge_grad(const float *gx, const float *gy, const int64_t *hed
                             const int64_t *vedge, int64_t V, int64_t E, float *g_edge,
                             hipStream_t st);
 
+// Pupil loss and its cotangent (workspace: pupil_loss_workspace_bytes()).
+size_t pupil_loss_workspace_bytes();
+hipError_t launch_pupil_loss(const float *F, const float *G, const float *H, int K, int L, double r2,
+                             double *loss, float *grad, void *ws, hipStream_t st);
 hipError_t launch_apply_offsets(const int32_t *bx, const int32_t *by, const int64_t *hedge,
                                 const int64_t *vedge, const float *off, int64_t V, int32_t *x,
                                 int32_t *y, hipStream_t st, int frac_bits = 0);

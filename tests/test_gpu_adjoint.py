@@ -156,3 +156,48 @@ def test_autograd_low_pass(P, oracle_lib, prec):
     e = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
     _say(f"low-pass autograd {prec}: err/max|g| = {e:.3e}")
     assert e <= GTOL[prec]
+
+
+def test_pupil_loss_kernel(P):
+    # value and cotangent of sum |H F - G|^2 against the same arithmetic in
+    # numpy FP64, for the disc mask and for explicit weights
+    rng = np.random.default_rng(11)
+    K, L = 70, 45
+    F = (rng.normal(size=(2 * K + 1, 2 * L + 1)) + 1j * rng.normal(size=(2 * K + 1, 2 * L + 1))).astype(np.complex64)
+    G = (rng.normal(size=F.shape) + 1j * rng.normal(size=F.shape)).astype(np.complex64)
+    kk, ll = np.meshgrid(np.arange(-K, K + 1), np.arange(-L, L + 1), indexing="ij")
+    for H, radius in ((None, 30.5), (rng.uniform(0, 2, F.shape).astype(np.float32), None)):
+        Ft = torch.as_tensor(F).cuda().requires_grad_(True)
+        Gt = torch.as_tensor(G).cuda()
+        loss = P.PupilLoss.apply(Ft, Gt, radius, None if H is None else torch.as_tensor(H).cuda())
+        loss.backward()
+        torch.cuda.synchronize()
+        h = (kk ** 2 + ll ** 2 <= radius ** 2).astype(np.float64) if H is None else H.astype(np.float64)
+        d = h * F.astype(np.complex128) - G.astype(np.complex128)
+        want = float(np.sum(np.abs(d) ** 2))
+        assert abs(float(loss.item()) - want) <= 1e-12 * want
+        gw = (2 * h * d)
+        got = Ft.grad.cpu().numpy()
+        assert np.array_equal(got.real, gw.real.astype(np.float32))
+        assert np.array_equal(got.imag, gw.imag.astype(np.float32))
+
+
+def test_pupil_loss_in_the_optimisation_step(P):
+    # the fused loss gives the same edge gradient as the loss written in torch ops
+    T, K = 1024, 40
+    r = 0.35 * K
+    rb = int(np.floor(r))
+    clip = synth.clip(43, T, K, n_polygons=50)
+    geom = P.Geometry(clip.xy, clip.off, T, K)
+    kk, ll = np.meshgrid(np.arange(-K, K + 1), np.arange(-K, K + 1), indexing="ij")
+    Hd = torch.as_tensor((kk ** 2 + ll ** 2 <= r * r).astype(np.float32)).cuda()
+    rng = np.random.default_rng(3)
+    Gt = Hd * torch.as_tensor((rng.normal(size=kk.shape) + 1j * rng.normal(size=kk.shape)).astype(np.complex64)).cuda()
+    grads = []
+    for fused in (False, True):
+        off = torch.zeros(geom.n_edges, dtype=torch.float32, device="cuda", requires_grad=True)
+        Fv = P.FCFSFunction.apply(off, geom, "fp32", (rb, rb), r)
+        loss = P.PupilLoss.apply(Fv, Gt, r) if fused else ((Hd * Fv - Gt).abs() ** 2).sum()
+        loss.backward()
+        grads.append(off.grad.cpu().numpy().astype(np.float64))
+    assert np.max(np.abs(grads[0] - grads[1])) <= 1e-5 * np.max(np.abs(grads[0]))
