@@ -71,19 +71,21 @@ def timed(fn, steps: int, warmup: int, handle, kinds=("contract",)):
     """Runs fn warmup + steps times; returns (ms per step, per-kernel events).
 
     Only the launches of ``kinds`` are bracketed by events inside the timed
-    region (two event records per launch on the launch's own stream)."""
+    region (two event records per launch on the launch's own stream); with
+    kinds None nothing is."""
     import torch
 
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    handle.profile_begin(kinds)
+    if kinds is not None:
+        handle.profile_begin(kinds)
     t_a = time.perf_counter()
     for _ in range(steps):
         fn()
     torch.cuda.synchronize()
     t_b = time.perf_counter()
-    prof = handle.profile_end()
+    prof = handle.profile_end() if kinds is not None else None
     return (t_b - t_a) * 1e3 / steps, prof
 
 
@@ -379,8 +381,10 @@ def main() -> int:
 
     # ------------------------------------------------------------------ C1
     # One 64-corner polygon, T = 2048, |k|,|l| <= 64: a latency case (a few
-    # microseconds of work).  The direct call and a one-clip captured graph
-    # are timed; the error is over the whole 129 x 129 grid.
+    # microseconds of work).  Timed: the call (one launch of the FP64 direct
+    # form at this size), the staged MFMA path forced with a tile variant,
+    # and a one-clip captured batch graph; the error is over the whole
+    # 129 x 129 grid.
     c1, _, _ = synth.clip_c1(1)
     x1, y1, s1, _, _ = P.loops_to_corners(c1.xy, c1.off)
     x1d, y1d, s1d = (torch.as_tensor(a).to(dev) for a in (x1, y1, s1))
@@ -393,19 +397,27 @@ def main() -> int:
     for prec in ("fp32", "bf16"):
         F1 = torch.empty((2 * c1.K + 1, 2 * c1.L + 1), dtype=torch.complex64, device=dev)
         a1 = torch.empty(1, dtype=torch.int64, device=dev)
-        ms1, _ = timed(lambda: P.forward(x1d, y1d, s1d, c1.T, c1.K, c1.L, precision=prec,
-                                         out=F1, area_out=a1), n1, 5, h)
+        call = lambda: P.forward(x1d, y1d, s1d, c1.T, c1.K, c1.L, precision=prec, out=F1,
+                                 area_out=a1)
+        ms1, _ = timed(call, n1, 5, h, kinds=None)
+        _, pr1 = timed(call, n1, 0, h, kinds=("direct",))
         e1 = float(np.max(np.abs(F1.cpu().numpy().astype(np.complex128) - ref1)) / f001)
+        mss, _ = timed(lambda: P.forward(x1d, y1d, s1d, c1.T, c1.K, c1.L, precision=prec,
+                                         out=F1, area_out=a1, tile=0), n1, 5, h, kinds=None)
+        es = float(np.max(np.abs(F1.cpu().numpy().astype(np.complex128) - ref1)) / f001)
         b1 = P.Batch([(x1d, y1d, s1d, c1.T, c1.K, c1.L)], precision=prec)
-        msg, _ = timed(b1.run, n1, 5, h, kinds=("batch",))
+        msg, _ = timed(b1.run, n1, 5, h, kinds=None)
         eg = float(np.max(np.abs(b1.F[0].cpu().numpy().astype(np.complex128) - ref1)) / f001)
-        single[prec] = {"us_per_call": ms1 * 1e3, "us_per_graph_replay": msg * 1e3,
+        single[prec] = {"us_per_call": ms1 * 1e3, "direct_kernel_us": kavg(pr1, "direct") * 1e3,
+                        "us_per_call_staged": mss * 1e3, "err_rel_f00_staged": es,
+                        "us_per_graph_replay": msg * 1e3,
                         "value": p1 / (ms1 * 1e-3), "err_rel_f00": max(e1, eg),
                         "area_exact": int(a1.item()) == int(area1)
                         and int(b1.area[0].item()) == int(area1)}
         b1.close()
-        log(f"single polygon {prec}: {ms1 * 1e3:.1f} us per call, {msg * 1e3:.1f} us per "
-            f"graph replay, err {max(e1, eg):.2e}")
+        log(f"single polygon {prec}: {ms1 * 1e3:.1f} us per call (direct kernel "
+            f"{kavg(pr1, 'direct') * 1e3:.1f} us), staged {mss * 1e3:.1f} us, "
+            f"{msg * 1e3:.1f} us per graph replay, err {max(e1, eg):.2e}")
     forms["single_polygon"] = single
 
     # ------------------------------------------------------------- general tile

@@ -115,7 +115,12 @@ fcfs_status fcfs_workspace_size(const fcfs_clip *c, fcfs_precision p, int adjoin
 /* Forward transform (Prop. 3 / Alg. 2 for one tile): writes c->F and
  * c->area.  ws: (device) workspace of at least fcfs_workspace_size bytes,
  * 256-byte aligned.  Steps enqueued: pre-pass (phase reduction, area),
- * axis sums (FP64), vertex contraction on MFMA, epilogue. */
+ * axis sums (FP64), vertex contraction on MFMA, epilogue.
+ * Small problems (V <= 1024 corners and V (K+1)(2L+1) <= 2^22) are evaluated
+ * in one launch by the direct form, in FP64 whatever `p` asks for (the same
+ * exact integer phases; the result is at least as accurate as the requested
+ * form); a tile variant forced with fcfs_set_tile selects the staged MFMA
+ * path at every size.  The workspace size is the same either way. */
 fcfs_status fcfs_forward(fcfs_handle *h, const fcfs_clip *c, fcfs_precision p, void *ws,
                          size_t ws_bytes);
 
@@ -348,7 +353,7 @@ fcfs_status fcfs_workspace_size_tile(const fcfs_clip *c, fcfs_precision p, int32
  * work (histograms, guard block, axis DFTs), 2 contraction, 3 epilogue,
  * 4 adjoint kernels, 5 batched graph, 6 lattice form, 7 Haar quadtree walk
  * (the Haar transform's clear-and-plan launches count as pre-pass, its
- * scaling pass as epilogue), 8 pupil loss.
+ * scaling pass as epilogue), 8 pupil loss, 9 direct form of small problems.
  * Each bracketed launch adds two event records to its stream. */
 fcfs_status fcfs_profile_begin(fcfs_handle *h, uint32_t kinds);
 fcfs_status fcfs_profile_end(fcfs_handle *h, double *ms, int64_t *count, int32_t nkinds);

@@ -9,6 +9,7 @@ raises if the library or the device is missing.
 from __future__ import annotations
 
 import ctypes
+import functools
 
 import numpy as np
 
@@ -70,6 +71,7 @@ def _clip(x, y, s, V, T, K, L, F=None, area=None) -> FcfsClip:
     return c
 
 
+@functools.lru_cache(maxsize=256)
 def workspace_size(V: int, T: int, K: int, L: int, precision="bf16", adjoint: bool = False,
                    tile: int | None = None) -> int:
     lib = load()
@@ -98,6 +100,7 @@ class Handle:
         self._h = ctypes.c_void_p()
         stream = torch.cuda.current_stream(dev).cuda_stream
         check(self.lib.fcfs_create(ctypes.byref(self._h), dev.index, ctypes.c_void_p(stream)))
+        self._stream = stream
         self._ws = None
 
     def close(self):
@@ -119,13 +122,15 @@ class Handle:
         import torch
 
         stream = torch.cuda.current_stream(self.device).cuda_stream
-        check(self.lib.fcfs_set_stream(self._h, ctypes.c_void_p(stream)), self._h)
+        if stream != self._stream:
+            check(self.lib.fcfs_set_stream(self._h, ctypes.c_void_p(stream)), self._h)
+            self._stream = stream
 
     def set_tile(self, variant: int = -1):
         check(self.lib.fcfs_set_tile(self._h, int(variant)), self._h)
 
     PROFILE_KINDS = ("prepass", "axis", "contract", "epilogue", "adjoint", "batch", "fft",
-                     "haar", "loss")
+                     "haar", "loss", "direct")
 
     def profile_begin(self, kinds=None):
         """Starts event timing of the named kinds (all kinds when None)."""
@@ -164,12 +169,20 @@ def default_handle(device=None) -> Handle:
     return h
 
 
+def _on(dev, a, dtype):
+    import torch
+
+    if isinstance(a, torch.Tensor) and a.dtype == dtype and a.device == dev and a.is_contiguous():
+        return a
+    return torch.as_tensor(a, dtype=dtype).to(dev).contiguous()
+
+
 def _corners_on(dev, x, y, s):
     import torch
 
-    x = torch.as_tensor(x, dtype=torch.int32).to(dev).contiguous()
-    y = torch.as_tensor(y, dtype=torch.int32).to(dev).contiguous()
-    s = torch.as_tensor(s, dtype=torch.int8).to(dev).contiguous()
+    x = _on(dev, x, torch.int32)
+    y = _on(dev, y, torch.int32)
+    s = _on(dev, s, torch.int8)
     if not (x.numel() == y.numel() == s.numel()):
         raise ValueError("x, y, s differ in length")
     return x, y, s

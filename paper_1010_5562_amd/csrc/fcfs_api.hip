@@ -20,7 +20,7 @@ using fcfs::Tables;
 
 // Kernel families timed by the profiling hooks.
 enum ProfKind { kProfPrepass = 0, kProfAxis, kProfContract, kProfEpilogue, kProfAdjoint,
-                kProfBatch, kProfFft, kProfHaar, kProfLoss, kProfKinds };
+                kProfBatch, kProfFft, kProfHaar, kProfLoss, kProfDirect, kProfKinds };
 
 struct fcfs_handle {
   int device = 0;
@@ -438,6 +438,16 @@ struct ProfScope {
 template <class T>
 T *ws_at(void *ws, size_t off) {
   return (T *)((char *)ws + off);
+}
+
+// Small problems (at most kDirectMaxCorners corners and kDirectMaxPairs
+// corner-coefficient pairs) take the one-launch FP64 direct form: there the
+// staged path is bound by its launches, not by arithmetic.
+constexpr int64_t kDirectMaxCorners = 1024;
+constexpr int64_t kDirectMaxPairs = int64_t(1) << 22;
+
+bool use_direct(int64_t V, int K, int L) {
+  return V <= kDirectMaxCorners && V * (K + 1) * (2 * (int64_t)L + 1) <= kDirectMaxPairs;
 }
 
 fcfs_status run_forward(fcfs_handle *h, const fcfs_clip *c, const FwdPlan &p, void *ws) {
@@ -895,6 +905,11 @@ fcfs_status fcfs_forward(fcfs_handle *h, const fcfs_clip *c, fcfs_precision p, v
   FwdPlan q;
   if ((st = make_plan(h, c->V, c->T, c->K, c->L, (int)p, h->tile_override, &q))) return st;
   if ((st = check_ws(h, q, ws, ws_bytes))) return st;
+  if (h->tile_override < 0 && use_direct(c->V, c->K, c->L)) {
+    ProfScope ps(h, kProfDirect);
+    hipError_t e = fcfs::launch_direct(q, c->x, c->y, c->s, h->tab.w64, c->F, c->area, h->stream);
+    return e ? hip_fail(h, e, "direct launch") : FCFS_OK;
+  }
   return run_forward(h, c, q, ws);
 }
 

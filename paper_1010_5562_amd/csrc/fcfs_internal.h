@@ -89,6 +89,10 @@ hipError_t launch_epilogue(const FwdPlan &p, const void *ws, float *F, int64_t *
 // the axes and DC entries only (lattice form)
 hipError_t launch_epilogue_axes(const FwdPlan &p, const void *ws, float *F, int64_t *area,
                                 hipStream_t st);
+// direct form for small problems: every coefficient in FP64 from the raw
+// corner arrays in one launch (uses p.V, T, shift, K, L and the output grid)
+hipError_t launch_direct(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
+                         const double2 *w64, float *F, int64_t *area, hipStream_t st);
 // lattice form of the general term (fcfs_fft.hip): writes F for k, l != 0
 // General tile (periods Mx, My in [2, 8192], any integers): pre-pass into
 // residue records, side-stream work (histograms, FP64 guard block, axis DFTs

@@ -990,6 +990,151 @@ hipError_t launch_epilogue_axes(const FwdPlan &p, const void *ws, float *F, int6
 }
 
 // ---------------------------------------------------------------------------
+// Direct form for small problems: every coefficient of Prop. 3 as an FP64 sum
+// over the corners, in one launch from the raw corner arrays (no pre-pass,
+// workspace, partials or second pass).  At a few hundred corners and a few
+// thousand frequencies the staged path is launch-bound; this form costs one
+// launch and V/4 corner steps per wave.
+// Block roles (block-uniform):
+//   [0, nq)            P, U, R, Q of one k >= 1 and 64 consecutive l >= 1
+//   [nq, nq + nax)     64 consecutive frequencies of one axis sum (Steps 2, 3)
+//   nq + nax           the exact area (Step 1) and F[0, 0]
+// A block first stages its per-corner factors in LDS (for a quadrant block
+// s_v e(k x_v) from the exact table, for an axis block the integer weight),
+// then wave w takes corners [w V4, (w + 1) V4), V4 = ceil(V / 4): the factor
+// is an LDS broadcast, the lane's entry e(l y_v) a table lookup at the exact
+// integer phase, as in the contraction.  The four wave sums are added in
+// wave order, so the result does not depend on scheduling.
+// ---------------------------------------------------------------------------
+constexpr int kDirectUnroll = 8;
+constexpr int kDirectMaxV = 1024;  // corners staged in LDS
+
+__global__ __launch_bounds__(256) void k_direct(const int32_t *__restrict__ x,
+                                                const int32_t *__restrict__ y,
+                                                const int8_t *__restrict__ s, int64_t V, int T,
+                                                int shift, int K, int L,
+                                                const double2 *__restrict__ w64, OutGrid o,
+                                                int64_t *__restrict__ area) {
+  // per corner: the block's uniform factor (s_v e(k x_v) for a quadrant
+  // block, s_v times the other coordinate for an axis block) and the scaled
+  // residue of the coordinate whose phase varies along the lanes
+  __shared__ double2 s_a[kDirectMaxV];
+  __shared__ uint32_t s_c[kDirectMaxV];
+  __shared__ double4 red[4][64];
+  __shared__ unsigned long long ared[4];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nlb = (L + 63) / 64, nkb = (K + 63) / 64;
+  const int nq = K > 0 && L > 0 ? K * nlb : 0;
+  const int nax = nkb + nlb;
+  const int b = blockIdx.x;
+  const uint32_t tmask = (uint32_t)(T - 1), mask = (uint32_t)(kTabN - 1);
+  const int nv = (int)V;
+
+  if (b >= nq + nax) {
+    // area = sum s x y modulo 2^64 (exact whenever the true area fits int64)
+    unsigned long long acc = 0;
+    for (int v = threadIdx.x; v < nv; v += 256)
+      acc += (unsigned long long)((long long)s[v] * (long long)x[v] * (long long)y[v]);
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) ared[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const long long A = (long long)(ared[0] + ared[1] + ared[2] + ared[3]);
+      put(o, 0, 0, (float)((double)A * o.dc), 0.0f);
+      if (area) *area = A;
+    }
+    return;
+  }
+
+  const bool quad = b < nq;
+  const bool xaxis = !quad && b - nq < nkb;
+  const uint32_t k = quad ? 1u + (uint32_t)(b / nlb) : 0u;
+  // the lane's frequency: l for a quadrant block, f for an axis block
+  const int f = 1 + (quad ? (b % nlb) : xaxis ? b - nq : b - nq - nkb) * 64 + lane;
+  for (int v = threadIdx.x; v < nv; v += 256) {
+    const int32_t xv = x[v], yv = y[v];
+    const int sv = s[v];
+    if (quad) {
+      const double2 w = w64[(k * (((uint32_t)xv & tmask) << shift)) & mask];
+      s_a[v] = make_double2(sv * w.x, sv * w.y);
+      s_c[v] = ((uint32_t)yv & tmask) << shift;
+    } else {
+      s_a[v] = make_double2((double)(sv * (xaxis ? yv : xv)), 0.0);
+      s_c[v] = ((uint32_t)(xaxis ? xv : yv) & tmask) << shift;
+    }
+  }
+  __syncthreads();
+  const int per = (nv + 3) / 4;
+  const int v0 = min(nv, wave * per), v1 = min(nv, v0 + per);
+  double P = 0.0, U = 0.0, R = 0.0, Q = 0.0;
+  for (int vb = v0; vb < v1; vb += kDirectUnroll) {
+    double2 a[kDirectUnroll], w[kDirectUnroll];
+#pragma unroll
+    for (int u = 0; u < kDirectUnroll; ++u) {
+      const int v = min(vb + u, v1 - 1);  // in range; the tail weight is zero
+      const double2 av = s_a[v];
+      const bool in = vb + u < v1;
+      a[u] = make_double2(in ? av.x : 0.0, in ? av.y : 0.0);
+      w[u] = w64[((uint32_t)f * s_c[v]) & mask];
+    }
+    if (quad) {
+#pragma unroll
+      for (int u = 0; u < kDirectUnroll; ++u) {
+        P = fma(a[u].x, w[u].x, P);
+        U = fma(a[u].x, w[u].y, U);
+        R = fma(a[u].y, w[u].x, R);
+        Q = fma(a[u].y, w[u].y, Q);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < kDirectUnroll; ++u) {
+        P = fma(a[u].x, w[u].x, P);   // Re sum h e(f q), e = conj(w)
+        U = fma(-a[u].x, w[u].y, U);  // Im
+      }
+    }
+  }
+  red[wave][lane] = make_double4(P, U, R, Q);
+  __syncthreads();
+  if (wave != 0) return;
+  for (int wv = 1; wv < 4; ++wv) {
+    P += red[wv][lane].x;
+    U += red[wv][lane].y;
+    R += red[wv][lane].z;
+    Q += red[wv][lane].w;
+  }
+  if (quad) {
+    if (f <= L) store_quad(o, (int)k, f, (double)T, P, U, R, Q);
+    return;
+  }
+  if (f > (xaxis ? K : L)) return;
+  // F[f,0] = j/(2 pi f) Sx[f] (and F[0,f] likewise), Hermitian partners
+  const double sc = (xaxis ? o.ax : o.ay) / (2.0 * kPi * (double)f);
+  const float fre = (float)(-U * sc), fim = (float)(P * sc);
+  if (xaxis) {
+    put(o, f, 0, fre, fim);
+    put(o, -f, 0, fre, -fim);
+  } else {
+    put(o, 0, f, fre, fim);
+    put(o, 0, -f, fre, -fim);
+  }
+}
+
+int direct_block_count(int K, int L) {
+  const int nlb = (L + 63) / 64, nkb = (K + 63) / 64;
+  return (K > 0 && L > 0 ? K * nlb : 0) + nkb + nlb + 1;
+}
+
+hipError_t launch_direct(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
+                         const double2 *w64, float *F, int64_t *area, hipStream_t st) {
+  if (p.V > kDirectMaxV) return hipErrorInvalidValue;
+  const OutGrid o{(float2 *)F, p.KO, p.LO, p.r2, p.eg, p.eax, p.eay, p.edc};
+  hipLaunchKernelGGL(k_direct, dim3(direct_block_count(p.K, p.L)), dim3(256), 0, st, x, y, s,
+                     p.V, p.T, p.shift, p.K, p.L, w64, o, area);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Debug export of the integer phases used by the contraction:
 // out[i*V + v] = ((k0+i) * x_v) mod T  (axis 0) or with y_v (axis 1, the
 // sign-free phase), recovered from the same byte offsets the kernels use.

@@ -92,19 +92,75 @@ def test_phases_bit_exact(P):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_degenerate_sizes(P, oracle_lib, prec):
+@pytest.mark.parametrize("tile", [None, 0])  # None: direct form at this size; 0: staged MFMA path
+def test_degenerate_sizes(P, oracle_lib, prec, tile):
     clip = synth.clip(12, 512, 20, n_polygons=9)
     x, y, s = _corners(P, clip)
     for K, L in ((0, 0), (0, 7), (9, 0), (1, 1), (33, 2)):
-        _say(f"degenerate K={K} L={L} prec={prec}")
+        _say(f"degenerate K={K} L={L} prec={prec} tile={tile}")
         ref, area = oracle_lib.cfs_grid(clip.xy, clip.off, 512, K, L)
-        F, a = _run(P, x, y, s, 512, K, L, prec)
+        F, a = _run(P, x, y, s, 512, K, L, prec, tile=tile)
         assert a == area
         assert _err(F, ref, K, L) <= TOL[prec]
     # no corners at all: every coefficient is zero
     e = np.zeros(0, np.int32)
-    F, a = _run(P, e, e, e.astype(np.int8), 512, 5, 4, prec)
+    F, a = _run(P, e, e, e.astype(np.int8), 512, 5, 4, prec, tile=tile)
     assert a == 0 and np.all(F == 0)
+
+
+def _launches(P, fn):
+    h = P.default_handle()
+    h.profile_begin(("direct", "contract"))
+    fn()
+    prof = h.profile_end()
+    return prof["direct"][1], prof["contract"][1]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_direct_form_small_problems(P, oracle_lib, prec):
+    # At most 1024 corners and 2^22 corner-coefficient pairs: one launch of
+    # the FP64 direct form whatever the precision (so the FP32 bound holds);
+    # a forced tile variant runs the staged MFMA path on the same input.
+    c1, _, _ = synth.clip_c1(1)
+    big = synth.clip(41, 4096, 20, n_polygons=60)
+    out = synth.clip(42, 300, 12, n_polygons=25)
+    cases = [(c1.xy, c1.off, c1.T, c1.K, c1.L),
+             (big.xy, big.off, 4096, 20, 20),
+             (synth.shift_loops(out.xy, -150, 77), out.off, 2, 6, 6),        # K > T
+             (synth.shift_loops(out.xy, 70000, -90000), out.off, 512, 40, 9)]
+    for xy, off, T, K, L in cases:
+        x, y, s, _, _ = P.loops_to_corners(xy, off)
+        V = x.size
+        assert V <= 1024 and V * (K + 1) * (2 * L + 1) <= 1 << 22
+        ref, area = oracle_lib.cfs_grid(xy, off, T, K, L)
+        res = {}
+        for tile in (None, 0):
+            def go():
+                res[tile] = _run(P, x, y, s, T, K, L, prec, tile=tile)
+            nd, nc = _launches(P, go)
+            assert (nd, nc) == ((1, 0) if tile is None else (0, 1 if K and L else 0))
+            F, a = res[tile]
+            assert a == area
+            e = _err(F, ref, K, L)
+            _say(f"small V={V} T={T} K={K} L={L} {prec} tile={tile}: err/|F00| = {e:.3e}")
+            assert e <= (TOL["fp32"] if tile is None else TOL[prec])
+        assert res[None][0][K, L] == res[0][0][K, L]  # the same exact DC entry
+
+
+def test_direct_form_threshold(P):
+    # one step past either bound (1024 corners, 2^22 corner-coefficient
+    # pairs) selects the staged path
+    clip = synth.clip(43, 2048, 8, n_polygons=50)
+    x, y, s, _, _ = P.loops_to_corners(clip.xy, clip.off)
+    V = x.size
+    assert 512 < V <= 1024
+    lo = max(l for l in range(4096) if V * 2 * (2 * l + 1) <= 1 << 22)  # K = 1
+    for l, want in ((lo, (1, 0)), (lo + 1, (0, 1))):
+        assert _launches(P, lambda: _run(P, x, y, s, 2048, 1, l, "bf16")) == want
+    many = synth.clip(44, 2048, 8, n_polygons=70)
+    xm, ym, sm, _, _ = P.loops_to_corners(many.xy, many.off)
+    assert xm.size > 1024
+    assert _launches(P, lambda: _run(P, xm, ym, sm, 2048, 1, 1, "bf16")) == (0, 1)
 
 
 @pytest.mark.parametrize("T", [2, 16, 8192])
