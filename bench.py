@@ -89,6 +89,29 @@ def timed(fn, steps: int, warmup: int, handle, kinds=("contract",)):
     return (t_b - t_a) * 1e3 / steps, prof
 
 
+def step_stats(fn, n: int):
+    """Per-step device time of n further steps, each bracketed by events on
+    the current stream (every kernel of a step, side stream included, ends
+    before the step's last launch): mean with its 95% confidence half-width,
+    median, min and max in ms."""
+    import numpy as np
+    import torch
+
+    evs = []
+    for _ in range(n):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        evs.append((a, b))
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in evs])
+    return {"n": n, "mean": float(t.mean()),
+            "ci95": float(1.96 * t.std(ddof=1) / np.sqrt(n)) if n > 1 else None,
+            "median": float(np.median(t)), "min": float(t.min()), "max": float(t.max())}
+
+
 def breakdown(fn, steps: int, handle):
     """Per-kind average kernel times from extra, untimed steps with events
     around every launch."""
@@ -177,6 +200,8 @@ def main() -> int:
             legs[prec]["breakdown"] = breakdown(
                 lambda: P.forward(xd, yd, sd, T, K, L, precision=prec, out=F, area_out=area),
                 max(3, args.steps // 2), h)
+            legs[prec]["stats"] = step_stats(
+                lambda: P.forward(xd, yd, sd, T, K, L, precision=prec, out=F, area_out=area), 10)
         log(f"{prec}: {ms:.3f} ms/step  {pairs / ms * 1e3:.4g} pairs/s  "
             f"contract {kavg(prof, 'contract'):.3f} ms")
 
@@ -259,6 +284,9 @@ def main() -> int:
         # per-kind kernel times from separate steps with events on every launch
         # (the side-stream figure spans the histograms, guard block and axis DFTs)
         "kernels_ms": main_leg["breakdown"],
+        # 10 further steps timed one by one with events (the paper's protocol
+        # of repeated runs): mean +- 95% CI, median
+        "step_ms_stats": main_leg["stats"],
         "area_exact": main_leg["area"],
     }
     for prec in ("fp32", "fp16"):
