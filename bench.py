@@ -541,7 +541,9 @@ def main() -> int:
     r5 = 0.35 * K5
     rb = int(np.floor(r5))
     c5 = synth.clip(5, T5, K5, min_vertices=100_000)
-    geom = P.Geometry(c5.xy, c5.off, T5, K5)
+    # the optimisation loop's offsets lie on the lattice by construction: no
+    # per-call host comparison (which would wait for the device every step)
+    geom = P.Geometry(c5.xy, c5.off, T5, K5, check_offsets=False)
     kk5, ll5 = np.meshgrid(np.arange(-K5, K5 + 1), np.arange(-K5, K5 + 1), indexing="ij")
     Hp = ((kk5 ** 2 + ll5 ** 2) <= r5 * r5).astype(np.float32)
     Hd = torch.as_tensor(Hp).to(dev)

@@ -223,10 +223,7 @@ def forward(x, y, s, T: int, K: int, L: int | None = None, precision="bf16", han
         else:
             kmax, lmax = (K, L) if band is None else (int(band[0]), int(band[1]))
             rad = -1.0 if radius is None else float(radius)
-            nb = ctypes.c_size_t(0)
-            check(h.lib.fcfs_band_workspace_size(ctypes.byref(c), kmax, lmax, rad,
-                                                 _prec(precision), ctypes.byref(nb)))
-            ws = h.workspace(nb.value)
+            ws = h.workspace(_band_workspace_size(V, T, K, L, kmax, lmax, rad, _prec(precision)))
             check(h.lib.fcfs_forward_band(h.ptr, ctypes.byref(c), kmax, lmax, rad,
                                           _prec(precision), ctypes.c_void_p(ws.data_ptr()),
                                           ctypes.c_size_t(ws.numel())), h.ptr)
@@ -389,7 +386,7 @@ def adjoint(x, y, s, T: int, K: int, L: int, grad_F, precision="bf16", band=None
     h.sync_stream()
     x, y, s = _corners_on(h.device, x, y, s)
     V = x.numel()
-    G = torch.as_tensor(grad_F).to(h.device, torch.complex64).contiguous()
+    G = _on(h.device, grad_F, torch.complex64)
     if G.numel() != (2 * K + 1) * (2 * L + 1):
         raise ValueError("grad_F must have (2K+1)(2L+1) entries")
     gx = torch.empty(V, dtype=torch.float32, device=h.device)
@@ -414,8 +411,8 @@ def edge_grad(gx, gy, hedge, vedge, n_edges: int, handle=None):
     h = handle or default_handle()
     h.sync_stream()
     dev = h.device
-    hedge = torch.as_tensor(hedge, dtype=torch.int64).to(dev).contiguous()
-    vedge = torch.as_tensor(vedge, dtype=torch.int64).to(dev).contiguous()
+    hedge = _on(dev, hedge, torch.int64)
+    vedge = _on(dev, vedge, torch.int64)
     g = torch.empty(int(n_edges), dtype=torch.float32, device=dev)
     check(h.lib.fcfs_edge_grad(h.ptr, ctypes.c_void_p(gx.data_ptr()), ctypes.c_void_p(gy.data_ptr()),
                                ctypes.c_void_p(hedge.data_ptr()), ctypes.c_void_p(vedge.data_ptr()),
@@ -431,12 +428,18 @@ class Geometry:
     offsets.  General tile (``Ny`` given, T not a power of two, or
     ``frac_bits`` > 0): periods T x Ny and corners on the grid of step
     2^-frac_bits (``xy`` holds the true coordinates); edge offsets are then
-    multiples of 2^-frac_bits."""
+    multiples of 2^-frac_bits.
+
+    ``check_offsets``: offsets off that grid raise FcfsError (a comparison
+    that waits for the device on every call); with False they are rounded to
+    the nearest grid point (ties to even) on the device and nothing waits,
+    for loops whose offsets lie on the grid by construction."""
 
     def __init__(self, xy, off, T: int, K: int, L: int | None = None, handle=None,
-                 Ny: int | None = None, frac_bits: int = 0):
+                 Ny: int | None = None, frac_bits: int = 0, check_offsets: bool = True):
         import torch
 
+        self.check_offsets = bool(check_offsets)
         self.handle = handle or default_handle()
         dev = self.handle.device
         self.frac_bits = int(frac_bits)
@@ -465,7 +468,7 @@ class Geometry:
         if off.numel() != self.n_edges:
             raise ValueError("one offset per edge")
         sc = float(1 << self.frac_bits)
-        if not torch.equal(off * sc, torch.round(off * sc)):
+        if self.check_offsets and not torch.equal(off * sc, torch.round(off * sc)):
             raise FcfsError(-1, "edge offsets must be multiples of 2^-frac_bits")
         V = self.base_x.numel()
         x = torch.empty_like(self.base_x)
@@ -481,6 +484,21 @@ class Geometry:
             check(h.lib.fcfs_apply_edge_offsets(h.ptr, *args, ctypes.c_void_p(x.data_ptr()),
                                                 ctypes.c_void_p(y.data_ptr())), h.ptr)
         return x, y
+
+
+@functools.lru_cache(maxsize=1)
+def _loss_workspace_size() -> int:
+    nb = ctypes.c_size_t(0)
+    check(load().fcfs_pupil_loss_workspace_size(ctypes.byref(nb)))
+    return int(nb.value)
+
+
+@functools.lru_cache(maxsize=256)
+def _band_workspace_size(V, T, K, L, kmax, lmax, rad, prec) -> int:
+    c = _clip(None, None, None, V, T, K, L)
+    nb = ctypes.c_size_t(0)
+    check(load().fcfs_band_workspace_size(ctypes.byref(c), kmax, lmax, rad, prec, ctypes.byref(nb)))
+    return int(nb.value)
 
 
 def _autograd_function():
@@ -535,14 +553,12 @@ def _autograd_function():
             h = handle or default_handle()
             h.sync_stream()
             F = F.detach().contiguous()
-            G = torch.as_tensor(G).to(h.device, torch.complex64).contiguous()
+            G = _on(h.device, G, torch.complex64)
             K2, L2 = F.shape
             grad = torch.empty_like(F)
             loss = torch.empty((), dtype=torch.float64, device=h.device)
-            Hc = None if H is None else torch.as_tensor(H).to(h.device, torch.float32).contiguous()
-            nb = ctypes.c_size_t(0)
-            check(h.lib.fcfs_pupil_loss_workspace_size(ctypes.byref(nb)))
-            ws = h.workspace(nb.value)
+            Hc = None if H is None else _on(h.device, H, torch.float32)
+            ws = h.workspace(_loss_workspace_size())
             check(h.lib.fcfs_pupil_loss(
                 h.ptr, ctypes.c_void_p(F.data_ptr()), ctypes.c_void_p(G.data_ptr()),
                 None if Hc is None else ctypes.c_void_p(Hc.data_ptr()), (K2 - 1) // 2, (L2 - 1) // 2,
