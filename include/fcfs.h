@@ -180,6 +180,18 @@ fcfs_status fcfs_general_workspace_size(const fcfs_gclip *c, fcfs_precision p, s
  * exact phases (f x) mod M, epilogue with the alpha factors above. */
 fcfs_status fcfs_forward_general(fcfs_handle *h, const fcfs_gclip *c, fcfs_precision p, void *ws,
                                  size_t ws_bytes);
+/* Low-pass form of fcfs_forward_general (the pupil of the lithography use in
+ * Sec. I and Sec. V, as fcfs_forward_band for the square tile): writes the
+ * whole (2K+1) x (2L+1) grid of c->F, computing only |k| <= kmax,
+ * |l| <= lmax and, when radius >= 0, k^2 + l^2 <= radius^2; every other entry
+ * is zero.  Frequency tiles wholly outside the disc are skipped.  ws: at least
+ * fcfs_general_band_workspace_size bytes, 256-byte aligned.
+ * FCFS_ERR_INVALID_ARG for a negative band or a NaN radius. */
+fcfs_status fcfs_general_band_workspace_size(const fcfs_gclip *c, int32_t kmax, int32_t lmax,
+                                             double radius, fcfs_precision p, size_t *bytes);
+fcfs_status fcfs_forward_general_band(fcfs_handle *h, const fcfs_gclip *c, int32_t kmax,
+                                      int32_t lmax, double radius, fcfs_precision p, void *ws,
+                                      size_t ws_bytes);
 
 /* Adjoint of fcfs_forward_general with respect to the corner coordinates, in
  * lattice units (the derivative of the general closed forms of Prop. 3):

@@ -259,12 +259,14 @@ def forward_fft(x, y, s, T: int, K: int, L: int | None = None, handle=None, out=
 
 
 def forward_general(x, y, s, Nx: int, Ny: int, K: int, L: int | None = None, frac_bits: int = 0,
-                    precision="bf16", handle=None, out=None, area_out=None):
+                    precision="bf16", handle=None, out=None, area_out=None, band=None,
+                    radius=None):
     """Coefficients of a general tile (``fcfs_forward_general``): periods Nx,
     Ny (any integers), corners on the grid of step 2^-frac_bits given as
     integers (true coordinate times 2^frac_bits).  Returns ``(F, area)`` as
     ``forward``; area is sum s x y in grid units (the area times
-    4^frac_bits)."""
+    4^frac_bits).  ``band`` and ``radius`` as for ``forward``
+    (``fcfs_forward_general_band``)."""
     import torch
 
     L = K if L is None else L
@@ -279,11 +281,22 @@ def forward_general(x, y, s, Nx: int, Ny: int, K: int, L: int | None = None, fra
     c = FcfsGClip(x.data_ptr(), y.data_ptr(), s.data_ptr(), x.numel(), int(Nx), int(Ny),
                   int(frac_bits), int(K), int(L), F.data_ptr(), area.data_ptr())
     nb = ctypes.c_size_t(0)
-    check(h.lib.fcfs_general_workspace_size(ctypes.byref(c), _prec(precision), ctypes.byref(nb)))
-    ws = h.workspace(nb.value)
-    check(h.lib.fcfs_forward_general(h.ptr, ctypes.byref(c), _prec(precision),
-                                     ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel())),
-          h.ptr)
+    if band is None and radius is None:
+        check(h.lib.fcfs_general_workspace_size(ctypes.byref(c), _prec(precision),
+                                                ctypes.byref(nb)))
+        ws = h.workspace(nb.value)
+        check(h.lib.fcfs_forward_general(h.ptr, ctypes.byref(c), _prec(precision),
+                                         ctypes.c_void_p(ws.data_ptr()),
+                                         ctypes.c_size_t(ws.numel())), h.ptr)
+    else:
+        kmax, lmax = (K, L) if band is None else (int(band[0]), int(band[1]))
+        rad = -1.0 if radius is None else float(radius)
+        check(h.lib.fcfs_general_band_workspace_size(ctypes.byref(c), kmax, lmax, rad,
+                                                     _prec(precision), ctypes.byref(nb)))
+        ws = h.workspace(nb.value)
+        check(h.lib.fcfs_forward_general_band(h.ptr, ctypes.byref(c), kmax, lmax, rad,
+                                              _prec(precision), ctypes.c_void_p(ws.data_ptr()),
+                                              ctypes.c_size_t(ws.numel())), h.ptr)
     return F, area
 
 
@@ -516,11 +529,9 @@ def _autograd_function():
         def forward(ctx, offsets, geom, precision="bf16", band=None, radius=None):
             x, y = geom.corners(offsets)
             if geom.general:
-                if band is not None or radius is not None:
-                    raise NotImplementedError("no low-pass forward for general tiles")
                 F, _ = forward_general(x, y, geom.s, geom.T, geom.Ny, geom.K, geom.L,
                                        frac_bits=geom.frac_bits, precision=precision,
-                                       handle=geom.handle)
+                                       handle=geom.handle, band=band, radius=radius)
             else:
                 F, _ = forward(x, y, geom.s, geom.T, geom.K, geom.L, precision=precision,
                                handle=geom.handle, band=band, radius=radius)
@@ -535,7 +546,7 @@ def _autograd_function():
             if g.general:
                 gx, gy = adjoint_general(x, y, g.s, g.T, g.Ny, g.K, g.L, grad_F.contiguous(),
                                          frac_bits=g.frac_bits, precision=ctx.precision,
-                                         handle=g.handle)
+                                         band=ctx.band, radius=ctx.radius, handle=g.handle)
             else:
                 gx, gy = adjoint(x, y, g.s, g.T, g.K, g.L, grad_F.contiguous(), ctx.precision,
                                  band=ctx.band, handle=g.handle, radius=ctx.radius)

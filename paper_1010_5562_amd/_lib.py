@@ -31,6 +31,7 @@ EXPORTS = (
     "fcfs_workspace_size", "fcfs_forward", "fcfs_band_workspace_size", "fcfs_forward_band",
     "fcfs_fft_workspace_size", "fcfs_forward_fft", "fcfs_haar_workspace_size", "fcfs_haar",
     "fcfs_general_workspace_size", "fcfs_forward_general",
+    "fcfs_general_band_workspace_size", "fcfs_forward_general_band",
     "fcfs_general_adjoint_workspace_size", "fcfs_adjoint_general", "fcfs_apply_edge_offsets_grid",
     "fcfs_pupil_loss_workspace_size", "fcfs_pupil_loss",
     "fcfs_adjoint", "fcfs_adjoint_band", "fcfs_edge_grad",
@@ -126,6 +127,10 @@ def load() -> ctypes.CDLL:
         "fcfs_haar_workspace_size": [ctypes.POINTER(FcfsHaarClip), sz],
         "fcfs_general_workspace_size": [ctypes.POINTER(FcfsGClip), c_int, sz],
         "fcfs_forward_general": [P, ctypes.POINTER(FcfsGClip), c_int, P, ctypes.c_size_t],
+        "fcfs_general_band_workspace_size": [ctypes.POINTER(FcfsGClip), i32, i32, ctypes.c_double,
+                                             c_int, sz],
+        "fcfs_forward_general_band": [P, ctypes.POINTER(FcfsGClip), i32, i32, ctypes.c_double,
+                                      c_int, P, ctypes.c_size_t],
         "fcfs_general_adjoint_workspace_size": [ctypes.POINTER(FcfsGClip), c_int, sz],
         "fcfs_adjoint_general": [P, ctypes.POINTER(FcfsGClip), P, i32, i32, ctypes.c_double, P, P,
                                  c_int, P, ctypes.c_size_t],

@@ -579,7 +579,10 @@ fcfs_status gen_tables(fcfs_handle *h, int Mx, int My, fcfs_handle::GenTab *tx,
   return FCFS_OK;
 }
 
-fcfs_status make_plan_general(fcfs_handle *h, const fcfs_gclip *c, int prec, FwdPlan *p) {
+// kmax, lmax, r2: the low-pass form (as make_band_plan for the square tile):
+// only |k| <= kmax, |l| <= lmax and k^2 + l^2 <= r2 (r2 >= 0) are computed.
+fcfs_status make_plan_general(fcfs_handle *h, const fcfs_gclip *c, int prec, FwdPlan *p,
+                              int kmax = -1, int lmax = -1, double r2 = -1.0) {
   if (!c) return fail(h, FCFS_ERR_INVALID_ARG, "clip is NULL");
   if (c->V < 0) return fail(h, FCFS_ERR_INVALID_ARG, "V < 0");
   if (c->V > ((int64_t)1 << 34)) return fail(h, FCFS_ERR_UNSUPPORTED, "V too large");
@@ -597,9 +600,11 @@ fcfs_status make_plan_general(fcfs_handle *h, const fcfs_gclip *c, int prec, Fwd
   q.T = (int)Mx;
   q.Mx = (int)Mx;
   q.My = (int)My;
-  q.K = q.KO = c->K;
-  q.L = q.LO = c->L;
-  q.r2 = -1.0;
+  q.KO = c->K;
+  q.LO = c->L;
+  q.K = kmax >= 0 ? std::min(kmax, c->K) : c->K;
+  q.L = lmax >= 0 ? std::min(lmax, c->L) : c->L;
+  q.r2 = r2;
   q.V = c->V;
   q.shift = 0;
   q.tile = -1;
@@ -612,13 +617,23 @@ fcfs_status make_plan_general(fcfs_handle *h, const fcfs_gclip *c, int prec, Fwd
   q.eay = sc * std::sqrt((double)My / (double)Mx);
   q.edc = sc / std::sqrt((double)Mx * (double)My);
   q.wgk = q.wgl = 128;
-  q.kp = (int)round_up(c->K + 1, 128);
-  q.lp = (int)round_up(c->L + 1, 128);
+  q.kp = (int)round_up(q.K + 1, 128);
+  q.lp = (int)round_up(q.L + 1, 128);
   q.tiles_k = q.kp / 128;
   q.tiles_l = q.lp / 128;
+  int64_t tiles = (int64_t)q.tiles_k * q.tiles_l;
+  if (r2 >= 0.0) {  // tiles the pupil reaches (same test as the kernel)
+    int64_t active = 0;
+    for (int tk = 0; tk < q.tiles_k; ++tk)
+      for (int tl = 0; tl < q.tiles_l; ++tl) {
+        const double k0 = (double)tk * 128, l0 = (double)tl * 128;
+        active += k0 * k0 + l0 * l0 <= r2;
+      }
+    tiles = std::max<int64_t>(1, active);
+  }
   // one workgroup of 8 waves per CU when both tables fill the LDS, else two
   const int wpc = (Mx + 1 + (Mx == My ? 0 : My)) * 8 <= 80 * 1024 ? 2 : 1;
-  finish_plan(q, (int64_t)q.tiles_k * q.tiles_l, wpc, 16, false);
+  finish_plan(q, tiles, wpc, 16, false);
   *p = q;
   return FCFS_OK;
 }
@@ -1064,6 +1079,37 @@ fcfs_status fcfs_forward_general(fcfs_handle *h, const fcfs_gclip *c, fcfs_preci
   if (st) return st;
   FwdPlan q;
   if ((st = make_plan_general(h, c, (int)p, &q))) return st;
+  if (c->V > 0 && (!c->x || !c->y || !c->s))
+    return fail(h, FCFS_ERR_INVALID_ARG, "corner arrays are NULL");
+  if (!c->F) return fail(h, FCFS_ERR_INVALID_ARG, "output F is NULL");
+  if ((st = check_ws(h, q, ws, ws_bytes))) return st;
+  return run_forward_general(h, c, q, ws);
+}
+
+fcfs_status fcfs_general_band_workspace_size(const fcfs_gclip *c, int32_t kmax, int32_t lmax,
+                                             double radius, fcfs_precision p, size_t *bytes) {
+  if (!bytes) return fail(nullptr, FCFS_ERR_INVALID_ARG, "NULL argument");
+  if (kmax < 0 || lmax < 0) return fail(nullptr, FCFS_ERR_INVALID_ARG, "band must be >= 0");
+  if (!(radius == radius)) return fail(nullptr, FCFS_ERR_INVALID_ARG, "radius is NaN");
+  FwdPlan q;
+  fcfs_status st = make_plan_general(nullptr, c, (int)p, &q, kmax, lmax,
+                                     radius >= 0.0 ? radius * radius : -1.0);
+  if (st) return st;
+  *bytes = q.bytes;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_forward_general_band(fcfs_handle *h, const fcfs_gclip *c, int32_t kmax,
+                                      int32_t lmax, double radius, fcfs_precision p, void *ws,
+                                      size_t ws_bytes) {
+  fcfs_status st = enter(h);
+  if (st) return st;
+  if (kmax < 0 || lmax < 0) return fail(h, FCFS_ERR_INVALID_ARG, "band must be >= 0");
+  if (!(radius == radius)) return fail(h, FCFS_ERR_INVALID_ARG, "radius is NaN");
+  FwdPlan q;
+  if ((st = make_plan_general(h, c, (int)p, &q, kmax, lmax,
+                              radius >= 0.0 ? radius * radius : -1.0)))
+    return st;
   if (c->V > 0 && (!c->x || !c->y || !c->s))
     return fail(h, FCFS_ERR_INVALID_ARG, "corner arrays are NULL");
   if (!c->F) return fail(h, FCFS_ERR_INVALID_ARG, "output F is NULL");

@@ -67,6 +67,15 @@ __device__ __forceinline__ f32x16 mfma16(const u32x4 &a, const u32x4 &b, const f
 }
 
 
+// A frequency tile whose corner nearest the origin lies outside the pupil
+// k^2 + l^2 <= r2 (r2 >= 0) holds only coefficients the epilogue writes as zero:
+// its workgroups return at once.
+__device__ __forceinline__ bool tile_outside(int tile, int tiles_l, int wgk, int wgl, double r2) {
+  if (r2 < 0.0) return false;
+  const double k0 = (double)(tile / tiles_l) * wgk, l0 = (double)(tile % tiles_l) * wgl;
+  return k0 * k0 + l0 * l0 > r2;
+}
+
 // ---------------------------------------------------------------------------
 // Contraction building blocks shared by the power-of-two and general-period
 // kernels: partial stores, corner loads, raw table entries, MFMA fragments.

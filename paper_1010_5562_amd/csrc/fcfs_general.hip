@@ -67,7 +67,9 @@ __device__ __forceinline__ void gen_gather(E (&a)[kGenNKB][8], E (&b)[kGenNLB][8
 template <int PREC>
 __global__ __launch_bounds__(64 * kGenWaves) void k_contract_gen(
     const uint4 *__restrict__ packed, const void *__restrict__ tabx, const void *__restrict__ taby,
-    int Mx, int My, int64_t chunk, int tiles_l, int kp, int lp, float *__restrict__ part) {
+    int Mx, int My, int64_t chunk, int tiles_l, int kp, int lp, float *__restrict__ part,
+    double r2) {
+  if (tile_outside(blockIdx.x, tiles_l, 128, 128, r2)) return;
   using E = typename std::conditional<PREC == kFP32, float2, uint2>::type;
   extern __shared__ uint2 lds[];
   E *tx = reinterpret_cast<E *>(lds);
@@ -149,7 +151,7 @@ hipError_t launch_gen_t(const FwdPlan &p, const uint4 *packed, const void *tx, c
   }
   hipLaunchKernelGGL(k_contract_gen<PREC>, dim3(p.tiles_k * p.tiles_l, p.nsplit),
                      dim3(64 * kGenWaves), lds, st, packed, tx, ty, p.Mx, p.My, p.chunk, p.tiles_l,
-                     p.kp, p.lp, part);
+                     p.kp, p.lp, part, p.r2);
   return hipGetLastError();
 }
 

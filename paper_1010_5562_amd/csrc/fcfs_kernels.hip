@@ -377,15 +377,6 @@ hipError_t launch_gen_side(const FwdPlan &p, const int32_t *x, const int32_t *y,
   return hipGetLastError();
 }
 
-// A frequency tile whose corner nearest the origin lies outside the pupil
-// k^2 + l^2 <= r2 (r2 >= 0) holds only coefficients the epilogue writes as zero:
-// its workgroups return at once.
-__device__ __forceinline__ bool tile_outside(int tile, int tiles_l, int wgk, int wgl, double r2) {
-  if (r2 < 0.0) return false;
-  const double k0 = (double)(tile / tiles_l) * wgk, l0 = (double)(tile % tiles_l) * wgl;
-  return k0 * k0 + l0 * l0 > r2;
-}
-
 // ---------------------------------------------------------------------------
 // Vertex contraction (Step 4) in real-trigonometric form:
 //   Z = X diag(s) Y^T,  X = [cos; sin](2 pi k x_v / T), Y likewise in l,

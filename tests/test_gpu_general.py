@@ -190,3 +190,62 @@ def test_general_autograd_fractional_offsets(P, oracle_lib, prec):
     e = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
     _say(f"general autograd {prec}: err/max|g| = {e:.3e}")
     assert e <= GTOL[prec]
+
+
+# ---------------------------------------------------------------- low-pass
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_general_band_forward(P, oracle_lib, prec):
+    # band |k| <= 60, |l| <= 40 and disc k^2 + l^2 <= 45^2 of a 1500 x 1100
+    # tile on half units (periods 3000 x 2200): the oracle's full grid inside,
+    # exact zeros outside; tiles of 128 x 128 frequencies beyond the disc skipped
+    Nx, Ny, F, K, L = 1500, 1100, 1, 300, 140
+    clip = synth.clip(56, 3000, K, L, n_polygons=80)
+    xy = clip.xy.astype(np.float64) / 2
+    ref, area = oracle_lib.cfs_grid_general(xy, clip.off, Nx, Ny, K, L, frac_bits=F)
+    kk, ll = np.meshgrid(np.arange(-K, K + 1), np.arange(-L, L + 1), indexing="ij")
+    keep = (np.abs(kk) <= 60) & (np.abs(ll) <= 40) & (kk ** 2 + ll ** 2 <= 45.0 ** 2)
+    x, y, s, _, _ = P.loops_to_corners(clip.xy, clip.off)
+    Fg, a = P.forward_general(x, y, s, Nx, Ny, K, L, frac_bits=F, precision=prec,
+                              band=(60, 40), radius=45.0)
+    torch.cuda.synchronize()
+    Fg = Fg.cpu().numpy().astype(np.complex128)
+    assert int(a.item()) == area
+    assert np.all(Fg[~keep] == 0)
+    e = float(np.max(np.abs(Fg[keep] - ref[keep])) / abs(ref[K, L]))
+    _say(f"general band {prec}: err/|F00| = {e:.3e}")
+    assert e <= TOL[prec]
+    with pytest.raises(P.FcfsError):
+        P.forward_general(x, y, s, Nx, Ny, K, L, frac_bits=F, band=(-1, 3))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_general_autograd_low_pass(P, oracle_lib, prec):
+    # loss sum |H F - G|^2 behind a pupil on a general tile through the
+    # low-pass forward and its adjoint; gradient against the oracle's
+    # analytic gradient with the cotangent 2 H (H F - G)
+    Nx, Ny, F, K = 700, 520, 1, 30
+    r = 0.35 * K
+    rb = int(np.floor(r))
+    clip = synth.clip(57, 1040, K, n_polygons=20)
+    geom = P.Geometry(clip.xy.astype(np.float64) / 2, clip.off, Nx, K, Ny=Ny, frac_bits=F)
+    kk, ll = np.meshgrid(np.arange(-K, K + 1), np.arange(-K, K + 1), indexing="ij")
+    H = (kk ** 2 + ll ** 2 <= r * r).astype(np.float64)
+    rng = np.random.default_rng(11)
+    G = H * (rng.normal(size=H.shape) + 1j * rng.normal(size=H.shape))
+    Gd = torch.as_tensor(G.astype(np.complex64)).cuda()
+    off = torch.zeros(geom.n_edges, dtype=torch.float32, device="cuda", requires_grad=True)
+    Fv = P.FCFSFunction.apply(off, geom, prec, (rb, rb), r)
+    loss = P.PupilLoss.apply(Fv, Gd, r)
+    loss.backward()
+    torch.cuda.synchronize()
+    xy = clip.xy.astype(np.float64) / 2
+    Fo, _ = oracle_lib.cfs_grid_general(xy, clip.off, Nx, Ny, K, K, frac_bits=F)
+    Fh = Fv.detach().cpu().numpy().astype(np.complex128)
+    assert np.all(Fh[H == 0] == 0)
+    assert float(np.max(np.abs(Fh - H * Fo)) / abs(Fo[K, K])) <= TOL[prec]
+    cot = 2 * H * (H * Fo - G.astype(np.complex64).astype(np.complex128))
+    want = oracle_lib.edge_grad_general(xy, clip.off, Nx, Ny, K, K, cot, frac_bits=F)
+    got = off.grad.cpu().numpy().astype(np.float64)
+    e = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+    _say(f"general autograd low-pass {prec}: err/max|g| = {e:.3e}")
+    assert e <= GTOL[prec]
