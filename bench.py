@@ -89,6 +89,22 @@ def timed(fn, steps: int, warmup: int, handle, kinds=("contract",)):
     return (t_b - t_a) * 1e3 / steps, prof
 
 
+def host_cpu():
+    """Model name and logical CPU count of the host (from /proc/cpuinfo)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(),
+            "usable_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+            else None}
+
+
 def step_stats(fn, n: int):
     """Per-step device time of n further steps, each bracketed by events on
     the current stream (every kernel of a step, side stream included, ends
@@ -229,6 +245,13 @@ def main() -> int:
             t_pts += time.perf_counter() - tc
             kk, ll = np.concatenate([kk, rk]), np.concatenate([ll, rl])
             ref = np.concatenate([ref, ref2])
+        # the same oracle on one thread, on the |k|,|l| <= 4 block
+        lo1 = np.array([(k, l) for k in range(-4, 5) for l in range(-4, 5)])
+        oracle.threads(1)
+        tc = time.perf_counter()
+        oracle.cfs_points(clip.xy, clip.off, T, lo1[:, 0], lo1[:, 1])
+        t_one = time.perf_counter() - tc
+        oracle.threads(cores)
         cpu = {
             "value": V * kk.size / t_pts,
             "unit": "pairs/s",
@@ -237,6 +260,9 @@ def main() -> int:
             "sample": (f"same clip, {kk.size} coefficients (the |k|,|l|<=8 block plus uniform "
                        f"random (k,l)), {t_pts:.1f} s of FP64 edge-form evaluation on {cores} "
                        "host threads"),
+            "single_thread_value": V * lo1.shape[0] / t_one,
+            "single_thread_sample": f"same clip, the {lo1.shape[0]} coefficients |k|,|l|<=4",
+            "host": host_cpu(),
         }
     f00 = abs(oracle.cfs_points(clip.xy, clip.off, T, [0], [0])[0])
     errs = {}
