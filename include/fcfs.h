@@ -177,7 +177,10 @@ typedef struct {
 fcfs_status fcfs_general_workspace_size(const fcfs_gclip *c, fcfs_precision p, size_t *bytes);
 /* Forward transform of a general tile: pre-pass (residues, area), axis sums
  * and FP64 low-frequency block on the side stream, MFMA contraction with
- * exact phases (f x) mod M, epilogue with the alpha factors above. */
+ * exact phases (f x) mod M, epilogue with the alpha factors above.  The split
+ * precisions run a software-pipelined contraction kernel (one wave per SIMD);
+ * FP32, or a handle with a tile variant forced by fcfs_set_tile, an eight-wave
+ * kernel.  The workspace size covers either. */
 fcfs_status fcfs_forward_general(fcfs_handle *h, const fcfs_gclip *c, fcfs_precision p, void *ws,
                                  size_t ws_bytes);
 /* Low-pass form of fcfs_forward_general (the pupil of the lithography use in

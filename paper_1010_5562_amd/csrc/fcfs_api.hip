@@ -581,8 +581,11 @@ fcfs_status gen_tables(fcfs_handle *h, int Mx, int My, fcfs_handle::GenTab *tx,
 
 // kmax, lmax, r2: the low-pass form (as make_band_plan for the square tile):
 // only |k| <= kmax, |l| <= lmax and k^2 + l^2 <= r2 (r2 >= 0) are computed.
+// variant: -1 the handle's choice (the pipelined kernel for the split
+// precisions unless a tile variant is forced on the handle), else the
+// contraction kernel given as in FwdPlan::tile.
 fcfs_status make_plan_general(fcfs_handle *h, const fcfs_gclip *c, int prec, FwdPlan *p,
-                              int kmax = -1, int lmax = -1, double r2 = -1.0) {
+                              int kmax = -1, int lmax = -1, double r2 = -1.0, int variant = -1) {
   if (!c) return fail(h, FCFS_ERR_INVALID_ARG, "clip is NULL");
   if (c->V < 0) return fail(h, FCFS_ERR_INVALID_ARG, "V < 0");
   if (c->V > ((int64_t)1 << 34)) return fail(h, FCFS_ERR_UNSUPPORTED, "V too large");
@@ -607,7 +610,9 @@ fcfs_status make_plan_general(fcfs_handle *h, const fcfs_gclip *c, int prec, Fwd
   q.r2 = r2;
   q.V = c->V;
   q.shift = 0;
-  q.tile = -1;
+  if (variant < 0)
+    variant = prec != fcfs::kFP32 && !(h && h->tile_override >= 0) ? fcfs::kGenPipeTile : 0;
+  q.tile = prec != fcfs::kFP32 && variant == fcfs::kGenPipeTile ? fcfs::kGenPipeTile : 0;
   // alpha of Prop. 3 for the tile Nx x Ny, with sums taken in grid units
   // (coordinates 2^F times the true ones, periods Mx, My): 2^-F sqrt(Mx My)
   // = sqrt(Nx Ny) and so on
@@ -631,10 +636,27 @@ fcfs_status make_plan_general(fcfs_handle *h, const fcfs_gclip *c, int prec, Fwd
       }
     tiles = std::max<int64_t>(1, active);
   }
-  // one workgroup of 8 waves per CU when both tables fill the LDS, else two
-  const int wpc = (Mx + 1 + (Mx == My ? 0 : My)) * 8 <= 80 * 1024 ? 2 : 1;
-  finish_plan(q, tiles, wpc, 16, false);
+  // eight-wave kernel: one workgroup per CU when both tables fill the LDS,
+  // else two; pipelined kernel: one workgroup of four waves per CU
+  const bool pipe = q.tile == fcfs::kGenPipeTile;
+  const int wpc = !pipe && (Mx + 1 + (Mx == My ? 0 : My)) * 8 <= 80 * 1024 ? 2 : 1;
+  finish_plan(q, tiles, wpc, pipe ? 32 : 16, false);
   *p = q;
+  return FCFS_OK;
+}
+
+// Workspace of a general-tile forward: the larger of the two kernels'
+// layouts, so that the size does not depend on the handle's choice.
+fcfs_status general_ws_bytes(const fcfs_gclip *c, int prec, int kmax, int lmax, double r2,
+                             size_t *bytes) {
+  size_t b = 0;
+  for (int variant : {0, fcfs::kGenPipeTile}) {
+    FwdPlan q;
+    fcfs_status st = make_plan_general(nullptr, c, prec, &q, kmax, lmax, r2, variant);
+    if (st) return st;
+    b = std::max(b, q.bytes);
+  }
+  *bytes = b;
   return FCFS_OK;
 }
 
@@ -1066,11 +1088,7 @@ fcfs_status fcfs_haar(fcfs_handle *h, const fcfs_haar_clip *c, void *ws, size_t 
 
 fcfs_status fcfs_general_workspace_size(const fcfs_gclip *c, fcfs_precision p, size_t *bytes) {
   if (!bytes) return fail(nullptr, FCFS_ERR_INVALID_ARG, "NULL argument");
-  FwdPlan q;
-  fcfs_status st = make_plan_general(nullptr, c, (int)p, &q);
-  if (st) return st;
-  *bytes = q.bytes;
-  return FCFS_OK;
+  return general_ws_bytes(c, (int)p, -1, -1, -1.0, bytes);
 }
 
 fcfs_status fcfs_forward_general(fcfs_handle *h, const fcfs_gclip *c, fcfs_precision p, void *ws,
@@ -1091,12 +1109,7 @@ fcfs_status fcfs_general_band_workspace_size(const fcfs_gclip *c, int32_t kmax, 
   if (!bytes) return fail(nullptr, FCFS_ERR_INVALID_ARG, "NULL argument");
   if (kmax < 0 || lmax < 0) return fail(nullptr, FCFS_ERR_INVALID_ARG, "band must be >= 0");
   if (!(radius == radius)) return fail(nullptr, FCFS_ERR_INVALID_ARG, "radius is NaN");
-  FwdPlan q;
-  fcfs_status st = make_plan_general(nullptr, c, (int)p, &q, kmax, lmax,
-                                     radius >= 0.0 ? radius * radius : -1.0);
-  if (st) return st;
-  *bytes = q.bytes;
-  return FCFS_OK;
+  return general_ws_bytes(c, (int)p, kmax, lmax, radius >= 0.0 ? radius * radius : -1.0, bytes);
 }
 
 fcfs_status fcfs_forward_general_band(fcfs_handle *h, const fcfs_gclip *c, int32_t kmax,

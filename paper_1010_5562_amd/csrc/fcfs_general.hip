@@ -12,11 +12,14 @@
 // exact because x M < 2^32 (the error term x (m - f' 2^32 / M) / 2^32 is below
 // x / 2^32 < 1 / M).  The sign s_v flips the sign bits of the y-side entry
 // (record field z) and padding records send the x-side lookup to the zero
-// entry (record field w = Mx).
+// entry (record field w = 8 Mx, added before the clamp to Mx).
 //
-// Workgroup: 8 waves (2 in k x 4 in l), each 64 k x 32 l, so a 128 x 128
-// frequency tile; one or two workgroups per CU depending on the table sizes
-// (at most (8193 + 8192) 8-byte entries of LDS), i.e. two waves per SIMD or more.
+// Two kernels.  Eight-wave form (FP32, and the split precisions on request):
+// 8 waves (2 in k x 4 in l), each 64 k x 32 l, so a 128 x 128 frequency tile;
+// one or two workgroups per CU depending on the table sizes (at most
+// (8193 + 8192) 8-byte entries of LDS), i.e. two waves per SIMD or more.
+// Pipelined form (the split precisions): 4 waves of 64 x 64, one per SIMD,
+// software-pipelined as the power-of-two production kernel.
 #include "fcfs_device.h"
 
 namespace fcfs {
@@ -34,9 +37,26 @@ __device__ __forceinline__ uint32_t gen_phase(uint32_t fr, uint32_t m, uint32_t 
   return __umul24(fr, x) - __umul24(__umulhi(x, m), M);
 }
 
+template <int NKB, int NLB>
 struct GenLane {
-  uint32_t kr[kGenNKB], km[kGenNKB], lr[kGenNLB], lm[kGenNLB];
+  uint32_t kr[NKB], km[NKB], lr[NLB], lm[NLB];
 };
+
+// Phase constants of the lane's frequencies k0 + 32 kb + li and l0 + 32 lb + li.
+template <int NKB, int NLB>
+__device__ __forceinline__ void gen_lane(GenLane<NKB, NLB> &g, int k0, int l0, int li,
+                                         uint32_t ux, uint32_t uy) {
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb) {
+    g.kr[kb] = (uint32_t)(k0 + 32 * kb + li) % ux;
+    g.km[kb] = gen_magic(g.kr[kb], ux);
+  }
+#pragma unroll
+  for (int lb = 0; lb < NLB; ++lb) {
+    g.lr[lb] = (uint32_t)(l0 + 32 * lb + li) % uy;
+    g.lm[lb] = gen_magic(g.lr[lb], uy);
+  }
+}
 
 // Entries of one 16-corner step: a[kb][j] = Wx[(k x_j) mod Mx] (zero for
 // padding), b[lb][j] = s_j Wy[(l y_j) mod My].
@@ -48,17 +68,17 @@ __device__ __forceinline__ E flip(E e, uint32_t m) {
   return __builtin_bit_cast(E, u);
 }
 
-template <typename E>
-__device__ __forceinline__ void gen_gather(E (&a)[kGenNKB][8], E (&b)[kGenNLB][8], const E *tx,
-                                           const E *ty, const uint4 (&c)[8], const GenLane &g,
-                                           uint32_t Mx, uint32_t My) {
+template <typename E, int NKB, int NLB>
+__device__ __forceinline__ void gen_gather(E (&a)[NKB][8], E (&b)[NLB][8], const E *tx,
+                                           const E *ty, const uint4 (&c)[8],
+                                           const GenLane<NKB, NLB> &g, uint32_t Mx, uint32_t My) {
 #pragma unroll
-  for (int kb = 0; kb < kGenNKB; ++kb)
+  for (int kb = 0; kb < NKB; ++kb)
 #pragma unroll
     for (int j = 0; j < 8; ++j)
       a[kb][j] = tx[min(gen_phase(g.kr[kb], g.km[kb], c[j].x, Mx) + c[j].w, Mx)];
 #pragma unroll
-  for (int lb = 0; lb < kGenNLB; ++lb)
+  for (int lb = 0; lb < NLB; ++lb)
 #pragma unroll
     for (int j = 0; j < 8; ++j) b[lb][j] = flip(ty[gen_phase(g.lr[lb], g.lm[lb], c[j].y, My)], c[j].z);
 }
@@ -86,17 +106,8 @@ __global__ __launch_bounds__(64 * kGenWaves) void k_contract_gen(
   const int k0 = tk * 128 + (wave >> 2) * 64;
   const int l0 = tl * 128 + (wave & 3) * 32;
   const uint32_t ux = (uint32_t)Mx, uy = (uint32_t)My;
-  GenLane g;
-#pragma unroll
-  for (int kb = 0; kb < kGenNKB; ++kb) {
-    g.kr[kb] = (uint32_t)(k0 + 32 * kb + li) % ux;
-    g.km[kb] = gen_magic(g.kr[kb], ux);
-  }
-#pragma unroll
-  for (int lb = 0; lb < kGenNLB; ++lb) {
-    g.lr[lb] = (uint32_t)(l0 + 32 * lb + li) % uy;
-    g.lm[lb] = gen_magic(g.lr[lb], uy);
-  }
+  GenLane<kGenNKB, kGenNLB> g;
+  gen_lane(g, k0, l0, li, ux, uy);
 
   f32x16 acc[kGenNKB][kGenNLB][4];
 #pragma unroll
@@ -137,6 +148,127 @@ __global__ __launch_bounds__(64 * kGenWaves) void k_contract_gen(
   store_part<kGenNKB, kGenNLB>(part, acc, split, kp, lp, k0, l0, li, lh);
 }
 
+// Byte offset base + 8 ((f x) mod M) of the table entry, from the lane
+// constants fr8 = 8 (f mod M), m = gen_magic(f mod M, M) and M8 = 8 M: the
+// quotient is that of gen_phase, and both 24-bit products stay below 2^29.
+__device__ __forceinline__ uint32_t gen_phase8(uint32_t fr8, uint32_t m, uint32_t x, uint32_t M8,
+                                               uint32_t base) {
+  return (__umul24(fr8, x) + base) - __umul24(__umulhi(x, m), M8);
+}
+
+// gen_gather for the pipelined kernel, with LDS byte addresses: the x table at
+// byte 0 (padding records, w = 8 Mx, land on its zero entry at byte 8 Mx), the
+// y table at byte ybase.
+__device__ __forceinline__ void gen_gather8(Raw<2, 2> &r, const uint2 *lds,
+                                            const uint4 (&c)[8], const uint32_t (&kr8)[2],
+                                            const uint32_t (&km)[2], const uint32_t (&lr8)[2],
+                                            const uint32_t (&lm)[2], uint32_t Mx8, uint32_t My8,
+                                            uint32_t ybase) {
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      r.a[kb][j] = lds_entry(lds, min(gen_phase8(kr8[kb], km[kb], c[j].x, Mx8, c[j].w), Mx8));
+#pragma unroll
+  for (int lb = 0; lb < 2; ++lb)
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      r.b[lb][j] = flip(lds_entry(lds, gen_phase8(lr8[lb], lm[lb], c[j].y, My8, ybase)), c[j].z);
+}
+
+// Software-pipelined split form for one wave per SIMD, as the power-of-two
+// production kernel: 4 waves of 64 x 64 frequencies (128 x 128 per
+// workgroup), the 48 MFMAs of step s interleaved with the lookups and packing
+// of step s+1 and the corner loads of step s+2.  chunk is a multiple of 32.
+__device__ __forceinline__ void gen_pipe_schedule() {
+  constexpr int NM = 48;                 // MFMAs per step
+  constexpr int ND = 32;                 // LDS lookups per step
+  constexpr int NV = 16 * 5 + 16 * 6 + 64;  // phases, clamps, sign flips, packing
+#pragma unroll
+  for (int i = 0; i < NM; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                   // MFMA
+    if (i % 6 == 0) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // corner load
+    if (i < ND / 2) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);   // LDS lookups
+    __builtin_amdgcn_sched_group_barrier(0x002, (NV + NM - 1) / NM, 0);  // VALU
+  }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256, 1) void k_contract_gen_pipe(
+    const uint4 *__restrict__ packed, const uint2 *__restrict__ tabx,
+    const uint2 *__restrict__ taby, int Mx, int My, int64_t chunk, int tiles_l, int kp, int lp,
+    float *__restrict__ part, double r2) {
+  if (tile_outside(blockIdx.x, tiles_l, 128, 128, r2)) return;
+  // a static array (at LDS address 0, so the lookups need no base add) large
+  // enough for both tables
+  __shared__ uint2 lds[2 * kTabN + 1];
+  uint2 *tx = lds;
+  uint2 *ty = tabx == taby ? tx : tx + (Mx + 1);
+  for (int i = threadIdx.x; i <= Mx; i += 256) tx[i] = tabx[i];
+  if (tabx != taby)
+    for (int i = threadIdx.x; i < My; i += 256) ty[i] = taby[i];
+  __syncthreads();
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 31, lh = lane >> 5;
+  const int tk = blockIdx.x / tiles_l, tl = blockIdx.x % tiles_l;
+  const int split = blockIdx.y;
+  const int k0 = tk * 128 + (wave >> 1) * 64;
+  const int l0 = tl * 128 + (wave & 1) * 64;
+  const uint32_t ux = (uint32_t)Mx, uy = (uint32_t)My;
+  GenLane<2, 2> g;
+  gen_lane(g, k0, l0, li, ux, uy);
+  const uint32_t kr8[2] = {g.kr[0] << 3, g.kr[1] << 3}, lr8[2] = {g.lr[0] << 3, g.lr[1] << 3};
+  const uint32_t Mx8 = ux << 3, My8 = uy << 3;
+  const uint32_t ybase = tabx == taby ? 0u : Mx8 + 8u;
+
+  f32x16 acc[2][2][4];
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+    for (int lb = 0; lb < 2; ++lb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[kb][lb][q][r] = 0.0f;
+
+  const uint4 *vp = packed + (size_t)split * chunk + 8 * lh;
+  const int nsteps = (int)(chunk >> 4);  // even
+  const int last = nsteps - 1;
+  uint4 c0[8], c1[8];
+  Raw<2, 2> raw;
+  Frag<2, 2> fa, fb;
+  load_corners(c0, vp);
+  gen_gather8(raw, lds, c0, kr8, g.km, lr8, g.lm, Mx8, My8, ybase);
+  build(fa, raw);
+  load_corners(c1, vp + 16);
+  for (int s = 0; s < nsteps; s += 2) {
+    // fa: operands of step s; c1: corners of step s+1
+    load_corners(c0, vp + 16 * min(s + 2, last));
+    gen_gather8(raw, lds, c1, kr8, g.km, lr8, g.lm, Mx8, My8, ybase);
+    build(fb, raw);
+    mma<PREC>(acc, fa);
+    gen_pipe_schedule();
+    // fb: operands of step s+1; c0: corners of step s+2 (the last iteration
+    // prepares a step that is never multiplied)
+    load_corners(c1, vp + 16 * min(s + 3, last));
+    gen_gather8(raw, lds, c0, kr8, g.km, lr8, g.lm, Mx8, My8, ybase);
+    build(fa, raw);
+    mma<PREC>(acc, fb);
+    gen_pipe_schedule();
+  }
+  store_part<2, 2>(part, acc, split, kp, lp, k0, l0, li, lh);
+}
+
+template <int PREC>
+hipError_t launch_gen_pipe_t(const FwdPlan &p, const uint4 *packed, const void *tx,
+                             const void *ty, float *part, hipStream_t st) {
+  hipLaunchKernelGGL(k_contract_gen_pipe<PREC>, dim3(p.tiles_k * p.tiles_l, p.nsplit), dim3(256),
+                     0, st, packed, (const uint2 *)tx, (const uint2 *)ty, p.Mx, p.My, p.chunk,
+                     p.tiles_l, p.kp, p.lp, part, p.r2);
+  return hipGetLastError();
+}
+
 template <int PREC>
 hipError_t launch_gen_t(const FwdPlan &p, const uint4 *packed, const void *tx, const void *ty,
                         float *part, hipStream_t st) {
@@ -159,6 +291,11 @@ hipError_t launch_gen_t(const FwdPlan &p, const uint4 *packed, const void *tx, c
 
 hipError_t launch_gen_contract(const FwdPlan &p, const uint4 *packed, const void *tx,
                                const void *ty, float *part, hipStream_t st) {
+  if (p.tile == kGenPipeTile) {
+    if (p.chunk % 32) return hipErrorInvalidValue;
+    return p.prec == kBF16 ? launch_gen_pipe_t<kBF16>(p, packed, tx, ty, part, st)
+                           : launch_gen_pipe_t<kFP16>(p, packed, tx, ty, part, st);
+  }
   switch (p.prec) {
     case kFP32: return launch_gen_t<kFP32>(p, packed, tx, ty, part, st);
     case kBF16: return launch_gen_t<kBF16>(p, packed, tx, ty, part, st);

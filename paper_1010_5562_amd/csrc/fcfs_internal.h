@@ -108,6 +108,10 @@ hipError_t launch_gen_prepass_records(const int32_t *x, const int32_t *y, const 
                                       hipStream_t st);
 hipError_t launch_gen_side(const FwdPlan &p, const int32_t *x, const int32_t *y,
                            const double2 *wx, const double2 *wy, void *ws, hipStream_t st);
+// FwdPlan::tile of a general-tile plan: kGenPipeTile selects the pipelined
+// split kernel (one wave per SIMD, chunk a multiple of 32), any other value
+// the eight-wave kernel.
+constexpr int kGenPipeTile = 1;
 hipError_t launch_gen_contract(const FwdPlan &p, const uint4 *packed, const void *tx,
                                const void *ty, float *part, hipStream_t st);
 hipError_t launch_fft(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,

@@ -81,8 +81,9 @@ hipError_t launch_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y, 
 // units of the grid): records {x mod Mx, y mod My, sign mask, pad}.  The sign
 // mask flips the sign bits of a y-side table entry (smask = 0x80008000 for the
 // packed 16-bit split entries, 0x80000000 for FP32 pairs); padding records
-// carry pad = Mx, which sends the x-side lookup to the zero entry Mx.  Bins
-// of the axis histograms are the residues themselves.
+// carry pad = 8 Mx, which sends the x-side lookup (an entry index or a byte
+// offset, clamped to the zero entry) to the zero entry Mx.  Bins of the axis
+// histograms are the residues themselves.
 __global__ __launch_bounds__(256) void k_gen_prepass(const int32_t *__restrict__ x,
                                                      const int32_t *__restrict__ y,
                                                      const int8_t *__restrict__ s, int64_t V,
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(256) void k_gen_prepass(const int32_t *__restrict__
       w.w = 0u;
       acc += (unsigned long long)((long long)sv * (long long)xv * (long long)yv);
     } else {
-      w = make_uint4(0u, 0u, 0u, (uint32_t)Mx);
+      w = make_uint4(0u, 0u, 0u, 8u * (uint32_t)Mx);
     }
     packed[i] = w;
   }

@@ -249,3 +249,39 @@ def test_general_autograd_low_pass(P, oracle_lib, prec):
     e = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
     _say(f"general autograd low-pass {prec}: err/max|g| = {e:.3e}")
     assert e <= GTOL[prec]
+
+
+@pytest.mark.parametrize("Nx,Ny,F,K,L,npol,seed", [
+    (3000, 2000, 0, 300, 200, 400, 61),   # several 128 x 128 tiles, ragged in both
+    (8192, 8000, 0, 64, 64, 300, 62),     # both tables at their largest
+    (1000, 1000, 1, 100, 100, 300, 63),   # one shared table
+])
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_general_pipelined_and_eight_wave_kernels(P, oracle_lib, Nx, Ny, F, K, L, npol, seed,
+                                                  prec):
+    # the split precisions run the pipelined kernel; a tile variant forced on
+    # the handle selects the eight-wave kernel: both against the oracle
+    Mx, My = Nx << F, Ny << F
+    clip = synth.clip(seed, min(Mx, My), K, L, n_polygons=npol)
+    xy = clip.xy.astype(np.float64) / 2 ** F
+    rng = np.random.default_rng(seed)
+    lo = np.array([(k, l) for k in range(-8, 9) for l in range(-8, 9)])
+    kk = np.concatenate([lo[:, 0], rng.integers(-K, K + 1, 300)])
+    ll = np.concatenate([lo[:, 1], rng.integers(-L, L + 1, 300)])
+    ref = oracle_lib.cfs_points_general(xy, clip.off, Nx, Ny, kk, ll, frac_bits=F)
+    f00 = abs(oracle_lib.cfs_points_general(xy, clip.off, Nx, Ny, [0], [0], frac_bits=F)[0])
+    h = P.default_handle()
+    out = {}
+    for forced in (False, True):
+        if forced:
+            h.set_tile(0)
+        try:
+            out[forced] = _gpu(P, clip.xy, clip.off, Nx, Ny, K, L, F, prec)
+        finally:
+            h.set_tile(-1)
+        Fg, _ = out[forced]
+        e = float(np.max(np.abs(Fg[kk + K, ll + L] - ref)) / f00)
+        _say(f"general {Nx}x{Ny} {prec} {'eight-wave' if forced else 'pipelined'}: "
+             f"err/|F00| = {e:.3e}")
+        assert e <= TOL[prec]
+    assert out[False][1] == out[True][1]
