@@ -118,6 +118,26 @@ def test_workspace_sizes():
     assert ei.value.status == -1
 
 
+def test_general_workspace_sizes(lib):
+    # the low-pass form needs less than the full grid; invalid bands, radii
+    # and periods are rejected before any device work
+    from paper_1010_5562_amd import _lib
+
+    c = _lib.FcfsGClip(None, None, None, 200000, 8000, 6000, 0, 511, 511, None, None)
+    full, band = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    for prec in (0, 1, 2):
+        assert lib.fcfs_general_workspace_size(ctypes.byref(c), prec, ctypes.byref(full)) == 0
+        assert lib.fcfs_general_band_workspace_size(ctypes.byref(c), 100, 100, 90.0, prec,
+                                                    ctypes.byref(band)) == 0
+        assert 0 < band.value < full.value < 1 << 32
+    assert lib.fcfs_general_band_workspace_size(ctypes.byref(c), -1, 3, -1.0, 1,
+                                                ctypes.byref(band)) == -1
+    assert lib.fcfs_general_band_workspace_size(ctypes.byref(c), 3, 3, float("nan"), 1,
+                                                ctypes.byref(band)) == -1
+    c.Nx = 9000
+    assert lib.fcfs_general_workspace_size(ctypes.byref(c), 1, ctypes.byref(full)) == -4
+
+
 def test_null_handle_is_rejected(lib):
     from paper_1010_5562_amd import _lib
 
