@@ -608,7 +608,7 @@ def main() -> int:
         px, py, ps, _, _ = P.loops_to_corners(c.xy, c.off)
         pargs.append((px, py, ps, Tp, Kp, Kp))
         ppairs += int(px.size) * (2 * Kp + 1) ** 2
-    pb = P.Batch(pargs, precision="bf16")
+    pb = P.Batch(pargs, precision="bf16", tune=True)  # the autotuner picks for these tiles
     msp, _ = timed(pb.run, max(3, args.steps // 4), 1, h, kinds=None)
     ep = 0.0
     for i in (0, 1):
@@ -623,10 +623,12 @@ def main() -> int:
         "value": ppairs / (msp * 1e-3), "unit": "pairs/s",
         "output_GBps": ntp * (2 * Kp + 1) ** 2 * 8 / (msp * 1e-3) / 1e9,
         "err_rel_f00_full_grid_2_tiles": ep,
+        "autotune": {"tile_variant": pb.choice[0], "corners_per_item": pb.choice[1]},
         "paper_cpu_us_per_tile": 15648.0,
     }
     log(f"paper-shaped tiles: {msp * 1e3 / ntp:.2f} us per tile "
-        f"({forms['paper_shaped_tiles']['output_GBps']:.0f} GB/s of output), err {ep:.2e}")
+        f"({forms['paper_shaped_tiles']['output_GBps']:.0f} GB/s of output), err {ep:.2e}, "
+        f"choice {pb.choice}")
     pb.close()
     del pb
 

@@ -1409,7 +1409,9 @@ fcfs_status batch_layout(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec
       for (int t = 0; t < tiles; ++t)
         for (int sp = 0; sp < b.nsplit; ++sp)
           items.push_back({b.chunk * (int64_t)wgk * wgl, make_int4(i, t, sp, 0)});
-    L->epi_off[i + 1] = L->epi_off[i] + fcfs::epilogue_block_count(ci.K, ci.L);
+    // one split: the contraction writes F itself (kernels with two waves per SIMD)
+    b.direct = b.nsplit == 1 && ci.K > 0 && ci.L > 0 && tv.pipe != 2 ? 1 : 0;
+    L->epi_off[i + 1] = L->epi_off[i] + fcfs::epilogue_block_count(ci.K, ci.L, b.direct != 0);
     L->off_packed[i] = off;
     off += align256(sizeof(uint4) * (size_t)b.vpad);
     L->off_area[i] = off;
@@ -1419,7 +1421,7 @@ fcfs_status batch_layout(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec
     L->off_axis[i] = off;
     off += align256(sizeof(double2) * (size_t)b.ax_chunks * (size_t)std::max(1, ci.K + ci.L));
     L->off_part[i] = off;
-    off += align256(sizeof(float) * 4 * (size_t)b.nsplit * (size_t)b.kp * (size_t)b.lp);
+    if (!b.direct) off += align256(sizeof(float) * 4 * (size_t)b.nsplit * (size_t)b.kp * (size_t)b.lp);
     L->off_guard[i] = off;
     off += align256(sizeof(double) * fcfs::kGuardD * (size_t)b.g_chunks);
     L->off_gfinal[i] = off;
@@ -1493,7 +1495,7 @@ fcfs_status build_plan(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec, 
     b.packed = ws_at<uint4>(ws, L.off_packed[i]);
     b.area_part = ws_at<unsigned long long>(ws, L.off_area[i]);
     b.axis_part = ws_at<double2>(ws, L.off_axis[i]);
-    b.part = ws_at<float>(ws, L.off_part[i]);
+    b.part = b.direct ? nullptr : ws_at<float>(ws, L.off_part[i]);  // direct: no partials
     b.gpart = ws_at<double>(ws, L.off_guard[i]);
     b.gfinal = ws_at<double>(ws, L.off_gfinal[i]);
     b.gcount = ws_at<unsigned int>(ws, L.off_gcount[i]);

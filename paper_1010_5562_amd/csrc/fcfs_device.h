@@ -66,6 +66,37 @@ __device__ __forceinline__ f32x16 mfma16(const u32x4 &a, const u32x4 &b, const f
                                                   __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
 }
 
+// Output grid of one clip: F holds (2 KO + 1) x (2 LO + 1) coefficients,
+// k-major, index (KO + k)(2 LO + 1) + (LO + l).  It may be larger than the
+// computed band |k| <= K, |l| <= L (the rest is cleared beforehand); with
+// r2 >= 0 the entries with k^2 + l^2 > r2 are written as zero (a pupil).
+// The factors of alpha_{k,l} (Prop. 3) come with the grid: alpha_{k,l} =
+// -g / (4 pi^2 k l), alpha_{k,0} = j ax / (2 pi k), alpha_{0,l} = j ay / (2 pi l),
+// F[0,0] = dc * area.  A square tile of period T has g = T, ax = ay = 1,
+// dc = 1 / T; a general one carries the sqrt(Nx/Ny)-type factors.
+struct OutGrid {
+  float2 *F;
+  int KO, LO;
+  double r2;
+  double g, ax, ay, dc;
+};
+
+__device__ __forceinline__ void put(const OutGrid &o, int k, int l, float re, float im) {
+  if (o.r2 >= 0.0 && (double)k * k + (double)l * l > o.r2) re = im = 0.0f;
+  o.F[(size_t)(o.KO + k) * (2 * (size_t)o.LO + 1) + (o.LO + l)] = make_float2(re, im);
+}
+
+__device__ __forceinline__ void store_quad(const OutGrid &o, int k, int l, double T, double P,
+                                           double U, double R, double Q) {
+  (void)T;
+  const double a = -o.g / (4.0 * kPi * kPi * (double)k * (double)l);
+  const double pre = a * (P - Q), pim = -a * (R + U);  // F[k, l]
+  const double mre = -a * (P + Q), mim = a * (R - U);  // F[k, -l]
+  put(o, k, l, (float)pre, (float)pim);
+  put(o, -k, -l, (float)pre, (float)-pim);
+  put(o, k, -l, (float)mre, (float)mim);
+  put(o, -k, l, (float)mre, (float)-mim);
+}
 
 // A frequency tile whose corner nearest the origin lies outside the pupil
 // k^2 + l^2 <= r2 (r2 >= 0) holds only coefficients the epilogue writes as zero:

@@ -183,6 +183,7 @@ struct BatchClip {
   int64_t V, vpad, chunk, g_chunk;
   int T, shift, K, L, kp, lp, tiles_l, nsplit;
   int ax_fb_k, ax_chunks, g_chunks, hist_blocks;
+  int direct;  // one split: the contraction writes F itself (no partials)
 };
 
 struct BatchLaunch {
@@ -208,7 +209,7 @@ hipError_t launch_batch_contract(const BatchLaunch &b, const Tables &t, hipStrea
 hipError_t launch_batch_epilogue(const BatchLaunch &b, hipStream_t st);
 int batch_grid(int tile, int prec);
 // blocks of the epilogue launch of one clip
-int epilogue_block_count(int K, int L);
+int epilogue_block_count(int K, int L, bool direct = false);
 
 // Contraction tile variants (wave tile in k x l frequencies; 2 x 2 waves).
 struct TileVariant {

@@ -379,6 +379,46 @@ hipError_t launch_gen_side(const FwdPlan &p, const int32_t *x, const int32_t *y,
 }
 
 // ---------------------------------------------------------------------------
+// Direct store of a clip contracted in one split (batch form, two-wave-per-SIMD
+// kernels): the work item unfolds its accumulators into F itself, as the
+// epilogue would (the sum over one split is that split, added to an FP64 zero
+// in the same way), so no quadrant partials are written or read back.  The
+// guard block's entries are left to the epilogue, which writes them from the
+// FP64 sums.  The one-wave-per-SIMD kernel keeps writing partials: with its
+// 256 accumulators the unfolding does not fit beside them without spills.
+// ---------------------------------------------------------------------------
+struct DirectOut {
+  OutGrid o;
+  int K, L;
+  int on;  // 0: this clip writes partials
+};
+
+// Output of a batch clip for the direct store (on when it has one split).
+__device__ __forceinline__ DirectOut direct_out(const BatchClip &c) {
+  return DirectOut{OutGrid{c.F, c.K, c.L, -1.0, (double)c.T, 1.0, 1.0, 1.0 / (double)c.T}, c.K,
+                   c.L, c.direct};
+}
+
+template <int NKB, int NLB>
+__device__ __forceinline__ void store_direct(const DirectOut &d, const f32x16 (&acc)[NKB][NLB][4],
+                                             int k0, int l0, int li, int lh) {
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+    for (int lb = 0; lb < NLB; ++lb) {
+      const int l = l0 + 32 * lb + li;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int k = k0 + 32 * kb + 8 * (r >> 2) + 4 * lh + (r & 3);
+        if (k < 1 || k > d.K || l < 1 || l > d.L || (k <= kGuard && l <= kGuard)) continue;
+        store_quad(d.o, k, l, 0.0, 0.0 + (double)acc[kb][lb][0][r],
+                   0.0 + (double)acc[kb][lb][1][r], 0.0 + (double)acc[kb][lb][2][r],
+                   0.0 + (double)acc[kb][lb][3][r]);
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Vertex contraction (Step 4) in real-trigonometric form:
 //   Z = X diag(s) Y^T,  X = [cos; sin](2 pi k x_v / T), Y likewise in l,
 // giving per (k, l >= 0) the four sums P = sum s c c', U = sum s c s',
@@ -481,11 +521,12 @@ __global__ __launch_bounds__(256) void k_contract_split(const uint4 *__restrict_
 // Lean form of the same contraction for two waves per SIMD: no software
 // pipeline inside the wave (lookups, fragment build and MFMAs of a step in
 // sequence); the second wave on the SIMD hides the latencies.
-template <int PREC, int NKB, int NLB>
+template <int PREC, int NKB, int NLB, bool DIRECT = false>
 __device__ __forceinline__ void contract_lean_body(const uint2 *s_tab,
                                                    const uint4 *__restrict__ packed,
                                                    int64_t chunk, int tiles_l, int kp, int lp,
-                                                   float *__restrict__ part, int tile, int split) {
+                                                   float *__restrict__ part, int tile, int split,
+                                                   const BatchClip *bc = nullptr) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 31, lh = lane >> 5;
   const int tk = tile / tiles_l, tl = tile % tiles_l;
@@ -517,6 +558,13 @@ __device__ __forceinline__ void contract_lean_body(const uint2 *s_tab,
     Frag<NKB, NLB> f;
     build(f, raw);
     mma<PREC>(acc, f);
+  }
+  if constexpr (DIRECT) {
+    // read after the loop, so that nothing of it stays live through the MFMAs
+    if (bc->direct) {
+      store_direct<NKB, NLB>(direct_out(*bc), acc, k0, l0, li, lh);
+      return;
+    }
   }
   store_part<NKB, NLB>(part, acc, split, kp, lp, k0, l0, li, lh);
 }
@@ -630,11 +678,12 @@ __global__ __launch_bounds__(256, 1) void k_contract_split_pipe(const uint4 *__r
 
 // FP32 form: v_mfma_f32_32x32x2_f32, two corners per product (lanes 0-31
 // carry corner j of the lane's group, lanes 32-63 corner 8 + j).
-template <int NKB, int NLB>
+template <int NKB, int NLB, bool DIRECT = false>
 __device__ __forceinline__ void contract_fp32_body(const float2 *s_tab,
                                                    const uint4 *__restrict__ packed,
                                                    int64_t chunk, int tiles_l, int kp, int lp,
-                                                   float *__restrict__ part, int tile, int split) {
+                                                   float *__restrict__ part, int tile, int split,
+                                                   const BatchClip *bc = nullptr) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 31, lh = lane >> 5;
   const int tk = tile / tiles_l, tl = tile % tiles_l;
@@ -679,6 +728,13 @@ __device__ __forceinline__ void contract_fp32_body(const float2 *s_tab,
           acc[kb][lb][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[kb].y, b[lb].x, acc[kb][lb][2], 0, 0, 0);
           acc[kb][lb][3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[kb].y, b[lb].y, acc[kb][lb][3], 0, 0, 0);
         }
+    }
+  }
+  if constexpr (DIRECT) {
+    // read after the loop, so that nothing of it stays live through the MFMAs
+    if (bc->direct) {
+      store_direct<NKB, NLB>(direct_out(*bc), acc, k0, l0, li, lh);
+      return;
     }
   }
   store_part<NKB, NLB>(part, acc, split, kp, lp, k0, l0, li, lh);
@@ -771,39 +827,9 @@ hipError_t launch_contract(const FwdPlan &p, const uint4 *packed, const Tables &
 // Split partials are summed in FP64 in a fixed order.  One launch covers the
 // contraction grid (blocks [0, nmain), the guard block's entries excepted),
 // the axes and DC (the next nax blocks) and the guard block (the last one).
+// The output grid and the unfolding (OutGrid, put, store_quad) are shared with
+// the contraction kernels that write single-split clips directly.
 // ---------------------------------------------------------------------------
-// Output grid of one clip: F holds (2 KO + 1) x (2 LO + 1) coefficients,
-// k-major, index (KO + k)(2 LO + 1) + (LO + l).  It may be larger than the
-// computed band |k| <= K, |l| <= L (the rest is cleared beforehand); with
-// r2 >= 0 the entries with k^2 + l^2 > r2 are written as zero (a pupil).
-// The factors of alpha_{k,l} (Prop. 3) come with the grid: alpha_{k,l} =
-// -g / (4 pi^2 k l), alpha_{k,0} = j ax / (2 pi k), alpha_{0,l} = j ay / (2 pi l),
-// F[0,0] = dc * area.  A square tile of period T has g = T, ax = ay = 1,
-// dc = 1 / T; a general one carries the sqrt(Nx/Ny)-type factors.
-struct OutGrid {
-  float2 *F;
-  int KO, LO;
-  double r2;
-  double g, ax, ay, dc;
-};
-
-__device__ __forceinline__ void put(const OutGrid &o, int k, int l, float re, float im) {
-  if (o.r2 >= 0.0 && (double)k * k + (double)l * l > o.r2) re = im = 0.0f;
-  o.F[(size_t)(o.KO + k) * (2 * (size_t)o.LO + 1) + (o.LO + l)] = make_float2(re, im);
-}
-
-__device__ __forceinline__ void store_quad(const OutGrid &o, int k, int l, double T, double P,
-                                           double U, double R, double Q) {
-  (void)T;
-  const double a = -o.g / (4.0 * kPi * kPi * (double)k * (double)l);
-  const double pre = a * (P - Q), pim = -a * (R + U);  // F[k, l]
-  const double mre = -a * (P + Q), mim = a * (R - U);  // F[k, -l]
-  put(o, k, l, (float)pre, (float)pim);
-  put(o, -k, -l, (float)pre, (float)-pim);
-  put(o, k, -l, (float)mre, (float)mim);
-  put(o, -k, l, (float)mre, (float)-mim);
-}
-
 __device__ __forceinline__ void epilogue_body(const float *__restrict__ part, int nsplit, int kp,
                                               int lp, int K, int L, double T, const OutGrid &o,
                                               int bx, int by) {
@@ -909,10 +935,10 @@ __device__ __forceinline__ void epilogue_block(const float *__restrict__ part, i
                                                const unsigned long long *__restrict__ area_part,
                                                int pre_blocks, const double *__restrict__ gfinal,
                                                const OutGrid &o, int64_t *__restrict__ area,
-                                               int b) {
+                                               int b, bool direct = false) {
   const bool grid2d = K > 0 && L > 0;
   const int nbx = (L + 63) / 64;
-  const int nmain = grid2d ? nbx * K : 0;
+  const int nmain = grid2d && !direct ? nbx * K : 0;
   const int nax = max(1, (K + L + 15) / 16);
   if (b < nmain)
     epilogue_body(part, nsplit, kp, lp, K, L, T, o, b % nbx, b / nbx);
@@ -922,8 +948,8 @@ __device__ __forceinline__ void epilogue_block(const float *__restrict__ part, i
     guard_store(gfinal, K, L, T, o);
 }
 
-int epilogue_block_count(int K, int L) {
-  const int nmain = K > 0 && L > 0 ? ((L + 63) / 64) * K : 0;
+int epilogue_block_count(int K, int L, bool direct) {
+  const int nmain = K > 0 && L > 0 && !direct ? ((L + 63) / 64) * K : 0;
   const int nax = std::max(1, (K + L + 15) / 16);
   return nmain + nax + (K > 0 && L > 0 ? 1 : 0);
 }
@@ -1211,8 +1237,8 @@ __global__ __launch_bounds__(256, 2) void k_batch_contract(const BatchClip *__re
     if (it < 0) break;
     const int4 d = items[it];
     const BatchClip &c = clips[d.x];
-    contract_lean_body<PREC, NKB, NLB>(s_tab, c.packed, c.chunk, c.tiles_l, c.kp, c.lp, c.part,
-                                       d.y, d.z);
+    contract_lean_body<PREC, NKB, NLB, true>(s_tab, c.packed, c.chunk, c.tiles_l, c.kp, c.lp,
+                                             c.part, d.y, d.z, &c);
   }
 }
 
@@ -1248,8 +1274,8 @@ __global__ __launch_bounds__(256, 2) void k_batch_contract_fp32(const BatchClip 
     if (it < 0) break;
     const int4 d = items[it];
     const BatchClip &c = clips[d.x];
-    contract_fp32_body<NKB, NLB>(s_tab, c.packed, c.chunk, c.tiles_l, c.kp, c.lp, c.part, d.y,
-                                 d.z);
+    contract_fp32_body<NKB, NLB, true>(s_tab, c.packed, c.chunk, c.tiles_l, c.kp, c.lp, c.part,
+                                       d.y, d.z, &c);
   }
 }
 
@@ -1273,7 +1299,7 @@ __global__ __launch_bounds__(256) void k_batch_epilogue(const BatchClip *__restr
   const BatchClip &c = clips[ci];
   const OutGrid o{c.F, c.K, c.L, -1.0, (double)c.T, 1.0, 1.0, 1.0 / (double)c.T};
   epilogue_block(c.part, c.nsplit, c.kp, c.lp, c.K, c.L, (double)c.T, c.axis_part, c.ax_chunks,
-                 c.area_part, pre_blocks, c.gfinal, o, c.area, blockIdx.x - off[ci]);
+                 c.area_part, pre_blocks, c.gfinal, o, c.area, blockIdx.x - off[ci], c.direct != 0);
 }
 
 hipError_t launch_batch_prepass(const BatchLaunch &b, hipStream_t st) {

@@ -95,6 +95,37 @@ def test_batch_equals_single_clip_and_replays(P):
     b.close()
 
 
+def test_batch_single_split_clips_write_directly(P, oracle_lib):
+    # clips contracted in one split unfold their sums into F in the work item
+    # itself (no partials); small bands inside the FP64 guard block, one-sided
+    # bands and a multi-split clip ride in the same batch
+    base = synth.clip(71, 2048, 127, n_polygons=120)
+    big = synth.clip(72, 4096, 63, min_vertices=40_000)
+    spec = [(base, 2048, 5, 5), (base, 2048, 0, 7), (base, 2048, 9, 0), (base, 2048, 20, 3),
+            (base, 2048, 127, 127), (big, 4096, 63, 63)]
+    args = []
+    for c, T, K, L in spec:
+        x, y, s, _, _ = P.loops_to_corners(c.xy, c.off)
+        args.append((x, y, s, T, K, L))
+    _say(f"single-split batch: V = {[a[0].size for a in args]}")
+    b = P.Batch(args, precision="bf16")
+    F = [f.cpu().numpy().astype(np.complex128) for f in b.run()]
+    torch.cuda.synchronize()
+    for i, (c, T, K, L) in enumerate(spec):
+        ref, area = oracle_lib.cfs_grid(c.xy, c.off, T, K, L) if c is base else (None, None)
+        if ref is None:
+            kk, ll = _sample(K, 80, i)
+            refp = oracle_lib.cfs_points(c.xy, c.off, T, kk, ll)
+            f00 = abs(oracle_lib.cfs_points(c.xy, c.off, T, [0], [0])[0])
+            e = float(np.max(np.abs(F[i][kk + K, ll + L] - refp)) / f00)
+        else:
+            e = float(np.max(np.abs(F[i] - ref)) / abs(ref[K, L]))
+            assert int(b.area[i].item()) == area
+        _say(f"  clip {i} T={T} K={K} L={L}: err/|F00| = {e:.3e}")
+        assert e <= TOL["bf16"], (i, e)
+    b.close()
+
+
 def test_autotune_and_cache(P, tmp_path):
     path = tmp_path / "tune.json"
     h = P.Handle()
