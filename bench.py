@@ -675,6 +675,15 @@ def main() -> int:
     ms5t, _ = timed(step5_torch_loss, max(3, args.steps // 4), 1, h)
     ms5, prof5 = timed(step5, max(3, args.steps // 4), 1, h,
                        kinds=("prepass", "contract", "epilogue", "adjoint"))
+    # the same step as one library call (fcfs_pupil_step): identical launches
+    # without the autograd engine between them; its gradient is compared with
+    # the autograd step's bit for bit
+    off0 = off.detach().clone()
+    ms5s, _ = timed(lambda: P.pupil_step(geom, off0, Gt, radius=r5, band=(rb, rb)),
+                    max(3, args.steps // 4), 1, h, kinds=None)
+    step5()
+    _, g_one = P.pupil_step(geom, off0, Gt, radius=r5, band=(rb, rb))
+    one_call_same = bool(torch.equal(g_one, off.grad))
     V5 = int(geom.base_x.numel())
     adj = {
         "workload": (f"adjoint: {V5} corners, T={T5}, |k|,|l|<={K5}, loss sum |H F - G|^2 with a "
@@ -683,6 +692,8 @@ def main() -> int:
                      "the loss in torch ops is reported beside it)"),
         "ms_per_step": ms5,
         "ms_per_step_loss_in_torch_ops": ms5t,
+        "ms_per_step_one_call": ms5s,
+        "one_call_gradient_equals_autograd": one_call_same,
         "forward_ms": sum(kavg(prof5, k) or 0.0 for k in ("prepass", "contract", "epilogue")),
         "adjoint_ms": kavg(prof5, "adjoint"),
         "value": V5 * (2 * K5 + 1) ** 2 / (ms5 * 1e-3),
@@ -706,7 +717,8 @@ def main() -> int:
         got = off.grad.detach().cpu().numpy().astype(np.float64)[edges]
         adj["grad_err_rel_max"] = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
     forms["adjoint"] = adj
-    log(f"adjoint: {ms5:.3f} ms per forward+backward (loss in torch ops: {ms5t:.3f} ms)")
+    log(f"adjoint: {ms5:.3f} ms per forward+backward (loss in torch ops: {ms5t:.3f} ms; "
+        f"one library call {ms5s:.3f} ms, same gradient: {one_call_same})")
     out["forms"] = forms
     print(json.dumps(out))
     return 0

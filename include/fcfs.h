@@ -223,6 +223,32 @@ fcfs_status fcfs_pupil_loss(fcfs_handle *h, const float *F, const float *G, cons
                             int32_t K, int32_t L, double radius, double *loss, float *grad,
                             void *ws, size_t ws_bytes);
 
+/* One step of the edge-moving optimisation behind a pupil in a single call,
+ * for loops that drive the step without an autograd engine: the launches of
+ *   fcfs_apply_edge_offsets (corners from base_x, base_y and the offsets),
+ *   fcfs_forward_band (kmax, lmax, radius),
+ *   fcfs_pupil_loss (G, H or the disc of radius),
+ *   fcfs_adjoint_band (same band and disc) and fcfs_edge_grad,
+ * enqueued in that order on the handle's stream with no host work between
+ * them; results are bit-identical to making those calls one by one.  All
+ * arrays (device): base_x, base_y, s, hedge, vedge [V] as from
+ * fcfs_loops_to_corners (E = V edges), offsets [V] (one per edge, rounded to
+ * integers), G (and H unless NULL) (2K+1)(2L+1) complex64 (real for H).
+ * Outputs: loss (one double), g_edge [V] = dLoss/d(edge offset), and F_out
+ * ((2K+1)(2L+1) complex64, the low-pass spectrum) unless NULL.  T a power of
+ * two.  ws: at least fcfs_pupil_step_workspace_size bytes, 256-byte aligned;
+ * it also holds the moved corners, the spectrum (when F_out is NULL), the
+ * cotangent and the per-corner gradients. */
+fcfs_status fcfs_pupil_step_workspace_size(int64_t V, int32_t T, int32_t K, int32_t L,
+                                           int32_t kmax, int32_t lmax, double radius,
+                                           fcfs_precision p, size_t *bytes);
+fcfs_status fcfs_pupil_step(fcfs_handle *h, const int32_t *base_x, const int32_t *base_y,
+                            const int8_t *s, const int64_t *hedge, const int64_t *vedge,
+                            const float *offsets, int64_t V, int32_t T, int32_t K, int32_t L,
+                            int32_t kmax, int32_t lmax, double radius, const float *G,
+                            const float *H, fcfs_precision p, double *loss, float *g_edge,
+                            float *F_out, void *ws, size_t ws_bytes);
+
 /* Pruned continuous Haar transform (PCHT, Sec. III-B1) of the polygons of one
  * tile [0,Nx) x [0,Ny): the inner products of the sum of polygon indicators
  * with the 2-D Haar basis of Sec. II-B (scaling function phi_{0,0,0} and the

@@ -499,6 +499,53 @@ class Geometry:
         return x, y
 
 
+def pupil_step(geom, offsets, G, radius=None, band=None, H=None, precision="bf16", F_out=None):
+    """One optimisation step behind a pupil in a single library call
+    (``fcfs_pupil_step``): corners moved by ``offsets`` (one per edge, rounded
+    to integers), low-pass forward over ``band`` / ``radius``, loss
+    sum |H F - G|^2 (H the disc indicator when None), adjoint and edge
+    reduction.  The same launches as ``FCFSFunction`` + ``PupilLoss`` +
+    ``backward()``, without the autograd engine.  Square tiles only.
+    Returns ``(loss, g_edge)``: a 0-d float64 tensor and the float32 edge
+    gradient; the spectrum goes to ``F_out`` when given."""
+    import torch
+
+    if geom.general:
+        raise NotImplementedError("pupil_step takes square power-of-two tiles")
+    h = geom.handle
+    h.sync_stream()
+    dev = h.device
+    V, T, K, L = geom.n_edges, geom.T, geom.K, geom.L
+    off = _on(dev, offsets.detach() if isinstance(offsets, torch.Tensor) else offsets,
+              torch.float32)
+    G = _on(dev, G, torch.complex64)
+    Hc = None if H is None else _on(dev, H, torch.float32)
+    if off.numel() != V or G.numel() != (2 * K + 1) * (2 * L + 1):
+        raise ValueError("one offset per edge and a (2K+1, 2L+1) target")
+    if F_out is not None and (F_out.dtype != torch.complex64 or F_out.numel() != G.numel()
+                              or not F_out.is_contiguous()):
+        raise ValueError("F_out must be a contiguous complex64 tensor like G")
+    kmax, lmax = (K, L) if band is None else (int(band[0]), int(band[1]))
+    rad = -1.0 if radius is None else float(radius)
+    loss = torch.empty((), dtype=torch.float64, device=dev)
+    g = torch.empty(V, dtype=torch.float32, device=dev)
+    ws = h.workspace(_step_workspace_size(V, T, K, L, kmax, lmax, rad, _prec(precision)))
+    vp = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    check(h.lib.fcfs_pupil_step(h.ptr, vp(geom.base_x), vp(geom.base_y), vp(geom.s),
+                                vp(geom.hedge), vp(geom.vedge), vp(off), V, T, K, L, kmax, lmax,
+                                rad, vp(G), vp(Hc), _prec(precision), vp(loss), vp(g), vp(F_out),
+                                vp(ws), ctypes.c_size_t(ws.numel())), h.ptr)
+    return loss, g
+
+
+@functools.lru_cache(maxsize=64)
+def _step_workspace_size(V, T, K, L, kmax, lmax, rad, prec) -> int:
+    nb = ctypes.c_size_t(0)
+    check(load().fcfs_pupil_step_workspace_size(V, T, K, L, kmax, lmax, rad, prec,
+                                                ctypes.byref(nb)))
+    return int(nb.value)
+
+
 @functools.lru_cache(maxsize=1)
 def _loss_workspace_size() -> int:
     nb = ctypes.c_size_t(0)

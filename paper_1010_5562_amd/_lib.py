@@ -34,6 +34,7 @@ EXPORTS = (
     "fcfs_general_band_workspace_size", "fcfs_forward_general_band",
     "fcfs_general_adjoint_workspace_size", "fcfs_adjoint_general", "fcfs_apply_edge_offsets_grid",
     "fcfs_pupil_loss_workspace_size", "fcfs_pupil_loss",
+    "fcfs_pupil_step_workspace_size", "fcfs_pupil_step",
     "fcfs_adjoint", "fcfs_adjoint_band", "fcfs_edge_grad",
     "fcfs_apply_edge_offsets", "fcfs_batch_workspace_size", "fcfs_forward_batch", "fcfs_plan_destroy",
     "fcfs_debug_phases", "fcfs_autotune", "fcfs_autotune_batch", "fcfs_batch_choice",
@@ -137,6 +138,10 @@ def load() -> ctypes.CDLL:
         "fcfs_apply_edge_offsets_grid": [P, P, P, P, P, P, i64, i32, P, P],
         "fcfs_pupil_loss_workspace_size": [sz],
         "fcfs_pupil_loss": [P, P, P, P, i32, i32, ctypes.c_double, P, P, P, ctypes.c_size_t],
+        "fcfs_pupil_step_workspace_size": [i64, i32, i32, i32, i32, i32, ctypes.c_double, c_int,
+                                           sz],
+        "fcfs_pupil_step": [P, P, P, P, P, P, P, i64, i32, i32, i32, i32, i32, ctypes.c_double,
+                            P, P, c_int, P, P, P, P, ctypes.c_size_t],
         "fcfs_haar": [P, ctypes.POINTER(FcfsHaarClip), P, ctypes.c_size_t],
         "fcfs_adjoint": [P, clip_p, P, P, P, c_int, P, ctypes.c_size_t],
         "fcfs_adjoint_band": [P, clip_p, P, i32, i32, ctypes.c_double, P, P, c_int, P,

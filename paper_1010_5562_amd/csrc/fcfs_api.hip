@@ -1265,6 +1265,106 @@ fcfs_status fcfs_pupil_loss(fcfs_handle *h, const float *F, const float *G, cons
   return FCFS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// One optimisation step behind a pupil in one call: the same launches, in the
+// same order, as the autograd path (edge offsets, low-pass forward, fused
+// loss, adjoint, edge reduction), with no host work in between.
+// Workspace: corners x, y | F | cotangent | area | gx, gy | the largest
+// workspace of the forward, loss and adjoint calls (used by one at a time).
+// ---------------------------------------------------------------------------
+struct StepLayout {
+  size_t x, y, F, cot, area, gx, gy, sub, sub_bytes, bytes;
+};
+
+static fcfs_status step_layout(int64_t V, int32_t T, int32_t K, int32_t L, int32_t kmax,
+                               int32_t lmax, double radius, int prec, StepLayout *out) {
+  if (V < 0) return fail(nullptr, FCFS_ERR_INVALID_ARG, "V < 0");
+  if (kmax < 0 || lmax < 0) return fail(nullptr, FCFS_ERR_INVALID_ARG, "band must be >= 0");
+  if (!(radius == radius)) return fail(nullptr, FCFS_ERR_INVALID_ARG, "radius is NaN");
+  fcfs_clip c{};
+  c.V = V;
+  c.T = T;
+  c.K = K;
+  c.L = L;
+  size_t fwd = 0, adj = 0;
+  fcfs_status st = fcfs_band_workspace_size(&c, kmax, lmax, radius, (fcfs_precision)prec, &fwd);
+  if (st) return st;
+  if ((st = fcfs_workspace_size(&c, (fcfs_precision)prec, 1, &adj))) return st;
+  const size_t nf = (2 * (size_t)K + 1) * (2 * (size_t)L + 1) * sizeof(float2);
+  StepLayout q{};
+  size_t off = 0;
+  q.x = off;
+  off += align256(sizeof(int32_t) * (size_t)std::max<int64_t>(V, 1));
+  q.y = off;
+  off += align256(sizeof(int32_t) * (size_t)std::max<int64_t>(V, 1));
+  q.F = off;
+  off += align256(nf);
+  q.cot = off;
+  off += align256(nf);
+  q.area = off;
+  off += 256;
+  q.gx = off;
+  off += align256(sizeof(float) * (size_t)std::max<int64_t>(V, 1));
+  q.gy = off;
+  off += align256(sizeof(float) * (size_t)std::max<int64_t>(V, 1));
+  q.sub = off;
+  q.sub_bytes = std::max(std::max(fwd, adj), fcfs::pupil_loss_workspace_bytes());
+  q.bytes = off + q.sub_bytes;
+  *out = q;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_pupil_step_workspace_size(int64_t V, int32_t T, int32_t K, int32_t L,
+                                           int32_t kmax, int32_t lmax, double radius,
+                                           fcfs_precision p, size_t *bytes) {
+  if (!bytes) return fail(nullptr, FCFS_ERR_INVALID_ARG, "NULL argument");
+  StepLayout q;
+  fcfs_status st = step_layout(V, T, K, L, kmax, lmax, radius, (int)p, &q);
+  if (st) return st;
+  *bytes = q.bytes;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_pupil_step(fcfs_handle *h, const int32_t *base_x, const int32_t *base_y,
+                            const int8_t *s, const int64_t *hedge, const int64_t *vedge,
+                            const float *offsets, int64_t V, int32_t T, int32_t K, int32_t L,
+                            int32_t kmax, int32_t lmax, double radius, const float *G,
+                            const float *H, fcfs_precision p, double *loss, float *g_edge,
+                            float *F_out, void *ws, size_t ws_bytes) {
+  fcfs_status st = enter(h);
+  if (st) return st;
+  StepLayout q;
+  if ((st = step_layout(V, T, K, L, kmax, lmax, radius, (int)p, &q)))
+    return fail(h, st, std::string("pupil step: ") + fcfs_last_error(nullptr));
+  if (!G || !loss || (V > 0 && !g_edge)) return fail(h, FCFS_ERR_INVALID_ARG, "NULL array");
+  if (ws_bytes < q.bytes)
+    return fail(h, FCFS_ERR_WORKSPACE,
+                "workspace too small: need " + std::to_string(q.bytes) + " bytes, got " +
+                    std::to_string(ws_bytes));
+  if (!ws || ((uintptr_t)ws & 255u)) return fail(h, FCFS_ERR_WORKSPACE, "workspace NULL or misaligned");
+  int32_t *x = ws_at<int32_t>(ws, q.x), *y = ws_at<int32_t>(ws, q.y);
+  float *F = F_out ? F_out : ws_at<float>(ws, q.F);
+  float *cot = ws_at<float>(ws, q.cot);
+  float *gx = ws_at<float>(ws, q.gx), *gy = ws_at<float>(ws, q.gy);
+  void *sub = ws_at<char>(ws, q.sub);
+  if ((st = fcfs_apply_edge_offsets(h, base_x, base_y, hedge, vedge, offsets, V, x, y))) return st;
+  fcfs_clip c{};
+  c.x = x;
+  c.y = y;
+  c.s = s;
+  c.V = V;
+  c.T = T;
+  c.K = K;
+  c.L = L;
+  c.F = F;
+  c.area = ws_at<int64_t>(ws, q.area);
+  if ((st = fcfs_forward_band(h, &c, kmax, lmax, radius, p, sub, q.sub_bytes))) return st;
+  if ((st = fcfs_pupil_loss(h, F, G, H, K, L, radius, loss, cot, sub, q.sub_bytes))) return st;
+  if ((st = fcfs_adjoint_band(h, &c, cot, kmax, lmax, radius, gx, gy, p, sub, q.sub_bytes)))
+    return st;
+  return fcfs_edge_grad(h, gx, gy, hedge, vedge, V, V, g_edge);
+}
+
 fcfs_status fcfs_general_adjoint_workspace_size(const fcfs_gclip *c, fcfs_precision p,
                                                 size_t *bytes) {
   if (!bytes) return fail(nullptr, FCFS_ERR_INVALID_ARG, "NULL argument");

@@ -138,6 +138,23 @@ def test_general_workspace_sizes(lib):
     assert lib.fcfs_general_workspace_size(ctypes.byref(c), 1, ctypes.byref(full)) == -4
 
 
+def test_pupil_step_workspace_size(lib):
+    n = ctypes.c_size_t(0)
+    assert lib.fcfs_pupil_step_workspace_size(100000, 4096, 255, 255, 89, 89, 89.25, 1,
+                                              ctypes.byref(n)) == 0
+    full = ctypes.c_size_t(0)
+    assert lib.fcfs_pupil_step_workspace_size(100000, 4096, 255, 255, 255, 255, -1.0, 1,
+                                              ctypes.byref(full)) == 0
+    # moved corners, spectrum, cotangent and per-corner gradients come on top
+    assert full.value >= n.value > 2 * 511 * 511 * 8 + 4 * 4 * 100000
+    assert lib.fcfs_pupil_step_workspace_size(100, 1000, 8, 8, 8, 8, -1.0, 1,
+                                              ctypes.byref(n)) == -4  # T not a power of two
+    assert lib.fcfs_pupil_step_workspace_size(100, 1024, 8, 8, -1, 8, -1.0, 1,
+                                              ctypes.byref(n)) == -1
+    assert lib.fcfs_pupil_step_workspace_size(100, 1024, 8, 8, 8, 8, float("nan"), 1,
+                                              ctypes.byref(n)) == -1
+
+
 def test_null_handle_is_rejected(lib):
     from paper_1010_5562_amd import _lib
 

@@ -269,3 +269,33 @@ def test_optimisation_step_in_a_graph(P):
         torch.cuda.synchronize()
         assert torch.equal(off.grad, want[it % 2][0])
     del keep
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_pupil_step_matches_the_autograd_step(P, prec):
+    # the one-call step enqueues the same launches as the autograd path:
+    # loss, edge gradient and spectrum agree bit for bit (disc H and given H)
+    T, K = 2048, 60
+    r = 0.35 * K
+    rb = int(np.floor(r))
+    clip = synth.clip(45, T, K, n_polygons=150)
+    geom = P.Geometry(clip.xy, clip.off, T, K, check_offsets=False)
+    kk, ll = np.meshgrid(np.arange(-K, K + 1), np.arange(-K, K + 1), indexing="ij")
+    Hn = (kk ** 2 + ll ** 2 <= r * r).astype(np.float32)
+    rng = np.random.default_rng(8)
+    Gt = torch.as_tensor((Hn * (rng.normal(size=kk.shape) + 1j * rng.normal(size=kk.shape)))
+                         .astype(np.complex64)).cuda()
+    offs = torch.as_tensor(rng.integers(-3, 4, geom.n_edges).astype(np.float32)).cuda()
+    for H in (None, torch.as_tensor(Hn * 0.5).cuda()):
+        off = offs.clone().requires_grad_(True)
+        Fv = P.FCFSFunction.apply(off, geom, prec, (rb, rb), r)
+        loss = P.PupilLoss.apply(Fv, Gt, r, H)
+        loss.backward()
+        Fs = torch.empty_like(Fv)
+        ls, gs = P.pupil_step(geom, offs, Gt, radius=r, band=(rb, rb), H=H, precision=prec,
+                              F_out=Fs)
+        torch.cuda.synchronize()
+        assert torch.equal(Fs, Fv.detach())
+        assert torch.equal(ls, loss.detach())
+        assert torch.equal(gs, off.grad)
+        _say(f"pupil step {prec} H={'disc' if H is None else 'weights'}: loss {float(ls):.6e}")
