@@ -684,6 +684,12 @@ def main() -> int:
     step5()
     _, g_one = P.pupil_step(geom, off0, Gt, radius=r5, band=(rb, rb))
     one_call_same = bool(torch.equal(g_one, off.grad))
+    # and captured once into a graph, replayed per step (new offsets copied in)
+    plan5 = P.PupilStep(geom, Gt, radius=r5, band=(rb, rb))
+    ms5g, _ = timed(lambda: plan5.run(off0), max(3, args.steps // 4), 1, h, kinds=None)
+    _, g_graph = plan5.run(off0)
+    graph_same = bool(torch.equal(g_graph, off.grad))
+    plan5.close()
     V5 = int(geom.base_x.numel())
     adj = {
         "workload": (f"adjoint: {V5} corners, T={T5}, |k|,|l|<={K5}, loss sum |H F - G|^2 with a "
@@ -694,6 +700,8 @@ def main() -> int:
         "ms_per_step_loss_in_torch_ops": ms5t,
         "ms_per_step_one_call": ms5s,
         "one_call_gradient_equals_autograd": one_call_same,
+        "ms_per_step_graph_replay": ms5g,
+        "graph_gradient_equals_autograd": graph_same,
         "forward_ms": sum(kavg(prof5, k) or 0.0 for k in ("prepass", "contract", "epilogue")),
         "adjoint_ms": kavg(prof5, "adjoint"),
         "value": V5 * (2 * K5 + 1) ** 2 / (ms5 * 1e-3),
@@ -718,7 +726,8 @@ def main() -> int:
         adj["grad_err_rel_max"] = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
     forms["adjoint"] = adj
     log(f"adjoint: {ms5:.3f} ms per forward+backward (loss in torch ops: {ms5t:.3f} ms; "
-        f"one library call {ms5s:.3f} ms, same gradient: {one_call_same})")
+        f"one library call {ms5s:.3f} ms, same gradient: {one_call_same}; captured step "
+        f"{ms5g:.3f} ms per replay, same gradient: {graph_same})")
     out["forms"] = forms
     print(json.dumps(out))
     return 0

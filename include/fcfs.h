@@ -68,6 +68,7 @@ typedef enum { FCFS_FP32 = 0, FCFS_SPLIT_BF16 = 1, FCFS_SPLIT_FP16 = 2 } fcfs_pr
 
 typedef struct fcfs_handle fcfs_handle;
 typedef struct fcfs_plan fcfs_plan;
+typedef struct fcfs_step_plan fcfs_step_plan;
 
 /* One clip: a signed corner list (the concatenated sparse lists of Alg. 2 for
  * all polygons of the tile, Sec. III-C1 "multiple polygons") and its output. */
@@ -249,6 +250,23 @@ fcfs_status fcfs_pupil_step(fcfs_handle *h, const int32_t *base_x, const int32_t
                             const float *H, fcfs_precision p, double *loss, float *g_edge,
                             float *F_out, void *ws, size_t ws_bytes);
 
+/* fcfs_pupil_step captured once into a HIP graph and replayed: for loops that
+ * repeat the step with new values in the same buffers (offsets, G, H).
+ * fcfs_pupil_step_plan takes the arguments of fcfs_pupil_step, runs one
+ * step eagerly (argument checks, one-time kernel set-up; the outputs hold its
+ * result) and captures the next one on a stream of its own.  Every buffer,
+ * the workspace included, must stay allocated and unmoved while the plan
+ * lives; fcfs_step_plan_launch replays the step on the handle's stream (same
+ * device).  The plan owns its graph; fcfs_step_plan_destroy frees it. */
+fcfs_status fcfs_pupil_step_plan(fcfs_handle *h, const int32_t *base_x, const int32_t *base_y,
+                                 const int8_t *s, const int64_t *hedge, const int64_t *vedge,
+                                 const float *offsets, int64_t V, int32_t T, int32_t K, int32_t L,
+                                 int32_t kmax, int32_t lmax, double radius, const float *G,
+                                 const float *H, fcfs_precision p, double *loss, float *g_edge,
+                                 float *F_out, void *ws, size_t ws_bytes, fcfs_step_plan **plan);
+fcfs_status fcfs_step_plan_launch(fcfs_handle *h, fcfs_step_plan *plan);
+fcfs_status fcfs_step_plan_destroy(fcfs_step_plan *plan);
+
 /* Pruned continuous Haar transform (PCHT, Sec. III-B1) of the polygons of one
  * tile [0,Nx) x [0,Ny): the inner products of the sum of polygon indicators
  * with the 2-D Haar basis of Sec. II-B (scaling function phi_{0,0,0} and the
@@ -394,7 +412,8 @@ fcfs_status fcfs_workspace_size_tile(const fcfs_clip *c, fcfs_precision p, int32
  * work (histograms, guard block, axis DFTs), 2 contraction, 3 epilogue,
  * 4 adjoint kernels, 5 batched graph, 6 lattice form, 7 Haar quadtree walk
  * (the Haar transform's clear-and-plan launches count as pre-pass, its
- * scaling pass as epilogue), 8 pupil loss, 9 direct form of small problems.
+ * scaling pass as epilogue), 8 pupil loss, 9 direct form of small problems,
+ * 10 replay of a captured optimisation step.
  * Each bracketed launch adds two event records to its stream. */
 fcfs_status fcfs_profile_begin(fcfs_handle *h, uint32_t kinds);
 fcfs_status fcfs_profile_end(fcfs_handle *h, double *ms, int64_t *count, int32_t nkinds);

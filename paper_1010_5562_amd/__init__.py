@@ -130,7 +130,7 @@ class Handle:
         check(self.lib.fcfs_set_tile(self._h, int(variant)), self._h)
 
     PROFILE_KINDS = ("prepass", "axis", "contract", "epilogue", "adjoint", "batch", "fft",
-                     "haar", "loss", "direct")
+                     "haar", "loss", "direct", "step")
 
     def profile_begin(self, kinds=None):
         """Starts event timing of the named kinds (all kinds when None)."""
@@ -536,6 +536,65 @@ def pupil_step(geom, offsets, G, radius=None, band=None, H=None, precision="bf16
                                 rad, vp(G), vp(Hc), _prec(precision), vp(loss), vp(g), vp(F_out),
                                 vp(ws), ctypes.c_size_t(ws.numel())), h.ptr)
     return loss, g
+
+
+class PupilStep:
+    """``pupil_step`` captured once into a graph (``fcfs_pupil_step_plan``)
+    and replayed by ``run(offsets)``: the offsets are copied into the plan's
+    own buffer, then the graph runs on the current stream.  ``loss``,
+    ``g_edge`` and ``F`` are the plan's output tensors, overwritten by every
+    run; G (and H) are copied at construction, and ``G.copy_(...)`` between
+    runs changes the target.  The plan holds its own workspace."""
+
+    def __init__(self, geom, G, radius=None, band=None, H=None, precision="bf16"):
+        import torch
+
+        if geom.general:
+            raise NotImplementedError("PupilStep takes square power-of-two tiles")
+        self.geom = geom
+        h = self.handle = geom.handle
+        h.sync_stream()
+        dev = h.device
+        V, T, K, L = geom.n_edges, geom.T, geom.K, geom.L
+        self.offsets = torch.zeros(V, dtype=torch.float32, device=dev)
+        self.G = _on(dev, G, torch.complex64).clone()
+        if self.G.numel() != (2 * K + 1) * (2 * L + 1):
+            raise ValueError("G must have (2K+1)(2L+1) entries")
+        self.H = None if H is None else _on(dev, H, torch.float32).clone()
+        self.loss = torch.empty((), dtype=torch.float64, device=dev)
+        self.g_edge = torch.empty(V, dtype=torch.float32, device=dev)
+        self.F = torch.empty_like(self.G)
+        kmax, lmax = (K, L) if band is None else (int(band[0]), int(band[1]))
+        rad = -1.0 if radius is None else float(radius)
+        nb = _step_workspace_size(V, T, K, L, kmax, lmax, rad, _prec(precision))
+        self._ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
+        self._plan = ctypes.c_void_p()
+        vp = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())  # noqa: E731
+        check(h.lib.fcfs_pupil_step_plan(
+            h.ptr, vp(geom.base_x), vp(geom.base_y), vp(geom.s), vp(geom.hedge), vp(geom.vedge),
+            vp(self.offsets), V, T, K, L, kmax, lmax, rad, vp(self.G), vp(self.H),
+            _prec(precision), vp(self.loss), vp(self.g_edge), vp(self.F), vp(self._ws),
+            ctypes.c_size_t(self._ws.numel()), ctypes.byref(self._plan)), h.ptr)
+
+    def run(self, offsets=None):
+        """One step (after copying ``offsets`` in); returns (loss, g_edge)."""
+        h = self.handle
+        h.sync_stream()
+        if offsets is not None:
+            self.offsets.copy_(offsets)
+        check(h.lib.fcfs_step_plan_launch(h.ptr, self._plan), h.ptr)
+        return self.loss, self.g_edge
+
+    def close(self):
+        if self._plan:
+            self.handle.lib.fcfs_step_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 @functools.lru_cache(maxsize=64)

@@ -34,7 +34,8 @@ EXPORTS = (
     "fcfs_general_band_workspace_size", "fcfs_forward_general_band",
     "fcfs_general_adjoint_workspace_size", "fcfs_adjoint_general", "fcfs_apply_edge_offsets_grid",
     "fcfs_pupil_loss_workspace_size", "fcfs_pupil_loss",
-    "fcfs_pupil_step_workspace_size", "fcfs_pupil_step",
+    "fcfs_pupil_step_workspace_size", "fcfs_pupil_step", "fcfs_pupil_step_plan",
+    "fcfs_step_plan_launch", "fcfs_step_plan_destroy",
     "fcfs_adjoint", "fcfs_adjoint_band", "fcfs_edge_grad",
     "fcfs_apply_edge_offsets", "fcfs_batch_workspace_size", "fcfs_forward_batch", "fcfs_plan_destroy",
     "fcfs_debug_phases", "fcfs_autotune", "fcfs_autotune_batch", "fcfs_batch_choice",
@@ -142,6 +143,11 @@ def load() -> ctypes.CDLL:
                                            sz],
         "fcfs_pupil_step": [P, P, P, P, P, P, P, i64, i32, i32, i32, i32, i32, ctypes.c_double,
                             P, P, c_int, P, P, P, P, ctypes.c_size_t],
+        "fcfs_pupil_step_plan": [P, P, P, P, P, P, P, i64, i32, i32, i32, i32, i32,
+                                 ctypes.c_double, P, P, c_int, P, P, P, P, ctypes.c_size_t,
+                                 ctypes.POINTER(P)],
+        "fcfs_step_plan_launch": [P, P],
+        "fcfs_step_plan_destroy": [P],
         "fcfs_haar": [P, ctypes.POINTER(FcfsHaarClip), P, ctypes.c_size_t],
         "fcfs_adjoint": [P, clip_p, P, P, P, c_int, P, ctypes.c_size_t],
         "fcfs_adjoint_band": [P, clip_p, P, i32, i32, ctypes.c_double, P, P, c_int, P,

@@ -20,7 +20,7 @@ using fcfs::Tables;
 
 // Kernel families timed by the profiling hooks.
 enum ProfKind { kProfPrepass = 0, kProfAxis, kProfContract, kProfEpilogue, kProfAdjoint,
-                kProfBatch, kProfFft, kProfHaar, kProfLoss, kProfDirect, kProfKinds };
+                kProfBatch, kProfFft, kProfHaar, kProfLoss, kProfDirect, kProfStep, kProfKinds };
 
 struct fcfs_handle {
   int device = 0;
@@ -66,6 +66,14 @@ struct fcfs_plan {
   fcfs::BatchLaunch launch{};
   hipStream_t cap = nullptr, side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+// A captured optimisation step (fcfs_pupil_step) replayed as one graph.
+struct fcfs_step_plan {
+  int device = 0;
+  hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -1363,6 +1371,84 @@ fcfs_status fcfs_pupil_step(fcfs_handle *h, const int32_t *base_x, const int32_t
   if ((st = fcfs_adjoint_band(h, &c, cot, kmax, lmax, radius, gx, gy, p, sub, q.sub_bytes)))
     return st;
   return fcfs_edge_grad(h, gx, gy, hedge, vedge, V, V, g_edge);
+}
+
+static void step_plan_free(fcfs_step_plan *p) {
+  if (!p) return;
+  (void)hipSetDevice(p->device);
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  delete p;
+}
+
+fcfs_status fcfs_pupil_step_plan(fcfs_handle *h, const int32_t *base_x, const int32_t *base_y,
+                                 const int8_t *s, const int64_t *hedge, const int64_t *vedge,
+                                 const float *offsets, int64_t V, int32_t T, int32_t K, int32_t L,
+                                 int32_t kmax, int32_t lmax, double radius, const float *G,
+                                 const float *H, fcfs_precision p, double *loss, float *g_edge,
+                                 float *F_out, void *ws, size_t ws_bytes, fcfs_step_plan **out) {
+  if (!out) return fail(h, FCFS_ERR_INVALID_ARG, "plan pointer is NULL");
+  *out = nullptr;
+  // one eager step: validates the arguments, does the one-time set-up of the
+  // kernels, and leaves the outputs of the current offsets
+  fcfs_status st = fcfs_pupil_step(h, base_x, base_y, s, hedge, vedge, offsets, V, T, K, L, kmax,
+                                   lmax, radius, G, H, p, loss, g_edge, F_out, ws, ws_bytes);
+  if (st) return st;
+  auto *q = new fcfs_step_plan;
+  q->device = h->device;
+  hipError_t e = hipStreamCreateWithFlags(&q->cap, hipStreamNonBlocking);
+  if (e) {
+    step_plan_free(q);
+    return hip_fail(h, e, "plan stream");
+  }
+  // capture on the plan's own stream (the handle's side stream joins through
+  // the forward's fork and join events); profiling is off meanwhile
+  const hipStream_t saved = h->stream;
+  const bool prof = h->prof;
+  h->prof = false;
+  h->stream = q->cap;
+  if ((e = hipStreamBeginCapture(q->cap, hipStreamCaptureModeThreadLocal))) {
+    h->stream = saved;
+    h->prof = prof;
+    step_plan_free(q);
+    return hip_fail(h, e, "hipStreamBeginCapture");
+  }
+  st = fcfs_pupil_step(h, base_x, base_y, s, hedge, vedge, offsets, V, T, K, L, kmax, lmax, radius,
+                       G, H, p, loss, g_edge, F_out, ws, ws_bytes);
+  e = hipStreamEndCapture(q->cap, &q->graph);
+  h->stream = saved;
+  h->prof = prof;
+  if (st) {
+    step_plan_free(q);
+    return st;
+  }
+  if (e) {
+    step_plan_free(q);
+    return hip_fail(h, e, "hipStreamEndCapture");
+  }
+  if ((e = hipGraphInstantiate(&q->exec, q->graph, nullptr, nullptr, 0))) {
+    step_plan_free(q);
+    return hip_fail(h, e, "hipGraphInstantiate");
+  }
+  *out = q;
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_step_plan_launch(fcfs_handle *h, fcfs_step_plan *plan) {
+  fcfs_status st = enter(h);
+  if (st) return st;
+  if (!plan || !plan->exec) return fail(h, FCFS_ERR_INVALID_ARG, "plan is NULL");
+  if (plan->device != h->device) return fail(h, FCFS_ERR_INVALID_ARG, "plan of another device");
+  ProfScope ps(h, kProfStep);
+  hipError_t e = hipGraphLaunch(plan->exec, h->stream);
+  if (e) return hip_fail(h, e, "hipGraphLaunch");
+  return FCFS_OK;
+}
+
+fcfs_status fcfs_step_plan_destroy(fcfs_step_plan *plan) {
+  step_plan_free(plan);
+  return FCFS_OK;
 }
 
 fcfs_status fcfs_general_adjoint_workspace_size(const fcfs_gclip *c, fcfs_precision p,

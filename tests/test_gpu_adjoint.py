@@ -299,3 +299,37 @@ def test_pupil_step_matches_the_autograd_step(P, prec):
         assert torch.equal(ls, loss.detach())
         assert torch.equal(gs, off.grad)
         _say(f"pupil step {prec} H={'disc' if H is None else 'weights'}: loss {float(ls):.6e}")
+
+
+def test_pupil_step_plan_replays(P):
+    # the captured step replayed with new offsets, eager work and
+    # synchronisations in between: every replay equals the one-call step
+    T, K = 2048, 60
+    r = 0.35 * K
+    rb = int(np.floor(r))
+    clip = synth.clip(46, T, K, n_polygons=150)
+    geom = P.Geometry(clip.xy, clip.off, T, K, check_offsets=False)
+    kk, ll = np.meshgrid(np.arange(-K, K + 1), np.arange(-K, K + 1), indexing="ij")
+    Hn = (kk ** 2 + ll ** 2 <= r * r).astype(np.float32)
+    rng = np.random.default_rng(9)
+    Gt = torch.as_tensor((Hn * (rng.normal(size=kk.shape) + 1j * rng.normal(size=kk.shape)))
+                         .astype(np.complex64)).cuda()
+    offs = [torch.as_tensor(rng.integers(-3, 4, geom.n_edges).astype(np.float32)).cuda()
+            for _ in range(3)]
+    want = []
+    for o in offs:
+        Fw = torch.empty_like(Gt)
+        lw, gw = P.pupil_step(geom, o, Gt, radius=r, band=(rb, rb), F_out=Fw)
+        want.append((lw.clone(), gw.clone(), Fw))
+    plan = P.PupilStep(geom, Gt, radius=r, band=(rb, rb))
+    for it in range(6):
+        i = it % 3
+        loss, g = plan.run(offs[i])
+        torch.cuda.synchronize()
+        _say(f"step plan replay {it}")
+        assert torch.equal(loss, want[i][0]) and torch.equal(g, want[i][1])
+        assert torch.equal(plan.F, want[i][2])
+        junk = torch.randn(1 << 18, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        del junk
+    plan.close()
