@@ -333,3 +333,38 @@ def test_pupil_step_plan_replays(P):
         torch.cuda.synchronize()
         del junk
     plan.close()
+
+
+def test_optimisation_step_full_size_sampled(P, oracle_lib):
+    # the differentiation workload at full size: 100k corners, T = 4096,
+    # |k|,|l| <= 255, pupil of radius 0.35 K, target the pupil-filtered
+    # spectrum of a second clip (from the oracle); the one-call step's edge
+    # gradient on 128 sampled edges against the oracle's analytic gradient
+    T, K = 4096, 255
+    r = 0.35 * K
+    rb = int(np.floor(r))
+    clip = synth.clip(5, T, K, min_vertices=100_000)
+    clip2 = synth.clip(6, T, K, min_vertices=100_000)
+    _say(f"full-size step V={clip.n_vertices} T={T} K={K}")
+    Hp = _pupil(K, K, r)
+    kk, ll = np.nonzero(Hp)
+    Gt = np.zeros_like(Hp, dtype=np.complex128)
+    Gt[kk, ll] = oracle_lib.cfs_points(clip2.xy, clip2.off, T, kk - K, ll - K)
+    Gt = Gt.astype(np.complex64).astype(np.complex128)
+    Fo = np.zeros_like(Gt)
+    Fo[kk, ll] = oracle_lib.cfs_points(clip.xy, clip.off, T, kk - K, ll - K)
+    rng = np.random.default_rng(12)
+    edges = rng.choice(clip.n_vertices, 128, replace=False)
+    want = oracle_lib.edge_grad(clip.xy, clip.off, T, K, K, 2 * Hp * (Hp * Fo - Gt), edges=edges)
+    geom = P.Geometry(clip.xy, clip.off, T, K, check_offsets=False)
+    off = torch.zeros(geom.n_edges, dtype=torch.float32, device="cuda")
+    loss, g = P.pupil_step(geom, off, torch.as_tensor(Gt.astype(np.complex64)).cuda(), radius=r,
+                           band=(rb, rb))
+    torch.cuda.synchronize()
+    got = g.cpu().numpy().astype(np.float64)[edges]
+    e = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+    lo = float(np.sum(np.abs(Hp * Fo - Gt) ** 2))
+    _say(f"  err/max|g| over {edges.size} edges = {e:.3e}; loss rel err "
+         f"{abs(float(loss) - lo) / lo:.2e}")
+    assert e <= GTOL["bf16"]
+    assert abs(float(loss) - lo) <= 1e-4 * lo

@@ -163,3 +163,27 @@ def test_batch_autotuner_on_its_clips(P):
         d = np.max(np.abs(Fs.cpu().numpy() - F[i])) / abs(F[i][K, L])
         assert d <= 2e-6, (i, d)
     b.close()
+
+
+def test_batch_full_size_sampled(P, oracle_lib):
+    # the batching workload at full size: 256 clips, corners log-uniform in
+    # [1k, 200k], (T, K) over {(1024,63),(2048,127),(4096,255),(8192,511)};
+    # sampled coefficients of the 4 smallest, 4 largest and 4 random clips
+    clips = synth.batch_clips(4, n_clips=256)
+    args = _as_args(P, clips)
+    _say(f"full-size batch: {sum(a[0].size for a in args)} corners")
+    b = P.Batch(args, precision="bf16")
+    F = b.run()
+    torch.cuda.synchronize()
+    order = np.argsort([a[0].size for a in args])
+    rng = np.random.default_rng(13)
+    pick = list(order[:4]) + list(order[-4:]) + list(rng.choice(order[4:-4], 4, replace=False))
+    for i in pick:
+        c = clips[i]
+        kk, ll = _sample(c.K, 40, int(i))
+        ref = oracle_lib.cfs_points(c.xy, c.off, c.T, kk, ll)
+        f00 = abs(oracle_lib.cfs_points(c.xy, c.off, c.T, [0], [0])[0])
+        e = float(np.max(np.abs(F[i].cpu().numpy()[kk + c.K, ll + c.L] - ref)) / f00)
+        _say(f"  clip {i}: V={c.n_vertices} T={c.T} K={c.K} err/|F00| = {e:.3e}")
+        assert e <= TOL["bf16"], (i, e)
+    b.close()
