@@ -105,6 +105,19 @@ def host_cpu():
             else None}
 
 
+def streaming_gbps(P, V, T, K, L, breakdown):
+    info = P.plan_info(V, T, K, L, "bf16")
+    vpad = info["nsplit"] * info["chunk"]
+    pre_bytes = 9 * V + 16 * vpad
+    epi_bytes = 16 * info["nsplit"] * K * L + 8 * (2 * K + 1) * (2 * L + 1)
+    out = {"plan": info, "prepass_bytes": pre_bytes, "epilogue_bytes": epi_bytes}
+    if breakdown.get("prepass"):
+        out["prepass"] = pre_bytes / (breakdown["prepass"] * 1e-3) / 1e9
+    if breakdown.get("epilogue"):
+        out["epilogue"] = epi_bytes / (breakdown["epilogue"] * 1e-3) / 1e9
+    return out
+
+
 def step_stats(fn, n: int):
     """Per-step device time of n further steps, each bracketed by events on
     the current stream (every kernel of a step, side stream included, ends
@@ -310,6 +323,11 @@ def main() -> int:
         # per-kind kernel times from separate steps with events on every launch
         # (the side-stream figure spans the histograms, guard block and axis DFTs)
         "kernels_ms": main_leg["breakdown"],
+        # the streaming steps against the 8 TB/s HBM peak: the pre-pass reads
+        # x, y, s (9 B per corner) and writes 16-byte records; the epilogue
+        # reads the four FP32 quadrant partials of every split over the
+        # computed K x L block and writes the complex64 grid
+        "streaming_GBps": streaming_gbps(P, V, T, K, L, main_leg["breakdown"]),
         # 10 further steps timed one by one with events (the paper's protocol
         # of repeated runs): mean +- 95% CI, median
         "step_ms_stats": main_leg["stats"],

@@ -400,6 +400,12 @@ fcfs_status fcfs_load_tune(fcfs_handle *h, const char *cache_path);
  * fcfs_workspace_size_tile is fcfs_workspace_size (forward) for a given
  * variant. */
 int32_t fcfs_tile_variants(int32_t *wk, int32_t *wl, int32_t cap);
+/* The plan fcfs_forward makes for clip `c` at precision `p` with the automatic
+ * tile choice (pointers in `c` are not read): vertex splits, corners per split,
+ * frequency tiles, and whether the one-launch direct form runs instead.  Any
+ * output pointer may be NULL. */
+fcfs_status fcfs_forward_plan_info(const fcfs_clip *c, fcfs_precision p, int32_t *nsplit,
+                                   int64_t *chunk, int32_t *tiles, int32_t *direct);
 fcfs_status fcfs_set_tile(fcfs_handle *h, int32_t variant);
 fcfs_status fcfs_workspace_size_tile(const fcfs_clip *c, fcfs_precision p, int32_t tile,
                                      size_t *bytes);

@@ -86,6 +86,18 @@ def workspace_size(V: int, T: int, K: int, L: int, precision="bf16", adjoint: bo
     return int(n.value)
 
 
+def plan_info(V: int, T: int, K: int, L: int, precision="bf16") -> dict:
+    """The automatic plan of ``forward`` for these sizes (``fcfs_forward_plan_info``):
+    vertex splits, corners per split, frequency tiles, direct form."""
+    lib = load()
+    c = _clip(None, None, None, V, T, K, L)
+    ns, ti, di = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    ch = ctypes.c_int64(0)
+    check(lib.fcfs_forward_plan_info(ctypes.byref(c), _prec(precision), ctypes.byref(ns),
+                                     ctypes.byref(ch), ctypes.byref(ti), ctypes.byref(di)))
+    return {"nsplit": ns.value, "chunk": ch.value, "tiles": ti.value, "direct": bool(di.value)}
+
+
 class Handle:
     """Owns an ``fcfs_handle`` (twiddle tables) on one device."""
 

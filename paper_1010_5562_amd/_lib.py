@@ -39,7 +39,7 @@ EXPORTS = (
     "fcfs_adjoint", "fcfs_adjoint_band", "fcfs_edge_grad",
     "fcfs_apply_edge_offsets", "fcfs_batch_workspace_size", "fcfs_forward_batch", "fcfs_plan_destroy",
     "fcfs_debug_phases", "fcfs_autotune", "fcfs_autotune_batch", "fcfs_batch_choice",
-    "fcfs_load_tune", "fcfs_tile_variants", "fcfs_set_tile",
+    "fcfs_load_tune", "fcfs_tile_variants", "fcfs_set_tile", "fcfs_forward_plan_info",
     "fcfs_workspace_size_tile", "fcfs_profile_begin", "fcfs_profile_end",
     "fcfs_status_string", "fcfs_last_error",
 )
@@ -121,6 +121,8 @@ def load() -> ctypes.CDLL:
         "fcfs_loops_to_corners": [P, P, i64, P, P, P, P, P],
         "fcfs_workspace_size": [clip_p, c_int, c_int, sz],
         "fcfs_workspace_size_tile": [clip_p, c_int, i32, sz],
+        "fcfs_forward_plan_info": [clip_p, c_int, ctypes.POINTER(i32), ctypes.POINTER(i64),
+                                   ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "fcfs_forward": [P, clip_p, c_int, P, ctypes.c_size_t],
         "fcfs_band_workspace_size": [clip_p, i32, i32, ctypes.c_double, c_int, sz],
         "fcfs_forward_band": [P, clip_p, i32, i32, ctypes.c_double, c_int, P, ctypes.c_size_t],

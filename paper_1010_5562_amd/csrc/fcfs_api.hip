@@ -932,6 +932,19 @@ fcfs_status fcfs_workspace_size(const fcfs_clip *c, fcfs_precision p, int adjoin
 }
 
 // Workspace size for an explicit tile variant (autotuning and tests).
+fcfs_status fcfs_forward_plan_info(const fcfs_clip *c, fcfs_precision p, int32_t *nsplit,
+                                   int64_t *chunk, int32_t *tiles, int32_t *direct) {
+  if (!c) return fail(nullptr, FCFS_ERR_INVALID_ARG, "NULL argument");
+  FwdPlan q;
+  fcfs_status st = make_plan(nullptr, c->V, c->T, c->K, c->L, (int)p, -1, &q);
+  if (st) return st;
+  if (nsplit) *nsplit = q.nsplit;
+  if (chunk) *chunk = q.chunk;
+  if (tiles) *tiles = q.tiles_k * q.tiles_l;
+  if (direct) *direct = use_direct(c->V, c->K, c->L) ? 1 : 0;
+  return FCFS_OK;
+}
+
 fcfs_status fcfs_workspace_size_tile(const fcfs_clip *c, fcfs_precision p, int32_t tile,
                                      size_t *bytes) {
   if (!c || !bytes) return fail(nullptr, FCFS_ERR_INVALID_ARG, "NULL argument");
