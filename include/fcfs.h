@@ -256,7 +256,8 @@ fcfs_status fcfs_pupil_step(fcfs_handle *h, const int32_t *base_x, const int32_t
  * step eagerly (argument checks, one-time kernel set-up; the outputs hold its
  * result) and captures the next one on a stream of its own.  Every buffer,
  * the workspace included, must stay allocated and unmoved while the plan
- * lives; fcfs_step_plan_launch replays the step on the handle's stream (same
+ * lives, and so must the handle (the graph reads its twiddle tables);
+ * fcfs_step_plan_launch replays the step on the handle's stream (same
  * device).  The plan owns its graph; fcfs_step_plan_destroy frees it. */
 fcfs_status fcfs_pupil_step_plan(fcfs_handle *h, const int32_t *base_x, const int32_t *base_y,
                                  const int8_t *s, const int64_t *hedge, const int64_t *vedge,
