@@ -210,7 +210,12 @@ def main() -> int:
     L = K
     t0 = time.time()
     clip = synth.clip(3, T, K, min_vertices=200_000)
-    x, y, s, _, _ = P.loops_to_corners(clip.xy, clip.off)
+    # canonicalisation (host, outside the timed region): loops -> signed corner
+    # list and edge maps, timed on its own
+    tc = time.perf_counter()
+    for _ in range(5):
+        x, y, s, _, _ = P.loops_to_corners(clip.xy, clip.off)
+    canon_ms = (time.perf_counter() - tc) / 5 * 1e3
     V = int(x.size)
     pairs = V * (2 * K + 1) * (2 * L + 1)
     log(f"precision clip V={V} polygons={clip.n_loops} T={T} K={K} "
@@ -331,6 +336,9 @@ def main() -> int:
         # 10 further steps timed one by one with events (the paper's protocol
         # of repeated runs): mean +- 95% CI, median
         "step_ms_stats": main_leg["stats"],
+        # host canonicalisation of the clip's loops (validation, signs, edge
+        # maps), not part of the step
+        "canonicalize_host_ms": canon_ms,
         "area_exact": main_leg["area"],
     }
     for prec in ("fp32", "fp16"):
