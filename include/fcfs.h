@@ -416,7 +416,7 @@ fcfs_status fcfs_workspace_size_tile(const fcfs_clip *c, fcfs_precision p, int32
  * every kind) is bracketed by two events; fcfs_profile_end waits for them and
  * writes, for kind i < nkinds, the summed milliseconds ms[i] and the launch
  * count count[i], then stops recording.  Kinds: 0 pre-pass, 1 side-stream
- * work (histograms, guard block, axis DFTs), 2 contraction, 3 epilogue,
+ * work (histograms, guard region, axis DFTs), 2 contraction, 3 epilogue,
  * 4 adjoint kernels, 5 batched graph, 6 lattice form, 7 Haar quadtree walk
  * (the Haar transform's clear-and-plan launches count as pre-pass, its
  * scaling pass as epilogue), 8 pupil loss, 9 direct form of small problems,

@@ -211,7 +211,8 @@ void free_tables(Tables &t) {
 // ---------------------------------------------------------------------------
 constexpr int kMaxFreq = 4095;  // |k|, |l| cut-off limit (phases stay below 2^29)
 constexpr int kCUs = 256;  // compute units of the target GPU (MI355X)
-constexpr int kGuardBlocks = 64;  // most blocks of the guard block's corner split
+constexpr int kGuardBlocks = 64;       // most corner ranges of the guard region
+constexpr int kBatchGuardBlocks = 16;  // the same per clip of a batch
 
 int kbucket(int K) {
   int b = 0;
@@ -243,6 +244,19 @@ fcfs_status check_dims(fcfs_handle *h, int64_t V, int T, int K, int L, int prec)
   return FCFS_OK;
 }
 
+// Guard-span model factor of a plan (guard_span): 2 eps P / (4 pi^2 1e-5)
+// with P = Mx My and eps the per-term rounding of the split contraction,
+// 2^-17.5 for bf16 hi + lo (8 + 8 significant bits) and 2^-21.5 for fp16
+// hi + lo (11 + 11), fitted to the errors measured on low-fill clips.  The
+// FP32 form keeps the core block (its error is set by the FP32
+// accumulation, far inside its bound).
+double guard_scale(int prec, int Mx, int My) {
+  const double eps = prec == fcfs::kBF16 ? std::ldexp(1.0, -17) * std::sqrt(0.5)
+                     : prec == fcfs::kFP16 ? std::ldexp(1.0, -21) * std::sqrt(0.5) : 0.0;
+  const double kPi = 3.14159265358979323846;
+  return 2.0 * eps * (double)Mx * (double)My / (4.0 * kPi * kPi * 1e-5);
+}
+
 // Split count, chunk and workspace layout of a forward plan whose tile grid
 // (kp, lp, tiles_k, tiles_l) is set: one wave of workgroups over the CUs, but
 // at least 512 corners per split.
@@ -263,9 +277,10 @@ void finish_plan(FwdPlan &q, int64_t tiles, int wg_per_cu, int chunk_mult, bool 
   q.ax_fb_k = (int)ceil_div(K, 256);
   q.ax_fb_l = (int)ceil_div(L, 256);
   q.ax_chunks = (int)ceil_div(Tmax, fcfs::kAxisBins);
-  // guard block: at most kGuardBlocks blocks of at least 512 corners
+  // guard region: at most kGuardBlocks corner ranges of at least 512 corners
   q.g_chunk = std::max<int64_t>(512, round_up(ceil_div(V, kGuardBlocks), 64));
   q.g_chunks = (int)std::max<int64_t>(1, ceil_div(V, q.g_chunk));
+  q.gscale = guard_scale(q.prec, q.Mx, q.My);
   size_t off = 0;
   q.off_packed = off;
   off += align256(sizeof(uint4) * (size_t)q.vpad);
@@ -278,10 +293,9 @@ void finish_plan(FwdPlan &q, int64_t tiles, int wg_per_cu, int chunk_mult, bool 
   q.off_part = off;
   if (!lattice) off += align256(sizeof(float) * 4 * (size_t)q.nsplit * (size_t)q.kp * (size_t)q.lp);
   q.off_guard = off;
-  if (!lattice) off += align256(sizeof(double) * fcfs::kGuardD * (size_t)q.g_chunks);
-  q.off_gfinal = off;
-  if (!lattice) off += align256(sizeof(double) * fcfs::kGuardD);
-  q.off_gcount = off;
+  if (!lattice)
+    off += align256(sizeof(double) * fcfs::kGuardD * fcfs::kGuardSlots * (size_t)q.g_chunks);
+  q.off_gspan = off;
   off += 256;
   q.off_fcnt = q.off_flist = q.off_fd = off;
   if (lattice) {
@@ -465,8 +479,7 @@ fcfs_status run_forward(fcfs_handle *h, const fcfs_clip *c, const FwdPlan &p, vo
     ProfScope ps(h, kProfPrepass);
     if ((e = fcfs::launch_prepass(p, c->x, c->y, c->s, ws_at<uint4>(ws, p.off_packed),
                                   ws_at<unsigned long long>(ws, p.off_area),
-                                  ws_at<unsigned long long>(ws, p.off_hist),
-                                  ws_at<unsigned int>(ws, p.off_gcount), h->stream)))
+                                  ws_at<unsigned long long>(ws, p.off_hist), h->stream)))
       return hip_fail(h, e, "pre-pass launch");
   }
   if (side && (e = hipEventRecord(h->ev_fork, h->stream))) return hip_fail(h, e, "fork");
@@ -1028,8 +1041,7 @@ fcfs_status fcfs_forward_fft(fcfs_handle *h, const fcfs_clip *c, void *ws, size_
     ProfScope ps(h, kProfPrepass);
     if ((e = fcfs::launch_prepass(q, c->x, c->y, c->s, ws_at<uint4>(ws, q.off_packed),
                                   ws_at<unsigned long long>(ws, q.off_area),
-                                  ws_at<unsigned long long>(ws, q.off_hist),
-                                  ws_at<unsigned int>(ws, q.off_gcount), h->stream)))
+                                  ws_at<unsigned long long>(ws, q.off_hist), h->stream)))
       return hip_fail(h, e, "pre-pass launch");
   }
   {
@@ -1166,7 +1178,7 @@ fcfs_status fcfs_debug_phases(fcfs_handle *h, const fcfs_clip *c, int32_t axis, 
   if (e) return hip_fail(h, e, "hipMalloc");
   uint4 *packed = (uint4 *)tmp;
   auto *ap = ws_at<unsigned long long>(tmp, align256(sizeof(uint4) * (size_t)q.vpad));
-  if ((e = fcfs::launch_prepass(q, c->x, c->y, c->s, packed, ap, nullptr, nullptr, h->stream)) ||
+  if ((e = fcfs::launch_prepass(q, c->x, c->y, c->s, packed, ap, nullptr, h->stream)) ||
       (e = fcfs::launch_debug_phases(q, packed, axis, k0, nk, p, h->stream)) ||
       (e = hipStreamSynchronize(h->stream))) {
     (void)hipFree(tmp);
@@ -1208,8 +1220,7 @@ fcfs_status fcfs_adjoint_band(fcfs_handle *h, const fcfs_clip *c, const float *g
   hipError_t e;
   ProfScope ps(h, kProfAdjoint);
   if ((e = fcfs::launch_prepass(q, c->x, c->y, c->s, ws_at<uint4>(ws, a.off_packed),
-                                ws_at<unsigned long long>(ws, a.off_area), nullptr, nullptr,
-                                h->stream)))
+                                ws_at<unsigned long long>(ws, a.off_area), nullptr, h->stream)))
     return hip_fail(h, e, "pre-pass launch");
   if ((e = fcfs::launch_adjoint(a, c->x, c->y, c->s, grad_F, h->tab, ws, gx, gy, h->stream)))
     return hip_fail(h, e, "adjoint launch");
@@ -1541,8 +1552,7 @@ constexpr int kBatchPreBlocks = 64;
 // device pointers are filled in once the workspace base is known).
 struct BatchLayout {
   std::vector<fcfs::BatchClip> bc;
-  std::vector<size_t> off_packed, off_area, off_hist, off_axis, off_part, off_guard, off_gfinal,
-      off_gcount;
+  std::vector<size_t> off_packed, off_area, off_hist, off_axis, off_part, off_guard, off_gspan;
   std::vector<int4> ax_desc, items, side_desc;
   std::vector<int> epi_off;
   size_t bytes = 0;
@@ -1562,8 +1572,7 @@ fcfs_status batch_layout(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec
   L->off_axis.assign(n, 0);
   L->off_part.assign(n, 0);
   L->off_guard.assign(n, 0);
-  L->off_gfinal.assign(n, 0);
-  L->off_gcount.assign(n, 0);
+  L->off_gspan.assign(n, 0);
   L->off_hist.assign(n, 0);
   L->side_desc.clear();
   L->ax_desc.clear();
@@ -1597,11 +1606,13 @@ fcfs_status batch_layout(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec
     b.ax_chunks = (int)ceil_div(ci.T, fcfs::kAxisBins);
     for (int fb = 0; fb < fk + fl; ++fb)
       for (int ch = 0; ch < b.ax_chunks; ++ch) L->ax_desc.push_back(make_int4(i, fb, ch, 0));
-    b.g_chunk = std::max<int64_t>(512, round_up(ceil_div(ci.V, kGuardBlocks), 64));
+    b.g_chunk = std::max<int64_t>(512, round_up(ceil_div(ci.V, kBatchGuardBlocks), 64));
     b.g_chunks = (int)std::max<int64_t>(1, ceil_div(ci.V, b.g_chunk));
+    b.gscale = guard_scale(prec, ci.T, ci.T);
     b.hist_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(64, ceil_div(ci.V, 1024)));
     if (ci.K > 0 && ci.L > 0)
-      for (int ch = 0; ch < b.g_chunks; ++ch) L->side_desc.push_back(make_int4(i, 1, ch, 0));
+      for (int ch = 0; ch < fcfs::kGuardGroups * b.g_chunks; ++ch)
+        L->side_desc.push_back(make_int4(i, 1, ch, 0));
     if (ci.K + ci.L > 0)
       for (int hb = 0; hb < b.hist_blocks; ++hb) L->side_desc.push_back(make_int4(i, 0, hb, 0));
     if (ci.K > 0 && ci.L > 0)
@@ -1622,10 +1633,8 @@ fcfs_status batch_layout(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec
     L->off_part[i] = off;
     if (!b.direct) off += align256(sizeof(float) * 4 * (size_t)b.nsplit * (size_t)b.kp * (size_t)b.lp);
     L->off_guard[i] = off;
-    off += align256(sizeof(double) * fcfs::kGuardD * (size_t)b.g_chunks);
-    L->off_gfinal[i] = off;
-    off += align256(sizeof(double) * fcfs::kGuardD);
-    L->off_gcount[i] = off;
+    off += align256(sizeof(double) * fcfs::kGuardD * fcfs::kGuardSlots * (size_t)b.g_chunks);
+    L->off_gspan[i] = off;
     off += 256;
   }
   // longest processing time first; ties keep clip order
@@ -1696,8 +1705,7 @@ fcfs_status build_plan(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec, 
     b.axis_part = ws_at<double2>(ws, L.off_axis[i]);
     b.part = b.direct ? nullptr : ws_at<float>(ws, L.off_part[i]);  // direct: no partials
     b.gpart = ws_at<double>(ws, L.off_guard[i]);
-    b.gfinal = ws_at<double>(ws, L.off_gfinal[i]);
-    b.gcount = ws_at<unsigned int>(ws, L.off_gcount[i]);
+    b.gspan = ws_at<unsigned int>(ws, L.off_gspan[i]);
     b.hist = ws_at<unsigned long long>(ws, L.off_hist[i]);
   }
   fcfs::BatchLaunch &bl = p->launch;

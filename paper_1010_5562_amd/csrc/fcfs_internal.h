@@ -30,8 +30,91 @@ enum Prec { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
 
 // Histogram bins per block of the axis DFTs (partials per frequency: T / kAxisBins).
 constexpr int kAxisBins = 128;
-// The FP64 low-frequency guard block: 16 x 16 sums ([cos; sin] for k, l = 1..8).
+// The FP64 guard region.  Blocks of 8 x 8 frequencies whose sums are taken in
+// FP64 and replace the MFMA values where the 1/(k l) factor of alpha_{k,l}
+// amplifies the contraction's rounding most: the core block k, l = 1..8
+// always, and for a span n > 1 the strips k = 1..8, l <= 8 n and l = 1..8,
+// k <= 8 n next to the axes, plus the block k, l = 9..16 once n reaches
+// kGuardDiagSpan.  Each block holds 16 x 16 sums ([cos; sin] of its 8 k by
+// [cos; sin] of its 8 l).  Slot 0 is the core block, slot g (1 <= g < n) the
+// strip block l = 8 g + 1..8 g + 8, slot kGuardSpanMax - 1 + h (1 <= h < n)
+// the strip block k = 8 h + 1..8 h + 8, slot kGuardSlots - 1 the block 9..16.
+constexpr int kGuard = 8;
+constexpr int kGuardSpanMax = 16;
+constexpr int kGuardDiagSpan = 11;  // 8 n > 81 = 9 x 9
+constexpr int kGuardSlots = 2 * kGuardSpanMax;
 constexpr int kGuardD = 256;
+// The side kernel computes the slots in groups of up to four per corner
+// range (guard_group); groups 0..3 walk the l strip, 4..7 the k strip, group
+// 8 is the block 9..16.
+constexpr int kGuardGroups = 9;
+__host__ __device__ inline bool guarded(int k, int l, int n) {
+  return (k <= kGuard && l <= kGuard * n) || (l <= kGuard && k <= kGuard * n) ||
+         (n >= kGuardDiagSpan && k > kGuard && k <= 2 * kGuard && l > kGuard && l <= 2 * kGuard);
+}
+// Frequency-block offsets (in units of kGuard) of slot j: k = 8 kb + 1..8,
+// l = 8 lb + 1..8.
+__host__ __device__ inline void guard_slot_block(int j, int &kb, int &lb) {
+  if (j < kGuardSpanMax) {
+    kb = 0;
+    lb = j;
+  } else if (j < kGuardSlots - 1) {
+    kb = j - kGuardSpanMax + 1;
+    lb = 0;
+  } else {
+    kb = lb = 1;
+  }
+}
+// Slot j is in use for span n.
+__host__ __device__ inline bool guard_slot_used(int j, int n) {
+  int kb, lb;
+  guard_slot_block(j, kb, lb);
+  return j == kGuardSlots - 1 ? n >= kGuardDiagSpan : (kb > lb ? kb : lb) < n;
+}
+// Slot group g: the first slot's block offsets (kb, lb), whether the group
+// steps along l (else along k) and how many of its slots span n uses.
+struct GuardGroup {
+  int kb, lb, ymove, ns, slot;
+};
+__host__ __device__ inline GuardGroup guard_group(int g, int n) {
+  GuardGroup r;
+  if (g < 4) {
+    r.kb = 0;
+    r.lb = 4 * g;
+    r.ymove = 1;
+    r.ns = n - r.lb;
+    r.slot = r.lb;
+  } else if (g < 8) {
+    r.kb = 4 * (g - 4) + 1;
+    r.lb = 0;
+    r.ymove = 0;
+    r.ns = (kGuardSpanMax < n ? kGuardSpanMax : n) - r.kb;
+    r.slot = kGuardSpanMax - 1 + r.kb;
+  } else {
+    r.kb = r.lb = 1;
+    r.ymove = 1;
+    r.ns = n >= kGuardDiagSpan ? 1 : 0;
+    r.slot = kGuardSlots - 1;
+  }
+  r.ns = r.ns < 0 ? 0 : (r.ns > 4 ? 4 : r.ns);
+  return r;
+}
+// Span of the guard region from a rounding model of the split contraction.
+// Every corner term carries a rounding of about eps (the split table entry and
+// the dropped lo x lo product), so the error of S(k, l) grows like
+// eps sqrt(V); alpha_{k,l} turns it into an error relative to |F[0,0]| of
+// about eps sqrt(V) P / (4 pi^2 |A| k l), P the period area and A the exact
+// polygon area in the same units.  gscale = 2 eps P / (4 pi^2 tol) (a factor 2
+// of margin, tol = 1e-5) is fixed by the plan; the strips are widened until
+// that estimate drops below tol outside them.  gscale = 0 keeps the core block.
+__host__ __device__ inline int guard_span(double gscale, int64_t V, long long A) {
+  if (gscale <= 0.0 || V <= 0) return 1;
+  const double a = A < 0 ? -(double)A : (double)A;
+  if (a <= 0.0) return kGuardSpanMax;
+  const double reach = gscale * sqrt((double)V) / a;  // guard k l below this
+  const double n = ceil(reach / kGuard);
+  return n <= 1.0 ? 1 : (n >= (double)kGuardSpanMax ? kGuardSpanMax : (int)n);
+}
 
 // Device-resident constant tables owned by a handle.
 struct Tables {
@@ -64,22 +147,23 @@ struct FwdPlan {
   int ax_fb_k;       // 256-frequency blocks of the x-axis DFT
   int ax_fb_l;       // and of the y-axis DFT
   int ax_chunks;     // bin chunks of the axis DFTs (partials per frequency)
-  int g_chunks;      // corner chunks (blocks) of the FP64 low-frequency guard block
+  int g_chunks;      // corner chunks (blocks) of the FP64 guard region
   int64_t g_chunk;
-  // workspace offsets (bytes)
-  size_t off_packed, off_area, off_hist, off_axis, off_part, off_guard, off_gfinal, off_gcount,
-      bytes;
+  double gscale;     // guard-span model factor (guard_span; 0: core block only)
+  // workspace offsets (bytes): off_guard holds the guard partials
+  // [chunk][slot][16 x 16], off_gspan the span the side kernel chose
+  size_t off_packed, off_area, off_hist, off_axis, off_part, off_guard, off_gspan, bytes;
   // lattice (FFT) form only: bin counters, corner list, row transforms
   size_t off_fcnt, off_flist, off_fd;
 };
 
 // Kernel launchers (fcfs_kernels.hip).  All enqueue on `st` and return the
 // launch status; `ws` is the workspace laid out by the plan.  The pre-pass
-// also clears the histograms and the guard counter when they are non-NULL.
+// also clears the histograms when they are non-NULL.
 hipError_t launch_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
                           uint4 *packed, unsigned long long *area_part,
-                          unsigned long long *hist, unsigned int *gcount, hipStream_t st);
-// histograms + guard block (unless guard is false), then the axis DFTs
+                          unsigned long long *hist, hipStream_t st);
+// histograms + guard region (unless guard is false), then the axis DFTs
 hipError_t launch_side(const FwdPlan &p, const int32_t *x, const int32_t *y, const double2 *w64,
                        void *ws, hipStream_t st, bool guard = true);
 hipError_t launch_contract(const FwdPlan &p, const uint4 *packed, const Tables &t, float *part,
@@ -95,7 +179,7 @@ hipError_t launch_direct(const FwdPlan &p, const int32_t *x, const int32_t *y, c
                          const double2 *w64, float *F, int64_t *area, hipStream_t st);
 // lattice form of the general term (fcfs_fft.hip): writes F for k, l != 0
 // General tile (periods Mx, My in [2, 8192], any integers): pre-pass into
-// residue records, side-stream work (histograms, FP64 guard block, axis DFTs
+// residue records, side-stream work (histograms, FP64 guard region, axis DFTs
 // with the per-period FP64 tables wx, wy) and the MFMA contraction with the
 // per-period operand tables tx, ty (split or FP32 entries; tx has Mx + 1
 // entries, the last zero).
@@ -177,8 +261,9 @@ struct BatchClip {
   unsigned long long *area_part;
   double2 *axis_part;
   float *part;
-  double *gpart, *gfinal;
-  unsigned int *gcount;
+  double *gpart;        // guard partials [chunk][slot][16 x 16]
+  unsigned int *gspan;  // guard span chosen by the side kernel
+  double gscale;
   unsigned long long *hist;
   int64_t V, vpad, chunk, g_chunk;
   int T, shift, K, L, kp, lp, tiles_l, nsplit;

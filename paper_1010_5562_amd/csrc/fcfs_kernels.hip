@@ -15,8 +15,8 @@ namespace fcfs {
 // Pre-pass: pack corners, exact area.  Corners with index >= V (up to the
 // padded count) become padding records.  The area sum is done modulo 2^64,
 // which is exact whenever the true area fits in int64.  The same launch
-// clears the axis histograms (the 2T bins in use) and the guard block's
-// completion counter for the side-stream kernels that follow.
+// clears the axis histograms (the 2T bins in use) for the side-stream kernels
+// that follow.
 // ---------------------------------------------------------------------------
 constexpr int kHistN = kTabN;  // bins per axis histogram (T <= 8192)
 
@@ -25,8 +25,7 @@ __device__ __forceinline__ void prepass_body(const int32_t *__restrict__ x,
                                              const int8_t *__restrict__ s, int64_t V, int64_t vpad,
                                              int T, int shift, uint4 *__restrict__ packed,
                                              unsigned long long *__restrict__ area_part,
-                                             unsigned long long *__restrict__ hist,
-                                             unsigned int *__restrict__ gcount, int blk,
+                                             unsigned long long *__restrict__ hist, int blk,
                                              int nblk) {
   const uint32_t tmask = (uint32_t)(T - 1);
   unsigned long long acc = 0;
@@ -48,7 +47,6 @@ __device__ __forceinline__ void prepass_body(const int32_t *__restrict__ x,
   if (hist)
     for (int i = blk * 256 + threadIdx.x; i < 2 * T; i += nblk * 256)
       hist[i < T ? i : kHistN + (i - T)] = 0ull;
-  if (gcount && blk == 0 && threadIdx.x == 0) *gcount = 0u;
   // fixed-order block reduction (integer, exact)
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
   __shared__ unsigned long long red[4];
@@ -63,17 +61,15 @@ __global__ __launch_bounds__(256) void k_prepass(const int32_t *__restrict__ x,
                                                  int64_t vpad, int T, int shift,
                                                  uint4 *__restrict__ packed,
                                                  unsigned long long *__restrict__ area_part,
-                                                 unsigned long long *__restrict__ hist,
-                                                 unsigned int *__restrict__ gcount) {
-  prepass_body(x, y, s, V, vpad, T, shift, packed, area_part, hist, gcount, blockIdx.x,
-               gridDim.x);
+                                                 unsigned long long *__restrict__ hist) {
+  prepass_body(x, y, s, V, vpad, T, shift, packed, area_part, hist, blockIdx.x, gridDim.x);
 }
 
 hipError_t launch_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
                           uint4 *packed, unsigned long long *area_part,
-                          unsigned long long *hist, unsigned int *gcount, hipStream_t st) {
+                          unsigned long long *hist, hipStream_t st) {
   hipLaunchKernelGGL(k_prepass, dim3(p.pre_blocks), dim3(256), 0, st, x, y, s, p.V, p.vpad, p.T,
-                     p.shift, packed, area_part, hist, gcount);
+                     p.shift, packed, area_part, hist);
   return hipGetLastError();
 }
 
@@ -90,8 +86,7 @@ __global__ __launch_bounds__(256) void k_gen_prepass(const int32_t *__restrict__
                                                      int64_t vpad, int Mx, int My, uint32_t smask,
                                                      uint4 *__restrict__ packed,
                                                      unsigned long long *__restrict__ area_part,
-                                                     unsigned long long *__restrict__ hist,
-                                                     unsigned int *__restrict__ gcount) {
+                                                     unsigned long long *__restrict__ hist) {
   const int blk = blockIdx.x, nblk = gridDim.x;
   unsigned long long acc = 0;
   for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < vpad; i += (int64_t)nblk * 256) {
@@ -113,7 +108,6 @@ __global__ __launch_bounds__(256) void k_gen_prepass(const int32_t *__restrict__
   if (hist)
     for (int i = blk * 256 + threadIdx.x; i < Mx + My; i += nblk * 256)
       hist[i < Mx ? i : kHistN + (i - Mx)] = 0ull;
-  if (gcount && blk == 0 && threadIdx.x == 0) *gcount = 0u;
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
   __shared__ unsigned long long red[4];
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -126,8 +120,7 @@ hipError_t launch_gen_prepass(const FwdPlan &p, const int32_t *x, const int32_t 
   char *w = (char *)ws;
   hipLaunchKernelGGL(k_gen_prepass, dim3(p.pre_blocks), dim3(256), 0, st, x, y, s, p.V, p.vpad,
                      p.Mx, p.My, smask, (uint4 *)(w + p.off_packed),
-                     (unsigned long long *)(w + p.off_area), (unsigned long long *)(w + p.off_hist),
-                     (unsigned int *)(w + p.off_gcount));
+                     (unsigned long long *)(w + p.off_area), (unsigned long long *)(w + p.off_hist));
   return hipGetLastError();
 }
 
@@ -136,7 +129,7 @@ hipError_t launch_gen_prepass_records(const int32_t *x, const int32_t *y, const 
                                       uint4 *packed, unsigned long long *area_part,
                                       hipStream_t st) {
   hipLaunchKernelGGL(k_gen_prepass, dim3(pre_blocks), dim3(256), 0, st, x, y, s, V, vpad, Mx, My,
-                     0x80008000u, packed, area_part, nullptr, nullptr);
+                     0x80008000u, packed, area_part, nullptr);
   return hipGetLastError();
 }
 
@@ -218,100 +211,201 @@ __global__ __launch_bounds__(256) void k_axis_dft(const unsigned long long *__re
 }
 
 // ---------------------------------------------------------------------------
-// Low-frequency guard block: S(k, l) = sum_v s_v e(k x_v) e(l y_v) for
-// 1 <= k <= 8, 1 <= |l| <= 8 in FP64, replacing the MFMA values there.  The
-// 1/(k l) factor of alpha_{k,l} amplifies any error of the contraction most
-// at these frequencies.
-// It is the same real-trigonometric GEMM as the contraction, restricted to a
-// 16 x 16 block and run on the FP64 matrix cores: rows a_i = cos((i+1) th_x)
-// for i < 8 and sin((i-7) th_x) for i >= 8, columns b_j likewise in th_y with
-// the sign s_v, every value an exact entry of the FP64 table (integer phase).
+// FP64 guard region: S(k, l) = sum_v s_v e(k x_v) e(l y_v) in FP64 for the
+// 8 x 8 frequency blocks of the guard region (the core block k, l = 1..8 and,
+// for a span n > 1, the strips next to the axes), replacing the MFMA values
+// there.  The 1/(k l) factor of alpha_{k,l} amplifies the rounding of the
+// contraction most at these frequencies.  The span follows from a rounding
+// model of the split forms and the exact area (guard_span): clips of high
+// fill keep the core block alone, clips of low fill widen the strips.
+// Each block is the same real-trigonometric GEMM as the contraction,
+// restricted to 16 x 16 and run on the FP64 matrix cores: rows a_i =
+// cos(k_i th_x) for i < 8 and sin(k_{i-8} th_x) for i >= 8 (the block's 8 k),
+// columns b_j likewise in th_y with the sign s_v.
 // v_mfma_f64_16x16x4_f64 takes 4 corners per instruction: lane i + 16 q holds
 // A[i][q] = a_i(v_q) and B[q][i] = s b_i(v_q); D[i][j] is element i / 4 of
 // lane j + 16 (i % 4).
-// Each 256-thread block reduces its corner range to a 16 x 16 partial in a
-// fixed order; the last block to finish (completion counter) adds the block
-// partials in block order, so the result does not depend on scheduling.
+// A lane reads (cos, sin) of its frequency f = 1..8 and of 8 th for both
+// coordinates from the FP64 table (exact integer phases); the strip blocks
+// step from one block to the next by the angle-addition rotation through
+// 8 th in FP64 (at most kGuardSpanMax - 1 steps, a few ulp).
+// Each 256-thread block reduces its corner range to one 16 x 16 partial per
+// slot in use, in a fixed order; the epilogue adds the ranges in order, so the
+// result does not depend on scheduling.
 // ---------------------------------------------------------------------------
-constexpr int kGuard = 8;     // |k|, |l| <= kGuard
-constexpr int kGuardUnroll = 8;
+// Corner groups in flight per wave: the side kernel has to fit in the
+// registers the one-wave-per-SIMD contraction leaves free (about 88 per lane)
+// to run beside it.
+constexpr int kGuardUnroll = 8;     // one block per corner range
+constexpr int kGuardUnrollRot = 1;  // several blocks (rotations)
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// GEN: general-tile records; x phases (f x) mod Mx index wx, y phases wy.
+__device__ __forceinline__ double2 rot(double2 v, double2 r) {
+  return make_double2(v.x * r.x - v.y * r.y, v.y * r.x + v.x * r.y);
+}
+
+// Span of the guard region (block-uniform) from the exact area partials,
+// limited to the strips that reach into |k| <= K or |l| <= L.
+__device__ __forceinline__ int guard_span_block(const unsigned long long *__restrict__ area_part,
+                                                int pre_blocks, int64_t V, double gscale, int K,
+                                                int L) {
+  __shared__ int s_n;
+  if (threadIdx.x < 64) {
+    unsigned long long a = 0;
+#pragma unroll 4
+    for (int b = threadIdx.x; b < pre_blocks; b += 64) a += area_part[b];
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if (threadIdx.x == 0) {
+      const int nmax = (max(K, L) + kGuard - 1) / kGuard;
+      s_n = max(1, min(guard_span(gscale, V, (long long)a), nmax));
+    }
+  }
+  __syncthreads();
+  return s_n;
+}
+
+// Slot group gi of the guard region over corner range blk (guard_group).
+// The group's blocks share one side: the l-strip groups keep the row
+// frequencies k = 1..8 and step the columns along l, the k-strip groups keep
+// l = 1..8 and step the rows along k.
+// GEN: general-tile records (residues); x phases (f x) mod Mx index wx, y
+// phases wy.  Otherwise byte-offset records and the one table wx.
 template <bool GEN = false>
 __device__ __forceinline__ void guard_body(const uint4 *__restrict__ packed,
-                                           const double *__restrict__ w64, int64_t V,
-                                           int64_t g_chunk, int nblk, int blk,
-                                           double *__restrict__ gpart, double *__restrict__ gfinal,
-                                           unsigned int *__restrict__ gcount,
-                                           const double *__restrict__ wy = nullptr, int Mx = 0,
+                                           const double2 *__restrict__ wx, int64_t V,
+                                           int64_t g_chunk, int blk, int gi,
+                                           const unsigned long long *__restrict__ area_part,
+                                           int pre_blocks, double gscale, int K, int L,
+                                           double *__restrict__ gpart,
+                                           unsigned int *__restrict__ gspan,
+                                           const double2 *__restrict__ wy = nullptr, int Mx = 0,
                                            int My = 0) {
   __shared__ double red[4][kGuardD];
-  __shared__ int s_last;
+  const int n =
+      __builtin_amdgcn_readfirstlane(guard_span_block(area_part, pre_blocks, V, gscale, K, L));
+  if (blk == 0 && gi == 0 && threadIdx.x == 0) *gspan = (unsigned int)n;
+  const GuardGroup gg = guard_group(gi, n);
+  const int ns = gg.ns;  // slots of the group in use (block-uniform)
+  if (ns == 0) return;
+  const bool ymove = gg.ymove != 0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, q = lane >> 4;
   const uint32_t f = (uint32_t)(i & 7) + 1u;
-  const int sc = i >> 3;  // 0: cos, 1: sin
+  const uint32_t fx = f + (uint32_t)(kGuard * gg.kb);
+  const uint32_t fy = f + (uint32_t)(kGuard * gg.lb);
+  const bool sn = i >= 8;  // sin row / column
   const int64_t v0 = (int64_t)blk * g_chunk;
   const int64_t v1 = min(V, v0 + g_chunk);
-  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t base = v0 + 4 * wave; base < v1; base += 16 * kGuardUnroll) {
-    double a[kGuardUnroll], b[kGuardUnroll];
+  f64x4 acc[4];
 #pragma unroll
-    for (int u = 0; u < kGuardUnroll; ++u) {
-      const int64_t v = base + 16 * u + q;
-      a[u] = 0.0;
-      b[u] = 0.0;
-      if (v < v1) {
-        const uint4 c = packed[v];
-        uint32_t px, py;
-        if constexpr (GEN) {
-          px = (f * c.x) % (uint32_t)Mx;
-          py = (f * c.y) % (uint32_t)My;
-        } else {
-          px = __umul24(f, c.x >> 3) & (uint32_t)(kTabN - 1);
-          py = __umul24(f, c.y >> 3) & (uint32_t)(kTabN - 1);
+  for (int j = 0; j < 4; ++j) acc[j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  if (ns == 1) {
+    // one block: each lane reads only the entry it feeds (cos or sin)
+    for (int64_t base = v0 + 4 * wave; base < v1; base += 16 * kGuardUnroll) {
+      double ea[kGuardUnroll], eb[kGuardUnroll];
+#pragma unroll
+      for (int u = 0; u < kGuardUnroll; ++u) {
+        const int64_t v = base + 16 * u + q;
+        ea[u] = eb[u] = 0.0;
+        if (v < v1) {
+          const uint4 c = packed[v];
+          uint32_t px, py;
+          if constexpr (GEN) {
+            px = (fx * c.x) % (uint32_t)Mx;
+            py = (fy * c.y) % (uint32_t)My;
+          } else {
+            px = __umul24(fx, c.x >> 3) & (uint32_t)(kTabN - 1);
+            py = __umul24(fy, c.y >> 3) & (uint32_t)(kTabN - 1);
+          }
+          const double *tx = (const double *)wx, *ty = (const double *)(GEN ? wy : wx);
+          ea[u] = tx[2 * px + (sn ? 1 : 0)];
+          const double tb = ty[2 * py + (sn ? 1 : 0)];
+          eb[u] = c.z ? -tb : tb;
         }
-        a[u] = w64[2 * px + sc];
-        const double t = GEN ? wy[2 * py + sc] : w64[2 * py + sc];
-        b[u] = c.z ? -t : t;
+      }
+#pragma unroll
+      for (int u = 0; u < kGuardUnroll; ++u)
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ea[u], eb[u], acc[0], 0, 0, 0);
+    }
+  } else {
+    // several blocks: (cos, sin) of the first and of the 8-step, rotated
+    for (int64_t base = v0 + 4 * wave; base < v1; base += 16 * kGuardUnrollRot) {
+      double2 ex[kGuardUnrollRot], ey[kGuardUnrollRot], e8[kGuardUnrollRot];
+#pragma unroll
+      for (int u = 0; u < kGuardUnrollRot; ++u) {
+        const int64_t v = base + 16 * u + q;
+        ex[u] = ey[u] = make_double2(0.0, 0.0);
+        e8[u] = make_double2(1.0, 0.0);
+        if (v < v1) {
+          const uint4 c = packed[v];
+          uint32_t px, py, p8;
+          if constexpr (GEN) {
+            px = (fx * c.x) % (uint32_t)Mx;
+            py = (fy * c.y) % (uint32_t)My;
+            p8 = ymove ? (8u * c.y) % (uint32_t)My : (8u * c.x) % (uint32_t)Mx;
+          } else {
+            const uint32_t xs = c.x >> 3, ys = c.y >> 3;
+            px = __umul24(fx, xs) & (uint32_t)(kTabN - 1);
+            py = __umul24(fy, ys) & (uint32_t)(kTabN - 1);
+            p8 = (8u * (ymove ? ys : xs)) & (uint32_t)(kTabN - 1);
+          }
+          ex[u] = wx[px];
+          const double2 t = GEN ? wy[py] : wx[py];
+          ey[u] = c.z ? make_double2(-t.x, -t.y) : t;
+          e8[u] = (GEN && ymove) ? wy[p8] : wx[p8];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kGuardUnrollRot; ++u) {
+        double2 a = ex[u], b = ey[u];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (j < ns) {
+            if (j > 0) {
+              if (ymove)
+                b = rot(b, e8[u]);
+              else
+                a = rot(a, e8[u]);
+            }
+            acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(sn ? a.y : a.x, sn ? b.y : b.x, acc[j],
+                                                          0, 0, 0);
+          }
       }
     }
-#pragma unroll
-    for (int u = 0; u < kGuardUnroll; ++u)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
   }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) red[wave][(q + 4 * r) * 16 + i] = acc[r];
-  __syncthreads();
   const int t = threadIdx.x;
-  gpart[(size_t)blk * kGuardD + t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
-  __threadfence();
-  __syncthreads();
-  if (t == 0) s_last = atomicAdd(gcount, 1u) == (unsigned int)(nblk - 1);
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  double sum = 0.0;
-  for (int bb = 0; bb < nblk; ++bb) sum += gpart[(size_t)bb * kGuardD + t];
-  gfinal[t] = sum;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (j >= ns) break;
+    const int slot = gg.slot + j;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[wave][(q + 4 * r) * 16 + i] = acc[j][r];
+    __syncthreads();
+    gpart[((size_t)blk * kGuardSlots + slot) * kGuardD + t] =
+        ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+    __syncthreads();
+  }
 }
 
 // Side-stream kernel of one clip: blocks [0, nh) bin the axis histograms,
-// blocks [nh, nh + g_chunks) compute the guard block.
+// blocks [nh, nh + kGuardGroups g_chunks) compute the guard region (slot
+// group b / g_chunks over corner range b % g_chunks: the core group first).
 __global__ __launch_bounds__(256) void k_side(const int32_t *__restrict__ x,
                                               const int32_t *__restrict__ y,
                                               const uint4 *__restrict__ packed, int64_t V,
                                               int shift, unsigned long long *__restrict__ hist,
-                                              int nh, const double *__restrict__ w64,
+                                              int nh, const double2 *__restrict__ w64,
                                               int64_t g_chunk, int g_chunks,
+                                              const unsigned long long *__restrict__ area_part,
+                                              int pre_blocks, double gscale, int K, int L,
                                               double *__restrict__ gpart,
-                                              double *__restrict__ gfinal,
-                                              unsigned int *__restrict__ gcount) {
+                                              unsigned int *__restrict__ gspan) {
   if ((int)blockIdx.x < nh)
     hist_body(x, y, packed, V, shift, hist, blockIdx.x, nh);
   else
-    guard_body(packed, w64, V, g_chunk, g_chunks, blockIdx.x - nh, gpart, gfinal, gcount);
+    guard_body(packed, w64, V, g_chunk, (blockIdx.x - nh) % g_chunks,
+               (blockIdx.x - nh) / g_chunks, area_part, pre_blocks, gscale, K, L, gpart,
+               gspan);
 }
 
 hipError_t launch_side(const FwdPlan &p, const int32_t *x, const int32_t *y, const double2 *w64,
@@ -320,12 +414,12 @@ hipError_t launch_side(const FwdPlan &p, const int32_t *x, const int32_t *y, con
   const uint4 *packed = (const uint4 *)(w + p.off_packed);
   auto *hist = (unsigned long long *)(w + p.off_hist);
   const int nh = p.K + p.L > 0 ? p.hist_blocks : 0;
-  const int ng = guard && p.K > 0 && p.L > 0 ? p.g_chunks : 0;
+  const int ng = guard && p.K > 0 && p.L > 0 ? kGuardGroups * p.g_chunks : 0;
   if (nh + ng > 0)
     hipLaunchKernelGGL(k_side, dim3(nh + ng), dim3(256), 0, st, x, y, packed, p.V, p.shift, hist,
-                       nh, (const double *)w64, p.g_chunk, p.g_chunks,
-                       (double *)(w + p.off_guard), (double *)(w + p.off_gfinal),
-                       (unsigned int *)(w + p.off_gcount));
+                       nh, w64, p.g_chunk, p.g_chunks, (const unsigned long long *)(w + p.off_area),
+                       p.pre_blocks, p.gscale, p.K, p.L, (double *)(w + p.off_guard),
+                       (unsigned int *)(w + p.off_gspan));
   if (p.K + p.L > 0)
     hipLaunchKernelGGL(k_axis_dft, dim3(p.ax_fb_k + p.ax_fb_l, p.ax_chunks), dim3(256), 0, st,
                        hist, w64, p.T, p.shift, p.K, p.L, p.ax_fb_k,
@@ -339,17 +433,19 @@ __global__ __launch_bounds__(256) void k_gen_side(const int32_t *__restrict__ x,
                                                   const int32_t *__restrict__ y,
                                                   const uint4 *__restrict__ packed, int64_t V,
                                                   unsigned long long *__restrict__ hist, int nh,
-                                                  const double *__restrict__ wx,
-                                                  const double *__restrict__ wy, int Mx, int My,
+                                                  const double2 *__restrict__ wx,
+                                                  const double2 *__restrict__ wy, int Mx, int My,
                                                   int64_t g_chunk, int g_chunks,
+                                                  const unsigned long long *__restrict__ area_part,
+                                                  int pre_blocks, double gscale, int K, int L,
                                                   double *__restrict__ gpart,
-                                                  double *__restrict__ gfinal,
-                                                  unsigned int *__restrict__ gcount) {
+                                                  unsigned int *__restrict__ gspan) {
   if ((int)blockIdx.x < nh)
     hist_body<true>(x, y, packed, V, 0, hist, blockIdx.x, nh);
   else
-    guard_body<true>(packed, wx, V, g_chunk, g_chunks, blockIdx.x - nh, gpart, gfinal, gcount, wy,
-                     Mx, My);
+    guard_body<true>(packed, wx, V, g_chunk, (blockIdx.x - nh) % g_chunks,
+                     (blockIdx.x - nh) / g_chunks, area_part, pre_blocks, gscale, K, L, gpart,
+                     gspan, wy, Mx, My);
 }
 
 __global__ __launch_bounds__(256) void k_gen_axis_dft(const unsigned long long *__restrict__ hist,
@@ -366,12 +462,13 @@ hipError_t launch_gen_side(const FwdPlan &p, const int32_t *x, const int32_t *y,
   const uint4 *packed = (const uint4 *)(w + p.off_packed);
   auto *hist = (unsigned long long *)(w + p.off_hist);
   const int nh = p.K + p.L > 0 ? p.hist_blocks : 0;
-  const int ng = p.K > 0 && p.L > 0 ? p.g_chunks : 0;
+  const int ng = p.K > 0 && p.L > 0 ? kGuardGroups * p.g_chunks : 0;
   if (nh + ng > 0)
     hipLaunchKernelGGL(k_gen_side, dim3(nh + ng), dim3(256), 0, st, x, y, packed, p.V, hist, nh,
-                       (const double *)wx, (const double *)wy, p.Mx, p.My, p.g_chunk, p.g_chunks,
-                       (double *)(w + p.off_guard), (double *)(w + p.off_gfinal),
-                       (unsigned int *)(w + p.off_gcount));
+                       wx, wy, p.Mx, p.My, p.g_chunk, p.g_chunks,
+                       (const unsigned long long *)(w + p.off_area),
+                       p.pre_blocks, p.gscale, p.K, p.L, (double *)(w + p.off_guard),
+                       (unsigned int *)(w + p.off_gspan));
   if (p.K + p.L > 0)
     hipLaunchKernelGGL(k_gen_axis_dft, dim3(p.ax_fb_k + p.ax_fb_l, p.ax_chunks), dim3(256), 0, st,
                        hist, wx, wy, p.Mx, p.My, p.K, p.L, p.ax_fb_k, (double2 *)(w + p.off_axis));
@@ -383,8 +480,9 @@ hipError_t launch_gen_side(const FwdPlan &p, const int32_t *x, const int32_t *y,
 // kernels): the work item unfolds its accumulators into F itself, as the
 // epilogue would (the sum over one split is that split, added to an FP64 zero
 // in the same way), so no quadrant partials are written or read back.  The
-// guard block's entries are left to the epilogue, which writes them from the
-// FP64 sums.  The one-wave-per-SIMD kernel keeps writing partials: with its
+// core guard block's entries are left to the epilogue, which writes them from
+// the FP64 sums; it overwrites the entries of wider guard strips after this
+// kernel.  The one-wave-per-SIMD kernel keeps writing partials: with its
 // 256 accumulators the unfolding does not fit beside them without spills.
 // ---------------------------------------------------------------------------
 struct DirectOut {
@@ -825,14 +923,15 @@ hipError_t launch_contract(const FwdPlan &p, const uint4 *packed, const Tables &
 // F[k, l] = alpha_{k,l} S(k, l) with alpha_{k,l} = -T / (4 pi^2 k l) (Prop. 3),
 // alpha_{k,-l} = -alpha_{k,l}; F[-k,-l] = conj F[k,l] (real signal).
 // Split partials are summed in FP64 in a fixed order.  One launch covers the
-// contraction grid (blocks [0, nmain), the guard block's entries excepted),
-// the axes and DC (the next nax blocks) and the guard block (the last one).
+// contraction grid (blocks [0, nmain), the guard region's entries excepted),
+// the axes and DC (the next nax blocks) and the guard slots (the last
+// kGuardSlots blocks; the span n the side kernel chose says which are used).
 // The output grid and the unfolding (OutGrid, put, store_quad) are shared with
 // the contraction kernels that write single-split clips directly.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void epilogue_body(const float *__restrict__ part, int nsplit, int kp,
                                               int lp, int K, int L, double T, const OutGrid &o,
-                                              int bx, int by) {
+                                              int bx, int by, int gn) {
   // 64 consecutive l per block, 4 threads per l summing splits q, q+4, ...
   __shared__ double4 red[4][64];
   const int t = threadIdx.x & 63, q = threadIdx.x >> 6;
@@ -852,7 +951,7 @@ __device__ __forceinline__ void epilogue_body(const float *__restrict__ part, in
   }
   red[q][t] = make_double4(P, U, R, Q);
   __syncthreads();
-  if (q != 0 || l > L || (k <= kGuard && l <= kGuard)) return;
+  if (q != 0 || l > L || guarded(k, l, gn)) return;
   for (int w = 1; w < 4; ++w) {
     P += red[w][t].x;
     U += red[w][t].y;
@@ -862,17 +961,28 @@ __device__ __forceinline__ void epilogue_body(const float *__restrict__ part, in
   store_quad(o, k, l, T, P, U, R, Q);
 }
 
-// Guard block entries from the final 16 x 16 sums D (row-major):
-// P = D[k-1][l-1], U = D[k-1][8+l-1], R = D[8+k-1][l-1], Q = D[8+k-1][8+l-1].
-__device__ __forceinline__ void guard_store(const double *__restrict__ gfinal, int K, int L,
-                                            double T, const OutGrid &o) {
+// Entries of guard slot j (span gn): the 16 x 16 sums D (row-major) are the
+// corner-range partials added in range order; the block's a-th k and b-th l
+// take P = D[a][b], U = D[a][8+b], R = D[8+a][b], Q = D[8+a][8+b].
+__device__ __forceinline__ void guard_store(const double *__restrict__ gpart, int g_chunks,
+                                            int gn, int K, int L, double T, const OutGrid &o,
+                                            int j) {
+  if (!guard_slot_used(j, gn)) return;
+  __shared__ double d[kGuardD];
   const int t = threadIdx.x;
+  double sum = 0.0;
+#pragma unroll 16
+  for (int c = 0; c < g_chunks; ++c) sum += gpart[((size_t)c * kGuardSlots + j) * kGuardD + t];
+  d[t] = sum;
+  __syncthreads();
   if (t >= kGuard * kGuard) return;
-  const int k = 1 + t / kGuard, l = 1 + t % kGuard;
+  const int a = t / kGuard, b = t % kGuard;
+  int kb, lb;
+  guard_slot_block(j, kb, lb);
+  const int k = kGuard * kb + 1 + a, l = kGuard * lb + 1 + b;
   if (k > K || l > L) return;
-  const double *d = gfinal;
-  store_quad(o, k, l, T, d[(k - 1) * 16 + (l - 1)], d[(k - 1) * 16 + 8 + (l - 1)],
-             d[(8 + k - 1) * 16 + (l - 1)], d[(8 + k - 1) * 16 + 8 + (l - 1)]);
+  store_quad(o, k, l, T, d[a * 16 + b], d[a * 16 + 8 + b], d[(8 + a) * 16 + b],
+             d[(8 + a) * 16 + 8 + b]);
 }
 
 // Axis entries (Steps 2, 3) and DC (Step 1):
@@ -933,7 +1043,9 @@ __device__ __forceinline__ void epilogue_block(const float *__restrict__ part, i
                                                const double2 *__restrict__ axis_part,
                                                int ax_chunks,
                                                const unsigned long long *__restrict__ area_part,
-                                               int pre_blocks, const double *__restrict__ gfinal,
+                                               int pre_blocks, const double *__restrict__ gpart,
+                                               int g_chunks,
+                                               const unsigned int *__restrict__ gspan,
                                                const OutGrid &o, int64_t *__restrict__ area,
                                                int b, bool direct = false) {
   const bool grid2d = K > 0 && L > 0;
@@ -941,17 +1053,17 @@ __device__ __forceinline__ void epilogue_block(const float *__restrict__ part, i
   const int nmain = grid2d && !direct ? nbx * K : 0;
   const int nax = max(1, (K + L + 15) / 16);
   if (b < nmain)
-    epilogue_body(part, nsplit, kp, lp, K, L, T, o, b % nbx, b / nbx);
+    epilogue_body(part, nsplit, kp, lp, K, L, T, o, b % nbx, b / nbx, (int)*gspan);
   else if (b < nmain + nax)
     epilogue_axes_body(axis_part, ax_chunks, K, L, T, area_part, pre_blocks, o, area, b - nmain);
   else if (grid2d)
-    guard_store(gfinal, K, L, T, o);
+    guard_store(gpart, g_chunks, (int)*gspan, K, L, T, o, b - nmain - nax);
 }
 
 int epilogue_block_count(int K, int L, bool direct) {
   const int nmain = K > 0 && L > 0 && !direct ? ((L + 63) / 64) * K : 0;
   const int nax = std::max(1, (K + L + 15) / 16);
-  return nmain + nax + (K > 0 && L > 0 ? 1 : 0);
+  return nmain + nax + (K > 0 && L > 0 ? kGuardSlots : 0);
 }
 
 __global__ __launch_bounds__(256) void k_epilogue(const float *__restrict__ part, int nsplit,
@@ -960,10 +1072,11 @@ __global__ __launch_bounds__(256) void k_epilogue(const float *__restrict__ part
                                                   int ax_chunks,
                                                   const unsigned long long *__restrict__ area_part,
                                                   int pre_blocks,
-                                                  const double *__restrict__ gfinal,
+                                                  const double *__restrict__ gpart, int g_chunks,
+                                                  const unsigned int *__restrict__ gspan,
                                                   OutGrid o, int64_t *__restrict__ area) {
   epilogue_block(part, nsplit, kp, lp, K, L, T, axis_part, ax_chunks, area_part, pre_blocks,
-                 gfinal, o, area, blockIdx.x);
+                 gpart, g_chunks, gspan, o, area, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_epilogue_axes(const double2 *__restrict__ axis_part,
@@ -993,7 +1106,8 @@ hipError_t launch_epilogue(const FwdPlan &p, const void *ws, float *F, int64_t *
                      (const float *)(w + p.off_part), p.nsplit, p.kp, p.lp, p.K, p.L, (double)p.T,
                      (const double2 *)(w + p.off_axis), p.ax_chunks,
                      (const unsigned long long *)(w + p.off_area), p.pre_blocks,
-                     (const double *)(w + p.off_gfinal), o, area);
+                     (const double *)(w + p.off_guard), p.g_chunks,
+                     (const unsigned int *)(w + p.off_gspan), o, area);
   return hipGetLastError();
 }
 
@@ -1190,21 +1304,24 @@ __global__ void k_batch_reset(unsigned int *counter) {
 
 __global__ __launch_bounds__(256) void k_batch_prepass(const BatchClip *__restrict__ clips) {
   const BatchClip &c = clips[blockIdx.y];
-  prepass_body(c.x, c.y, c.s, c.V, c.vpad, c.T, c.shift, c.packed, c.area_part, c.hist, c.gcount,
+  prepass_body(c.x, c.y, c.s, c.V, c.vpad, c.T, c.shift, c.packed, c.area_part, c.hist,
                blockIdx.x, gridDim.x);
 }
 
 // Side-stream blocks of a batch, one descriptor each: (clip, 0, b) bins
-// histogram block b of the clip, (clip, 1, b) computes its guard block b.
+// histogram block b of the clip, (clip, 1, b) its guard block b (slot group
+// b / g_chunks over corner range b % g_chunks).
 __global__ __launch_bounds__(256) void k_batch_side(const BatchClip *__restrict__ clips,
                                                     const int4 *__restrict__ desc,
-                                                    const double *__restrict__ w64) {
+                                                    const double2 *__restrict__ w64,
+                                                    int pre_blocks) {
   const int4 d = desc[blockIdx.x];
   const BatchClip &c = clips[d.x];
   if (d.y == 0)
     hist_body(c.x, c.y, c.packed, c.V, c.shift, c.hist, d.z, c.hist_blocks);
   else
-    guard_body(c.packed, w64, c.V, c.g_chunk, c.g_chunks, d.z, c.gpart, c.gfinal, c.gcount);
+    guard_body(c.packed, w64, c.V, c.g_chunk, d.z % c.g_chunks, d.z / c.g_chunks, c.area_part,
+               pre_blocks, c.gscale, c.K, c.L, c.gpart, c.gspan);
 }
 
 __global__ __launch_bounds__(256) void k_batch_axis(const BatchClip *__restrict__ clips,
@@ -1299,7 +1416,8 @@ __global__ __launch_bounds__(256) void k_batch_epilogue(const BatchClip *__restr
   const BatchClip &c = clips[ci];
   const OutGrid o{c.F, c.K, c.L, -1.0, (double)c.T, 1.0, 1.0, 1.0 / (double)c.T};
   epilogue_block(c.part, c.nsplit, c.kp, c.lp, c.K, c.L, (double)c.T, c.axis_part, c.ax_chunks,
-                 c.area_part, pre_blocks, c.gfinal, o, c.area, blockIdx.x - off[ci], c.direct != 0);
+                 c.area_part, pre_blocks, c.gpart, c.g_chunks, c.gspan, o, c.area,
+                 blockIdx.x - off[ci], c.direct != 0);
 }
 
 hipError_t launch_batch_prepass(const BatchLaunch &b, hipStream_t st) {
@@ -1311,7 +1429,7 @@ hipError_t launch_batch_prepass(const BatchLaunch &b, hipStream_t st) {
 hipError_t launch_batch_side(const BatchLaunch &b, const double2 *w64, hipStream_t st) {
   if (b.n_side > 0)
     hipLaunchKernelGGL(k_batch_side, dim3(b.n_side), dim3(256), 0, st, b.clips, b.side_desc,
-                       (const double *)w64);
+                       w64, b.pre_blocks);
   if (b.n_ax > 0)
     hipLaunchKernelGGL(k_batch_axis, dim3(b.n_ax), dim3(256), 0, st, b.clips, b.ax_desc, w64);
   return hipGetLastError();

@@ -67,6 +67,31 @@ def test_batch_matches_oracle(P, oracle_lib, prec):
     b.close()
 
 
+def test_batch_low_fill_clips_near_axes(P, oracle_lib):
+    # low-fill clips (disjoint cells) beside a dense one in one batch: every
+    # coefficient with |k l| <= 160 meets the split bound, so the guard region
+    # of each clip widened by itself; two replays give the same values
+    cs = [synth.clip(22, 4096, 255, n_polygons=2000, disjoint=True),
+          synth.clip(41, 2048, 127, n_polygons=300, disjoint=True),
+          synth.clip(3, 1024, 63, n_polygons=400)]
+    _say(f"low-fill batch V = {[c.n_vertices for c in cs]}")
+    b = P.Batch(_as_args(P, cs), precision="bf16")
+    F1 = [f.cpu().numpy().copy() for f in b.run()]
+    F2 = [f.cpu().numpy() for f in b.run()]
+    for i, c in enumerate(cs):
+        pts = [(k, l) for k in range(-c.K, c.K + 1) for l in range(-c.L, c.L + 1)
+               if k and l and abs(k * l) <= 160]
+        kk, ll = np.array(pts).T
+        ref = oracle_lib.cfs_points(c.xy, c.off, c.T, kk, ll)
+        f00 = abs(oracle_lib.cfs_points(c.xy, c.off, c.T, [0], [0])[0])
+        e = np.abs(F1[i][kk + c.K, ll + c.L] - ref) / f00
+        w = int(np.argmax(e))
+        _say(f"  clip {i}: max err/|F00| = {e[w]:.3e} at ({kk[w]},{ll[w]})")
+        assert e[w] <= TOL["bf16"], (i, e[w])
+        assert np.array_equal(F1[i], F2[i])
+    b.close()
+
+
 def test_batch_equals_single_clip_and_replays(P):
     clips = _clips(8, 6)
     args = _as_args(P, clips)

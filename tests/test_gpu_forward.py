@@ -240,6 +240,38 @@ def test_disjoint_low_fill_clip(P, oracle_lib, prec):
     assert e <= TOL[prec]
 
 
+def _hyperbola_points(K, L, kl_max):
+    # every (k, l) with k, l != 0 and |k l| <= kl_max inside the grid: where
+    # the 1/(k l) factor of alpha amplifies the contraction's rounding most
+    pts = [(k, l) for k in range(-K, K + 1) for l in range(-L, L + 1)
+           if k and l and abs(k * l) <= kl_max]
+    a = np.array(pts)
+    return a[:, 0], a[:, 1]
+
+
+@pytest.mark.parametrize("case", ["layout", "precision"])
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_disjoint_low_fill_near_axes(P, oracle_lib, prec, case):
+    # low-fill clips checked on every coefficient with |k l| <= 160 (both
+    # strips next to the axes and the low corner), against the bound 1e-5
+    # |F[0,0]| of the split forms: the guard region has to widen here
+    if case == "layout":
+        T, K = 4096, 255
+        clip = synth.clip(22, T, K, n_polygons=2000, disjoint=True)
+    else:
+        T, K = 8192, 511
+        clip = synth.clip(33, T, K, min_vertices=200_000, disjoint=True)
+    kk, ll = _hyperbola_points(K, K, 160)
+    _say(f"disjoint {case} clip V={clip.n_vertices} T={T} K={K} prec={prec}, {kk.size} points")
+    ref = oracle_lib.cfs_points(clip.xy, clip.off, T, kk, ll)
+    f00 = oracle_lib.cfs_points(clip.xy, clip.off, T, [0], [0])[0]
+    F, a = _run(P, *_corners(P, clip), T, K, K, prec)
+    err = np.abs(F[kk + K, ll + K] - ref) / abs(f00)
+    w = int(np.argmax(err))
+    _say(f"  fill {abs(f00) * T / T**2:.3f}, max err/|F00| = {err[w]:.3e} at ({kk[w]},{ll[w]})")
+    assert err[w] <= TOL[prec]
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_band_forward(P, oracle_lib, prec):
     # low-pass forward: |k| <= kmax, |l| <= lmax, optionally k^2 + l^2 <= r^2;

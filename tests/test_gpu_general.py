@@ -285,3 +285,23 @@ def test_general_pipelined_and_eight_wave_kernels(P, oracle_lib, Nx, Ny, F, K, L
              f"err/|F00| = {e:.3e}")
         assert e <= TOL[prec]
     assert out[False][1] == out[True][1]
+
+
+def test_general_low_fill_clip_near_axes(P, oracle_lib):
+    # polygons in disjoint cells on a 4000 x 3000 tile with half-unit corners:
+    # every coefficient with |k l| <= 160 (where the guard region widens on
+    # low-fill clips) meets the split bound
+    Nx, Ny, F, K = 4000, 3000, 1, 255
+    clip = synth.clip(22, 8000, K, n_polygons=2000, disjoint=True)
+    xy = clip.xy.astype(np.float64) / 2
+    pts = [(k, l) for k in range(-K, K + 1) for l in range(-K, K + 1)
+           if k and l and abs(k * l) <= 160]
+    kk, ll = np.array(pts).T
+    ref = oracle_lib.cfs_points_general(xy, clip.off, Nx, Ny, kk, ll, frac_bits=F)
+    f00 = abs(oracle_lib.cfs_points_general(xy, clip.off, Nx, Ny, [0], [0], frac_bits=F)[0])
+    for prec in ("bf16", "fp16"):
+        Fg, _ = _gpu(P, clip.xy, clip.off, Nx, Ny, K, K, F, prec)
+        e = np.abs(Fg[kk + K, ll + K] - ref) / f00
+        w = int(np.argmax(e))
+        _say(f"general low-fill clip {prec}: max err/|F00| = {e[w]:.3e} at ({kk[w]},{ll[w]})")
+        assert e[w] <= TOL[prec]
