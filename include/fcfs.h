@@ -155,7 +155,12 @@ fcfs_status fcfs_forward_fft(fcfs_handle *h, const fcfs_clip *c, void *ws, size_
  * w_y = 2 pi / Ny), and corners may sit on the finer grid of step 2^-F
  * (F = frac_bits; F = 0 is the integer lattice of Sec. II-A2): x[v], y[v] are
  * the coordinates times 2^F.  The phases k x / Nx are reduced exactly modulo
- * Mx = Nx 2^F (likewise My); Mx and My must lie in [2, 8192].  Output as
+ * Mx = Nx 2^F (likewise My); Mx and My must lie in [2, 2^24].  Periods up to
+ * 8192 use one table entry per residue; past 8192 the twiddle is the product
+ * of two table entries, e(2 pi p / M) = Whi[p >> 12] Wlo[p mod 4096] (a
+ * two-level twiddle for fine sub-lattice grids), the phase being reduced
+ * exactly in FP64, and the axis sums are taken over the corners
+ * directly instead of over residue histograms.  Output as
  * fcfs_forward with alpha_{k,l} = -sqrt(Nx Ny)/(4 pi^2 k l),
  * alpha_{k,0} = j sqrt(Nx/Ny)/(2 pi k), alpha_{0,l} = j sqrt(Ny/Nx)/(2 pi l),
  * F[0,0] = area / sqrt(Nx Ny); `area` receives sum_v s_v x[v] y[v] (the area
@@ -174,14 +179,16 @@ typedef struct {
 } fcfs_gclip;
 
 /* Workspace of fcfs_forward_general (256-byte aligned).  FCFS_ERR_UNSUPPORTED
- * when Nx 2^F or Ny 2^F is outside [2, 8192], F > 13 or K, L > 4095. */
+ * when Nx 2^F or Ny 2^F is outside [2, 2^24], F > 13 or K, L > 4095. */
 fcfs_status fcfs_general_workspace_size(const fcfs_gclip *c, fcfs_precision p, size_t *bytes);
 /* Forward transform of a general tile: pre-pass (residues, area), axis sums
  * and FP64 low-frequency block on the side stream, MFMA contraction with
  * exact phases (f x) mod M, epilogue with the alpha factors above.  The split
  * precisions run a software-pipelined contraction kernel (one wave per SIMD);
  * FP32, or a handle with a tile variant forced by fcfs_set_tile, an eight-wave
- * kernel.  The workspace size covers either. */
+ * kernel; periods past 8192 an eight-wave kernel on two-level tables (the
+ * split entries rounded from the FP32 product in the kernel).  The workspace
+ * size covers either. */
 fcfs_status fcfs_forward_general(fcfs_handle *h, const fcfs_gclip *c, fcfs_precision p, void *ws,
                                  size_t ws_bytes);
 /* Low-pass form of fcfs_forward_general (the pupil of the lithography use in
@@ -203,7 +210,8 @@ fcfs_status fcfs_forward_general_band(fcfs_handle *h, const fcfs_gclip *c, int32
  * x[v] / 2^frac_bits.  grad_F, band (kmax, lmax) and radius as in
  * fcfs_adjoint_band.  ws: at least fcfs_general_adjoint_workspace_size bytes,
  * 256-byte aligned.  Uses the per-period tables of the handle (built on first
- * use, as for the forward). */
+ * use, as for the forward).  Periods Mx, My up to 8192 only:
+ * FCFS_ERR_UNSUPPORTED past that (the two-level tables serve the forward). */
 fcfs_status fcfs_general_adjoint_workspace_size(const fcfs_gclip *c, fcfs_precision p,
                                                 size_t *bytes);
 fcfs_status fcfs_adjoint_general(fcfs_handle *h, const fcfs_gclip *c, const float *grad_F,

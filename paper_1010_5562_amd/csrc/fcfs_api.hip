@@ -45,6 +45,7 @@ struct fcfs_handle {
   // per-period tables of the general-tile path, built on first use
   struct GenTab {
     int N = 0;
+    int nh = 0;  // > 0: two-level table (nh entries of Whi, then Wlo)
     double2 *w64 = nullptr;
     float2 *w32 = nullptr;
     uint2 *wbf16 = nullptr, *wfp16 = nullptr;
@@ -276,7 +277,10 @@ void finish_plan(FwdPlan &q, int64_t tiles, int wg_per_cu, int chunk_mult, bool 
   q.hist_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(256, ceil_div(V, 1024)));
   q.ax_fb_k = (int)ceil_div(K, 256);
   q.ax_fb_l = (int)ceil_div(L, 256);
-  q.ax_chunks = (int)ceil_div(Tmax, fcfs::kAxisBins);
+  // axis partials: bin chunks of the histograms, or corner ranges of the
+  // direct sums of a two-level plan
+  q.ax_chunks = q.big ? (int)std::max<int64_t>(1, std::min<int64_t>(256, ceil_div(V, 512)))
+                      : (int)ceil_div(Tmax, fcfs::kAxisBins);
   // guard region: at most kGuardBlocks corner ranges of at least 512 corners
   q.g_chunk = std::max<int64_t>(512, round_up(ceil_div(V, kGuardBlocks), 64));
   q.g_chunks = (int)std::max<int64_t>(1, ceil_div(V, q.g_chunk));
@@ -565,21 +569,58 @@ fcfs_status build_gen_table(fcfs_handle *h, int N, fcfs_handle::GenTab *out) {
   return FCFS_OK;
 }
 
+// Two-level tables of a period N (2 <= N <= 2^24): Whi[j] = (cos, sin)(2 pi j
+// kBigLo / N) for j < big_hi(N), then Wlo[i] = (cos, sin)(2 pi i / N) for
+// i < kBigLo, in FP64 and rounded to FP32 (the contraction's operands).
+fcfs_status build_big_table(fcfs_handle *h, int N, fcfs_handle::GenTab *out) {
+  const int nh = fcfs::big_hi(N), n = nh + fcfs::kBigLo;
+  std::vector<double2> w64(n);
+  std::vector<float2> w32(n);
+  for (int i = 0; i < n; ++i) {
+    const double p = i < nh ? (double)i * fcfs::kBigLo : (double)(i - nh);
+    const double a = 2.0 * M_PI * std::fmod(p, (double)N) / (double)N;
+    double c = std::cos(a), sn = std::sin(a);
+    c = c == 0.0 ? 0.0 : c;
+    sn = sn == 0.0 ? 0.0 : sn;
+    w64[i] = make_double2(c, sn);
+    w32[i] = make_float2((float)c, (float)sn);
+  }
+  fcfs_handle::GenTab t;
+  t.N = N;
+  t.nh = nh;
+  hipError_t e;
+  if ((e = hipMalloc(&t.w64, sizeof(double2) * n)) || (e = hipMalloc(&t.w32, sizeof(float2) * n))) {
+    (void)hipFree(t.w64);
+    (void)hipFree(t.w32);
+    return hip_fail(h, e, "hipMalloc");
+  }
+  if ((e = hipMemcpy(t.w64, w64.data(), sizeof(double2) * n, hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(t.w32, w32.data(), sizeof(float2) * n, hipMemcpyHostToDevice))) {
+    (void)hipFree(t.w64);
+    (void)hipFree(t.w32);
+    return hip_fail(h, e, "hipMemcpy");
+  }
+  *out = t;
+  return FCFS_OK;
+}
+
 // The tables of both periods of a call (copies of the cache entries).  When
 // the cache is full, the oldest entry that this call does not use is dropped,
 // after the device has drained.
+// big: two-level tables (a cache entry is one period in one form).
 fcfs_status gen_tables(fcfs_handle *h, int Mx, int My, fcfs_handle::GenTab *tx,
-                       fcfs_handle::GenTab *ty) {
+                       fcfs_handle::GenTab *ty, bool big = false) {
+  auto match = [big](const fcfs_handle::GenTab &t, int N) { return t.N == N && (t.nh > 0) == big; };
   for (int N : {Mx, My}) {
     bool have = false;
-    for (const auto &t : h->gen_tabs) have = have || t.N == N;
+    for (const auto &t : h->gen_tabs) have = have || match(t, N);
     if (have) continue;
     if ((int)h->gen_tabs.size() >= kGenMaxTabs) {
       hipError_t e = hipDeviceSynchronize();
       if (e) return hip_fail(h, e, "hipDeviceSynchronize");
       for (size_t i = 0; i < h->gen_tabs.size(); ++i) {
         auto &t = h->gen_tabs[i];
-        if (t.N == Mx || t.N == My) continue;
+        if (match(t, Mx) || match(t, My)) continue;
         (void)hipFree(t.w64);
         (void)hipFree(t.w32);
         (void)hipFree(t.wbf16);
@@ -589,13 +630,13 @@ fcfs_status gen_tables(fcfs_handle *h, int Mx, int My, fcfs_handle::GenTab *tx,
       }
     }
     fcfs_handle::GenTab t;
-    fcfs_status st = build_gen_table(h, N, &t);
+    fcfs_status st = big ? build_big_table(h, N, &t) : build_gen_table(h, N, &t);
     if (st) return st;
     h->gen_tabs.push_back(t);
   }
   for (const auto &t : h->gen_tabs) {
-    if (t.N == Mx) *tx = t;
-    if (t.N == My) *ty = t;
+    if (match(t, Mx)) *tx = t;
+    if (match(t, My)) *ty = t;
   }
   return FCFS_OK;
 }
@@ -614,8 +655,8 @@ fcfs_status make_plan_general(fcfs_handle *h, const fcfs_gclip *c, int prec, Fwd
     return fail(h, FCFS_ERR_UNSUPPORTED, "frac_bits must be in [0, 13]");
   if (c->Nx < 1 || c->Ny < 1) return fail(h, FCFS_ERR_INVALID_ARG, "Nx, Ny must be >= 1");
   const int64_t Mx = (int64_t)c->Nx << c->frac_bits, My = (int64_t)c->Ny << c->frac_bits;
-  if (Mx < 2 || My < 2 || Mx > fcfs::kTabN || My > fcfs::kTabN)
-    return fail(h, FCFS_ERR_UNSUPPORTED, "Nx 2^frac_bits and Ny 2^frac_bits must be in [2, 8192]");
+  if (Mx < 2 || My < 2 || Mx > fcfs::kBigMaxPeriod || My > fcfs::kBigMaxPeriod)
+    return fail(h, FCFS_ERR_UNSUPPORTED, "Nx 2^frac_bits and Ny 2^frac_bits must be in [2, 2^24]");
   if (c->K < 0 || c->L < 0) return fail(h, FCFS_ERR_INVALID_ARG, "K and L must be >= 0");
   if (c->K > kMaxFreq || c->L > kMaxFreq) return fail(h, FCFS_ERR_UNSUPPORTED, "K, L must be <= 4095");
   if (prec < 0 || prec > 2) return fail(h, FCFS_ERR_INVALID_ARG, "unknown precision");
@@ -631,8 +672,13 @@ fcfs_status make_plan_general(fcfs_handle *h, const fcfs_gclip *c, int prec, Fwd
   q.r2 = r2;
   q.V = c->V;
   q.shift = 0;
+  // periods past the LDS tables: two-level twiddles, eight-wave kernel only
+  q.big = Mx > fcfs::kTabN || My > fcfs::kTabN;
+  q.nhx = q.big ? fcfs::big_hi(Mx) : 0;
+  q.nhy = q.big ? fcfs::big_hi(My) : 0;
   if (variant < 0)
     variant = prec != fcfs::kFP32 && !(h && h->tile_override >= 0) ? fcfs::kGenPipeTile : 0;
+  if (q.big) variant = 0;
   q.tile = prec != fcfs::kFP32 && variant == fcfs::kGenPipeTile ? fcfs::kGenPipeTile : 0;
   // alpha of Prop. 3 for the tile Nx x Ny, with sums taken in grid units
   // (coordinates 2^F times the true ones, periods Mx, My): 2^-F sqrt(Mx My)
@@ -660,7 +706,7 @@ fcfs_status make_plan_general(fcfs_handle *h, const fcfs_gclip *c, int prec, Fwd
   // eight-wave kernel: one workgroup per CU when both tables fill the LDS,
   // else two; pipelined kernel: one workgroup of four waves per CU
   const bool pipe = q.tile == fcfs::kGenPipeTile;
-  const int wpc = !pipe && (Mx + 1 + (Mx == My ? 0 : My)) * 8 <= 80 * 1024 ? 2 : 1;
+  const int wpc = q.big ? 1 : !pipe && (Mx + 1 + (Mx == My ? 0 : My)) * 8 <= 80 * 1024 ? 2 : 1;
   finish_plan(q, tiles, wpc, pipe ? 32 : 16, false);
   *p = q;
   return FCFS_OK;
@@ -683,7 +729,7 @@ fcfs_status general_ws_bytes(const fcfs_gclip *c, int prec, int kmax, int lmax, 
 
 fcfs_status run_forward_general(fcfs_handle *h, const fcfs_gclip *c, const FwdPlan &p, void *ws) {
   fcfs_handle::GenTab gx, gy;
-  fcfs_status st = gen_tables(h, p.Mx, p.My, &gx, &gy);
+  fcfs_status st = gen_tables(h, p.Mx, p.My, &gx, &gy, p.big != 0);
   if (st) return st;
   const fcfs_handle::GenTab *tx = &gx, *ty = &gy;
   hipError_t e;
@@ -697,7 +743,7 @@ fcfs_status run_forward_general(fcfs_handle *h, const fcfs_gclip *c, const FwdPl
   if (side && (e = hipEventRecord(h->ev_fork, h->stream))) return hip_fail(h, e, "fork");
   if (grid2d) {
     const void *ox, *oy;
-    switch (p.prec) {
+    switch (p.big ? fcfs::kFP32 : p.prec) {
       case fcfs::kFP32: ox = tx->w32; oy = ty->w32; break;
       case fcfs::kBF16: ox = tx->wbf16; oy = ty->wbf16; break;
       default: ox = tx->wfp16; oy = ty->wfp16; break;
@@ -1475,12 +1521,19 @@ fcfs_status fcfs_step_plan_destroy(fcfs_step_plan *plan) {
   return FCFS_OK;
 }
 
+namespace {
+constexpr const char *kAdjBigMsg =
+    "the adjoint takes periods Nx 2^frac_bits, Ny 2^frac_bits up to 8192 (two-level tables are "
+    "built for the forward transform)";
+}  // namespace
+
 fcfs_status fcfs_general_adjoint_workspace_size(const fcfs_gclip *c, fcfs_precision p,
                                                 size_t *bytes) {
   if (!bytes) return fail(nullptr, FCFS_ERR_INVALID_ARG, "NULL argument");
   FwdPlan q;
   fcfs_status st = make_plan_general(nullptr, c, (int)p, &q);
   if (st) return st;
+  if (q.big) return fail(nullptr, FCFS_ERR_UNSUPPORTED, kAdjBigMsg);
   fcfs::AdjPlan a;
   if ((st = make_adj_plan(nullptr, c->V, fcfs::kTabN, c->K, c->L, c->K, c->L, (int)p, &a)))
     return st;
@@ -1495,6 +1548,7 @@ fcfs_status fcfs_adjoint_general(fcfs_handle *h, const fcfs_gclip *c, const floa
   if (st) return st;
   FwdPlan q;
   if ((st = make_plan_general(h, c, (int)p, &q))) return st;
+  if (q.big) return fail(h, FCFS_ERR_UNSUPPORTED, kAdjBigMsg);
   if (c->V > 0 && (!c->x || !c->y || !c->s))
     return fail(h, FCFS_ERR_INVALID_ARG, "corner arrays are NULL");
   if (!grad_F) return fail(h, FCFS_ERR_INVALID_ARG, "grad_F is NULL");

@@ -260,6 +260,152 @@ __global__ __launch_bounds__(256, 1) void k_contract_gen_pipe(
   store_part<2, 2>(part, acc, split, kp, lp, k0, l0, li, lh);
 }
 
+// ---------------------------------------------------------------------------
+// Periods past 8192 grid units (two-level twiddles).  The eight-wave layout
+// of k_contract_gen; per entry the phase (f x) mod M is reduced exactly in
+// FP64 and the twiddle is the FP32 complex product of the two table entries
+// (both tables of both periods in LDS, at most 4 x 4096 entries).  The split
+// precisions round that product to hi + lo in the kernel (the FP32 product is
+// accurate to a few 2^-24, far below the split's own rounding).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+
+__device__ __forceinline__ float2 big_entry(const float2 *t, int nh, uint32_t p) {
+  return cmulf(t[p >> kBigBits], t[nh + (p & (uint32_t)(kBigLo - 1))]);
+}
+
+// Round to nearest even of an FP32 value to bf16 (bit pattern), finite input.
+__device__ __forceinline__ uint32_t bf16_rne(float v) {
+  const uint32_t u = __float_as_uint(v);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+// Split entry {hi(c)|hi(s)<<16, lo(c)|lo(s)<<16} of w (as the host tables).
+template <int PREC>
+__device__ __forceinline__ uint2 split_entry(float2 w) {
+  if constexpr (PREC == kBF16) {
+    const uint32_t hc = bf16_rne(w.x), hs = bf16_rne(w.y);
+    const uint32_t lc = bf16_rne(w.x - __uint_as_float(hc << 16));
+    const uint32_t ls = bf16_rne(w.y - __uint_as_float(hs << 16));
+    return make_uint2(hc | hs << 16, lc | ls << 16);
+  } else {
+    const _Float16 hc = (_Float16)w.x, hs = (_Float16)w.y;
+    const _Float16 lc = (_Float16)(w.x - (float)hc), ls = (_Float16)(w.y - (float)hs);
+    return make_uint2((uint32_t)__builtin_bit_cast(uint16_t, hc) |
+                          (uint32_t)__builtin_bit_cast(uint16_t, hs) << 16,
+                      (uint32_t)__builtin_bit_cast(uint16_t, lc) |
+                          (uint32_t)__builtin_bit_cast(uint16_t, ls) << 16);
+  }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(64 * kGenWaves) void k_contract_big(
+    const uint4 *__restrict__ packed, const float2 *__restrict__ tabx,
+    const float2 *__restrict__ taby, int Mx, int My, int nhx, int nhy, int64_t chunk,
+    int tiles_l, int kp, int lp, float *__restrict__ part, double r2) {
+  if (tile_outside(blockIdx.x, tiles_l, 128, 128, r2)) return;
+  extern __shared__ float2 lds_big[];
+  const int nx = nhx + kBigLo, ny = nhy + kBigLo;
+  float2 *tx = lds_big;
+  float2 *ty = tabx == taby ? tx : tx + nx;
+  for (int i = threadIdx.x; i < nx; i += 64 * kGenWaves) tx[i] = tabx[i];
+  if (tabx != taby)
+    for (int i = threadIdx.x; i < ny; i += 64 * kGenWaves) ty[i] = taby[i];
+  __syncthreads();
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 31, lh = lane >> 5;
+  const int tk = blockIdx.x / tiles_l, tl = blockIdx.x % tiles_l;
+  const int split = blockIdx.y;
+  const int k0 = tk * 128 + (wave >> 2) * 64;
+  const int l0 = tl * 128 + (wave & 3) * 32;
+  const double dMx = (double)Mx, dMy = (double)My, iMx = 1.0 / dMx, iMy = 1.0 / dMy;
+  uint32_t kf[kGenNKB], lf[kGenNLB];
+#pragma unroll
+  for (int kb = 0; kb < kGenNKB; ++kb) kf[kb] = (uint32_t)(k0 + 32 * kb + li);
+#pragma unroll
+  for (int lb = 0; lb < kGenNLB; ++lb) lf[lb] = (uint32_t)(l0 + 32 * lb + li);
+
+  f32x16 acc[kGenNKB][kGenNLB][4];
+#pragma unroll
+  for (int kb = 0; kb < kGenNKB; ++kb)
+#pragma unroll
+    for (int lb = 0; lb < kGenNLB; ++lb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[kb][lb][q][r] = 0.0f;
+
+  const uint4 *vp = packed + (size_t)split * chunk + 8 * lh;
+  for (int64_t vb = 0; vb < chunk; vb += 16) {
+    uint4 c[8];
+    load_corners(c, vp + vb);
+    float2 a[kGenNKB][8], b[kGenNLB][8];
+#pragma unroll
+    for (int kb = 0; kb < kGenNKB; ++kb)
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        a[kb][j] = c[j].w ? make_float2(0.0f, 0.0f)
+                          : big_entry(tx, nhx, big_phase(kf[kb], c[j].x, dMx, iMx));
+#pragma unroll
+    for (int lb = 0; lb < kGenNLB; ++lb)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float2 w = big_entry(ty, nhy, big_phase(lf[lb], c[j].y, dMy, iMy));
+        b[lb][j] = c[j].z ? make_float2(-w.x, -w.y) : w;
+      }
+    if constexpr (PREC == kFP32) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int kb = 0; kb < kGenNKB; ++kb)
+#pragma unroll
+          for (int lb = 0; lb < kGenNLB; ++lb) {
+            acc[kb][lb][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[kb][j].x, b[lb][j].x, acc[kb][lb][0], 0, 0, 0);
+            acc[kb][lb][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[kb][j].x, b[lb][j].y, acc[kb][lb][1], 0, 0, 0);
+            acc[kb][lb][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[kb][j].y, b[lb][j].x, acc[kb][lb][2], 0, 0, 0);
+            acc[kb][lb][3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[kb][j].y, b[lb][j].y, acc[kb][lb][3], 0, 0, 0);
+          }
+    } else {
+      Raw<kGenNKB, kGenNLB> raw;
+#pragma unroll
+      for (int kb = 0; kb < kGenNKB; ++kb)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) raw.a[kb][j] = split_entry<PREC>(a[kb][j]);
+#pragma unroll
+      for (int lb = 0; lb < kGenNLB; ++lb)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) raw.b[lb][j] = split_entry<PREC>(b[lb][j]);
+      Frag<kGenNKB, kGenNLB> f;
+      build(f, raw);
+      mma<PREC>(acc, f);
+    }
+  }
+  store_part<kGenNKB, kGenNLB>(part, acc, split, kp, lp, k0, l0, li, lh);
+}
+
+template <int PREC>
+hipError_t launch_big_t(const FwdPlan &p, const uint4 *packed, const void *tx, const void *ty,
+                        float *part, hipStream_t st) {
+  const size_t lds = sizeof(float2) * ((size_t)p.nhx + kBigLo +
+                                       (tx == ty ? 0 : (size_t)p.nhy + kBigLo));
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_contract_big<PREC>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(sizeof(float2) * 4 * kBigLo));
+    if (e) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_contract_big<PREC>, dim3(p.tiles_k * p.tiles_l, p.nsplit),
+                     dim3(64 * kGenWaves), lds, st, packed, (const float2 *)tx,
+                     (const float2 *)ty, p.Mx, p.My, p.nhx, p.nhy, p.chunk, p.tiles_l, p.kp, p.lp,
+                     part, p.r2);
+  return hipGetLastError();
+}
+
 template <int PREC>
 hipError_t launch_gen_pipe_t(const FwdPlan &p, const uint4 *packed, const void *tx,
                              const void *ty, float *part, hipStream_t st) {
@@ -291,6 +437,13 @@ hipError_t launch_gen_t(const FwdPlan &p, const uint4 *packed, const void *tx, c
 
 hipError_t launch_gen_contract(const FwdPlan &p, const uint4 *packed, const void *tx,
                                const void *ty, float *part, hipStream_t st) {
+  if (p.big) {
+    switch (p.prec) {
+      case kFP32: return launch_big_t<kFP32>(p, packed, tx, ty, part, st);
+      case kBF16: return launch_big_t<kBF16>(p, packed, tx, ty, part, st);
+      default: return launch_big_t<kFP16>(p, packed, tx, ty, part, st);
+    }
+  }
   if (p.tile == kGenPipeTile) {
     if (p.chunk % 32) return hipErrorInvalidValue;
     return p.prec == kBF16 ? launch_gen_pipe_t<kBF16>(p, packed, tx, ty, part, st)

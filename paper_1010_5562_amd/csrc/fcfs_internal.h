@@ -116,6 +116,26 @@ __host__ __device__ inline int guard_span(double gscale, int64_t V, long long A)
   return n <= 1.0 ? 1 : (n >= (double)kGuardSpanMax ? kGuardSpanMax : (int)n);
 }
 
+// Periods above the LDS table size (general tiles with Nx 2^F or Ny 2^F past
+// 8192 grid units): two-level twiddles.  The phase p = (f x) mod M is reduced
+// exactly in FP64 and the entry is e(2 pi p / M) = Whi[p >> kBigBits] x
+// Wlo[p & (kBigLo - 1)], Whi[j] = e(2 pi j kBigLo / M), Wlo[i] = e(2 pi i / M),
+// both tables at most 4096 entries (M <= kBigMaxPeriod).  A two-level table
+// of period M stores Whi (big_hi(M) entries) followed by Wlo (kBigLo).
+constexpr int kBigBits = 12;
+constexpr int kBigLo = 1 << kBigBits;
+constexpr int64_t kBigMaxPeriod = (int64_t)1 << 24;
+__host__ __device__ inline int big_hi(int64_t M) { return (int)((M + kBigLo - 1) / kBigLo); }
+// (f x) mod M for x < M <= 2^24 and f < 2^13: f x < 2^37 is exact in FP64, the
+// quotient estimate is off by at most one and the remainder fma is exact.
+__device__ __forceinline__ uint32_t big_phase(uint32_t f, uint32_t x, double M, double invM) {
+  const double t = (double)f * (double)x;
+  const double q = floor(t * invM);
+  double r = fma(-q, M, t);
+  r = r < 0.0 ? r + M : (r >= M ? r - M : r);
+  return (uint32_t)r;
+}
+
 // Device-resident constant tables owned by a handle.
 struct Tables {
   double2 *w64 = nullptr;    // [kTabN]       (cos, sin)(2 pi p / N), FP64
@@ -150,6 +170,8 @@ struct FwdPlan {
   int g_chunks;      // corner chunks (blocks) of the FP64 guard region
   int64_t g_chunk;
   double gscale;     // guard-span model factor (guard_span; 0: core block only)
+  int big;           // general tile with a period past 8192: two-level tables
+  int nhx, nhy;      // two-level tables: entries of Whi per period (big_hi)
   // workspace offsets (bytes): off_guard holds the guard partials
   // [chunk][slot][16 x 16], off_gspan the span the side kernel chose
   size_t off_packed, off_area, off_hist, off_axis, off_part, off_guard, off_gspan, bytes;
@@ -190,12 +212,16 @@ hipError_t launch_gen_prepass_records(const int32_t *x, const int32_t *y, const 
                                       int64_t V, int64_t vpad, int Mx, int My, int pre_blocks,
                                       uint4 *packed, unsigned long long *area_part,
                                       hipStream_t st);
+// With p.big, wx and wy are two-level FP64 tables, the histograms are not used
+// and the axis sums are taken directly over the corners.
 hipError_t launch_gen_side(const FwdPlan &p, const int32_t *x, const int32_t *y,
                            const double2 *wx, const double2 *wy, void *ws, hipStream_t st);
 // FwdPlan::tile of a general-tile plan: kGenPipeTile selects the pipelined
 // split kernel (one wave per SIMD, chunk a multiple of 32), any other value
 // the eight-wave kernel.
 constexpr int kGenPipeTile = 1;
+// With p.big, tx and ty are two-level FP32 tables for every precision (the
+// split entries are formed from the FP32 product in the kernel).
 hipError_t launch_gen_contract(const FwdPlan &p, const uint4 *packed, const void *tx,
                                const void *ty, float *part, hipStream_t st);
 hipError_t launch_fft(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,

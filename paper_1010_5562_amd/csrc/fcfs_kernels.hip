@@ -118,9 +118,12 @@ __global__ __launch_bounds__(256) void k_gen_prepass(const int32_t *__restrict__
 hipError_t launch_gen_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y,
                               const int8_t *s, uint32_t smask, void *ws, hipStream_t st) {
   char *w = (char *)ws;
+  // the histograms (Mx + My bins, at most 2 x 8192) are not used by plans
+  // with periods past 8192, which sum the axes over the corners
   hipLaunchKernelGGL(k_gen_prepass, dim3(p.pre_blocks), dim3(256), 0, st, x, y, s, p.V, p.vpad,
                      p.Mx, p.My, smask, (uint4 *)(w + p.off_packed),
-                     (unsigned long long *)(w + p.off_area), (unsigned long long *)(w + p.off_hist));
+                     (unsigned long long *)(w + p.off_area),
+                     p.big ? nullptr : (unsigned long long *)(w + p.off_hist));
   return hipGetLastError();
 }
 
@@ -244,6 +247,22 @@ __device__ __forceinline__ double2 rot(double2 v, double2 r) {
   return make_double2(v.x * r.x - v.y * r.y, v.y * r.x + v.x * r.y);
 }
 
+// Entry p of a two-level FP64 table (nh entries of Whi, then Wlo).
+__device__ __forceinline__ double2 big_entry64(const double2 *__restrict__ t, int nh, uint32_t p) {
+  return rot(t[p >> kBigBits], t[nh + (p & (uint32_t)(kBigLo - 1))]);
+}
+
+// Phase and table entry of a general tile: one-level (residue tables) or
+// two-level for periods past 8192 (BIG).
+template <bool BIG>
+__device__ __forceinline__ double2 gen_entry64(const double2 *__restrict__ t, int nh, uint32_t f,
+                                               uint32_t x, uint32_t M, double dM, double iM) {
+  if constexpr (BIG)
+    return big_entry64(t, nh, big_phase(f, x, dM, iM));
+  else
+    return t[(f * x) % M];
+}
+
 // Span of the guard region (block-uniform) from the exact area partials,
 // limited to the strips that reach into |k| <= K or |l| <= L.
 __device__ __forceinline__ int guard_span_block(const unsigned long long *__restrict__ area_part,
@@ -269,8 +288,9 @@ __device__ __forceinline__ int guard_span_block(const unsigned long long *__rest
 // frequencies k = 1..8 and step the columns along l, the k-strip groups keep
 // l = 1..8 and step the rows along k.
 // GEN: general-tile records (residues); x phases (f x) mod Mx index wx, y
-// phases wy.  Otherwise byte-offset records and the one table wx.
-template <bool GEN = false>
+// phases wy (BIG: two-level tables with nhx, nhy entries of Whi).  Otherwise
+// byte-offset records and the one table wx.
+template <bool GEN = false, bool BIG = false>
 __device__ __forceinline__ void guard_body(const uint4 *__restrict__ packed,
                                            const double2 *__restrict__ wx, int64_t V,
                                            int64_t g_chunk, int blk, int gi,
@@ -279,7 +299,9 @@ __device__ __forceinline__ void guard_body(const uint4 *__restrict__ packed,
                                            double *__restrict__ gpart,
                                            unsigned int *__restrict__ gspan,
                                            const double2 *__restrict__ wy = nullptr, int Mx = 0,
-                                           int My = 0) {
+                                           int My = 0, int nhx = 0, int nhy = 0) {
+  const double dMx = (double)Mx, dMy = (double)My;
+  const double iMx = BIG ? 1.0 / dMx : 0.0, iMy = BIG ? 1.0 / dMy : 0.0;
   __shared__ double red[4][kGuardD];
   const int n =
       __builtin_amdgcn_readfirstlane(guard_span_block(area_part, pre_blocks, V, gscale, K, L));
@@ -309,18 +331,26 @@ __device__ __forceinline__ void guard_body(const uint4 *__restrict__ packed,
         ea[u] = eb[u] = 0.0;
         if (v < v1) {
           const uint4 c = packed[v];
-          uint32_t px, py;
-          if constexpr (GEN) {
-            px = (fx * c.x) % (uint32_t)Mx;
-            py = (fy * c.y) % (uint32_t)My;
+          if constexpr (BIG) {
+            const double2 wa = gen_entry64<true>(wx, nhx, fx, c.x, Mx, dMx, iMx);
+            const double2 wb = gen_entry64<true>(wy, nhy, fy, c.y, My, dMy, iMy);
+            ea[u] = sn ? wa.y : wa.x;
+            const double tb = sn ? wb.y : wb.x;
+            eb[u] = c.z ? -tb : tb;
           } else {
-            px = __umul24(fx, c.x >> 3) & (uint32_t)(kTabN - 1);
-            py = __umul24(fy, c.y >> 3) & (uint32_t)(kTabN - 1);
+            uint32_t px, py;
+            if constexpr (GEN) {
+              px = (fx * c.x) % (uint32_t)Mx;
+              py = (fy * c.y) % (uint32_t)My;
+            } else {
+              px = __umul24(fx, c.x >> 3) & (uint32_t)(kTabN - 1);
+              py = __umul24(fy, c.y >> 3) & (uint32_t)(kTabN - 1);
+            }
+            const double *tx = (const double *)wx, *ty = (const double *)(GEN ? wy : wx);
+            ea[u] = tx[2 * px + (sn ? 1 : 0)];
+            const double tb = ty[2 * py + (sn ? 1 : 0)];
+            eb[u] = c.z ? -tb : tb;
           }
-          const double *tx = (const double *)wx, *ty = (const double *)(GEN ? wy : wx);
-          ea[u] = tx[2 * px + (sn ? 1 : 0)];
-          const double tb = ty[2 * py + (sn ? 1 : 0)];
-          eb[u] = c.z ? -tb : tb;
         }
       }
 #pragma unroll
@@ -338,21 +368,29 @@ __device__ __forceinline__ void guard_body(const uint4 *__restrict__ packed,
         e8[u] = make_double2(1.0, 0.0);
         if (v < v1) {
           const uint4 c = packed[v];
-          uint32_t px, py, p8;
-          if constexpr (GEN) {
-            px = (fx * c.x) % (uint32_t)Mx;
-            py = (fy * c.y) % (uint32_t)My;
-            p8 = ymove ? (8u * c.y) % (uint32_t)My : (8u * c.x) % (uint32_t)Mx;
+          double2 t;
+          if constexpr (BIG) {
+            ex[u] = gen_entry64<true>(wx, nhx, fx, c.x, Mx, dMx, iMx);
+            t = gen_entry64<true>(wy, nhy, fy, c.y, My, dMy, iMy);
+            e8[u] = ymove ? gen_entry64<true>(wy, nhy, 8u, c.y, My, dMy, iMy)
+                          : gen_entry64<true>(wx, nhx, 8u, c.x, Mx, dMx, iMx);
           } else {
-            const uint32_t xs = c.x >> 3, ys = c.y >> 3;
-            px = __umul24(fx, xs) & (uint32_t)(kTabN - 1);
-            py = __umul24(fy, ys) & (uint32_t)(kTabN - 1);
-            p8 = (8u * (ymove ? ys : xs)) & (uint32_t)(kTabN - 1);
+            uint32_t px, py, p8;
+            if constexpr (GEN) {
+              px = (fx * c.x) % (uint32_t)Mx;
+              py = (fy * c.y) % (uint32_t)My;
+              p8 = ymove ? (8u * c.y) % (uint32_t)My : (8u * c.x) % (uint32_t)Mx;
+            } else {
+              const uint32_t xs = c.x >> 3, ys = c.y >> 3;
+              px = __umul24(fx, xs) & (uint32_t)(kTabN - 1);
+              py = __umul24(fy, ys) & (uint32_t)(kTabN - 1);
+              p8 = (8u * (ymove ? ys : xs)) & (uint32_t)(kTabN - 1);
+            }
+            ex[u] = wx[px];
+            t = GEN ? wy[py] : wx[py];
+            e8[u] = (GEN && ymove) ? wy[p8] : wx[p8];
           }
-          ex[u] = wx[px];
-          const double2 t = GEN ? wy[py] : wx[py];
           ey[u] = c.z ? make_double2(-t.x, -t.y) : t;
-          e8[u] = (GEN && ymove) ? wy[p8] : wx[p8];
         }
       }
 #pragma unroll
@@ -456,10 +494,75 @@ __global__ __launch_bounds__(256) void k_gen_axis_dft(const unsigned long long *
   dft_body<true>(hist, wx, Mx, 0, K, L, fb_k, axis_part, blockIdx.x, blockIdx.y, wy, My);
 }
 
+// Periods past 8192 (two-level tables): the guard blocks alone.
+__global__ __launch_bounds__(256) void k_gen_side_big(
+    const uint4 *__restrict__ packed, int64_t V, const double2 *__restrict__ wx,
+    const double2 *__restrict__ wy, int Mx, int My, int nhx, int nhy, int64_t g_chunk,
+    int g_chunks, const unsigned long long *__restrict__ area_part, int pre_blocks, double gscale,
+    int K, int L, double *__restrict__ gpart, unsigned int *__restrict__ gspan) {
+  guard_body<true, true>(packed, wx, V, g_chunk, blockIdx.x % g_chunks, blockIdx.x / g_chunks,
+                         area_part, pre_blocks, gscale, K, L, gpart, gspan, wy, Mx, My, nhx, nhy);
+}
+
+// Axis sums (Steps 2 and 3) over the corners directly, for periods past 8192
+// where a histogram over the residues would be too large: block (fb, chunk)
+// takes 256 frequencies of one axis against the corners of its range,
+//   Sx[f] += sum_v s_v y_v e^{-j 2 pi f x_v / Mx},  Sy[f] += sum_v s_v x_v e^{-j 2 pi f y_v / My},
+// raw coordinates as the moments and residues for the exact phases; the same
+// per-chunk partials as k_gen_axis_dft, reduced by the epilogue.
+__global__ __launch_bounds__(256) void k_gen_axis_big(
+    const int32_t *__restrict__ x, const int32_t *__restrict__ y, const uint4 *__restrict__ packed,
+    int64_t V, int64_t ax_chunk, const double2 *__restrict__ wx, const double2 *__restrict__ wy,
+    int Mx, int My, int nhx, int nhy, int K, int L, int fb_k, double2 *__restrict__ axis_part) {
+  __shared__ uint32_t s_q[256];
+  __shared__ double s_m[256];
+  const int fb = blockIdx.x, chunk = blockIdx.y, t = threadIdx.x;
+  const bool xaxis = fb < fb_k;
+  const int f = 1 + (xaxis ? fb : fb - fb_k) * 256 + t;
+  const int nf = xaxis ? K : L;
+  const double2 *W = xaxis ? wx : wy;
+  const int nh = xaxis ? nhx : nhy;
+  const double dM = (double)(xaxis ? Mx : My), iM = 1.0 / dM;
+  const int64_t v0 = (int64_t)chunk * ax_chunk, v1 = min(V, v0 + ax_chunk);
+  double re = 0.0, im = 0.0;
+  for (int64_t b = v0; b < v1; b += 256) {
+    const int n = (int)min((int64_t)256, v1 - b);
+    __syncthreads();
+    if (t < n) {
+      const uint4 c = packed[b + t];
+      const double m = (double)(xaxis ? y[b + t] : x[b + t]);
+      s_q[t] = xaxis ? c.x : c.y;
+      s_m[t] = c.z ? -m : m;
+    }
+    __syncthreads();
+    if (f <= nf)
+      for (int i = 0; i < n; ++i) {
+        const double2 w = big_entry64(W, nh, big_phase((uint32_t)f, s_q[i], dM, iM));
+        re = fma(s_m[i], w.x, re);
+        im = fma(-s_m[i], w.y, im);
+      }
+  }
+  if (f <= nf) axis_part[(size_t)chunk * (K + L) + (xaxis ? f - 1 : K + f - 1)] = make_double2(re, im);
+}
+
 hipError_t launch_gen_side(const FwdPlan &p, const int32_t *x, const int32_t *y,
                            const double2 *wx, const double2 *wy, void *ws, hipStream_t st) {
   char *w = (char *)ws;
   const uint4 *packed = (const uint4 *)(w + p.off_packed);
+  if (p.big) {
+    if (p.K > 0 && p.L > 0)
+      hipLaunchKernelGGL(k_gen_side_big, dim3(kGuardGroups * p.g_chunks), dim3(256), 0, st, packed,
+                         p.V, wx, wy, p.Mx, p.My, p.nhx, p.nhy, p.g_chunk, p.g_chunks,
+                         (const unsigned long long *)(w + p.off_area), p.pre_blocks, p.gscale,
+                         p.K, p.L, (double *)(w + p.off_guard), (unsigned int *)(w + p.off_gspan));
+    if (p.K + p.L > 0) {
+      const int64_t ax_chunk = std::max<int64_t>(1, (p.V + p.ax_chunks - 1) / p.ax_chunks);
+      hipLaunchKernelGGL(k_gen_axis_big, dim3(p.ax_fb_k + p.ax_fb_l, p.ax_chunks), dim3(256), 0,
+                         st, x, y, packed, p.V, ax_chunk, wx, wy, p.Mx, p.My, p.nhx, p.nhy, p.K,
+                         p.L, p.ax_fb_k, (double2 *)(w + p.off_axis));
+    }
+    return hipGetLastError();
+  }
   auto *hist = (unsigned long long *)(w + p.off_hist);
   const int nh = p.K + p.L > 0 ? p.hist_blocks : 0;
   const int ng = p.K > 0 && p.L > 0 ? kGuardGroups * p.g_chunks : 0;

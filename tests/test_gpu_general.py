@@ -106,7 +106,8 @@ def test_general_empty_and_errors(P):
     assert int(a.item()) == 0 and bool((Fg == 0).all())
     sq = synth.rectangle_loop(0, 0, 3, 3)
     x, y, s, _, _ = P.loops_to_corners(sq, np.array([0, 4]))
-    for Nx, Ny, F in ((9000, 100, 0), (100, 100, 14), (3000, 100, 2), (1, 1, 0)):
+    # periods past 2^24 grid units, F > 13 and a period below 2
+    for Nx, Ny, F in ((5000, 100, 12), (100, 100, 14), (100, 2049, 13), (1, 1, 0)):
         with pytest.raises(P.FcfsError):
             P.forward_general(x, y, s, Nx, Ny, 4, 4, frac_bits=F)
 
@@ -305,3 +306,79 @@ def test_general_low_fill_clip_near_axes(P, oracle_lib):
         w = int(np.argmax(e))
         _say(f"general low-fill clip {prec}: max err/|F00| = {e[w]:.3e} at ({kk[w]},{ll[w]})")
         assert e[w] <= TOL[prec]
+
+
+def _fine_grid_clip(seed, Nx, Ny, F, K, L, npol):
+    # polygons drawn on the lattice of the tile, then every loop shifted by its
+    # own random sub-lattice step (a multiple of 2^-F): corners on the fine
+    # grid at the fill of a lattice clip, whatever F
+    clip = synth.clip(seed, max(Nx, Ny), K, L, n_polygons=npol)
+    rng = np.random.default_rng(seed)
+    X = clip.xy.astype(np.int64) << F
+    for i in range(clip.off.size - 1):
+        X[clip.off[i]:clip.off[i + 1]] += rng.integers(0, 1 << F, 2)
+    return X.astype(np.int32), clip.off
+
+
+@pytest.mark.parametrize("Nx,Ny,F,K,L,npol,seed", [
+    (3000, 2000, 3, 40, 33, 150, 41),      # periods 24000 x 16000 (two-level tables)
+    (5000, 5000, 2, 45, 45, 150, 42),      # equal periods past 8192 (one shared table)
+    (2000, 9000, 0, 37, 41, 200, 43),      # one period below 8192, one above
+    (1000, 700, 13, 30, 28, 60, 44),       # grid step 2^-13: periods 8192000 x 5734400
+])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_general_two_level_full_grid(P, oracle_lib, Nx, Ny, F, K, L, npol, seed, prec):
+    # periods past 8192 grid units: two-level twiddles, exact FP64 phases,
+    # direct axis sums; every coefficient against the FP64 oracle
+    Mx, My = Nx << F, Ny << F
+    X, off = _fine_grid_clip(seed, Nx, Ny, F, K, L, npol)
+    xy = X.astype(np.float64) / 2 ** F
+    _say(f"two-level {Nx}x{Ny} F={F} (periods {Mx} x {My}) K={K} L={L} {prec}")
+    ref, area = oracle_lib.cfs_grid_general(xy, off, Nx, Ny, K, L, frac_bits=F)
+    Fg, a = _gpu(P, X, off, Nx, Ny, K, L, F, prec)
+    assert a == area
+    e = float(np.max(np.abs(Fg - ref)) / abs(ref[K, L]))
+    _say(f"  err/|F00| = {e:.3e}")
+    assert e <= TOL[prec]
+
+
+def test_general_two_level_layout_clip(P, oracle_lib):
+    # 2,000 polygons on a 4000 x 3000 tile with corners on the 1/16 grid
+    # (periods 64000 x 48000), |k|, |l| <= 255: sampled coefficients, every
+    # coefficient with |k l| <= 160, and the low-pass form
+    Nx, Ny, F, K = 4000, 3000, 4, 255
+    clip = synth.clip(45, 64000, K, n_polygons=2000)
+    xy = clip.xy.astype(np.float64) / 2 ** F
+    rng = np.random.default_rng(9)
+    pts = [(k, l) for k in range(-K, K + 1) for l in range(-K, K + 1)
+           if k and l and abs(k * l) <= 160]
+    kk = np.concatenate([np.array(pts)[:, 0], rng.integers(-K, K + 1, 300), [0] * 5, [1, 2, 3]])
+    ll = np.concatenate([np.array(pts)[:, 1], rng.integers(-K, K + 1, 300), [1, 2, 3, 4, 5],
+                         [0] * 3])
+    ref = oracle_lib.cfs_points_general(xy, clip.off, Nx, Ny, kk, ll, frac_bits=F)
+    f00 = abs(oracle_lib.cfs_points_general(xy, clip.off, Nx, Ny, [0], [0], frac_bits=F)[0])
+    for prec in ("fp32", "bf16"):
+        Fg, _ = _gpu(P, clip.xy, clip.off, Nx, Ny, K, K, F, prec)
+        e = np.abs(Fg[kk + K, ll + K] - ref) / f00
+        w = int(np.argmax(e))
+        _say(f"two-level layout clip {prec}: max err/|F00| = {e[w]:.3e} at ({kk[w]},{ll[w]})")
+        assert e[w] <= TOL[prec]
+    x, y, s, _, _ = P.loops_to_corners(clip.xy, clip.off)
+    Fb, _ = P.forward_general(x, y, s, Nx, Ny, K, K, frac_bits=F, precision="bf16",
+                              band=(60, 60), radius=50.0)
+    torch.cuda.synchronize()
+    Fb = Fb.cpu().numpy().astype(np.complex128)
+    ins = (np.abs(kk) <= 60) & (np.abs(ll) <= 60) & (kk ** 2 + ll ** 2 <= 2500)
+    assert np.all(np.abs(Fb[kk[~ins] + K, ll[~ins] + K]) == 0)
+    e = float(np.max(np.abs(Fb[kk[ins] + K, ll[ins] + K] - ref[ins])) / f00)
+    _say(f"two-level layout clip low-pass bf16: err/|F00| = {e:.3e}")
+    assert e <= TOL["bf16"]
+
+
+def test_general_two_level_adjoint_refused(P):
+    clip = synth.clip(46, 24000, 20, n_polygons=20)
+    x, y, s, _, _ = P.loops_to_corners(clip.xy, clip.off)
+    g = torch.zeros((41, 41), dtype=torch.complex64, device="cuda")
+    with pytest.raises(P.FcfsError) as ei:
+        P.adjoint_general(x, y, s, 3000, 3000, 20, 20, g, frac_bits=3)
+    assert ei.value.status == -4
