@@ -210,8 +210,8 @@ fcfs_status fcfs_forward_general_band(fcfs_handle *h, const fcfs_gclip *c, int32
  * x[v] / 2^frac_bits.  grad_F, band (kmax, lmax) and radius as in
  * fcfs_adjoint_band.  ws: at least fcfs_general_adjoint_workspace_size bytes,
  * 256-byte aligned.  Uses the per-period tables of the handle (built on first
- * use, as for the forward).  Periods Mx, My up to 8192 only:
- * FCFS_ERR_UNSUPPORTED past that (the two-level tables serve the forward). */
+ * use, as for the forward).  Periods Mx, My up to 2^23 (two-level tables
+ * past 8192, as for the forward): FCFS_ERR_UNSUPPORTED past that. */
 fcfs_status fcfs_general_adjoint_workspace_size(const fcfs_gclip *c, fcfs_precision p,
                                                 size_t *bytes);
 fcfs_status fcfs_adjoint_general(fcfs_handle *h, const fcfs_gclip *c, const float *grad_F,

@@ -230,8 +230,9 @@ __global__ void k_adj_axcoef(const float2 *__restrict__ G, int K, int L, int kma
 // sum_f Re[c_f e(f t)] with e(f t) = conj(w^f), w = e^{j 2 pi ts / N}: the
 // powers come from repeated multiplication, restarted from the exact table
 // every 32 steps.
-// GEN: residue records of a general tile, tables wx (period Mx) and wy (My).
-template <bool GEN>
+// GEN: residue records of a general tile, tables wx (period Mx) and wy (My);
+// BIG: two-level tables (nhx, nhy entries of Whi) for periods past 8192.
+template <bool GEN, bool BIG = false>
 __global__ __launch_bounds__(256) void k_adj_axis(const int32_t *__restrict__ x,
                                                   const int32_t *__restrict__ y,
                                                   const uint4 *__restrict__ packed,
@@ -240,8 +241,10 @@ __global__ __launch_bounds__(256) void k_adj_axis(const int32_t *__restrict__ x,
                                                   int K, int L, int kmax, int lmax, double dcf,
                                                   float *__restrict__ gx, float *__restrict__ gy,
                                                   const double2 *__restrict__ wy = nullptr,
-                                                  int Mx = 0, int My = 0) {
+                                                  int Mx = 0, int My = 0, int nhx = 0,
+                                                  int nhy = 0) {
   const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const double dMx = (double)Mx, dMy = (double)My;
   if (v >= V) return;
   const uint4 c = packed[v];
   const double sg = c.z ? -1.0 : 1.0;
@@ -250,14 +253,15 @@ __global__ __launch_bounds__(256) void k_adj_axis(const int32_t *__restrict__ x,
   double sx1 = 0.0, sx2 = 0.0;  // sum Re[P e(kx)],  sum Re[P j/(2 pi k) e(kx)]
   {
     const uint32_t ph = GEN ? c.x : c.x >> 3;
-    const double2 w1 = w64[ph];
+    const double2 w1 = BIG ? big_entry64(w64, nhx, ph) : w64[ph];
     double2 w = w1;
     // unrolled so that the uniform coefficient loads of 8 steps are issued together
 #pragma unroll 8
     for (int k = 1; k <= kmax; ++k) {
       if ((k & 31) == 0)
-        w = GEN ? w64[((uint32_t)k * ph) % (uint32_t)Mx]
-                : w64[((uint32_t)k * ph) & (uint32_t)(kTabN - 1)];
+        w = BIG ? big_entry64(w64, nhx, big_phase((uint32_t)k, ph, dMx, 1.0 / dMx))
+            : GEN ? w64[((uint32_t)k * ph) % (uint32_t)Mx]
+                  : w64[((uint32_t)k * ph) & (uint32_t)(kTabN - 1)];
       const double2 p = coef[k - 1], ps = coef_s[k - 1];
       // e(kx) = w.x - j w.y;  Re[j z] = -Im z
       sx1 += p.x * w.x + p.y * w.y;
@@ -270,13 +274,14 @@ __global__ __launch_bounds__(256) void k_adj_axis(const int32_t *__restrict__ x,
   {
     const double2 *W = GEN ? wy : w64;
     const uint32_t ph = GEN ? c.y : c.y >> 3;
-    const double2 w1 = W[ph];
+    const double2 w1 = BIG ? big_entry64(W, nhy, ph) : W[ph];
     double2 w = w1;
 #pragma unroll 8
     for (int l = 1; l <= lmax; ++l) {
       if ((l & 31) == 0)
-        w = GEN ? W[((uint32_t)l * ph) % (uint32_t)My]
-                : W[((uint32_t)l * ph) & (uint32_t)(kTabN - 1)];
+        w = BIG ? big_entry64(W, nhy, big_phase((uint32_t)l, ph, dMy, 1.0 / dMy))
+            : GEN ? W[((uint32_t)l * ph) % (uint32_t)My]
+                  : W[((uint32_t)l * ph) & (uint32_t)(kTabN - 1)];
       const double2 q = coef[K + l - 1], qs = coef_s[K + l - 1];
       sy1 += q.x * w.x + q.y * w.y;
       sy2 -= qs.y * w.x - qs.x * w.y;
@@ -327,17 +332,26 @@ __device__ __forceinline__ void stage_period_tables(E *dyn, const void *tx, cons
 }
 
 // GEN: a general tile (residue records, per-period tables tab / taby in
-// dynamic LDS, exact phases by adj_phase).
-template <int PREC, bool GEN>
+// dynamic LDS, exact phases by adj_phase).  BIG: periods past 8192, tab and
+// taby two-level FP32 tables (nhx, nhy entries of Whi), phases by big_phase,
+// the x-side split entries rounded from the FP32 product in the kernel.
+template <int PREC, bool GEN, bool BIG = false>
 __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_split(
     const uint4 *__restrict__ packed, const uint2 *__restrict__ tab,
     const uint16_t *__restrict__ whi,
     const uint16_t *__restrict__ wlo, const int *__restrict__ scale, int64_t V, int kb, int lb,
     float *__restrict__ gx, float *__restrict__ gy, const uint2 *__restrict__ taby = nullptr,
-    int Mx = 0, int My = 0) {
+    int Mx = 0, int My = 0, int nhx = 0, int nhy = 0) {
   __shared__ u32x4 s_w[2][4 * kAdjNB][64];
-  const uint2 *s_tab, *s_taby;
-  if constexpr (GEN) {
+  const uint2 *s_tab = nullptr, *s_taby = nullptr;
+  const float2 *b_tab = nullptr, *b_taby = nullptr;
+  const double dMx = (double)Mx, dMy = (double)My;
+  const double iMx = BIG ? 1.0 / dMx : 0.0, iMy = BIG ? 1.0 / dMy : 0.0;
+  if constexpr (BIG) {
+    extern __shared__ uint2 s_dyn[];
+    stage_period_tables<float2>((float2 *)s_dyn, tab, taby, nhx + kBigLo, nhy + kBigLo, b_tab,
+                                b_taby);
+  } else if constexpr (GEN) {
     extern __shared__ uint2 s_dyn[];
     stage_period_tables<uint2>(s_dyn, tab, taby, Mx, My, s_tab, s_taby);
   } else {
@@ -375,10 +389,10 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_split(
   for (int r = 0; r < 16; ++r) {
     const uint4 c = packed[vbase + 8 * (r >> 2) + 4 * lh + (r & 3)];
     ys8[r] = c.y;
-    ym[r] = GEN ? adj_magic(c.y, (uint32_t)My) : 0u;
+    ym[r] = GEN && !BIG ? adj_magic(c.y, (uint32_t)My) : 0u;
     neg[r] = c.z != 0u;
   }
-  const uint32_t xm = GEN ? adj_magic(ca.x, (uint32_t)Mx) : 0u;
+  const uint32_t xm = GEN && !BIG ? adj_magic(ca.x, (uint32_t)Mx) : 0u;
   float sx[16], sy[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) sx[r] = sy[r] = 0.f;
@@ -408,7 +422,10 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_split(
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const uint32_t f = (uint32_t)(1 + ib + 8 * lh + j);
-        d[j] = GEN ? s_tab[adj_phase(f, ca.x, xm, (uint32_t)Mx)] : lds_entry(s_tab, phase_x(f, ca));
+        if constexpr (BIG)
+          d[j] = split_entry<PREC>(big_entry(b_tab, nhx, big_phase(f, ca.x, dMx, iMx)));
+        else
+          d[j] = GEN ? s_tab[adj_phase(f, ca.x, xm, (uint32_t)Mx)] : lds_entry(s_tab, phase_x(f, ca));
       }
       u32x4 ach, ash, acl, asl;
       pack4(d, ach, ash, acl, asl);
@@ -430,13 +447,19 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_split(
       const uint32_t l = (uint32_t)((cg >> 2) + li + 1);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const uint2 e = GEN ? s_taby[adj_phase(l, ys8[r], ym[r], (uint32_t)My)]
-                            : lds_entry(s_taby, phase_x(l, make_uint4(ys8[r], 0u, 0u, 0u)));
         float yc, ys;
-        if constexpr (PREC == kBF16) {
+        if constexpr (BIG) {
+          const float2 e = big_entry(b_taby, nhy, big_phase(l, ys8[r], dMy, iMy));
+          yc = e.x;
+          ys = e.y;
+        } else if constexpr (PREC == kBF16) {
+          const uint2 e = GEN ? s_taby[adj_phase(l, ys8[r], ym[r], (uint32_t)My)]
+                              : lds_entry(s_taby, phase_x(l, make_uint4(ys8[r], 0u, 0u, 0u)));
           yc = __uint_as_float(e.x << 16) + __uint_as_float(e.y << 16);
           ys = __uint_as_float(e.x & 0xFFFF0000u) + __uint_as_float(e.y & 0xFFFF0000u);
         } else {
+          const uint2 e = GEN ? s_taby[adj_phase(l, ys8[r], ym[r], (uint32_t)My)]
+                              : lds_entry(s_taby, phase_x(l, make_uint4(ys8[r], 0u, 0u, 0u)));
           yc = (float)__builtin_bit_cast(_Float16, (uint16_t)(e.x & 0xFFFFu)) +
                (float)__builtin_bit_cast(_Float16, (uint16_t)(e.y & 0xFFFFu));
           ys = (float)__builtin_bit_cast(_Float16, (uint16_t)(e.x >> 16)) +
@@ -470,16 +493,21 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_split(
 // FP32 main term: v_mfma_f32_32x32x2_f32, two frequencies per product, with
 // the operand records of rec_index_f32 shared through LDS as in the split form
 // (eight waves, 256 corners per workgroup, double-buffered 16-row steps).
-template <bool GEN>
+template <bool GEN, bool BIG = false>
 __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_fp32(
     const uint4 *__restrict__ packed, const float2 *__restrict__ tab32g,
     const float *__restrict__ Wr, int64_t V, int kb, int lb, float *__restrict__ gx,
-    float *__restrict__ gy, const float2 *__restrict__ taby = nullptr, int Mx = 0, int My = 0) {
+    float *__restrict__ gy, const float2 *__restrict__ taby = nullptr, int Mx = 0, int My = 0,
+    int nhx = 0, int nhy = 0) {
   __shared__ float s_w[2][2 * kAdjNB][8][64];
   const float2 *s_tab, *s_taby;
+  const double dMx = (double)Mx, dMy = (double)My;
+  const double iMx = BIG ? 1.0 / dMx : 0.0, iMy = BIG ? 1.0 / dMy : 0.0;
   if constexpr (GEN) {
     extern __shared__ float2 s_dynf[];
-    stage_period_tables<float2>(s_dynf, tab32g, taby, Mx, My, s_tab, s_taby);
+    // BIG: two-level tables (nhx, nhy entries of Whi, then Wlo)
+    stage_period_tables<float2>(s_dynf, tab32g, taby, BIG ? nhx + kBigLo : Mx,
+                                BIG ? nhy + kBigLo : My, s_tab, s_taby);
   } else {
     __shared__ float2 s_fix[kTabEntries];
     for (int i = threadIdx.x; i < kTabEntries; i += 64 * kAdjWaves) s_fix[i] = tab32g[i];
@@ -512,10 +540,10 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_fp32(
   for (int r = 0; r < 16; ++r) {
     const uint4 c = packed[vbase + 8 * (r >> 2) + 4 * lh + (r & 3)];
     ys8[r] = c.y;
-    ym[r] = GEN ? adj_magic(c.y, (uint32_t)My) : 0u;
+    ym[r] = GEN && !BIG ? adj_magic(c.y, (uint32_t)My) : 0u;
     neg[r] = c.z != 0u;
   }
-  const uint32_t xm = GEN ? adj_magic(ca.x, (uint32_t)Mx) : 0u;
+  const uint32_t xm = GEN && !BIG ? adj_magic(ca.x, (uint32_t)Mx) : 0u;
   float sx[16], sy[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) sx[r] = sy[r] = 0.f;
@@ -544,8 +572,9 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_fp32(
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const uint32_t f = (uint32_t)(1 + ib + 2 * u + lh);
-        const float2 a = GEN ? s_tab[adj_phase(f, ca.x, xm, (uint32_t)Mx)]
-                             : *(const float2 *)((const char *)s_tab + phase_x(f, ca));
+        const float2 a = BIG   ? big_entry(s_tab, nhx, big_phase(f, ca.x, dMx, iMx))
+                         : GEN ? s_tab[adj_phase(f, ca.x, xm, (uint32_t)Mx)]
+                               : *(const float2 *)((const char *)s_tab + phase_x(f, ca));
 #pragma unroll
         for (int nb = 0; nb < kAdjNB; ++nb) {
           acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, s_w[buf][nb][u][lane], acc[nb], 0,
@@ -560,9 +589,10 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_fp32(
       const uint32_t l = (uint32_t)((cg >> 2) + li + 1);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const float2 w = GEN ? s_taby[adj_phase(l, ys8[r], ym[r], (uint32_t)My)]
-                             : *(const float2 *)((const char *)s_taby +
-                                                 phase_x(l, make_uint4(ys8[r], 0u, 0u, 0u)));
+        const float2 w = BIG   ? big_entry(s_taby, nhy, big_phase(l, ys8[r], dMy, iMy))
+                         : GEN ? s_taby[adj_phase(l, ys8[r], ym[r], (uint32_t)My)]
+                               : *(const float2 *)((const char *)s_taby +
+                                                   phase_x(l, make_uint4(ys8[r], 0u, 0u, 0u)));
         sx[r] = fmaf(acc[0][r], w.x, fmaf(acc[1][r], w.y, sx[r]));
         sy[r] = fmaf(acc[2][r], w.x, fmaf(acc[3][r], w.y, sy[r]));
       }
@@ -615,7 +645,11 @@ hipError_t launch_adjoint(const AdjPlan &a, const int32_t *x, const int32_t *y, 
   hipLaunchKernelGGL(k_adj_axcoef, dim3((a.K + a.L + 1 + 255) / 256), dim3(256), 0, st, G, a.K,
                      a.L, a.kmax, a.lmax, a.rx, a.ry, coef);
   if (a.V > 0) {
-    if (gen)
+    if (gen && a.big)
+      hipLaunchKernelGGL((k_adj_axis<true, true>), dim3((unsigned)((a.V + 255) / 256)), dim3(256),
+                         0, st, x, y, packed, gtab->w64x, coef, a.V, a.K, a.L, a.kmax, a.lmax,
+                         a.dcf, gx, gy, gtab->w64y, a.Mx, a.My, a.nhx, a.nhy);
+    else if (gen)
       hipLaunchKernelGGL(k_adj_axis<true>, dim3((unsigned)((a.V + 255) / 256)), dim3(256), 0, st,
                          x, y, packed, gtab->w64x, coef, a.V, a.K, a.L, a.kmax, a.lmax, a.dcf, gx,
                          gy, gtab->w64y, a.Mx, a.My);
@@ -638,11 +672,22 @@ hipError_t launch_adjoint(const AdjPlan &a, const int32_t *x, const int32_t *y, 
                        a.kb, a.lb, a.rx, a.ry, Wf, wmax, whi, wlo, scale);
   }
   const unsigned sblocks = (unsigned)(a.vpad / (32 * kAdjWaves));
-  // general tile: both period tables in dynamic LDS
-  const size_t glds = gen ? sizeof(uint2) * ((size_t)a.Mx + (gtab->opx == gtab->opy ? 0 : a.My)) : 0;
+  // general tile: both period tables in dynamic LDS (two-level: Whi and Wlo
+  // of each period, FP32 pairs)
+  const bool same = gen && gtab->opx == gtab->opy;
+  const size_t glds =
+      !gen ? 0
+      : a.big ? sizeof(float2) * ((size_t)a.nhx + kBigLo + (same ? 0 : (size_t)a.nhy + kBigLo))
+              : sizeof(uint2) * ((size_t)a.Mx + (same ? 0 : a.My));
   hipError_t e;
   if (a.prec == kFP32) {
-    if (gen) {
+    if (gen && a.big) {
+      static bool done = false;
+      if ((e = allow_big_lds(k_adj_gemm_fp32<true, true>, done))) return e;
+      hipLaunchKernelGGL((k_adj_gemm_fp32<true, true>), dim3(sblocks), dim3(64 * kAdjWaves), glds,
+                         st, packed, (const float2 *)gtab->opx, Wf, a.V, a.kb, a.lb, gx, gy,
+                         (const float2 *)gtab->opy, a.Mx, a.My, a.nhx, a.nhy);
+    } else if (gen) {
       static bool done = false;
       if ((e = allow_big_lds(k_adj_gemm_fp32<true>, done))) return e;
       hipLaunchKernelGGL(k_adj_gemm_fp32<true>, dim3(sblocks), dim3(64 * kAdjWaves), glds, st,
@@ -659,7 +704,23 @@ hipError_t launch_adjoint(const AdjPlan &a, const int32_t *x, const int32_t *y, 
       hipLaunchKernelGGL(k_adj_split<kFP16>, dim3(sb), dim3(256), 0, st, Wf, a.R, a.NC, a.lb,
                          wmax, whi, wlo, scale);
     const uint2 *tb = a.prec == kBF16 ? t.wbf16 : t.wfp16;
-    if (gen) {
+    if (gen && a.big) {
+      if (a.prec == kBF16) {
+        static bool done = false;
+        if ((e = allow_big_lds(k_adj_gemm_split<kBF16, true, true>, done))) return e;
+        hipLaunchKernelGGL((k_adj_gemm_split<kBF16, true, true>), dim3(sblocks),
+                           dim3(64 * kAdjWaves), glds, st, packed, (const uint2 *)gtab->opx, whi,
+                           wlo, scale, a.V, a.kb, a.lb, gx, gy, (const uint2 *)gtab->opy, a.Mx,
+                           a.My, a.nhx, a.nhy);
+      } else {
+        static bool done = false;
+        if ((e = allow_big_lds(k_adj_gemm_split<kFP16, true, true>, done))) return e;
+        hipLaunchKernelGGL((k_adj_gemm_split<kFP16, true, true>), dim3(sblocks),
+                           dim3(64 * kAdjWaves), glds, st, packed, (const uint2 *)gtab->opx, whi,
+                           wlo, scale, a.V, a.kb, a.lb, gx, gy, (const uint2 *)gtab->opy, a.Mx,
+                           a.My, a.nhx, a.nhy);
+      }
+    } else if (gen) {
       if (a.prec == kBF16) {
         static bool done = false;
         if ((e = allow_big_lds(k_adj_gemm_split<kBF16, true>, done))) return e;

@@ -1522,9 +1522,12 @@ fcfs_status fcfs_step_plan_destroy(fcfs_step_plan *plan) {
 }
 
 namespace {
+// The adjoint stages both two-level tables in LDS beside its operand
+// buffers: periods up to 2^23 (at most 2048 entries of Whi each).
+constexpr int kAdjBigMaxHi = 2048;
 constexpr const char *kAdjBigMsg =
-    "the adjoint takes periods Nx 2^frac_bits, Ny 2^frac_bits up to 8192 (two-level tables are "
-    "built for the forward transform)";
+    "the adjoint takes periods Nx 2^frac_bits, Ny 2^frac_bits up to 2^23";
+bool adj_big_ok(const FwdPlan &q) { return !q.big || (q.nhx <= kAdjBigMaxHi && q.nhy <= kAdjBigMaxHi); }
 }  // namespace
 
 fcfs_status fcfs_general_adjoint_workspace_size(const fcfs_gclip *c, fcfs_precision p,
@@ -1533,7 +1536,7 @@ fcfs_status fcfs_general_adjoint_workspace_size(const fcfs_gclip *c, fcfs_precis
   FwdPlan q;
   fcfs_status st = make_plan_general(nullptr, c, (int)p, &q);
   if (st) return st;
-  if (q.big) return fail(nullptr, FCFS_ERR_UNSUPPORTED, kAdjBigMsg);
+  if (!adj_big_ok(q)) return fail(nullptr, FCFS_ERR_UNSUPPORTED, kAdjBigMsg);
   fcfs::AdjPlan a;
   if ((st = make_adj_plan(nullptr, c->V, fcfs::kTabN, c->K, c->L, c->K, c->L, (int)p, &a)))
     return st;
@@ -1548,7 +1551,7 @@ fcfs_status fcfs_adjoint_general(fcfs_handle *h, const fcfs_gclip *c, const floa
   if (st) return st;
   FwdPlan q;
   if ((st = make_plan_general(h, c, (int)p, &q))) return st;
-  if (q.big) return fail(h, FCFS_ERR_UNSUPPORTED, kAdjBigMsg);
+  if (!adj_big_ok(q)) return fail(h, FCFS_ERR_UNSUPPORTED, kAdjBigMsg);
   if (c->V > 0 && (!c->x || !c->y || !c->s))
     return fail(h, FCFS_ERR_INVALID_ARG, "corner arrays are NULL");
   if (!grad_F) return fail(h, FCFS_ERR_INVALID_ARG, "grad_F is NULL");
@@ -1566,6 +1569,9 @@ fcfs_status fcfs_adjoint_general(fcfs_handle *h, const fcfs_gclip *c, const floa
   a.T = q.Mx;
   a.Mx = q.Mx;
   a.My = q.My;
+  a.big = q.big;
+  a.nhx = q.nhx;
+  a.nhy = q.nhy;
   // derivative factors of the general alpha (see fcfs_forward_general)
   a.rx = std::sqrt((double)q.My / (double)q.Mx);
   a.ry = std::sqrt((double)q.Mx / (double)q.My);
@@ -1576,11 +1582,11 @@ fcfs_status fcfs_adjoint_general(fcfs_handle *h, const fcfs_gclip *c, const floa
                     std::to_string(ws_bytes));
   if (!ws || ((uintptr_t)ws & 255u)) return fail(h, FCFS_ERR_WORKSPACE, "workspace NULL or misaligned");
   fcfs_handle::GenTab tx, ty;
-  if ((st = gen_tables(h, q.Mx, q.My, &tx, &ty))) return st;
+  if ((st = gen_tables(h, q.Mx, q.My, &tx, &ty, q.big != 0))) return st;
   fcfs::PeriodTables pt;
   pt.w64x = tx.w64;
   pt.w64y = ty.w64;
-  switch (a.prec) {
+  switch (q.big ? fcfs::kFP32 : a.prec) {
     case fcfs::kFP32: pt.opx = tx.w32; pt.opy = ty.w32; break;
     case fcfs::kBF16: pt.opx = tx.wbf16; pt.opy = ty.wbf16; break;
     default: pt.opx = tx.wfp16; pt.opy = ty.wfp16; break;

@@ -181,4 +181,46 @@ __device__ __forceinline__ void mma(f32x16 (&acc)[NKB][NLB][4], const Frag<NKB, 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Two-level twiddles (periods past 8192): entry p of a table of nh entries of
+// Whi followed by kBigLo of Wlo is Whi[p >> kBigBits] x Wlo[p mod kBigLo].
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+
+__device__ __forceinline__ float2 big_entry(const float2 *t, int nh, uint32_t p) {
+  return cmulf(t[p >> kBigBits], t[nh + (p & (uint32_t)(kBigLo - 1))]);
+}
+
+__device__ __forceinline__ double2 big_entry64(const double2 *__restrict__ t, int nh, uint32_t p) {
+  const double2 a = t[p >> kBigBits], b = t[nh + (p & (uint32_t)(kBigLo - 1))];
+  return make_double2(a.x * b.x - a.y * b.y, a.y * b.x + a.x * b.y);
+}
+
+// Round to nearest even of an FP32 value to bf16 (bit pattern), finite input.
+__device__ __forceinline__ uint32_t bf16_rne(float v) {
+  const uint32_t u = __float_as_uint(v);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+// Split entry {hi(c)|hi(s)<<16, lo(c)|lo(s)<<16} of w (the layout of the
+// host-built split tables), rounded in the kernel.
+template <int PREC>
+__device__ __forceinline__ uint2 split_entry(float2 w) {
+  if constexpr (PREC == kBF16) {
+    const uint32_t hc = bf16_rne(w.x), hs = bf16_rne(w.y);
+    const uint32_t lc = bf16_rne(w.x - __uint_as_float(hc << 16));
+    const uint32_t ls = bf16_rne(w.y - __uint_as_float(hs << 16));
+    return make_uint2(hc | hs << 16, lc | ls << 16);
+  } else {
+    const _Float16 hc = (_Float16)w.x, hs = (_Float16)w.y;
+    const _Float16 lc = (_Float16)(w.x - (float)hc), ls = (_Float16)(w.y - (float)hs);
+    return make_uint2((uint32_t)__builtin_bit_cast(uint16_t, hc) |
+                          (uint32_t)__builtin_bit_cast(uint16_t, hs) << 16,
+                      (uint32_t)__builtin_bit_cast(uint16_t, lc) |
+                          (uint32_t)__builtin_bit_cast(uint16_t, ls) << 16);
+  }
+}
+
 }  // namespace fcfs

@@ -248,6 +248,7 @@ struct AdjPlan {
   // dcf = 2^-F / sqrt(Nx Ny) replaces 1/T in the axis and DC terms
   bool gen;
   int Mx, My;
+  int big, nhx, nhy;  // periods past 8192: two-level tables (nh entries of Whi)
   double rx, ry, dcf;
 };
 

@@ -247,11 +247,6 @@ __device__ __forceinline__ double2 rot(double2 v, double2 r) {
   return make_double2(v.x * r.x - v.y * r.y, v.y * r.x + v.x * r.y);
 }
 
-// Entry p of a two-level FP64 table (nh entries of Whi, then Wlo).
-__device__ __forceinline__ double2 big_entry64(const double2 *__restrict__ t, int nh, uint32_t p) {
-  return rot(t[p >> kBigBits], t[nh + (p & (uint32_t)(kBigLo - 1))]);
-}
-
 // Phase and table entry of a general tile: one-level (residue tables) or
 // two-level for periods past 8192 (BIG).
 template <bool BIG>

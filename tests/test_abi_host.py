@@ -134,11 +134,15 @@ def test_general_workspace_sizes(lib):
                                                 ctypes.byref(band)) == -1
     assert lib.fcfs_general_band_workspace_size(ctypes.byref(c), 3, 3, float("nan"), 1,
                                                 ctypes.byref(band)) == -1
-    # periods past 8192 take the two-level tables (forward only); past 2^24
-    # they are rejected
+    # periods past 8192 take the two-level tables (the adjoint up to 2^23);
+    # past 2^24 they are rejected
     c.Nx = 9000
     assert lib.fcfs_general_workspace_size(ctypes.byref(c), 1, ctypes.byref(full)) == 0
+    assert lib.fcfs_general_adjoint_workspace_size(ctypes.byref(c), 1, ctypes.byref(full)) == 0
+    c.Nx, c.Ny, c.frac_bits = 3000, 3000, 12
+    assert lib.fcfs_general_workspace_size(ctypes.byref(c), 1, ctypes.byref(full)) == 0
     assert lib.fcfs_general_adjoint_workspace_size(ctypes.byref(c), 1, ctypes.byref(full)) == -4
+    c.Ny, c.frac_bits = 6000, 0
     c.Nx, c.frac_bits = 4097, 12
     assert lib.fcfs_general_workspace_size(ctypes.byref(c), 1, ctypes.byref(full)) == -4
     c.Nx = 4096

@@ -375,10 +375,66 @@ def test_general_two_level_layout_clip(P, oracle_lib):
     assert e <= TOL["bf16"]
 
 
-def test_general_two_level_adjoint_refused(P):
-    clip = synth.clip(46, 24000, 20, n_polygons=20)
-    x, y, s, _, _ = P.loops_to_corners(clip.xy, clip.off)
+@pytest.mark.parametrize("Nx,Ny,F,K,L,seed", [
+    (3000, 2000, 3, 37, 45, 61),      # periods 24000 x 16000
+    (5000, 5000, 2, 40, 40, 62),      # equal periods past 8192 (one table)
+    (1000, 700, 13, 30, 28, 63),      # periods 8192000 x 5734400 (grid step 2^-13)
+])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_general_two_level_adjoint(P, oracle_lib, Nx, Ny, F, K, L, seed, prec):
+    X, off = _fine_grid_clip(seed, Nx, Ny, F, K, L, 40)
+    xy = X.astype(np.float64) / 2 ** F
+    G = _rand_G(K, L, seed)
+    want = oracle_lib.edge_grad_general(xy, off, Nx, Ny, K, L, G.astype(np.complex64),
+                                        frac_bits=F)
+    x, y, s, he, ve = P.loops_to_corners(X, off)
+    Gd = torch.as_tensor(G.astype(np.complex64)).cuda()
+    _say(f"two-level adjoint {Nx}x{Ny} F={F} K={K} L={L} {prec}")
+    gx, gy = P.adjoint_general(x, y, s, Nx, Ny, K, L, Gd, frac_bits=F, precision=prec)
+    got = P.edge_grad(gx, gy, he, ve, x.size).cpu().numpy().astype(np.float64)
+    e = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+    _say(f"  err/max|g| = {e:.3e}")
+    assert e <= GTOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_general_two_level_autograd(P, oracle_lib, prec):
+    # edges moved by multiples of 2^-10 on a 600 x 420 tile (periods 614400 x
+    # 430080): loss sum |F|^2, forward and gradient against the oracle at the
+    # moved corners
+    Nx, Ny, F, K = 600, 420, 10, 24
+    clip = synth.clip(57, 420, K, n_polygons=12)
+    geom = P.Geometry(clip.xy, clip.off, Nx, K, Ny=Ny, frac_bits=F)
+    rng = np.random.default_rng(10)
+    offs = rng.integers(-700, 701, geom.n_edges) / 1024.0
+    off = torch.tensor(offs, dtype=torch.float32, device="cuda", requires_grad=True)
+    Fv = P.FCFSFunction.apply(off, geom, prec)
+    (Fv.abs() ** 2).sum().backward()
+    torch.cuda.synchronize()
+    xy = clip.xy.astype(np.float64).copy()
+    for m in range(clip.off.size - 1):
+        a0, a1 = clip.off[m], clip.off[m + 1]
+        for e in range(a0, a1):
+            b = a0 + (e - a0 + 1) % (a1 - a0)
+            axis = 0 if clip.xy[e, 0] == clip.xy[b, 0] else 1
+            xy[e, axis] += offs[e]
+            xy[b, axis] += offs[e]
+    ref, _ = oracle_lib.cfs_grid_general(xy, clip.off, Nx, Ny, K, K, frac_bits=F)
+    Fg = Fv.detach().cpu().numpy().astype(np.complex128)
+    ef = float(np.max(np.abs(Fg - ref)) / abs(ref[K, K]))
+    want = oracle_lib.edge_grad_general(xy, clip.off, Nx, Ny, K, K, 2 * ref, frac_bits=F)
+    got = off.grad.cpu().numpy().astype(np.float64)
+    e = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+    _say(f"two-level autograd {prec}: F err/|F00| = {ef:.3e}, grad err/max|g| = {e:.3e}")
+    assert ef <= TOL[prec]
+    assert e <= GTOL[prec]
+
+
+def test_general_two_level_adjoint_limit(P):
+    # the adjoint takes periods up to 2^23; 3000 x 2^12 is past that
+    clip = synth.clip(46, 3000, 20, n_polygons=20)
+    x, y, s, _, _ = P.loops_to_corners(clip.xy.astype(np.int64) << 12, clip.off)
     g = torch.zeros((41, 41), dtype=torch.complex64, device="cuda")
     with pytest.raises(P.FcfsError) as ei:
-        P.adjoint_general(x, y, s, 3000, 3000, 20, 20, g, frac_bits=3)
+        P.adjoint_general(x, y, s, 3000, 3000, 20, 20, g, frac_bits=12)
     assert ei.value.status == -4
