@@ -153,3 +153,24 @@ def test_general_edge_grad_square_tile_matches_square_oracle(oracle_lib):
     g1 = oracle_lib.edge_grad_general(clip.xy.astype(float), clip.off, 64, 64, 6, 5, G)
     g2 = oracle_lib.edge_grad(clip.xy, clip.off, 64, 6, 5, G)
     assert np.max(np.abs(g1 - g2)) <= 1e-12 * np.max(np.abs(g2))
+
+
+@pytest.mark.parametrize("Nx,Ny,F", [(7, 5, 13), (1000, 700, 13), (3000, 2000, 3)])
+def test_general_fine_grid_rectangle_closed_form(oracle_lib, Nx, Ny, F):
+    # a rectangle with corners on the grid of step 2^-F, periods Nx 2^F up to
+    # 2^23 grid units: the coefficients are the product of the two 1-D
+    # interval integrals over sqrt(Nx Ny) (the separable closed form)
+    rng = np.random.default_rng(F * 1000 + Nx)
+    s = 2.0 ** -F
+    x0 = rng.integers(0, (Nx << F) // 2) * s
+    y0 = rng.integers(0, (Ny << F) // 2) * s
+    x1 = x0 + rng.integers(1, (Nx << F) // 3) * s
+    y1 = y0 + rng.integers(1, (Ny << F) // 3) * s
+    xy = np.array([[x0, y0], [x0, y1], [x1, y1], [x1, y0]])  # clockwise, y up
+    off = np.array([0, 4], np.int64)
+    K, L = 9, 7
+    Fo, area = oracle_lib.cfs_grid_general(xy, off, Nx, Ny, K, L, frac_bits=F)
+    G = np.outer(H.rect_interval(x0, x1, np.arange(-K, K + 1), Nx),
+                 H.rect_interval(y0, y1, np.arange(-L, L + 1), Ny)) / np.sqrt(Nx * Ny)
+    assert area == round((x1 - x0) * (y1 - y0) * 4 ** F)
+    assert np.max(np.abs(Fo - G)) <= 1e-9 * abs(G[K, L])
