@@ -317,7 +317,7 @@ void finish_plan(FwdPlan &q, int64_t tiles, int wg_per_cu, int chunk_mult, bool 
 // r2 >= 0: only the pupil k^2 + l^2 <= r2 is kept (tiles wholly outside it
 // are skipped and the split count is sized for the remaining ones).
 // lattice: the plan of the lattice (FFT) form: no contraction partials or
-// guard block, but the bin counters, corner list and row transforms.
+// guard region, but the bin counters, corner list and row transforms.
 fcfs_status make_plan(fcfs_handle *h, int64_t V, int T, int K, int L, int prec, int tile,
                       FwdPlan *p, double r2 = -1.0, bool lattice = false) {
   fcfs_status st = check_dims(h, V, T, K, L, prec);
@@ -488,7 +488,7 @@ fcfs_status run_forward(fcfs_handle *h, const fcfs_clip *c, const FwdPlan &p, vo
   }
   if (side && (e = hipEventRecord(h->ev_fork, h->stream))) return hip_fail(h, e, "fork");
   // the contraction is enqueued first so that it starts right after the
-  // pre-pass; the histograms, guard block and axis DFTs run beside it on the
+  // pre-pass; the histograms, guard region and axis DFTs run beside it on the
   // side stream
   if (grid2d) {
     ProfScope ps(h, kProfContract);
