@@ -276,6 +276,23 @@ fcfs_status fcfs_pupil_step_plan(fcfs_handle *h, const int32_t *base_x, const in
 fcfs_status fcfs_step_plan_launch(fcfs_handle *h, fcfs_step_plan *plan);
 fcfs_status fcfs_step_plan_destroy(fcfs_step_plan *plan);
 
+/* Batch of general tiles (fcfs_forward_general for every clip c[0..n-1],
+ * each with its own periods, grid step, cut-offs, corners and outputs) as one
+ * captured graph, in the manner of fcfs_pupil_step_plan: the workspace holds
+ * one 256-byte aligned slice per clip (fcfs_general_batch_workspace_size);
+ * the plan runs every clip once eagerly (the outputs hold the result), then
+ * captures all their launches on a stream of its own.  Replays
+ * (fcfs_step_plan_launch) recompute every clip from the current contents of
+ * the corner arrays.  The period tables the graph reads are pinned in the
+ * handle's cache until the plan is destroyed (the cache grows past its 16
+ * entries rather than evict a pinned table).  Buffers, workspace and handle
+ * must outlive the plan, as for fcfs_pupil_step_plan. */
+fcfs_status fcfs_general_batch_workspace_size(const fcfs_gclip *c, int32_t n, fcfs_precision p,
+                                              size_t *bytes);
+fcfs_status fcfs_general_batch_plan(fcfs_handle *h, const fcfs_gclip *c, int32_t n,
+                                    fcfs_precision p, void *ws, size_t ws_bytes,
+                                    fcfs_step_plan **plan);
+
 /* Pruned continuous Haar transform (PCHT, Sec. III-B1) of the polygons of one
  * tile [0,Nx) x [0,Ny): the inner products of the sum of polygon indicators
  * with the 2-D Haar basis of Sec. II-B (scaling function phi_{0,0,0} and the

@@ -609,6 +609,61 @@ class PupilStep:
             pass
 
 
+class GeneralBatch:
+    """Many general tiles (``forward_general`` each) captured once into a
+    graph (``fcfs_general_batch_plan``) and replayed by ``run()``.  ``clips``
+    holds ``(x, y, s, Nx, Ny, K, L, frac_bits)`` per clip (corners in grid
+    units); ``F`` and ``area`` are the plan's output tensors, overwritten by
+    every run, which recomputes from the current contents of the corner
+    tensors (``corners[i]``).  The plan holds its own workspace."""
+
+    def __init__(self, clips, precision="bf16", handle=None):
+        import torch
+
+        h = self.handle = handle or default_handle()
+        h.sync_stream()
+        dev = h.device
+        self.corners, self.F, self.area = [], [], []
+        cs = (FcfsGClip * len(clips))()
+        for i, (x, y, s, Nx, Ny, K, L, fb) in enumerate(clips):
+            x, y, s = _corners_on(dev, x, y, s)
+            F = torch.empty((2 * K + 1, 2 * L + 1), dtype=torch.complex64, device=dev)
+            a = torch.empty(1, dtype=torch.int64, device=dev)
+            self.corners.append((x, y, s))
+            self.F.append(F)
+            self.area.append(a)
+            cs[i] = FcfsGClip(x.data_ptr(), y.data_ptr(), s.data_ptr(), x.numel(), int(Nx),
+                              int(Ny), int(fb), int(K), int(L), F.data_ptr(), a.data_ptr())
+        self._clips = cs
+        nb = ctypes.c_size_t(0)
+        check(h.lib.fcfs_general_batch_workspace_size(cs, len(clips), _prec(precision),
+                                                      ctypes.byref(nb)))
+        self._ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=dev)
+        self._plan = ctypes.c_void_p()
+        check(h.lib.fcfs_general_batch_plan(h.ptr, cs, len(clips), _prec(precision),
+                                            ctypes.c_void_p(self._ws.data_ptr()),
+                                            ctypes.c_size_t(self._ws.numel()),
+                                            ctypes.byref(self._plan)), h.ptr)
+
+    def run(self):
+        """Replays the batch; returns the list of output grids."""
+        h = self.handle
+        h.sync_stream()
+        check(h.lib.fcfs_step_plan_launch(h.ptr, self._plan), h.ptr)
+        return self.F
+
+    def close(self):
+        if self._plan:
+            self.handle.lib.fcfs_step_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 @functools.lru_cache(maxsize=64)
 def _step_workspace_size(V, T, K, L, kmax, lmax, rad, prec) -> int:
     nb = ctypes.c_size_t(0)

@@ -36,6 +36,7 @@ EXPORTS = (
     "fcfs_pupil_loss_workspace_size", "fcfs_pupil_loss",
     "fcfs_pupil_step_workspace_size", "fcfs_pupil_step", "fcfs_pupil_step_plan",
     "fcfs_step_plan_launch", "fcfs_step_plan_destroy",
+    "fcfs_general_batch_workspace_size", "fcfs_general_batch_plan",
     "fcfs_adjoint", "fcfs_adjoint_band", "fcfs_edge_grad",
     "fcfs_apply_edge_offsets", "fcfs_batch_workspace_size", "fcfs_forward_batch", "fcfs_plan_destroy",
     "fcfs_debug_phases", "fcfs_autotune", "fcfs_autotune_batch", "fcfs_batch_choice",
@@ -149,6 +150,9 @@ def load() -> ctypes.CDLL:
                                  ctypes.c_double, P, P, c_int, P, P, P, P, ctypes.c_size_t,
                                  ctypes.POINTER(P)],
         "fcfs_step_plan_launch": [P, P],
+        "fcfs_general_batch_workspace_size": [ctypes.POINTER(FcfsGClip), i32, c_int, sz],
+        "fcfs_general_batch_plan": [P, ctypes.POINTER(FcfsGClip), i32, c_int, P, ctypes.c_size_t,
+                                    ctypes.POINTER(P)],
         "fcfs_step_plan_destroy": [P],
         "fcfs_haar": [P, ctypes.POINTER(FcfsHaarClip), P, ctypes.c_size_t],
         "fcfs_adjoint": [P, clip_p, P, P, P, c_int, P, ctypes.c_size_t],

@@ -45,7 +45,8 @@ struct fcfs_handle {
   // per-period tables of the general-tile path, built on first use
   struct GenTab {
     int N = 0;
-    int nh = 0;  // > 0: two-level table (nh entries of Whi, then Wlo)
+    int nh = 0;    // > 0: two-level table (nh entries of Whi, then Wlo)
+    int pins = 0;  // plans whose graphs hold this table (never evicted meanwhile)
     double2 *w64 = nullptr;
     float2 *w32 = nullptr;
     uint2 *wbf16 = nullptr, *wfp16 = nullptr;
@@ -72,11 +73,16 @@ struct fcfs_plan {
 };
 
 // A captured optimisation step (fcfs_pupil_step) replayed as one graph.
+// A captured sequence of launches (an optimisation step, or a batch of
+// general-tile forwards): the graph, and the period tables it pins in the
+// handle's cache as (period, two-level) pairs.
 struct fcfs_step_plan {
   int device = 0;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  fcfs_handle *h = nullptr;
+  std::vector<std::pair<int, bool>> pinned;
 };
 
 namespace {
@@ -620,7 +626,7 @@ fcfs_status gen_tables(fcfs_handle *h, int Mx, int My, fcfs_handle::GenTab *tx,
       if (e) return hip_fail(h, e, "hipDeviceSynchronize");
       for (size_t i = 0; i < h->gen_tabs.size(); ++i) {
         auto &t = h->gen_tabs[i];
-        if (match(t, Mx) || match(t, My)) continue;
+        if (match(t, Mx) || match(t, My) || t.pins > 0) continue;
         (void)hipFree(t.w64);
         (void)hipFree(t.w32);
         (void)hipFree(t.wbf16);
@@ -1449,6 +1455,13 @@ static void step_plan_free(fcfs_step_plan *p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap) (void)hipStreamDestroy(p->cap);
+  if (p->h)
+    for (const auto &pk : p->pinned)
+      for (auto &t : p->h->gen_tabs)
+        if (t.N == pk.first && (t.nh > 0) == pk.second && t.pins > 0) {
+          --t.pins;
+          break;
+        }
   delete p;
 }
 
@@ -1486,6 +1499,111 @@ fcfs_status fcfs_pupil_step_plan(fcfs_handle *h, const int32_t *base_x, const in
   }
   st = fcfs_pupil_step(h, base_x, base_y, s, hedge, vedge, offsets, V, T, K, L, kmax, lmax, radius,
                        G, H, p, loss, g_edge, F_out, ws, ws_bytes);
+  e = hipStreamEndCapture(q->cap, &q->graph);
+  h->stream = saved;
+  h->prof = prof;
+  if (st) {
+    step_plan_free(q);
+    return st;
+  }
+  if (e) {
+    step_plan_free(q);
+    return hip_fail(h, e, "hipStreamEndCapture");
+  }
+  if ((e = hipGraphInstantiate(&q->exec, q->graph, nullptr, nullptr, 0))) {
+    step_plan_free(q);
+    return hip_fail(h, e, "hipGraphInstantiate");
+  }
+  *out = q;
+  return FCFS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batch of general-tile forwards: one workspace slice per clip, every clip's
+// launches captured once into one graph.
+// ---------------------------------------------------------------------------
+namespace {
+fcfs_status general_batch_offsets(fcfs_handle *h, const fcfs_gclip *c, int32_t n, int prec,
+                                  std::vector<size_t> *off, size_t *total) {
+  if (!c || n < 1) return fail(h, FCFS_ERR_INVALID_ARG, "empty batch");
+  size_t o = 0;
+  off->assign((size_t)n + 1, 0);
+  for (int32_t i = 0; i < n; ++i) {
+    size_t b = 0;
+    fcfs_status st = general_ws_bytes(&c[i], prec, -1, -1, -1.0, &b);
+    if (st) return st;
+    (*off)[i] = o;
+    o += align256(b);
+  }
+  (*off)[n] = o;
+  *total = o;
+  return FCFS_OK;
+}
+}  // namespace
+
+fcfs_status fcfs_general_batch_workspace_size(const fcfs_gclip *c, int32_t n, fcfs_precision p,
+                                              size_t *bytes) {
+  if (!bytes) return fail(nullptr, FCFS_ERR_INVALID_ARG, "NULL argument");
+  std::vector<size_t> off;
+  return general_batch_offsets(nullptr, c, n, (int)p, &off, bytes);
+}
+
+fcfs_status fcfs_general_batch_plan(fcfs_handle *h, const fcfs_gclip *c, int32_t n,
+                                    fcfs_precision p, void *ws, size_t ws_bytes,
+                                    fcfs_step_plan **out) {
+  fcfs_status st = enter(h);
+  if (st) return st;
+  if (!out) return fail(h, FCFS_ERR_INVALID_ARG, "plan pointer is NULL");
+  *out = nullptr;
+  std::vector<size_t> off;
+  size_t total = 0;
+  if ((st = general_batch_offsets(h, c, n, (int)p, &off, &total))) return st;
+  if (ws_bytes < total)
+    return fail(h, FCFS_ERR_WORKSPACE, "workspace too small: need " + std::to_string(total) +
+                                           " bytes, got " + std::to_string(ws_bytes));
+  if (!ws || ((uintptr_t)ws & 255u)) return fail(h, FCFS_ERR_WORKSPACE, "workspace NULL or misaligned");
+  auto slice = [&](int32_t i) { return (void *)((char *)ws + off[i]); };
+  // one eager pass: validates every clip, builds the period tables (pinned
+  // at once, so that later clips of the batch cannot evict them: the cache
+  // grows past its size instead) and leaves the outputs
+  auto *q = new fcfs_step_plan;
+  q->device = h->device;
+  q->h = h;
+  for (int32_t i = 0; i < n; ++i) {
+    FwdPlan fp;
+    if ((st = fcfs_forward_general(h, &c[i], p, slice(i), off[i + 1] - off[i])) ||
+        (st = make_plan_general(h, &c[i], (int)p, &fp))) {
+      step_plan_free(q);
+      return st;
+    }
+    for (int N : {fp.Mx, fp.My}) {
+      const std::pair<int, bool> key(N, fp.big != 0);
+      if (std::find(q->pinned.begin(), q->pinned.end(), key) != q->pinned.end()) continue;
+      for (auto &g : h->gen_tabs)
+        if (g.N == N && (g.nh > 0) == key.second) {
+          ++g.pins;
+          q->pinned.push_back(key);
+          break;
+        }
+    }
+  }
+  hipError_t e = hipStreamCreateWithFlags(&q->cap, hipStreamNonBlocking);
+  if (e) {
+    step_plan_free(q);
+    return hip_fail(h, e, "plan stream");
+  }
+  const hipStream_t saved = h->stream;
+  const bool prof = h->prof;
+  h->prof = false;
+  h->stream = q->cap;
+  if ((e = hipStreamBeginCapture(q->cap, hipStreamCaptureModeThreadLocal))) {
+    h->stream = saved;
+    h->prof = prof;
+    step_plan_free(q);
+    return hip_fail(h, e, "hipStreamBeginCapture");
+  }
+  for (int32_t i = 0; i < n && !st; ++i)
+    st = fcfs_forward_general(h, &c[i], p, slice(i), off[i + 1] - off[i]);
   e = hipStreamEndCapture(q->cap, &q->graph);
   h->stream = saved;
   h->prof = prof;

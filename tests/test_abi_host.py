@@ -151,6 +151,25 @@ def test_general_workspace_sizes(lib):
     assert lib.fcfs_general_workspace_size(ctypes.byref(c), 1, ctypes.byref(full)) == 0
 
 
+def test_general_batch_workspace_size(lib):
+    # one 256-byte aligned slice per clip; an empty batch is rejected
+    from paper_1010_5562_amd import _lib
+
+    specs = [(200000, 8000, 6000, 0, 511, 511), (3000, 3000, 2000, 3, 40, 33),
+             (500, 7, 5, 3, 30, 29)]
+    cs = (_lib.FcfsGClip * 3)(*[_lib.FcfsGClip(None, None, None, V, Nx, Ny, F, K, L, None, None)
+                                for V, Nx, Ny, F, K, L in specs])
+    each = []
+    for c in cs:
+        n = ctypes.c_size_t(0)
+        assert lib.fcfs_general_workspace_size(ctypes.byref(c), 1, ctypes.byref(n)) == 0
+        each.append((n.value + 255) // 256 * 256)
+    total = ctypes.c_size_t(0)
+    assert lib.fcfs_general_batch_workspace_size(cs, 3, 1, ctypes.byref(total)) == 0
+    assert total.value == sum(each)
+    assert lib.fcfs_general_batch_workspace_size(cs, 0, 1, ctypes.byref(total)) == -1
+
+
 def test_pupil_step_workspace_size(lib):
     n = ctypes.c_size_t(0)
     assert lib.fcfs_pupil_step_workspace_size(100000, 4096, 255, 255, 89, 89, 89.25, 1,

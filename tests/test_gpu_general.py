@@ -438,3 +438,43 @@ def test_general_two_level_adjoint_limit(P):
     with pytest.raises(P.FcfsError) as ei:
         P.adjoint_general(x, y, s, 3000, 3000, 20, 20, g, frac_bits=12)
     assert ei.value.status == -4
+
+
+def test_general_batch_graph(P, oracle_lib):
+    # clips of different periods, grid steps and cut-offs (two of them past
+    # 8192 grid units) in one captured graph: the eager pass equals the single
+    # calls bit for bit, replays repeat it, the oracle agrees
+    specs = [(3000, 2000, 0, 40, 33, 150, 71), (750, 1000, 2, 37, 45, 150, 72),
+             (1000, 700, 13, 30, 28, 60, 73), (3000, 2000, 3, 41, 29, 100, 74),
+             (7, 5, 3, 30, 29, 6, 75)]
+    clips, refs = [], []
+    for Nx, Ny, F, K, L, npol, seed in specs:
+        if Nx < 100:  # a tiny tile: polygons drawn on the grid itself
+            c = synth.clip(seed, max(Nx, Ny) << F, K, L, n_polygons=npol)
+            X, off = c.xy, c.off
+        else:
+            X, off = _fine_grid_clip(seed, Nx, Ny, F, K, L, npol)
+        x, y, s, _, _ = P.loops_to_corners(X, off)
+        clips.append((x, y, s, Nx, Ny, K, L, F))
+        refs.append(oracle_lib.cfs_grid_general(X.astype(np.float64) / 2 ** F, off, Nx, Ny, K, L,
+                                                frac_bits=F))
+    _say(f"general batch of {len(clips)} clips (graph)")
+    b = P.GeneralBatch(clips, precision="bf16")
+    torch.cuda.synchronize()
+    eager = [f.cpu().numpy().copy() for f in b.F]
+    for i, (x, y, s, Nx, Ny, K, L, F) in enumerate(clips):
+        Fs, a = P.forward_general(x, y, s, Nx, Ny, K, L, frac_bits=F, precision="bf16")
+        torch.cuda.synchronize()
+        assert np.array_equal(Fs.cpu().numpy(), eager[i]), i
+        ref, area = refs[i]
+        assert int(b.area[i].item()) == area
+        e = float(np.max(np.abs(eager[i].astype(np.complex128) - ref)) / abs(ref[K, L]))
+        assert e <= TOL["bf16"], (i, e)
+    for _ in range(2):
+        for f in b.F:
+            f.zero_()
+        b.run()
+        torch.cuda.synchronize()
+        for i in range(len(clips)):
+            assert np.array_equal(b.F[i].cpu().numpy(), eager[i]), i
+    b.close()
