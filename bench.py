@@ -592,6 +592,30 @@ def main() -> int:
             log(f"general tile {name} {prec}: {msg:.3f} ms  {pg / msg * 1e3:.4g} pairs/s  "
                 f"err {eg:.2e}  contract {cms:.3f} ms")
         gen[name] = entry
+    # Batch of general tiles in one captured graph: 32 clips of 150-600
+    # polygons on tiles of random periods (1000..6000 lattice units, grid
+    # steps 2^-F with F in 0..4, some past 8192 grid units), K = L = 127.
+    gclips, gpairs = [], 0
+    grng = np.random.default_rng(77)
+    for i in range(32):
+        Ngx, Ngy = (int(v) for v in grng.integers(1000, 6001, 2))
+        Fq = int(grng.integers(0, 5))
+        cg = synth.clip(500 + i, max(Ngx, Ngy), 127, n_polygons=int(grng.integers(150, 601)))
+        Xg = cg.xy.astype(np.int64) << Fq
+        for j in range(cg.off.size - 1):
+            Xg[cg.off[j]:cg.off[j + 1]] += grng.integers(0, 1 << Fq, 2)
+        gxg, gyg, gsg, _, _ = P.loops_to_corners(Xg.astype(np.int32), cg.off)
+        gclips.append((gxg, gyg, gsg, Ngx, Ngy, 127, 127, Fq))
+        gpairs += int(gxg.size) * 255 * 255
+    gb = P.GeneralBatch(gclips, precision="bf16")
+    msb, _ = timed(gb.run, args.steps, args.warmup, h, kinds=None)
+    gb.close()
+    gen["batch_32_general_tiles"] = {
+        "workload": (f"32 clips, {sum(int(c[0].numel()) for c in gb.corners)} corners, periods "
+                     "1000..6000 lattice units on grids of step 2^-F (F in 0..4), K = L = 127, "
+                     "one graph replay"),
+        "bf16": {"value": gpairs / (msb * 1e-3), "ms_per_step": msb}}
+    log(f"general batch of 32 tiles bf16: {msb:.3f} ms per replay  {gpairs / msb * 1e3:.4g} pairs/s")
     forms["general_tile"] = gen
 
     # ------------------------------------------------------------------ C4
