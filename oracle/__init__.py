@@ -7,7 +7,9 @@ the HIP library (``paper_1010_5562_amd``) and imports nothing from it.
 
 The arithmetic lives in ``fcfs_oracle.c`` (plain C, FP64, optional OpenMP)
 and ``pcht_oracle.c`` (plain C, int64 areas); this module only compiles them
-with gcc and marshals numpy arrays through ctypes.  See the headers of the C
+with gcc and marshals numpy arrays through ctypes.  ``edge_matmul.py`` holds
+the same edge form in numpy with the general term as one matrix product
+(``cfs_grid_matmul``), for full grids of large clips.  See the headers of the C
 files for the formulas and their sources in the paper (Prop. 3 of Sec.
 III-C1, edge form; Sec. III-B1 and Algorithm 1 for the Haar transform).
 
@@ -22,6 +24,8 @@ import os
 import subprocess
 
 import numpy as np
+
+from .edge_matmul import EdgeFormError, cfs_grid_matmul  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRCS = [os.path.join(_HERE, "fcfs_oracle.c"), os.path.join(_HERE, "pcht_oracle.c")]

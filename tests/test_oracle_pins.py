@@ -17,27 +17,41 @@ def _rect_loop(x1, y1, x2, y2):
     return synth.rectangle_loop(x1, y1, x2, y2), np.array([0, 4])
 
 
-@pytest.mark.parametrize("lattice", [True, False])
-def test_single_rectangle_sinc_product(oracle_lib, lattice):
+# Both full-grid forms of the oracle take every pin below: the C edge sums
+# (cfs_grid) and the numpy form whose general term is one matrix product
+# (cfs_grid_matmul, used for full grids of large clips).
+@pytest.fixture(params=["edge_sums", "matmul"])
+def grid(request, oracle_lib):
+    if request.param == "edge_sums":
+        return lambda xy, off, T, K, L: oracle_lib.cfs_grid(xy, off, T, K, L)
+    return lambda xy, off, T, K, L: oracle_lib.cfs_grid_matmul(xy, off, T, K, L)
+
+
+@pytest.mark.parametrize("form", ["lattice", "real", "matmul"])
+def test_single_rectangle_sinc_product(oracle_lib, form):
     # Sec. II-C basis integrated over [x1,x2) x [y1,y2): sinc product, all
     # (k, l) including the axes and DC.  dx != dy and K != L catch a k/l swap.
     T, K, L = 64, 11, 7
     x1, y1, x2, y2 = 3, 5, 20, 41
     xy, off = _rect_loop(x1, y1, x2, y2)
-    F, area = oracle_lib.cfs_grid(xy, off, T, K, L, lattice=lattice)
+    lattice = form != "real"
+    if form == "matmul":
+        F, area = oracle_lib.cfs_grid_matmul(xy, off, T, K, L)
+    else:
+        F, area = oracle_lib.cfs_grid(xy, off, T, K, L, lattice=lattice)
     G = H.rect_cfs(x1, y1, x2, y2, T, K, L)
     assert np.max(np.abs(F - G)) <= 1e-13 * abs(G[K, L])
     if lattice:
         assert area == (x2 - x1) * (y2 - y1)
 
 
-def test_rectangle_counter_clockwise_is_reversed(oracle_lib):
+def test_rectangle_counter_clockwise_is_reversed(grid):
     # Clockwise order is the paper's convention (Sec. II-A2); the reversed loop
     # describes the same set and must give the same coefficients.
     T, K = 32, 6
     xy, off = _rect_loop(2, 3, 9, 17)
-    F1, a1 = oracle_lib.cfs_grid(xy, off, T, K, K)
-    F2, a2 = oracle_lib.cfs_grid(xy[::-1].copy(), off, T, K, K)
+    F1, a1 = grid(xy, off, T, K, K)
+    F2, a2 = grid(xy[::-1].copy(), off, T, K, K)
     assert a1 == a2 == 7 * 14
     assert np.max(np.abs(F1 - F2)) <= 1e-14
 
@@ -63,26 +77,26 @@ def _union_clip(seed, T, n_polys, lo=3, hi=12):
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_exact_raster_identity(oracle_lib, seed):
+def test_exact_raster_identity(grid, seed):
     # Lattice polygons are unions of unit cells; each cell's CFS is a closed
     # form, so the sum over the rasterised cells is an exact brute force.
     # Overlapping polygons add (signal model, Sec. III-A).
     T, K, L = 48, 13, 9
     xy, off, _ = _union_clip(seed, T, 4)
-    F, area = oracle_lib.cfs_grid(xy, off, T, K, L)
+    F, area = grid(xy, off, T, K, L)
     img = H.raster(xy, off, T)
     R = H.raster_cfs(img, T, K, L)
     assert area == int(img.sum())
     assert np.max(np.abs(F - R)) <= 1e-12 * abs(R[K, L])
 
 
-def test_fft_of_corner_image(oracle_lib):
+def test_fft_of_corner_image(grid):
     # Step 4 of Sec. III-C1: the double sum is a 2-D DFT of the sparse +/-1
     # corner image.  The corner weights come from the raster (mixed second
     # difference), not from the oracle's edge walk.
     T, K, L = 64, 20, 17
     xy, off, _ = _union_clip(7, T, 3)
-    F, _ = oracle_lib.cfs_grid(xy, off, T, K, L)
+    F, _ = grid(xy, off, T, K, L)
     W = H.corner_image(H.raster(xy, off, T))
     # corners on x = T or y = T wrap to 0 under the period
     D = np.fft.fft2(_fold(W, T))
@@ -116,9 +130,11 @@ def test_area_matches_shoelace_and_dc(oracle_lib):
     F, A = oracle_lib.cfs_grid(clip.xy, clip.off, 4096, 0, 0)
     assert A == int(areas.sum())
     assert F[0, 0].real == pytest.approx(A / 4096, rel=1e-15)
+    Fm, Am = oracle_lib.cfs_grid_matmul(clip.xy, clip.off, 4096, 0, 0)
+    assert Am == A and Fm[0, 0] == F[0, 0]
 
 
-def test_linearity_and_inclusion_exclusion(oracle_lib):
+def test_linearity_and_inclusion_exclusion(grid):
     # Sec. III-A linearity: f(A u B) = f(A) + f(B) - f(A n B).
     T, K, L = 128, 9, 12
     a = (10, 20, 70, 60)
@@ -126,42 +142,42 @@ def test_linearity_and_inclusion_exclusion(oracle_lib):
     inter = (40, 35, 70, 60)
     u = synth.loops_of_rect_union([a, b])
     assert u is not None and len(u) == 1
-    Fu, Au = oracle_lib.cfs_grid(u[0], [0, u[0].shape[0]], T, K, L)
-    Fa, Aa = oracle_lib.cfs_grid(*_rect_loop(*a), T, K, L)
-    Fb, Ab = oracle_lib.cfs_grid(*_rect_loop(*b), T, K, L)
-    Fi, Ai = oracle_lib.cfs_grid(*_rect_loop(*inter), T, K, L)
+    Fu, Au = grid(u[0], [0, u[0].shape[0]], T, K, L)
+    Fa, Aa = grid(*_rect_loop(*a), T, K, L)
+    Fb, Ab = grid(*_rect_loop(*b), T, K, L)
+    Fi, Ai = grid(*_rect_loop(*inter), T, K, L)
     assert Au == Aa + Ab - Ai
     assert np.max(np.abs(Fu - (Fa + Fb - Fi))) <= 1e-12 * abs(Fu[K, L])
     # several loops in one call add up
     both = np.concatenate([synth.rectangle_loop(*a), synth.rectangle_loop(*b)])
-    F2, A2 = oracle_lib.cfs_grid(both, [0, 4, 8], T, K, L)
+    F2, A2 = grid(both, [0, 4, 8], T, K, L)
     assert A2 == Aa + Ab
     assert np.max(np.abs(F2 - (Fa + Fb))) <= 1e-12 * abs(F2[K, L])
 
 
-def test_symmetries(oracle_lib):
+def test_symmetries(grid):
     T, K, L = 256, 12, 10
     xy, off, _ = _union_clip(3, 200, 5, lo=10, hi=40)
-    F, _ = oracle_lib.cfs_grid(xy, off, T, K, L)
+    F, _ = grid(xy, off, T, K, L)
     # Hermitian: F[-k,-l] = conj F[k,l] (real signal)
     assert np.max(np.abs(F - np.conj(F[::-1, ::-1]))) <= 1e-13 * abs(F[K, L])
     # shift theorem, axes and DC included
     dx, dy = 17, -5
-    Fs, _ = oracle_lib.cfs_grid(synth.shift_loops(xy, dx, dy), off, T, K, L)
+    Fs, _ = grid(synth.shift_loops(xy, dx, dy), off, T, K, L)
     k = np.arange(-K, K + 1)[:, None]
     l = np.arange(-L, L + 1)[None, :]
     ph = np.exp(-2j * np.pi * (k * dx + l * dy) / T)
     assert np.max(np.abs(Fs - F * ph)) <= 1e-12 * abs(F[K, L])
     # translation by whole periods changes nothing (exact integer reduction)
-    Ft, _ = oracle_lib.cfs_grid(synth.shift_loops(xy, 3 * T, -2 * T), off, T, K, L)
+    Ft, _ = grid(synth.shift_loops(xy, 3 * T, -2 * T), off, T, K, L)
     assert np.max(np.abs(Ft - F)) <= 1e-12 * abs(F[K, L])
     # integer scaling by m with period m T multiplies F by m
     m = 3
-    Fm, _ = oracle_lib.cfs_grid(xy * m, off, m * T, K, L)
+    Fm, _ = grid(xy * m, off, m * T, K, L)
     assert np.max(np.abs(Fm - m * F)) <= 1e-12 * abs(Fm[K, L])
     # rotation by +90 degrees, (x, y) -> (-y, x): F'[k, l] = F[l, -k]
     rot = np.stack([-xy[:, 1], xy[:, 0]], axis=1)
-    Fr, _ = oracle_lib.cfs_grid(rot, off, T, L, K)
+    Fr, _ = grid(rot, off, T, L, K)
     # Fr is indexed [k + L, l + K]; F[l, -k] is F[l + K, -k + L]
     assert np.max(np.abs(Fr - F.T[::-1, :])) <= 1e-12 * abs(F[K, L])
 
@@ -186,6 +202,19 @@ def test_rejects_invalid_loops(oracle_lib):
     for xy, off in bad:
         with pytest.raises(oracle_lib.OracleError):
             oracle_lib.cfs_grid(xy, off, 16, 2, 2)
+        with pytest.raises(oracle_lib.EdgeFormError):
+            oracle_lib.cfs_grid_matmul(xy, off, 16, 2, 2)
+
+
+def test_matmul_form_matches_edge_sums_on_a_clip(oracle_lib):
+    # the two forms on a layout-like clip, K != L, polygons sticking out of
+    # the tile (phases reduced modulo T, moments from the raw coordinates)
+    T, K, L = 512, 21, 14
+    clip = synth.clip(9, 600, K, L, n_polygons=30)
+    F, A = oracle_lib.cfs_grid(clip.xy, clip.off, T, K, L)
+    G, B = oracle_lib.cfs_grid_matmul(clip.xy, clip.off, T, K, L)
+    assert A == B
+    assert np.max(np.abs(F - G)) <= 1e-13 * abs(F[K, L])
 
 
 def test_gradient_rectangle_closed_form(oracle_lib):
