@@ -165,11 +165,14 @@ def _pack(loops: list[np.ndarray]):
 
 
 def clip(seed: int, T: int, K: int, L: int | None = None, *, n_polygons: int | None = None,
-         min_vertices: int | None = None, disjoint: bool = False) -> Clip:
+         min_vertices: int | None = None, disjoint: bool = False,
+         size_scale: float = 1.0) -> Clip:
     """A clip of random polygons (see the module docstring for the recipe).
 
     Exactly one of ``n_polygons`` (a fixed count) or ``min_vertices`` (draw
     polygons until the total vertex count reaches it) must be given.
+    ``size_scale`` (disjoint clips only) multiplies the rectangle sizes drawn
+    for a cell (cell/20 .. cell/4 at 1.0), which sets the fill factor.
     """
     if (n_polygons is None) == (min_vertices is None):
         raise ValueError("give n_polygons or min_vertices")
@@ -190,13 +193,15 @@ def clip(seed: int, T: int, K: int, L: int | None = None, *, n_polygons: int | N
             total += p.shape[0]
     else:
         # Estimate the polygon count, then give each polygon its own cell.
-        want = n_polygons if n_polygons is not None else int(np.ceil(min_vertices / 14.0)) + 16
+        # (larger rectangles make simpler unions: fewer corners per polygon)
+        per = 14.0 if size_scale == 1.0 else 8.0
+        want = n_polygons if n_polygons is not None else int(np.ceil(min_vertices / per)) + 16
         g = int(np.ceil(np.sqrt(want)))
         cell = T // g
         if cell < 16:
             raise ValueError("too many polygons for disjoint cells")
-        lo = max(2, cell // 20)
-        hi = max(lo + 1, cell // 4)
+        lo = max(2, int(cell * size_scale) // 20)
+        hi = min(cell - 2, max(lo + 1, int(cell * size_scale) // 4))
         cells = rng.permutation(g * g)
         for c in cells:
             if n_polygons is not None and len(loops) >= n_polygons:
