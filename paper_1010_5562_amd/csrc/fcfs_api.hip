@@ -251,17 +251,20 @@ fcfs_status check_dims(fcfs_handle *h, int64_t V, int T, int K, int L, int prec)
   return FCFS_OK;
 }
 
-// Guard-span model factor of a plan (guard_span): 2 eps P / (4 pi^2 1e-5)
-// with P = Mx My and eps the per-term rounding of the split contraction,
-// 2^-17.5 for bf16 hi + lo (8 + 8 significant bits) and 2^-21.5 for fp16
-// hi + lo (11 + 11), fitted to the errors measured on low-fill clips.  The
-// FP32 form keeps the core block (its error is set by the FP32
-// accumulation, far inside its bound).
+// Guard-span model factor of a plan (guard_span): 2 eps P / (4 pi^2 tol)
+// with P = Mx My, tol the bound of the precision (1e-5 |F[0,0]| for the split
+// forms, 1e-6 for FP32) and eps the error of S(k, l) per sqrt(V):
+// 2^-17.5 for bf16 hi + lo (8 + 8 significant bits), 2^-21.5 for fp16 hi + lo
+// (11 + 11) and 2^-24.5 for FP32, the largest per-sqrt(V) errors measured at
+// the edge of the guard region on low-fill clips (fill 0.07, 30k and 200k
+// corners); the model is checked on clips of other seeds, sizes and fills.
 double guard_scale(int prec, int Mx, int My) {
-  const double eps = prec == fcfs::kBF16 ? std::ldexp(1.0, -17) * std::sqrt(0.5)
-                     : prec == fcfs::kFP16 ? std::ldexp(1.0, -21) * std::sqrt(0.5) : 0.0;
+  const double eps = prec == fcfs::kBF16   ? std::ldexp(1.0, -17) * std::sqrt(0.5)
+                     : prec == fcfs::kFP16 ? std::ldexp(1.0, -21) * std::sqrt(0.5)
+                                           : std::ldexp(1.0, -24) * std::sqrt(0.5);
+  const double tol = prec == fcfs::kFP32 ? 1e-6 : 1e-5;
   const double kPi = 3.14159265358979323846;
-  return 2.0 * eps * (double)Mx * (double)My / (4.0 * kPi * kPi * 1e-5);
+  return 2.0 * eps * (double)Mx * (double)My / (4.0 * kPi * kPi * tol);
 }
 
 // Split count, chunk and workspace layout of a forward plan whose tile grid
@@ -291,6 +294,7 @@ void finish_plan(FwdPlan &q, int64_t tiles, int wg_per_cu, int chunk_mult, bool 
   q.g_chunk = std::max<int64_t>(512, round_up(ceil_div(V, kGuardBlocks), 64));
   q.g_chunks = (int)std::max<int64_t>(1, ceil_div(V, q.g_chunk));
   q.gscale = guard_scale(q.prec, q.Mx, q.My);
+  q.gscale_alt = q.prec == fcfs::kBF16 ? guard_scale(fcfs::kFP16, q.Mx, q.My) : 0.0;
   size_t off = 0;
   q.off_packed = off;
   off += align256(sizeof(uint4) * (size_t)q.vpad);
@@ -499,7 +503,8 @@ fcfs_status run_forward(fcfs_handle *h, const fcfs_clip *c, const FwdPlan &p, vo
   if (grid2d) {
     ProfScope ps(h, kProfContract);
     if ((e = fcfs::launch_contract(p, ws_at<uint4>(ws, p.off_packed), h->tab,
-                                   ws_at<float>(ws, p.off_part), h->stream)))
+                                   ws_at<float>(ws, p.off_part), h->stream,
+                                   ws_at<unsigned long long>(ws, p.off_area))))
       return hip_fail(h, e, "contraction launch");
   }
   if (side) {
@@ -756,7 +761,9 @@ fcfs_status run_forward_general(fcfs_handle *h, const fcfs_gclip *c, const FwdPl
     }
     ProfScope ps(h, kProfContract);
     if ((e = fcfs::launch_gen_contract(p, ws_at<uint4>(ws, p.off_packed), ox, oy,
-                                       ws_at<float>(ws, p.off_part), h->stream)))
+                                       ws_at<float>(ws, p.off_part), h->stream,
+                                       ws_at<unsigned long long>(ws, p.off_area),
+                                       p.big ? nullptr : tx->wfp16, p.big ? nullptr : ty->wfp16)))
       return hip_fail(h, e, "contraction launch");
   }
   if (side) {
@@ -1756,7 +1763,8 @@ fcfs_status batch_layout(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec
   L->ax_desc.clear();
   L->items.clear();
   L->epi_off.assign(n + 1, 0);
-  size_t off = 256;  // the work counter lives at the head of the workspace
+  // the work counters live at the head of the workspace, the clips' routes next
+  size_t off = 256 + align256(sizeof(unsigned int) * (size_t)std::max(n, 1));
   std::vector<std::pair<int64_t, int4>> items;
   for (int i = 0; i < n; ++i) {
     const fcfs_clip &ci = c[i];
@@ -1787,6 +1795,7 @@ fcfs_status batch_layout(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec
     b.g_chunk = std::max<int64_t>(512, round_up(ceil_div(ci.V, kBatchGuardBlocks), 64));
     b.g_chunks = (int)std::max<int64_t>(1, ceil_div(ci.V, b.g_chunk));
     b.gscale = guard_scale(prec, ci.T, ci.T);
+    b.gscale_alt = prec == fcfs::kBF16 ? guard_scale(fcfs::kFP16, ci.T, ci.T) : 0.0;
     b.hist_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(64, ceil_div(ci.V, 1024)));
     if (ci.K > 0 && ci.L > 0)
       for (int ch = 0; ch < fcfs::kGuardGroups * b.g_chunks; ++ch)
@@ -1895,6 +1904,7 @@ fcfs_status build_plan(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec, 
   bl.n_items = (int)L.items.size();
   bl.grid = fcfs::batch_grid(p->tile, prec);
   bl.counter = ws_at<unsigned int>(ws, 0);
+  bl.route = prec == fcfs::kBF16 ? ws_at<unsigned int>(ws, 256) : nullptr;
   bl.n_epi = L.epi_off[n];
   if (!st) st = upload(h, p, L.bc, &bl.clips);
   if (!st) st = upload(h, p, L.ax_desc, &bl.ax_desc);

@@ -107,6 +107,39 @@ __device__ __forceinline__ bool tile_outside(int tile, int tiles_l, int wgk, int
   return k0 * k0 + l0 * l0 > r2;
 }
 
+// Exact area of a clip from the pre-pass partials (modulo 2^64, exact when
+// the area fits in int64), for the whole block: every thread calls it and
+// gets the same value.  Blocks of up to 1024 threads (16 waves).
+__device__ __forceinline__ long long block_area(const unsigned long long *__restrict__ area_part,
+                                                int pre_blocks) {
+  __shared__ unsigned long long s_red[16];
+  unsigned long long a = 0;
+  for (int b = threadIdx.x; b < pre_blocks; b += blockDim.x) a += area_part[b];
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  unsigned long long t = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += s_red[w];
+  __syncthreads();
+  return (long long)t;
+}
+
+// Inputs of the precision routing of a split-bf16 contraction (route_fp16):
+// the pre-pass area partials and both guard factors; gscale_alt = 0 turns the
+// routing off.
+struct RouteArgs {
+  const unsigned long long *area_part;
+  int pre_blocks;
+  int64_t V;
+  double gscale, gscale_alt;
+};
+
+// Block-uniform routing decision (every thread of a 256-thread block calls it).
+__device__ __forceinline__ bool block_route_fp16(const RouteArgs &r) {
+  if (r.gscale_alt <= 0.0) return false;
+  return route_fp16(r.gscale, r.gscale_alt, r.V, block_area(r.area_part, r.pre_blocks));
+}
+
 // ---------------------------------------------------------------------------
 // Contraction building blocks shared by the power-of-two and general-period
 // kernels: partial stores, corner loads, raw table entries, MFMA fragments.

@@ -83,22 +83,26 @@ __device__ __forceinline__ void gen_gather(E (&a)[NKB][8], E (&b)[NLB][8], const
     for (int j = 0; j < 8; ++j) b[lb][j] = flip(ty[gen_phase(g.lr[lb], g.lm[lb], c[j].y, My)], c[j].z);
 }
 
+// Both period tables in LDS (one when they coincide): Mx + 1 entries of tabx
+// (the last the zero entry), then My of taby.
+template <typename E>
+__device__ __forceinline__ E *stage_gen_tables(E *tx, const void *__restrict__ tabx,
+                                               const void *__restrict__ taby, int Mx, int My) {
+  E *ty = tabx == taby ? tx : tx + (Mx + 1);
+  for (int i = threadIdx.x; i <= Mx; i += blockDim.x) tx[i] = static_cast<const E *>(tabx)[i];
+  if (tabx != taby)
+    for (int i = threadIdx.x; i < My; i += blockDim.x) ty[i] = static_cast<const E *>(taby)[i];
+  __syncthreads();
+  return ty;
+}
+
 // PREC: kBF16 / kFP16 (E = uint2 split entries) or kFP32 (E = float2).
 template <int PREC>
-__global__ __launch_bounds__(64 * kGenWaves) void k_contract_gen(
-    const uint4 *__restrict__ packed, const void *__restrict__ tabx, const void *__restrict__ taby,
-    int Mx, int My, int64_t chunk, int tiles_l, int kp, int lp, float *__restrict__ part,
-    double r2) {
-  if (tile_outside(blockIdx.x, tiles_l, 128, 128, r2)) return;
-  using E = typename std::conditional<PREC == kFP32, float2, uint2>::type;
-  extern __shared__ uint2 lds[];
-  E *tx = reinterpret_cast<E *>(lds);
-  E *ty = tabx == taby ? tx : tx + (Mx + 1);
-  for (int i = threadIdx.x; i <= Mx; i += 64 * kGenWaves) tx[i] = static_cast<const E *>(tabx)[i];
-  if (tabx != taby)
-    for (int i = threadIdx.x; i < My; i += 64 * kGenWaves) ty[i] = static_cast<const E *>(taby)[i];
-  __syncthreads();
-
+__device__ __forceinline__ void contract_gen_body(
+    const uint4 *__restrict__ packed,
+    const typename std::conditional<PREC == kFP32, float2, uint2>::type *tx,
+    const typename std::conditional<PREC == kFP32, float2, uint2>::type *ty, int Mx, int My,
+    int64_t chunk, int tiles_l, int kp, int lp, float *__restrict__ part) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 31, lh = lane >> 5;
   const int tk = blockIdx.x / tiles_l, tl = blockIdx.x % tiles_l;
@@ -148,6 +152,29 @@ __global__ __launch_bounds__(64 * kGenWaves) void k_contract_gen(
   store_part<kGenNKB, kGenNLB>(part, acc, split, kp, lp, k0, l0, li, lh);
 }
 
+// Split-bf16 launches take the split-fp16 tables of both periods as well: a
+// clip the rounding model routes to split-fp16 (block_route_fp16) runs the
+// fp16 form.
+template <int PREC>
+__global__ __launch_bounds__(64 * kGenWaves) void k_contract_gen(
+    const uint4 *__restrict__ packed, const void *__restrict__ tabx, const void *__restrict__ taby,
+    int Mx, int My, int64_t chunk, int tiles_l, int kp, int lp, float *__restrict__ part,
+    double r2, RouteArgs ra, const void *__restrict__ tabx16, const void *__restrict__ taby16) {
+  if (tile_outside(blockIdx.x, tiles_l, 128, 128, r2)) return;
+  using E = typename std::conditional<PREC == kFP32, float2, uint2>::type;
+  extern __shared__ uint2 lds[];
+  if constexpr (PREC == kBF16) {
+    if (block_route_fp16(ra)) {
+      const uint2 *ty = stage_gen_tables<uint2>(lds, tabx16, taby16, Mx, My);
+      contract_gen_body<kFP16>(packed, lds, ty, Mx, My, chunk, tiles_l, kp, lp, part);
+      return;
+    }
+  }
+  E *tx = reinterpret_cast<E *>(lds);
+  const E *ty = stage_gen_tables<E>(tx, tabx, taby, Mx, My);
+  contract_gen_body<PREC>(packed, tx, ty, Mx, My, chunk, tiles_l, kp, lp, part);
+}
+
 // Byte offset base + 8 ((f x) mod M) of the table entry, from the lane
 // constants fr8 = 8 (f mod M), m = gen_magic(f mod M, M) and M8 = 8 M: the
 // quotient is that of gen_phase, and both 24-bit products stay below 2^29.
@@ -193,22 +220,13 @@ __device__ __forceinline__ void gen_pipe_schedule() {
   }
 }
 
+// lds: both tables staged (a static array at LDS address 0, so the lookups
+// need no base add); one_tab: the two periods share one table.
 template <int PREC>
-__global__ __launch_bounds__(256, 1) void k_contract_gen_pipe(
-    const uint4 *__restrict__ packed, const uint2 *__restrict__ tabx,
-    const uint2 *__restrict__ taby, int Mx, int My, int64_t chunk, int tiles_l, int kp, int lp,
-    float *__restrict__ part, double r2) {
-  if (tile_outside(blockIdx.x, tiles_l, 128, 128, r2)) return;
-  // a static array (at LDS address 0, so the lookups need no base add) large
-  // enough for both tables
-  __shared__ uint2 lds[2 * kTabN + 1];
-  uint2 *tx = lds;
-  uint2 *ty = tabx == taby ? tx : tx + (Mx + 1);
-  for (int i = threadIdx.x; i <= Mx; i += 256) tx[i] = tabx[i];
-  if (tabx != taby)
-    for (int i = threadIdx.x; i < My; i += 256) ty[i] = taby[i];
-  __syncthreads();
-
+__device__ __forceinline__ void contract_gen_pipe_body(const uint2 *lds, bool one_tab,
+                                                       const uint4 *__restrict__ packed, int Mx,
+                                                       int My, int64_t chunk, int tiles_l, int kp,
+                                                       int lp, float *__restrict__ part) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 31, lh = lane >> 5;
   const int tk = blockIdx.x / tiles_l, tl = blockIdx.x % tiles_l;
@@ -220,7 +238,7 @@ __global__ __launch_bounds__(256, 1) void k_contract_gen_pipe(
   gen_lane(g, k0, l0, li, ux, uy);
   const uint32_t kr8[2] = {g.kr[0] << 3, g.kr[1] << 3}, lr8[2] = {g.lr[0] << 3, g.lr[1] << 3};
   const uint32_t Mx8 = ux << 3, My8 = uy << 3;
-  const uint32_t ybase = tabx == taby ? 0u : Mx8 + 8u;
+  const uint32_t ybase = one_tab ? 0u : Mx8 + 8u;
 
   f32x16 acc[2][2][4];
 #pragma unroll
@@ -260,6 +278,27 @@ __global__ __launch_bounds__(256, 1) void k_contract_gen_pipe(
   store_part<2, 2>(part, acc, split, kp, lp, k0, l0, li, lh);
 }
 
+template <int PREC>
+__global__ __launch_bounds__(256, 1) void k_contract_gen_pipe(
+    const uint4 *__restrict__ packed, const uint2 *__restrict__ tabx,
+    const uint2 *__restrict__ taby, int Mx, int My, int64_t chunk, int tiles_l, int kp, int lp,
+    float *__restrict__ part, double r2, RouteArgs ra, const uint2 *__restrict__ tabx16,
+    const uint2 *__restrict__ taby16) {
+  if (tile_outside(blockIdx.x, tiles_l, 128, 128, r2)) return;
+  // large enough for both tables
+  __shared__ uint2 lds[2 * kTabN + 1];
+  if constexpr (PREC == kBF16) {
+    if (block_route_fp16(ra)) {
+      stage_gen_tables<uint2>(lds, tabx16, taby16, Mx, My);
+      contract_gen_pipe_body<kFP16>(lds, tabx16 == taby16, packed, Mx, My, chunk, tiles_l, kp,
+                                    lp, part);
+      return;
+    }
+  }
+  stage_gen_tables<uint2>(lds, tabx, taby, Mx, My);
+  contract_gen_pipe_body<PREC>(lds, tabx == taby, packed, Mx, My, chunk, tiles_l, kp, lp, part);
+}
+
 // ---------------------------------------------------------------------------
 // Periods past 8192 grid units (two-level twiddles).  The eight-wave layout
 // of k_contract_gen; per entry the phase (f x) mod M is reduced exactly in
@@ -269,20 +308,11 @@ __global__ __launch_bounds__(256, 1) void k_contract_gen_pipe(
 // accurate to a few 2^-24, far below the split's own rounding).
 // ---------------------------------------------------------------------------
 template <int PREC>
-__global__ __launch_bounds__(64 * kGenWaves) void k_contract_big(
-    const uint4 *__restrict__ packed, const float2 *__restrict__ tabx,
-    const float2 *__restrict__ taby, int Mx, int My, int nhx, int nhy, int64_t chunk,
-    int tiles_l, int kp, int lp, float *__restrict__ part, double r2) {
-  if (tile_outside(blockIdx.x, tiles_l, 128, 128, r2)) return;
-  extern __shared__ float2 lds_big[];
-  const int nx = nhx + kBigLo, ny = nhy + kBigLo;
-  float2 *tx = lds_big;
-  float2 *ty = tabx == taby ? tx : tx + nx;
-  for (int i = threadIdx.x; i < nx; i += 64 * kGenWaves) tx[i] = tabx[i];
-  if (tabx != taby)
-    for (int i = threadIdx.x; i < ny; i += 64 * kGenWaves) ty[i] = taby[i];
-  __syncthreads();
-
+__device__ __forceinline__ void contract_big_body(const uint4 *__restrict__ packed,
+                                                  const float2 *tx, const float2 *ty, int Mx,
+                                                  int My, int nhx, int nhy, int64_t chunk,
+                                                  int tiles_l, int kp, int lp,
+                                                  float *__restrict__ part) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 31, lh = lane >> 5;
   const int tk = blockIdx.x / tiles_l, tl = blockIdx.x % tiles_l;
@@ -354,9 +384,34 @@ __global__ __launch_bounds__(64 * kGenWaves) void k_contract_big(
   store_part<kGenNKB, kGenNLB>(part, acc, split, kp, lp, k0, l0, li, lh);
 }
 
+// The split entries are rounded in the kernel from the FP32 tables, so a clip
+// routed to split-fp16 (block_route_fp16) uses the same tables.
+template <int PREC>
+__global__ __launch_bounds__(64 * kGenWaves) void k_contract_big(
+    const uint4 *__restrict__ packed, const float2 *__restrict__ tabx,
+    const float2 *__restrict__ taby, int Mx, int My, int nhx, int nhy, int64_t chunk,
+    int tiles_l, int kp, int lp, float *__restrict__ part, double r2, RouteArgs ra) {
+  if (tile_outside(blockIdx.x, tiles_l, 128, 128, r2)) return;
+  extern __shared__ float2 lds_big[];
+  const int nx = nhx + kBigLo, ny = nhy + kBigLo;
+  float2 *tx = lds_big;
+  float2 *ty = tabx == taby ? tx : tx + nx;
+  for (int i = threadIdx.x; i < nx; i += 64 * kGenWaves) tx[i] = tabx[i];
+  if (tabx != taby)
+    for (int i = threadIdx.x; i < ny; i += 64 * kGenWaves) ty[i] = taby[i];
+  __syncthreads();
+  if constexpr (PREC == kBF16) {
+    if (block_route_fp16(ra)) {
+      contract_big_body<kFP16>(packed, tx, ty, Mx, My, nhx, nhy, chunk, tiles_l, kp, lp, part);
+      return;
+    }
+  }
+  contract_big_body<PREC>(packed, tx, ty, Mx, My, nhx, nhy, chunk, tiles_l, kp, lp, part);
+}
+
 template <int PREC>
 hipError_t launch_big_t(const FwdPlan &p, const uint4 *packed, const void *tx, const void *ty,
-                        float *part, hipStream_t st) {
+                        float *part, const RouteArgs &ra, hipStream_t st) {
   const size_t lds = sizeof(float2) * ((size_t)p.nhx + kBigLo +
                                        (tx == ty ? 0 : (size_t)p.nhy + kBigLo));
   static bool attr_set = false;
@@ -370,22 +425,25 @@ hipError_t launch_big_t(const FwdPlan &p, const uint4 *packed, const void *tx, c
   hipLaunchKernelGGL(k_contract_big<PREC>, dim3(p.tiles_k * p.tiles_l, p.nsplit),
                      dim3(64 * kGenWaves), lds, st, packed, (const float2 *)tx,
                      (const float2 *)ty, p.Mx, p.My, p.nhx, p.nhy, p.chunk, p.tiles_l, p.kp, p.lp,
-                     part, p.r2);
+                     part, p.r2, ra);
   return hipGetLastError();
 }
 
 template <int PREC>
 hipError_t launch_gen_pipe_t(const FwdPlan &p, const uint4 *packed, const void *tx,
-                             const void *ty, float *part, hipStream_t st) {
+                             const void *ty, const void *tx16, const void *ty16, float *part,
+                             const RouteArgs &ra, hipStream_t st) {
   hipLaunchKernelGGL(k_contract_gen_pipe<PREC>, dim3(p.tiles_k * p.tiles_l, p.nsplit), dim3(256),
                      0, st, packed, (const uint2 *)tx, (const uint2 *)ty, p.Mx, p.My, p.chunk,
-                     p.tiles_l, p.kp, p.lp, part, p.r2);
+                     p.tiles_l, p.kp, p.lp, part, p.r2, ra, (const uint2 *)tx16,
+                     (const uint2 *)ty16);
   return hipGetLastError();
 }
 
 template <int PREC>
 hipError_t launch_gen_t(const FwdPlan &p, const uint4 *packed, const void *tx, const void *ty,
-                        float *part, hipStream_t st) {
+                        const void *tx16, const void *ty16, float *part, const RouteArgs &ra,
+                        hipStream_t st) {
   const size_t lds = sizeof(uint2) * ((size_t)p.Mx + 1 + (tx == ty ? 0 : (size_t)p.My));
   static bool attr_set = false;
   if (!attr_set) {
@@ -397,30 +455,34 @@ hipError_t launch_gen_t(const FwdPlan &p, const uint4 *packed, const void *tx, c
   }
   hipLaunchKernelGGL(k_contract_gen<PREC>, dim3(p.tiles_k * p.tiles_l, p.nsplit),
                      dim3(64 * kGenWaves), lds, st, packed, tx, ty, p.Mx, p.My, p.chunk, p.tiles_l,
-                     p.kp, p.lp, part, p.r2);
+                     p.kp, p.lp, part, p.r2, ra, tx16, ty16);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_gen_contract(const FwdPlan &p, const uint4 *packed, const void *tx,
-                               const void *ty, float *part, hipStream_t st) {
+                               const void *ty, float *part, hipStream_t st,
+                               const unsigned long long *area_part, const void *tx16,
+                               const void *ty16) {
+  RouteArgs ra = route_args(p, area_part);
+  if (!p.big && (!tx16 || !ty16)) ra.gscale_alt = 0.0;
   if (p.big) {
     switch (p.prec) {
-      case kFP32: return launch_big_t<kFP32>(p, packed, tx, ty, part, st);
-      case kBF16: return launch_big_t<kBF16>(p, packed, tx, ty, part, st);
-      default: return launch_big_t<kFP16>(p, packed, tx, ty, part, st);
+      case kFP32: return launch_big_t<kFP32>(p, packed, tx, ty, part, ra, st);
+      case kBF16: return launch_big_t<kBF16>(p, packed, tx, ty, part, ra, st);
+      default: return launch_big_t<kFP16>(p, packed, tx, ty, part, ra, st);
     }
   }
   if (p.tile == kGenPipeTile) {
     if (p.chunk % 32) return hipErrorInvalidValue;
-    return p.prec == kBF16 ? launch_gen_pipe_t<kBF16>(p, packed, tx, ty, part, st)
-                           : launch_gen_pipe_t<kFP16>(p, packed, tx, ty, part, st);
+    return p.prec == kBF16 ? launch_gen_pipe_t<kBF16>(p, packed, tx, ty, tx16, ty16, part, ra, st)
+                           : launch_gen_pipe_t<kFP16>(p, packed, tx, ty, tx16, ty16, part, ra, st);
   }
   switch (p.prec) {
-    case kFP32: return launch_gen_t<kFP32>(p, packed, tx, ty, part, st);
-    case kBF16: return launch_gen_t<kBF16>(p, packed, tx, ty, part, st);
-    default: return launch_gen_t<kFP16>(p, packed, tx, ty, part, st);
+    case kFP32: return launch_gen_t<kFP32>(p, packed, tx, ty, tx16, ty16, part, ra, st);
+    case kBF16: return launch_gen_t<kBF16>(p, packed, tx, ty, tx16, ty16, part, ra, st);
+    default: return launch_gen_t<kFP16>(p, packed, tx, ty, tx16, ty16, part, ra, st);
   }
 }
 

@@ -99,21 +99,42 @@ __host__ __device__ inline GuardGroup guard_group(int g, int n) {
   r.ns = r.ns < 0 ? 0 : (r.ns > 4 ? 4 : r.ns);
   return r;
 }
-// Span of the guard region from a rounding model of the split contraction.
-// Every corner term carries a rounding of about eps (the split table entry and
-// the dropped lo x lo product), so the error of S(k, l) grows like
-// eps sqrt(V); alpha_{k,l} turns it into an error relative to |F[0,0]| of
-// about eps sqrt(V) P / (4 pi^2 |A| k l), P the period area and A the exact
+// Span of the guard region from a rounding model of the contraction.
+// Every corner term carries a rounding of about eps (the table entries and, in
+// the split forms, the dropped lo x lo product), so the error of S(k, l) grows
+// like eps sqrt(V); alpha_{k,l} turns it into an error relative to |F[0,0]|
+// of about eps sqrt(V) P / (4 pi^2 |A| k l), P the period area and A the exact
 // polygon area in the same units.  gscale = 2 eps P / (4 pi^2 tol) (a factor 2
-// of margin, tol = 1e-5) is fixed by the plan; the strips are widened until
-// that estimate drops below tol outside them.  gscale = 0 keeps the core block.
-__host__ __device__ inline int guard_span(double gscale, int64_t V, long long A) {
-  if (gscale <= 0.0 || V <= 0) return 1;
+// of margin, tol the bound of the precision) is fixed by the plan; the guard
+// has to cover every k l below reach = gscale sqrt(V) / |A|.  gscale = 0 keeps
+// the core block.
+__host__ __device__ inline double guard_reach(double gscale, int64_t V, long long A) {
+  if (gscale <= 0.0 || V <= 0) return 0.0;
   const double a = A < 0 ? -(double)A : (double)A;
-  if (a <= 0.0) return kGuardSpanMax;
-  const double reach = gscale * sqrt((double)V) / a;  // guard k l below this
-  const double n = ceil(reach / kGuard);
+  return a > 0.0 ? gscale * sqrt((double)V) / a : 1e300;
+}
+// The strips k <= 8, l <= 8 n (and mirrored) plus the block 9..16 cover every
+// k l <= 8 n up to the widest span; past it the model asks for more than the
+// guard region holds.
+__host__ __device__ inline bool guard_exceeded(double gscale, int64_t V, long long A) {
+  return guard_reach(gscale, V, A) > (double)(kGuard * kGuardSpanMax);
+}
+__host__ __device__ inline int guard_span(double gscale, int64_t V, long long A) {
+  const double n = ceil(guard_reach(gscale, V, A) / kGuard);
   return n <= 1.0 ? 1 : (n >= (double)kGuardSpanMax ? kGuardSpanMax : (int)n);
+}
+// Precision routing of split-bf16 plans (gscale_alt > 0, the split-fp16
+// factor): a clip whose bf16 reach exceeds the guard region runs its
+// contraction in split-fp16 (11 + 11 significant bits, eps 16 times smaller)
+// and sizes its guard with the fp16 factor.  Decided on the device from the
+// exact area, identically by the contraction and the side kernels.
+__host__ __device__ inline bool route_fp16(double gscale, double gscale_alt, int64_t V,
+                                           long long A) {
+  return gscale_alt > 0.0 && guard_exceeded(gscale, V, A);
+}
+__host__ __device__ inline int guard_span_routed(double gscale, double gscale_alt, int64_t V,
+                                                 long long A) {
+  return guard_span(route_fp16(gscale, gscale_alt, V, A) ? gscale_alt : gscale, V, A);
 }
 
 // Periods above the LDS table size (general tiles with Nx 2^F or Ny 2^F past
@@ -170,6 +191,7 @@ struct FwdPlan {
   int g_chunks;      // corner chunks (blocks) of the FP64 guard region
   int64_t g_chunk;
   double gscale;     // guard-span model factor (guard_span; 0: core block only)
+  double gscale_alt; // split-bf16: the split-fp16 factor of a routed clip (route_fp16), else 0
   int big;           // general tile with a period past 8192: two-level tables
   int nhx, nhy;      // two-level tables: entries of Whi per period (big_hi)
   // workspace offsets (bytes): off_guard holds the guard partials
@@ -188,8 +210,10 @@ hipError_t launch_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y, 
 // histograms + guard region (unless guard is false), then the axis DFTs
 hipError_t launch_side(const FwdPlan &p, const int32_t *x, const int32_t *y, const double2 *w64,
                        void *ws, hipStream_t st, bool guard = true);
+// area_part: the pre-pass area partials, which let a split-bf16 plan route a
+// clip to split-fp16 (route_fp16); nullptr keeps the plan's precision.
 hipError_t launch_contract(const FwdPlan &p, const uint4 *packed, const Tables &t, float *part,
-                           hipStream_t st);
+                           hipStream_t st, const unsigned long long *area_part = nullptr);
 hipError_t launch_epilogue(const FwdPlan &p, const void *ws, float *F, int64_t *area,
                            hipStream_t st);
 // the axes and DC entries only (lattice form)
@@ -222,8 +246,16 @@ hipError_t launch_gen_side(const FwdPlan &p, const int32_t *x, const int32_t *y,
 constexpr int kGenPipeTile = 1;
 // With p.big, tx and ty are two-level FP32 tables for every precision (the
 // split entries are formed from the FP32 product in the kernel).
+// area_part, tx16, ty16: the pre-pass area partials and the split-fp16 tables
+// of both periods, which let a split-bf16 plan route a clip to split-fp16
+// (route_fp16); nullptr keeps the plan's precision.
 hipError_t launch_gen_contract(const FwdPlan &p, const uint4 *packed, const void *tx,
-                               const void *ty, float *part, hipStream_t st);
+                               const void *ty, float *part, hipStream_t st,
+                               const unsigned long long *area_part = nullptr,
+                               const void *tx16 = nullptr, const void *ty16 = nullptr);
+struct RouteArgs;
+// routing inputs of a forward plan (fcfs_kernels.hip)
+RouteArgs route_args(const FwdPlan &p, const unsigned long long *area_part);
 hipError_t launch_fft(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
                       const double2 *w64, void *ws, float *F, hipStream_t st);
 hipError_t launch_debug_phases(const FwdPlan &p, const uint4 *packed, int axis, int k0, int nk,
@@ -290,7 +322,7 @@ struct BatchClip {
   float *part;
   double *gpart;        // guard partials [chunk][slot][16 x 16]
   unsigned int *gspan;  // guard span chosen by the side kernel
-  double gscale;
+  double gscale, gscale_alt;
   unsigned long long *hist;
   int64_t V, vpad, chunk, g_chunk;
   int T, shift, K, L, kp, lp, tiles_l, nsplit;
@@ -310,7 +342,8 @@ struct BatchLaunch {
   const int4 *items;        // device: (clip, tile, split) per work item, LPT order
   int n_items;
   int grid;                 // persistent workgroups
-  unsigned int *counter;    // device work counter
+  unsigned int *counter;    // device work counters: [0] the plan's precision, [1] routed clips
+  unsigned int *route;      // device: per clip 1 if routed to split-fp16 (split-bf16 plans)
   const int *epi_off;       // device: prefix of epilogue blocks per clip [n+1]
   int n_epi;
 };

@@ -259,23 +259,14 @@ __device__ __forceinline__ double2 gen_entry64(const double2 *__restrict__ t, in
 }
 
 // Span of the guard region (block-uniform) from the exact area partials,
-// limited to the strips that reach into |k| <= K or |l| <= L.
+// limited to the strips that reach into |k| <= K or |l| <= L; a split-bf16
+// clip routed to split-fp16 (gscale_alt > 0) sizes it with the fp16 factor.
 __device__ __forceinline__ int guard_span_block(const unsigned long long *__restrict__ area_part,
-                                                int pre_blocks, int64_t V, double gscale, int K,
-                                                int L) {
-  __shared__ int s_n;
-  if (threadIdx.x < 64) {
-    unsigned long long a = 0;
-#pragma unroll 4
-    for (int b = threadIdx.x; b < pre_blocks; b += 64) a += area_part[b];
-    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-    if (threadIdx.x == 0) {
-      const int nmax = (max(K, L) + kGuard - 1) / kGuard;
-      s_n = max(1, min(guard_span(gscale, V, (long long)a), nmax));
-    }
-  }
-  __syncthreads();
-  return s_n;
+                                                int pre_blocks, int64_t V, double gscale,
+                                                double gscale_alt, int K, int L) {
+  const long long a = block_area(area_part, pre_blocks);
+  const int nmax = (max(K, L) + kGuard - 1) / kGuard;
+  return max(1, min(guard_span_routed(gscale, gscale_alt, V, a), nmax));
 }
 
 // Slot group gi of the guard region over corner range blk (guard_group).
@@ -290,8 +281,8 @@ __device__ __forceinline__ void guard_body(const uint4 *__restrict__ packed,
                                            const double2 *__restrict__ wx, int64_t V,
                                            int64_t g_chunk, int blk, int gi,
                                            const unsigned long long *__restrict__ area_part,
-                                           int pre_blocks, double gscale, int K, int L,
-                                           double *__restrict__ gpart,
+                                           int pre_blocks, double gscale, double gscale_alt,
+                                           int K, int L, double *__restrict__ gpart,
                                            unsigned int *__restrict__ gspan,
                                            const double2 *__restrict__ wy = nullptr, int Mx = 0,
                                            int My = 0, int nhx = 0, int nhy = 0) {
@@ -299,7 +290,7 @@ __device__ __forceinline__ void guard_body(const uint4 *__restrict__ packed,
   const double iMx = BIG ? 1.0 / dMx : 0.0, iMy = BIG ? 1.0 / dMy : 0.0;
   __shared__ double red[4][kGuardD];
   const int n =
-      __builtin_amdgcn_readfirstlane(guard_span_block(area_part, pre_blocks, V, gscale, K, L));
+      __builtin_amdgcn_readfirstlane(guard_span_block(area_part, pre_blocks, V, gscale, gscale_alt, K, L));
   if (blk == 0 && gi == 0 && threadIdx.x == 0) *gspan = (unsigned int)n;
   const GuardGroup gg = guard_group(gi, n);
   const int ns = gg.ns;  // slots of the group in use (block-uniform)
@@ -430,15 +421,15 @@ __global__ __launch_bounds__(256) void k_side(const int32_t *__restrict__ x,
                                               int nh, const double2 *__restrict__ w64,
                                               int64_t g_chunk, int g_chunks,
                                               const unsigned long long *__restrict__ area_part,
-                                              int pre_blocks, double gscale, int K, int L,
-                                              double *__restrict__ gpart,
+                                              int pre_blocks, double gscale, double gscale_alt,
+                                              int K, int L, double *__restrict__ gpart,
                                               unsigned int *__restrict__ gspan) {
   if ((int)blockIdx.x < nh)
     hist_body(x, y, packed, V, shift, hist, blockIdx.x, nh);
   else
     guard_body(packed, w64, V, g_chunk, (blockIdx.x - nh) % g_chunks,
-               (blockIdx.x - nh) / g_chunks, area_part, pre_blocks, gscale, K, L, gpart,
-               gspan);
+               (blockIdx.x - nh) / g_chunks, area_part, pre_blocks, gscale, gscale_alt, K, L,
+               gpart, gspan);
 }
 
 hipError_t launch_side(const FwdPlan &p, const int32_t *x, const int32_t *y, const double2 *w64,
@@ -451,7 +442,7 @@ hipError_t launch_side(const FwdPlan &p, const int32_t *x, const int32_t *y, con
   if (nh + ng > 0)
     hipLaunchKernelGGL(k_side, dim3(nh + ng), dim3(256), 0, st, x, y, packed, p.V, p.shift, hist,
                        nh, w64, p.g_chunk, p.g_chunks, (const unsigned long long *)(w + p.off_area),
-                       p.pre_blocks, p.gscale, p.K, p.L, (double *)(w + p.off_guard),
+                       p.pre_blocks, p.gscale, p.gscale_alt, p.K, p.L, (double *)(w + p.off_guard),
                        (unsigned int *)(w + p.off_gspan));
   if (p.K + p.L > 0)
     hipLaunchKernelGGL(k_axis_dft, dim3(p.ax_fb_k + p.ax_fb_l, p.ax_chunks), dim3(256), 0, st,
@@ -470,15 +461,16 @@ __global__ __launch_bounds__(256) void k_gen_side(const int32_t *__restrict__ x,
                                                   const double2 *__restrict__ wy, int Mx, int My,
                                                   int64_t g_chunk, int g_chunks,
                                                   const unsigned long long *__restrict__ area_part,
-                                                  int pre_blocks, double gscale, int K, int L,
+                                                  int pre_blocks, double gscale,
+                                                  double gscale_alt, int K, int L,
                                                   double *__restrict__ gpart,
                                                   unsigned int *__restrict__ gspan) {
   if ((int)blockIdx.x < nh)
     hist_body<true>(x, y, packed, V, 0, hist, blockIdx.x, nh);
   else
     guard_body<true>(packed, wx, V, g_chunk, (blockIdx.x - nh) % g_chunks,
-                     (blockIdx.x - nh) / g_chunks, area_part, pre_blocks, gscale, K, L, gpart,
-                     gspan, wy, Mx, My);
+                     (blockIdx.x - nh) / g_chunks, area_part, pre_blocks, gscale, gscale_alt, K,
+                     L, gpart, gspan, wy, Mx, My);
 }
 
 __global__ __launch_bounds__(256) void k_gen_axis_dft(const unsigned long long *__restrict__ hist,
@@ -494,9 +486,10 @@ __global__ __launch_bounds__(256) void k_gen_side_big(
     const uint4 *__restrict__ packed, int64_t V, const double2 *__restrict__ wx,
     const double2 *__restrict__ wy, int Mx, int My, int nhx, int nhy, int64_t g_chunk,
     int g_chunks, const unsigned long long *__restrict__ area_part, int pre_blocks, double gscale,
-    int K, int L, double *__restrict__ gpart, unsigned int *__restrict__ gspan) {
+    double gscale_alt, int K, int L, double *__restrict__ gpart, unsigned int *__restrict__ gspan) {
   guard_body<true, true>(packed, wx, V, g_chunk, blockIdx.x % g_chunks, blockIdx.x / g_chunks,
-                         area_part, pre_blocks, gscale, K, L, gpart, gspan, wy, Mx, My, nhx, nhy);
+                         area_part, pre_blocks, gscale, gscale_alt, K, L, gpart, gspan, wy, Mx,
+                         My, nhx, nhy);
 }
 
 // Axis sums (Steps 2 and 3) over the corners directly, for periods past 8192
@@ -549,7 +542,8 @@ hipError_t launch_gen_side(const FwdPlan &p, const int32_t *x, const int32_t *y,
       hipLaunchKernelGGL(k_gen_side_big, dim3(kGuardGroups * p.g_chunks), dim3(256), 0, st, packed,
                          p.V, wx, wy, p.Mx, p.My, p.nhx, p.nhy, p.g_chunk, p.g_chunks,
                          (const unsigned long long *)(w + p.off_area), p.pre_blocks, p.gscale,
-                         p.K, p.L, (double *)(w + p.off_guard), (unsigned int *)(w + p.off_gspan));
+                         p.gscale_alt, p.K, p.L, (double *)(w + p.off_guard),
+                         (unsigned int *)(w + p.off_gspan));
     if (p.K + p.L > 0) {
       const int64_t ax_chunk = std::max<int64_t>(1, (p.V + p.ax_chunks - 1) / p.ax_chunks);
       hipLaunchKernelGGL(k_gen_axis_big, dim3(p.ax_fb_k + p.ax_fb_l, p.ax_chunks), dim3(256), 0,
@@ -565,7 +559,7 @@ hipError_t launch_gen_side(const FwdPlan &p, const int32_t *x, const int32_t *y,
     hipLaunchKernelGGL(k_gen_side, dim3(nh + ng), dim3(256), 0, st, x, y, packed, p.V, hist, nh,
                        wx, wy, p.Mx, p.My, p.g_chunk, p.g_chunks,
                        (const unsigned long long *)(w + p.off_area),
-                       p.pre_blocks, p.gscale, p.K, p.L, (double *)(w + p.off_guard),
+                       p.pre_blocks, p.gscale, p.gscale_alt, p.K, p.L, (double *)(w + p.off_guard),
                        (unsigned int *)(w + p.off_gspan));
   if (p.K + p.L > 0)
     hipLaunchKernelGGL(k_gen_axis_dft, dim3(p.ax_fb_k + p.ax_fb_l, p.ax_chunks), dim3(256), 0, st,
@@ -645,15 +639,10 @@ __device__ __forceinline__ void gather(Raw<NKB, NLB> &r, const uint2 *s_tab, con
 // being loaded while the MFMAs of step s run; operand fragments are double
 // buffered (two unrolled half-iterations swap their roles).
 template <int PREC, int NKB, int NLB>
-__global__ __launch_bounds__(256) void k_contract_split(const uint4 *__restrict__ packed,
-                                                        const uint2 *__restrict__ tab,
-                                                        int64_t chunk, int tiles_l, int kp,
-                                                        int lp, float *__restrict__ part, double r2) {
-  if (tile_outside(blockIdx.x, tiles_l, 64 * NKB, 64 * NLB, r2)) return;
-  __shared__ uint2 s_tab[kTabEntries];
-  for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
-  __syncthreads();
-
+__device__ __forceinline__ void contract_split_body(const uint2 *s_tab,
+                                                    const uint4 *__restrict__ packed,
+                                                    int64_t chunk, int tiles_l, int kp, int lp,
+                                                    float *__restrict__ part) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 31, lh = lane >> 5;
   const int tk = blockIdx.x / tiles_l, tl = blockIdx.x % tiles_l;
@@ -712,6 +701,33 @@ __global__ __launch_bounds__(256) void k_contract_split(const uint4 *__restrict_
     f0 = f1;
   }
   store_part<NKB, NLB>(part, acc, split, kp, lp, k0, l0, li, lh);
+}
+
+// Operand table of a contraction staged in LDS (8193 entries).
+__device__ __forceinline__ void stage_table(uint2 *s_tab, const uint2 *__restrict__ tab) {
+  for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
+  __syncthreads();
+}
+
+// Split-bf16 launches take the split-fp16 table as well: a clip the rounding
+// model routes to split-fp16 (block_route_fp16) runs the fp16 form.
+template <int PREC, int NKB, int NLB>
+__global__ __launch_bounds__(256) void k_contract_split(const uint4 *__restrict__ packed,
+                                                        const uint2 *__restrict__ tab,
+                                                        int64_t chunk, int tiles_l, int kp,
+                                                        int lp, float *__restrict__ part, double r2,
+                                                        RouteArgs ra, const uint2 *__restrict__ tab16) {
+  if (tile_outside(blockIdx.x, tiles_l, 64 * NKB, 64 * NLB, r2)) return;
+  __shared__ uint2 s_tab[kTabEntries];
+  if constexpr (PREC == kBF16) {
+    if (block_route_fp16(ra)) {
+      stage_table(s_tab, tab16);
+      contract_split_body<kFP16, NKB, NLB>(s_tab, packed, chunk, tiles_l, kp, lp, part);
+      return;
+    }
+  }
+  stage_table(s_tab, tab);
+  contract_split_body<PREC, NKB, NLB>(s_tab, packed, chunk, tiles_l, kp, lp, part);
 }
 
 // Lean form of the same contraction for two waves per SIMD: no software
@@ -773,11 +789,20 @@ __global__ __launch_bounds__(256, 2) void k_contract_split_lean(const uint4 *__r
                                                                 const uint2 *__restrict__ tab,
                                                                 int64_t chunk, int tiles_l,
                                                                 int kp, int lp,
-                                                                float *__restrict__ part, double r2) {
+                                                                float *__restrict__ part, double r2,
+                                                                RouteArgs ra,
+                                                                const uint2 *__restrict__ tab16) {
   if (tile_outside(blockIdx.x, tiles_l, 64 * NKB, 64 * NLB, r2)) return;
   __shared__ uint2 s_tab[kTabEntries];
-  for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
-  __syncthreads();
+  if constexpr (PREC == kBF16) {
+    if (block_route_fp16(ra)) {
+      stage_table(s_tab, tab16);
+      contract_lean_body<kFP16, NKB, NLB>(s_tab, packed, chunk, tiles_l, kp, lp, part,
+                                          blockIdx.x, blockIdx.y);
+      return;
+    }
+  }
+  stage_table(s_tab, tab);
   contract_lean_body<PREC, NKB, NLB>(s_tab, packed, chunk, tiles_l, kp, lp, part, blockIdx.x,
                                      blockIdx.y);
 }
@@ -863,11 +888,20 @@ __global__ __launch_bounds__(256, 1) void k_contract_split_pipe(const uint4 *__r
                                                                 const uint2 *__restrict__ tab,
                                                                 int64_t chunk, int tiles_l,
                                                                 int kp, int lp,
-                                                                float *__restrict__ part, double r2) {
+                                                                float *__restrict__ part, double r2,
+                                                                RouteArgs ra,
+                                                                const uint2 *__restrict__ tab16) {
   if (tile_outside(blockIdx.x, tiles_l, 128, 128, r2)) return;
   __shared__ uint2 s_tab[kTabEntries];
-  for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
-  __syncthreads();
+  if constexpr (PREC == kBF16) {
+    if (block_route_fp16(ra)) {
+      stage_table(s_tab, tab16);
+      contract_pipe_body<kFP16, 2, 2>(s_tab, packed, chunk, tiles_l, kp, lp, part, blockIdx.x,
+                                      blockIdx.y);
+      return;
+    }
+  }
+  stage_table(s_tab, tab);
   contract_pipe_body<PREC, 2, 2>(s_tab, packed, chunk, tiles_l, kp, lp, part, blockIdx.x,
                                  blockIdx.y);
 }
@@ -967,7 +1001,7 @@ const TileVariant &tile_variant(int i) { return kVariants[i]; }
 
 template <int NKB, int NLB, bool PIPE>
 static void launch_contract_t(const FwdPlan &p, const uint4 *packed, const Tables &t, float *part,
-                              hipStream_t st) {
+                              const RouteArgs &ra, hipStream_t st) {
   dim3 grid(p.tiles_k * p.tiles_l, p.nsplit), block(256);
   if (p.prec == kFP32) {
     hipLaunchKernelGGL((k_contract_fp32<NKB, NLB>), grid, block, 0, st, packed, t.w32, p.chunk,
@@ -975,36 +1009,47 @@ static void launch_contract_t(const FwdPlan &p, const uint4 *packed, const Table
   } else if constexpr (PIPE) {
     if (p.prec == kBF16)
       hipLaunchKernelGGL((k_contract_split<kBF16, NKB, NLB>), grid, block, 0, st, packed,
-                         t.wbf16, p.chunk, p.tiles_l, p.kp, p.lp, part, p.r2);
+                         t.wbf16, p.chunk, p.tiles_l, p.kp, p.lp, part, p.r2, ra, t.wfp16);
     else
       hipLaunchKernelGGL((k_contract_split<kFP16, NKB, NLB>), grid, block, 0, st, packed,
-                         t.wfp16, p.chunk, p.tiles_l, p.kp, p.lp, part, p.r2);
+                         t.wfp16, p.chunk, p.tiles_l, p.kp, p.lp, part, p.r2, ra, t.wfp16);
   } else {
     if (p.prec == kBF16)
       hipLaunchKernelGGL((k_contract_split_lean<kBF16, NKB, NLB>), grid, block, 0, st, packed,
-                         t.wbf16, p.chunk, p.tiles_l, p.kp, p.lp, part, p.r2);
+                         t.wbf16, p.chunk, p.tiles_l, p.kp, p.lp, part, p.r2, ra, t.wfp16);
     else
       hipLaunchKernelGGL((k_contract_split_lean<kFP16, NKB, NLB>), grid, block, 0, st, packed,
-                         t.wfp16, p.chunk, p.tiles_l, p.kp, p.lp, part, p.r2);
+                         t.wfp16, p.chunk, p.tiles_l, p.kp, p.lp, part, p.r2, ra, t.wfp16);
   }
 }
 
+RouteArgs route_args(const FwdPlan &p, const unsigned long long *area_part) {
+  RouteArgs ra;
+  ra.area_part = area_part;
+  ra.pre_blocks = p.pre_blocks;
+  ra.V = p.V;
+  ra.gscale = p.gscale;
+  ra.gscale_alt = area_part && p.prec == kBF16 ? p.gscale_alt : 0.0;
+  return ra;
+}
+
 hipError_t launch_contract(const FwdPlan &p, const uint4 *packed, const Tables &t, float *part,
-                           hipStream_t st) {
+                           hipStream_t st, const unsigned long long *area_part) {
+  const RouteArgs ra = route_args(p, area_part);
   switch (p.tile) {
-    case 0: launch_contract_t<1, 1, true>(p, packed, t, part, st); break;
-    case 1: launch_contract_t<2, 1, true>(p, packed, t, part, st); break;
-    case 2: launch_contract_t<2, 2, true>(p, packed, t, part, st); break;
-    case 3: launch_contract_t<1, 1, false>(p, packed, t, part, st); break;
-    case 4: launch_contract_t<2, 1, false>(p, packed, t, part, st); break;
+    case 0: launch_contract_t<1, 1, true>(p, packed, t, part, ra, st); break;
+    case 1: launch_contract_t<2, 1, true>(p, packed, t, part, ra, st); break;
+    case 2: launch_contract_t<2, 2, true>(p, packed, t, part, ra, st); break;
+    case 3: launch_contract_t<1, 1, false>(p, packed, t, part, ra, st); break;
+    case 4: launch_contract_t<2, 1, false>(p, packed, t, part, ra, st); break;
     case 5: {
       const dim3 grid(p.tiles_k * p.tiles_l, p.nsplit), block(256);
       if (p.prec == kBF16)
         hipLaunchKernelGGL(k_contract_split_pipe<kBF16>, grid, block, 0, st, packed, t.wbf16,
-                           p.chunk, p.tiles_l, p.kp, p.lp, part, p.r2);
+                           p.chunk, p.tiles_l, p.kp, p.lp, part, p.r2, ra, t.wfp16);
       else if (p.prec == kFP16)
         hipLaunchKernelGGL(k_contract_split_pipe<kFP16>, grid, block, 0, st, packed, t.wfp16,
-                           p.chunk, p.tiles_l, p.kp, p.lp, part, p.r2);
+                           p.chunk, p.tiles_l, p.kp, p.lp, part, p.r2, ra, t.wfp16);
       else
         return hipErrorInvalidValue;
       break;
@@ -1397,13 +1442,23 @@ hipError_t launch_debug_phases(const FwdPlan &p, const uint4 *packed, int axis, 
 // the head of the sequence, so a captured graph can be replayed.
 // ===========================================================================
 __global__ void k_batch_reset(unsigned int *counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0u;
+  if (threadIdx.x < 2 && blockIdx.x == 0) counter[threadIdx.x] = 0u;
 }
 
 __global__ __launch_bounds__(256) void k_batch_prepass(const BatchClip *__restrict__ clips) {
   const BatchClip &c = clips[blockIdx.y];
   prepass_body(c.x, c.y, c.s, c.V, c.vpad, c.T, c.shift, c.packed, c.area_part, c.hist,
                blockIdx.x, gridDim.x);
+}
+
+// Precision routing of the clips of a split-bf16 batch (route_fp16), one block
+// per clip, after the pre-pass: route[c] = 1 sends clip c's work items to the
+// split-fp16 pass of the contraction.
+__global__ __launch_bounds__(256) void k_batch_route(const BatchClip *__restrict__ clips,
+                                                     int pre_blocks, unsigned int *route) {
+  const BatchClip &c = clips[blockIdx.x];
+  const long long a = block_area(c.area_part, pre_blocks);
+  if (threadIdx.x == 0) route[blockIdx.x] = route_fp16(c.gscale, c.gscale_alt, c.V, a) ? 1u : 0u;
 }
 
 // Side-stream blocks of a batch, one descriptor each: (clip, 0, b) bins
@@ -1419,7 +1474,7 @@ __global__ __launch_bounds__(256) void k_batch_side(const BatchClip *__restrict_
     hist_body(c.x, c.y, c.packed, c.V, c.shift, c.hist, d.z, c.hist_blocks);
   else
     guard_body(c.packed, w64, c.V, c.g_chunk, d.z % c.g_chunks, d.z / c.g_chunks, c.area_part,
-               pre_blocks, c.gscale, c.K, c.L, c.gpart, c.gspan);
+               pre_blocks, c.gscale, c.gscale_alt, c.K, c.L, c.gpart, c.gspan);
 }
 
 __global__ __launch_bounds__(256) void k_batch_axis(const BatchClip *__restrict__ clips,
@@ -1439,11 +1494,16 @@ __device__ __forceinline__ int next_item(unsigned int *counter, int n_items, int
   return it < n_items ? it : -1;
 }
 
+// route (split-bf16 batches): the contraction runs as two passes over the work
+// list, the bf16 pass (want 0) and the split-fp16 pass of routed clips (want
+// 1), each skipping the other's items; nullptr: every item.
 template <int PREC, int NKB, int NLB>
 __global__ __launch_bounds__(256, 2) void k_batch_contract(const BatchClip *__restrict__ clips,
                                                            const int4 *__restrict__ items,
                                                            int n_items, unsigned int *counter,
-                                                           const uint2 *__restrict__ tab) {
+                                                           const uint2 *__restrict__ tab,
+                                                           const unsigned int *__restrict__ route,
+                                                           unsigned int want) {
   __shared__ uint2 s_tab[kTabEntries];
   __shared__ int s_item;
   for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
@@ -1451,6 +1511,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_contract(const BatchClip *__re
     const int it = next_item(counter, n_items, &s_item);
     if (it < 0) break;
     const int4 d = items[it];
+    if (route && route[d.x] != want) continue;
     const BatchClip &c = clips[d.x];
     contract_lean_body<PREC, NKB, NLB, true>(s_tab, c.packed, c.chunk, c.tiles_l, c.kp, c.lp,
                                              c.part, d.y, d.z, &c);
@@ -1462,7 +1523,9 @@ __global__ __launch_bounds__(256, 1) void k_batch_contract_pipe(const BatchClip 
                                                                 const int4 *__restrict__ items,
                                                                 int n_items,
                                                                 unsigned int *counter,
-                                                                const uint2 *__restrict__ tab) {
+                                                                const uint2 *__restrict__ tab,
+                                                                const unsigned int *__restrict__ route,
+                                                                unsigned int want) {
   __shared__ uint2 s_tab[kTabEntries];
   __shared__ int s_item;
   for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
@@ -1470,6 +1533,7 @@ __global__ __launch_bounds__(256, 1) void k_batch_contract_pipe(const BatchClip 
     const int it = next_item(counter, n_items, &s_item);
     if (it < 0) break;
     const int4 d = items[it];
+    if (route && route[d.x] != want) continue;
     const BatchClip &c = clips[d.x];
     contract_pipe_body<PREC, 2, 2>(s_tab, c.packed, c.chunk, c.tiles_l, c.kp, c.lp, c.part, d.y,
                                    d.z);
@@ -1521,6 +1585,9 @@ __global__ __launch_bounds__(256) void k_batch_epilogue(const BatchClip *__restr
 hipError_t launch_batch_prepass(const BatchLaunch &b, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, b.counter);
   hipLaunchKernelGGL(k_batch_prepass, dim3(b.pre_blocks, b.n_clips), dim3(256), 0, st, b.clips);
+  if (b.prec == kBF16 && b.route && b.n_clips > 0)
+    hipLaunchKernelGGL(k_batch_route, dim3(b.n_clips), dim3(256), 0, st, b.clips, b.pre_blocks,
+                       b.route);
   return hipGetLastError();
 }
 
@@ -1538,38 +1605,52 @@ int batch_grid(int tile, int prec) {
   return tile_variant(tile).wg_per_cu * 256;  // persistent workgroups on 256 CUs
 }
 
-hipError_t launch_batch_contract(const BatchLaunch &b, const Tables &t, hipStream_t st) {
-  if (b.n_items == 0) return hipSuccess;
+// One persistent pass over the work list in precision prec (want: the route
+// value of the clips it takes, or all clips when route is nullptr).
+static void batch_pass(const BatchLaunch &b, const Tables &t, int prec, const unsigned int *route,
+                       unsigned int want, unsigned int *counter, hipStream_t st) {
   const dim3 grid(b.grid), block(256);
   const bool wide = tile_variant(b.tile).wk == 64;
-  if (b.prec == kFP32) {
+  const uint2 *tab = prec == kBF16 ? t.wbf16 : t.wfp16;
+  if (prec == kFP32) {
     if (wide)
       hipLaunchKernelGGL((k_batch_contract_fp32<2, 1>), grid, block, 0, st, b.clips, b.items,
-                         b.n_items, b.counter, t.w32);
+                         b.n_items, counter, t.w32);
     else
       hipLaunchKernelGGL((k_batch_contract_fp32<1, 1>), grid, block, 0, st, b.clips, b.items,
-                         b.n_items, b.counter, t.w32);
+                         b.n_items, counter, t.w32);
   } else if (b.tile == 5) {
-    if (b.prec == kBF16)
+    if (prec == kBF16)
       hipLaunchKernelGGL(k_batch_contract_pipe<kBF16>, grid, block, 0, st, b.clips, b.items,
-                         b.n_items, b.counter, t.wbf16);
+                         b.n_items, counter, tab, route, want);
     else
       hipLaunchKernelGGL(k_batch_contract_pipe<kFP16>, grid, block, 0, st, b.clips, b.items,
-                         b.n_items, b.counter, t.wfp16);
-  } else if (b.prec == kBF16) {
+                         b.n_items, counter, tab, route, want);
+  } else if (prec == kBF16) {
     if (wide)
       hipLaunchKernelGGL((k_batch_contract<kBF16, 2, 1>), grid, block, 0, st, b.clips, b.items,
-                         b.n_items, b.counter, t.wbf16);
+                         b.n_items, counter, tab, route, want);
     else
       hipLaunchKernelGGL((k_batch_contract<kBF16, 1, 1>), grid, block, 0, st, b.clips, b.items,
-                         b.n_items, b.counter, t.wbf16);
+                         b.n_items, counter, tab, route, want);
   } else {
     if (wide)
       hipLaunchKernelGGL((k_batch_contract<kFP16, 2, 1>), grid, block, 0, st, b.clips, b.items,
-                         b.n_items, b.counter, t.wfp16);
+                         b.n_items, counter, tab, route, want);
     else
       hipLaunchKernelGGL((k_batch_contract<kFP16, 1, 1>), grid, block, 0, st, b.clips, b.items,
-                         b.n_items, b.counter, t.wfp16);
+                         b.n_items, counter, tab, route, want);
+  }
+}
+
+hipError_t launch_batch_contract(const BatchLaunch &b, const Tables &t, hipStream_t st) {
+  if (b.n_items == 0) return hipSuccess;
+  if (b.prec == kBF16 && b.route) {
+    // split-bf16: the clips the rounding model keeps in bf16, then the routed ones
+    batch_pass(b, t, kBF16, b.route, 0u, b.counter, st);
+    batch_pass(b, t, kFP16, b.route, 1u, b.counter + 1, st);
+  } else {
+    batch_pass(b, t, b.prec, nullptr, 0u, b.counter, st);
   }
   return hipGetLastError();
 }
