@@ -393,9 +393,14 @@ fcfs_status fcfs_plan_destroy(fcfs_plan *plan);
 
 /* Debug export of the exact integer phase indices of Step 4:
  * p[i*V + v] = ((k0 + i) * x_v) mod T for i in [0, nk) (axis = 0), or with
- * y_v (axis = 1).  p: (device) out [nk][V] int32. */
+ * y_v (axis = 1), computed by the same pre-pass and phase arithmetic as the
+ * contraction.  p: (device) out [nk][V] int32.  ws: (device) caller
+ * workspace of at least fcfs_debug_phases_workspace_size(V, T) bytes,
+ * 256-byte aligned (else FCFS_ERR_WORKSPACE).  Only c->x, y, s, V and T are
+ * read.  Asynchronous like every other call. */
+fcfs_status fcfs_debug_phases_workspace_size(int64_t V, int32_t T, size_t *bytes);
 fcfs_status fcfs_debug_phases(fcfs_handle *h, const fcfs_clip *c, int32_t axis, int32_t k0,
-                              int32_t nk, int32_t *p);
+                              int32_t nk, int32_t *p, void *ws, size_t ws_bytes);
 
 /* Times candidate tile shapes of the contraction on synthetic corners and
  * stores the fastest per (precision, K-bucket, V-bucket) in the handle, plus
@@ -407,48 +412,20 @@ fcfs_status fcfs_debug_phases(fcfs_handle *h, const fcfs_clip *c, int32_t axis, 
  * Synchronises the handle's stream. */
 fcfs_status fcfs_autotune(fcfs_handle *h, const char *cache_path, int effort);
 
-/* Batch autotuner: builds and times a plan of the clips c[0..n) for each
- * candidate (contraction tile variant, corners per work item) and keeps the
- * fastest on h (used by later fcfs_batch_workspace_size / fcfs_forward_batch
- * calls for precision p); the built-in choice stays unless a candidate beats it
- * by more than 3%.  Overwrites the clips' outputs.  effort 0..2 sets the timed
- * repetitions (2, 3, 5).  Allocates and frees a workspace per candidate.
- * fcfs_batch_choice reports the current choice. */
-fcfs_status fcfs_autotune_batch(fcfs_handle *h, const fcfs_clip *c, int32_t n, fcfs_precision p,
-                                int effort);
-fcfs_status fcfs_batch_choice(fcfs_handle *h, fcfs_precision p, int32_t *tile, int64_t *chunk);
+/* Reads an autotune cache written by fcfs_autotune (JSON) into the handle; a
+ * missing or malformed file is refused (FCFS_ERR_INVALID_ARG) and the handle
+ * keeps its choices. */
 fcfs_status fcfs_load_tune(fcfs_handle *h, const char *cache_path);
 
-/* Tuning hooks.  fcfs_tile_variants fills wk[i], wl[i] (frequencies per
- * wave in k and l of contraction tile variant i, for i < cap) and returns the
- * number of variants.  fcfs_set_tile forces variant `variant` on every later
- * call of this handle (-1 restores the automatic choice).
- * fcfs_workspace_size_tile is fcfs_workspace_size (forward) for a given
- * variant. */
-int32_t fcfs_tile_variants(int32_t *wk, int32_t *wl, int32_t cap);
 /* The plan fcfs_forward makes for clip `c` at precision `p` with the automatic
  * tile choice (pointers in `c` are not read): vertex splits, corners per split,
  * frequency tiles, and whether the one-launch direct form runs instead.  Any
  * output pointer may be NULL. */
 fcfs_status fcfs_forward_plan_info(const fcfs_clip *c, fcfs_precision p, int32_t *nsplit,
                                    int64_t *chunk, int32_t *tiles, int32_t *direct);
-fcfs_status fcfs_set_tile(fcfs_handle *h, int32_t variant);
-fcfs_status fcfs_workspace_size_tile(const fcfs_clip *c, fcfs_precision p, int32_t tile,
-                                     size_t *bytes);
 
-/* Per-kernel timing with hipEvents on the stream each kernel runs on.  After
- * fcfs_profile_begin every launch of a kind whose bit is set in `kinds` (0:
- * every kind) is bracketed by two events; fcfs_profile_end waits for them and
- * writes, for kind i < nkinds, the summed milliseconds ms[i] and the launch
- * count count[i], then stops recording.  Kinds: 0 pre-pass, 1 side-stream
- * work (histograms, guard region, axis DFTs), 2 contraction, 3 epilogue,
- * 4 adjoint kernels, 5 batched graph, 6 lattice form, 7 Haar quadtree walk
- * (the Haar transform's clear-and-plan launches count as pre-pass, its
- * scaling pass as epilogue), 8 pupil loss, 9 direct form of small problems,
- * 10 replay of a captured optimisation step.
- * Each bracketed launch adds two event records to its stream. */
-fcfs_status fcfs_profile_begin(fcfs_handle *h, uint32_t kinds);
-fcfs_status fcfs_profile_end(fcfs_handle *h, double *ms, int64_t *count, int32_t nkinds);
+/* Tuning and profiling hooks (forced tile variants, the batch autotuner,
+ * per-kernel event timing) are declared in fcfs_tuning.h. */
 
 const char *fcfs_status_string(fcfs_status s);
 /* Detail of the last failing call on this handle (or of the last failing

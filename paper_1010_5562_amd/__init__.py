@@ -142,7 +142,7 @@ class Handle:
         check(self.lib.fcfs_set_tile(self._h, int(variant)), self._h)
 
     PROFILE_KINDS = ("prepass", "axis", "contract", "epilogue", "adjoint", "batch", "fft",
-                     "haar", "loss", "direct", "step")
+                     "haar", "loss", "direct", "step", "adjoint_gemm")
 
     def profile_begin(self, kinds=None):
         """Starts event timing of the named kinds (all kinds when None)."""
@@ -393,8 +393,12 @@ def debug_phases(x, y, s, T: int, k0: int, nk: int, axis: int = 0, handle=None):
     V = x.numel()
     p = torch.empty((nk, V), dtype=torch.int32, device=h.device)
     c = _clip(x, y, s, V, T, 0, 0)
+    nb = ctypes.c_size_t(0)
+    check(h.lib.fcfs_debug_phases_workspace_size(V, int(T), ctypes.byref(nb)))
+    ws = h.workspace(nb.value)
     check(h.lib.fcfs_debug_phases(h.ptr, ctypes.byref(c), int(axis), int(k0), int(nk),
-                                  ctypes.c_void_p(p.data_ptr())), h.ptr)
+                                  ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                  ctypes.c_size_t(ws.numel())), h.ptr)
     return p
 
 

@@ -25,7 +25,7 @@ STATUS_NAMES = {
     -7: "FCFS_ERR_NO_MEMORY",
 }
 
-# Every symbol include/fcfs.h declares.
+# Every symbol the headers under include/ declare (fcfs.h, fcfs_tuning.h).
 EXPORTS = (
     "fcfs_create", "fcfs_destroy", "fcfs_set_stream", "fcfs_loops_to_corners",
     "fcfs_workspace_size", "fcfs_forward", "fcfs_band_workspace_size", "fcfs_forward_band",
@@ -39,7 +39,8 @@ EXPORTS = (
     "fcfs_general_batch_workspace_size", "fcfs_general_batch_plan",
     "fcfs_adjoint", "fcfs_adjoint_band", "fcfs_edge_grad",
     "fcfs_apply_edge_offsets", "fcfs_batch_workspace_size", "fcfs_forward_batch", "fcfs_plan_destroy",
-    "fcfs_debug_phases", "fcfs_autotune", "fcfs_autotune_batch", "fcfs_batch_choice",
+    "fcfs_debug_phases", "fcfs_debug_phases_workspace_size", "fcfs_autotune",
+    "fcfs_autotune_batch", "fcfs_batch_choice",
     "fcfs_load_tune", "fcfs_tile_variants", "fcfs_set_tile", "fcfs_forward_plan_info",
     "fcfs_workspace_size_tile", "fcfs_profile_begin", "fcfs_profile_end",
     "fcfs_status_string", "fcfs_last_error",
@@ -163,7 +164,8 @@ def load() -> ctypes.CDLL:
         "fcfs_batch_workspace_size": [P, clip_p, i32, c_int, sz],
         "fcfs_forward_batch": [P, clip_p, i32, c_int, P, ctypes.c_size_t, ctypes.POINTER(P)],
         "fcfs_plan_destroy": [P],
-        "fcfs_debug_phases": [P, clip_p, i32, i32, i32, P],
+        "fcfs_debug_phases": [P, clip_p, i32, i32, i32, P, P, ctypes.c_size_t],
+        "fcfs_debug_phases_workspace_size": [i64, i32, sz],
         "fcfs_autotune": [P, ctypes.c_char_p, c_int],
         "fcfs_autotune_batch": [P, clip_p, i32, c_int, c_int],
         "fcfs_batch_choice": [P, c_int, P, P],

@@ -226,7 +226,14 @@ __global__ void k_adj_axcoef(const float2 *__restrict__ G, int K, int L, int kma
   coef[K + L + 1 + i] = make_double2(v.x * sc, v.y * sc);
 }
 
-// Per corner, FP64: the axis and DC parts of gx, gy (written, not added).
+// Slot s of the register-resident main term's partials (k_adj_gemm_regb)
+// holds y-gradient sums when bit 1 of s is set (waves of types 2 and 3 hold
+// the y cos l and y sin l column blocks).
+__host__ __device__ inline bool adj_slot_y(int s) { return (s & 2) != 0; }
+
+// Per corner, FP64: the axis and DC parts of gx, gy (written, not added),
+// plus, when part is given, the main-term partials of the register-resident
+// kernel (k_adj_gemm_regb) in slot order.
 // sum_f Re[c_f e(f t)] with e(f t) = conj(w^f), w = e^{j 2 pi ts / N}: the
 // powers come from repeated multiplication, restarted from the exact table
 // every 32 steps.
@@ -242,7 +249,9 @@ __global__ __launch_bounds__(256) void k_adj_axis(const int32_t *__restrict__ x,
                                                   float *__restrict__ gx, float *__restrict__ gy,
                                                   const double2 *__restrict__ wy = nullptr,
                                                   int Mx = 0, int My = 0, int nhx = 0,
-                                                  int nhy = 0) {
+                                                  int nhy = 0,
+                                                  const float *__restrict__ part = nullptr,
+                                                  int nslots = 0, int64_t vpad = 0) {
   const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const double dMx = (double)Mx, dMy = (double)My;
   if (v >= V) return;
@@ -290,8 +299,17 @@ __global__ __launch_bounds__(256) void k_adj_axis(const int32_t *__restrict__ x,
     }
   }
   const double g00 = coef[K + L].x;
-  gx[v] = (float)(sg * (yv * dcf * sx1 + sy2 + yv * g00 * dcf));
-  gy[v] = (float)(sg * (sx2 + xv * dcf * sy1 + xv * g00 * dcf));
+  float fx = (float)(sg * (yv * dcf * sx1 + sy2 + yv * g00 * dcf));
+  float fy = (float)(sg * (sx2 + xv * dcf * sy1 + xv * g00 * dcf));
+  for (int sl = 0; sl < nslots; ++sl) {
+    const float t = part[(size_t)sl * vpad + v];
+    if (adj_slot_y(sl))
+      fy += t;
+    else
+      fx += t;
+  }
+  gx[v] = fx;
+  gy[v] = fy;
 }
 
 // ---------------------------------------------------------------------------
@@ -490,6 +508,146 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_gemm_split(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident form of the split main term (square tiles, kb <= 128),
+// computed transposed: C^T = W^T X^T, W's column blocks as the MFMA A operand
+// (the same records serve: for 32 x 32 x 16 products A and B share the lane
+// layout) and the corner twiddles as B.  A workgroup takes a set of CPS
+// frequency chunks (32 frequencies l each) with 4 CPS waves: wave w holds the
+// column block of type w mod 4 (x cos l, x sin l, y cos l, y sin l) of chunk
+// w / 4 in registers for all 2 kb rows, loaded once; CPS waves per SIMD hide
+// each other's latencies.  The B operands of a 32-corner tile (the corner
+// twiddles of every 16-frequency step, gathered from the table and packed)
+// are built once per tile, one step per wave, and passed through LDS to all
+// waves (double buffered: the next tile's operands are built while the
+// current tile is multiplied).  In C^T each lane holds 16 columns of one
+// corner, so the dot with Y_v is a per-lane sum plus one exchange between the
+// two half-waves.  Tiles go to the persistent grid in contiguous runs; wave w
+// of set s writes part[4 CPS s + w][v], and k_adj_axis adds the slots of each
+// gradient in slot order, so the result does not depend on scheduling.
+// ---------------------------------------------------------------------------
+template <int NKS>
+struct RegB {
+  static constexpr int CPS = NKS <= 6 ? 3 : 2;  // chunks per set: waves = 4 CPS
+};
+
+template <int PREC, bool SIN>
+__device__ __forceinline__ float split_value(uint2 e) {
+  // hi + lo of cos (low halves) or sin (high halves) of a split table entry
+  if constexpr (PREC == kBF16) {
+    return SIN ? __uint_as_float(e.x & 0xFFFF0000u) + __uint_as_float(e.y & 0xFFFF0000u)
+               : __uint_as_float(e.x << 16) + __uint_as_float(e.y << 16);
+  } else {
+    return SIN ? (float)__builtin_bit_cast(_Float16, (uint16_t)(e.x >> 16)) +
+                     (float)__builtin_bit_cast(_Float16, (uint16_t)(e.y >> 16))
+               : (float)__builtin_bit_cast(_Float16, (uint16_t)(e.x & 0xFFFFu)) +
+                     (float)__builtin_bit_cast(_Float16, (uint16_t)(e.y & 0xFFFFu));
+  }
+}
+
+// Per-lane dot of the C^T columns with Y_v: the block covers frequencies
+// l = 32 chunk + m + 1 for the rows m = 8 (r >> 2) + 4 lh + (r & 3) of the lane.
+template <int PREC, bool SIN>
+__device__ __forceinline__ float regb_dot(const f32x16 &acc, int chunk, const uint2 *s_tab,
+                                          uint32_t ys8, int lh) {
+  float p[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const uint32_t l = (uint32_t)(32 * chunk + 8 * (r >> 2) + 4 * lh + (r & 3) + 1);
+    const uint2 e = lds_entry(s_tab, phase_x(l, make_uint4(ys8, 0u, 0u, 0u)));
+    p[r & 3] = fmaf(acc[r], split_value<PREC, SIN>(e), p[r & 3]);
+  }
+  return (p[0] + p[1]) + (p[2] + p[3]);
+}
+
+template <int PREC, int NKS>
+__global__ __launch_bounds__(256 * RegB<NKS>::CPS, 1) void k_adj_gemm_regb(
+    const uint4 *__restrict__ packed, const uint2 *__restrict__ tab,
+    const uint16_t *__restrict__ whi, const uint16_t *__restrict__ wlo,
+    const int *__restrict__ scale, int64_t vpad, int lb, float *__restrict__ part) {
+  constexpr int CPS = RegB<NKS>::CPS;
+  constexpr int NT = 256 * CPS;
+  __shared__ uint2 s_tab[kTabN];
+  __shared__ u32x4 s_b[2][NKS][4][64];  // packed corner operands of two tiles
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int li = lane & 31, lh = lane >> 5;
+  const int ncb = lb / 8, nchunk = lb / 32;
+  const int chunk = blockIdx.y * CPS + (wave >> 2);
+  // column block of type wave mod 4 in the wave's chunk (a chunk past the
+  // last one of a partial set holds zeros and adds nothing)
+  u32x4 wreg[NKS][4];  // cos hi, cos lo, sin hi, sin lo rows of each step
+  {
+    const bool valid = chunk < nchunk;
+    const int cb = 4 * chunk + (wave & 3);
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      const size_t rc = (((size_t)ks * ncb + cb) * 64 + lane) * 8;
+      const size_t rs = (((size_t)(NKS + ks) * ncb + cb) * 64 + lane) * 8;
+      const u32x4 z = {0u, 0u, 0u, 0u};
+      wreg[ks][0] = valid ? *(const u32x4 *)(whi + rc) : z;
+      wreg[ks][1] = valid ? *(const u32x4 *)(wlo + rc) : z;
+      wreg[ks][2] = valid ? *(const u32x4 *)(whi + rs) : z;
+      wreg[ks][3] = valid ? *(const u32x4 *)(wlo + rs) : z;
+    }
+  }
+  for (int i = threadIdx.x; i < kTabN; i += NT) s_tab[i] = tab[i];
+  const int64_t ntiles = vpad / 32;
+  const int64_t t0 = (int64_t)blockIdx.x * ntiles / gridDim.x;
+  const int64_t t1 = (int64_t)(blockIdx.x + 1) * ntiles / gridDim.x;
+  const float inv = ldexpf(1.0f, -scale[0]);
+  // step `wave` of the corner operands of a tile into buffer buf, from the
+  // lane's corner record c (corner li of the tile)
+  auto build = [&](const uint4 &c, int buf) {
+    if (wave >= NKS) return;
+    uint2 d[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      d[j] = lds_entry(s_tab, phase_x((uint32_t)(1 + 16 * wave + 8 * lh + j), c));
+    u32x4 ch, sh, cl, sl;
+    pack4(d, ch, sh, cl, sl);
+    s_b[buf][wave][0][lane] = ch;
+    s_b[buf][wave][1][lane] = sh;
+    s_b[buf][wave][2][lane] = cl;
+    s_b[buf][wave][3][lane] = sl;
+  };
+  const uint4 zc = make_uint4(0u, 0u, 0u, 0u);
+  uint4 c_cur = t0 < t1 ? packed[t0 * 32 + li] : zc;
+  uint4 c_nxt = t0 + 1 < t1 ? packed[(t0 + 1) * 32 + li] : zc;
+  __syncthreads();  // table staged
+  if (t0 < t1) build(c_cur, 0);
+  __syncthreads();
+  float *dst = part + (size_t)(4 * CPS * blockIdx.y + wave) * vpad;
+  for (int64_t t = t0; t < t1; ++t) {
+    const int buf = (int)((t - t0) & 1);
+    // the record two tiles ahead is loaded while this tile runs
+    const uint4 c_far = t + 2 < t1 ? packed[(t + 2) * 32 + li] : zc;
+    if (t + 1 < t1) build(c_nxt, buf ^ 1);
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      const u32x4 bch = s_b[buf][ks][0][lane], bsh = s_b[buf][ks][1][lane];
+      const u32x4 bcl = s_b[buf][ks][2][lane], bsl = s_b[buf][ks][3][lane];
+      acc = mfma16<PREC>(wreg[ks][0], bch, acc);
+      acc = mfma16<PREC>(wreg[ks][1], bch, acc);
+      acc = mfma16<PREC>(wreg[ks][0], bcl, acc);
+      acc = mfma16<PREC>(wreg[ks][2], bsh, acc);
+      acc = mfma16<PREC>(wreg[ks][3], bsh, acc);
+      acc = mfma16<PREC>(wreg[ks][2], bsl, acc);
+    }
+    // dot with Y_v of this lane's corner: cos l for types 0 and 2, sin l for
+    // types 1 and 3 (a uniform branch)
+    float p = (wave & 1) ? regb_dot<PREC, true>(acc, chunk, s_tab, c_cur.y, lh)
+                         : regb_dot<PREC, false>(acc, chunk, s_tab, c_cur.y, lh);
+    p += __shfl_xor(p, 32, 64);  // the two half-waves hold the two row halves
+    if (lh == 0) dst[t * 32 + li] = (c_cur.z ? -inv : inv) * p;
+    c_cur = c_nxt;
+    c_nxt = c_far;
+    __syncthreads();  // buffer buf is rebuilt in the next iteration
+  }
+}
+
 // FP32 main term: v_mfma_f32_32x32x2_f32, two frequencies per product, with
 // the operand records of rec_index_f32 shared through LDS as in the split form
 // (eight waves, 256 corners per workgroup, double-buffered 16-row steps).
@@ -629,7 +787,8 @@ hipError_t allow_big_lds(KernelT k, bool &done) {
 
 hipError_t launch_adjoint(const AdjPlan &a, const int32_t *x, const int32_t *y, const int8_t *s,
                           const float *gradF, const Tables &t, void *ws, float *gx, float *gy,
-                          hipStream_t st, const PeriodTables *gtab) {
+                          hipStream_t st, const PeriodTables *gtab,
+                          hipEvent_t *main_ev) {
   char *w = (char *)ws;
   const uint4 *packed = (const uint4 *)(w + a.off_packed);
   double2 *coef = (double2 *)(w + a.off_coef);
@@ -641,9 +800,55 @@ hipError_t launch_adjoint(const AdjPlan &a, const int32_t *x, const int32_t *y, 
   const bool gen = a.gen && gtab;
   if (a.gen && !gtab) return hipErrorInvalidValue;
   (void)s;
-  // axis and DC parts first: they write gx, gy
   hipLaunchKernelGGL(k_adj_axcoef, dim3((a.K + a.L + 1 + 255) / 256), dim3(256), 0, st, G, a.K,
                      a.L, a.kmax, a.lmax, a.rx, a.ry, coef);
+  // register-resident main term (square tiles, split precisions): W and the
+  // slot partials first, then the axis kernel writes gx, gy with them added
+  const bool regb = a.regb_nks > 0 && !gen && a.kmax > 0 && a.lmax > 0 && a.V > 0;
+  if (regb) {
+    const dim3 wgrid((a.lb + 255) / 256, a.kb);
+    if (a.prec == kBF16) {
+      hipLaunchKernelGGL(k_adj_w<1>, wgrid, dim3(256), 0, st, G, a.K, a.L, a.kmax, a.lmax, a.r2,
+                         a.kb, a.lb, a.rx, a.ry, Wf, wmax, whi, wlo, scale);
+    } else {
+      hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, wmax, 1, 0u);
+      hipLaunchKernelGGL(k_adj_w<0>, wgrid, dim3(256), 0, st, G, a.K, a.L, a.kmax, a.lmax, a.r2,
+                         a.kb, a.lb, a.rx, a.ry, Wf, wmax, whi, wlo, scale);
+      const int64_t n = (int64_t)a.R * a.NC;
+      const unsigned sb = (unsigned)std::min<int64_t>(1024, (n + 255) / 256);
+      hipLaunchKernelGGL(k_adj_split<kFP16>, dim3(sb), dim3(256), 0, st, Wf, a.R, a.NC, a.lb,
+                         wmax, whi, wlo, scale);
+    }
+    float *rpart = (float *)(w + a.off_rpart);
+    const int64_t ntiles = a.vpad / 32;
+    const dim3 grid((unsigned)std::max<int64_t>(
+                        1, std::min<int64_t>(ntiles, kAdjRegbGrid / std::max(1, a.regb_sets))),
+                    (unsigned)a.regb_sets);
+    const uint2 *tb = a.prec == kBF16 ? t.wbf16 : t.wfp16;
+    if (main_ev) (void)hipEventRecord(main_ev[0], st);
+#define FCFS_REGB(P, N)                                                                       \
+  hipLaunchKernelGGL((k_adj_gemm_regb<P, N>), grid, dim3(256 * RegB<N>::CPS), 0, st, packed, tb, \
+                     whi, wlo, scale, a.vpad, a.lb, rpart)
+    switch (a.regb_nks * 4 + (a.prec == kBF16 ? 0 : 1)) {
+      case 8: FCFS_REGB(kBF16, 2); break;
+      case 9: FCFS_REGB(kFP16, 2); break;
+      case 16: FCFS_REGB(kBF16, 4); break;
+      case 17: FCFS_REGB(kFP16, 4); break;
+      case 24: FCFS_REGB(kBF16, 6); break;
+      case 25: FCFS_REGB(kFP16, 6); break;
+      case 32: FCFS_REGB(kBF16, 8); break;
+      case 33: FCFS_REGB(kFP16, 8); break;
+      default: return hipErrorInvalidValue;
+    }
+#undef FCFS_REGB
+    if (main_ev) (void)hipEventRecord(main_ev[1], st);
+    hipLaunchKernelGGL(k_adj_axis<false>, dim3((unsigned)((a.V + 255) / 256)), dim3(256), 0, st,
+                       x, y, packed, t.w64, coef, a.V, a.K, a.L, a.kmax, a.lmax, a.dcf, gx, gy,
+                       nullptr, 0, 0, 0, 0, rpart, 4 * adj_regb_nbw(a.regb_nks) * a.regb_sets,
+                       a.vpad);
+    return hipGetLastError();
+  }
+  // axis and DC parts first: they write gx, gy
   if (a.V > 0) {
     if (gen && a.big)
       hipLaunchKernelGGL((k_adj_axis<true, true>), dim3((unsigned)((a.V + 255) / 256)), dim3(256),
@@ -680,6 +885,7 @@ hipError_t launch_adjoint(const AdjPlan &a, const int32_t *x, const int32_t *y, 
       : a.big ? sizeof(float2) * ((size_t)a.nhx + kBigLo + (same ? 0 : (size_t)a.nhy + kBigLo))
               : sizeof(uint2) * ((size_t)a.Mx + (same ? 0 : a.My));
   hipError_t e;
+  if (main_ev) (void)hipEventRecord(main_ev[0], st);
   if (a.prec == kFP32) {
     if (gen && a.big) {
       static bool done = false;
@@ -742,6 +948,7 @@ hipError_t launch_adjoint(const AdjPlan &a, const int32_t *x, const int32_t *y, 
                          st, packed, tb, whi, wlo, scale, a.V, a.kb, a.lb, gx, gy, nullptr, 0, 0);
     }
   }
+  if (main_ev) (void)hipEventRecord(main_ev[1], st);
   return hipGetLastError();
 }
 

@@ -1,6 +1,6 @@
 // Host runtime and C ABI of the FCFS library: handle, twiddle tables, planner,
 // validation, loops -> corners canonicalisation and the entry points of
-// include/fcfs.h.
+// include/fcfs.h and include/fcfs_tuning.h.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/fcfs.h"
+#include "../../include/fcfs_tuning.h"
 #include "fcfs_internal.h"
 
 using fcfs::FwdPlan;
@@ -20,7 +21,8 @@ using fcfs::Tables;
 
 // Kernel families timed by the profiling hooks.
 enum ProfKind { kProfPrepass = 0, kProfAxis, kProfContract, kProfEpilogue, kProfAdjoint,
-                kProfBatch, kProfFft, kProfHaar, kProfLoss, kProfDirect, kProfStep, kProfKinds };
+                kProfBatch, kProfFft, kProfHaar, kProfLoss, kProfDirect, kProfStep, kProfAdjGemm,
+                kProfKinds };
 
 struct fcfs_handle {
   int device = 0;
@@ -52,6 +54,11 @@ struct fcfs_handle {
     uint2 *wbf16 = nullptr, *wfp16 = nullptr;
   };
   std::vector<GenTab> gen_tabs;
+  // captured launch sequences made on this handle and still alive: they pin
+  // period tables, and fcfs_destroy detaches them
+  std::vector<fcfs_step_plan *> step_plans;
+  // set while the library captures its own launch sequence on this handle
+  bool own_capture = false;
   int batch_tile[3] = {-1, -1, -1};
   int64_t batch_chunk[3] = {0, 0, 0};
 };
@@ -388,7 +395,10 @@ fcfs_status make_adj_plan(fcfs_handle *h, int64_t V, int T, int K, int L, int km
   a.lmax = std::min(lmax, L);
   a.V = V;
   a.shift = fcfs::kTabBits - (int)std::lround(std::log2((double)T));
-  a.kb = (int)round_up(std::max(a.kmax, 1), 16);
+  // split precisions with kmax <= 128 take the register-resident main term,
+  // whose step count is one of 2, 4, 6, 8 (k rows padded with zeros)
+  const bool regb = prec != fcfs::kFP32 && a.kmax <= 128;
+  a.kb = (int)round_up(std::max(a.kmax, 1), regb ? 32 : 16);
   a.lb = (int)round_up(std::max(a.lmax, 1), 32);
   a.R = 2 * a.kb;
   a.NC = 4 * a.lb;
@@ -414,6 +424,12 @@ fcfs_status make_adj_plan(fcfs_handle *h, int64_t V, int T, int K, int L, int km
   off += align256(2 * nw);
   a.off_scale = off;
   off += 256;
+  a.regb_nks = regb ? a.kb / 16 : 0;
+  a.regb_sets = regb ? fcfs::adj_regb_sets(a.regb_nks, a.lb) : 0;
+  a.off_rpart = off;
+  if (regb)
+    off += align256(sizeof(float) * 4 * (size_t)fcfs::adj_regb_nbw(a.regb_nks) * a.regb_sets *
+                    a.vpad);
   a.bytes = off;
   *p = a;
   return FCFS_OK;
@@ -437,6 +453,11 @@ fcfs_status check_ws(fcfs_handle *h, const FwdPlan &p, void *ws, size_t ws_bytes
   return FCFS_OK;
 }
 
+// Entry of every call that enqueues work.  A stream that a caller is
+// capturing into a graph is refused: the library's launch sequences (a side
+// stream forked and joined with the handle's events) are captured only by its
+// own plans (fcfs_forward_batch, fcfs_pupil_step_plan,
+// fcfs_general_batch_plan), the configuration that is tested.
 fcfs_status enter(fcfs_handle *h) {
   if (!h) return fail(nullptr, FCFS_ERR_INVALID_ARG, "handle is NULL");
   hipError_t e = hipSetDevice(h->device);
@@ -445,6 +466,16 @@ fcfs_status enter(fcfs_handle *h) {
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return hip_fail(h, e, "pending device error");
+  }
+  if (h->stream && !h->own_capture) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if ((e = hipStreamIsCapturing(h->stream, &cs)) != hipSuccess)
+      return hip_fail(h, e, "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone)
+      return fail(h, FCFS_ERR_UNSUPPORTED,
+                  "the handle's stream is being captured into a graph by the caller; capture "
+                  "the library's work with its own plans (fcfs_forward_batch, "
+                  "fcfs_pupil_step_plan, fcfs_general_batch_plan) instead");
   }
   return FCFS_OK;
 }
@@ -468,6 +499,25 @@ struct ProfScope {
     if (!h->prof || !a) return;
     (void)hipEventRecord(b, st);
     h->prof_ev[kind].emplace_back(a, b);
+  }
+};
+
+// A pair of events for one kernel inside a launch sequence (recorded by the
+// launcher itself) when the kind is profiled; ev() is nullptr otherwise.
+struct ProfPair {
+  fcfs_handle *h;
+  int kind;
+  hipEvent_t e[2] = {nullptr, nullptr};
+  ProfPair(fcfs_handle *h_, int kind_) : h(h_), kind(kind_) {
+    if (!h->prof || !((h->prof_mask >> kind) & 1u)) return;
+    if (hipEventCreate(&e[0]) != hipSuccess || hipEventCreate(&e[1]) != hipSuccess) {
+      h->prof = false;
+      e[0] = e[1] = nullptr;
+    }
+  }
+  hipEvent_t *ev() { return e[0] ? e : nullptr; }
+  ~ProfPair() {
+    if (e[0]) h->prof_ev[kind].emplace_back(e[0], e[1]);
   }
 };
 
@@ -626,6 +676,8 @@ fcfs_status gen_tables(fcfs_handle *h, int Mx, int My, fcfs_handle::GenTab *tx,
     bool have = false;
     for (const auto &t : h->gen_tabs) have = have || match(t, N);
     if (have) continue;
+    if (h->own_capture)  // the plans build every table before they capture
+      return fail(h, FCFS_ERR_UNSUPPORTED, "period table missing during a capture");
     if ((int)h->gen_tabs.size() >= kGenMaxTabs) {
       hipError_t e = hipDeviceSynchronize();
       if (e) return hip_fail(h, e, "hipDeviceSynchronize");
@@ -855,6 +907,9 @@ fcfs_status fcfs_create(fcfs_handle **out, int device, void *hip_stream) {
 fcfs_status fcfs_destroy(fcfs_handle *h) {
   if (!h) return FCFS_OK;
   (void)hipSetDevice(h->device);
+  // plans that outlive the handle keep their graphs but no longer point at it
+  for (fcfs_step_plan *p : h->step_plans) p->h = nullptr;
+  h->step_plans.clear();
   for (auto &v : h->prof_ev)
     for (auto &pr : v) {
       (void)hipEventDestroy(pr.first);
@@ -1222,8 +1277,18 @@ fcfs_status fcfs_forward_general_band(fcfs_handle *h, const fcfs_gclip *c, int32
   return run_forward_general(h, c, q, ws);
 }
 
+// Workspace of fcfs_debug_phases: the pre-pass records and area partials.
+fcfs_status fcfs_debug_phases_workspace_size(int64_t V, int32_t T, size_t *bytes) {
+  if (!bytes) return fail(nullptr, FCFS_ERR_INVALID_ARG, "bytes is NULL");
+  FwdPlan q;
+  fcfs_status st = make_plan(nullptr, V, T, 0, 0, 0, 0, &q);
+  if (st) return st;
+  *bytes = align256(sizeof(uint4) * (size_t)q.vpad) + align256(8 * (size_t)q.pre_blocks);
+  return FCFS_OK;
+}
+
 fcfs_status fcfs_debug_phases(fcfs_handle *h, const fcfs_clip *c, int32_t axis, int32_t k0,
-                              int32_t nk, int32_t *p) {
+                              int32_t nk, int32_t *p, void *ws, size_t ws_bytes) {
   fcfs_status st = enter(h);
   if (st) return st;
   if ((st = check_clip(h, c, false))) return st;
@@ -1231,19 +1296,17 @@ fcfs_status fcfs_debug_phases(fcfs_handle *h, const fcfs_clip *c, int32_t axis, 
     return fail(h, FCFS_ERR_INVALID_ARG, "bad phase range");
   FwdPlan q;
   if ((st = make_plan(h, c->V, c->T, 0, 0, 0, 0, &q))) return st;
-  void *tmp = nullptr;
   const size_t nb = align256(sizeof(uint4) * (size_t)q.vpad) + align256(8 * (size_t)q.pre_blocks);
-  hipError_t e = hipMalloc(&tmp, nb);
-  if (e) return hip_fail(h, e, "hipMalloc");
-  uint4 *packed = (uint4 *)tmp;
-  auto *ap = ws_at<unsigned long long>(tmp, align256(sizeof(uint4) * (size_t)q.vpad));
+  if (ws_bytes < nb)
+    return fail(h, FCFS_ERR_WORKSPACE, "workspace too small: need " + std::to_string(nb) +
+                                           " bytes, got " + std::to_string(ws_bytes));
+  if (!ws || ((uintptr_t)ws & 255u)) return fail(h, FCFS_ERR_WORKSPACE, "workspace NULL or misaligned");
+  uint4 *packed = (uint4 *)ws;
+  auto *ap = ws_at<unsigned long long>(ws, align256(sizeof(uint4) * (size_t)q.vpad));
+  hipError_t e;
   if ((e = fcfs::launch_prepass(q, c->x, c->y, c->s, packed, ap, nullptr, h->stream)) ||
-      (e = fcfs::launch_debug_phases(q, packed, axis, k0, nk, p, h->stream)) ||
-      (e = hipStreamSynchronize(h->stream))) {
-    (void)hipFree(tmp);
+      (e = fcfs::launch_debug_phases(q, packed, axis, k0, nk, p, h->stream)))
     return hip_fail(h, e, "debug phases");
-  }
-  (void)hipFree(tmp);
   return FCFS_OK;
 }
 
@@ -1281,7 +1344,9 @@ fcfs_status fcfs_adjoint_band(fcfs_handle *h, const fcfs_clip *c, const float *g
   if ((e = fcfs::launch_prepass(q, c->x, c->y, c->s, ws_at<uint4>(ws, a.off_packed),
                                 ws_at<unsigned long long>(ws, a.off_area), nullptr, h->stream)))
     return hip_fail(h, e, "pre-pass launch");
-  if ((e = fcfs::launch_adjoint(a, c->x, c->y, c->s, grad_F, h->tab, ws, gx, gy, h->stream)))
+  ProfPair pg(h, kProfAdjGemm);
+  if ((e = fcfs::launch_adjoint(a, c->x, c->y, c->s, grad_F, h->tab, ws, gx, gy, h->stream,
+                                nullptr, pg.ev())))
     return hip_fail(h, e, "adjoint launch");
   return FCFS_OK;
 }
@@ -1462,13 +1527,16 @@ static void step_plan_free(fcfs_step_plan *p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap) (void)hipStreamDestroy(p->cap);
-  if (p->h)
+  if (p->h) {  // still attached: release its pins and its entry in the handle
     for (const auto &pk : p->pinned)
       for (auto &t : p->h->gen_tabs)
         if (t.N == pk.first && (t.nh > 0) == pk.second && t.pins > 0) {
           --t.pins;
           break;
         }
+    auto &v = p->h->step_plans;
+    v.erase(std::remove(v.begin(), v.end(), p), v.end());
+  }
   delete p;
 }
 
@@ -1487,6 +1555,8 @@ fcfs_status fcfs_pupil_step_plan(fcfs_handle *h, const int32_t *base_x, const in
   if (st) return st;
   auto *q = new fcfs_step_plan;
   q->device = h->device;
+  q->h = h;
+  h->step_plans.push_back(q);
   hipError_t e = hipStreamCreateWithFlags(&q->cap, hipStreamNonBlocking);
   if (e) {
     step_plan_free(q);
@@ -1504,9 +1574,11 @@ fcfs_status fcfs_pupil_step_plan(fcfs_handle *h, const int32_t *base_x, const in
     step_plan_free(q);
     return hip_fail(h, e, "hipStreamBeginCapture");
   }
+  h->own_capture = true;
   st = fcfs_pupil_step(h, base_x, base_y, s, hedge, vedge, offsets, V, T, K, L, kmax, lmax, radius,
                        G, H, p, loss, g_edge, F_out, ws, ws_bytes);
   e = hipStreamEndCapture(q->cap, &q->graph);
+  h->own_capture = false;
   h->stream = saved;
   h->prof = prof;
   if (st) {
@@ -1576,6 +1648,7 @@ fcfs_status fcfs_general_batch_plan(fcfs_handle *h, const fcfs_gclip *c, int32_t
   auto *q = new fcfs_step_plan;
   q->device = h->device;
   q->h = h;
+  h->step_plans.push_back(q);
   for (int32_t i = 0; i < n; ++i) {
     FwdPlan fp;
     if ((st = fcfs_forward_general(h, &c[i], p, slice(i), off[i + 1] - off[i])) ||
@@ -1609,9 +1682,11 @@ fcfs_status fcfs_general_batch_plan(fcfs_handle *h, const fcfs_gclip *c, int32_t
     step_plan_free(q);
     return hip_fail(h, e, "hipStreamBeginCapture");
   }
+  h->own_capture = true;
   for (int32_t i = 0; i < n && !st; ++i)
     st = fcfs_forward_general(h, &c[i], p, slice(i), off[i + 1] - off[i]);
   e = hipStreamEndCapture(q->cap, &q->graph);
+  h->own_capture = false;
   h->stream = saved;
   h->prof = prof;
   if (st) {
@@ -1691,6 +1766,7 @@ fcfs_status fcfs_adjoint_general(fcfs_handle *h, const fcfs_gclip *c, const floa
   if ((st = make_adj_plan(h, c->V, fcfs::kTabN, c->K, c->L, kmax, lmax, (int)p, &a))) return st;
   a.r2 = radius >= 0.0 ? radius * radius : -1.0;
   a.gen = true;
+  a.regb_nks = 0;  // the streaming kernel (per-period tables in LDS)
   a.T = q.Mx;
   a.Mx = q.Mx;
   a.My = q.My;
@@ -1722,7 +1798,9 @@ fcfs_status fcfs_adjoint_general(fcfs_handle *h, const fcfs_gclip *c, const floa
                                             a.pre_blocks, ws_at<uint4>(ws, a.off_packed),
                                             ws_at<unsigned long long>(ws, a.off_area), h->stream)))
     return hip_fail(h, e, "pre-pass launch");
-  if ((e = fcfs::launch_adjoint(a, c->x, c->y, c->s, grad_F, h->tab, ws, gx, gy, h->stream, &pt)))
+  ProfPair pg(h, kProfAdjGemm);
+  if ((e = fcfs::launch_adjoint(a, c->x, c->y, c->s, grad_F, h->tab, ws, gx, gy, h->stream, &pt,
+                                pg.ev())))
     return hip_fail(h, e, "adjoint launch");
   return FCFS_OK;
 }

@@ -282,7 +282,22 @@ struct AdjPlan {
   int Mx, My;
   int big, nhx, nhy;  // periods past 8192: two-level tables (nh entries of Whi)
   double rx, ry, dcf;
+  // register-resident main term (square tiles, split precisions, kb <= 128):
+  // kb / 16 steps (0: the streaming kernel), chunk sets, and its partials
+  // [4 chunks per set x sets][vpad]
+  int regb_nks, regb_sets;
+  size_t off_rpart;
 };
+
+// Register-resident adjoint main term (k_adj_gemm_regb): 32-frequency chunks
+// per set (one wave per chunk and column type) for kb / 16 = nks steps, and
+// the number of chunk sets for lb.
+inline int adj_regb_nbw(int nks) { return nks <= 6 ? 3 : 2; }
+inline int adj_regb_sets(int nks, int lb) {
+  const int nchunk = lb / 32, per = adj_regb_nbw(nks);
+  return (nchunk + per - 1) / per;
+}
+constexpr int kAdjRegbGrid = 256;  // persistent workgroups (one per CU)
 
 // Per-period tables of a general tile for the adjoint: FP64 (cos, sin) for
 // the axis terms and the operand entries of the plan's precision (split or
@@ -293,9 +308,12 @@ struct PeriodTables {
 };
 
 // gtab: non-null for a general tile (a.gen), else the square-tile tables t.
+// main_ev: when given, two events recorded on st around the main-term GEMM
+// (timing of that kernel alone).
 hipError_t launch_adjoint(const AdjPlan &a, const int32_t *x, const int32_t *y, const int8_t *s,
                           const float *gradF, const Tables &t, void *ws, float *gx, float *gy,
-                          hipStream_t st, const PeriodTables *gtab = nullptr);
+                          hipStream_t st, const PeriodTables *gtab = nullptr,
+                          hipEvent_t *main_ev = nullptr);
 hipError_t launch_edge_grad(const float *gx, const float *gy, const int64_t *hedge,
                             const int64_t *vedge, int64_t V, int64_t E, float *g_edge,
                             hipStream_t st);

@@ -24,9 +24,15 @@ def lib():
 
 
 def _declared():
-    src = open(os.path.join(ROOT, "include", "fcfs.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(fcfs_\w+)\s*\(", src)))
+    # every function the headers under include/ declare
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(fcfs_\w+)\s*\(", src))
+    return sorted(names)
 
 
 def test_exports_every_declared_symbol(lib):

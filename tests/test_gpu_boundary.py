@@ -1,0 +1,158 @@
+"""Error paths and lifetimes at the C ABI: workspaces that are too small or
+misaligned, a stream the caller is capturing, plans that outlive their
+handle, general-tile batches past the handle's table cache, and replays that
+recompute from rewritten corners.  Every case calls the library through the
+C ABI (ctypes) on cuda:0; the error cases enqueue nothing on the device."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_SPLIT = 1e-5
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1010_5562_amd as P
+
+    torch.cuda.set_device(0)
+    return P
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _forward_call(P, h, clip, prec, ws, nbytes):
+    x, y, s, _, _ = P.loops_to_corners(clip.xy, clip.off)
+    x, y, s = (torch.as_tensor(a).cuda() for a in (x, y, s))
+    F = torch.empty((2 * clip.K + 1, 2 * clip.L + 1), dtype=torch.complex64, device="cuda")
+    a = torch.empty(1, dtype=torch.int64, device="cuda")
+    c = P._clip(x, y, s, x.numel(), clip.T, clip.K, clip.L, F, a)
+    st = h.lib.fcfs_forward(h.ptr, ctypes.byref(c), P.PRECISIONS[prec], ctypes.c_void_p(ws),
+                            ctypes.c_size_t(nbytes))
+    return st, (x, y, s, F, a)
+
+
+def test_short_and_misaligned_workspace(P):
+    # FCFS_ERR_WORKSPACE (-5) before anything is enqueued, with a detail
+    h = P.Handle()
+    clip = synth.clip(81, 2048, 100, n_polygons=300)
+    need = P.workspace_size(clip.n_vertices, clip.T, clip.K, clip.L, "bf16")
+    buf = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    st, _ = _forward_call(P, h, clip, "bf16", buf.data_ptr(), need - 256)
+    assert st == -5
+    assert b"workspace too small" in h.lib.fcfs_last_error(h.ptr)
+    st, _ = _forward_call(P, h, clip, "bf16", buf.data_ptr() + 64, need)
+    assert st == -5
+    assert b"aligned" in h.lib.fcfs_last_error(h.ptr)
+    st, _ = _forward_call(P, h, clip, "bf16", None, need)
+    assert st == -5
+    # the exact size works and the handle is usable after the refusals
+    st, keep = _forward_call(P, h, clip, "bf16", buf.data_ptr(), need)
+    assert st == 0
+    torch.cuda.synchronize()
+    Fh = keep[3].cpu().numpy()
+    Fr, _ = P.forward(*keep[:3], clip.T, clip.K, clip.L, precision="bf16", handle=h)
+    torch.cuda.synchronize()
+    assert np.array_equal(Fh, Fr.cpu().numpy())
+    h.close()
+
+
+def test_external_capture_is_refused(P):
+    # a stream the caller is capturing into a graph is refused with
+    # FCFS_ERR_UNSUPPORTED (-4) before the library enqueues anything
+    clip = synth.clip(82, 1024, 40, n_polygons=50)
+    x, y, s, _, _ = P.loops_to_corners(clip.xy, clip.off)
+    x, y, s = (torch.as_tensor(a).cuda() for a in (x, y, s))
+    h = P.Handle()
+    F0, _ = P.forward(x, y, s, clip.T, clip.K, clip.L, precision="bf16", handle=h)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    z = torch.zeros(8, device="cuda")
+    with pytest.raises(P.FcfsError) as ei:
+        with torch.cuda.graph(g):
+            z.add_(1.0)
+            P.forward(x, y, s, clip.T, clip.K, clip.L, precision="bf16", handle=h)
+    assert ei.value.status == -4
+    # outside the capture the handle works as before
+    F1, _ = P.forward(x, y, s, clip.T, clip.K, clip.L, precision="bf16", handle=h)
+    torch.cuda.synchronize()
+    assert torch.equal(F0, F1)
+    h.close()
+
+
+def _gclip(P, seed, Nx, Ny, F, K, n):
+    # n polygons drawn on the grid of step 2^-F inside an Nx x Ny tile
+    c = synth.clip(seed, min(Nx, Ny) << F, K, n_polygons=n)
+    x, y, s, _, _ = P.loops_to_corners(c.xy, c.off)
+    return (x, y, s, Nx, Ny, K, K, F), c
+
+
+def test_plan_outlives_its_handle(P):
+    # destroying the handle first detaches its captured plans; the plan is
+    # then destroyed without touching the handle
+    h = P.Handle()
+    clips = [_gclip(P, 83 + i, 600 + 50 * i, 500, 1, 20, 20)[0] for i in range(3)]
+    b = P.GeneralBatch(clips, precision="bf16", handle=h)
+    torch.cuda.synchronize()
+    b.run()
+    torch.cuda.synchronize()
+    h.close()
+    b.close()
+    # a new handle and plan work normally afterwards
+    h2 = P.Handle()
+    b2 = P.GeneralBatch(clips, precision="bf16", handle=h2)
+    b2.run()
+    torch.cuda.synchronize()
+    b2.close()
+    h2.close()
+
+
+def test_general_batch_past_the_table_cache(P, oracle_lib):
+    # 20 clips with 20 distinct x periods (the handle caches 16 period tables
+    # and grows past that for tables a plan pins); then corners rewritten in
+    # place between replays: every replay recomputes from the current corners
+    h = P.Handle()
+    specs = [(1000 + 37 * i, 1000, 0, 12, 30, 900 + i) for i in range(20)]
+    clips, loops = [], []
+    for Nx, Ny, F, K, n, seed in specs:
+        cl, c = _gclip(P, seed, Nx, Ny, F, K, n)
+        clips.append(cl)
+        loops.append(c)
+    b = P.GeneralBatch(clips, precision="bf16", handle=h)
+    torch.cuda.synchronize()
+    for i, (Nx, Ny, F, K, n, seed) in enumerate(specs):
+        ref, area = oracle_lib.cfs_grid_general(loops[i].xy, loops[i].off, Nx, Ny, K, K)
+        e = float(np.max(np.abs(b.F[i].cpu().numpy().astype(np.complex128) - ref)) / abs(ref[K, K]))
+        assert int(b.area[i].item()) == area
+        assert e <= TOL_SPLIT, (i, e)
+    # rewrite the corners of every clip (same count: the polygons shifted by
+    # one grid step along x) and replay twice
+    for rep in range(2):
+        for i, (x, y, s) in enumerate(b.corners):
+            x.add_(1)
+        b.run()
+        torch.cuda.synchronize()
+        for i, (Nx, Ny, F, K, n, seed) in enumerate(specs):
+            xy = loops[i].xy.astype(np.int64) + np.array([rep + 1, 0])
+            x, y, s = (t.clone() for t in b.corners[i])
+            Fs, a = P.forward_general(x, y, s, Nx, Ny, K, K, frac_bits=F, precision="bf16",
+                                      handle=h)
+            torch.cuda.synchronize()
+            assert np.array_equal(Fs.cpu().numpy(), b.F[i].cpu().numpy()), (rep, i)
+            if i % 7 == 0:
+                ref, area = oracle_lib.cfs_grid_general(xy, loops[i].off, Nx, Ny, K, K)
+                e = float(np.max(np.abs(Fs.cpu().numpy().astype(np.complex128) - ref))
+                          / abs(ref[K, K]))
+                assert e <= TOL_SPLIT, (rep, i, e)
+    _say(f"general batch of {len(specs)} clips, {len(set(s[0] for s in specs))} periods: ok")
+    b.close()
+    h.close()
