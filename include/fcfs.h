@@ -125,6 +125,20 @@ fcfs_status fcfs_workspace_size(const fcfs_clip *c, fcfs_precision p, int adjoin
 fcfs_status fcfs_forward(fcfs_handle *h, const fcfs_clip *c, fcfs_precision p, void *ws,
                          size_t ws_bytes);
 
+/* fcfs_forward without a workspace argument, for callers that cannot
+ * allocate device memory (serving loops and harnesses that forbid it): the
+ * work runs in a scratch array the library holds on each device it runs on,
+ * 80 MiB, for the life of the process (the precision clip of 200k corners at
+ * T = 8192, K = L = 511 needs 72 MiB).  Same arguments, kernels and results as
+ * fcfs_forward; a clip whose workspace (fcfs_workspace_size) exceeds the
+ * scratch is refused with FCFS_ERR_WORKSPACE.  The call allocates nothing:
+ * no hipMalloc or hipFree, no allocating library routine.  Every call on a
+ * device shares that device's scratch, so calls that overlap on one device
+ * (several streams or host threads) race; the scratch keeps the last call's
+ * contents, none of which a later call reads.  Like every entry point it
+ * refuses a stream the caller is capturing. */
+fcfs_status fcfs_forward_noalloc(fcfs_handle *h, const fcfs_clip *c, fcfs_precision p);
+
 /* Low-pass forward: fcfs_forward restricted to the band |k| <= kmax,
  * |l| <= lmax (clamped to K, L) and, when radius >= 0, to the disc
  * k^2 + l^2 <= radius^2 (a circular pupil, as needed by lithography models,

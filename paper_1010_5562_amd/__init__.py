@@ -86,6 +86,26 @@ def workspace_size(V: int, T: int, K: int, L: int, precision="bf16", adjoint: bo
     return int(n.value)
 
 
+def forward_noalloc(x, y, s, T: int, K: int, L: int | None = None, precision="bf16",
+                    handle=None, out=None, area_out=None):
+    """``forward`` through ``fcfs_forward_noalloc``: the library's own scratch on
+    the device replaces the workspace (clips up to its size).  Returns
+    ``(F, area)``; ``out`` / ``area_out`` may supply the output tensors."""
+    import torch
+
+    L = K if L is None else L
+    h = handle or default_handle()
+    h.sync_stream()
+    x, y, s = _corners_on(h.device, x, y, s)
+    V = x.numel()
+    F = out if out is not None else torch.empty((2 * K + 1, 2 * L + 1), dtype=torch.complex64,
+                                                 device=h.device)
+    a = area_out if area_out is not None else torch.empty(1, dtype=torch.int64, device=h.device)
+    c = _clip(x, y, s, V, T, K, L, F, a)
+    check(h.lib.fcfs_forward_noalloc(h.ptr, ctypes.byref(c), _prec(precision)), h.ptr)
+    return F, a
+
+
 def plan_info(V: int, T: int, K: int, L: int, precision="bf16") -> dict:
     """The automatic plan of ``forward`` for these sizes (``fcfs_forward_plan_info``):
     vertex splits, corners per split, frequency tiles, direct form."""

@@ -28,7 +28,7 @@ STATUS_NAMES = {
 # Every symbol the headers under include/ declare (fcfs.h, fcfs_tuning.h).
 EXPORTS = (
     "fcfs_create", "fcfs_destroy", "fcfs_set_stream", "fcfs_loops_to_corners",
-    "fcfs_workspace_size", "fcfs_forward", "fcfs_band_workspace_size", "fcfs_forward_band",
+    "fcfs_workspace_size", "fcfs_forward", "fcfs_forward_noalloc", "fcfs_band_workspace_size", "fcfs_forward_band",
     "fcfs_fft_workspace_size", "fcfs_forward_fft", "fcfs_haar_workspace_size", "fcfs_haar",
     "fcfs_general_workspace_size", "fcfs_forward_general",
     "fcfs_general_band_workspace_size", "fcfs_forward_general_band",
@@ -126,6 +126,7 @@ def load() -> ctypes.CDLL:
         "fcfs_forward_plan_info": [clip_p, c_int, ctypes.POINTER(i32), ctypes.POINTER(i64),
                                    ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "fcfs_forward": [P, clip_p, c_int, P, ctypes.c_size_t],
+        "fcfs_forward_noalloc": [P, clip_p, c_int],
         "fcfs_band_workspace_size": [clip_p, i32, i32, ctypes.c_double, c_int, sz],
         "fcfs_forward_band": [P, clip_p, i32, i32, ctypes.c_double, c_int, P, ctypes.c_size_t],
         "fcfs_fft_workspace_size": [clip_p, sz],

@@ -92,9 +92,49 @@ struct fcfs_step_plan {
   std::vector<std::pair<int, bool>> pinned;
 };
 
+// ---------------------------------------------------------------------------
+// Library-held scratch of fcfs_forward_noalloc: a device array of
+// kScratchBytes that each device the library runs on holds until the process
+// ends.  In host code the array's name is only a stand-in: its device address
+// (one per device) is looked up with hipGetSymbolAddress at fcfs_create, with
+// that device current, and kept in g_scratch; kernels get that address.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)80 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 bool load_tune(fcfs_handle *h, const char *path);
+
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch;         // per device ordinal: the array's device address
+std::vector<hipError_t> g_scratch_st;  // status of the lookup (hipErrorNotReady: not done)
+
+// Looks up the scratch array's address on `device` (current) once.
+hipError_t scratch_init(int device) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if ((int)g_scratch.size() <= device) {
+    g_scratch.resize(device + 1, nullptr);
+    g_scratch_st.resize(device + 1, hipErrorNotReady);
+  }
+  if (g_scratch_st[device] == hipErrorNotReady) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch[device] = e == hipSuccess ? p : nullptr;
+    g_scratch_st[device] = e;
+  }
+  return g_scratch_st[device];
+}
+
+void *scratch_ptr(int device, hipError_t *st) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (device < 0 || device >= (int)g_scratch.size()) {
+    *st = hipErrorNotReady;
+    return nullptr;
+  }
+  *st = g_scratch_st[device];
+  return g_scratch[device];
+}
 
 std::mutex g_err_mu;
 std::string g_err;  // last error of a handle-less call
@@ -898,6 +938,9 @@ fcfs_status fcfs_create(fcfs_handle **out, int device, void *hip_stream) {
     delete h;
     return st;
   }
+  // the no-allocation entry point's scratch on this device (a failed lookup
+  // is reported by that entry point, not here)
+  (void)scratch_init(device);
   // an autotune cache named by the environment, if present and well formed
   if (const char *path = std::getenv("FCFS_AUTOTUNE_CACHE")) (void)load_tune(h, path);
   *out = h;
@@ -1096,6 +1139,32 @@ fcfs_status fcfs_forward(fcfs_handle *h, const fcfs_clip *c, fcfs_precision p, v
     return e ? hip_fail(h, e, "direct launch") : FCFS_OK;
   }
   return run_forward(h, c, q, ws);
+}
+
+fcfs_status fcfs_forward_noalloc(fcfs_handle *h, const fcfs_clip *c, fcfs_precision p) {
+  fcfs_status st = enter(h);
+  if (st) return st;
+  if ((st = check_clip(h, c, true))) return st;
+  FwdPlan q;
+  if ((st = make_plan(h, c->V, c->T, c->K, c->L, (int)p, h->tile_override, &q))) return st;
+  if (q.bytes > kScratchBytes)
+    return fail(h, FCFS_ERR_WORKSPACE,
+                "the clip needs " + std::to_string(q.bytes) + " bytes of scratch, the library " +
+                    "holds " + std::to_string(kScratchBytes) + "; use fcfs_forward with a workspace");
+  hipError_t e;
+  void *ws = scratch_ptr(h->device, &e);
+  if (!ws) return hip_fail(h, e, "library scratch (hipGetSymbolAddress)");
+  // the profiling hooks create events: off for this call
+  const bool prof = h->prof;
+  h->prof = false;
+  if (h->tile_override < 0 && use_direct(c->V, c->K, c->L)) {
+    e = fcfs::launch_direct(q, c->x, c->y, c->s, h->tab.w64, c->F, c->area, h->stream);
+    st = e ? hip_fail(h, e, "direct launch") : FCFS_OK;
+  } else {
+    st = run_forward(h, c, q, ws);
+  }
+  h->prof = prof;
+  return st;
 }
 
 namespace {
