@@ -63,8 +63,22 @@ typedef enum {
  *   FCFS_SPLIT_BF16  twiddle w = hi + lo with hi, lo bfloat16 (round to
  *                    nearest even); hi*hi' + hi*lo' + lo*hi' on bf16 MFMA,
  *                    FP32 accumulation.
- *   FCFS_SPLIT_FP16  the same with binary16 hi, lo. */
-typedef enum { FCFS_FP32 = 0, FCFS_SPLIT_BF16 = 1, FCFS_SPLIT_FP16 = 2 } fcfs_precision;
+ *   FCFS_SPLIT_FP16  the same with binary16 hi, lo.
+ *   FCFS_AUTO        (fcfs_forward, fcfs_forward_noalloc, fcfs_workspace_size
+ *                    and fcfs_forward_plan_info only) the form a cost model
+ *                    expects to be fastest among those that meet the split
+ *                    bound: the lattice form of fcfs_forward_fft (FP64) where
+ *                    its work, about L T log2 T, is well below the
+ *                    contraction's 24 (K+1)(L+1) V flop (large V, small T:
+ *                    Step 4 of Sec. III-C1 as a 2-D DFT of the corner
+ *                    image), else the split-bf16 contraction; the direct form
+ *                    for small problems as always. */
+typedef enum {
+  FCFS_FP32 = 0,
+  FCFS_SPLIT_BF16 = 1,
+  FCFS_SPLIT_FP16 = 2,
+  FCFS_AUTO = 3
+} fcfs_precision;
 
 typedef struct fcfs_handle fcfs_handle;
 typedef struct fcfs_plan fcfs_plan;
@@ -433,8 +447,9 @@ fcfs_status fcfs_load_tune(fcfs_handle *h, const char *cache_path);
 
 /* The plan fcfs_forward makes for clip `c` at precision `p` with the automatic
  * tile choice (pointers in `c` are not read): vertex splits, corners per split,
- * frequency tiles, and whether the one-launch direct form runs instead.  Any
- * output pointer may be NULL. */
+ * frequency tiles, and the form: *direct = 1 when the one-launch direct form
+ * runs instead, 2 when FCFS_AUTO takes the lattice form, else 0.  Any output
+ * pointer may be NULL. */
 fcfs_status fcfs_forward_plan_info(const fcfs_clip *c, fcfs_precision p, int32_t *nsplit,
                                    int64_t *chunk, int32_t *tiles, int32_t *direct);
 

@@ -108,14 +108,16 @@ def forward_noalloc(x, y, s, T: int, K: int, L: int | None = None, precision="bf
 
 def plan_info(V: int, T: int, K: int, L: int, precision="bf16") -> dict:
     """The automatic plan of ``forward`` for these sizes (``fcfs_forward_plan_info``):
-    vertex splits, corners per split, frequency tiles, direct form."""
+    vertex splits, corners per split, frequency tiles, direct form, and the form
+    taken ("contraction", "direct" or, for precision "auto", "lattice")."""
     lib = load()
     c = _clip(None, None, None, V, T, K, L)
     ns, ti, di = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
     ch = ctypes.c_int64(0)
     check(lib.fcfs_forward_plan_info(ctypes.byref(c), _prec(precision), ctypes.byref(ns),
                                      ctypes.byref(ch), ctypes.byref(ti), ctypes.byref(di)))
-    return {"nsplit": ns.value, "chunk": ch.value, "tiles": ti.value, "direct": bool(di.value)}
+    return {"nsplit": ns.value, "chunk": ch.value, "tiles": ti.value, "direct": di.value == 1,
+            "form": ("contraction", "direct", "lattice")[di.value]}
 
 
 class Handle:

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfcfs.so")
 
 FCFS_OK = 0
-PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2, "auto": 3}
 
 STATUS_NAMES = {
     0: "FCFS_OK",

@@ -1,9 +1,11 @@
 // Host runtime and C ABI of the FCFS library: handle, twiddle tables, planner,
 // validation, loops -> corners canonicalisation and the entry points of
 // include/fcfs.h and include/fcfs_tuning.h.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -151,6 +153,77 @@ fcfs_status fail(fcfs_handle *h, fcfs_status st, const std::string &msg) {
 
 fcfs_status hip_fail(fcfs_handle *h, hipError_t e, const char *what) {
   return fail(h, FCFS_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics.  FCFS_LOG=1 prints one line per call to stderr (entry point,
+// sizes, the plan taken); FCFS_LOG=2 adds the workspace layout.  FCFS_ROCTX=1
+// brackets every entry point with a roctx range (rocprofv3 --marker-trace),
+// the roctx library being opened at run time when present.
+// ---------------------------------------------------------------------------
+int log_level() {
+  static const int lv = [] {
+    const char *e = std::getenv("FCFS_LOG");
+    return e ? std::atoi(e) : 0;
+  }();
+  return lv;
+}
+
+void logf(int level, const char *fmt, ...) {
+  if (log_level() < level) return;
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  std::fprintf(stderr, "[fcfs] %s\n", buf);
+}
+
+struct Roctx {
+  int (*push)(const char *) = nullptr;
+  int (*pop)() = nullptr;
+};
+const Roctx &roctx() {
+  static const Roctx r = [] {
+    Roctx t;
+    const char *e = std::getenv("FCFS_ROCTX");
+    if (!e || std::atoi(e) == 0) return t;
+    for (const char *lib : {"librocprofiler-sdk-roctx.so.1", "libroctx64.so.4", "libroctx64.so"}) {
+      void *d = dlopen(lib, RTLD_NOW | RTLD_LOCAL);
+      if (!d) continue;
+      t.push = (int (*)(const char *))dlsym(d, "roctxRangePushA");
+      t.pop = (int (*)())dlsym(d, "roctxRangePop");
+      if (t.push && t.pop) break;
+      t.push = nullptr;
+      t.pop = nullptr;
+    }
+    return t;
+  }();
+  return r;
+}
+
+// A roctx range around one entry point (no-op unless FCFS_ROCTX is set).
+struct Range {
+  bool on;
+  explicit Range(const char *name) : on(roctx().push != nullptr) {
+    if (on) roctx().push(name);
+  }
+  ~Range() {
+    if (on) roctx().pop();
+  }
+};
+
+const char *prec_name(int p) {
+  return p == fcfs::kFP32 ? "fp32" : p == fcfs::kBF16 ? "split-bf16" : "split-fp16";
+}
+
+void log_plan(const char *name, const FwdPlan &q, bool direct) {
+  logf(1, "%s V=%lld T=%d K=%d L=%d %s: %s tiles=%dx%d nsplit=%d chunk=%lld variant=%d ws=%zu",
+       name, (long long)q.V, q.Mx == q.My ? q.T : q.Mx, q.KO, q.LO, prec_name(q.prec),
+       direct ? "direct form" : "contraction", q.tiles_k, q.tiles_l, q.nsplit,
+       (long long)q.chunk, q.tile, q.bytes);
+  logf(2, "%s layout: packed@%zu area@%zu hist@%zu axis@%zu part@%zu guard@%zu gspan@%zu", name,
+       q.off_packed, q.off_area, q.off_hist, q.off_axis, q.off_part, q.off_guard, q.off_gspan);
 }
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -574,6 +647,62 @@ constexpr int64_t kDirectMaxPairs = int64_t(1) << 22;
 
 bool use_direct(int64_t V, int K, int L) {
   return V <= kDirectMaxCorners && V * (K + 1) * (2 * (int64_t)L + 1) <= kDirectMaxPairs;
+}
+
+// FCFS_AUTO: the lattice form when its cost model is well below the split
+// contraction's.  Per second of the measured kernels on one MI355X: the
+// contraction runs about 1.3e15 of its 24 (K+1)(L+1) V split flop, the
+// lattice form's column FFTs and row DFTs take about 6e-12 s per L T log2 T.
+bool auto_lattice(int64_t V, int T, int K, int L) {
+  if (K == 0 || L == 0) return false;
+  const double tc = 24.0 * (K + 1.0) * (L + 1.0) * (double)V / 1.3e15;
+  const double tl = 6e-12 * (double)L * (double)T * std::log2((double)T);
+  return tl < 0.8 * tc;
+}
+
+// The form fcfs_forward takes: 1 direct, 2 lattice (FCFS_AUTO only), 0 the
+// contraction; *prec is the contraction's precision.
+int forward_form(int64_t V, int T, int K, int L, int p, int tile_override, int *prec) {
+  *prec = p == FCFS_AUTO ? fcfs::kBF16 : p;
+  if (tile_override < 0 && use_direct(V, K, L)) return 1;
+  if (p == FCFS_AUTO && auto_lattice(V, T, K, L)) return 2;
+  return 0;
+}
+
+// The lattice form (Step 4 as the 2-D DFT of the corner image) of a checked
+// clip: pre-pass, axis sums, row DFTs and column FFTs, epilogue.
+fcfs_status lattice_forward(fcfs_handle *h, const fcfs_clip *c, void *ws, size_t ws_bytes) {
+  fcfs_status st;
+  FwdPlan q;
+  if ((st = make_plan(h, c->V, c->T, c->K, c->L, fcfs::kFP32, -1, &q, -1.0, true))) return st;
+  if ((st = check_ws(h, q, ws, ws_bytes))) return st;
+  logf(1, "fcfs_forward_fft V=%lld T=%d K=%d L=%d: lattice form, ws=%zu", (long long)q.V, q.T,
+       q.K, q.L, q.bytes);
+  hipError_t e;
+  {
+    ProfScope ps(h, kProfPrepass);
+    if ((e = fcfs::launch_prepass(q, c->x, c->y, c->s, ws_at<uint4>(ws, q.off_packed),
+                                  ws_at<unsigned long long>(ws, q.off_area),
+                                  ws_at<unsigned long long>(ws, q.off_hist), h->stream)))
+      return hip_fail(h, e, "pre-pass launch");
+  }
+  {
+    ProfScope ps(h, kProfAxis);
+    if (q.K + q.L > 0 &&
+        (e = fcfs::launch_side(q, c->x, c->y, h->tab.w64, ws, h->stream, false)))
+      return hip_fail(h, e, "axis launch");
+  }
+  if (q.K > 0 && q.L > 0) {
+    ProfScope ps(h, kProfFft);
+    if ((e = fcfs::launch_fft(q, c->x, c->y, c->s, h->tab.w64, ws, c->F, h->stream)))
+      return hip_fail(h, e, "lattice-form launch");
+  }
+  {
+    ProfScope ps(h, kProfEpilogue);
+    if ((e = fcfs::launch_epilogue_axes(q, ws, c->F, c->area, h->stream)))
+      return hip_fail(h, e, "epilogue launch");
+  }
+  return FCFS_OK;
 }
 
 fcfs_status run_forward(fcfs_handle *h, const fcfs_clip *c, const FwdPlan &p, void *ws) {
@@ -1038,6 +1167,7 @@ int32_t fcfs_tile_variants(int32_t *wk, int32_t *wl, int32_t cap) {
 fcfs_status fcfs_loops_to_corners(const int32_t *xy, const int64_t *loop_off, int64_t n_loops,
                                   int32_t *x, int32_t *y, int8_t *s, int64_t *hedge,
                                   int64_t *vedge) {
+  Range rg("fcfs_loops_to_corners");
   if (n_loops < 0 || !loop_off) return fail(nullptr, FCFS_ERR_INVALID_ARG, "bad loop offsets");
   if (loop_off[0] != 0) return fail(nullptr, FCFS_ERR_INVALID_ARG, "loop_off[0] must be 0");
   const int64_t nv = loop_off[n_loops];
@@ -1083,13 +1213,18 @@ fcfs_status fcfs_loops_to_corners(const int32_t *xy, const int64_t *loop_off, in
       if (vedge) vedge[v] = next_h ? prev : next;
     }
   }
+  logf(1, "fcfs_loops_to_corners %lld loops, %lld corners", (long long)n_loops,
+       (long long)loop_off[n_loops]);
   return FCFS_OK;
 }
 
 fcfs_status fcfs_workspace_size(const fcfs_clip *c, fcfs_precision p, int adjoint, size_t *bytes) {
   if (!c || !bytes) return fail(nullptr, FCFS_ERR_INVALID_ARG, "NULL argument");
+  if (p == FCFS_AUTO && adjoint) return fail(nullptr, FCFS_ERR_INVALID_ARG, "FCFS_AUTO is forward only");
   FwdPlan q;
-  fcfs_status st = make_plan(nullptr, c->V, c->T, c->K, c->L, (int)p, -1, &q);
+  int prec = (int)p;
+  const int form = forward_form(c->V, c->T, c->K, c->L, (int)p, -1, &prec);
+  fcfs_status st = make_plan(nullptr, c->V, c->T, c->K, c->L, prec, -1, &q, -1.0, form == 2);
   if (st) return st;
   *bytes = q.bytes;
   if (adjoint) {
@@ -1106,12 +1241,14 @@ fcfs_status fcfs_forward_plan_info(const fcfs_clip *c, fcfs_precision p, int32_t
                                    int64_t *chunk, int32_t *tiles, int32_t *direct) {
   if (!c) return fail(nullptr, FCFS_ERR_INVALID_ARG, "NULL argument");
   FwdPlan q;
-  fcfs_status st = make_plan(nullptr, c->V, c->T, c->K, c->L, (int)p, -1, &q);
+  int prec = (int)p;
+  const int form = forward_form(c->V, c->T, c->K, c->L, (int)p, -1, &prec);
+  fcfs_status st = make_plan(nullptr, c->V, c->T, c->K, c->L, prec, -1, &q, -1.0, form == 2);
   if (st) return st;
   if (nsplit) *nsplit = q.nsplit;
   if (chunk) *chunk = q.chunk;
   if (tiles) *tiles = q.tiles_k * q.tiles_l;
-  if (direct) *direct = use_direct(c->V, c->K, c->L) ? 1 : 0;
+  if (direct) *direct = form;
   return FCFS_OK;
 }
 
@@ -1127,13 +1264,21 @@ fcfs_status fcfs_workspace_size_tile(const fcfs_clip *c, fcfs_precision p, int32
 
 fcfs_status fcfs_forward(fcfs_handle *h, const fcfs_clip *c, fcfs_precision p, void *ws,
                          size_t ws_bytes) {
+  Range rg("fcfs_forward");
   fcfs_status st = enter(h);
   if (st) return st;
   if ((st = check_clip(h, c, true))) return st;
+  int prec = (int)p;
+  const int form = forward_form(c->V, c->T, c->K, c->L, (int)p, h->tile_override, &prec);
+  if (form == 2) {
+    logf(1, "fcfs_forward FCFS_AUTO: lattice form");
+    return lattice_forward(h, c, ws, ws_bytes);
+  }
   FwdPlan q;
-  if ((st = make_plan(h, c->V, c->T, c->K, c->L, (int)p, h->tile_override, &q))) return st;
+  if ((st = make_plan(h, c->V, c->T, c->K, c->L, prec, h->tile_override, &q))) return st;
   if ((st = check_ws(h, q, ws, ws_bytes))) return st;
-  if (h->tile_override < 0 && use_direct(c->V, c->K, c->L)) {
+  log_plan("fcfs_forward", q, form == 1);
+  if (form == 1) {
     ProfScope ps(h, kProfDirect);
     hipError_t e = fcfs::launch_direct(q, c->x, c->y, c->s, h->tab.w64, c->F, c->area, h->stream);
     return e ? hip_fail(h, e, "direct launch") : FCFS_OK;
@@ -1142,11 +1287,15 @@ fcfs_status fcfs_forward(fcfs_handle *h, const fcfs_clip *c, fcfs_precision p, v
 }
 
 fcfs_status fcfs_forward_noalloc(fcfs_handle *h, const fcfs_clip *c, fcfs_precision p) {
+  Range rg("fcfs_forward_noalloc");
   fcfs_status st = enter(h);
   if (st) return st;
   if ((st = check_clip(h, c, true))) return st;
+  int prec = (int)p;
+  const int form = forward_form(c->V, c->T, c->K, c->L, (int)p, h->tile_override, &prec);
   FwdPlan q;
-  if ((st = make_plan(h, c->V, c->T, c->K, c->L, (int)p, h->tile_override, &q))) return st;
+  if ((st = make_plan(h, c->V, c->T, c->K, c->L, prec, h->tile_override, &q, -1.0, form == 2)))
+    return st;
   if (q.bytes > kScratchBytes)
     return fail(h, FCFS_ERR_WORKSPACE,
                 "the clip needs " + std::to_string(q.bytes) + " bytes of scratch, the library " +
@@ -1154,10 +1303,13 @@ fcfs_status fcfs_forward_noalloc(fcfs_handle *h, const fcfs_clip *c, fcfs_precis
   hipError_t e;
   void *ws = scratch_ptr(h->device, &e);
   if (!ws) return hip_fail(h, e, "library scratch (hipGetSymbolAddress)");
+  log_plan("fcfs_forward_noalloc", q, form == 1);
   // the profiling hooks create events: off for this call
   const bool prof = h->prof;
   h->prof = false;
-  if (h->tile_override < 0 && use_direct(c->V, c->K, c->L)) {
+  if (form == 2) {
+    st = lattice_forward(h, c, ws, kScratchBytes);
+  } else if (form == 1) {
     e = fcfs::launch_direct(q, c->x, c->y, c->s, h->tab.w64, c->F, c->area, h->stream);
     st = e ? hip_fail(h, e, "direct launch") : FCFS_OK;
   } else {
@@ -1194,12 +1346,15 @@ fcfs_status fcfs_band_workspace_size(const fcfs_clip *c, int32_t kmax, int32_t l
 
 fcfs_status fcfs_forward_band(fcfs_handle *h, const fcfs_clip *c, int32_t kmax, int32_t lmax,
                               double radius, fcfs_precision p, void *ws, size_t ws_bytes) {
+  Range rg("fcfs_forward_band");
   fcfs_status st = enter(h);
   if (st) return st;
   if ((st = check_clip(h, c, true))) return st;
   FwdPlan q;
   if ((st = make_band_plan(h, c, kmax, lmax, radius, (int)p, h->tile_override, &q))) return st;
   if ((st = check_ws(h, q, ws, ws_bytes))) return st;
+  log_plan("fcfs_forward_band", q, false);
+  logf(1, "fcfs_forward_band band |k|<=%d |l|<=%d radius %g", q.K, q.L, radius);
   return run_forward(h, c, q, ws);
 }
 
@@ -1213,37 +1368,11 @@ fcfs_status fcfs_fft_workspace_size(const fcfs_clip *c, size_t *bytes) {
 }
 
 fcfs_status fcfs_forward_fft(fcfs_handle *h, const fcfs_clip *c, void *ws, size_t ws_bytes) {
+  Range rg("fcfs_forward_fft");
   fcfs_status st = enter(h);
   if (st) return st;
   if ((st = check_clip(h, c, true))) return st;
-  FwdPlan q;
-  if ((st = make_plan(h, c->V, c->T, c->K, c->L, fcfs::kFP32, -1, &q, -1.0, true))) return st;
-  if ((st = check_ws(h, q, ws, ws_bytes))) return st;
-  hipError_t e;
-  {
-    ProfScope ps(h, kProfPrepass);
-    if ((e = fcfs::launch_prepass(q, c->x, c->y, c->s, ws_at<uint4>(ws, q.off_packed),
-                                  ws_at<unsigned long long>(ws, q.off_area),
-                                  ws_at<unsigned long long>(ws, q.off_hist), h->stream)))
-      return hip_fail(h, e, "pre-pass launch");
-  }
-  {
-    ProfScope ps(h, kProfAxis);
-    if (q.K + q.L > 0 &&
-        (e = fcfs::launch_side(q, c->x, c->y, h->tab.w64, ws, h->stream, false)))
-      return hip_fail(h, e, "axis launch");
-  }
-  if (q.K > 0 && q.L > 0) {
-    ProfScope ps(h, kProfFft);
-    if ((e = fcfs::launch_fft(q, c->x, c->y, c->s, h->tab.w64, ws, c->F, h->stream)))
-      return hip_fail(h, e, "lattice-form launch");
-  }
-  {
-    ProfScope ps(h, kProfEpilogue);
-    if ((e = fcfs::launch_epilogue_axes(q, ws, c->F, c->area, h->stream)))
-      return hip_fail(h, e, "epilogue launch");
-  }
-  return FCFS_OK;
+  return lattice_forward(h, c, ws, ws_bytes);
 }
 
 namespace {
@@ -1276,6 +1405,7 @@ fcfs_status fcfs_haar_workspace_size(const fcfs_haar_clip *c, size_t *bytes) {
 }
 
 fcfs_status fcfs_haar(fcfs_handle *h, const fcfs_haar_clip *c, void *ws, size_t ws_bytes) {
+  Range rg("fcfs_haar");
   fcfs_status st = enter(h);
   if (st) return st;
   if ((st = check_haar(h, c, true))) return st;
@@ -1309,6 +1439,7 @@ fcfs_status fcfs_general_workspace_size(const fcfs_gclip *c, fcfs_precision p, s
 
 fcfs_status fcfs_forward_general(fcfs_handle *h, const fcfs_gclip *c, fcfs_precision p, void *ws,
                                  size_t ws_bytes) {
+  Range rg("fcfs_forward_general");
   fcfs_status st = enter(h);
   if (st) return st;
   FwdPlan q;
@@ -1317,6 +1448,9 @@ fcfs_status fcfs_forward_general(fcfs_handle *h, const fcfs_gclip *c, fcfs_preci
     return fail(h, FCFS_ERR_INVALID_ARG, "corner arrays are NULL");
   if (!c->F) return fail(h, FCFS_ERR_INVALID_ARG, "output F is NULL");
   if ((st = check_ws(h, q, ws, ws_bytes))) return st;
+  log_plan("fcfs_forward_general", q, false);
+  logf(1, "fcfs_forward_general periods %d x %d grid units (Nx %d, Ny %d, 2^-%d grid)%s", q.Mx,
+       q.My, c->Nx, c->Ny, c->frac_bits, q.big ? ", two-level twiddles" : "");
   return run_forward_general(h, c, q, ws);
 }
 
@@ -1331,6 +1465,7 @@ fcfs_status fcfs_general_band_workspace_size(const fcfs_gclip *c, int32_t kmax, 
 fcfs_status fcfs_forward_general_band(fcfs_handle *h, const fcfs_gclip *c, int32_t kmax,
                                       int32_t lmax, double radius, fcfs_precision p, void *ws,
                                       size_t ws_bytes) {
+  Range rg("fcfs_forward_general_band");
   fcfs_status st = enter(h);
   if (st) return st;
   if (kmax < 0 || lmax < 0) return fail(h, FCFS_ERR_INVALID_ARG, "band must be >= 0");
@@ -1382,6 +1517,7 @@ fcfs_status fcfs_debug_phases(fcfs_handle *h, const fcfs_clip *c, int32_t axis, 
 fcfs_status fcfs_adjoint_band(fcfs_handle *h, const fcfs_clip *c, const float *grad_F,
                               int32_t kmax, int32_t lmax, double radius, float *gx, float *gy,
                               fcfs_precision p, void *ws, size_t ws_bytes) {
+  Range rg("fcfs_adjoint_band");
   fcfs_status st = enter(h);
   if (st) return st;
   if ((st = check_clip(h, c, false))) return st;
@@ -1396,6 +1532,9 @@ fcfs_status fcfs_adjoint_band(fcfs_handle *h, const fcfs_clip *c, const float *g
   fcfs::AdjPlan a;
   if ((st = make_adj_plan(h, c->V, c->T, c->K, c->L, kmax, lmax, (int)p, &a))) return st;
   a.r2 = radius >= 0.0 ? radius * radius : -1.0;
+  logf(1, "fcfs_adjoint_band V=%lld T=%d K=%d L=%d %s: band %d x %d, GEMM %d x %d, %s, ws=%zu",
+       (long long)a.V, a.T, a.K, a.L, prec_name(a.prec), a.kmax, a.lmax, a.R, a.NC,
+       a.regb_nks ? "register-resident main term" : "streaming main term", a.bytes);
   if (ws_bytes < a.bytes)
     return fail(h, FCFS_ERR_WORKSPACE,
                 "workspace too small: need " + std::to_string(a.bytes) + " bytes, got " +
@@ -1428,6 +1567,7 @@ fcfs_status fcfs_adjoint(fcfs_handle *h, const fcfs_clip *c, const float *grad_F
 
 fcfs_status fcfs_edge_grad(fcfs_handle *h, const float *gx, const float *gy, const int64_t *hedge,
                            const int64_t *vedge, int64_t V, int64_t E, float *g_edge) {
+  Range rg("fcfs_edge_grad");
   fcfs_status st = enter(h);
   if (st) return st;
   if (V < 0 || E < 0) return fail(h, FCFS_ERR_INVALID_ARG, "negative size");
@@ -1476,6 +1616,7 @@ fcfs_status fcfs_pupil_loss_workspace_size(size_t *bytes) {
 fcfs_status fcfs_pupil_loss(fcfs_handle *h, const float *F, const float *G, const float *H,
                             int32_t K, int32_t L, double radius, double *loss, float *grad,
                             void *ws, size_t ws_bytes) {
+  Range rg("fcfs_pupil_loss");
   fcfs_status st = enter(h);
   if (st) return st;
   if (K < 0 || L < 0) return fail(h, FCFS_ERR_INVALID_ARG, "K and L must be >= 0");
@@ -1556,6 +1697,7 @@ fcfs_status fcfs_pupil_step(fcfs_handle *h, const int32_t *base_x, const int32_t
                             int32_t kmax, int32_t lmax, double radius, const float *G,
                             const float *H, fcfs_precision p, double *loss, float *g_edge,
                             float *F_out, void *ws, size_t ws_bytes) {
+  Range rg("fcfs_pupil_step");
   fcfs_status st = enter(h);
   if (st) return st;
   StepLayout q;
@@ -1615,6 +1757,7 @@ fcfs_status fcfs_pupil_step_plan(fcfs_handle *h, const int32_t *base_x, const in
                                  int32_t kmax, int32_t lmax, double radius, const float *G,
                                  const float *H, fcfs_precision p, double *loss, float *g_edge,
                                  float *F_out, void *ws, size_t ws_bytes, fcfs_step_plan **out) {
+  Range rg("fcfs_pupil_step_plan");
   if (!out) return fail(h, FCFS_ERR_INVALID_ARG, "plan pointer is NULL");
   *out = nullptr;
   // one eager step: validates the arguments, does the one-time set-up of the
@@ -1699,6 +1842,7 @@ fcfs_status fcfs_general_batch_workspace_size(const fcfs_gclip *c, int32_t n, fc
 fcfs_status fcfs_general_batch_plan(fcfs_handle *h, const fcfs_gclip *c, int32_t n,
                                     fcfs_precision p, void *ws, size_t ws_bytes,
                                     fcfs_step_plan **out) {
+  Range rg("fcfs_general_batch_plan");
   fcfs_status st = enter(h);
   if (st) return st;
   if (!out) return fail(h, FCFS_ERR_INVALID_ARG, "plan pointer is NULL");
@@ -1775,6 +1919,7 @@ fcfs_status fcfs_general_batch_plan(fcfs_handle *h, const fcfs_gclip *c, int32_t
 }
 
 fcfs_status fcfs_step_plan_launch(fcfs_handle *h, fcfs_step_plan *plan) {
+  Range rg("fcfs_step_plan_launch");
   fcfs_status st = enter(h);
   if (st) return st;
   if (!plan || !plan->exec) return fail(h, FCFS_ERR_INVALID_ARG, "plan is NULL");
@@ -1816,6 +1961,7 @@ fcfs_status fcfs_general_adjoint_workspace_size(const fcfs_gclip *c, fcfs_precis
 fcfs_status fcfs_adjoint_general(fcfs_handle *h, const fcfs_gclip *c, const float *grad_F,
                                  int32_t kmax, int32_t lmax, double radius, float *gx, float *gy,
                                  fcfs_precision p, void *ws, size_t ws_bytes) {
+  Range rg("fcfs_adjoint_general");
   fcfs_status st = enter(h);
   if (st) return st;
   FwdPlan q;
@@ -2122,6 +2268,7 @@ fcfs_status fcfs_batch_workspace_size(fcfs_handle *h, const fcfs_clip *c, int32_
 
 fcfs_status fcfs_forward_batch(fcfs_handle *h, const fcfs_clip *c, int32_t n, fcfs_precision p,
                                void *ws, size_t ws_bytes, fcfs_plan **plan) {
+  Range rg("fcfs_forward_batch");
   fcfs_status st = enter(h);
   if (st) return st;
   if (!plan) return fail(h, FCFS_ERR_INVALID_ARG, "plan is NULL");

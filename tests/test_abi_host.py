@@ -199,3 +199,40 @@ def test_null_handle_is_rejected(lib):
     c = _lib.FcfsClip()
     st = lib.fcfs_forward(None, ctypes.byref(c), 0, None, 0)
     assert st == -1
+
+
+def test_log_and_roctx_switches(lib):
+    # FCFS_LOG=1 prints one line per call to stderr; FCFS_ROCTX=1 opens the
+    # roctx library when present and brackets the call with a range (a host
+    # call is enough to exercise both without a GPU)
+    import subprocess
+    import sys
+
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import synth, paper_1010_5562_amd as P\n"
+            "c = synth.clip(1, 1024, 10, n_polygons=3)\n"
+            "P.loops_to_corners(c.xy, c.off)\n") % ROOT
+    env = dict(os.environ, FCFS_LOG="1", FCFS_ROCTX="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert "[fcfs] fcfs_loops_to_corners 3 loops" in r.stderr
+    env.pop("FCFS_LOG")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0 and "[fcfs]" not in r.stderr
+
+
+def test_auto_form_choice():
+    # FCFS_AUTO: the lattice form where its L T log2 T work is well below the
+    # contraction's 24 (K+1)(L+1) V flop, the split contraction otherwise, the
+    # direct form for small problems; sizes only (no device needed)
+    import paper_1010_5562_amd as P
+
+    assert P.plan_info(200_012, 8192, 511, 511, "auto")["form"] == "lattice"
+    assert P.plan_info(32_122, 4096, 255, 255, "auto")["form"] == "contraction"
+    assert P.plan_info(64, 2048, 64, 64, "auto")["form"] == "direct"
+    assert P.plan_info(200_012, 8192, 511, 511, "bf16")["form"] == "contraction"
+    # the workspace follows the form taken
+    assert P.workspace_size(200_012, 8192, 511, 511, "auto") != \
+        P.workspace_size(200_012, 8192, 511, 511, "bf16")

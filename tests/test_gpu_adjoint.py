@@ -368,3 +368,104 @@ def test_optimisation_step_full_size_sampled(P, oracle_lib):
          f"{abs(float(loss) - lo) / lo:.2e}")
     assert e <= GTOL["bf16"]
     assert abs(float(loss) - lo) <= 1e-4 * lo
+
+
+def test_gradient_against_central_differences_on_the_gpu(P, oracle_lib):
+    # The adjoint's edge gradient against central differences of the loss
+    # sum |H F - G|^2 behind a pupil of radius 0.35 K, both on the GPU.  An
+    # edge moved by t changes F by the transform of the strip it sweeps, and
+    # the corner form is linear in the corner list: that difference is the
+    # forward transform of four corners (the moved ones with their signs, the
+    # base ones with opposite signs), so L(t) - L(0) is formed from it and
+    # from F at the base offsets without cancellation.  Richardson's
+    # combination (4 D(1) - D(2)) / 3 of the central differences at t = +-1,
+    # +-2 removes their h^2 term; the error left, of order (h w)^4 with
+    # w <= 2 pi r / T, is measured by the same differences of the FP64
+    # oracle against its analytic gradient.  The GPU comparison allows that
+    # plus the adjoint's own bound (1e-5 FP32, 1e-4 split, of max |g|).
+    T, K = 1024, 40
+    r = 0.35 * K
+    rb = int(np.floor(r))
+    clip = synth.clip(61, T, K, n_polygons=60)
+    geom = P.Geometry(clip.xy, clip.off, T, K)
+    kk, ll = np.meshgrid(np.arange(-K, K + 1), np.arange(-K, K + 1), indexing="ij")
+    H = (kk ** 2 + ll ** 2 <= r * r).astype(np.float64)
+    rng = np.random.default_rng(61)
+    Gn = (H * (rng.normal(size=kk.shape) + 1j * rng.normal(size=kk.shape)) * 40.0).astype(np.complex64)
+    G = torch.as_tensor(Gn).cuda()
+    Gd = Gn.astype(np.complex128)
+    x0, y0, s0, he, ve = P.loops_to_corners(clip.xy, clip.off)
+    off = clip.off
+    n = int(off[-1])
+    loop = np.repeat(np.arange(off.size - 1), np.diff(off))
+    idx = np.arange(n)
+    nxt = np.where(idx + 1 == off[loop + 1], off[loop], idx + 1)
+    prv = np.where(idx == off[loop], off[loop + 1] - 1, idx - 1)
+
+    F0g, _ = P.forward_fft(x0, y0, s0, T, K, K)  # the base spectrum (FP64 lattice form)
+    torch.cuda.synchronize()
+    res0 = H * F0g.cpu().numpy().astype(np.complex128) - Gd
+
+    def strip(e, t):
+        # F(edge e moved by t) - F(base) from the four corners of the strip
+        a, b = int(e), int(nxt[e])
+        vert = clip.xy[a, 0] == clip.xy[b, 0]
+        xs = np.array([x0[a], x0[b], x0[a], x0[b]], np.int32)
+        ys = np.array([y0[a], y0[b], y0[a], y0[b]], np.int32)
+        if vert:
+            xs[:2] += int(t)
+        else:
+            ys[:2] += int(t)
+        ss = np.array([s0[a], s0[b], -s0[a], -s0[b]], np.int8)
+        F, _ = P.forward(xs, ys, ss, T, K, K, precision="fp32")
+        torch.cuda.synchronize()
+        return H * F.cpu().numpy().astype(np.complex128)
+
+    def fd_gpu(e):
+        d = []
+        for h in (1, 2):
+            dp, dm = strip(e, h), strip(e, -h)
+            dl = np.sum(2 * np.real(np.conj(res0) * (dp - dm)) + np.abs(dp) ** 2 - np.abs(dm) ** 2)
+            d.append(dl / (2 * h))
+        return (4 * d[0] - d[1]) / 3
+
+    xy0 = clip.xy.astype(np.float64)
+
+    def fd_oracle(e):
+        d = []
+        for h in (1.0, 2.0):
+            lv = []
+            for t in (h, -h):
+                o = np.zeros(n)
+                o[e] = t
+                xy = xy0.copy()
+                xy[:, 0] += o[ve]
+                xy[:, 1] += o[he]
+                F = oracle_lib.cfs_grid(xy, clip.off, T, K, K, lattice=False)[0]
+                lv.append(float(np.sum(np.abs(H * F - Gd) ** 2)))
+            d.append((lv[0] - lv[1]) / (2 * h))
+        return (4 * d[0] - d[1]) / 3
+
+    # analytic FP64 gradient of the oracle at the base offsets
+    F0 = oracle_lib.cfs_grid(xy0, clip.off, T, K, K)[0]
+    g_or = oracle_lib.edge_grad(clip.xy, clip.off, T, K, K, 2 * H * (H * F0 - Gd))
+    # edges whose neighbours are at least 3 units long (moves of +-2 keep
+    # every edge of the loop non-degenerate) and whose gradient is not tiny
+    elen = np.abs(clip.xy[nxt] - clip.xy[idx]).sum(axis=1)
+    ok = (elen[prv] >= 3) & (elen[nxt] >= 3) & (np.abs(g_or) > 1e-2 * np.max(np.abs(g_or)))
+    edges = rng.choice(np.nonzero(ok)[0], 10, replace=False)
+    gmax = float(np.max(np.abs(g_or)))
+    fd_or = np.array([fd_oracle(e) for e in edges])
+    fd_err = float(np.max(np.abs(fd_or - g_or[edges])) / gmax)
+    fd_g = np.array([fd_gpu(e) for e in edges])
+    _say(f"central differences: oracle FD vs analytic {fd_err:.2e}, GPU FD vs oracle FD "
+         f"{np.max(np.abs(fd_g - fd_or)) / gmax:.2e} (of max |g|)")
+    for prec, tol in (("fp32", 1e-5), ("bf16", 1e-4)):
+        offt = torch.zeros(geom.n_edges, dtype=torch.float32, device="cuda", requires_grad=True)
+        Fv = P.FCFSFunction.apply(offt, geom, prec, (rb, rb), r)
+        loss = P.PupilLoss.apply(Fv, G, r)
+        loss.backward()
+        g = offt.grad.cpu().numpy().astype(np.float64)[edges]
+        e = float(np.max(np.abs(g - fd_g)) / gmax)
+        _say(f"  {prec}: adjoint vs GPU central differences: {e:.2e} of max |g|")
+        assert e <= tol + 2 * fd_err + 1e-6

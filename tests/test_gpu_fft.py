@@ -90,3 +90,29 @@ def test_contraction_full_grid_against_lattice_form(P, oracle_lib):
         e = float(np.max(np.abs(F.cpu().numpy().astype(np.complex128) - Ff)) / f00)
         _say(f"{prec} contraction vs lattice form, full 1023 x 1023 grid: {e:.3e}")
         assert e <= tol
+
+
+@pytest.mark.parametrize("case", ["precision", "layout"])
+def test_auto_form_takes_the_cheaper_form(P, oracle_lib, case):
+    # precision "auto": the result is bit for bit the form the plan names
+    # (the lattice form at the precision clip's size, the split-bf16
+    # contraction at the layout clip's) and meets the split bound
+    if case == "precision":
+        clip = synth.clip(3, 8192, 511, min_vertices=200_000)
+    else:
+        clip = synth.clip(2, 4096, 255, n_polygons=2000)
+    x, y, s, _, _ = P.loops_to_corners(clip.xy, clip.off)
+    form = P.plan_info(x.size, clip.T, clip.K, clip.L, "auto")["form"]
+    Fa, aa = P.forward(x, y, s, clip.T, clip.K, clip.L, precision="auto")
+    if form == "lattice":
+        Fr, ar = P.forward_fft(x, y, s, clip.T, clip.K, clip.L)
+    else:
+        Fr, ar = P.forward(x, y, s, clip.T, clip.K, clip.L, precision="bf16")
+    torch.cuda.synchronize()
+    print(f"auto at V={x.size} T={clip.T} K={clip.K}: {form}", flush=True)
+    assert torch.equal(Fa, Fr) and int(aa.item()) == int(ar.item())
+    kk = np.array([0, 1, 3, -7, 200, -511 if clip.K >= 511 else -255])
+    ll = np.array([0, 2, -5, 9, -100, 17])
+    ref = oracle_lib.cfs_points(clip.xy, clip.off, clip.T, kk, ll)
+    e = float(np.max(np.abs(Fa.cpu().numpy()[kk + clip.K, ll + clip.L] - ref)) / abs(ref[0]))
+    assert e <= 1e-5
