@@ -226,11 +226,11 @@ template <int PREC>
 __device__ __forceinline__ void contract_gen_pipe_body(const uint2 *lds, bool one_tab,
                                                        const uint4 *__restrict__ packed, int Mx,
                                                        int My, int64_t chunk, int tiles_l, int kp,
-                                                       int lp, float *__restrict__ part) {
+                                                       int lp, float *__restrict__ part, int tile,
+                                                       int split) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 31, lh = lane >> 5;
-  const int tk = blockIdx.x / tiles_l, tl = blockIdx.x % tiles_l;
-  const int split = blockIdx.y;
+  const int tk = tile / tiles_l, tl = tile % tiles_l;
   const int k0 = tk * 128 + (wave >> 1) * 64;
   const int l0 = tl * 128 + (wave & 1) * 64;
   const uint32_t ux = (uint32_t)Mx, uy = (uint32_t)My;
@@ -291,12 +291,40 @@ __global__ __launch_bounds__(256, 1) void k_contract_gen_pipe(
     if (block_route_fp16(ra)) {
       stage_gen_tables<uint2>(lds, tabx16, taby16, Mx, My);
       contract_gen_pipe_body<kFP16>(lds, tabx16 == taby16, packed, Mx, My, chunk, tiles_l, kp,
-                                    lp, part);
+                                    lp, part, blockIdx.x, blockIdx.y);
       return;
     }
   }
   stage_gen_tables<uint2>(lds, tabx, taby, Mx, My);
-  contract_gen_pipe_body<PREC>(lds, tabx == taby, packed, Mx, My, chunk, tiles_l, kp, lp, part);
+  contract_gen_pipe_body<PREC>(lds, tabx == taby, packed, Mx, My, chunk, tiles_l, kp, lp, part,
+                               blockIdx.x, blockIdx.y);
+}
+
+// Batch of general tiles: one workgroup per (clip, tile, split) work item,
+// each staging its clip's period tables (GBatchLaunch).
+template <int PREC>
+__global__ __launch_bounds__(256, 1) void k_gbatch_contract(const GBatchClip *__restrict__ clips,
+                                                            const int4 *__restrict__ items) {
+  const int4 d = items[blockIdx.x];
+  const GBatchClip &c = clips[d.x];
+  __shared__ uint2 lds[2 * kTabN + 1];
+  if constexpr (PREC == kBF16) {
+    RouteArgs ra;
+    ra.area_part = c.area_part;
+    ra.pre_blocks = c.pre_blocks;
+    ra.V = c.V;
+    ra.gscale = c.gscale;
+    ra.gscale_alt = c.gscale_alt;
+    if (block_route_fp16(ra)) {
+      stage_gen_tables<uint2>(lds, c.tx16, c.ty16, c.Mx, c.My);
+      contract_gen_pipe_body<kFP16>(lds, c.tx16 == c.ty16, c.packed, c.Mx, c.My, c.chunk,
+                                    c.tiles_l, c.kp, c.lp, c.part, d.y, d.z);
+      return;
+    }
+  }
+  stage_gen_tables<uint2>(lds, c.tx, c.ty, c.Mx, c.My);
+  contract_gen_pipe_body<PREC>(lds, c.tx == c.ty, c.packed, c.Mx, c.My, c.chunk, c.tiles_l, c.kp,
+                               c.lp, c.part, d.y, d.z);
 }
 
 // ---------------------------------------------------------------------------
@@ -460,6 +488,19 @@ hipError_t launch_gen_t(const FwdPlan &p, const uint4 *packed, const void *tx, c
 }
 
 }  // namespace
+
+hipError_t launch_gbatch_contract(const GBatchLaunch &b, hipStream_t st) {
+  if (b.n_items == 0) return hipSuccess;
+  if (b.prec == kBF16)
+    hipLaunchKernelGGL(k_gbatch_contract<kBF16>, dim3(b.n_items), dim3(256), 0, st, b.clips,
+                       b.items);
+  else if (b.prec == kFP16)
+    hipLaunchKernelGGL(k_gbatch_contract<kFP16>, dim3(b.n_items), dim3(256), 0, st, b.clips,
+                       b.items);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
 
 hipError_t launch_gen_contract(const FwdPlan &p, const uint4 *packed, const void *tx,
                                const void *ty, float *part, hipStream_t st,

@@ -366,6 +366,53 @@ struct BatchLaunch {
   int n_epi;
 };
 
+// Batch of general tiles (split precisions, periods up to 8192 grid units) as
+// one launch per step over all clips: the pre-pass (blocks (b, clip)), the
+// side-stream blocks and axis DFT blocks (one descriptor each), the
+// contraction (one workgroup per (clip, tile, split) work item, longest
+// first; each stages its clip's period tables) and the epilogue (blocks
+// mapped to clips by a prefix).  Each clip keeps the workspace layout of its
+// single-clip plan.
+struct GBatchClip {
+  const int32_t *x, *y;
+  const int8_t *s;
+  float2 *F;
+  int64_t *area;
+  uint4 *packed;
+  unsigned long long *area_part, *hist;
+  double2 *axis_part;
+  float *part;
+  double *gpart;
+  unsigned int *gspan;
+  const uint2 *tx, *ty;        // split operand tables of the plan's precision
+  const uint2 *tx16, *ty16;    // split-fp16 tables (routing of split-bf16 plans)
+  const double2 *w64x, *w64y;  // FP64 tables (axis sums and guard region)
+  double gscale, gscale_alt;
+  double eg, eax, eay, edc;    // alpha factors of the output grid
+  int64_t V, vpad, chunk, g_chunk;
+  int Mx, My, K, L, kp, lp, tiles_l, nsplit, pre_blocks, hist_blocks, ax_fb_k, ax_chunks,
+      g_chunks;
+  uint32_t smask;
+};
+
+struct GBatchLaunch {
+  int n_clips, prec;
+  const GBatchClip *clips;  // device
+  int max_pre_blocks;
+  const int4 *side_desc;    // device: (clip, 0 = histogram | 1 = guard, block)
+  int n_side;
+  const int4 *ax_desc;      // device: (clip, frequency block, bin chunk)
+  int n_ax;
+  const int4 *items;        // device: (clip, tile, split), longest first
+  int n_items;
+  const int *epi_off;       // device: prefix of epilogue blocks per clip [n + 1]
+  int n_epi;
+};
+hipError_t launch_gbatch_prepass(const GBatchLaunch &b, hipStream_t st);
+hipError_t launch_gbatch_side(const GBatchLaunch &b, hipStream_t st);
+hipError_t launch_gbatch_contract(const GBatchLaunch &b, hipStream_t st);
+hipError_t launch_gbatch_epilogue(const GBatchLaunch &b, hipStream_t st);
+
 hipError_t launch_batch_prepass(const BatchLaunch &b, hipStream_t st);
 hipError_t launch_batch_side(const BatchLaunch &b, const double2 *w64, hipStream_t st);
 hipError_t launch_batch_contract(const BatchLaunch &b, const Tables &t, hipStream_t st);

@@ -80,14 +80,14 @@ hipError_t launch_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y, 
 // carry pad = 8 Mx, which sends the x-side lookup (an entry index or a byte
 // offset, clamped to the zero entry) to the zero entry Mx.  Bins of the axis
 // histograms are the residues themselves.
-__global__ __launch_bounds__(256) void k_gen_prepass(const int32_t *__restrict__ x,
-                                                     const int32_t *__restrict__ y,
-                                                     const int8_t *__restrict__ s, int64_t V,
-                                                     int64_t vpad, int Mx, int My, uint32_t smask,
-                                                     uint4 *__restrict__ packed,
-                                                     unsigned long long *__restrict__ area_part,
-                                                     unsigned long long *__restrict__ hist) {
-  const int blk = blockIdx.x, nblk = gridDim.x;
+__device__ __forceinline__ void gen_prepass_body(const int32_t *__restrict__ x,
+                                                 const int32_t *__restrict__ y,
+                                                 const int8_t *__restrict__ s, int64_t V,
+                                                 int64_t vpad, int Mx, int My, uint32_t smask,
+                                                 uint4 *__restrict__ packed,
+                                                 unsigned long long *__restrict__ area_part,
+                                                 unsigned long long *__restrict__ hist, int blk,
+                                                 int nblk) {
   unsigned long long acc = 0;
   for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < vpad; i += (int64_t)nblk * 256) {
     uint4 w;
@@ -113,6 +113,17 @@ __global__ __launch_bounds__(256) void k_gen_prepass(const int32_t *__restrict__
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) area_part[blk] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(256) void k_gen_prepass(const int32_t *__restrict__ x,
+                                                     const int32_t *__restrict__ y,
+                                                     const int8_t *__restrict__ s, int64_t V,
+                                                     int64_t vpad, int Mx, int My, uint32_t smask,
+                                                     uint4 *__restrict__ packed,
+                                                     unsigned long long *__restrict__ area_part,
+                                                     unsigned long long *__restrict__ hist) {
+  gen_prepass_body(x, y, s, V, vpad, Mx, My, smask, packed, area_part, hist, blockIdx.x,
+                   gridDim.x);
 }
 
 hipError_t launch_gen_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y,
@@ -1441,8 +1452,10 @@ hipError_t launch_debug_phases(const FwdPlan &p, const uint4 *packed, int axis, 
 // counter until the list is exhausted.  The counter is reset by a kernel at
 // the head of the sequence, so a captured graph can be replayed.
 // ===========================================================================
+// counter[0], counter[1]: work counters of the two passes; counter[2]: set
+// when some clip is routed to split-fp16 (the second pass exits otherwise)
 __global__ void k_batch_reset(unsigned int *counter) {
-  if (threadIdx.x < 2 && blockIdx.x == 0) counter[threadIdx.x] = 0u;
+  if (threadIdx.x < 3 && blockIdx.x == 0) counter[threadIdx.x] = 0u;
 }
 
 __global__ __launch_bounds__(256) void k_batch_prepass(const BatchClip *__restrict__ clips) {
@@ -1455,10 +1468,15 @@ __global__ __launch_bounds__(256) void k_batch_prepass(const BatchClip *__restri
 // per clip, after the pre-pass: route[c] = 1 sends clip c's work items to the
 // split-fp16 pass of the contraction.
 __global__ __launch_bounds__(256) void k_batch_route(const BatchClip *__restrict__ clips,
-                                                     int pre_blocks, unsigned int *route) {
+                                                     int pre_blocks, unsigned int *route,
+                                                     unsigned int *any) {
   const BatchClip &c = clips[blockIdx.x];
   const long long a = block_area(c.area_part, pre_blocks);
-  if (threadIdx.x == 0) route[blockIdx.x] = route_fp16(c.gscale, c.gscale_alt, c.V, a) ? 1u : 0u;
+  if (threadIdx.x == 0) {
+    const bool r = route_fp16(c.gscale, c.gscale_alt, c.V, a);
+    route[blockIdx.x] = r ? 1u : 0u;
+    if (r) *any = 1u;  // every writer stores the same value
+  }
 }
 
 // Side-stream blocks of a batch, one descriptor each: (clip, 0, b) bins
@@ -1503,7 +1521,9 @@ __global__ __launch_bounds__(256, 2) void k_batch_contract(const BatchClip *__re
                                                            int n_items, unsigned int *counter,
                                                            const uint2 *__restrict__ tab,
                                                            const unsigned int *__restrict__ route,
-                                                           unsigned int want) {
+                                                           unsigned int want,
+                                                           const unsigned int *__restrict__ any) {
+  if (any && *any == 0u) return;  // a routed-clip pass with no routed clip
   __shared__ uint2 s_tab[kTabEntries];
   __shared__ int s_item;
   for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
@@ -1525,7 +1545,9 @@ __global__ __launch_bounds__(256, 1) void k_batch_contract_pipe(const BatchClip 
                                                                 unsigned int *counter,
                                                                 const uint2 *__restrict__ tab,
                                                                 const unsigned int *__restrict__ route,
-                                                                unsigned int want) {
+                                                                unsigned int want,
+                                                                const unsigned int *__restrict__ any) {
+  if (any && *any == 0u) return;  // a routed-clip pass with no routed clip
   __shared__ uint2 s_tab[kTabEntries];
   __shared__ int s_item;
   for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
@@ -1582,12 +1604,76 @@ __global__ __launch_bounds__(256) void k_batch_epilogue(const BatchClip *__restr
                  blockIdx.x - off[ci], c.direct != 0);
 }
 
+// ===========================================================================
+// Batch of general tiles: one launch per step over all clips (GBatchLaunch).
+// ===========================================================================
+__global__ __launch_bounds__(256) void k_gbatch_prepass(const GBatchClip *__restrict__ clips) {
+  const GBatchClip &c = clips[blockIdx.y];
+  if ((int)blockIdx.x >= c.pre_blocks) return;
+  gen_prepass_body(c.x, c.y, c.s, c.V, c.vpad, c.Mx, c.My, c.smask, c.packed, c.area_part,
+                   c.hist, blockIdx.x, c.pre_blocks);
+}
+
+// (clip, 0, b): histogram block b; (clip, 1, b): guard block b (slot group
+// b / g_chunks over corner range b % g_chunks)
+__global__ __launch_bounds__(256) void k_gbatch_side(const GBatchClip *__restrict__ clips,
+                                                     const int4 *__restrict__ desc) {
+  const int4 d = desc[blockIdx.x];
+  const GBatchClip &c = clips[d.x];
+  if (d.y == 0)
+    hist_body<true>(c.x, c.y, c.packed, c.V, 0, c.hist, d.z, c.hist_blocks);
+  else
+    guard_body<true>(c.packed, c.w64x, c.V, c.g_chunk, d.z % c.g_chunks, d.z / c.g_chunks,
+                     c.area_part, c.pre_blocks, c.gscale, c.gscale_alt, c.K, c.L, c.gpart,
+                     c.gspan, c.w64y, c.Mx, c.My);
+}
+
+__global__ __launch_bounds__(256) void k_gbatch_axis(const GBatchClip *__restrict__ clips,
+                                                     const int4 *__restrict__ desc) {
+  const int4 d = desc[blockIdx.x];
+  const GBatchClip &c = clips[d.x];
+  dft_body<true>(c.hist, c.w64x, c.Mx, 0, c.K, c.L, c.ax_fb_k, c.axis_part, d.y, d.z, c.w64y,
+                 c.My);
+}
+
+__global__ __launch_bounds__(256) void k_gbatch_epilogue(const GBatchClip *__restrict__ clips,
+                                                         const int *__restrict__ off, int n) {
+  const int ci = owner(off, n, blockIdx.x);
+  const GBatchClip &c = clips[ci];
+  const OutGrid o{c.F, c.K, c.L, -1.0, c.eg, c.eax, c.eay, c.edc};
+  epilogue_block(c.part, c.nsplit, c.kp, c.lp, c.K, c.L, (double)c.Mx, c.axis_part, c.ax_chunks,
+                 c.area_part, c.pre_blocks, c.gpart, c.g_chunks, c.gspan, o, c.area,
+                 blockIdx.x - off[ci]);
+}
+
+hipError_t launch_gbatch_prepass(const GBatchLaunch &b, hipStream_t st) {
+  if (b.n_clips > 0)
+    hipLaunchKernelGGL(k_gbatch_prepass, dim3(b.max_pre_blocks, b.n_clips), dim3(256), 0, st,
+                       b.clips);
+  return hipGetLastError();
+}
+
+hipError_t launch_gbatch_side(const GBatchLaunch &b, hipStream_t st) {
+  if (b.n_side > 0)
+    hipLaunchKernelGGL(k_gbatch_side, dim3(b.n_side), dim3(256), 0, st, b.clips, b.side_desc);
+  if (b.n_ax > 0)
+    hipLaunchKernelGGL(k_gbatch_axis, dim3(b.n_ax), dim3(256), 0, st, b.clips, b.ax_desc);
+  return hipGetLastError();
+}
+
+hipError_t launch_gbatch_epilogue(const GBatchLaunch &b, hipStream_t st) {
+  if (b.n_epi > 0)
+    hipLaunchKernelGGL(k_gbatch_epilogue, dim3(b.n_epi), dim3(256), 0, st, b.clips, b.epi_off,
+                       b.n_clips);
+  return hipGetLastError();
+}
+
 hipError_t launch_batch_prepass(const BatchLaunch &b, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, b.counter);
   hipLaunchKernelGGL(k_batch_prepass, dim3(b.pre_blocks, b.n_clips), dim3(256), 0, st, b.clips);
   if (b.prec == kBF16 && b.route && b.n_clips > 0)
     hipLaunchKernelGGL(k_batch_route, dim3(b.n_clips), dim3(256), 0, st, b.clips, b.pre_blocks,
-                       b.route);
+                       b.route, b.counter + 2);
   return hipGetLastError();
 }
 
@@ -1607,8 +1693,10 @@ int batch_grid(int tile, int prec) {
 
 // One persistent pass over the work list in precision prec (want: the route
 // value of the clips it takes, or all clips when route is nullptr).
+// any: when given, the pass exits at once unless *any is set.
 static void batch_pass(const BatchLaunch &b, const Tables &t, int prec, const unsigned int *route,
-                       unsigned int want, unsigned int *counter, hipStream_t st) {
+                       unsigned int want, unsigned int *counter, hipStream_t st,
+                       const unsigned int *any = nullptr) {
   const dim3 grid(b.grid), block(256);
   const bool wide = tile_variant(b.tile).wk == 64;
   const uint2 *tab = prec == kBF16 ? t.wbf16 : t.wfp16;
@@ -1622,24 +1710,24 @@ static void batch_pass(const BatchLaunch &b, const Tables &t, int prec, const un
   } else if (b.tile == 5) {
     if (prec == kBF16)
       hipLaunchKernelGGL(k_batch_contract_pipe<kBF16>, grid, block, 0, st, b.clips, b.items,
-                         b.n_items, counter, tab, route, want);
+                         b.n_items, counter, tab, route, want, any);
     else
       hipLaunchKernelGGL(k_batch_contract_pipe<kFP16>, grid, block, 0, st, b.clips, b.items,
-                         b.n_items, counter, tab, route, want);
+                         b.n_items, counter, tab, route, want, any);
   } else if (prec == kBF16) {
     if (wide)
       hipLaunchKernelGGL((k_batch_contract<kBF16, 2, 1>), grid, block, 0, st, b.clips, b.items,
-                         b.n_items, counter, tab, route, want);
+                         b.n_items, counter, tab, route, want, any);
     else
       hipLaunchKernelGGL((k_batch_contract<kBF16, 1, 1>), grid, block, 0, st, b.clips, b.items,
-                         b.n_items, counter, tab, route, want);
+                         b.n_items, counter, tab, route, want, any);
   } else {
     if (wide)
       hipLaunchKernelGGL((k_batch_contract<kFP16, 2, 1>), grid, block, 0, st, b.clips, b.items,
-                         b.n_items, counter, tab, route, want);
+                         b.n_items, counter, tab, route, want, any);
     else
       hipLaunchKernelGGL((k_batch_contract<kFP16, 1, 1>), grid, block, 0, st, b.clips, b.items,
-                         b.n_items, counter, tab, route, want);
+                         b.n_items, counter, tab, route, want, any);
   }
 }
 
@@ -1648,7 +1736,7 @@ hipError_t launch_batch_contract(const BatchLaunch &b, const Tables &t, hipStrea
   if (b.prec == kBF16 && b.route) {
     // split-bf16: the clips the rounding model keeps in bf16, then the routed ones
     batch_pass(b, t, kBF16, b.route, 0u, b.counter, st);
-    batch_pass(b, t, kFP16, b.route, 1u, b.counter + 1, st);
+    batch_pass(b, t, kFP16, b.route, 1u, b.counter + 1, st, b.counter + 2);
   } else {
     batch_pass(b, t, b.prec, nullptr, 0u, b.counter, st);
   }
