@@ -554,19 +554,28 @@ def main() -> int:
     # on half units over a 4000 x 3000 tile (periods 8000 x 6000 grid units).
     # The third: the layout clip on a 4000 x 3000 tile with every polygon
     # shifted by its own random multiple of 1/16 (periods 64000 x 48000 grid
-    # units, past the LDS tables: two-level twiddles).
+    # units, past the LDS tables: two-level twiddles).  The fourth: the
+    # precision clip on an 8000 x 6000 tile, polygons shifted by multiples of
+    # 1/8 (periods 64000 x 48000 grid units, the two-level kernel at the
+    # headline's size).
     import types
-    Xs = c2.xy.astype(np.int64) << 4
-    for i in range(c2.off.size - 1):
-        Xs[c2.off[i]:c2.off[i + 1]] += rng.integers(0, 16, 2)
-    c16 = types.SimpleNamespace(xy=Xs.astype(np.int32), off=c2.off)
-    x16, y16, s16, _, _ = P.loops_to_corners(c16.xy, c16.off)
-    x16d, y16d, s16d = (torch.as_tensor(a).to(dev) for a in (x16, y16, s16))
+
+    def shifted(cl, fb):
+        Xs = cl.xy.astype(np.int64) << fb
+        for i in range(cl.off.size - 1):
+            Xs[cl.off[i]:cl.off[i + 1]] += rng.integers(0, 1 << fb, 2)
+        cs = types.SimpleNamespace(xy=Xs.astype(np.int32), off=cl.off)
+        xs, ys, ss, _, _ = P.loops_to_corners(cs.xy, cs.off)
+        return (cs,) + tuple(torch.as_tensor(a).to(dev) for a in (xs, ys, ss))
+
+    c16, x16d, y16d, s16d = shifted(c2, 4)
+    c8, x8d, y8d, s8d = shifted(clip, 3)
     gen = {}
     for name, gclip, gx, gy, gs, Ng, Mg, Fb, Kg in (
             ("precision_clip_8000x6000", clip, xd, yd, sd, 8000, 6000, 0, K),
             ("layout_clip_half_units_4000x3000", c2, x2d, y2d, s2d, 4000, 3000, 1, K2),
-            ("layout_clip_sixteenth_units_4000x3000", c16, x16d, y16d, s16d, 4000, 3000, 4, K2)):
+            ("layout_clip_sixteenth_units_4000x3000", c16, x16d, y16d, s16d, 4000, 3000, 4, K2),
+            ("precision_clip_eighth_units_8000x6000", c8, x8d, y8d, s8d, 8000, 6000, 3, K)):
         Vg = int(gx.numel())
         pg = Vg * (2 * Kg + 1) ** 2
         kq = np.concatenate([kk[:289] if Kg >= 8 else kk, rng.integers(-Kg, Kg + 1, 200)])

@@ -92,6 +92,11 @@ struct fcfs_step_plan {
   hipGraphExec_t exec = nullptr;
   fcfs_handle *h = nullptr;
   std::vector<std::pair<int, bool>> pinned;
+  // a general-tile batch in the one-launch-per-step form: its own side
+  // stream and events, and the device copies of its descriptors
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  std::vector<void *> dev_allocs;
 };
 
 // ---------------------------------------------------------------------------
@@ -390,13 +395,16 @@ double guard_scale(int prec, int Mx, int My) {
 // Split count, chunk and workspace layout of a forward plan whose tile grid
 // (kp, lp, tiles_k, tiles_l) is set: one wave of workgroups over the CUs, but
 // at least 512 corners per split.
-void finish_plan(FwdPlan &q, int64_t tiles, int wg_per_cu, int chunk_mult, bool lattice) {
+// ns_force > 0: that split count (a batch that sizes its work items itself).
+void finish_plan(FwdPlan &q, int64_t tiles, int wg_per_cu, int chunk_mult, bool lattice,
+                 int64_t ns_force = 0) {
   const int64_t V = q.V;
   const int K = q.K, L = q.L;
   const int Tmax = std::max(q.Mx, q.My);
   int64_t ns = ceil_div((int64_t)kCUs * wg_per_cu, tiles);
   const int64_t ns_max = std::max<int64_t>(1, ceil_div(V, 512));
   ns = std::max<int64_t>(1, std::min(ns, ns_max));
+  if (ns_force > 0) ns = ns_force;
   ns = std::min<int64_t>(ns, 65535);
   q.nsplit = (int)ns;
   const int cm = chunk_mult;
@@ -404,8 +412,11 @@ void finish_plan(FwdPlan &q, int64_t tiles, int wg_per_cu, int chunk_mult, bool 
   q.vpad = q.chunk * q.nsplit;
   q.pre_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(q.vpad, 256)));
   q.hist_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(256, ceil_div(V, 1024)));
-  q.ax_fb_k = (int)ceil_div(K, 256);
-  q.ax_fb_l = (int)ceil_div(L, 256);
+  // frequencies per axis block: 256 (DFT of the histograms), 128 (the direct
+  // sums of a two-level plan)
+  const int fpb = q.big ? 128 : 256;
+  q.ax_fb_k = (int)ceil_div(K, fpb);
+  q.ax_fb_l = (int)ceil_div(L, fpb);
   // axis partials: bin chunks of the histograms, or corner ranges of the
   // direct sums of a two-level plan
   q.ax_chunks = q.big ? (int)std::max<int64_t>(1, std::min<int64_t>(256, ceil_div(V, 512)))
@@ -431,6 +442,8 @@ void finish_plan(FwdPlan &q, int64_t tiles, int wg_per_cu, int chunk_mult, bool 
     off += align256(sizeof(double) * fcfs::kGuardD * fcfs::kGuardSlots * (size_t)q.g_chunks);
   q.off_gspan = off;
   off += 256;
+  q.off_phi = off;
+  if (q.big) off += align256(sizeof(uint4) * (size_t)q.vpad);
   q.off_fcnt = q.off_flist = q.off_fd = off;
   if (lattice) {
     const int T = q.T;
@@ -879,7 +892,8 @@ fcfs_status gen_tables(fcfs_handle *h, int Mx, int My, fcfs_handle::GenTab *tx,
 // precisions unless a tile variant is forced on the handle), else the
 // contraction kernel given as in FwdPlan::tile.
 fcfs_status make_plan_general(fcfs_handle *h, const fcfs_gclip *c, int prec, FwdPlan *p,
-                              int kmax = -1, int lmax = -1, double r2 = -1.0, int variant = -1) {
+                              int kmax = -1, int lmax = -1, double r2 = -1.0, int variant = -1,
+                              int64_t ns_force = 0) {
   if (!c) return fail(h, FCFS_ERR_INVALID_ARG, "clip is NULL");
   if (c->V < 0) return fail(h, FCFS_ERR_INVALID_ARG, "V < 0");
   if (c->V > ((int64_t)1 << 34)) return fail(h, FCFS_ERR_UNSUPPORTED, "V too large");
@@ -939,7 +953,7 @@ fcfs_status make_plan_general(fcfs_handle *h, const fcfs_gclip *c, int prec, Fwd
   // else two; pipelined kernel: one workgroup of four waves per CU
   const bool pipe = q.tile == fcfs::kGenPipeTile;
   const int wpc = q.big ? 1 : !pipe && (Mx + 1 + (Mx == My ? 0 : My)) * 8 <= 80 * 1024 ? 2 : 1;
-  finish_plan(q, tiles, wpc, pipe ? 32 : 16, false);
+  finish_plan(q, tiles, wpc, pipe ? 32 : 16, false, ns_force);
   *p = q;
   return FCFS_OK;
 }
@@ -984,7 +998,8 @@ fcfs_status run_forward_general(fcfs_handle *h, const fcfs_gclip *c, const FwdPl
     if ((e = fcfs::launch_gen_contract(p, ws_at<uint4>(ws, p.off_packed), ox, oy,
                                        ws_at<float>(ws, p.off_part), h->stream,
                                        ws_at<unsigned long long>(ws, p.off_area),
-                                       p.big ? nullptr : tx->wfp16, p.big ? nullptr : ty->wfp16)))
+                                       p.big ? nullptr : tx->wfp16, p.big ? nullptr : ty->wfp16,
+                                       p.big ? ws_at<uint4>(ws, p.off_phi) : nullptr)))
       return hip_fail(h, e, "contraction launch");
   }
   if (side) {
@@ -1738,6 +1753,10 @@ static void step_plan_free(fcfs_step_plan *p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap) (void)hipStreamDestroy(p->cap);
+  if (p->side) (void)hipStreamDestroy(p->side);
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+  for (void *a : p->dev_allocs) (void)hipFree(a);
   if (p->h) {  // still attached: release its pins and its entry in the handle
     for (const auto &pk : p->pinned)
       for (auto &t : p->h->gen_tabs)
@@ -1810,33 +1829,231 @@ fcfs_status fcfs_pupil_step_plan(fcfs_handle *h, const int32_t *base_x, const in
 }
 
 // ---------------------------------------------------------------------------
-// Batch of general-tile forwards: one workspace slice per clip, every clip's
-// launches captured once into one graph.
+// Batch of general-tile forwards: one workspace slice per clip and one graph.
+// Split-precision batches whose clips all fit the batch kernels run one launch
+// per step over every clip (GBatchLaunch): the split counts are chosen for the
+// whole batch (about two work items per compute unit, at least
+// kGBatchItemMin corners each) and the items are dispatched longest first.
+// Other batches capture every clip's single-clip launches in sequence.
 // ---------------------------------------------------------------------------
+}  // extern "C"
+
 namespace {
-fcfs_status general_batch_offsets(fcfs_handle *h, const fcfs_gclip *c, int32_t n, int prec,
-                                  std::vector<size_t> *off, size_t *total) {
+constexpr int64_t kGBatchItemMin = 256;
+constexpr int64_t kGBatchItems = 2 * kCUs;
+
+struct GBatchLayout {
+  bool flat = false;
+  std::vector<FwdPlan> fp;  // flat: the clips' plans with the batch split counts
+  std::vector<size_t> off;  // workspace slices [n + 1]
+};
+
+fcfs_status gbatch_layout(fcfs_handle *h, const fcfs_gclip *c, int32_t n, int prec,
+                          GBatchLayout *L) {
   if (!c || n < 1) return fail(h, FCFS_ERR_INVALID_ARG, "empty batch");
+  L->fp.assign((size_t)n, FwdPlan{});
+  L->off.assign((size_t)n + 1, 0);
+  L->flat = prec != fcfs::kFP32;
+  int64_t work = 0;  // corner-tiles of the contraction
+  for (int32_t i = 0; i < n; ++i) {
+    FwdPlan q;
+    fcfs_status st = make_plan_general(h, &c[i], prec, &q, -1, -1, -1.0, fcfs::kGenPipeTile);
+    if (st) return st;
+    if (q.big && fcfs::big_shared_lds_bytes(q.nhx, q.nhy, q.Mx == q.My) > fcfs::kGBatchLds)
+      L->flat = false;
+    if (q.K > 0 && q.L > 0) work += (int64_t)q.tiles_k * q.tiles_l * std::max<int64_t>(q.V, 1);
+  }
+  const int64_t w = std::max(kGBatchItemMin, ceil_div(work, kGBatchItems));
   size_t o = 0;
-  off->assign((size_t)n + 1, 0);
   for (int32_t i = 0; i < n; ++i) {
     size_t b = 0;
-    fcfs_status st = general_ws_bytes(&c[i], prec, -1, -1, -1.0, &b);
+    fcfs_status st;
+    if (L->flat) {
+      const int64_t ns = std::max<int64_t>(1, (c[i].V + w / 2) / w);
+      st = make_plan_general(h, &c[i], prec, &L->fp[i], -1, -1, -1.0, fcfs::kGenPipeTile, ns);
+      b = L->fp[i].bytes;
+    } else {
+      st = general_ws_bytes(&c[i], prec, -1, -1, -1.0, &b);
+    }
     if (st) return st;
-    (*off)[i] = o;
+    L->off[i] = o;
     o += align256(b);
   }
-  (*off)[n] = o;
-  *total = o;
+  L->off[n] = o;
+  return FCFS_OK;
+}
+
+template <class T>
+fcfs_status step_upload(fcfs_handle *h, fcfs_step_plan *q, const std::vector<T> &v, const T **out) {
+  void *d = nullptr;
+  const size_t nb = std::max<size_t>(sizeof(T), sizeof(T) * v.size());
+  hipError_t e = hipMalloc(&d, nb);
+  if (e) return hip_fail(h, e, "hipMalloc (plan)");
+  q->dev_allocs.push_back(d);
+  if (!v.empty() && (e = hipMemcpy(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice)))
+    return hip_fail(h, e, "hipMemcpy (plan)");
+  *out = (const T *)d;
+  return FCFS_OK;
+}
+
+// Pins the cache entry of period N (two-level or not) for the plan.
+void pin_table(fcfs_handle *h, fcfs_step_plan *q, int N, bool big) {
+  const std::pair<int, bool> key(N, big);
+  if (std::find(q->pinned.begin(), q->pinned.end(), key) != q->pinned.end()) return;
+  for (auto &g : h->gen_tabs)
+    if (g.N == N && (g.nh > 0) == big) {
+      ++g.pins;
+      q->pinned.push_back(key);
+      return;
+    }
+}
+
+// The one-launch-per-step form: descriptors, capture, and one launch that
+// leaves the outputs.
+fcfs_status gbatch_flat_plan(fcfs_handle *h, const fcfs_gclip *c, int32_t n, int prec,
+                             const GBatchLayout &L, void *ws, fcfs_step_plan *q) {
+  std::vector<fcfs::GBatchClip> gc((size_t)n);
+  std::vector<int4> side, ax;
+  std::vector<std::pair<double, int4>> items;
+  std::vector<int> epi((size_t)n + 1, 0);
+  int max_pre = 1;
+  for (int32_t i = 0; i < n; ++i) {
+    const FwdPlan &p = L.fp[i];
+    if (c[i].V > 0 && (!c[i].x || !c[i].y || !c[i].s))
+      return fail(h, FCFS_ERR_INVALID_ARG, "NULL corners");
+    if (!c[i].F) return fail(h, FCFS_ERR_INVALID_ARG, "NULL output");
+    fcfs_handle::GenTab gx, gy;
+    fcfs_status st = gen_tables(h, p.Mx, p.My, &gx, &gy, p.big != 0);
+    if (st) return st;
+    pin_table(h, q, p.Mx, p.big != 0);
+    pin_table(h, q, p.My, p.big != 0);
+    char *w = (char *)ws + L.off[i];
+    fcfs::GBatchClip &g = gc[i];
+    g.x = c[i].x;
+    g.y = c[i].y;
+    g.s = c[i].s;
+    g.F = (float2 *)c[i].F;
+    g.area = c[i].area;
+    g.packed = (uint4 *)(w + p.off_packed);
+    g.words = p.big ? (uint4 *)(w + p.off_phi) : nullptr;
+    g.area_part = (unsigned long long *)(w + p.off_area);
+    g.hist = (unsigned long long *)(w + p.off_hist);
+    g.axis_part = (double2 *)(w + p.off_axis);
+    g.part = (float *)(w + p.off_part);
+    g.gpart = (double *)(w + p.off_guard);
+    g.gspan = (unsigned int *)(w + p.off_gspan);
+    if (p.big) {
+      g.tx = gx.w32;
+      g.ty = gy.w32;
+      g.tx16 = g.ty16 = nullptr;
+    } else {
+      g.tx = prec == fcfs::kBF16 ? gx.wbf16 : gx.wfp16;
+      g.ty = prec == fcfs::kBF16 ? gy.wbf16 : gy.wfp16;
+      g.tx16 = gx.wfp16;
+      g.ty16 = gy.wfp16;
+    }
+    g.w64x = gx.w64;
+    g.w64y = gy.w64;
+    g.gscale = p.gscale;
+    g.gscale_alt = p.gscale_alt;
+    g.eg = p.eg;
+    g.eax = p.eax;
+    g.eay = p.eay;
+    g.edc = p.edc;
+    g.V = p.V;
+    g.vpad = p.vpad;
+    g.chunk = p.chunk;
+    g.g_chunk = p.g_chunk;
+    g.ax_chunk = std::max<int64_t>(1, ceil_div(p.V, p.ax_chunks));
+    g.Mx = p.Mx;
+    g.My = p.My;
+    g.K = p.K;
+    g.L = p.L;
+    g.kp = p.kp;
+    g.lp = p.lp;
+    g.tiles_l = p.tiles_l;
+    g.nsplit = p.nsplit;
+    g.pre_blocks = p.pre_blocks;
+    g.hist_blocks = p.hist_blocks;
+    g.ax_fb_k = p.ax_fb_k;
+    g.ax_chunks = p.ax_chunks;
+    g.g_chunks = p.g_chunks;
+    g.big = p.big;
+    g.nhx = p.nhx;
+    g.nhy = p.nhy;
+    g.smask = 0x80008000u;
+    max_pre = std::max(max_pre, p.pre_blocks);
+    const bool grid2d = p.K > 0 && p.L > 0;
+    if (!p.big && p.K + p.L > 0)
+      for (int b = 0; b < p.hist_blocks; ++b) side.push_back(make_int4(i, 0, b, 0));
+    if (grid2d)
+      for (int b = 0; b < fcfs::kGuardGroups * p.g_chunks; ++b)
+        side.push_back(make_int4(i, p.big ? 2 : 1, b, 0));
+    if (p.K + p.L > 0)
+      for (int fb = 0; fb < p.ax_fb_k + p.ax_fb_l; ++fb)
+        for (int ch = 0; ch < p.ax_chunks; ++ch) ax.push_back(make_int4(i, p.big ? 1 : 0, fb, ch));
+    // a two-level corner step costs about 1.3 one-level ones
+    if (grid2d)
+      for (int t = 0; t < p.tiles_k * p.tiles_l; ++t)
+        for (int sp = 0; sp < p.nsplit; ++sp)
+          items.push_back({(double)p.chunk * (p.big ? 1.3 : 1.0), make_int4(i, t, sp, 0)});
+    epi[i + 1] = epi[i] + fcfs::epilogue_block_count(p.K, p.L);
+  }
+  std::stable_sort(items.begin(), items.end(),
+                   [](const std::pair<double, int4> &a, const std::pair<double, int4> &b) {
+                     return a.first > b.first;
+                   });
+  std::vector<int4> it;
+  for (auto &x : items) it.push_back(x.second);
+  fcfs::GBatchLaunch bl{};
+  bl.n_clips = n;
+  bl.prec = prec;
+  bl.max_pre_blocks = max_pre;
+  bl.n_side = (int)side.size();
+  bl.n_ax = (int)ax.size();
+  bl.n_items = (int)it.size();
+  bl.n_epi = epi[n];
+  fcfs_status st;
+  if ((st = step_upload(h, q, gc, &bl.clips)) || (st = step_upload(h, q, side, &bl.side_desc)) ||
+      (st = step_upload(h, q, ax, &bl.ax_desc)) || (st = step_upload(h, q, it, &bl.items)) ||
+      (st = step_upload(h, q, epi, &bl.epi_off)))
+    return st;
+  hipError_t e;
+  if ((e = hipStreamCreateWithFlags(&q->cap, hipStreamNonBlocking)) ||
+      (e = hipStreamCreateWithFlags(&q->side, hipStreamNonBlocking)) ||
+      (e = hipEventCreateWithFlags(&q->ev_fork, hipEventDisableTiming)) ||
+      (e = hipEventCreateWithFlags(&q->ev_join, hipEventDisableTiming)))
+    return hip_fail(h, e, "plan streams");
+  if ((e = hipStreamBeginCapture(q->cap, hipStreamCaptureModeThreadLocal)))
+    return hip_fail(h, e, "hipStreamBeginCapture");
+  hipError_t le = fcfs::launch_gbatch_prepass(bl, q->cap);
+  if (!le) le = hipEventRecord(q->ev_fork, q->cap);
+  if (!le) le = fcfs::launch_gbatch_contract(bl, q->cap);
+  if (!le) le = hipStreamWaitEvent(q->side, q->ev_fork, 0);
+  if (!le) le = fcfs::launch_gbatch_side(bl, q->side);
+  if (!le) le = hipEventRecord(q->ev_join, q->side);
+  if (!le) le = hipStreamWaitEvent(q->cap, q->ev_join, 0);
+  if (!le) le = fcfs::launch_gbatch_epilogue(bl, q->cap);
+  e = hipStreamEndCapture(q->cap, &q->graph);
+  if (le) return hip_fail(h, le, "general batch capture");
+  if (e) return hip_fail(h, e, "hipStreamEndCapture");
+  if ((e = hipGraphInstantiate(&q->exec, q->graph, nullptr, nullptr, 0)))
+    return hip_fail(h, e, "hipGraphInstantiate");
+  if ((e = hipGraphLaunch(q->exec, h->stream))) return hip_fail(h, e, "hipGraphLaunch");
   return FCFS_OK;
 }
 }  // namespace
 
+extern "C" {
+
 fcfs_status fcfs_general_batch_workspace_size(const fcfs_gclip *c, int32_t n, fcfs_precision p,
                                               size_t *bytes) {
   if (!bytes) return fail(nullptr, FCFS_ERR_INVALID_ARG, "NULL argument");
-  std::vector<size_t> off;
-  return general_batch_offsets(nullptr, c, n, (int)p, &off, bytes);
+  GBatchLayout L;
+  fcfs_status st = gbatch_layout(nullptr, c, n, (int)p, &L);
+  if (st) return st;
+  *bytes = L.off[n];
+  return FCFS_OK;
 }
 
 fcfs_status fcfs_general_batch_plan(fcfs_handle *h, const fcfs_gclip *c, int32_t n,
@@ -1847,38 +2064,39 @@ fcfs_status fcfs_general_batch_plan(fcfs_handle *h, const fcfs_gclip *c, int32_t
   if (st) return st;
   if (!out) return fail(h, FCFS_ERR_INVALID_ARG, "plan pointer is NULL");
   *out = nullptr;
-  std::vector<size_t> off;
-  size_t total = 0;
-  if ((st = general_batch_offsets(h, c, n, (int)p, &off, &total))) return st;
+  GBatchLayout L;
+  if ((st = gbatch_layout(h, c, n, (int)p, &L))) return st;
+  const size_t total = L.off[n];
   if (ws_bytes < total)
     return fail(h, FCFS_ERR_WORKSPACE, "workspace too small: need " + std::to_string(total) +
                                            " bytes, got " + std::to_string(ws_bytes));
   if (!ws || ((uintptr_t)ws & 255u)) return fail(h, FCFS_ERR_WORKSPACE, "workspace NULL or misaligned");
-  auto slice = [&](int32_t i) { return (void *)((char *)ws + off[i]); };
-  // one eager pass: validates every clip, builds the period tables (pinned
-  // at once, so that later clips of the batch cannot evict them: the cache
-  // grows past its size instead) and leaves the outputs
   auto *q = new fcfs_step_plan;
   q->device = h->device;
   q->h = h;
   h->step_plans.push_back(q);
+  if (L.flat) {
+    if ((st = gbatch_flat_plan(h, c, n, (int)p, L, ws, q))) {
+      step_plan_free(q);
+      return st;
+    }
+    logf(1, "general batch: %d clips, one launch per step", (int)n);
+    *out = q;
+    return FCFS_OK;
+  }
+  auto slice = [&](int32_t i) { return (void *)((char *)ws + L.off[i]); };
+  // one eager pass: validates every clip, builds the period tables (pinned
+  // at once, so that later clips of the batch cannot evict them: the cache
+  // grows past its size instead) and leaves the outputs
   for (int32_t i = 0; i < n; ++i) {
     FwdPlan fp;
-    if ((st = fcfs_forward_general(h, &c[i], p, slice(i), off[i + 1] - off[i])) ||
+    if ((st = fcfs_forward_general(h, &c[i], p, slice(i), L.off[i + 1] - L.off[i])) ||
         (st = make_plan_general(h, &c[i], (int)p, &fp))) {
       step_plan_free(q);
       return st;
     }
-    for (int N : {fp.Mx, fp.My}) {
-      const std::pair<int, bool> key(N, fp.big != 0);
-      if (std::find(q->pinned.begin(), q->pinned.end(), key) != q->pinned.end()) continue;
-      for (auto &g : h->gen_tabs)
-        if (g.N == N && (g.nh > 0) == key.second) {
-          ++g.pins;
-          q->pinned.push_back(key);
-          break;
-        }
-    }
+    pin_table(h, q, fp.Mx, fp.big != 0);
+    pin_table(h, q, fp.My, fp.big != 0);
   }
   hipError_t e = hipStreamCreateWithFlags(&q->cap, hipStreamNonBlocking);
   if (e) {
@@ -1897,7 +2115,7 @@ fcfs_status fcfs_general_batch_plan(fcfs_handle *h, const fcfs_gclip *c, int32_t
   }
   h->own_capture = true;
   for (int32_t i = 0; i < n && !st; ++i)
-    st = fcfs_forward_general(h, &c[i], p, slice(i), off[i + 1] - off[i]);
+    st = fcfs_forward_general(h, &c[i], p, slice(i), L.off[i + 1] - L.off[i]);
   e = hipStreamEndCapture(q->cap, &q->graph);
   h->own_capture = false;
   h->stream = saved;

@@ -9,6 +9,8 @@ namespace fcfs {
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
@@ -212,6 +214,53 @@ __device__ __forceinline__ void mma(f32x16 (&acc)[NKB][NLB][4], const Frag<NKB, 
       acc[kb][lb][2] = mfma16<PREC>(f.asl[kb], f.bch[lb], acc[kb][lb][2]);
       acc[kb][lb][3] = mfma16<PREC>(f.asl[kb], f.bsh[lb], acc[kb][lb][3]);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Copy of n 8-byte table entries from device memory into LDS by the whole
+// block (blockDim.x threads): 16-byte loads, eight in flight per thread, then
+// the stores (src 16-byte aligned; dst 8-byte aligned).  Tables are staged
+// once per workgroup, so the loads' latency, not their bandwidth, is the cost.
+// ---------------------------------------------------------------------------
+template <typename E>
+__device__ __forceinline__ void stage_entries(E *dst, const E *__restrict__ src, int n) {
+  static_assert(sizeof(E) == 8, "8-byte entries");
+  const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
+  uint2 *d = reinterpret_cast<uint2 *>(dst);
+  const int nt = blockDim.x, n2 = n >> 1;
+  int i = threadIdx.x;
+  for (; i + 7 * nt < n2; i += 8 * nt) {
+    uint4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = s4[i + u * nt];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      d[2 * (i + u * nt)] = make_uint2(v[u].x, v[u].y);
+      d[2 * (i + u * nt) + 1] = make_uint2(v[u].z, v[u].w);
+    }
+  }
+  for (; i < n2; i += nt) {
+    const uint4 v = s4[i];
+    d[2 * i] = make_uint2(v.x, v.y);
+    d[2 * i + 1] = make_uint2(v.z, v.w);
+  }
+  if ((n & 1) && threadIdx.x == 0) dst[n - 1] = src[n - 1];
+}
+
+// ---------------------------------------------------------------------------
+// Exact phase reduction of one-level general periods (M <= 8192): (f x) mod M
+// for x < M and a lane-constant frequency f is
+//     f' x - floor(x m / 2^32) M,   f' = f mod M,  m = ceil(f' 2^32 / M),
+// exact because x M < 2^32 (the error term x (m - f' 2^32 / M) / 2^32 is below
+// x / 2^32 < 1 / M).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t gen_magic(uint32_t fr, uint32_t M) {
+  return (uint32_t)((((uint64_t)fr << 32) + M - 1u) / M);
+}
+
+// (f x) mod M with fr = f mod M and m = gen_magic(fr, M), for x < M <= 8192.
+__device__ __forceinline__ uint32_t gen_phase(uint32_t fr, uint32_t m, uint32_t x, uint32_t M) {
+  return __umul24(fr, x) - __umul24(__umulhi(x, m), M);
 }
 
 // ---------------------------------------------------------------------------

@@ -28,15 +28,6 @@ namespace {
 constexpr int kGenWaves = 8;
 constexpr int kGenNKB = 2, kGenNLB = 1;
 
-__device__ __forceinline__ uint32_t gen_magic(uint32_t fr, uint32_t M) {
-  return (uint32_t)((((uint64_t)fr << 32) + M - 1u) / M);
-}
-
-// (f x) mod M with fr = f mod M and m = gen_magic(fr, M), for x < M <= 8192.
-__device__ __forceinline__ uint32_t gen_phase(uint32_t fr, uint32_t m, uint32_t x, uint32_t M) {
-  return __umul24(fr, x) - __umul24(__umulhi(x, m), M);
-}
-
 template <int NKB, int NLB>
 struct GenLane {
   uint32_t kr[NKB], km[NKB], lr[NLB], lm[NLB];
@@ -89,9 +80,8 @@ template <typename E>
 __device__ __forceinline__ E *stage_gen_tables(E *tx, const void *__restrict__ tabx,
                                                const void *__restrict__ taby, int Mx, int My) {
   E *ty = tabx == taby ? tx : tx + (Mx + 1);
-  for (int i = threadIdx.x; i <= Mx; i += blockDim.x) tx[i] = static_cast<const E *>(tabx)[i];
-  if (tabx != taby)
-    for (int i = threadIdx.x; i < My; i += blockDim.x) ty[i] = static_cast<const E *>(taby)[i];
+  stage_entries(tx, static_cast<const E *>(tabx), Mx + 1);
+  if (tabx != taby) stage_entries(ty, static_cast<const E *>(taby), My);
   __syncthreads();
   return ty;
 }
@@ -300,43 +290,18 @@ __global__ __launch_bounds__(256, 1) void k_contract_gen_pipe(
                                blockIdx.x, blockIdx.y);
 }
 
-// Batch of general tiles: one workgroup per (clip, tile, split) work item,
-// each staging its clip's period tables (GBatchLaunch).
-template <int PREC>
-__global__ __launch_bounds__(256, 1) void k_gbatch_contract(const GBatchClip *__restrict__ clips,
-                                                            const int4 *__restrict__ items) {
-  const int4 d = items[blockIdx.x];
-  const GBatchClip &c = clips[d.x];
-  __shared__ uint2 lds[2 * kTabN + 1];
-  if constexpr (PREC == kBF16) {
-    RouteArgs ra;
-    ra.area_part = c.area_part;
-    ra.pre_blocks = c.pre_blocks;
-    ra.V = c.V;
-    ra.gscale = c.gscale;
-    ra.gscale_alt = c.gscale_alt;
-    if (block_route_fp16(ra)) {
-      stage_gen_tables<uint2>(lds, c.tx16, c.ty16, c.Mx, c.My);
-      contract_gen_pipe_body<kFP16>(lds, c.tx16 == c.ty16, c.packed, c.Mx, c.My, c.chunk,
-                                    c.tiles_l, c.kp, c.lp, c.part, d.y, d.z);
-      return;
-    }
-  }
-  stage_gen_tables<uint2>(lds, c.tx, c.ty, c.Mx, c.My);
-  contract_gen_pipe_body<PREC>(lds, c.tx == c.ty, c.packed, c.Mx, c.My, c.chunk, c.tiles_l, c.kp,
-                               c.lp, c.part, d.y, d.z);
-}
-
 // ---------------------------------------------------------------------------
 // Periods past 8192 grid units (two-level twiddles).  The eight-wave layout
 // of k_contract_gen; per entry the phase (f x) mod M is reduced exactly in
-// FP64 and the twiddle is the FP32 complex product of the two table entries
-// (both tables of both periods in LDS, at most 4 x 4096 entries).  The split
-// precisions round that product to hi + lo in the kernel (the FP32 product is
-// accurate to a few 2^-24, far below the split's own rounding).
+// 32-bit integers from the corner's magic (big_phase_int) and the twiddle is
+// the FP32 complex product of the two table entries (both tables of both
+// periods in LDS, at most 4 x 4096 entries).  The split precisions round that
+// product to hi + lo in the kernel (the FP32 product is accurate to a few
+// 2^-24, far below the split's own rounding).  This form serves FP32, and the
+// split precisions where the shared-operand kernel below does not fit in LDS.
 // ---------------------------------------------------------------------------
-template <int PREC>
-__device__ __forceinline__ void contract_big_body(const uint4 *__restrict__ packed,
+template <int PREC, bool NARROW>
+__device__ __forceinline__ void contract_big_body(const uint4 *__restrict__ phi,
                                                   const float2 *tx, const float2 *ty, int Mx,
                                                   int My, int nhx, int nhy, int64_t chunk,
                                                   int tiles_l, int kp, int lp,
@@ -347,7 +312,7 @@ __device__ __forceinline__ void contract_big_body(const uint4 *__restrict__ pack
   const int split = blockIdx.y;
   const int k0 = tk * 128 + (wave >> 2) * 64;
   const int l0 = tl * 128 + (wave & 3) * 32;
-  const double dMx = (double)Mx, dMy = (double)My, iMx = 1.0 / dMx, iMy = 1.0 / dMy;
+  const uint32_t Mxm1 = (uint32_t)Mx - 1u, Mym1 = (uint32_t)My - 1u;
   uint32_t kf[kGenNKB], lf[kGenNLB];
 #pragma unroll
   for (int kb = 0; kb < kGenNKB; ++kb) kf[kb] = (uint32_t)(k0 + 32 * kb + li);
@@ -364,23 +329,24 @@ __device__ __forceinline__ void contract_big_body(const uint4 *__restrict__ pack
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[kb][lb][q][r] = 0.0f;
 
-  const uint4 *vp = packed + (size_t)split * chunk + 8 * lh;
+  const uint4 *pp = phi + (size_t)split * chunk + 8 * lh;
   for (int64_t vb = 0; vb < chunk; vb += 16) {
-    uint4 c[8];
-    load_corners(c, vp + vb);
+    uint4 m[8];
+    load_corners(m, pp + vb);
     float2 a[kGenNKB][8], b[kGenNLB][8];
 #pragma unroll
     for (int kb = 0; kb < kGenNKB; ++kb)
 #pragma unroll
       for (int j = 0; j < 8; ++j)
-        a[kb][j] = c[j].w ? make_float2(0.0f, 0.0f)
-                          : big_entry(tx, nhx, big_phase(kf[kb], c[j].x, dMx, iMx));
+        a[kb][j] = m[j].z >> 31 ? make_float2(0.0f, 0.0f)
+                                : big_entry(tx, nhx,
+                                            big_word_phase<NARROW, true>(kf[kb], m[j], Mxm1, -Mx));
 #pragma unroll
     for (int lb = 0; lb < kGenNLB; ++lb)
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const float2 w = big_entry(ty, nhy, big_phase(lf[lb], c[j].y, dMy, iMy));
-        b[lb][j] = c[j].z ? make_float2(-w.x, -w.y) : w;
+        const float2 w = big_entry(ty, nhy, big_word_phase<NARROW, false>(lf[lb], m[j], Mym1, -My));
+        b[lb][j] = (m[j].z >> 30) & 1u ? make_float2(-w.x, -w.y) : w;
       }
     if constexpr (PREC == kFP32) {
 #pragma unroll
@@ -416,30 +382,411 @@ __device__ __forceinline__ void contract_big_body(const uint4 *__restrict__ pack
 // routed to split-fp16 (block_route_fp16) uses the same tables.
 template <int PREC>
 __global__ __launch_bounds__(64 * kGenWaves) void k_contract_big(
-    const uint4 *__restrict__ packed, const float2 *__restrict__ tabx,
-    const float2 *__restrict__ taby, int Mx, int My, int nhx, int nhy, int64_t chunk,
-    int tiles_l, int kp, int lp, float *__restrict__ part, double r2, RouteArgs ra) {
+    const uint4 *__restrict__ phi, const float2 *__restrict__ tabx, const float2 *__restrict__ taby, int Mx, int My, int nhx,
+    int nhy, int64_t chunk, int tiles_l, int kp, int lp, float *__restrict__ part, double r2,
+    RouteArgs ra) {
   if (tile_outside(blockIdx.x, tiles_l, 128, 128, r2)) return;
   extern __shared__ float2 lds_big[];
   const int nx = nhx + kBigLo, ny = nhy + kBigLo;
   float2 *tx = lds_big;
   float2 *ty = tabx == taby ? tx : tx + nx;
-  for (int i = threadIdx.x; i < nx; i += 64 * kGenWaves) tx[i] = tabx[i];
-  if (tabx != taby)
-    for (int i = threadIdx.x; i < ny; i += 64 * kGenWaves) ty[i] = taby[i];
+  stage_entries(tx, tabx, nx);
+  if (tabx != taby) stage_entries(ty, taby, ny);
   __syncthreads();
   if constexpr (PREC == kBF16) {
     if (block_route_fp16(ra)) {
-      contract_big_body<kFP16>(packed, tx, ty, Mx, My, nhx, nhy, chunk, tiles_l, kp, lp, part);
+      if (big_narrow(Mx, My))
+        contract_big_body<kFP16, true>(phi, tx, ty, Mx, My, nhx, nhy, chunk, tiles_l, kp, lp,
+                                       part);
+      else
+        contract_big_body<kFP16, false>(phi, tx, ty, Mx, My, nhx, nhy, chunk, tiles_l, kp, lp,
+                                        part);
       return;
     }
   }
-  contract_big_body<PREC>(packed, tx, ty, Mx, My, nhx, nhy, chunk, tiles_l, kp, lp, part);
+  if (big_narrow(Mx, My))
+    contract_big_body<PREC, true>(phi, tx, ty, Mx, My, nhx, nhy, chunk, tiles_l, kp, lp, part);
+  else
+    contract_big_body<PREC, false>(phi, tx, ty, Mx, My, nhx, nhy, chunk, tiles_l, kp, lp, part);
+}
+
+// ---------------------------------------------------------------------------
+// Shared-operand form for periods past 8192 (split precisions).  Four waves of
+// 64 x 64 frequencies (128 x 128 per workgroup, the layout of the pipelined
+// kernel), but each operand entry of a 16-corner step is built once per
+// workgroup instead of once per wave that uses it: wave w takes the 8 corners
+// of half h = w / 2 and the frequencies 64 (w mod 2) + lane of both sides,
+// reduces the phases exactly (big_phase_int), multiplies the two FP32 table
+// entries, rounds the products to hi + lo two corners at a time and stores
+// the lane's four operand registers (cos-hi, sin-hi, cos-lo, sin-lo of its 8
+// corners) with 16-byte LDS writes; every wave then reads the fragments of
+// its 64 x 64 block.  The corner words (big_word) are wave-uniform: scalar
+// loads.  The build of step s+1 runs as eight units of two entries, each unit
+// finishing the entries whose table lookups the previous unit issued and
+// interleaved with six of the 48 MFMAs of step s.
+// LDS (bytes, from 0): x table (nhx + kBigLo FP32 pairs), y table (unless the
+// periods coincide), rounded to 16; the operand buffers of the two sides, each
+// [kind 4][half 2][frequency 128] x 16 bytes.
+// ---------------------------------------------------------------------------
+// Rounded pair {v0, v1} (low half v0) and the two values it rounds to.
+template <int PREC>
+__device__ __forceinline__ uint32_t bs_round2(float v0, float v1, float &r0, float &r1) {
+  if constexpr (PREC == kBF16) {
+    const bf16x2 h = {(__bf16)v0, (__bf16)v1};
+    const uint32_t u = __builtin_bit_cast(uint32_t, h);
+    r0 = __uint_as_float(u << 16);
+    r1 = __uint_as_float(u & 0xffff0000u);
+    return u;
+  } else {
+    const f16x2 h = {(_Float16)v0, (_Float16)v1};
+    r0 = (float)h[0];
+    r1 = (float)h[1];
+    return __builtin_bit_cast(uint32_t, h);
+  }
 }
 
 template <int PREC>
-hipError_t launch_big_t(const FwdPlan &p, const uint4 *packed, const void *tx, const void *ty,
-                        float *part, const RouteArgs &ra, hipStream_t st) {
+__device__ __forceinline__ uint32_t bs_round2(float v0, float v1) {
+  if constexpr (PREC == kBF16) {
+    const bf16x2 h = {(__bf16)v0, (__bf16)v1};
+    return __builtin_bit_cast(uint32_t, h);
+  } else {
+    const f16x2 h = {(_Float16)v0, (_Float16)v1};
+    return __builtin_bit_cast(uint32_t, h);
+  }
+}
+
+// (a << b) + c as one instruction (the compiler splits it otherwise).
+__device__ __forceinline__ uint32_t lshl_add(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t d;
+  asm("v_lshl_add_u32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+
+// LDS byte address of a pointer into LDS, and the FP32 pair at an address.
+typedef __attribute__((address_space(3))) const char lds_char;
+__device__ __forceinline__ uint32_t lds_addr(const void *p) {
+  return (uint32_t)(uintptr_t)(lds_char *)p;
+}
+__device__ __forceinline__ float2 lds_f2(uint32_t a) {
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  const f32x2 v = *(__attribute__((address_space(3))) const f32x2 *)(uintptr_t)a;
+  return make_float2(v.x, v.y);
+}
+
+struct BsSide {
+  uint32_t tab, lo_off, f, Mm1;  // table and Wlo LDS addresses, lane frequency, M - 1
+  int negM;                      // -M
+  // log2 of the entry size (3), a run-time value: the lookups then compile to
+  // one shift-add (v_lshl_add_u32) per address instead of shift, mask and add
+  uint32_t sh;
+};
+
+// The two table entries (Whi, Wlo) of the entries of two corners.
+struct BsPair {
+  float2 a[2], b[2];
+};
+
+template <bool NARROW, bool YSIDE>
+__device__ __forceinline__ void bs_lookup(BsPair &P, const BsSide &sd,
+                                          const uint4 &c0, const uint4 &c1) {
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const uint32_t p = big_word_phase<NARROW, !YSIDE>(sd.f, e ? c1 : c0, sd.Mm1, sd.negM);
+    P.a[e] = lds_f2(lshl_add(p >> kBigBits, sd.sh, sd.tab));
+    P.b[e] = lds_f2(lshl_add(p & (uint32_t)(kBigLo - 1), sd.sh, sd.lo_off));
+  }
+}
+
+// Entries of the pair (y side: times the corner's sign, zero for padding),
+// rounded into word i of the four operand registers.
+template <int PREC, bool YSIDE>
+__device__ __forceinline__ void bs_finish(const BsPair &P, const uint4 &c0, const uint4 &c1,
+                                          u32x4 &ch, u32x4 &sh, u32x4 &cl, u32x4 &sl, int i) {
+  float2 w[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    w[e] = cmulf(P.a[e], P.b[e]);
+    if (YSIDE) {
+      // 0, -1 or +1 from the (uniform) flags
+      const uint32_t fl = (e ? c1 : c0).z;
+      const uint32_t sb = (fl >> 31) ? 0u : ((fl >> 30) & 1u ? 0xbf800000u : 0x3f800000u);
+      const float sgn = __uint_as_float(sb);
+      w[e].x *= sgn;
+      w[e].y *= sgn;
+    }
+  }
+  float c0r, c1r, s0r, s1r;
+  ch[i] = bs_round2<PREC>(w[0].x, w[1].x, c0r, c1r);
+  sh[i] = bs_round2<PREC>(w[0].y, w[1].y, s0r, s1r);
+  cl[i] = bs_round2<PREC>(w[0].x - c0r, w[1].x - c1r);
+  sl[i] = bs_round2<PREC>(w[0].y - s0r, w[1].y - s1r);
+}
+
+__device__ __forceinline__ void bs_store(uint4 *op, int h, int fl, const u32x4 &ch,
+                                         const u32x4 &sh, const u32x4 &cl, const u32x4 &sl) {
+  op[(0 * 2 + h) * 128 + fl] = __builtin_bit_cast(uint4, ch);
+  op[(1 * 2 + h) * 128 + fl] = __builtin_bit_cast(uint4, sh);
+  op[(2 * 2 + h) * 128 + fl] = __builtin_bit_cast(uint4, cl);
+  op[(3 * 2 + h) * 128 + fl] = __builtin_bit_cast(uint4, sl);
+}
+
+// MFMA m of a step, in the order term (hi hi', hi lo', lo hi') major, then
+// (kb, lb, quadrant): successive MFMAs on one accumulator are 16 apart.
+template <int PREC, int M>
+__device__ __forceinline__ void bs_mfma(f32x16 (&acc)[2][2][4], const Frag<2, 2> &f) {
+  constexpr int term = M / 16, kb = (M >> 3) & 1, lb = (M >> 2) & 1, q = M & 3;
+  const u32x4 &a = term == 2 ? (q >> 1 ? f.asl[kb] : f.acl[kb]) : (q >> 1 ? f.ash[kb] : f.ach[kb]);
+  const u32x4 &b = term == 1 ? (q & 1 ? f.bsl[lb] : f.bcl[lb]) : (q & 1 ? f.bsh[lb] : f.bch[lb]);
+  acc[kb][lb][q] = mfma16<PREC>(a, b, acc[kb][lb][q]);
+}
+
+// Unit U of the build of a step (entries of pair U: x side for U < 4, then y
+// side) and, with MM, MFMAs 6U .. 6U+5 of the previous step.
+template <int PREC, bool NARROW, int U, bool MM>
+__device__ __forceinline__ void bs_unit(f32x16 (&acc)[2][2][4], const Frag<2, 2> &f,
+                                        BsPair (&P)[2], const uint4 (&cw)[8], const char *lds,
+                                        const BsSide &sx, const BsSide &sy, u32x4 (&o)[4],
+                                        uint4 *opA, uint4 *opB, int h, int fl) {
+  constexpr int N = U + 1;
+  if constexpr (N < 8) {
+    if constexpr (N < 4)
+      bs_lookup<NARROW, false>(P[N & 1], sx, cw[2 * (N & 3)], cw[2 * (N & 3) + 1]);
+    else
+      bs_lookup<NARROW, true>(P[N & 1], sy, cw[2 * (N & 3)], cw[2 * (N & 3) + 1]);
+  }
+  bs_finish<PREC, (U >= 4)>(P[U & 1], cw[2 * (U & 3)], cw[2 * (U & 3) + 1], o[0], o[1], o[2],
+                            o[3], U & 3);
+  if constexpr (U == 3) bs_store(opA, h, fl, o[0], o[1], o[2], o[3]);
+  if constexpr (U == 7) bs_store(opB, h, fl, o[0], o[1], o[2], o[3]);
+  if constexpr (MM) {
+    bs_mfma<PREC, 6 * U + 0>(acc, f);
+    bs_mfma<PREC, 6 * U + 1>(acc, f);
+    bs_mfma<PREC, 6 * U + 2>(acc, f);
+    bs_mfma<PREC, 6 * U + 3>(acc, f);
+    bs_mfma<PREC, 6 * U + 4>(acc, f);
+    bs_mfma<PREC, 6 * U + 5>(acc, f);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+      __builtin_amdgcn_sched_group_barrier(0x002, 7, 0);  // VALU
+      if (k < 4) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // LDS read
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// Build of one step (cw: the 8 corner words of the wave's half), with the
+// MFMAs of the previous step when MM.
+template <int PREC, bool NARROW, bool MM>
+__device__ __forceinline__ void bs_step(f32x16 (&acc)[2][2][4], const Frag<2, 2> &f,
+                                        const uint4 (&cw)[8], const char *lds, const BsSide &sx,
+                                        const BsSide &sy, uint4 *opA, uint4 *opB, int h, int fl) {
+  BsPair P[2];
+  u32x4 o[4];
+  bs_lookup<NARROW, false>(P[0], sx, cw[0], cw[1]);
+  bs_unit<PREC, NARROW, 0, MM>(acc, f, P, cw, lds, sx, sy, o, opA, opB, h, fl);
+  bs_unit<PREC, NARROW, 1, MM>(acc, f, P, cw, lds, sx, sy, o, opA, opB, h, fl);
+  bs_unit<PREC, NARROW, 2, MM>(acc, f, P, cw, lds, sx, sy, o, opA, opB, h, fl);
+  bs_unit<PREC, NARROW, 3, MM>(acc, f, P, cw, lds, sx, sy, o, opA, opB, h, fl);
+  bs_unit<PREC, NARROW, 4, MM>(acc, f, P, cw, lds, sx, sy, o, opA, opB, h, fl);
+  bs_unit<PREC, NARROW, 5, MM>(acc, f, P, cw, lds, sx, sy, o, opA, opB, h, fl);
+  bs_unit<PREC, NARROW, 6, MM>(acc, f, P, cw, lds, sx, sy, o, opA, opB, h, fl);
+  bs_unit<PREC, NARROW, 7, MM>(acc, f, P, cw, lds, sx, sy, o, opA, opB, h, fl);
+}
+
+template <int PREC, bool NARROW>
+__device__ __forceinline__ void contract_big_shared_body(
+    char *lds, uint32_t ybase, uint32_t opa, const uint4 *__restrict__ words, int Mx, int My,
+    int nhx, int nhy, int64_t chunk, int tiles_l, int kp, int lp, float *__restrict__ part,
+    int tile, int split, uint32_t sh) {
+  const int t = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
+  const int li = lane & 31, lh = lane >> 5;
+  const int tk = tile / tiles_l, tl = tile % tiles_l;
+  uint4 *opA = (uint4 *)(lds + opa);
+  uint4 *opB = (uint4 *)(lds + opa + 16u * kBsOpWords);
+  // builder role: half h, local frequency fl of both sides
+  const int h = wave >> 1, fl = 64 * (wave & 1) + lane;
+  const uint32_t l0 = lds_addr(lds);
+  const BsSide sx{l0, l0 + 8u * (uint32_t)nhx, (uint32_t)(tk * 128 + fl), (uint32_t)Mx - 1u, -Mx,
+                  sh};
+  const BsSide sy{l0 + ybase, l0 + ybase + 8u * (uint32_t)nhy, (uint32_t)(tl * 128 + fl),
+                  (uint32_t)My - 1u, -My, sh};
+  // MFMA role: block (wk, wl) of 64 x 64
+  const int wk = wave >> 1, wl = wave & 1;
+
+  f32x16 acc[2][2][4];
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+    for (int lb = 0; lb < 2; ++lb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[kb][lb][q][r] = 0.0f;
+
+  const int nsteps = (int)(chunk >> 4);
+  const uint4 *cp = words + (size_t)split * chunk + 8 * h;
+  Frag<2, 2> f;
+  uint4 cw[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) cw[j] = cp[j];
+  __syncthreads();  // the tables
+  bs_step<PREC, NARROW, false>(acc, f, cw, lds, sx, sy, opA, opB, h, fl);
+  __syncthreads();
+  for (int s = 0; s < nsteps; ++s) {
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+      const int i = lh * 128 + 64 * wk + 32 * kb + li;
+      f.ach[kb] = __builtin_bit_cast(u32x4, opA[0 * 256 + i]);
+      f.ash[kb] = __builtin_bit_cast(u32x4, opA[1 * 256 + i]);
+      f.acl[kb] = __builtin_bit_cast(u32x4, opA[2 * 256 + i]);
+      f.asl[kb] = __builtin_bit_cast(u32x4, opA[3 * 256 + i]);
+    }
+#pragma unroll
+    for (int lb = 0; lb < 2; ++lb) {
+      const int i = lh * 128 + 64 * wl + 32 * lb + li;
+      f.bch[lb] = __builtin_bit_cast(u32x4, opB[0 * 256 + i]);
+      f.bsh[lb] = __builtin_bit_cast(u32x4, opB[1 * 256 + i]);
+      f.bcl[lb] = __builtin_bit_cast(u32x4, opB[2 * 256 + i]);
+      f.bsl[lb] = __builtin_bit_cast(u32x4, opB[3 * 256 + i]);
+    }
+    // the last step builds its own corners again, into buffers nobody reads
+    const int sn = min(s + 1, nsteps - 1);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) cw[j] = cp[16 * sn + j];
+    __syncthreads();  // every wave holds its fragments: the buffers are free
+    bs_step<PREC, NARROW, true>(acc, f, cw, lds, sx, sy, opA, opB, h, fl);
+    __syncthreads();
+  }
+  store_part<2, 2>(part, acc, split, kp, lp, tk * 128 + 64 * wk, tl * 128 + 64 * wl, li, lh);
+}
+
+
+template <int PREC>
+__global__ __launch_bounds__(256, 1) void k_contract_big_shared(
+    const uint4 *__restrict__ words, const float2 *__restrict__ tabx, const float2 *__restrict__ taby, int Mx, int My, int nhx,
+    int nhy, int64_t chunk, int tiles_l, int kp, int lp, float *__restrict__ part, double r2,
+    RouteArgs ra, uint32_t sh /* 3 */) {
+  if (tile_outside(blockIdx.x, tiles_l, 128, 128, r2)) return;
+  extern __shared__ __align__(16) char lds_bs[];
+  const bool one = tabx == taby;
+  const int nx = nhx + kBigLo, ny = nhy + kBigLo;
+  float2 *tx = (float2 *)lds_bs;
+  float2 *ty = one ? tx : tx + nx;
+  stage_entries(tx, tabx, nx);
+  if (!one) stage_entries(ty, taby, ny);
+  const uint32_t ybase = one ? 0u : 8u * (uint32_t)nx;
+  const uint32_t opa = big_shared_tab_bytes(nhx, nhy, one);
+  const bool narrow = big_narrow(Mx, My);
+  if constexpr (PREC == kBF16) {
+    if (block_route_fp16(ra)) {
+      if (narrow)
+        contract_big_shared_body<kFP16, true>(lds_bs, ybase, opa, words, Mx, My, nhx, nhy,
+                                              chunk, tiles_l, kp, lp, part, blockIdx.x,
+                                              blockIdx.y, sh);
+      else
+        contract_big_shared_body<kFP16, false>(lds_bs, ybase, opa, words, Mx, My, nhx, nhy,
+                                               chunk, tiles_l, kp, lp, part, blockIdx.x,
+                                               blockIdx.y, sh);
+      return;
+    }
+  }
+  if (narrow)
+    contract_big_shared_body<PREC, true>(lds_bs, ybase, opa, words, Mx, My, nhx, nhy, chunk,
+                                         tiles_l, kp, lp, part, blockIdx.x, blockIdx.y, sh);
+  else
+    contract_big_shared_body<PREC, false>(lds_bs, ybase, opa, words, Mx, My, nhx, nhy, chunk,
+                                          tiles_l, kp, lp, part, blockIdx.x, blockIdx.y, sh);
+}
+
+// Batch of general tiles: one workgroup per (clip, tile, split) work item.
+// A one-level clip stages its split tables and runs the pipelined form; a
+// two-level clip stages its FP32 tables and runs the shared-operand form.
+// The LDS holds either (kGBatchLds); a split-bf16 clip the rounding model
+// routes (block_route_fp16) runs split-fp16.
+template <int PREC>
+__global__ __launch_bounds__(256, 1) void k_gbatch_contract(const GBatchClip *__restrict__ clips,
+                                                            const int4 *__restrict__ items) {
+  const int4 d = items[blockIdx.x];
+  const GBatchClip &c = clips[d.x];
+  __shared__ __align__(16) uint2 lds[kGBatchLds / 8];
+  bool fp16 = false;
+  if constexpr (PREC == kBF16) {
+    RouteArgs ra;
+    ra.area_part = c.area_part;
+    ra.pre_blocks = c.pre_blocks;
+    ra.V = c.V;
+    ra.gscale = c.gscale;
+    ra.gscale_alt = c.gscale_alt;
+    fp16 = block_route_fp16(ra);
+  }
+  if (c.big) {
+    const bool one = c.tx == c.ty;
+    const int nx = c.nhx + kBigLo, ny = c.nhy + kBigLo;
+    float2 *tx = (float2 *)lds;
+    float2 *ty = one ? tx : tx + nx;
+    stage_entries(tx, (const float2 *)c.tx, nx);
+    if (!one) stage_entries(ty, (const float2 *)c.ty, ny);
+    const uint32_t ybase = one ? 0u : 8u * (uint32_t)nx;
+    const uint32_t opa = big_shared_tab_bytes(c.nhx, c.nhy, one);
+    char *l = (char *)lds;
+    // the body's first barrier completes the tables
+    if (big_narrow(c.Mx, c.My)) {
+      if (fp16)
+        contract_big_shared_body<kFP16, true>(l, ybase, opa, c.words, c.Mx, c.My, c.nhx, c.nhy,
+                                              c.chunk, c.tiles_l, c.kp, c.lp, c.part, d.y, d.z,
+                                              3u);
+      else
+        contract_big_shared_body<PREC, true>(l, ybase, opa, c.words, c.Mx, c.My, c.nhx, c.nhy,
+                                             c.chunk, c.tiles_l, c.kp, c.lp, c.part, d.y, d.z, 3u);
+    } else {
+      if (fp16)
+        contract_big_shared_body<kFP16, false>(l, ybase, opa, c.words, c.Mx, c.My, c.nhx, c.nhy,
+                                               c.chunk, c.tiles_l, c.kp, c.lp, c.part, d.y, d.z,
+                                               3u);
+      else
+        contract_big_shared_body<PREC, false>(l, ybase, opa, c.words, c.Mx, c.My, c.nhx, c.nhy,
+                                              c.chunk, c.tiles_l, c.kp, c.lp, c.part, d.y, d.z,
+                                              3u);
+    }
+    return;
+  }
+  if (fp16) {
+    stage_gen_tables<uint2>(lds, c.tx16, c.ty16, c.Mx, c.My);
+    contract_gen_pipe_body<kFP16>(lds, c.tx16 == c.ty16, c.packed, c.Mx, c.My, c.chunk,
+                                  c.tiles_l, c.kp, c.lp, c.part, d.y, d.z);
+  } else {
+    stage_gen_tables<uint2>(lds, c.tx, c.ty, c.Mx, c.My);
+    contract_gen_pipe_body<PREC>(lds, c.tx == c.ty, c.packed, c.Mx, c.My, c.chunk, c.tiles_l,
+                                 c.kp, c.lp, c.part, d.y, d.z);
+  }
+}
+
+constexpr size_t kMaxLds = 160 * 1024;
+
+template <int PREC>
+hipError_t launch_big_t(const FwdPlan &p, const uint4 *packed, const uint4 *phi, const void *tx,
+                        const void *ty, float *part, const RouteArgs &ra, hipStream_t st) {
+  if constexpr (PREC != kFP32) {
+    const size_t lds = big_shared_lds_bytes(p.nhx, p.nhy, tx == ty);
+    if (lds <= kMaxLds - 1024 && p.chunk % 16 == 0) {
+      // the kernel's static LDS (the routing reduction) comes on top
+      static size_t attr = 0;
+      if (lds > attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_contract_big_shared<PREC>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e) return e;
+        attr = lds;
+      }
+      hipLaunchKernelGGL(k_contract_big_shared<PREC>, dim3(p.tiles_k * p.tiles_l, p.nsplit),
+                         dim3(256), lds, st, phi, (const float2 *)tx, (const float2 *)ty,
+                         p.Mx, p.My, p.nhx, p.nhy, p.chunk, p.tiles_l, p.kp, p.lp, part, p.r2, ra,
+                         3u);
+      return hipGetLastError();
+    }
+  }
   const size_t lds = sizeof(float2) * ((size_t)p.nhx + kBigLo +
                                        (tx == ty ? 0 : (size_t)p.nhy + kBigLo));
   static bool attr_set = false;
@@ -451,7 +798,7 @@ hipError_t launch_big_t(const FwdPlan &p, const uint4 *packed, const void *tx, c
     attr_set = true;
   }
   hipLaunchKernelGGL(k_contract_big<PREC>, dim3(p.tiles_k * p.tiles_l, p.nsplit),
-                     dim3(64 * kGenWaves), lds, st, packed, (const float2 *)tx,
+                     dim3(64 * kGenWaves), lds, st, phi, (const float2 *)tx,
                      (const float2 *)ty, p.Mx, p.My, p.nhx, p.nhy, p.chunk, p.tiles_l, p.kp, p.lp,
                      part, p.r2, ra);
   return hipGetLastError();
@@ -505,14 +852,15 @@ hipError_t launch_gbatch_contract(const GBatchLaunch &b, hipStream_t st) {
 hipError_t launch_gen_contract(const FwdPlan &p, const uint4 *packed, const void *tx,
                                const void *ty, float *part, hipStream_t st,
                                const unsigned long long *area_part, const void *tx16,
-                               const void *ty16) {
+                               const void *ty16, const uint4 *phi) {
   RouteArgs ra = route_args(p, area_part);
   if (!p.big && (!tx16 || !ty16)) ra.gscale_alt = 0.0;
   if (p.big) {
+    if (!phi) return hipErrorInvalidValue;
     switch (p.prec) {
-      case kFP32: return launch_big_t<kFP32>(p, packed, tx, ty, part, ra, st);
-      case kBF16: return launch_big_t<kBF16>(p, packed, tx, ty, part, ra, st);
-      default: return launch_big_t<kFP16>(p, packed, tx, ty, part, ra, st);
+      case kFP32: return launch_big_t<kFP32>(p, packed, phi, tx, ty, part, ra, st);
+      case kBF16: return launch_big_t<kBF16>(p, packed, phi, tx, ty, part, ra, st);
+      default: return launch_big_t<kFP16>(p, packed, phi, tx, ty, part, ra, st);
     }
   }
   if (p.tile == kGenPipeTile) {

@@ -157,6 +157,70 @@ __device__ __forceinline__ uint32_t big_phase(uint32_t f, uint32_t x, double M, 
   return (uint32_t)r;
 }
 
+// The same phase in 32-bit integer arithmetic, from a per-corner magic
+// ph = floor(x 2^38 / M) + 1 (38 bits, big_magic): ph exceeds x 2^38 / M by
+// d in (0, 1], so f ph / 2^38 exceeds f x / M by f d / 2^38 < 2^-25 <= 1 / (2 M)
+// < 1 / M, and as the
+// fractional part of f x / M is at most 1 - 1/M, the floor of f ph / 2^38 is
+// the exact quotient q; the remainder f x - q M < 2^24 is exact modulo 2^32.
+// With ph = hi 2^32 + lo: floor(f ph / 2^38) = (f hi + floor(f lo / 2^32)) >> 6.
+__host__ __device__ inline uint64_t big_magic(uint32_t x, uint32_t M) {
+  return ((uint64_t)x << 38) / M + 1u;
+}
+
+// x may carry other bits above bit 23 (the 24-bit products ignore them).
+__device__ __forceinline__ uint32_t big_phase_int(uint32_t f, uint32_t x, uint32_t ph_lo,
+                                                  uint32_t ph_hi, uint32_t Mm1) {
+  const uint32_t q = (__umul24(f, ph_hi) + __umulhi(f, ph_lo)) >> 6;
+  // q M = q (M - 1) + q keeps both 24-bit product operands below 2^24
+  return __umul24(f, x) - (__umul24(q, Mm1) + q);
+}
+
+// Periods up to 2^20 (narrow): a 32-bit magic mu = floor(x 2^32 / M) + 1
+// suffices, as f mu / 2^32 exceeds f x / M by f d / 2^32 with d in (0, 1] and
+// f M < 2^12 2^20 = 2^32 keeps that below 1 / M; then q = floor(f mu / 2^32)
+// and r = f x - q M, the product q M taken as the signed 24-bit product of q
+// and -M (M <= 2^20 < 2^23).  Frequencies f < 2^12.
+constexpr int64_t kBigNarrowMax = (int64_t)1 << 20;
+__host__ __device__ inline uint32_t big_magic32(uint32_t x, uint32_t M) {
+  return (uint32_t)(((uint64_t)x << 32) / M) + 1u;
+}
+
+__device__ __forceinline__ uint32_t big_phase_narrow(uint32_t f, uint32_t x, uint32_t mu,
+                                                     int negM) {
+  const uint32_t q = __umulhi(f, mu);
+  return __umul24(f, x) + (uint32_t)__mul24((int)q, negM);
+}
+
+// Corner word of a plan with a period past 8192 (written by the pre-pass):
+// {x | ph_x.hi << 24, ph_x.lo, y | ph_y.hi << 24 | sign << 30 | pad << 31,
+// ph_y.lo}, x, y the residues, ph the 38-bit magics (hi below 2^6), sign set
+// for s = -1 and pad for the padding records (x = y = 0).  When both periods
+// are narrow (big_narrow) the magics are the 32-bit mu and the hi fields 0.
+__host__ __device__ inline bool big_narrow(int64_t Mx, int64_t My) {
+  return Mx <= kBigNarrowMax && My <= kBigNarrowMax;
+}
+
+__host__ __device__ inline uint4 big_word(uint32_t x, uint32_t y, uint32_t Mx, uint32_t My,
+                                          bool neg, bool pad) {
+  const uint32_t fl = (neg ? 1u << 30 : 0u) | (pad ? 1u << 31 : 0u);
+  if (big_narrow(Mx, My)) return make_uint4(x, big_magic32(x, Mx), y | fl, big_magic32(y, My));
+  const uint64_t px = big_magic(x, Mx), py = big_magic(y, My);
+  return make_uint4(x | (uint32_t)(px >> 32) << 24, (uint32_t)px,
+                    y | (uint32_t)(py >> 32) << 24 | fl, (uint32_t)py);
+}
+
+// (f x) mod M of the x side (XS) or y side of a corner word.
+template <bool NARROW, bool XS>
+__device__ __forceinline__ uint32_t big_word_phase(uint32_t f, const uint4 &w, uint32_t Mm1,
+                                                   int negM) {
+  const uint32_t xw = XS ? w.x : w.z, lo = XS ? w.y : w.w;
+  if constexpr (NARROW)
+    return big_phase_narrow(f, xw, lo, negM);
+  else
+    return big_phase_int(f, xw, lo, (xw >> 24) & 63u, Mm1);
+}
+
 // Device-resident constant tables owned by a handle.
 struct Tables {
   double2 *w64 = nullptr;    // [kTabN]       (cos, sin)(2 pi p / N), FP64
@@ -185,7 +249,7 @@ struct FwdPlan {
   int64_t vpad;      // nsplit * chunk
   int pre_blocks;    // pre-pass blocks (area partials)
   int hist_blocks;   // histogram blocks of the side kernel
-  int ax_fb_k;       // 256-frequency blocks of the x-axis DFT
+  int ax_fb_k;       // 256-frequency blocks of the x-axis DFT (two-level: 128)
   int ax_fb_l;       // and of the y-axis DFT
   int ax_chunks;     // bin chunks of the axis DFTs (partials per frequency)
   int g_chunks;      // corner chunks (blocks) of the FP64 guard region
@@ -195,8 +259,9 @@ struct FwdPlan {
   int big;           // general tile with a period past 8192: two-level tables
   int nhx, nhy;      // two-level tables: entries of Whi per period (big_hi)
   // workspace offsets (bytes): off_guard holds the guard partials
-  // [chunk][slot][16 x 16], off_gspan the span the side kernel chose
-  size_t off_packed, off_area, off_hist, off_axis, off_part, off_guard, off_gspan, bytes;
+  // [chunk][slot][16 x 16], off_gspan the span the side kernel chose,
+  // off_phi the corner words (big_word) of a two-level plan (vpad x 16 bytes)
+  size_t off_packed, off_area, off_hist, off_axis, off_part, off_guard, off_gspan, off_phi, bytes;
   // lattice (FFT) form only: bin counters, corner list, row transforms
   size_t off_fcnt, off_flist, off_fd;
 };
@@ -252,7 +317,8 @@ constexpr int kGenPipeTile = 1;
 hipError_t launch_gen_contract(const FwdPlan &p, const uint4 *packed, const void *tx,
                                const void *ty, float *part, hipStream_t st,
                                const unsigned long long *area_part = nullptr,
-                               const void *tx16 = nullptr, const void *ty16 = nullptr);
+                               const void *tx16 = nullptr, const void *ty16 = nullptr,
+                               const uint4 *phi = nullptr);
 struct RouteArgs;
 // routing inputs of a forward plan (fcfs_kernels.hip)
 RouteArgs route_args(const FwdPlan &p, const unsigned long long *area_part);
@@ -366,32 +432,34 @@ struct BatchLaunch {
   int n_epi;
 };
 
-// Batch of general tiles (split precisions, periods up to 8192 grid units) as
-// one launch per step over all clips: the pre-pass (blocks (b, clip)), the
-// side-stream blocks and axis DFT blocks (one descriptor each), the
-// contraction (one workgroup per (clip, tile, split) work item, longest
-// first; each stages its clip's period tables) and the epilogue (blocks
-// mapped to clips by a prefix).  Each clip keeps the workspace layout of its
-// single-clip plan.
+// Batch of general tiles (split precisions) as one launch per step over all
+// clips: the pre-pass (blocks (b, clip)), the side-stream blocks and axis
+// blocks (one descriptor each), the contraction (one workgroup per (clip,
+// tile, split) work item, longest first; each stages its clip's period tables
+// and runs the pipelined form, or for periods past 8192 the shared-operand
+// two-level form) and the epilogue (blocks mapped to clips by a prefix).  Each
+// clip keeps the workspace layout of a single-clip plan, with the split count
+// chosen for the whole batch.
 struct GBatchClip {
   const int32_t *x, *y;
   const int8_t *s;
   float2 *F;
   int64_t *area;
   uint4 *packed;
+  uint4 *words;                // two-level clips: corner words (big_word), else nullptr
   unsigned long long *area_part, *hist;
   double2 *axis_part;
   float *part;
   double *gpart;
   unsigned int *gspan;
-  const uint2 *tx, *ty;        // split operand tables of the plan's precision
-  const uint2 *tx16, *ty16;    // split-fp16 tables (routing of split-bf16 plans)
-  const double2 *w64x, *w64y;  // FP64 tables (axis sums and guard region)
+  const void *tx, *ty;         // split operand tables (uint2), two-level: FP32 pairs (float2)
+  const void *tx16, *ty16;     // split-fp16 tables of a one-level split-bf16 clip (routing)
+  const double2 *w64x, *w64y;  // FP64 tables, one- or two-level (axis sums and guard region)
   double gscale, gscale_alt;
   double eg, eax, eay, edc;    // alpha factors of the output grid
-  int64_t V, vpad, chunk, g_chunk;
+  int64_t V, vpad, chunk, g_chunk, ax_chunk;
   int Mx, My, K, L, kp, lp, tiles_l, nsplit, pre_blocks, hist_blocks, ax_fb_k, ax_chunks,
-      g_chunks;
+      g_chunks, big, nhx, nhy;
   uint32_t smask;
 };
 
@@ -399,15 +467,32 @@ struct GBatchLaunch {
   int n_clips, prec;
   const GBatchClip *clips;  // device
   int max_pre_blocks;
-  const int4 *side_desc;    // device: (clip, 0 = histogram | 1 = guard, block)
+  // device: (clip, 0 = histogram | 1 = guard | 2 = two-level guard, block)
+  const int4 *side_desc;
   int n_side;
-  const int4 *ax_desc;      // device: (clip, frequency block, bin chunk)
+  // device: (clip, 0 = DFT of the histograms | 1 = two-level direct sums,
+  // frequency block, chunk); after the side blocks
+  const int4 *ax_desc;
   int n_ax;
   const int4 *items;        // device: (clip, tile, split), longest first
   int n_items;
   const int *epi_off;       // device: prefix of epilogue blocks per clip [n + 1]
   int n_epi;
 };
+
+// LDS of the shared-operand two-level contraction (tables rounded to 16
+// bytes, then the two operand buffers of kBsOpWords 16-byte words each), and
+// the static LDS of the batch contraction kernel, which holds either form.
+constexpr int kBsOpWords = 4 * 2 * 128;
+__host__ __device__ inline uint32_t big_shared_tab_bytes(int nhx, int nhy, bool one_tab) {
+  const uint32_t e = (uint32_t)(nhx + kBigLo + (one_tab ? 0 : nhy + kBigLo));
+  return (8u * e + 15u) & ~15u;
+}
+__host__ __device__ inline size_t big_shared_lds_bytes(int nhx, int nhy, bool one_tab) {
+  return big_shared_tab_bytes(nhx, nhy, one_tab) + 16 * (size_t)(2 * kBsOpWords);
+}
+constexpr size_t kGBatchLds = 159 * 1024;
+
 hipError_t launch_gbatch_prepass(const GBatchLaunch &b, hipStream_t st);
 hipError_t launch_gbatch_side(const GBatchLaunch &b, hipStream_t st);
 hipError_t launch_gbatch_contract(const GBatchLaunch &b, hipStream_t st);

@@ -80,6 +80,8 @@ hipError_t launch_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y, 
 // carry pad = 8 Mx, which sends the x-side lookup (an entry index or a byte
 // offset, clamped to the zero entry) to the zero entry Mx.  Bins of the axis
 // histograms are the residues themselves.
+// Plans with a period past 8192 also write the corner words big_word (phi;
+// nullptr otherwise).
 __device__ __forceinline__ void gen_prepass_body(const int32_t *__restrict__ x,
                                                  const int32_t *__restrict__ y,
                                                  const int8_t *__restrict__ s, int64_t V,
@@ -87,7 +89,7 @@ __device__ __forceinline__ void gen_prepass_body(const int32_t *__restrict__ x,
                                                  uint4 *__restrict__ packed,
                                                  unsigned long long *__restrict__ area_part,
                                                  unsigned long long *__restrict__ hist, int blk,
-                                                 int nblk) {
+                                                 int nblk, uint4 *__restrict__ phi = nullptr) {
   unsigned long long acc = 0;
   for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < vpad; i += (int64_t)nblk * 256) {
     uint4 w;
@@ -104,6 +106,7 @@ __device__ __forceinline__ void gen_prepass_body(const int32_t *__restrict__ x,
       w = make_uint4(0u, 0u, 0u, 8u * (uint32_t)Mx);
     }
     packed[i] = w;
+    if (phi) phi[i] = big_word(w.x, w.y, (uint32_t)Mx, (uint32_t)My, w.z != 0u, w.w != 0u);
   }
   if (hist)
     for (int i = blk * 256 + threadIdx.x; i < Mx + My; i += nblk * 256)
@@ -121,20 +124,23 @@ __global__ __launch_bounds__(256) void k_gen_prepass(const int32_t *__restrict__
                                                      int64_t vpad, int Mx, int My, uint32_t smask,
                                                      uint4 *__restrict__ packed,
                                                      unsigned long long *__restrict__ area_part,
-                                                     unsigned long long *__restrict__ hist) {
+                                                     unsigned long long *__restrict__ hist,
+                                                     uint4 *__restrict__ phi) {
   gen_prepass_body(x, y, s, V, vpad, Mx, My, smask, packed, area_part, hist, blockIdx.x,
-                   gridDim.x);
+                   gridDim.x, phi);
 }
 
 hipError_t launch_gen_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y,
                               const int8_t *s, uint32_t smask, void *ws, hipStream_t st) {
   char *w = (char *)ws;
   // the histograms (Mx + My bins, at most 2 x 8192) are not used by plans
-  // with periods past 8192, which sum the axes over the corners
+  // with periods past 8192, which sum the axes over the corners and take the
+  // phase magics instead
   hipLaunchKernelGGL(k_gen_prepass, dim3(p.pre_blocks), dim3(256), 0, st, x, y, s, p.V, p.vpad,
                      p.Mx, p.My, smask, (uint4 *)(w + p.off_packed),
                      (unsigned long long *)(w + p.off_area),
-                     p.big ? nullptr : (unsigned long long *)(w + p.off_hist));
+                     p.big ? nullptr : (unsigned long long *)(w + p.off_hist),
+                     p.big ? (uint4 *)(w + p.off_phi) : nullptr);
   return hipGetLastError();
 }
 
@@ -143,7 +149,7 @@ hipError_t launch_gen_prepass_records(const int32_t *x, const int32_t *y, const 
                                       uint4 *packed, unsigned long long *area_part,
                                       hipStream_t st) {
   hipLaunchKernelGGL(k_gen_prepass, dim3(pre_blocks), dim3(256), 0, st, x, y, s, V, vpad, Mx, My,
-                     0x80008000u, packed, area_part, nullptr);
+                     0x80008000u, packed, area_part, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -258,17 +264,6 @@ __device__ __forceinline__ double2 rot(double2 v, double2 r) {
   return make_double2(v.x * r.x - v.y * r.y, v.y * r.x + v.x * r.y);
 }
 
-// Phase and table entry of a general tile: one-level (residue tables) or
-// two-level for periods past 8192 (BIG).
-template <bool BIG>
-__device__ __forceinline__ double2 gen_entry64(const double2 *__restrict__ t, int nh, uint32_t f,
-                                               uint32_t x, uint32_t M, double dM, double iM) {
-  if constexpr (BIG)
-    return big_entry64(t, nh, big_phase(f, x, dM, iM));
-  else
-    return t[(f * x) % M];
-}
-
 // Span of the guard region (block-uniform) from the exact area partials,
 // limited to the strips that reach into |k| <= K or |l| <= L; a split-bf16
 // clip routed to split-fp16 (gscale_alt > 0) sizes it with the fp16 factor.
@@ -280,14 +275,60 @@ __device__ __forceinline__ int guard_span_block(const unsigned long long *__rest
   return max(1, min(guard_span_routed(gscale, gscale_alt, V, a), nmax));
 }
 
+// Phases of a guard lane's three frequencies (its row fx, its column fy and
+// the 8-step of the rotations) against a corner.  GEN: general-tile records
+// (residues; one-level periods reduced with lane magics, gen_phase).  BIG:
+// corner words of a two-level clip (big_word_phase; NARROW as big_narrow).
+template <bool GEN, bool BIG, bool NARROW>
+struct GuardPhases {
+  uint32_t fx, fy, rx, ry, r8x, r8y, mx, my, m8x, m8y;
+  __device__ __forceinline__ GuardPhases(uint32_t fx_, uint32_t fy_, uint32_t Mx, uint32_t My)
+      : fx(fx_), fy(fy_) {
+    if constexpr (GEN && !BIG) {
+      rx = fx % Mx;
+      ry = fy % My;
+      r8x = 8u % Mx;
+      r8y = 8u % My;
+      mx = gen_magic(rx, Mx);
+      my = gen_magic(ry, My);
+      m8x = gen_magic(r8x, Mx);
+      m8y = gen_magic(r8y, My);
+    }
+  }
+  // (f x) mod Mx for f = fx (or 8 when EIGHT), from record/word c
+  template <bool EIGHT>
+  __device__ __forceinline__ uint32_t px(const uint4 &c, uint32_t Mx) const {
+    if constexpr (BIG)
+      return big_word_phase<NARROW, true>(EIGHT ? 8u : fx, c, Mx - 1u, -(int)Mx);
+    else
+      return EIGHT ? gen_phase(r8x, m8x, c.x, Mx) : gen_phase(rx, mx, c.x, Mx);
+  }
+  template <bool EIGHT>
+  __device__ __forceinline__ uint32_t py(const uint4 &c, uint32_t My) const {
+    if constexpr (BIG)
+      return big_word_phase<NARROW, false>(EIGHT ? 8u : fy, c, My - 1u, -(int)My);
+    else
+      return EIGHT ? gen_phase(r8y, m8y, c.y, My) : gen_phase(ry, my, c.y, My);
+  }
+  // the corner's sign is -1
+  __device__ __forceinline__ bool neg(const uint4 &c) const {
+    if constexpr (BIG)
+      return (c.z >> 30) & 1u;
+    else
+      return c.z != 0u;
+  }
+};
+
 // Slot group gi of the guard region over corner range blk (guard_group).
 // The group's blocks share one side: the l-strip groups keep the row
 // frequencies k = 1..8 and step the columns along l, the k-strip groups keep
 // l = 1..8 and step the rows along k.
 // GEN: general-tile records (residues); x phases (f x) mod Mx index wx, y
-// phases wy (BIG: two-level tables with nhx, nhy entries of Whi).  Otherwise
-// byte-offset records and the one table wx.
-template <bool GEN = false, bool BIG = false>
+// phases wy (BIG: the corner words of a two-level clip in place of the
+// records, two-level tables with nhx, nhy entries of Whi).  Otherwise
+// byte-offset records and the one table wx.  UR: corners in flight per lane
+// on the rotation path.
+template <bool GEN = false, bool BIG = false, bool NARROW = false, int UR = kGuardUnrollRot>
 __device__ __forceinline__ void guard_body(const uint4 *__restrict__ packed,
                                            const double2 *__restrict__ wx, int64_t V,
                                            int64_t g_chunk, int blk, int gi,
@@ -297,8 +338,6 @@ __device__ __forceinline__ void guard_body(const uint4 *__restrict__ packed,
                                            unsigned int *__restrict__ gspan,
                                            const double2 *__restrict__ wy = nullptr, int Mx = 0,
                                            int My = 0, int nhx = 0, int nhy = 0) {
-  const double dMx = (double)Mx, dMy = (double)My;
-  const double iMx = BIG ? 1.0 / dMx : 0.0, iMy = BIG ? 1.0 / dMy : 0.0;
   __shared__ double red[4][kGuardD];
   const int n =
       __builtin_amdgcn_readfirstlane(guard_span_block(area_part, pre_blocks, V, gscale, gscale_alt, K, L));
@@ -313,6 +352,7 @@ __device__ __forceinline__ void guard_body(const uint4 *__restrict__ packed,
   const uint32_t fx = f + (uint32_t)(kGuard * gg.kb);
   const uint32_t fy = f + (uint32_t)(kGuard * gg.lb);
   const bool sn = i >= 8;  // sin row / column
+  const GuardPhases<GEN, BIG, NARROW> ph(fx, fy, (uint32_t)Mx, (uint32_t)My);
   const int64_t v0 = (int64_t)blk * g_chunk;
   const int64_t v1 = min(V, v0 + g_chunk);
   f64x4 acc[4];
@@ -329,16 +369,16 @@ __device__ __forceinline__ void guard_body(const uint4 *__restrict__ packed,
         if (v < v1) {
           const uint4 c = packed[v];
           if constexpr (BIG) {
-            const double2 wa = gen_entry64<true>(wx, nhx, fx, c.x, Mx, dMx, iMx);
-            const double2 wb = gen_entry64<true>(wy, nhy, fy, c.y, My, dMy, iMy);
+            const double2 wa = big_entry64(wx, nhx, ph.template px<false>(c, Mx));
+            const double2 wb = big_entry64(wy, nhy, ph.template py<false>(c, My));
             ea[u] = sn ? wa.y : wa.x;
             const double tb = sn ? wb.y : wb.x;
-            eb[u] = c.z ? -tb : tb;
+            eb[u] = ph.neg(c) ? -tb : tb;
           } else {
             uint32_t px, py;
             if constexpr (GEN) {
-              px = (fx * c.x) % (uint32_t)Mx;
-              py = (fy * c.y) % (uint32_t)My;
+              px = ph.template px<false>(c, Mx);
+              py = ph.template py<false>(c, My);
             } else {
               px = __umul24(fx, c.x >> 3) & (uint32_t)(kTabN - 1);
               py = __umul24(fy, c.y >> 3) & (uint32_t)(kTabN - 1);
@@ -356,27 +396,29 @@ __device__ __forceinline__ void guard_body(const uint4 *__restrict__ packed,
     }
   } else {
     // several blocks: (cos, sin) of the first and of the 8-step, rotated
-    for (int64_t base = v0 + 4 * wave; base < v1; base += 16 * kGuardUnrollRot) {
-      double2 ex[kGuardUnrollRot], ey[kGuardUnrollRot], e8[kGuardUnrollRot];
+    for (int64_t base = v0 + 4 * wave; base < v1; base += 16 * UR) {
+      double2 ex[UR], ey[UR], e8[UR];
+      bool ng[UR];
 #pragma unroll
-      for (int u = 0; u < kGuardUnrollRot; ++u) {
+      for (int u = 0; u < UR; ++u) {
         const int64_t v = base + 16 * u + q;
         ex[u] = ey[u] = make_double2(0.0, 0.0);
         e8[u] = make_double2(1.0, 0.0);
+        ng[u] = false;
         if (v < v1) {
           const uint4 c = packed[v];
-          double2 t;
+          ng[u] = ph.neg(c);
           if constexpr (BIG) {
-            ex[u] = gen_entry64<true>(wx, nhx, fx, c.x, Mx, dMx, iMx);
-            t = gen_entry64<true>(wy, nhy, fy, c.y, My, dMy, iMy);
-            e8[u] = ymove ? gen_entry64<true>(wy, nhy, 8u, c.y, My, dMy, iMy)
-                          : gen_entry64<true>(wx, nhx, 8u, c.x, Mx, dMx, iMx);
+            ex[u] = big_entry64(wx, nhx, ph.template px<false>(c, Mx));
+            ey[u] = big_entry64(wy, nhy, ph.template py<false>(c, My));
+            e8[u] = ymove ? big_entry64(wy, nhy, ph.template py<true>(c, My))
+                          : big_entry64(wx, nhx, ph.template px<true>(c, Mx));
           } else {
             uint32_t px, py, p8;
             if constexpr (GEN) {
-              px = (fx * c.x) % (uint32_t)Mx;
-              py = (fy * c.y) % (uint32_t)My;
-              p8 = ymove ? (8u * c.y) % (uint32_t)My : (8u * c.x) % (uint32_t)Mx;
+              px = ph.template px<false>(c, Mx);
+              py = ph.template py<false>(c, My);
+              p8 = ymove ? ph.template py<true>(c, My) : ph.template px<true>(c, Mx);
             } else {
               const uint32_t xs = c.x >> 3, ys = c.y >> 3;
               px = __umul24(fx, xs) & (uint32_t)(kTabN - 1);
@@ -384,15 +426,14 @@ __device__ __forceinline__ void guard_body(const uint4 *__restrict__ packed,
               p8 = (8u * (ymove ? ys : xs)) & (uint32_t)(kTabN - 1);
             }
             ex[u] = wx[px];
-            t = GEN ? wy[py] : wx[py];
+            ey[u] = GEN ? wy[py] : wx[py];
             e8[u] = (GEN && ymove) ? wy[p8] : wx[p8];
           }
-          ey[u] = c.z ? make_double2(-t.x, -t.y) : t;
         }
       }
 #pragma unroll
-      for (int u = 0; u < kGuardUnrollRot; ++u) {
-        double2 a = ex[u], b = ey[u];
+      for (int u = 0; u < UR; ++u) {
+        double2 a = ex[u], b = ng[u] ? make_double2(-ey[u].x, -ey[u].y) : ey[u];
 #pragma unroll
         for (int j = 0; j < 4; ++j)
           if (j < ns) {
@@ -492,56 +533,114 @@ __global__ __launch_bounds__(256) void k_gen_axis_dft(const unsigned long long *
   dft_body<true>(hist, wx, Mx, 0, K, L, fb_k, axis_part, blockIdx.x, blockIdx.y, wy, My);
 }
 
-// Periods past 8192 (two-level tables): the guard blocks alone.
+// Periods past 8192 (two-level tables): the guard blocks alone, over the
+// corner words.
 __global__ __launch_bounds__(256) void k_gen_side_big(
-    const uint4 *__restrict__ packed, int64_t V, const double2 *__restrict__ wx,
+    const uint4 *__restrict__ words, int64_t V, const double2 *__restrict__ wx,
     const double2 *__restrict__ wy, int Mx, int My, int nhx, int nhy, int64_t g_chunk,
     int g_chunks, const unsigned long long *__restrict__ area_part, int pre_blocks, double gscale,
     double gscale_alt, int K, int L, double *__restrict__ gpart, unsigned int *__restrict__ gspan) {
-  guard_body<true, true>(packed, wx, V, g_chunk, blockIdx.x % g_chunks, blockIdx.x / g_chunks,
-                         area_part, pre_blocks, gscale, gscale_alt, K, L, gpart, gspan, wy, Mx,
-                         My, nhx, nhy);
+  if (big_narrow(Mx, My))
+    guard_body<true, true, true>(words, wx, V, g_chunk, blockIdx.x % g_chunks,
+                                 blockIdx.x / g_chunks, area_part, pre_blocks, gscale, gscale_alt,
+                                 K, L, gpart, gspan, wy, Mx, My, nhx, nhy);
+  else
+    guard_body<true, true, false>(words, wx, V, g_chunk, blockIdx.x % g_chunks,
+                                  blockIdx.x / g_chunks, area_part, pre_blocks, gscale,
+                                  gscale_alt, K, L, gpart, gspan, wy, Mx, My, nhx, nhy);
 }
 
 // Axis sums (Steps 2 and 3) over the corners directly, for periods past 8192
 // where a histogram over the residues would be too large: block (fb, chunk)
-// takes 256 frequencies of one axis against the corners of its range,
+// takes 128 frequencies f = f0 + 1 + i of one axis against the corners of its
+// range,
 //   Sx[f] += sum_v s_v y_v e^{-j 2 pi f x_v / Mx},  Sy[f] += sum_v s_v x_v e^{-j 2 pi f y_v / My},
-// raw coordinates as the moments and residues for the exact phases; the same
-// per-chunk partials as k_gen_axis_dft, reduced by the epilogue.
-__global__ __launch_bounds__(256) void k_gen_axis_big(
-    const int32_t *__restrict__ x, const int32_t *__restrict__ y, const uint4 *__restrict__ packed,
+// raw coordinates as the moments.  With i = 16 a + b the twiddle factors as
+// e((f0 + 1 + 16 a) x / M) e(b x / M): per corner the block builds the 8 + 16
+// factors in FP64 (exact phases from the corner words, big_word_phase, and the
+// two-level FP64 tables) in LDS, 64 corners at a time, and each thread then
+// multiplies the two factors of its frequency for 32 of them (threads t and
+// t + 128 split the corners and add up at the end).  The same per-chunk
+// partials as k_gen_axis_dft, reduced by the epilogue.
+constexpr int kAxisBigFreqs = 128;
+constexpr int kAxisBigStep = 64;  // corners per LDS step
+template <bool NARROW>
+__device__ __forceinline__ void gen_axis_big_body(
+    const int32_t *__restrict__ x, const int32_t *__restrict__ y, const uint4 *__restrict__ words,
     int64_t V, int64_t ax_chunk, const double2 *__restrict__ wx, const double2 *__restrict__ wy,
-    int Mx, int My, int nhx, int nhy, int K, int L, int fb_k, double2 *__restrict__ axis_part) {
-  __shared__ uint32_t s_q[256];
-  __shared__ double s_m[256];
-  const int fb = blockIdx.x, chunk = blockIdx.y, t = threadIdx.x;
+    int Mx, int My, int nhx, int nhy, int K, int L, int fb_k, double2 *__restrict__ axis_part,
+    int fb, int chunk) {
+  __shared__ double2 fac[kAxisBigStep][24];
+  __shared__ double mom[kAxisBigStep];
+  const int t = threadIdx.x, fi = t & (kAxisBigFreqs - 1), half = t >> 7;
   const bool xaxis = fb < fb_k;
-  const int f = 1 + (xaxis ? fb : fb - fb_k) * 256 + t;
+  const int f0 = (xaxis ? fb : fb - fb_k) * kAxisBigFreqs;
+  const int f = f0 + 1 + fi;
   const int nf = xaxis ? K : L;
   const double2 *W = xaxis ? wx : wy;
   const int nh = xaxis ? nhx : nhy;
-  const double dM = (double)(xaxis ? Mx : My), iM = 1.0 / dM;
+  const uint32_t M = (uint32_t)(xaxis ? Mx : My);
   const int64_t v0 = (int64_t)chunk * ax_chunk, v1 = min(V, v0 + ax_chunk);
+  const int a = fi >> 4, b = fi & 15;
   double re = 0.0, im = 0.0;
-  for (int64_t b = v0; b < v1; b += 256) {
-    const int n = (int)min((int64_t)256, v1 - b);
-    __syncthreads();
-    if (t < n) {
-      const uint4 c = packed[b + t];
-      const double m = (double)(xaxis ? y[b + t] : x[b + t]);
-      s_q[t] = xaxis ? c.x : c.y;
-      s_m[t] = c.z ? -m : m;
+  for (int64_t base = v0; base < v1; base += kAxisBigStep) {
+    const int n = (int)min((int64_t)kAxisBigStep, v1 - base);
+    __syncthreads();  // the previous step's factors are consumed
+    // factors: slot s < 8: e((f0 + 1 + 16 s) x / M), else e((s - 8) x / M)
+    for (int e = t; e < kAxisBigStep * 24; e += 256) {
+      const int j = e / 24, sl = e - 24 * (e / 24);
+      double2 w = make_double2(0.0, 0.0);
+      if (j < n) {
+        const uint4 c = words[base + j];
+        const uint32_t g = sl < 8 ? (uint32_t)(f0 + 1 + 16 * sl) : (uint32_t)(sl - 8);
+        const uint32_t p = xaxis ? big_word_phase<NARROW, true>(g, c, M - 1u, -(int)M)
+                                 : big_word_phase<NARROW, false>(g, c, M - 1u, -(int)M);
+        w = big_entry64(W, nh, p);
+      }
+      fac[j][sl] = w;
+    }
+    if (t < kAxisBigStep) {
+      double m = 0.0;
+      if (t < n) {
+        const int64_t v = base + t;
+        const double r = (double)(xaxis ? y[v] : x[v]);
+        m = (words[v].z >> 30) & 1u ? -r : r;
+      }
+      mom[t] = m;
     }
     __syncthreads();
-    if (f <= nf)
-      for (int i = 0; i < n; ++i) {
-        const double2 w = big_entry64(W, nh, big_phase((uint32_t)f, s_q[i], dM, iM));
-        re = fma(s_m[i], w.x, re);
-        im = fma(-s_m[i], w.y, im);
+    if (f <= nf) {
+      const int j0 = half * (kAxisBigStep / 2);
+#pragma unroll 4
+      for (int j = j0; j < j0 + kAxisBigStep / 2; ++j) {
+        const double2 p = fac[j][a], q = fac[j][8 + b];
+        const double wr = p.x * q.x - p.y * q.y, wi = p.x * q.y + p.y * q.x;
+        re = fma(mom[j], wr, re);
+        im = fma(-mom[j], wi, im);
       }
+    }
   }
-  if (f <= nf) axis_part[(size_t)chunk * (K + L) + (xaxis ? f - 1 : K + f - 1)] = make_double2(re, im);
+  __syncthreads();
+  double2 *red = &fac[0][0];  // reused once the last step is consumed
+  if (half) red[fi] = make_double2(re, im);
+  __syncthreads();
+  if (!half && f <= nf) {
+    const double2 o = red[fi];
+    axis_part[(size_t)chunk * (K + L) + (xaxis ? f - 1 : K + f - 1)] =
+        make_double2(re + o.x, im + o.y);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gen_axis_big(
+    const int32_t *__restrict__ x, const int32_t *__restrict__ y, const uint4 *__restrict__ words,
+    int64_t V, int64_t ax_chunk, const double2 *__restrict__ wx, const double2 *__restrict__ wy,
+    int Mx, int My, int nhx, int nhy, int K, int L, int fb_k, double2 *__restrict__ axis_part) {
+  if (big_narrow(Mx, My))
+    gen_axis_big_body<true>(x, y, words, V, ax_chunk, wx, wy, Mx, My, nhx, nhy, K, L, fb_k,
+                            axis_part, blockIdx.x, blockIdx.y);
+  else
+    gen_axis_big_body<false>(x, y, words, V, ax_chunk, wx, wy, Mx, My, nhx, nhy, K, L, fb_k,
+                             axis_part, blockIdx.x, blockIdx.y);
 }
 
 hipError_t launch_gen_side(const FwdPlan &p, const int32_t *x, const int32_t *y,
@@ -549,8 +648,9 @@ hipError_t launch_gen_side(const FwdPlan &p, const int32_t *x, const int32_t *y,
   char *w = (char *)ws;
   const uint4 *packed = (const uint4 *)(w + p.off_packed);
   if (p.big) {
+    const uint4 *words = (const uint4 *)(w + p.off_phi);
     if (p.K > 0 && p.L > 0)
-      hipLaunchKernelGGL(k_gen_side_big, dim3(kGuardGroups * p.g_chunks), dim3(256), 0, st, packed,
+      hipLaunchKernelGGL(k_gen_side_big, dim3(kGuardGroups * p.g_chunks), dim3(256), 0, st, words,
                          p.V, wx, wy, p.Mx, p.My, p.nhx, p.nhy, p.g_chunk, p.g_chunks,
                          (const unsigned long long *)(w + p.off_area), p.pre_blocks, p.gscale,
                          p.gscale_alt, p.K, p.L, (double *)(w + p.off_guard),
@@ -558,7 +658,7 @@ hipError_t launch_gen_side(const FwdPlan &p, const int32_t *x, const int32_t *y,
     if (p.K + p.L > 0) {
       const int64_t ax_chunk = std::max<int64_t>(1, (p.V + p.ax_chunks - 1) / p.ax_chunks);
       hipLaunchKernelGGL(k_gen_axis_big, dim3(p.ax_fb_k + p.ax_fb_l, p.ax_chunks), dim3(256), 0,
-                         st, x, y, packed, p.V, ax_chunk, wx, wy, p.Mx, p.My, p.nhx, p.nhy, p.K,
+                         st, x, y, words, p.V, ax_chunk, wx, wy, p.Mx, p.My, p.nhx, p.nhy, p.K,
                          p.L, p.ax_fb_k, (double2 *)(w + p.off_axis));
     }
     return hipGetLastError();
@@ -716,7 +816,7 @@ __device__ __forceinline__ void contract_split_body(const uint2 *s_tab,
 
 // Operand table of a contraction staged in LDS (8193 entries).
 __device__ __forceinline__ void stage_table(uint2 *s_tab, const uint2 *__restrict__ tab) {
-  for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
+  stage_entries(s_tab, tab, kTabEntries);
   __syncthreads();
 }
 
@@ -990,7 +1090,7 @@ __global__ __launch_bounds__(256) void k_contract_fp32(const uint4 *__restrict__
                                                        float *__restrict__ part, double r2) {
   if (tile_outside(blockIdx.x, tiles_l, 64 * NKB, 64 * NLB, r2)) return;
   __shared__ float2 s_tab[kTabEntries];
-  for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
+  stage_entries(s_tab, tab, kTabEntries);
   __syncthreads();
   contract_fp32_body<NKB, NLB>(s_tab, packed, chunk, tiles_l, kp, lp, part, blockIdx.x,
                                blockIdx.y);
@@ -1526,7 +1626,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_contract(const BatchClip *__re
   if (any && *any == 0u) return;  // a routed-clip pass with no routed clip
   __shared__ uint2 s_tab[kTabEntries];
   __shared__ int s_item;
-  for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
+  stage_entries(s_tab, tab, kTabEntries);
   for (;;) {
     const int it = next_item(counter, n_items, &s_item);
     if (it < 0) break;
@@ -1550,7 +1650,7 @@ __global__ __launch_bounds__(256, 1) void k_batch_contract_pipe(const BatchClip 
   if (any && *any == 0u) return;  // a routed-clip pass with no routed clip
   __shared__ uint2 s_tab[kTabEntries];
   __shared__ int s_item;
-  for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
+  stage_entries(s_tab, tab, kTabEntries);
   for (;;) {
     const int it = next_item(counter, n_items, &s_item);
     if (it < 0) break;
@@ -1569,7 +1669,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_contract_fp32(const BatchClip 
                                                                 const float2 *__restrict__ tab) {
   __shared__ float2 s_tab[kTabEntries];
   __shared__ int s_item;
-  for (int i = threadIdx.x; i < kTabEntries; i += 256) s_tab[i] = tab[i];
+  stage_entries(s_tab, tab, kTabEntries);
   for (;;) {
     const int it = next_item(counter, n_items, &s_item);
     if (it < 0) break;
@@ -1611,29 +1711,50 @@ __global__ __launch_bounds__(256) void k_gbatch_prepass(const GBatchClip *__rest
   const GBatchClip &c = clips[blockIdx.y];
   if ((int)blockIdx.x >= c.pre_blocks) return;
   gen_prepass_body(c.x, c.y, c.s, c.V, c.vpad, c.Mx, c.My, c.smask, c.packed, c.area_part,
-                   c.hist, blockIdx.x, c.pre_blocks);
+                   c.big ? nullptr : c.hist, blockIdx.x, c.pre_blocks, c.big ? c.words : nullptr);
 }
 
-// (clip, 0, b): histogram block b; (clip, 1, b): guard block b (slot group
-// b / g_chunks over corner range b % g_chunks)
+// (clip, 0, b): histogram block b; (clip, 1 | 2, b): guard block b (slot group
+// b / g_chunks over corner range b % g_chunks), 2 with two-level tables
 __global__ __launch_bounds__(256) void k_gbatch_side(const GBatchClip *__restrict__ clips,
                                                      const int4 *__restrict__ desc) {
   const int4 d = desc[blockIdx.x];
   const GBatchClip &c = clips[d.x];
+  constexpr int UR = 4;  // no contraction workgroup shares a CU with these blocks
   if (d.y == 0)
     hist_body<true>(c.x, c.y, c.packed, c.V, 0, c.hist, d.z, c.hist_blocks);
+  else if (d.y == 1)
+    guard_body<true, false, false, UR>(c.packed, c.w64x, c.V, c.g_chunk, d.z % c.g_chunks,
+                                       d.z / c.g_chunks, c.area_part, c.pre_blocks, c.gscale,
+                                       c.gscale_alt, c.K, c.L, c.gpart, c.gspan, c.w64y, c.Mx,
+                                       c.My);
+  else if (big_narrow(c.Mx, c.My))
+    guard_body<true, true, true, UR>(c.words, c.w64x, c.V, c.g_chunk, d.z % c.g_chunks,
+                                     d.z / c.g_chunks, c.area_part, c.pre_blocks, c.gscale,
+                                     c.gscale_alt, c.K, c.L, c.gpart, c.gspan, c.w64y, c.Mx, c.My,
+                                     c.nhx, c.nhy);
   else
-    guard_body<true>(c.packed, c.w64x, c.V, c.g_chunk, d.z % c.g_chunks, d.z / c.g_chunks,
-                     c.area_part, c.pre_blocks, c.gscale, c.gscale_alt, c.K, c.L, c.gpart,
-                     c.gspan, c.w64y, c.Mx, c.My);
+    guard_body<true, true, false, UR>(c.words, c.w64x, c.V, c.g_chunk, d.z % c.g_chunks,
+                                      d.z / c.g_chunks, c.area_part, c.pre_blocks, c.gscale,
+                                      c.gscale_alt, c.K, c.L, c.gpart, c.gspan, c.w64y, c.Mx,
+                                      c.My, c.nhx, c.nhy);
 }
 
+// (clip, 0, fb, chunk): DFT of the histograms; (clip, 1, fb, chunk): the
+// direct sums of a two-level clip
 __global__ __launch_bounds__(256) void k_gbatch_axis(const GBatchClip *__restrict__ clips,
                                                      const int4 *__restrict__ desc) {
   const int4 d = desc[blockIdx.x];
   const GBatchClip &c = clips[d.x];
-  dft_body<true>(c.hist, c.w64x, c.Mx, 0, c.K, c.L, c.ax_fb_k, c.axis_part, d.y, d.z, c.w64y,
-                 c.My);
+  if (d.y == 0)
+    dft_body<true>(c.hist, c.w64x, c.Mx, 0, c.K, c.L, c.ax_fb_k, c.axis_part, d.z, d.w, c.w64y,
+                   c.My);
+  else if (big_narrow(c.Mx, c.My))
+    gen_axis_big_body<true>(c.x, c.y, c.words, c.V, c.ax_chunk, c.w64x, c.w64y, c.Mx, c.My,
+                            c.nhx, c.nhy, c.K, c.L, c.ax_fb_k, c.axis_part, d.z, d.w);
+  else
+    gen_axis_big_body<false>(c.x, c.y, c.words, c.V, c.ax_chunk, c.w64x, c.w64y, c.Mx, c.My,
+                             c.nhx, c.nhy, c.K, c.L, c.ax_fb_k, c.axis_part, d.z, d.w);
 }
 
 __global__ __launch_bounds__(256) void k_gbatch_epilogue(const GBatchClip *__restrict__ clips,

@@ -158,7 +158,10 @@ def test_general_workspace_sizes(lib):
 
 
 def test_general_batch_workspace_size(lib):
-    # one 256-byte aligned slice per clip; an empty batch is rejected
+    # one 256-byte aligned slice per clip; an FP32 batch keeps the single-clip
+    # layouts (a captured sequence of single-clip forwards), a split-precision
+    # batch sizes its own split counts (one launch per step); an empty batch
+    # is rejected
     from paper_1010_5562_amd import _lib
 
     specs = [(200000, 8000, 6000, 0, 511, 511), (3000, 3000, 2000, 3, 40, 33),
@@ -168,11 +171,17 @@ def test_general_batch_workspace_size(lib):
     each = []
     for c in cs:
         n = ctypes.c_size_t(0)
-        assert lib.fcfs_general_workspace_size(ctypes.byref(c), 1, ctypes.byref(n)) == 0
+        assert lib.fcfs_general_workspace_size(ctypes.byref(c), 0, ctypes.byref(n)) == 0
         each.append((n.value + 255) // 256 * 256)
     total = ctypes.c_size_t(0)
-    assert lib.fcfs_general_batch_workspace_size(cs, 3, 1, ctypes.byref(total)) == 0
+    assert lib.fcfs_general_batch_workspace_size(cs, 3, 0, ctypes.byref(total)) == 0
     assert total.value == sum(each)
+    t1, t2 = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.fcfs_general_batch_workspace_size(cs, 3, 1, ctypes.byref(t1)) == 0
+    assert lib.fcfs_general_batch_workspace_size(cs, 3, 1, ctypes.byref(t2)) == 0
+    assert t1.value == t2.value and t1.value % 256 == 0
+    # at least the corner records, magics and one 128 x 128 partial per clip
+    assert t1.value >= sum(16 * V + 4 * 4 * 128 * 128 for V, *_ in specs)
     assert lib.fcfs_general_batch_workspace_size(cs, 0, 1, ctypes.byref(total)) == -1
 
 

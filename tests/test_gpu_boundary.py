@@ -147,7 +147,12 @@ def test_general_batch_past_the_table_cache(P, oracle_lib):
             Fs, a = P.forward_general(x, y, s, Nx, Ny, K, K, frac_bits=F, precision="bf16",
                                       handle=h)
             torch.cuda.synchronize()
-            assert np.array_equal(Fs.cpu().numpy(), b.F[i].cpu().numpy()), (rep, i)
+            # the batch sums in its own split order: agreement to the
+            # precision's bound (a stale replay misses by orders more)
+            f00 = abs(complex(Fs[K, K].item()))
+            d = float(np.max(np.abs(Fs.cpu().numpy().astype(np.complex128)
+                                    - b.F[i].cpu().numpy())) / f00)
+            assert d <= TOL_SPLIT, (rep, i, d)
             if i % 7 == 0:
                 ref, area = oracle_lib.cfs_grid_general(xy, loops[i].off, Nx, Ny, K, K)
                 e = float(np.max(np.abs(Fs.cpu().numpy().astype(np.complex128) - ref))

@@ -442,8 +442,10 @@ def test_general_two_level_adjoint_limit(P):
 
 def test_general_batch_graph(P, oracle_lib):
     # clips of different periods, grid steps and cut-offs (two of them past
-    # 8192 grid units) in one captured graph: the eager pass equals the single
-    # calls bit for bit, replays repeat it, the oracle agrees
+    # 8192 grid units) in one plan: the oracle agrees with the first pass, the
+    # single calls agree with it to the precision's bound (the batch chooses
+    # its own split counts, so the FP32 sums are taken in another order), and
+    # replays repeat it bit for bit
     specs = [(3000, 2000, 0, 40, 33, 150, 71), (750, 1000, 2, 37, 45, 150, 72),
              (1000, 700, 13, 30, 28, 60, 73), (3000, 2000, 3, 41, 29, 100, 74),
              (7, 5, 3, 30, 29, 6, 75)]
@@ -465,8 +467,10 @@ def test_general_batch_graph(P, oracle_lib):
     for i, (x, y, s, Nx, Ny, K, L, F) in enumerate(clips):
         Fs, a = P.forward_general(x, y, s, Nx, Ny, K, L, frac_bits=F, precision="bf16")
         torch.cuda.synchronize()
-        assert np.array_equal(Fs.cpu().numpy(), eager[i]), i
         ref, area = refs[i]
+        d = float(np.max(np.abs(Fs.cpu().numpy().astype(np.complex128) - eager[i]))
+                  / abs(ref[K, L]))
+        assert d <= TOL["bf16"], (i, d)
         assert int(b.area[i].item()) == area
         e = float(np.max(np.abs(eager[i].astype(np.complex128) - ref)) / abs(ref[K, L]))
         assert e <= TOL["bf16"], (i, e)
