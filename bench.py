@@ -646,7 +646,8 @@ def main() -> int:
     t0 = time.time()
     batch = P.Batch(bargs, precision="bf16", tune=True)
     t_tune = time.time() - t0
-    log(f"batch autotune: {t_tune:.1f}s, choice (tile variant, corners per item) {batch.choice}")
+    log(f"batch autotune: {t_tune:.1f}s, choice per K bucket (tile variant, corners per item) "
+        f"{batch.choice}")
     msb, profb = timed(batch.run, max(3, args.steps // 4), 1, h, kinds=("batch",))
     # error on the four smallest clips and four random ones, sampled points
     order = np.argsort([int(a[0].size) for a in bargs])
@@ -672,8 +673,10 @@ def main() -> int:
         "roofline": {"bound": "mfma", "achieved": bflops / (msb * 1e-3) / 1e12,
                      "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
                      "frac": bflops / (msb * 1e-3) / 1e12 / PEAK_TFLOPS["bf16"]},
-        "autotune": {"seconds": t_tune, "tile_variant": batch.choice[0],
-                     "corners_per_item": batch.choice[1]},
+        "autotune": {"seconds": t_tune,
+                     "per_kbucket": {f"K<={P.BATCH_KBUCKET_MAX[kb]}" if kb < 4 else "K>511":
+                                     {"tile_variant": t, "corners_per_item": ch}
+                                     for kb, (t, ch) in batch.choice.items()}},
     }
     log(f"batch: {msb:.3f} ms  {bpairs / msb * 1e3:.4g} pairs/s  err {eb:.2e}")
     batch.close()
@@ -709,12 +712,12 @@ def main() -> int:
         "value": ppairs / (msp * 1e-3), "unit": "pairs/s",
         "output_GBps": ntp * (2 * Kp + 1) ** 2 * 8 / (msp * 1e-3) / 1e9,
         "err_rel_f00_full_grid_2_tiles": ep,
-        "autotune": {"tile_variant": pb.choice[0], "corners_per_item": pb.choice[1]},
+        "autotune": {"tile_variant": pb.choice[3][0], "corners_per_item": pb.choice[3][1]},
         "paper_cpu_us_per_tile": 15648.0,
     }
     log(f"paper-shaped tiles: {msp * 1e3 / ntp:.2f} us per tile "
         f"({forms['paper_shaped_tiles']['output_GBps']:.0f} GB/s of output), err {ep:.2e}, "
-        f"choice {pb.choice}")
+        f"choice {pb.choice[3]}")
     pb.close()
     del pb
 

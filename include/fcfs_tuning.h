@@ -13,17 +13,25 @@
 extern "C" {
 #endif
 
-/* Batch autotuner: builds and times a plan of the clips c[0..n) for each
- * candidate (contraction tile variant, corners per work item) and keeps the
- * fastest on h (used by later fcfs_batch_workspace_size / fcfs_forward_batch
- * calls for precision p); the built-in choice stays unless a candidate beats it
- * by more than 3%.  Overwrites the clips' outputs.  effort 0..2 sets the timed
- * repetitions (2, 3, 5).  Allocates and frees a workspace per candidate and
- * synchronises the handle's stream.  fcfs_batch_choice reports the current
- * choice. */
+/* Batch autotuner.  The batch takes its contraction tile variant and corners
+ * per work item per K bucket of a clip (bucket of max(K, L): 0 up to 63, 1 up
+ * to 127, 2 up to 255, 3 up to 511, 4 above; clips whose buckets share a
+ * variant share one persistent launch).  fcfs_autotune_batch builds and times
+ * a plan of the clips c[0..n) for each candidate (variant, corners per item),
+ * first alike for every bucket, then, when the clips span several buckets,
+ * per bucket on that bucket's clips; the per-bucket choices are kept only if
+ * the whole batch runs faster with them, and a candidate replaces the
+ * built-in choice only when more than 3% faster.  The choices hold on h for
+ * later fcfs_batch_workspace_size / fcfs_forward_batch calls of precision p.
+ * Overwrites the clips' outputs.  effort 0..2 sets the timed repetitions
+ * (2, 3, 5).  Allocates and frees a workspace per candidate and synchronises
+ * the handle's stream.  fcfs_batch_choice reports the current choice of K
+ * bucket kbucket (0..FCFS_BATCH_KBUCKETS-1). */
+#define FCFS_BATCH_KBUCKETS 5
 fcfs_status fcfs_autotune_batch(fcfs_handle *h, const fcfs_clip *c, int32_t n, fcfs_precision p,
                                 int effort);
-fcfs_status fcfs_batch_choice(fcfs_handle *h, fcfs_precision p, int32_t *tile, int64_t *chunk);
+fcfs_status fcfs_batch_choice(fcfs_handle *h, fcfs_precision p, int32_t kbucket, int32_t *tile,
+                              int64_t *chunk);
 
 /* Contraction tile variants.  fcfs_tile_variants fills wk[i], wl[i]
  * (frequencies per wave in k and l of variant i, for i < cap) and returns the

@@ -795,6 +795,19 @@ def __getattr__(name):
     raise AttributeError(name)
 
 
+BATCH_KBUCKET_MAX = (63, 127, 255, 511)
+
+
+def batch_kbucket(K, L):
+    """K bucket of a batch clip (the library's batch_kbucket): the index of the
+    first bound in BATCH_KBUCKET_MAX that max(K, L) does not exceed, else 4."""
+    m = max(int(K), int(L))
+    for i, b in enumerate(BATCH_KBUCKET_MAX):
+        if m <= b:
+            return i
+    return len(BATCH_KBUCKET_MAX)
+
+
 class Batch:
     """Many clips in one persistent, graph-captured launch (fcfs_forward_batch).
 
@@ -803,7 +816,8 @@ class Batch:
     captured graph's pointers stay valid; ``run()`` replays it.  Outputs:
     ``F[i]`` ((2K_i+1, 2L_i+1) complex64) and ``area[i]``.  ``tune=True`` runs
     the batch autotuner on these clips first (fcfs_autotune_batch); ``choice``
-    holds the (tile variant, corners per work item) the plan uses.
+    maps each K bucket present (``batch_kbucket``) to the (tile variant,
+    corners per work item) the plan uses for its clips.
     """
 
     def __init__(self, clips, precision="bf16", handle=None, tune=False, tune_effort=0):
@@ -827,10 +841,12 @@ class Batch:
         if tune:
             check(h.lib.fcfs_autotune_batch(h.ptr, arr, self.n, self.precision, int(tune_effort)),
                   h.ptr)
-        tile, chunk = ctypes.c_int32(0), ctypes.c_int64(0)
-        check(h.lib.fcfs_batch_choice(h.ptr, self.precision, ctypes.byref(tile),
-                                      ctypes.byref(chunk)), h.ptr)
-        self.choice = (int(tile.value), int(chunk.value))
+        self.choice = {}
+        for kb in sorted({batch_kbucket(c[4], c[5]) for c in clips}):
+            tile, chunk = ctypes.c_int32(0), ctypes.c_int64(0)
+            check(h.lib.fcfs_batch_choice(h.ptr, self.precision, kb, ctypes.byref(tile),
+                                          ctypes.byref(chunk)), h.ptr)
+            self.choice[kb] = (int(tile.value), int(chunk.value))
         nb = ctypes.c_size_t(0)
         check(h.lib.fcfs_batch_workspace_size(h.ptr, arr, self.n, self.precision,
                                               ctypes.byref(nb)), h.ptr)

@@ -169,7 +169,7 @@ def load() -> ctypes.CDLL:
         "fcfs_debug_phases_workspace_size": [i64, i32, sz],
         "fcfs_autotune": [P, ctypes.c_char_p, c_int],
         "fcfs_autotune_batch": [P, clip_p, i32, c_int, c_int],
-        "fcfs_batch_choice": [P, c_int, P, P],
+        "fcfs_batch_choice": [P, c_int, c_int, P, P],
         "fcfs_load_tune": [P, ctypes.c_char_p],
         "fcfs_set_tile": [P, i32],
         "fcfs_profile_begin": [P, u32],

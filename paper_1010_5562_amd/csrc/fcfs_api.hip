@@ -61,15 +61,22 @@ struct fcfs_handle {
   std::vector<fcfs_step_plan *> step_plans;
   // set while the library captures its own launch sequence on this handle
   bool own_capture = false;
-  int batch_tile[3] = {-1, -1, -1};
-  int64_t batch_chunk[3] = {0, 0, 0};
+  // batch choices per precision and K bucket (fcfs::batch_kbucket): tile
+  // variant (-1: built-in) and corners per work item (0: built-in)
+  int batch_tile[3][fcfs::kBatchKBuckets];
+  int64_t batch_chunk[3][fcfs::kBatchKBuckets];
+  fcfs_handle() {
+    for (int p = 0; p < 3; ++p)
+      for (int b = 0; b < fcfs::kBatchKBuckets; ++b) {
+        batch_tile[p][b] = -1;
+        batch_chunk[p][b] = 0;
+      }
+  }
 };
 
 struct fcfs_plan {
   int device = 0;
   int prec = 0;
-  int tile = 0;
-  int64_t chunk_target = 0;
   std::vector<fcfs_clip> clips;      // the clips the graph was captured for
   void *ws = nullptr;
   size_t ws_bytes = 0;
@@ -2251,17 +2258,18 @@ struct BatchLayout {
   std::vector<size_t> off_packed, off_area, off_hist, off_axis, off_part, off_guard, off_gspan;
   std::vector<int4> ax_desc, items, side_desc;
   std::vector<int> epi_off;
+  std::vector<int> group_tile, group_off;  // tile-variant groups of the items
   size_t bytes = 0;
 };
 
-int batch_tile(fcfs_handle *h, int prec);
-int64_t batch_chunk(fcfs_handle *h, int prec);
+int batch_tile(fcfs_handle *h, int prec, int bucket);
+int64_t batch_chunk(fcfs_handle *h, int prec, int bucket);
 
-fcfs_status batch_layout(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec, int tile,
-                         int64_t chunk_target, BatchLayout *L) {
+fcfs_status batch_layout(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec,
+                         BatchLayout *L) {
   if (n < 0 || (n > 0 && !c)) return fail(h, FCFS_ERR_INVALID_ARG, "bad clip array");
-  if (tile < 0 || tile >= fcfs::n_tile_variants()) return fail(h, FCFS_ERR_INVALID_ARG, "tile");
-  const fcfs::TileVariant &tv = fcfs::tile_variant(tile);
+  if (prec < 0 || prec > 2) return fail(h, FCFS_ERR_INVALID_ARG, "unknown precision");
+  L->group_tile.clear();
   L->bc.assign(n, fcfs::BatchClip{});
   L->off_packed.assign(n, 0);
   L->off_area.assign(n, 0);
@@ -2276,11 +2284,25 @@ fcfs_status batch_layout(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec
   L->epi_off.assign(n + 1, 0);
   // the work counters live at the head of the workspace, the clips' routes next
   size_t off = 256 + align256(sizeof(unsigned int) * (size_t)std::max(n, 1));
-  std::vector<std::pair<int64_t, int4>> items;
+  // items per tile-variant group, in order of the groups' first clips
+  std::vector<std::vector<std::pair<int64_t, int4>>> items;
   for (int i = 0; i < n; ++i) {
     const fcfs_clip &ci = c[i];
     fcfs_status st = check_dims(h, ci.V, ci.T, ci.K, ci.L, prec);
     if (st) return st;
+    const int bucket = fcfs::batch_kbucket(ci.K, ci.L);
+    const int tile = batch_tile(h, prec, bucket);
+    const int64_t chunk_target = batch_chunk(h, prec, bucket);
+    if (tile < 0 || tile >= fcfs::n_tile_variants() ||
+        !(fcfs::tile_variant(tile).prec_mask & (1 << prec)))
+      return fail(h, FCFS_ERR_INVALID_ARG, "tile variant not built for this precision");
+    const fcfs::TileVariant &tv = fcfs::tile_variant(tile);
+    int g = 0;
+    while (g < (int)L->group_tile.size() && L->group_tile[g] != tile) ++g;
+    if (g == (int)L->group_tile.size()) {
+      L->group_tile.push_back(tile);
+      items.emplace_back();
+    }
     fcfs::BatchClip &b = L->bc[i];
     b.V = ci.V;
     b.T = ci.T;
@@ -2316,7 +2338,7 @@ fcfs_status batch_layout(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec
     if (ci.K > 0 && ci.L > 0)
       for (int t = 0; t < tiles; ++t)
         for (int sp = 0; sp < b.nsplit; ++sp)
-          items.push_back({b.chunk * (int64_t)wgk * wgl, make_int4(i, t, sp, 0)});
+          items[g].push_back({b.chunk * (int64_t)wgk * wgl, make_int4(i, t, sp, 0)});
     // one split: the contraction writes F itself (kernels with two waves per SIMD)
     b.direct = b.nsplit == 1 && ci.K > 0 && ci.L > 0 && tv.pipe != 2 ? 1 : 0;
     L->epi_off[i + 1] = L->epi_off[i] + fcfs::epilogue_block_count(ci.K, ci.L, b.direct != 0);
@@ -2335,12 +2357,16 @@ fcfs_status batch_layout(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec
     L->off_gspan[i] = off;
     off += 256;
   }
-  // longest processing time first; ties keep clip order
-  std::stable_sort(items.begin(), items.end(),
-                   [](const std::pair<int64_t, int4> &a, const std::pair<int64_t, int4> &b) {
-                     return a.first > b.first;
-                   });
-  for (auto &it : items) L->items.push_back(it.second);
+  // longest processing time first within a group; ties keep clip order
+  L->group_off.assign(1, 0);
+  for (auto &gi : items) {
+    std::stable_sort(gi.begin(), gi.end(),
+                     [](const std::pair<int64_t, int4> &a, const std::pair<int64_t, int4> &b) {
+                       return a.first > b.first;
+                     });
+    for (auto &it : gi) L->items.push_back(it.second);
+    L->group_off.push_back((int)L->items.size());
+  }
   L->bytes = off;
   return FCFS_OK;
 }
@@ -2378,13 +2404,13 @@ fcfs_status build_plan(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec, 
   if (!p) return fail(h, FCFS_ERR_NO_MEMORY, "plan allocation");
   p->device = h->device;
   p->prec = prec;
-  p->tile = batch_tile(h, prec);
-  p->chunk_target = batch_chunk(h, prec);
   p->clips.assign(c, c + n);
   p->ws = ws;
   p->ws_bytes = ws_bytes;
   BatchLayout L;
-  fcfs_status st = batch_layout(h, c, n, prec, p->tile, p->chunk_target, &L);
+  fcfs_status st = batch_layout(h, c, n, prec, &L);
+  if (!st && (int)L.group_tile.size() > fcfs::kBatchMaxGroups)
+    st = fail(h, FCFS_ERR_UNSUPPORTED, "too many tile-variant groups");
   if (!st && ws_bytes < L.bytes)
     st = fail(h, FCFS_ERR_WORKSPACE, "batch workspace too small: need " + std::to_string(L.bytes));
   if (!st && (!ws || ((uintptr_t)ws & 255u)))
@@ -2409,11 +2435,15 @@ fcfs_status build_plan(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec, 
   fcfs::BatchLaunch &bl = p->launch;
   bl.n_clips = n;
   bl.prec = prec;
-  bl.tile = p->tile;
   bl.pre_blocks = kBatchPreBlocks;
   bl.n_ax = (int)L.ax_desc.size();
   bl.n_items = (int)L.items.size();
-  bl.grid = fcfs::batch_grid(p->tile, prec);
+  bl.n_groups = st ? 0 : (int)L.group_tile.size();
+  for (int g = 0; g < bl.n_groups; ++g) {
+    bl.group_tile[g] = L.group_tile[g];
+    bl.group_off[g] = L.group_off[g];
+  }
+  bl.group_off[bl.n_groups] = st ? 0 : L.group_off[bl.n_groups];
   bl.counter = ws_at<unsigned int>(ws, 0);
   bl.route = prec == fcfs::kBF16 ? ws_at<unsigned int>(ws, 256) : nullptr;
   bl.n_epi = L.epi_off[n];
@@ -2476,8 +2506,7 @@ fcfs_status fcfs_batch_workspace_size(fcfs_handle *h, const fcfs_clip *c, int32_
                                       fcfs_precision p, size_t *bytes) {
   if (!bytes) return fail(h, FCFS_ERR_INVALID_ARG, "bytes is NULL");
   BatchLayout L;
-  const int tile = batch_tile(h, (int)p);
-  fcfs_status st = batch_layout(h, c, n, (int)p, tile, batch_chunk(h, (int)p), &L);
+  fcfs_status st = batch_layout(h, c, n, (int)p, &L);
   if (st) return st;
   *bytes = L.bytes;
   return FCFS_OK;
@@ -2514,12 +2543,16 @@ fcfs_status fcfs_plan_destroy(fcfs_plan *plan) {
 
 namespace {
 
-int batch_tile(fcfs_handle *h, int prec) {
-  if (h && prec >= 0 && prec < 3 && h->batch_tile[prec] >= 0) return h->batch_tile[prec];
+int batch_tile(fcfs_handle *h, int prec, int bucket) {
+  if (h && prec >= 0 && prec < 3 && bucket >= 0 && bucket < fcfs::kBatchKBuckets &&
+      h->batch_tile[prec][bucket] >= 0)
+    return h->batch_tile[prec][bucket];
   return prec == fcfs::kFP32 ? 1 : 5;
 }
-int64_t batch_chunk(fcfs_handle *h, int prec) {
-  if (h && prec >= 0 && prec < 3 && h->batch_chunk[prec] > 0) return h->batch_chunk[prec];
+int64_t batch_chunk(fcfs_handle *h, int prec, int bucket) {
+  if (h && prec >= 0 && prec < 3 && bucket >= 0 && bucket < fcfs::kBatchKBuckets &&
+      h->batch_chunk[prec][bucket] > 0)
+    return h->batch_chunk[prec][bucket];
   return 16384;
 }
 
@@ -2583,22 +2616,35 @@ bool load_tune(fcfs_handle *h, const char *path) {
       return false;
     tune.push_back({(int)pr, (int)kb, (int)vb, (int)t, 0.0});
   }
-  int bt[3] = {-1, -1, -1};
-  int64_t bc[3] = {0, 0, 0};
+  // batch entries: per K bucket, or (no "kbucket") for every bucket
+  int bt[3][fcfs::kBatchKBuckets];
+  int64_t bc[3][fcfs::kBatchKBuckets];
+  for (int p = 0; p < 3; ++p)
+    for (int b = 0; b < fcfs::kBatchKBuckets; ++b) {
+      bt[p][b] = -1;
+      bc[p][b] = 0;
+    }
   for (const std::string &o : json_objects(doc, "batch")) {
-    long long pr, t, c;
+    long long pr, t, c, kb = -1;
     if (!json_int(o, "prec", &pr) || !json_int(o, "tile", &t) || !json_int(o, "chunk", &c))
       return false;
-    if (pr < 0 || pr > 2 || t < 0 || t >= fcfs::n_tile_variants() || c < 16 || c > (1 << 24))
+    const bool all = !json_int(o, "kbucket", &kb);
+    if (pr < 0 || pr > 2 || t < 0 || t >= fcfs::n_tile_variants() || c < 16 || c > (1 << 24) ||
+        !(fcfs::tile_variant((int)t).prec_mask & (1 << pr)) ||
+        (!all && (kb < 0 || kb >= fcfs::kBatchKBuckets)))
       return false;
-    bt[pr] = (int)t;
-    bc[pr] = c;
+    for (int b = 0; b < fcfs::kBatchKBuckets; ++b)
+      if (all || b == kb) {
+        bt[pr][b] = (int)t;
+        bc[pr][b] = c;
+      }
   }
   h->tune = tune;
-  for (int i = 0; i < 3; ++i) {
-    h->batch_tile[i] = bt[i];
-    h->batch_chunk[i] = bc[i];
-  }
+  for (int p = 0; p < 3; ++p)
+    for (int b = 0; b < fcfs::kBatchKBuckets; ++b) {
+      h->batch_tile[p][b] = bt[p][b];
+      h->batch_chunk[p][b] = bc[p][b];
+    }
   return true;
 }
 
@@ -2613,12 +2659,13 @@ bool save_tune(const fcfs_handle *h, const char *path) {
   }
   std::fprintf(f, "],\n \"batch\": [");
   bool first = true;
-  for (int p = 0; p < 3; ++p) {
-    if (h->batch_tile[p] < 0) continue;
-    std::fprintf(f, "%s\n  {\"prec\": %d, \"tile\": %d, \"chunk\": %lld}", first ? "" : ",", p,
-                 h->batch_tile[p], (long long)h->batch_chunk[p]);
-    first = false;
-  }
+  for (int p = 0; p < 3; ++p)
+    for (int b = 0; b < fcfs::kBatchKBuckets; ++b) {
+      if (h->batch_tile[p][b] < 0) continue;
+      std::fprintf(f, "%s\n  {\"prec\": %d, \"kbucket\": %d, \"tile\": %d, \"chunk\": %lld}",
+                   first ? "" : ",", p, b, h->batch_tile[p][b], (long long)h->batch_chunk[p][b]);
+      first = false;
+    }
   std::fprintf(f, "]}\n");
   return std::fclose(f) == 0;
 }
@@ -2647,6 +2694,116 @@ struct DevBuf {
     if (p) (void)hipFree(p);
   }
 };
+
+// Shortest of `reps` timed replays of a batch plan of clips c (built first,
+// untimed, with the handle's current choices).
+fcfs_status time_batch(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec, int reps,
+                       hipEvent_t e0, hipEvent_t e1, float *best_ms) {
+  size_t bb = 0;
+  fcfs_status st = fcfs_batch_workspace_size(h, c, n, (fcfs_precision)prec, &bb);
+  if (st) return st;
+  DevBuf bw;
+  hipError_t e;
+  if ((e = hipMalloc(&bw.p, bb))) return hip_fail(h, e, "batch workspace");
+  fcfs_plan *plan = nullptr;
+  float bm = 1e30f;
+  st = fcfs_forward_batch(h, c, n, (fcfs_precision)prec, bw.p, bb, &plan);
+  for (int r = 0; r < reps && !st; ++r) {
+    float ms = 0.f;
+    if ((e = hipEventRecord(e0, h->stream))) st = hip_fail(h, e, "event");
+    if (!st) st = fcfs_forward_batch(h, c, n, (fcfs_precision)prec, bw.p, bb, &plan);
+    if (!st && ((e = hipEventRecord(e1, h->stream)) || (e = hipEventSynchronize(e1)) ||
+                (e = hipEventElapsedTime(&ms, e0, e1))))
+      st = hip_fail(h, e, "event timing");
+    bm = std::min(bm, ms);
+  }
+  (void)hipStreamSynchronize(h->stream);
+  plan_free(plan);
+  *best_ms = bm;
+  return st;
+}
+
+// Batch choices of precision prec from clips c.  First one (tile variant,
+// corners per item) for every K bucket, timed on the whole batch; then, when
+// the clips span several buckets, each bucket's own choice timed on its clips
+// alone, and the per-bucket choices are kept only if the whole batch runs
+// faster with them.  A candidate replaces the built-in choice only when more
+// than 3% faster.  Overwrites the clips' outputs.
+fcfs_status tune_batch_buckets(fcfs_handle *h, const fcfs_clip *c, int32_t n, int prec, int reps,
+                               hipEvent_t e0, hipEvent_t e1) {
+  constexpr double kMargin = 0.97;
+  constexpr int NB = fcfs::kBatchKBuckets;
+  const int tiles[3] = {prec == fcfs::kFP32 ? 0 : 3, prec == fcfs::kFP32 ? 1 : 4, 5};
+  const int ntiles = prec == fcfs::kFP32 ? 2 : 3;
+  // corners per work item; smaller items balance better but multiply the
+  // split partials the epilogue reads
+  const int64_t chunks[4] = {8192, 16384, 32768, 65536};
+  auto set_all = [&](int t, int64_t ch) {
+    for (int b = 0; b < NB; ++b) {
+      h->batch_tile[prec][b] = t;
+      h->batch_chunk[prec][b] = ch;
+    }
+  };
+  // the candidates over the clips cs (every bucket set alike), the best kept
+  // in (bt, bc) and its time in *best
+  auto search = [&](const std::vector<fcfs_clip> &cs, int *bt, int64_t *bc, float *best) {
+    set_all(-1, 0);
+    const int def_t = batch_tile(h, prec, 0);
+    const int64_t def_c = batch_chunk(h, prec, 0);
+    float t_def = 1e30f;
+    *best = 1e30f;
+    *bt = def_t;
+    *bc = def_c;
+    for (int ti = 0; ti < ntiles; ++ti)
+      for (int ci = 0; ci < 4; ++ci) {
+        set_all(tiles[ti], chunks[ci]);
+        float ms = 0.f;
+        fcfs_status st = time_batch(h, cs.data(), (int32_t)cs.size(), prec, reps, e0, e1, &ms);
+        if (st) return st;
+        if (tiles[ti] == def_t && chunks[ci] == def_c) t_def = ms;
+        if (ms < *best) {
+          *best = ms;
+          *bt = tiles[ti];
+          *bc = chunks[ci];
+        }
+      }
+    if (!(*best < kMargin * t_def)) {
+      *bt = def_t;
+      *bc = def_c;
+      *best = t_def;
+    }
+    return FCFS_OK;
+  };
+  std::vector<fcfs_clip> all(c, c + n);
+  int ut;
+  int64_t uc;
+  float t_uniform;
+  fcfs_status st = search(all, &ut, &uc, &t_uniform);
+  if (st) return st;
+  std::vector<fcfs_clip> per[NB];
+  for (int i = 0; i < n; ++i) per[fcfs::batch_kbucket(c[i].K, c[i].L)].push_back(c[i]);
+  int nbk = 0;
+  for (int b = 0; b < NB; ++b) nbk += !per[b].empty();
+  set_all(ut, uc);
+  if (nbk < 2) return FCFS_OK;
+  int bt[NB];
+  int64_t bc[NB];
+  for (int b = 0; b < NB; ++b) {
+    bt[b] = ut;
+    bc[b] = uc;
+    if (per[b].empty()) continue;
+    float tb;
+    if ((st = search(per[b], &bt[b], &bc[b], &tb))) return st;
+  }
+  for (int b = 0; b < NB; ++b) {
+    h->batch_tile[prec][b] = bt[b];
+    h->batch_chunk[prec][b] = bc[b];
+  }
+  float t_mixed = 0.f;
+  if ((st = time_batch(h, c, n, prec, reps, e0, e1, &t_mixed))) return st;
+  if (!(t_mixed < t_uniform)) set_all(ut, uc);
+  return FCFS_OK;
+}
 
 }  // namespace
 
@@ -2758,52 +2915,7 @@ fcfs_status fcfs_autotune(fcfs_handle *h, const char *cache_path, int effort) {
       cl[i] = fcfs_clip{(const int32_t *)dx.p, (const int32_t *)dy.p, (const int8_t *)ds.p, V, T, K,
                         K, (float *)outs[i].p, nullptr};
     }
-    // corners per work item; smaller items balance better but multiply the
-    // split partials the epilogue reads
-    const int64_t chunks[4] = {8192, 16384, 32768, 65536};
-    for (int p = 0; p < 3 && !st; ++p) {
-      const int tiles[3] = {p == fcfs::kFP32 ? 0 : 3, p == fcfs::kFP32 ? 1 : 4, 5};
-      const int ntiles = p == fcfs::kFP32 ? 2 : 3;
-      h->batch_tile[p] = -1;
-      h->batch_chunk[p] = 0;
-      const int def_tile = batch_tile(h, p);
-      const int64_t def_chunk = batch_chunk(h, p);
-      double best = 1e30, t_def = 1e30;
-      int best_tile = -1;
-      int64_t best_chunk = 0;
-      for (int ti = 0; ti < ntiles && !st; ++ti)
-        for (int ci = 0; ci < 4 && !st; ++ci) {
-          h->batch_tile[p] = tiles[ti];
-          h->batch_chunk[p] = chunks[ci];
-          size_t bb = 0;
-          if ((st = fcfs_batch_workspace_size(h, cl.data(), nb, (fcfs_precision)p, &bb))) break;
-          DevBuf bw;
-          if ((e = hipMalloc(&bw.p, bb))) {
-            st = hip_fail(h, e, "batch workspace");
-            break;
-          }
-          fcfs_plan *plan = nullptr;
-          float ms = 0.f;
-          st = time_min([&]() {
-            return fcfs_forward_batch(h, cl.data(), nb, (fcfs_precision)p, bw.p, bb, &plan);
-          }, &ms);
-          (void)hipStreamSynchronize(h->stream);
-          plan_free(plan);
-          if (st) break;
-          if (tiles[ti] == def_tile && chunks[ci] == def_chunk) t_def = ms;
-          if (ms < best) {
-            best = ms;
-            best_tile = tiles[ti];
-            best_chunk = chunks[ci];
-          }
-        }
-      if (!(best < kMargin * t_def)) {
-        best_tile = def_tile;
-        best_chunk = def_chunk;
-      }
-      h->batch_tile[p] = best_tile;
-      h->batch_chunk[p] = best_chunk;
-    }
+    for (int p = 0; p < 3 && !st; ++p) st = tune_batch_buckets(h, cl.data(), nb, p, reps, e0, e1);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -2829,66 +2941,21 @@ fcfs_status fcfs_autotune_batch(fcfs_handle *h, const fcfs_clip *c, int32_t n, f
   if ((e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1))) return hip_fail(h, e, "events");
   const bool saved_prof = h->prof;
   h->prof = false;
-  const int tiles[3] = {pi == fcfs::kFP32 ? 0 : 3, pi == fcfs::kFP32 ? 1 : 4, 5};
-  const int ntiles = pi == fcfs::kFP32 ? 2 : 3;
-  const int64_t chunks[4] = {8192, 16384, 32768, 65536};
-  h->batch_tile[pi] = -1;
-  h->batch_chunk[pi] = 0;
-  const int def_tile = batch_tile(h, pi);
-  const int64_t def_chunk = batch_chunk(h, pi);
-  double best = 1e30, t_def = 1e30;
-  int best_tile = def_tile;
-  int64_t best_chunk = def_chunk;
-  for (int ti = 0; ti < ntiles && !st; ++ti)
-    for (int ci = 0; ci < 4 && !st; ++ci) {
-      h->batch_tile[pi] = tiles[ti];
-      h->batch_chunk[pi] = chunks[ci];
-      size_t bb = 0;
-      if ((st = fcfs_batch_workspace_size(h, c, n, p, &bb))) break;
-      DevBuf bw;
-      if ((e = hipMalloc(&bw.p, bb))) {
-        st = hip_fail(h, e, "batch workspace");
-        break;
-      }
-      fcfs_plan *plan = nullptr;
-      float bm = 1e30f;
-      st = fcfs_forward_batch(h, c, n, p, bw.p, bb, &plan);  // builds the plan, untimed
-      for (int r = 0; r < reps && !st; ++r) {
-        float ms = 0.f;
-        if ((e = hipEventRecord(e0, h->stream))) st = hip_fail(h, e, "event");
-        if (!st) st = fcfs_forward_batch(h, c, n, p, bw.p, bb, &plan);
-        if (!st && ((e = hipEventRecord(e1, h->stream)) || (e = hipEventSynchronize(e1)) ||
-                    (e = hipEventElapsedTime(&ms, e0, e1))))
-          st = hip_fail(h, e, "event timing");
-        bm = std::min(bm, ms);
-      }
-      (void)hipStreamSynchronize(h->stream);
-      plan_free(plan);
-      if (st) break;
-      if (tiles[ti] == def_tile && chunks[ci] == def_chunk) t_def = bm;
-      if (bm < best) {
-        best = bm;
-        best_tile = tiles[ti];
-        best_chunk = chunks[ci];
-      }
-    }
-  if (!(best < 0.97 * t_def)) {  // the built-in choice unless clearly slower
-    best_tile = def_tile;
-    best_chunk = def_chunk;
-  }
-  h->batch_tile[pi] = best_tile;
-  h->batch_chunk[pi] = best_chunk;
+  st = tune_batch_buckets(h, c, n, pi, reps, e0, e1);
   h->prof = saved_prof;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return st;
 }
 
-fcfs_status fcfs_batch_choice(fcfs_handle *h, fcfs_precision p, int32_t *tile, int64_t *chunk) {
+fcfs_status fcfs_batch_choice(fcfs_handle *h, fcfs_precision p, int32_t kbucket, int32_t *tile,
+                              int64_t *chunk) {
   if (!h) return fail(nullptr, FCFS_ERR_INVALID_ARG, "handle is NULL");
   if ((int)p < 0 || (int)p > 2) return fail(h, FCFS_ERR_INVALID_ARG, "unknown precision");
-  if (tile) *tile = batch_tile(h, (int)p);
-  if (chunk) *chunk = batch_chunk(h, (int)p);
+  if (kbucket < 0 || kbucket >= fcfs::kBatchKBuckets)
+    return fail(h, FCFS_ERR_INVALID_ARG, "kbucket out of range");
+  if (tile) *tile = batch_tile(h, (int)p, kbucket);
+  if (chunk) *chunk = batch_chunk(h, (int)p, kbucket);
   return FCFS_OK;
 }
 

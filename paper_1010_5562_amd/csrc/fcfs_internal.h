@@ -414,19 +414,36 @@ struct BatchClip {
   int direct;  // one split: the contraction writes F itself (no partials)
 };
 
+// K bucket of a batch clip, max(K, L) <= 63, 127, 255, 511 or larger: the
+// batch takes its contraction tile variant and corners per work item per
+// bucket.  Clips whose buckets share a variant share one persistent launch.
+constexpr int kBatchKBuckets = 5;
+__host__ __device__ inline int batch_kbucket(int K, int L) {
+  const int m = K > L ? K : L;
+  return m <= 63 ? 0 : (m <= 127 ? 1 : (m <= 255 ? 2 : (m <= 511 ? 3 : 4)));
+}
+constexpr int kBatchMaxGroups = 8;
+
 struct BatchLaunch {
   int n_clips;
-  int prec, tile;           // tile variant of the persistent contraction
+  int prec;
   const BatchClip *clips;   // device
   int pre_blocks;           // pre-pass blocks per clip
   const int4 *side_desc;    // device: (clip, 0 = histogram | 1 = guard, block) per side block
   int n_side;
   const int4 *ax_desc;      // device: (clip, frequency block, bin chunk) per axis block
   int n_ax;
-  const int4 *items;        // device: (clip, tile, split) per work item, LPT order
+  // device: (clip, tile, split) per work item, grouped by tile variant and in
+  // LPT order within a group; group g (variant group_tile[g]) holds the items
+  // [group_off[g], group_off[g + 1]) and runs as one persistent launch
+  const int4 *items;
   int n_items;
-  int grid;                 // persistent workgroups
-  unsigned int *counter;    // device work counters: [0] the plan's precision, [1] routed clips
+  int n_groups;
+  int group_tile[kBatchMaxGroups];
+  int group_off[kBatchMaxGroups + 1];
+  // device work counters: [g] group g's pass, [n_groups + g] its pass over the
+  // routed clips, [2 n_groups] set when some clip is routed to split-fp16
+  unsigned int *counter;
   unsigned int *route;      // device: per clip 1 if routed to split-fp16 (split-bf16 plans)
   const int *epi_off;       // device: prefix of epilogue blocks per clip [n+1]
   int n_epi;

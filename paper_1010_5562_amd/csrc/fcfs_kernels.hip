@@ -1552,10 +1552,9 @@ hipError_t launch_debug_phases(const FwdPlan &p, const uint4 *packed, int axis, 
 // counter until the list is exhausted.  The counter is reset by a kernel at
 // the head of the sequence, so a captured graph can be replayed.
 // ===========================================================================
-// counter[0], counter[1]: work counters of the two passes; counter[2]: set
-// when some clip is routed to split-fp16 (the second pass exits otherwise)
-__global__ void k_batch_reset(unsigned int *counter) {
-  if (threadIdx.x < 3 && blockIdx.x == 0) counter[threadIdx.x] = 0u;
+// The work counters of the passes and the routed-clip flag (BatchLaunch).
+__global__ void k_batch_reset(unsigned int *counter, int n) {
+  if ((int)threadIdx.x < n && blockIdx.x == 0) counter[threadIdx.x] = 0u;
 }
 
 __global__ __launch_bounds__(256) void k_batch_prepass(const BatchClip *__restrict__ clips) {
@@ -1790,11 +1789,11 @@ hipError_t launch_gbatch_epilogue(const GBatchLaunch &b, hipStream_t st) {
 }
 
 hipError_t launch_batch_prepass(const BatchLaunch &b, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, b.counter);
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, b.counter, 2 * b.n_groups + 1);
   hipLaunchKernelGGL(k_batch_prepass, dim3(b.pre_blocks, b.n_clips), dim3(256), 0, st, b.clips);
   if (b.prec == kBF16 && b.route && b.n_clips > 0)
     hipLaunchKernelGGL(k_batch_route, dim3(b.n_clips), dim3(256), 0, st, b.clips, b.pre_blocks,
-                       b.route, b.counter + 2);
+                       b.route, b.counter + 2 * b.n_groups);
   return hipGetLastError();
 }
 
@@ -1812,54 +1811,61 @@ int batch_grid(int tile, int prec) {
   return tile_variant(tile).wg_per_cu * 256;  // persistent workgroups on 256 CUs
 }
 
-// One persistent pass over the work list in precision prec (want: the route
-// value of the clips it takes, or all clips when route is nullptr).
-// any: when given, the pass exits at once unless *any is set.
-static void batch_pass(const BatchLaunch &b, const Tables &t, int prec, const unsigned int *route,
-                       unsigned int want, unsigned int *counter, hipStream_t st,
-                       const unsigned int *any = nullptr) {
-  const dim3 grid(b.grid), block(256);
-  const bool wide = tile_variant(b.tile).wk == 64;
+// One persistent pass over items [0, n) in precision prec with tile variant
+// `tile` (want: the route value of the clips it takes, or all clips when route
+// is nullptr).  any: when given, the pass exits at once unless *any is set.
+static void batch_pass(const BatchLaunch &b, const Tables &t, int prec, int tile,
+                       const int4 *items, int n, const unsigned int *route, unsigned int want,
+                       unsigned int *counter, hipStream_t st, const unsigned int *any = nullptr) {
+  const dim3 grid(batch_grid(tile, prec)), block(256);
+  const bool wide = tile_variant(tile).wk == 64;
   const uint2 *tab = prec == kBF16 ? t.wbf16 : t.wfp16;
   if (prec == kFP32) {
     if (wide)
-      hipLaunchKernelGGL((k_batch_contract_fp32<2, 1>), grid, block, 0, st, b.clips, b.items,
-                         b.n_items, counter, t.w32);
+      hipLaunchKernelGGL((k_batch_contract_fp32<2, 1>), grid, block, 0, st, b.clips, items, n,
+                         counter, t.w32);
     else
-      hipLaunchKernelGGL((k_batch_contract_fp32<1, 1>), grid, block, 0, st, b.clips, b.items,
-                         b.n_items, counter, t.w32);
-  } else if (b.tile == 5) {
+      hipLaunchKernelGGL((k_batch_contract_fp32<1, 1>), grid, block, 0, st, b.clips, items, n,
+                         counter, t.w32);
+  } else if (tile == 5) {
     if (prec == kBF16)
-      hipLaunchKernelGGL(k_batch_contract_pipe<kBF16>, grid, block, 0, st, b.clips, b.items,
-                         b.n_items, counter, tab, route, want, any);
+      hipLaunchKernelGGL(k_batch_contract_pipe<kBF16>, grid, block, 0, st, b.clips, items, n,
+                         counter, tab, route, want, any);
     else
-      hipLaunchKernelGGL(k_batch_contract_pipe<kFP16>, grid, block, 0, st, b.clips, b.items,
-                         b.n_items, counter, tab, route, want, any);
+      hipLaunchKernelGGL(k_batch_contract_pipe<kFP16>, grid, block, 0, st, b.clips, items, n,
+                         counter, tab, route, want, any);
   } else if (prec == kBF16) {
     if (wide)
-      hipLaunchKernelGGL((k_batch_contract<kBF16, 2, 1>), grid, block, 0, st, b.clips, b.items,
-                         b.n_items, counter, tab, route, want, any);
+      hipLaunchKernelGGL((k_batch_contract<kBF16, 2, 1>), grid, block, 0, st, b.clips, items, n,
+                         counter, tab, route, want, any);
     else
-      hipLaunchKernelGGL((k_batch_contract<kBF16, 1, 1>), grid, block, 0, st, b.clips, b.items,
-                         b.n_items, counter, tab, route, want, any);
+      hipLaunchKernelGGL((k_batch_contract<kBF16, 1, 1>), grid, block, 0, st, b.clips, items, n,
+                         counter, tab, route, want, any);
   } else {
     if (wide)
-      hipLaunchKernelGGL((k_batch_contract<kFP16, 2, 1>), grid, block, 0, st, b.clips, b.items,
-                         b.n_items, counter, tab, route, want, any);
+      hipLaunchKernelGGL((k_batch_contract<kFP16, 2, 1>), grid, block, 0, st, b.clips, items, n,
+                         counter, tab, route, want, any);
     else
-      hipLaunchKernelGGL((k_batch_contract<kFP16, 1, 1>), grid, block, 0, st, b.clips, b.items,
-                         b.n_items, counter, tab, route, want, any);
+      hipLaunchKernelGGL((k_batch_contract<kFP16, 1, 1>), grid, block, 0, st, b.clips, items, n,
+                         counter, tab, route, want, any);
   }
 }
 
 hipError_t launch_batch_contract(const BatchLaunch &b, const Tables &t, hipStream_t st) {
-  if (b.n_items == 0) return hipSuccess;
-  if (b.prec == kBF16 && b.route) {
-    // split-bf16: the clips the rounding model keeps in bf16, then the routed ones
-    batch_pass(b, t, kBF16, b.route, 0u, b.counter, st);
-    batch_pass(b, t, kFP16, b.route, 1u, b.counter + 1, st, b.counter + 2);
-  } else {
-    batch_pass(b, t, b.prec, nullptr, 0u, b.counter, st);
+  const int G = b.n_groups;
+  for (int g = 0; g < G; ++g) {
+    const int n = b.group_off[g + 1] - b.group_off[g];
+    if (n == 0) continue;
+    const int4 *items = b.items + b.group_off[g];
+    const int tile = b.group_tile[g];
+    if (b.prec == kBF16 && b.route) {
+      // split-bf16: the clips the rounding model keeps in bf16, then the routed ones
+      batch_pass(b, t, kBF16, tile, items, n, b.route, 0u, b.counter + g, st);
+      batch_pass(b, t, kFP16, tile, items, n, b.route, 1u, b.counter + G + g, st,
+                 b.counter + 2 * G);
+    } else {
+      batch_pass(b, t, b.prec, tile, items, n, nullptr, 0u, b.counter + g, st);
+    }
   }
   return hipGetLastError();
 }

@@ -180,13 +180,49 @@ def test_batch_autotuner_on_its_clips(P):
     args = _as_args(P, clips)
     h = P.Handle()
     b = P.Batch(args, precision="bf16", handle=h, tune=True)
-    tile, chunk = b.choice
-    assert tile in (3, 4, 5) and chunk in (8192, 16384, 32768, 65536)
+    assert set(b.choice) == {P.batch_kbucket(a[4], a[5]) for a in args}
+    for tile, chunk in b.choice.values():
+        assert tile in (3, 4, 5) and chunk in (8192, 16384, 32768, 65536)
     F = [f.cpu().numpy().copy() for f in b.run()]
     for i, (x, y, s, T, K, L) in enumerate(args):
         Fs, _ = P.forward(x, y, s, T, K, L, precision="bf16", handle=h)
         d = np.max(np.abs(Fs.cpu().numpy() - F[i])) / abs(F[i][K, L])
         assert d <= 2e-6, (i, d)
+    b.close()
+
+
+def test_batch_per_bucket_variants(P, oracle_lib, tmp_path):
+    # per-K-bucket choices from a cache file: K <= 63 on the two-wave variant 3
+    # with small work items, K <= 511 on the pipelined variant 5, K <= 255 on
+    # variant 4: three persistent launches in one plan; every clip matches the
+    # single-clip forward and the oracle, replays repeat the first run
+    cache = {"format": "fcfs-autotune-1", "forward": [], "batch": [
+        {"prec": 1, "kbucket": 0, "tile": 3, "chunk": 8192},
+        {"prec": 1, "kbucket": 2, "tile": 4, "chunk": 32768},
+        {"prec": 1, "kbucket": 3, "tile": 5, "chunk": 16384}]}
+    path = tmp_path / "buckets.json"
+    path.write_text(json.dumps(cache))
+    h = P.Handle()
+    P.load_tune(path, handle=h)
+    specs = [(1024, 63, 3000), (8192, 511, 9000), (4096, 255, 20000), (1024, 63, 25000),
+             (8192, 511, 1500)]
+    clips = [synth.clip(400 + i, T, K, min_vertices=V) for i, (T, K, V) in enumerate(specs)]
+    args = _as_args(P, clips)
+    b = P.Batch(args, precision="bf16", handle=h)
+    assert b.choice == {0: (3, 8192), 2: (4, 32768), 3: (5, 16384)}
+    F1 = [f.cpu().numpy().copy() for f in b.run()]
+    F2 = [f.cpu().numpy().copy() for f in b.run()]
+    for i, (x, y, s, T, K, L) in enumerate(args):
+        assert np.array_equal(F1[i], F2[i]), i
+        Fs, _ = P.forward(x, y, s, T, K, L, precision="bf16", handle=h)
+        d = np.max(np.abs(Fs.cpu().numpy() - F1[i])) / abs(F1[i][K, L])
+        assert d <= 2e-6, (i, d)
+        c = clips[i]
+        kk, ll = _sample(K, 40, i)
+        ref = oracle_lib.cfs_points(c.xy, c.off, T, kk, ll)
+        f00 = abs(oracle_lib.cfs_points(c.xy, c.off, T, [0], [0])[0])
+        e = float(np.max(np.abs(F1[i][kk + K, ll + L] - ref)) / f00)
+        assert e <= TOL["bf16"], (i, e)
     b.close()
 
 
