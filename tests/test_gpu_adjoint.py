@@ -211,8 +211,11 @@ def test_pupil_loss_in_the_optimisation_step(P):
 
 
 @pytest.mark.skip(reason="capturing the autograd step with torch.cuda.graph ended in a "
-                         "segmentation fault inside the HIP runtime at capture end; the cause "
-                         "is not identified, so the case stays off the GPU")
+                         "segmentation fault inside the HIP runtime at capture end (cause not "
+                         "identified); the library now refuses a stream the caller is capturing "
+                         "(FCFS_ERR_UNSUPPORTED, test_gpu_boundary.py::"
+                         "test_external_capture_is_refused) and captures the step itself "
+                         "(fcfs_pupil_step_plan, tested replay by replay)")
 def test_optimisation_step_in_a_graph(P):
     # The whole step (edge offsets -> low-pass forward -> fused loss ->
     # adjoint -> edge gradient) captured once in a graph and replayed: every
