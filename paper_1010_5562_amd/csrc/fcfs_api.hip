@@ -1839,7 +1839,7 @@ fcfs_status fcfs_pupil_step_plan(fcfs_handle *h, const int32_t *base_x, const in
 // Batch of general-tile forwards: one workspace slice per clip and one graph.
 // Split-precision batches whose clips all fit the batch kernels run one launch
 // per step over every clip (GBatchLaunch): the split counts are chosen for the
-// whole batch (about two work items per compute unit, at least
+// whole batch (about one work item per compute unit, at least
 // kGBatchItemMin corners each) and the items are dispatched longest first.
 // Other batches capture every clip's single-clip launches in sequence.
 // ---------------------------------------------------------------------------
@@ -1847,7 +1847,7 @@ fcfs_status fcfs_pupil_step_plan(fcfs_handle *h, const int32_t *base_x, const in
 
 namespace {
 constexpr int64_t kGBatchItemMin = 256;
-constexpr int64_t kGBatchItems = 2 * kCUs;
+constexpr int64_t kGBatchItems = kCUs;
 
 struct GBatchLayout {
   bool flat = false;
