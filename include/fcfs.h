@@ -351,14 +351,17 @@ typedef struct {
                                split a cell) and cell-corner pairs, or NULL    */
 } fcfs_haar_clip;
 
-/* Workspace of fcfs_haar (depends on M only: control words, per-polygon task
- * counts and the task list of large polygons split over several waves; about
- * 4 M + 8 max(M, 4096) bytes), 256-byte aligned.  FCFS_ERR_UNSUPPORTED /
- * FCFS_ERR_INVALID_ARG for sizes outside the limits. */
+/* Workspace of fcfs_haar (depends on M only: control words, 64 copies of the
+ * 64 x 64 int64 block of the levels j < 6 (2 MiB; the waves add into their
+ * own copy instead of all into the same few entries), per-polygon task counts
+ * and the task list of large polygons split over several waves; about
+ * 2 MiB + 4 M + 8 max(M, 4096) bytes), 256-byte aligned.
+ * FCFS_ERR_UNSUPPORTED / FCFS_ERR_INVALID_ARG for sizes outside the limits. */
 fcfs_status fcfs_haar_workspace_size(const fcfs_haar_clip *c, size_t *bytes);
 /* Enqueues the transform on the handle's stream: clears U (a fill kernel),
- * walks every polygon's quadtree (one wave per polygon), then scales U into
- * W when W is not NULL.  Calls that overlap on one workspace race. */
+ * walks every polygon's quadtree (one wave per polygon), then adds the coarse
+ * copies into U and scales U into W when W is not NULL.  Calls that overlap
+ * on one workspace race. */
 fcfs_status fcfs_haar(fcfs_handle *h, const fcfs_haar_clip *c, void *ws, size_t ws_bytes);
 
 /* Adjoint of fcfs_forward with respect to the corner coordinates (the

@@ -1449,7 +1449,7 @@ fcfs_status fcfs_haar(fcfs_handle *h, const fcfs_haar_clip *c, void *ws, size_t 
   }
   {
     ProfScope ps(h, kProfEpilogue);
-    if ((e = fcfs::launch_haar_scale(a, h->stream))) return hip_fail(h, e, "PCHT scale launch");
+    if ((e = fcfs::launch_haar_scale(a, ws, h->stream))) return hip_fail(h, e, "PCHT scale launch");
   }
   return FCFS_OK;
 }

@@ -23,8 +23,8 @@
 // All area arithmetic is 32-bit with wraparound: every true area is below
 // 2^26 (Nx, Ny <= 8192), so the wrapped sums are exact.
 //
-// Mapping: one wave per task (a dynamic task counter; a task is a polygon or,
-// for a large polygon, a share of its subtrees).  The polygon's horizontal
+// Mapping: one wave per task (a polygon or, for a large polygon, a share of
+// its subtrees), tasks dealt round-robin over the waves.  The polygon's horizontal
 // edges are staged in LDS (a negative strip with its ends swapped, so that
 // its width is negative and one signed multiply-add loop serves both) and
 // read as broadcasts.  All cells of the coarse
@@ -33,7 +33,11 @@
 // children); below that a LIFO stack of cell codes in LDS is popped 64 at a
 // time (one cell per lane).  Coefficients go to the caller's int64 pyramid
 // with 64-bit atomic adds (integers: the result does not depend on the
-// order), then one pass scales them to doubles.
+// order).  The levels below kHaarCoarse, which nearly every polygon meets, and
+// the scaling coefficient would make every wave add into the same few
+// entries; their sums go to kHaarReplicas copies of the coarse block instead
+// (copy chosen by the workgroup, area summed per wave first), and the last
+// pass adds the copies into U beside scaling U to doubles.
 #include "fcfs_internal.h"
 
 namespace fcfs {
@@ -52,6 +56,15 @@ constexpr int kHaarStage = kHaarStageCorners;
 // Workgroups of one wave; at 20 KB of LDS each, eight fit on a CU.
 constexpr int kHaarWgPerCU = 8;
 constexpr int kCUs = 256;
+// Levels j < kHaarCoarse (the pyramid's top-left kHaarCoarseSide square,
+// scaling coefficient included) are summed in kHaarReplicas copies of that
+// square in the workspace.
+constexpr int kHaarCoarse = 6;
+constexpr int kHaarCoarseSide = 1 << kHaarCoarse;
+constexpr int kHaarCoarseN = kHaarCoarseSide * kHaarCoarseSide;
+constexpr int kHaarReplicas = 64;
+constexpr size_t kHaarRepBytes = sizeof(unsigned long long) * kHaarCoarseN * kHaarReplicas;
+static_assert(kHaarReplicas == 64, "the fold splits the copies eight ways, eight each");
 
 static_assert(kHaarStack >= 256 + 192 * kHaarMaxJ, "cell stack too small for the deepest pyramid");
 
@@ -163,10 +176,15 @@ __device__ __forceinline__ void child_areas(const int4 *stg, int ne, int a1, int
   for (; i < ne; ++i) strip(stg[i], a1, mid, a2, b1, my, b2, acc);
 }
 
+// Clears U, the coarse-block copies and the control words.
 __global__ void k_haar_reset(unsigned long long *__restrict__ U, int64_t n,
+                             unsigned long long *__restrict__ rep,
                              unsigned long long *__restrict__ ctl, unsigned long long *__restrict__ stats) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) U[i] = 0ull;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)kHaarCoarseN * kHaarReplicas;
+       i += stride)
+    rep[i] = 0ull;
   if (blockIdx.x == 0 && threadIdx.x < 16) {
     ctl[threadIdx.x] = 0ull;
     if (stats && threadIdx.x < 2) stats[threadIdx.x] = 0ull;
@@ -227,9 +245,11 @@ __global__ void k_haar_plan(const int32_t *__restrict__ x, const int32_t *__rest
   nsplit[m] = n;
 }
 
-// ctl[8..15]: task counters; ctl[1]: set when a stack push had to be dropped
-// (cannot happen within the bound above; kept so that no push can leave LDS);
-// ctl[2]: extra tasks requested by the plan.
+// Task i of the M + extra tasks goes to workgroup i mod gridDim (a static
+// order: one shared task counter served past the per-XCD caches costs more
+// than the imbalance it removes).  ctl[1]: set when a stack push had to be
+// dropped (cannot happen within the bound above; kept so that no push can
+// leave LDS); ctl[2]: extra tasks requested by the plan.
 __global__ __launch_bounds__(64) void k_haar_walk(const int32_t *__restrict__ x,
                                                   const int32_t *__restrict__ y,
                                                   const int8_t *__restrict__ s,
@@ -238,6 +258,7 @@ __global__ __launch_bounds__(64) void k_haar_walk(const int32_t *__restrict__ x,
                                                   const int *__restrict__ nsplit,
                                                   const int2 *__restrict__ extra, int64_t cap,
                                                   unsigned long long *__restrict__ U,
+                                                  unsigned long long *__restrict__ rep,
                                                   unsigned long long *__restrict__ ctl,
                                                   unsigned long long *__restrict__ stats) {
   __shared__ uint32_t stk[kHaarStack];
@@ -246,15 +267,11 @@ __global__ __launch_bounds__(64) void k_haar_walk(const int32_t *__restrict__ x,
   const int64_t side = (int64_t)1 << J;
   const int64_t n_extra = min<int64_t>((int64_t)__atomic_load_n(&ctl[2], __ATOMIC_RELAXED), cap);
   const int64_t n_tasks = M + n_extra;
+  // this workgroup's copy of the coarse block
+  unsigned long long *const crep = rep + (size_t)(blockIdx.x % kHaarReplicas) * kHaarCoarseN;
   unsigned long long n_cells = 0, n_pairs = 0;
-  for (;;) {
-    // eight interleaved counters (task c + 8 k from counter c) spread the
-    // contention of one counter over eight addresses
-    unsigned long long tt = 0;
-    const unsigned c8 = blockIdx.x & 7u;
-    if (lane == 0) tt = c8 + 8ull * atomicAdd(&ctl[8 + c8], 1ull);
-    const int64_t task = (int64_t)__shfl(tt, 0, 64);
-    if (task >= n_tasks) break;
+  int64_t wave_area = 0;  // scaling-coefficient sum of this wave's polygons
+  for (int64_t task = blockIdx.x; task < n_tasks; task += gridDim.x) {
     int64_t m;
     int t;
     if (task < M) {
@@ -293,7 +310,7 @@ __global__ __launch_bounds__(64) void k_haar_walk(const int32_t *__restrict__ x,
       by1 = max(by1, __shfl_xor(by1, o, 64));
     }
     const int64_t area = (int32_t)a;
-    if (lane == 0 && area != 0 && t == 0) atomicAdd(&U[0], (unsigned long long)area);
+    if (t == 0) wave_area += area;
     if (!(J > 0 && area > 0 && area < (int64_t)Nx * Ny)) continue;
     const bool one_pass = K <= kHaarStageCorners;
     int ne = 0;
@@ -380,9 +397,13 @@ __global__ __launch_bounds__(64) void k_haar_walk(const int32_t *__restrict__ x,
         const int hg = A00 + A01 - A10 - A11;
         const int gh = A00 + A10 - A01 - A11;
         const int hh = A00 - A01 - A10 + A11;
-        if (hg) atomicAdd(&U[ky * side + p + kx], (unsigned long long)(int64_t)hg);
-        if (gh) atomicAdd(&U[(p + ky) * side + kx], (unsigned long long)(int64_t)gh);
-        if (hh) atomicAdd(&U[(p + ky) * side + p + kx], (unsigned long long)(int64_t)hh);
+        // level j's entries lie in rows and columns below 2p: levels below
+        // kHaarCoarse stay inside the coarse block
+        unsigned long long *const dst = j < kHaarCoarse ? crep : U;
+        const int64_t row = j < kHaarCoarse ? kHaarCoarseSide : side;
+        if (hg) atomicAdd(&dst[ky * row + p + kx], (unsigned long long)(int64_t)hg);
+        if (gh) atomicAdd(&dst[(p + ky) * row + kx], (unsigned long long)(int64_t)gh);
+        if (hh) atomicAdd(&dst[(p + ky) * row + p + kx], (unsigned long long)(int64_t)hh);
       }
       const int n_mine = __popcll(__ballot(emit && visited));
       n_cells += (unsigned long long)n_mine;
@@ -421,23 +442,60 @@ __global__ __launch_bounds__(64) void k_haar_walk(const int32_t *__restrict__ x,
     }
     wave_sync();
   }
+  if (lane == 0 && wave_area != 0) atomicAdd(&crep[0], (unsigned long long)wave_area);
   if (lane == 0 && stats && n_cells) {
     atomicAdd(&stats[0], n_cells);
     atomicAdd(&stats[1], n_pairs);
   }
 }
 
-// W = U * 2^level / sqrt(Nx Ny); level of pyramid entry (row, col) is
-// floor(log2(max(row, col))) (0 for the scaling coefficient at (0, 0)).
-__global__ void k_haar_scale(const unsigned long long *__restrict__ U, double *__restrict__ W,
-                             int J, double r, int64_t n) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const uint32_t mask = (1u << J) - 1u;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const uint32_t row = (uint32_t)(i >> J), col = (uint32_t)i & mask;
+// Coarse entries per fold block: 256 threads, eight per entry, each summing
+// an eighth of the copies (eight loads in flight), partial sums met in LDS.
+constexpr int kHaarFoldPerBlock = 32;
+
+// Last pass.  Blocks [0, nfold): the entries of the coarse block (rows and
+// columns below cs = min(2^J, kHaarCoarseSide)) summed from the copies into U
+// (and W).  The other blocks, when W is wanted, stream the rest of the
+// pyramid: W = U * 2^level / sqrt(Nx Ny), the level of entry (row, col)
+// being floor(log2(max(row, col))) (0 for the scaling coefficient).
+__global__ __launch_bounds__(256) void k_haar_finish(unsigned long long *__restrict__ U,
+                                                     double *__restrict__ W,
+                                                     const unsigned long long *__restrict__ rep,
+                                                     int J, double r, int64_t n, int nfold) {
+  __shared__ unsigned long long part[256];
+  const uint32_t cs = (uint32_t)min(1 << J, kHaarCoarseSide);
+  auto level = [](uint32_t row, uint32_t col) {
     const uint32_t mx = row > col ? row : col;
-    const int lev = mx ? 31 - __clz(mx) : 0;
-    W[i] = (double)(long long)U[i] * (r * (double)(1u << lev));
+    return mx ? 31 - __clz(mx) : 0;
+  };
+  if ((int)blockIdx.x < nfold) {
+    const uint32_t k = threadIdx.x % kHaarFoldPerBlock, sub = threadIdx.x / kHaarFoldPerBlock;
+    const uint32_t i = blockIdx.x * kHaarFoldPerBlock + k;
+    const bool live = i < cs * cs;
+    const uint32_t row = live ? i / cs : 0u, col = live ? i - row * cs : 0u;
+    const int e = (int)(row * kHaarCoarseSide + col);
+    unsigned long long w[8];
+    constexpr int per = kHaarReplicas / 8;
+#pragma unroll
+    for (int u = 0; u < per; ++u) w[u] = live ? rep[(size_t)(sub * per + u) * kHaarCoarseN + e] : 0ull;
+    part[threadIdx.x] = ((w[0] + w[1]) + (w[2] + w[3])) + ((w[4] + w[5]) + (w[6] + w[7]));
+    __syncthreads();
+    if (sub == 0 && live) {
+      unsigned long long v = 0ull;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v += part[q * kHaarFoldPerBlock + k];
+      const int64_t at = ((int64_t)row << J) + col;
+      U[at] = v;
+      if (W) W[at] = (double)(long long)v * (r * (double)(1u << level(row, col)));
+    }
+    return;
+  }
+  const int64_t stride = (int64_t)(gridDim.x - nfold) * blockDim.x;
+  const uint32_t mask = (1u << J) - 1u;
+  for (int64_t i = (int64_t)(blockIdx.x - nfold) * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const uint32_t row = (uint32_t)(i >> J), col = (uint32_t)i & mask;
+    if (row < cs && col < cs) continue;
+    W[i] = (double)(long long)U[i] * (r * (double)(1u << level(row, col)));
   }
 }
 
@@ -451,21 +509,27 @@ int haar_split_level(int Nx, int Ny, int J) {
 
 size_t haar_workspace_bytes(int64_t M) {
   const int64_t cap = std::max<int64_t>(M, 4096);
-  return 256 + ((sizeof(int) * (size_t)M + 255) & ~(size_t)255) + sizeof(int2) * (size_t)cap;
+  return 256 + kHaarRepBytes + ((sizeof(int) * (size_t)M + 255) & ~(size_t)255) +
+         sizeof(int2) * (size_t)cap;
 }
 
 namespace {
+// Workspace layout: control words (256 bytes), the coarse-block copies, task
+// counts per polygon, the extra-task list.
 struct HaarWs {
   unsigned long long *ctl;
+  unsigned long long *rep;
   int *nsplit;
   int2 *extra;
   int64_t cap;
 };
 HaarWs haar_ws(const HaarArgs &a, void *ws) {
   HaarWs w;
-  w.ctl = static_cast<unsigned long long *>(ws);
-  w.nsplit = reinterpret_cast<int *>(static_cast<char *>(ws) + 256);
-  w.extra = reinterpret_cast<int2 *>(static_cast<char *>(ws) + 256 +
+  char *b = static_cast<char *>(ws);
+  w.ctl = reinterpret_cast<unsigned long long *>(b);
+  w.rep = reinterpret_cast<unsigned long long *>(b + 256);
+  w.nsplit = reinterpret_cast<int *>(b + 256 + kHaarRepBytes);
+  w.extra = reinterpret_cast<int2 *>(b + 256 + kHaarRepBytes +
                                      ((sizeof(int) * (size_t)a.M + 255) & ~(size_t)255));
   w.cap = std::max<int64_t>(a.M, 4096);
   return w;
@@ -479,8 +543,8 @@ int pyramid_blocks(int J) {
 hipError_t launch_haar_prep(const HaarArgs &a, void *ws, hipStream_t st) {
   const HaarWs w = haar_ws(a, ws);
   const int64_t n = (int64_t)1 << (2 * a.J);
-  hipLaunchKernelGGL(k_haar_reset, dim3(pyramid_blocks(a.J)), dim3(256), 0, st,
-                     reinterpret_cast<unsigned long long *>(a.U), n, w.ctl,
+  hipLaunchKernelGGL(k_haar_reset, dim3(std::max(pyramid_blocks(a.J), 64)), dim3(256), 0, st,
+                     reinterpret_cast<unsigned long long *>(a.U), n, w.rep, w.ctl,
                      reinterpret_cast<unsigned long long *>(a.stats));
   hipError_t e = hipGetLastError();
   if (e || a.M == 0) return e;
@@ -496,17 +560,20 @@ hipError_t launch_haar_walk(const HaarArgs &a, void *ws, hipStream_t st) {
   const int64_t g = std::min<int64_t>(a.M + w.cap, (int64_t)kCUs * kHaarWgPerCU);
   hipLaunchKernelGGL(k_haar_walk, dim3((unsigned)g), dim3(64), 0, st, a.x, a.y, a.s, a.off, a.M,
                      a.V, a.Nx, a.Ny, a.J, haar_split_level(a.Nx, a.Ny, a.J), w.nsplit, w.extra,
-                     w.cap, reinterpret_cast<unsigned long long *>(a.U), w.ctl,
+                     w.cap, reinterpret_cast<unsigned long long *>(a.U), w.rep, w.ctl,
                      reinterpret_cast<unsigned long long *>(a.stats));
   return hipGetLastError();
 }
 
-hipError_t launch_haar_scale(const HaarArgs &a, hipStream_t st) {
-  if (!a.W) return hipSuccess;
+hipError_t launch_haar_scale(const HaarArgs &a, void *ws, hipStream_t st) {
+  const HaarWs w = haar_ws(a, ws);
+  const int cs = std::min(1 << a.J, kHaarCoarseSide);
+  const int nfold = (cs * cs + kHaarFoldPerBlock - 1) / kHaarFoldPerBlock;
   const int64_t n = (int64_t)1 << (2 * a.J);
   const double r = 1.0 / std::sqrt((double)a.Nx * (double)a.Ny);
-  hipLaunchKernelGGL(k_haar_scale, dim3(pyramid_blocks(a.J)), dim3(256), 0, st,
-                     reinterpret_cast<const unsigned long long *>(a.U), a.W, a.J, r, n);
+  const int g = nfold + (a.W ? pyramid_blocks(a.J) : 0);
+  hipLaunchKernelGGL(k_haar_finish, dim3(g), dim3(256), 0, st,
+                     reinterpret_cast<unsigned long long *>(a.U), a.W, w.rep, a.J, r, n, nfold);
   return hipGetLastError();
 }
 

@@ -548,14 +548,15 @@ struct HaarArgs {
   double *W;             // [4^J] coefficients, or nullptr
   int64_t *stats;        // [2] cells visited, cell-corner pairs; or nullptr
 };
-// Workspace of the Haar launches for M polygons (control words, task counts
-// and the list of extra tasks of split polygons).
+// Workspace of the Haar launches for M polygons (control words, copies of the
+// coarse levels' block, task counts and the list of extra tasks of split
+// polygons).
 size_t haar_workspace_bytes(int64_t M);
 // clears U and the control words, plans the split of large polygons
 hipError_t launch_haar_prep(const HaarArgs &a, void *ws, hipStream_t st);
 // the quadtree walk (coefficients into U)
 hipError_t launch_haar_walk(const HaarArgs &a, void *ws, hipStream_t st);
-// W from U (no-op when W is null)
-hipError_t launch_haar_scale(const HaarArgs &a, hipStream_t st);
+// coarse levels from their copies into U; W from U when W is not null
+hipError_t launch_haar_scale(const HaarArgs &a, void *ws, hipStream_t st);
 
 }  // namespace fcfs

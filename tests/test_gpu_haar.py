@@ -106,6 +106,37 @@ def test_haar_degenerate_sizes(P, oracle_lib):
     assert not U.any() and not W.any() and int(st[0]) == 0
 
 
+@pytest.mark.parametrize("J", [10, 5])
+def test_haar_overlapping_polygons_integer_only_and_repeated(P, oracle_lib, J):
+    # 3,000 overlapping rectangles, some across the tile edge: every wave takes
+    # several polygons and the coarse levels collect thousands of contributions
+    # (summed in per-workgroup copies, then added into U).  Calls without W
+    # (coarse block added by its own launch) and repeated calls on the same
+    # workspace, over a U that holds stale values, give the oracle's sums.
+    rng = np.random.default_rng(12)
+    n, T = 3000, 1024
+    x1, y1 = rng.integers(-40, T, n), rng.integers(-40, T, n)
+    w, h = rng.integers(1, 200, n), rng.integers(1, 200, n)
+    loops = [synth.rectangle_loop(int(a), int(b), int(a + c), int(b + d))
+             for a, b, c, d in zip(x1, y1, w, h)]
+    xy = np.concatenate(loops).astype(np.int32)
+    off = np.concatenate([[0], np.cumsum([lp.shape[0] for lp in loops])]).astype(np.int64)
+    _say(f"haar overlapping rectangles: {n} polygons, {T}x{T}, J={J}")
+    Uo, Wo, nodes = oracle_lib.pcht(xy, off, T, T, J)
+    x, y, s, _, _ = P.loops_to_corners(xy, off)
+    U = torch.full((1 << J, 1 << J), 12345, dtype=torch.int64, device="cuda")
+    for rep in range(2):
+        U2, W2, st = P.haar(x, y, s, off, T, T, J, out_U=U, coefficients=False, stats=True)
+        torch.cuda.synchronize()
+        assert W2 is None
+        assert np.array_equal(U.cpu().numpy(), Uo), f"U only, call {rep}"
+        assert int(st[0].item()) == nodes
+    U3, W3, _ = P.haar(x, y, s, off, T, T, J, out_U=U)
+    torch.cuda.synchronize()
+    assert np.array_equal(U3.cpu().numpy(), Uo)
+    assert np.array_equal(W3.cpu().numpy(), Wo)
+
+
 def test_haar_rejects_bad_sizes(P):
     sq = synth.rectangle_loop(0, 0, 3, 3)
     x, y, s, _, _ = P.loops_to_corners(sq, np.array([0, 4]))
