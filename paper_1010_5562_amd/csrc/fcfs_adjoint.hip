@@ -566,13 +566,26 @@ __global__ __launch_bounds__(256 * RegB<NKS>::CPS, 1) void k_adj_gemm_regb(
     const uint16_t *__restrict__ whi, const uint16_t *__restrict__ wlo,
     const int *__restrict__ scale, int64_t vpad, int lb, float *__restrict__ part) {
   constexpr int CPS = RegB<NKS>::CPS;
-  constexpr int NT = 256 * CPS;
   __shared__ uint2 s_tab[kTabN];
   __shared__ u32x4 s_b[2][NKS][4][64];  // packed corner operands of two tiles
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int li = lane & 31, lh = lane >> 5;
   const int ncb = lb / 8, nchunk = lb / 32;
   const int chunk = blockIdx.y * CPS + (wave >> 2);
+  const int64_t ntiles = vpad / 32;
+  const int64_t t0 = (int64_t)blockIdx.x * ntiles / gridDim.x;
+  const int64_t t1 = (int64_t)(blockIdx.x + 1) * ntiles / gridDim.x;
+  // in the order they are needed (memory waits count in issue order): the
+  // table, the first two corner records, then this wave's block of W, which
+  // only the first products wait for
+  stage_entries_once(s_tab, tab, kTabN);
+  // records of tiles past t1 - 1 are never used: the load is clamped to the
+  // last tile, unconditional (a conditional or selected load would leave the
+  // memory waits of the loop unable to tell the look-ahead load from the
+  // ones it needs); the grid is never wider than the tile count, so t0 < t1
+  auto record = [&](int64_t t) { return packed[min(t, t1 - 1) * 32 + li]; };
+  uint4 c_cur = record(t0);
+  uint4 c_nxt = record(t0 + 1);
   // column block of type wave mod 4 in the wave's chunk (a chunk past the
   // last one of a partial set holds zeros and adds nothing)
   u32x4 wreg[NKS][4];  // cos hi, cos lo, sin hi, sin lo rows of each step
@@ -590,10 +603,6 @@ __global__ __launch_bounds__(256 * RegB<NKS>::CPS, 1) void k_adj_gemm_regb(
       wreg[ks][3] = valid ? *(const u32x4 *)(wlo + rs) : z;
     }
   }
-  for (int i = threadIdx.x; i < kTabN; i += NT) s_tab[i] = tab[i];
-  const int64_t ntiles = vpad / 32;
-  const int64_t t0 = (int64_t)blockIdx.x * ntiles / gridDim.x;
-  const int64_t t1 = (int64_t)(blockIdx.x + 1) * ntiles / gridDim.x;
   const float inv = ldexpf(1.0f, -scale[0]);
   // step `wave` of the corner operands of a tile into buffer buf, from the
   // lane's corner record c (corner li of the tile)
@@ -610,17 +619,17 @@ __global__ __launch_bounds__(256 * RegB<NKS>::CPS, 1) void k_adj_gemm_regb(
     s_b[buf][wave][2][lane] = cl;
     s_b[buf][wave][3][lane] = sl;
   };
-  const uint4 zc = make_uint4(0u, 0u, 0u, 0u);
-  uint4 c_cur = t0 < t1 ? packed[t0 * 32 + li] : zc;
-  uint4 c_nxt = t0 + 1 < t1 ? packed[(t0 + 1) * 32 + li] : zc;
   __syncthreads();  // table staged
-  if (t0 < t1) build(c_cur, 0);
+  build(c_cur, 0);
+  // W and the first records have arrived before the loop: inside it the only
+  // load in flight is the look-ahead record
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // vmcnt(0)
   __syncthreads();
   float *dst = part + (size_t)(4 * CPS * blockIdx.y + wave) * vpad;
   for (int64_t t = t0; t < t1; ++t) {
     const int buf = (int)((t - t0) & 1);
     // the record two tiles ahead is loaded while this tile runs
-    const uint4 c_far = t + 2 < t1 ? packed[(t + 2) * 32 + li] : zc;
+    const uint4 c_far = record(t + 2);
     if (t + 1 < t1) build(c_nxt, buf ^ 1);
     f32x16 acc;
 #pragma unroll

@@ -247,6 +247,35 @@ __device__ __forceinline__ void stage_entries(E *dst, const E *__restrict__ src,
   if ((n & 1) && threadIdx.x == 0) dst[n - 1] = src[n - 1];
 }
 
+// The same for tables of at most 16 entries per thread: every thread's
+// 16-byte loads (at most eight) are in flight before its first LDS write.
+template <typename E>
+__device__ __forceinline__ void stage_entries_once(E *dst, const E *__restrict__ src, int n) {
+  static_assert(sizeof(E) == 8, "8-byte entries");
+  const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
+  uint2 *d = reinterpret_cast<uint2 *>(dst);
+  const int nt = blockDim.x, n2 = n >> 1;
+  if (n2 > 8 * nt) {
+    stage_entries(dst, src, n);
+    return;
+  }
+  uint4 v[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int k = threadIdx.x + u * nt;
+    if (k < n2) v[u] = s4[k];
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int k = threadIdx.x + u * nt;
+    if (k < n2) {
+      d[2 * k] = make_uint2(v[u].x, v[u].y);
+      d[2 * k + 1] = make_uint2(v[u].z, v[u].w);
+    }
+  }
+  if ((n & 1) && threadIdx.x == 0) dst[n - 1] = src[n - 1];
+}
+
 // ---------------------------------------------------------------------------
 // Exact phase reduction of one-level general periods (M <= 8192): (f x) mod M
 // for x < M and a lane-constant frequency f is
