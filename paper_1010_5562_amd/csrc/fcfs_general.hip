@@ -727,8 +727,8 @@ __global__ __launch_bounds__(256, 1) void k_gbatch_contract(const GBatchClip *__
     const int nx = c.nhx + kBigLo, ny = c.nhy + kBigLo;
     float2 *tx = (float2 *)lds;
     float2 *ty = one ? tx : tx + nx;
-    stage_entries(tx, (const float2 *)c.tx, nx);
-    if (!one) stage_entries(ty, (const float2 *)c.ty, ny);
+    stage_entries(tx, (const float2 *)(const void *)c.tx, nx);
+    if (!one) stage_entries(ty, (const float2 *)(const void *)c.ty, ny);
     const uint32_t ybase = one ? 0u : 8u * (uint32_t)nx;
     const uint32_t opa = big_shared_tab_bytes(c.nhx, c.nhy, one);
     char *l = (char *)lds;

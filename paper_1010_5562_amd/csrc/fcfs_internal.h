@@ -395,19 +395,36 @@ hipError_t launch_apply_offsets(const int32_t *bx, const int32_t *by, const int6
 // ---------------------------------------------------------------------------
 // Batched form: one descriptor per clip (device copy), work lists.
 // ---------------------------------------------------------------------------
+
+// A pointer into device global memory, as a descriptor field.  A plain
+// pointer read from memory is generic, so every access through it becomes a
+// flat access, which the hardware counts both as a memory and as an LDS
+// operation: an LDS wait then also waits for those loads.  The global address
+// space in the field's type keeps the accesses global; it converts to and
+// from a plain pointer.
+template <typename T>
+struct gptr {
+  __attribute__((address_space(1))) T *p;
+  __host__ __device__ operator T *() const { return (T *)p; }
+  __host__ __device__ gptr &operator=(T *q) {
+    p = (__attribute__((address_space(1))) T *)q;
+    return *this;
+  }
+};
+
 struct BatchClip {
-  const int32_t *x, *y;
-  const int8_t *s;
-  float2 *F;
-  int64_t *area;
-  uint4 *packed;
-  unsigned long long *area_part;
-  double2 *axis_part;
-  float *part;
-  double *gpart;        // guard partials [chunk][slot][16 x 16]
-  unsigned int *gspan;  // guard span chosen by the side kernel
+  gptr<const int32_t> x, y;
+  gptr<const int8_t> s;
+  gptr<float2> F;
+  gptr<int64_t> area;
+  gptr<uint4> packed;
+  gptr<unsigned long long> area_part;
+  gptr<double2> axis_part;
+  gptr<float> part;
+  gptr<double> gpart;        // guard partials [chunk][slot][16 x 16]
+  gptr<unsigned int> gspan;  // guard span chosen by the side kernel
   double gscale, gscale_alt;
-  unsigned long long *hist;
+  gptr<unsigned long long> hist;
   int64_t V, vpad, chunk, g_chunk;
   int T, shift, K, L, kp, lp, tiles_l, nsplit;
   int ax_fb_k, ax_chunks, g_chunks, hist_blocks;
@@ -458,20 +475,20 @@ struct BatchLaunch {
 // clip keeps the workspace layout of a single-clip plan, with the split count
 // chosen for the whole batch.
 struct GBatchClip {
-  const int32_t *x, *y;
-  const int8_t *s;
-  float2 *F;
-  int64_t *area;
-  uint4 *packed;
-  uint4 *words;                // two-level clips: corner words (big_word), else nullptr
-  unsigned long long *area_part, *hist;
-  double2 *axis_part;
-  float *part;
-  double *gpart;
-  unsigned int *gspan;
-  const void *tx, *ty;         // split operand tables (uint2), two-level: FP32 pairs (float2)
-  const void *tx16, *ty16;     // split-fp16 tables of a one-level split-bf16 clip (routing)
-  const double2 *w64x, *w64y;  // FP64 tables, one- or two-level (axis sums and guard region)
+  gptr<const int32_t> x, y;
+  gptr<const int8_t> s;
+  gptr<float2> F;
+  gptr<int64_t> area;
+  gptr<uint4> packed;
+  gptr<uint4> words;                // two-level clips: corner words (big_word), else null
+  gptr<unsigned long long> area_part, hist;
+  gptr<double2> axis_part;
+  gptr<float> part;
+  gptr<double> gpart;
+  gptr<unsigned int> gspan;
+  gptr<const void> tx, ty;          // split operand tables (uint2), two-level: FP32 pairs (float2)
+  gptr<const void> tx16, ty16;      // split-fp16 tables of a one-level split-bf16 clip (routing)
+  gptr<const double2> w64x, w64y;   // FP64 tables, one- or two-level (axis sums and guard region)
   double gscale, gscale_alt;
   double eg, eax, eay, edc;    // alpha factors of the output grid
   int64_t V, vpad, chunk, g_chunk, ax_chunk;
