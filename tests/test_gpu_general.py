@@ -482,3 +482,57 @@ def test_general_batch_graph(P, oracle_lib):
         for i in range(len(clips)):
             assert np.array_equal(b.F[i].cpu().numpy(), eager[i]), i
     b.close()
+
+
+def test_general_batch_many_periods_and_rewritten_corners(P, oracle_lib):
+    # 20 clips with 40 distinct periods, more than the handle keeps in its
+    # table cache (the plan pins its own); a single call on yet another period
+    # afterwards has to build its table beside the pinned ones.  Then the
+    # corners of every clip are shifted in place (same corner count) and the
+    # replay, which reads the current corner contents, is checked against
+    # single calls on the shifted corners and, for three clips, the oracle.
+    specs = []
+    for i in range(20):
+        Nx, Ny = 200 + 37 * i, 310 + 23 * i
+        specs.append((Nx, Ny, i % 3, 20, 18, 12, 600 + i))
+    clips, data = [], []
+    for Nx, Ny, F, K, L, npol, seed in specs:
+        X, off = _fine_grid_clip(seed, Nx, Ny, F, K, L, npol)
+        x, y, s, _, _ = P.loops_to_corners(X, off)
+        clips.append((x, y, s, Nx, Ny, K, L, F))
+        data.append((X, off))
+    _say(f"general batch of {len(clips)} clips, {2 * len(clips)} distinct periods")
+    b = P.GeneralBatch(clips, precision="bf16")
+    torch.cuda.synchronize()
+    Fo, _ = _gpu(P, *_fine_grid_clip(700, 333, 444, 1, 20, 18, 12), 333, 444, 20, 18, 1, "bf16")
+    assert np.isfinite(Fo).all()
+    for i, (Nx, Ny, F, K, L, npol, seed) in enumerate(specs):
+        X, off = data[i]
+        ref, area = oracle_lib.cfs_grid_general(X.astype(np.float64) / 2 ** F, off, Nx, Ny, K, L,
+                                                frac_bits=F)
+        e = float(np.max(np.abs(b.F[i].cpu().numpy().astype(np.complex128) - ref)) / abs(ref[K, L]))
+        assert e <= TOL["bf16"], (i, e)
+        assert int(b.area[i].item()) == area
+    # shift every clip by its own grid step (corners keep their count)
+    for i, (x, y, s) in enumerate(b.corners):
+        x.add_(3 + i)
+        y.sub_(5 + 2 * i)
+    b.run()
+    torch.cuda.synchronize()
+    for i, (x, y, s) in enumerate(b.corners):
+        Nx, Ny, F, K, L, npol, seed = specs[i]
+        Fs, a = P.forward_general(x, y, s, Nx, Ny, K, L, frac_bits=F, precision="bf16")
+        torch.cuda.synchronize()
+        Fs = Fs.cpu().numpy().astype(np.complex128)
+        d = float(np.max(np.abs(Fs - b.F[i].cpu().numpy())) / abs(Fs[K, L]))
+        assert d <= TOL["bf16"], (i, d)
+        assert int(b.area[i].item()) == int(a.item())
+        if i in (0, 7, 19):
+            X, off = data[i]
+            Xs = X.astype(np.float64) + np.array([3 + i, -(5 + 2 * i)], dtype=np.float64)
+            ref, area = oracle_lib.cfs_grid_general(Xs / 2 ** F, off, Nx, Ny, K, L, frac_bits=F)
+            e = float(np.max(np.abs(b.F[i].cpu().numpy().astype(np.complex128) - ref))
+                      / abs(ref[K, L]))
+            assert e <= TOL["bf16"], (i, e)
+            assert int(b.area[i].item()) == area
+    b.close()
