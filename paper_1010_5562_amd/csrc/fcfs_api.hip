@@ -419,9 +419,9 @@ void finish_plan(FwdPlan &q, int64_t tiles, int wg_per_cu, int chunk_mult, bool 
   q.vpad = q.chunk * q.nsplit;
   q.pre_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(q.vpad, 256)));
   q.hist_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(256, ceil_div(V, 1024)));
-  // frequencies per axis block: 256 (DFT of the histograms), 128 (the direct
-  // sums of a two-level plan)
-  const int fpb = q.big ? 128 : 256;
+  // frequencies per axis block: 256 (DFT of the histograms), axis_big_freqs
+  // (the direct sums of a two-level plan)
+  const int fpb = q.big ? fcfs::axis_big_freqs(K, L) : 256;
   q.ax_fb_k = (int)ceil_div(K, fpb);
   q.ax_fb_l = (int)ceil_div(L, fpb);
   // axis partials: bin chunks of the histograms, or corner ranges of the

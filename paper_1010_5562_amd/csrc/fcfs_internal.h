@@ -210,6 +210,13 @@ __host__ __device__ inline uint4 big_word(uint32_t x, uint32_t y, uint32_t Mx, u
                     y | (uint32_t)(py >> 32) << 24 | fl, (uint32_t)py);
 }
 
+// Frequencies per block of the direct axis sums of a two-level plan
+// (k_gen_axis_big): 128, 256 or 512, the smallest that covers max(K, L).
+__host__ __device__ inline int axis_big_freqs(int K, int L) {
+  const int m = K > L ? K : L;
+  return m <= 128 ? 128 : (m <= 256 ? 256 : 512);
+}
+
 // (f x) mod M of the x side (XS) or y side of a corner word.
 template <bool NARROW, bool XS>
 __device__ __forceinline__ uint32_t big_word_phase(uint32_t f, const uint4 &w, uint32_t Mm1,
@@ -249,7 +256,7 @@ struct FwdPlan {
   int64_t vpad;      // nsplit * chunk
   int pre_blocks;    // pre-pass blocks (area partials)
   int hist_blocks;   // histogram blocks of the side kernel
-  int ax_fb_k;       // 256-frequency blocks of the x-axis DFT (two-level: 128)
+  int ax_fb_k;       // 256-frequency blocks of the x-axis DFT (two-level: axis_big_freqs)
   int ax_fb_l;       // and of the y-axis DFT
   int ax_chunks;     // bin chunks of the axis DFTs (partials per frequency)
   int g_chunks;      // corner chunks (blocks) of the FP64 guard region

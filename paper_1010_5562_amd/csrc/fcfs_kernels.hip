@@ -552,82 +552,120 @@ __global__ __launch_bounds__(256) void k_gen_side_big(
 
 // Axis sums (Steps 2 and 3) over the corners directly, for periods past 8192
 // where a histogram over the residues would be too large: block (fb, chunk)
-// takes 128 frequencies f = f0 + 1 + i of one axis against the corners of its
-// range,
+// takes nb = axis_big_freqs(K, L) frequencies f = f0 + 1 + i of one axis
+// against the corners of its range,
 //   Sx[f] += sum_v s_v y_v e^{-j 2 pi f x_v / Mx},  Sy[f] += sum_v s_v x_v e^{-j 2 pi f y_v / My},
-// raw coordinates as the moments.  With i = 16 a + b the twiddle factors as
-// e((f0 + 1 + 16 a) x / M) e(b x / M): per corner the block builds the 8 + 16
-// factors in FP64 (exact phases from the corner words, big_word_phase, and the
-// two-level FP64 tables) in LDS, 64 corners at a time, and each thread then
-// multiplies the two factors of its frequency for 32 of them (threads t and
-// t + 128 split the corners and add up at the end).  The same per-chunk
-// partials as k_gen_axis_dft, reduced by the epilogue.
-constexpr int kAxisBigFreqs = 128;
+// raw coordinates as the moments.  With i = 16 a + b (a < na = nb / 16,
+// b < 16) the twiddle factors as e((f0 + 1 + 16 a) x / M) e(b x / M).  Per
+// step of 64 corners, four threads per corner build its na factors
+// m_v e((f0 + 1 + 16 a) x) and 16 factors e(b x) in FP64 from four table
+// lookups (exact phases of 1, 4 q, 16 and f0 + 1 + 4 na q times x from the
+// corner word, big_word_phase, and the two-level FP64 table) and short
+// products (a factor of e(x) or e(16 x) at most seven times: a few units in
+// the last place).  Thread t then adds the 4 x 4 frequencies of its group
+// t mod na over every (256 / na)-th corner (group t / na), one complex
+// multiply-add each, and the corner groups are added in a fixed order at the
+// end.  The same per-chunk partials as k_gen_axis_dft, reduced by the
+// epilogue.
 constexpr int kAxisBigStep = 64;  // corners per LDS step
+constexpr int kAxisBigLds = 4096;  // double2 entries
+static_assert(kAxisBigStep * 48 <= kAxisBigLds, "factor area");
 template <bool NARROW>
 __device__ __forceinline__ void gen_axis_big_body(
     const int32_t *__restrict__ x, const int32_t *__restrict__ y, const uint4 *__restrict__ words,
     int64_t V, int64_t ax_chunk, const double2 *__restrict__ wx, const double2 *__restrict__ wy,
     int Mx, int My, int nhx, int nhy, int K, int L, int fb_k, double2 *__restrict__ axis_part,
-    int fb, int chunk) {
-  __shared__ double2 fac[kAxisBigStep][24];
-  __shared__ double mom[kAxisBigStep];
-  const int t = threadIdx.x, fi = t & (kAxisBigFreqs - 1), half = t >> 7;
+    int fb, int chunk, double2 *abuf) {
+  // abuf (LDS, kAxisBigLds entries): the factors of a step, [j][32] a side,
+  // then [j][16] b side; at the end the partials of the corner groups,
+  // [group][16 a + b] (256 / na groups of 16 na: always 4096)
+  double2 *fa = abuf, *fbv = abuf + kAxisBigStep * 32;
+  const int nb = axis_big_freqs(K, L), na = nb >> 4, nq = na >> 2, ncg = 256 / na;
+  const int t = threadIdx.x;
   const bool xaxis = fb < fb_k;
-  const int f0 = (xaxis ? fb : fb - fb_k) * kAxisBigFreqs;
-  const int f = f0 + 1 + fi;
+  const int f0 = (xaxis ? fb : fb - fb_k) * nb;
   const int nf = xaxis ? K : L;
   const double2 *W = xaxis ? wx : wy;
   const int nh = xaxis ? nhx : nhy;
   const uint32_t M = (uint32_t)(xaxis ? Mx : My);
   const int64_t v0 = (int64_t)chunk * ax_chunk, v1 = min(V, v0 + ax_chunk);
-  const int a = fi >> 4, b = fi & 15;
-  double re = 0.0, im = 0.0;
+  const int jf = t >> 2, q = t & 3;  // factor stage: corner, quarter
+  const int g = t % na, cg = t / na, a0 = 4 * (g >> 2), b0 = 4 * (g & 3);
+  auto entry = [&](uint32_t f, const uint4 &c) {
+    const uint32_t p = xaxis ? big_word_phase<NARROW, true>(f, c, M - 1u, -(int)M)
+                             : big_word_phase<NARROW, false>(f, c, M - 1u, -(int)M);
+    return big_entry64(W, nh, p);
+  };
+  auto cmul = [](const double2 &u, const double2 &v) {
+    return make_double2(fma(u.x, v.x, -u.y * v.y), fma(u.x, v.y, u.y * v.x));
+  };
+  double accr[4][4], acci[4][4];
+#pragma unroll
+  for (int ia = 0; ia < 4; ++ia)
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib) accr[ia][ib] = acci[ia][ib] = 0.0;
   for (int64_t base = v0; base < v1; base += kAxisBigStep) {
     const int n = (int)min((int64_t)kAxisBigStep, v1 - base);
     __syncthreads();  // the previous step's factors are consumed
-    // factors: slot s < 8: e((f0 + 1 + 16 s) x / M), else e((s - 8) x / M)
-    for (int e = t; e < kAxisBigStep * 24; e += 256) {
-      const int j = e / 24, sl = e - 24 * (e / 24);
-      double2 w = make_double2(0.0, 0.0);
-      if (j < n) {
-        const uint4 c = words[base + j];
-        const uint32_t g = sl < 8 ? (uint32_t)(f0 + 1 + 16 * sl) : (uint32_t)(sl - 8);
-        const uint32_t p = xaxis ? big_word_phase<NARROW, true>(g, c, M - 1u, -(int)M)
-                                 : big_word_phase<NARROW, false>(g, c, M - 1u, -(int)M);
-        w = big_entry64(W, nh, p);
-      }
-      fac[j][sl] = w;
-    }
-    if (t < kAxisBigStep) {
+    {
+      double2 e1 = make_double2(0.0, 0.0), eb = e1, e16 = e1, ea = e1;
       double m = 0.0;
-      if (t < n) {
-        const int64_t v = base + t;
+      if (jf < n) {
+        const int64_t v = base + jf;
+        const uint4 c = words[v];
+        e1 = entry(1u, c);
+        eb = q ? entry(4u * (uint32_t)q, c) : make_double2(1.0, 0.0);
+        e16 = entry(16u, c);
+        ea = entry((uint32_t)(f0 + 1 + 16 * nq * q), c);
         const double r = (double)(xaxis ? y[v] : x[v]);
-        m = (words[v].z >> 30) & 1u ? -r : r;
+        m = (c.z >> 30) & 1u ? -r : r;
       }
-      mom[t] = m;
+      double2 w = eb;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        fbv[jf * 16 + 4 * q + i] = w;
+        w = cmul(w, e1);
+      }
+      w = make_double2(m * ea.x, m * ea.y);
+      for (int i = 0; i < nq; ++i) {
+        fa[jf * 32 + nq * q + i] = w;
+        w = cmul(w, e16);
+      }
     }
     __syncthreads();
-    if (f <= nf) {
-      const int j0 = half * (kAxisBigStep / 2);
-#pragma unroll 4
-      for (int j = j0; j < j0 + kAxisBigStep / 2; ++j) {
-        const double2 p = fac[j][a], q = fac[j][8 + b];
-        const double wr = p.x * q.x - p.y * q.y, wi = p.x * q.y + p.y * q.x;
-        re = fma(mom[j], wr, re);
-        im = fma(-mom[j], wi, im);
+    for (int j = cg; j < n; j += ncg) {
+      double2 A[4], B[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        A[i] = fa[j * 32 + a0 + i];
+        B[i] = fbv[j * 16 + b0 + i];
       }
+#pragma unroll
+      for (int ia = 0; ia < 4; ++ia)
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) {
+          accr[ia][ib] = fma(A[ia].x, B[ib].x, fma(-A[ia].y, B[ib].y, accr[ia][ib]));
+          acci[ia][ib] = fma(A[ia].x, B[ib].y, fma(A[ia].y, B[ib].x, acci[ia][ib]));
+        }
     }
   }
   __syncthreads();
-  double2 *red = &fac[0][0];  // reused once the last step is consumed
-  if (half) red[fi] = make_double2(re, im);
+#pragma unroll
+  for (int ia = 0; ia < 4; ++ia)
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib)
+      abuf[cg * nb + 16 * (a0 + ia) + b0 + ib] = make_double2(accr[ia][ib], acci[ia][ib]);
   __syncthreads();
-  if (!half && f <= nf) {
-    const double2 o = red[fi];
-    axis_part[(size_t)chunk * (K + L) + (xaxis ? f - 1 : K + f - 1)] =
-        make_double2(re + o.x, im + o.y);
+  for (int fl = t; fl < nb; fl += 256) {
+    const int f = f0 + 1 + fl;
+    if (f > nf) continue;
+    double re = 0.0, im = 0.0;
+    for (int k = 0; k < ncg; ++k) {
+      re += abuf[k * nb + fl].x;
+      im += abuf[k * nb + fl].y;
+    }
+    // W holds e^{+j theta}: the sum wanted is the conjugate
+    axis_part[(size_t)chunk * (K + L) + (xaxis ? f - 1 : K + f - 1)] = make_double2(re, -im);
   }
 }
 
@@ -635,12 +673,13 @@ __global__ __launch_bounds__(256) void k_gen_axis_big(
     const int32_t *__restrict__ x, const int32_t *__restrict__ y, const uint4 *__restrict__ words,
     int64_t V, int64_t ax_chunk, const double2 *__restrict__ wx, const double2 *__restrict__ wy,
     int Mx, int My, int nhx, int nhy, int K, int L, int fb_k, double2 *__restrict__ axis_part) {
+  __shared__ double2 abuf[kAxisBigLds];
   if (big_narrow(Mx, My))
     gen_axis_big_body<true>(x, y, words, V, ax_chunk, wx, wy, Mx, My, nhx, nhy, K, L, fb_k,
-                            axis_part, blockIdx.x, blockIdx.y);
+                            axis_part, blockIdx.x, blockIdx.y, abuf);
   else
     gen_axis_big_body<false>(x, y, words, V, ax_chunk, wx, wy, Mx, My, nhx, nhy, K, L, fb_k,
-                             axis_part, blockIdx.x, blockIdx.y);
+                             axis_part, blockIdx.x, blockIdx.y, abuf);
 }
 
 hipError_t launch_gen_side(const FwdPlan &p, const int32_t *x, const int32_t *y,
@@ -1743,6 +1782,7 @@ __global__ __launch_bounds__(256) void k_gbatch_side(const GBatchClip *__restric
 // direct sums of a two-level clip
 __global__ __launch_bounds__(256) void k_gbatch_axis(const GBatchClip *__restrict__ clips,
                                                      const int4 *__restrict__ desc) {
+  __shared__ double2 abuf[kAxisBigLds];
   const int4 d = desc[blockIdx.x];
   const GBatchClip &c = clips[d.x];
   if (d.y == 0)
@@ -1750,10 +1790,10 @@ __global__ __launch_bounds__(256) void k_gbatch_axis(const GBatchClip *__restric
                    c.My);
   else if (big_narrow(c.Mx, c.My))
     gen_axis_big_body<true>(c.x, c.y, c.words, c.V, c.ax_chunk, c.w64x, c.w64y, c.Mx, c.My,
-                            c.nhx, c.nhy, c.K, c.L, c.ax_fb_k, c.axis_part, d.z, d.w);
+                            c.nhx, c.nhy, c.K, c.L, c.ax_fb_k, c.axis_part, d.z, d.w, abuf);
   else
     gen_axis_big_body<false>(c.x, c.y, c.words, c.V, c.ax_chunk, c.w64x, c.w64y, c.Mx, c.My,
-                             c.nhx, c.nhy, c.K, c.L, c.ax_fb_k, c.axis_part, d.z, d.w);
+                             c.nhx, c.nhy, c.K, c.L, c.ax_fb_k, c.axis_part, d.z, d.w, abuf);
 }
 
 __global__ __launch_bounds__(256) void k_gbatch_epilogue(const GBatchClip *__restrict__ clips,
