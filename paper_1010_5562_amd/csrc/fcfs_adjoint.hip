@@ -252,52 +252,72 @@ __global__ __launch_bounds__(256) void k_adj_axis(const int32_t *__restrict__ x,
                                                   int nhy = 0,
                                                   const float *__restrict__ part = nullptr,
                                                   int nslots = 0, int64_t vpad = 0) {
-  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  // 64 corners per workgroup, four waves: wave r takes the frequencies
+  // f = r + 1 + 4 i of every corner (the coefficient loads stay uniform), its
+  // twiddle stepping by e(4 t) and re-read from the exact table every eighth
+  // step; the four partial sums meet in LDS in a fixed order
+  __shared__ double4 red[4][64];
+  const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int64_t v = (int64_t)blockIdx.x * 64 + lane;
   const double dMx = (double)Mx, dMy = (double)My;
-  if (v >= V) return;
-  const uint4 c = packed[v];
-  const double sg = c.z ? -1.0 : 1.0;
-  const double xv = (double)x[v], yv = (double)y[v];
+  const bool live = v < V;
+  const int64_t vv = live ? v : 0;
+  const uint4 c = packed[vv];
   const double2 *coef_s = coef + (K + L + 1);  // scaled by 1/(2 pi f)
   double sx1 = 0.0, sx2 = 0.0;  // sum Re[P e(kx)],  sum Re[P j/(2 pi k) e(kx)]
-  {
+  if (live) {
     const uint32_t ph = GEN ? c.x : c.x >> 3;
-    const double2 w1 = BIG ? big_entry64(w64, nhx, ph) : w64[ph];
-    double2 w = w1;
-    // unrolled so that the uniform coefficient loads of 8 steps are issued together
-#pragma unroll 8
-    for (int k = 1; k <= kmax; ++k) {
-      if ((k & 31) == 0)
-        w = BIG ? big_entry64(w64, nhx, big_phase((uint32_t)k, ph, dMx, 1.0 / dMx))
-            : GEN ? w64[((uint32_t)k * ph) % (uint32_t)Mx]
-                  : w64[((uint32_t)k * ph) & (uint32_t)(kTabN - 1)];
+    auto tw = [&](uint32_t k) {
+      return BIG ? big_entry64(w64, nhx, big_phase(k, ph, dMx, 1.0 / dMx))
+           : GEN ? w64[(k * ph) % (uint32_t)Mx]
+                 : w64[(k * ph) & (uint32_t)(kTabN - 1)];
+    };
+    const double2 w4 = tw(4u);
+    double2 w = w4;
+#pragma unroll 4
+    for (int k = r + 1, i = 0; k <= kmax; k += 4, ++i) {
+      if ((i & 7) == 0) w = tw((uint32_t)k);
       const double2 p = coef[k - 1], ps = coef_s[k - 1];
       // e(kx) = w.x - j w.y;  Re[j z] = -Im z
       sx1 += p.x * w.x + p.y * w.y;
       sx2 -= ps.y * w.x - ps.x * w.y;
-      const double nx = w.x * w1.x - w.y * w1.y, ny = w.x * w1.y + w.y * w1.x;
+      const double nx = w.x * w4.x - w.y * w4.y, ny = w.x * w4.y + w.y * w4.x;
       w = make_double2(nx, ny);
     }
   }
   double sy1 = 0.0, sy2 = 0.0;  // sum Re[Q e(ly)],  sum Re[Q j/(2 pi l) e(ly)]
-  {
+  if (live) {
     const double2 *W = GEN ? wy : w64;
     const uint32_t ph = GEN ? c.y : c.y >> 3;
-    const double2 w1 = BIG ? big_entry64(W, nhy, ph) : W[ph];
-    double2 w = w1;
-#pragma unroll 8
-    for (int l = 1; l <= lmax; ++l) {
-      if ((l & 31) == 0)
-        w = BIG ? big_entry64(W, nhy, big_phase((uint32_t)l, ph, dMy, 1.0 / dMy))
-            : GEN ? W[((uint32_t)l * ph) % (uint32_t)My]
-                  : W[((uint32_t)l * ph) & (uint32_t)(kTabN - 1)];
+    auto tw = [&](uint32_t l) {
+      return BIG ? big_entry64(W, nhy, big_phase(l, ph, dMy, 1.0 / dMy))
+           : GEN ? W[(l * ph) % (uint32_t)My]
+                 : W[(l * ph) & (uint32_t)(kTabN - 1)];
+    };
+    const double2 w4 = tw(4u);
+    double2 w = w4;
+#pragma unroll 4
+    for (int l = r + 1, i = 0; l <= lmax; l += 4, ++i) {
+      if ((i & 7) == 0) w = tw((uint32_t)l);
       const double2 q = coef[K + l - 1], qs = coef_s[K + l - 1];
       sy1 += q.x * w.x + q.y * w.y;
       sy2 -= qs.y * w.x - qs.x * w.y;
-      const double nx = w.x * w1.x - w.y * w1.y, ny = w.x * w1.y + w.y * w1.x;
+      const double nx = w.x * w4.x - w.y * w4.y, ny = w.x * w4.y + w.y * w4.x;
       w = make_double2(nx, ny);
     }
   }
+  red[r][lane] = make_double4(sx1, sx2, sy1, sy2);
+  __syncthreads();
+  if (!live || r != 0) return;
+  {
+    const double4 a = red[0][lane], b = red[1][lane], d = red[2][lane], e = red[3][lane];
+    sx1 = (a.x + b.x) + (d.x + e.x);
+    sx2 = (a.y + b.y) + (d.y + e.y);
+    sy1 = (a.z + b.z) + (d.z + e.z);
+    sy2 = (a.w + b.w) + (d.w + e.w);
+  }
+  const double sg = c.z ? -1.0 : 1.0;
+  const double xv = (double)x[v], yv = (double)y[v];
   const double g00 = coef[K + L].x;
   float fx = (float)(sg * (yv * dcf * sx1 + sy2 + yv * g00 * dcf));
   float fy = (float)(sg * (sx2 + xv * dcf * sy1 + xv * g00 * dcf));
@@ -851,7 +871,7 @@ hipError_t launch_adjoint(const AdjPlan &a, const int32_t *x, const int32_t *y, 
     }
 #undef FCFS_REGB
     if (main_ev) (void)hipEventRecord(main_ev[1], st);
-    hipLaunchKernelGGL(k_adj_axis<false>, dim3((unsigned)((a.V + 255) / 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_adj_axis<false>, dim3((unsigned)((a.V + 63) / 64)), dim3(256), 0, st,
                        x, y, packed, t.w64, coef, a.V, a.K, a.L, a.kmax, a.lmax, a.dcf, gx, gy,
                        nullptr, 0, 0, 0, 0, rpart, 4 * adj_regb_nbw(a.regb_nks) * a.regb_sets,
                        a.vpad);
@@ -860,15 +880,15 @@ hipError_t launch_adjoint(const AdjPlan &a, const int32_t *x, const int32_t *y, 
   // axis and DC parts first: they write gx, gy
   if (a.V > 0) {
     if (gen && a.big)
-      hipLaunchKernelGGL((k_adj_axis<true, true>), dim3((unsigned)((a.V + 255) / 256)), dim3(256),
+      hipLaunchKernelGGL((k_adj_axis<true, true>), dim3((unsigned)((a.V + 63) / 64)), dim3(256),
                          0, st, x, y, packed, gtab->w64x, coef, a.V, a.K, a.L, a.kmax, a.lmax,
                          a.dcf, gx, gy, gtab->w64y, a.Mx, a.My, a.nhx, a.nhy);
     else if (gen)
-      hipLaunchKernelGGL(k_adj_axis<true>, dim3((unsigned)((a.V + 255) / 256)), dim3(256), 0, st,
+      hipLaunchKernelGGL(k_adj_axis<true>, dim3((unsigned)((a.V + 63) / 64)), dim3(256), 0, st,
                          x, y, packed, gtab->w64x, coef, a.V, a.K, a.L, a.kmax, a.lmax, a.dcf, gx,
                          gy, gtab->w64y, a.Mx, a.My);
     else
-      hipLaunchKernelGGL(k_adj_axis<false>, dim3((unsigned)((a.V + 255) / 256)), dim3(256), 0, st,
+      hipLaunchKernelGGL(k_adj_axis<false>, dim3((unsigned)((a.V + 63) / 64)), dim3(256), 0, st,
                          x, y, packed, t.w64, coef, a.V, a.K, a.L, a.kmax, a.lmax, a.dcf, gx, gy,
                          nullptr, 0, 0);
   }
