@@ -142,8 +142,8 @@ fcfs_status fcfs_forward(fcfs_handle *h, const fcfs_clip *c, fcfs_precision p, v
 /* fcfs_forward without a workspace argument, for callers that cannot
  * allocate device memory (serving loops and harnesses that forbid it): the
  * work runs in a scratch array the library holds on each device it runs on,
- * 80 MiB, for the life of the process (the precision clip of 200k corners at
- * T = 8192, K = L = 511 needs 72 MiB).  Same arguments, kernels and results as
+ * 96 MiB, for the life of the process (the precision clip of 200k corners at
+ * T = 8192, K = L = 511 needs 84 MiB).  Same arguments, kernels and results as
  * fcfs_forward; a clip whose workspace (fcfs_workspace_size) exceeds the
  * scratch is refused with FCFS_ERR_WORKSPACE.  The call allocates nothing:
  * no hipMalloc or hipFree, no allocating library routine.  Every call on a

@@ -113,7 +113,7 @@ struct fcfs_step_plan {
 // (one per device) is looked up with hipGetSymbolAddress at fcfs_create, with
 // that device current, and kept in g_scratch; kernels get that address.
 // ---------------------------------------------------------------------------
-constexpr size_t kScratchBytes = (size_t)80 << 20;
+constexpr size_t kScratchBytes = (size_t)96 << 20;
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
@@ -350,7 +350,10 @@ void free_tables(Tables &t) {
 // ---------------------------------------------------------------------------
 constexpr int kMaxFreq = 4095;  // |k|, |l| cut-off limit (phases stay below 2^29)
 constexpr int kCUs = 256;  // compute units of the target GPU (MI355X)
-constexpr int kGuardBlocks = 64;       // most corner ranges of the guard region
+// Most corner ranges of the guard region: with a span of one only the core
+// group works, one block per range, so the ranges are kept short (at least 512
+// corners) for the side stream to finish beside the contraction.
+constexpr int kGuardBlocks = 256;
 constexpr int kBatchGuardBlocks = 16;  // the same per clip of a batch
 
 int kbucket(int K) {
