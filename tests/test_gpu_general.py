@@ -536,3 +536,28 @@ def test_general_batch_many_periods_and_rewritten_corners(P, oracle_lib):
             assert e <= TOL["bf16"], (i, e)
             assert int(b.area[i].item()) == area
     b.close()
+
+
+@pytest.mark.parametrize("K,L", [(600, 300), (200, 130)])
+def test_general_two_level_axes_wide_bands(P, oracle_lib, K, L):
+    # periods past 8192 grid units with bands of 512-frequency (K = 600: two
+    # blocks, the second starting at f0 = 512) and 256-frequency axis blocks:
+    # every axis coefficient F[k, 0], F[0, l] and a sample of the rest against
+    # the oracle
+    Nx, Ny, F = 1500, 1100, 5
+    X, off = _fine_grid_clip(47, Nx, Ny, F, K, L, 40)
+    xy = X.astype(np.float64) / 2 ** F
+    rng = np.random.default_rng(11)
+    kk = np.concatenate([np.arange(1, K + 1), -np.arange(1, K + 1), np.zeros(L, int),
+                         np.zeros(L, int), rng.integers(-K, K + 1, 400)])
+    ll = np.concatenate([np.zeros(K, int), np.zeros(K, int), np.arange(1, L + 1),
+                         -np.arange(1, L + 1), rng.integers(-L, L + 1, 400)])
+    ref = oracle_lib.cfs_points_general(xy, off, Nx, Ny, kk, ll, frac_bits=F)
+    f00 = abs(oracle_lib.cfs_points_general(xy, off, Nx, Ny, [0], [0], frac_bits=F)[0])
+    _say(f"two-level axes {Nx}x{Ny} F={F} K={K} L={L}: {off.size - 1} polygons")
+    for prec in ("fp32", "bf16"):
+        Fg, _ = _gpu(P, X, off, Nx, Ny, K, L, F, prec)
+        e = np.abs(Fg[kk + K, ll + L] - ref) / f00
+        w = int(np.argmax(e))
+        _say(f"  {prec}: max err/|F00| = {e[w]:.3e} at ({kk[w]},{ll[w]})")
+        assert e[w] <= TOL[prec]
