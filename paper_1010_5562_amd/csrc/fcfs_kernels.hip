@@ -504,8 +504,10 @@ hipError_t launch_side(const FwdPlan &p, const int32_t *x, const int32_t *y, con
 }
 
 // General-tile side-stream work: histogram blocks, guard blocks, then the
-// axis DFTs of both periods.
-__global__ __launch_bounds__(256) void k_gen_side(const int32_t *__restrict__ x,
+// axis DFTs of both periods.  Sized for six workgroups per CU (at most 80
+// registers per lane): the pipelined general contraction holds 432 of the
+// 512, so the side blocks can run beside it rather than after it.
+__global__ __launch_bounds__(256, 6) void k_gen_side(const int32_t *__restrict__ x,
                                                   const int32_t *__restrict__ y,
                                                   const uint4 *__restrict__ packed, int64_t V,
                                                   unsigned long long *__restrict__ hist, int nh,
