@@ -466,7 +466,10 @@ __device__ __forceinline__ void guard_body(const uint4 *__restrict__ packed,
 // Side-stream kernel of one clip: blocks [0, nh) bin the axis histograms,
 // blocks [nh, nh + kGuardGroups g_chunks) compute the guard region (slot
 // group b / g_chunks over corner range b % g_chunks: the core group first).
-__global__ __launch_bounds__(256) void k_side(const int32_t *__restrict__ x,
+// At most 80 registers per lane (six workgroups per CU), so that its blocks
+// fit beside the contraction: the interleaved kernel holds 424, two
+// workgroups of the two-waves-per-SIMD kernel 432.
+__global__ __launch_bounds__(256, 6) void k_side(const int32_t *__restrict__ x,
                                               const int32_t *__restrict__ y,
                                               const uint4 *__restrict__ packed, int64_t V,
                                               int shift, unsigned long long *__restrict__ hist,
