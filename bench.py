@@ -803,7 +803,7 @@ def main() -> int:
     if adj["adjoint_gemm_ms"]:
         tf = aflops / (adj["adjoint_gemm_ms"] * 1e-3) / 1e12
         adj["roofline"] = {"bound": "mfma",
-                           "kernel": "k_adj_gemm_res<bf16> (main term, W resident in LDS)",
+                           "kernel": "k_adj_gemm_regb<bf16> (main term, W resident in registers)",
                            "achieved": tf, "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
                            "frac": tf / PEAK_TFLOPS["bf16"], "flops_per_launch": aflops}
     if adj["adjoint_ms"]:
