@@ -188,7 +188,7 @@ def main() -> int:
         print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 3}))
         return 0
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no "
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the library has no "
               "multi-GPU path.", file=sys.stderr)
         return 2
 
