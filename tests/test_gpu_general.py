@@ -440,7 +440,8 @@ def test_general_two_level_adjoint_limit(P):
     assert ei.value.status == -4
 
 
-def test_general_batch_graph(P, oracle_lib):
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "fp32"])
+def test_general_batch_graph(P, oracle_lib, prec):
     # clips of different periods, grid steps and cut-offs (two of them past
     # 8192 grid units) in one plan: the oracle agrees with the first pass, the
     # single calls agree with it to the precision's bound (the batch chooses
@@ -460,20 +461,20 @@ def test_general_batch_graph(P, oracle_lib):
         clips.append((x, y, s, Nx, Ny, K, L, F))
         refs.append(oracle_lib.cfs_grid_general(X.astype(np.float64) / 2 ** F, off, Nx, Ny, K, L,
                                                 frac_bits=F))
-    _say(f"general batch of {len(clips)} clips (graph)")
-    b = P.GeneralBatch(clips, precision="bf16")
+    _say(f"general batch of {len(clips)} clips (graph), {prec}")
+    b = P.GeneralBatch(clips, precision=prec)
     torch.cuda.synchronize()
     eager = [f.cpu().numpy().copy() for f in b.F]
     for i, (x, y, s, Nx, Ny, K, L, F) in enumerate(clips):
-        Fs, a = P.forward_general(x, y, s, Nx, Ny, K, L, frac_bits=F, precision="bf16")
+        Fs, a = P.forward_general(x, y, s, Nx, Ny, K, L, frac_bits=F, precision=prec)
         torch.cuda.synchronize()
         ref, area = refs[i]
         d = float(np.max(np.abs(Fs.cpu().numpy().astype(np.complex128) - eager[i]))
                   / abs(ref[K, L]))
-        assert d <= TOL["bf16"], (i, d)
+        assert d <= TOL[prec], (i, d)
         assert int(b.area[i].item()) == area
         e = float(np.max(np.abs(eager[i].astype(np.complex128) - ref)) / abs(ref[K, L]))
-        assert e <= TOL["bf16"], (i, e)
+        assert e <= TOL[prec], (i, e)
     for _ in range(2):
         for f in b.F:
             f.zero_()
