@@ -58,6 +58,24 @@ def test_adjoint_random_cotangent(P, oracle_lib, prec):
     assert e <= GTOL[prec]
 
 
+@pytest.mark.parametrize("K,L", [(25, 110), (120, 80)])
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_adjoint_register_resident_step_counts(P, oracle_lib, K, L, prec):
+    # the register-resident main term for k bands of 32 and 128 rows (two and
+    # eight 16-row steps per column block, three and two chunks of 32
+    # frequencies per set), with chunk counts (4 and 3) that leave a partial
+    # set
+    T = 1024
+    clip = synth.clip(43, T, K, L, n_polygons=40)
+    _say(f"adjoint V={clip.n_vertices} T={T} K={K} L={L} prec={prec}")
+    G = _rand_G(K, L, 3)
+    want = oracle_lib.edge_grad(clip.xy, clip.off, T, K, L, G.astype(np.complex64))
+    got = _gpu_edge_grad(P, clip, G, prec)
+    e = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+    _say(f"  err/max|g| = {e:.3e}")
+    assert e <= GTOL[prec]
+
+
 def test_adjoint_band_matches_full(P):
     T, K, L = 1024, 64, 64
     clip = synth.clip(42, T, K, L, n_polygons=60)
