@@ -202,6 +202,27 @@ def test_pupil_step_workspace_size(lib):
                                               ctypes.byref(n)) == -1
 
 
+def test_haar_workspace_size(lib):
+    from paper_1010_5562_amd._lib import FcfsHaarClip
+
+    def size(M, Nx=4096, Ny=4096, J=12):
+        c = FcfsHaarClip(None, None, None, None, 10 * M, M, Nx, Ny, J, None, None, None)
+        n = ctypes.c_size_t(0)
+        st = lib.fcfs_haar_workspace_size(ctypes.byref(c), ctypes.byref(n))
+        return st, n.value
+
+    # control words, 64 copies of the 64 x 64 int64 coarse block, a task count
+    # per polygon and the extra-task list (at least 4096 entries)
+    st, n0 = size(0)
+    assert st == 0 and n0 >= 256 + 64 * 64 * 64 * 8 + 8 * 4096
+    st, n1 = size(100000)
+    assert st == 0 and n1 >= 256 + 64 * 64 * 64 * 8 + 4 * 100000 + 8 * 100000
+    # the size depends on M only
+    assert size(100000, 1024, 512, 9)[1] == n1
+    assert size(10, 24, 24, 4)[0] == -1      # 2^J does not divide the tile
+    assert size(10, 8192, 8192, 14)[0] == -4  # J past 13
+
+
 def test_null_handle_is_rejected(lib):
     from paper_1010_5562_amd import _lib
 
