@@ -34,7 +34,10 @@
  *  - The device path trusts the corner data it is given: s_v in {+1,-1},
  *    corners polygon-contiguous (accuracy depends on it), |x|,|y| < 2^30.
  *  - The tile period T is a power of two in [2, 8192]; K, L >= 0.
- *  - Threading: one handle per host thread.
+ *  - Threading: calls on one handle must not overlap in time.  A handle keeps
+ *    no per-thread state, so it may pass from one host thread to another
+ *    between calls (e.g. a backward pass run by another thread while the
+ *    caller waits).  Different handles may be used concurrently.
  */
 #ifndef FCFS_H_
 #define FCFS_H_
@@ -103,6 +106,13 @@ typedef struct {
  * e^{j 2 pi p / 8192}, p = 0..8191, in FP64, FP32 and bf16/fp16 hi+lo. */
 fcfs_status fcfs_create(fcfs_handle **h, int device, void *hip_stream);
 fcfs_status fcfs_destroy(fcfs_handle *h);
+/* Makes `hip_stream` the handle's stream for later calls.  The new stream
+ * waits (an event, no host wait) for everything enqueued on the previous one,
+ * so a workspace, an output or a table used before the switch may be reused
+ * after it.  The previous stream must still exist.  Neither stream may be
+ * capturing a graph for this order to be taken (the entry points refuse a
+ * capturing stream anyway).  Errors: FCFS_ERR_INVALID_ARG (NULL handle),
+ * FCFS_ERR_DEVICE (a failed HIP call). */
 fcfs_status fcfs_set_stream(fcfs_handle *h, void *hip_stream);
 
 /* (host) Polygon loops -> signed corner list and edge map.

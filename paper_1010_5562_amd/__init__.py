@@ -121,7 +121,13 @@ def plan_info(V: int, T: int, K: int, L: int, precision="bf16") -> dict:
 
 
 class Handle:
-    """Owns an ``fcfs_handle`` (twiddle tables) on one device."""
+    """Owns an ``fcfs_handle`` (twiddle tables) on one device.
+
+    Each call enqueues on torch's current stream; on a change of stream the
+    library orders the new stream after the old one, so the cached workspace
+    is never used by two streams at once.  Calls through one handle must not
+    overlap in time (autograd's backward thread uses it while the caller
+    waits)."""
 
     def __init__(self, device=None):
         import torch
@@ -186,6 +192,11 @@ class Handle:
         import torch
 
         if self._ws is None or self._ws.numel() < nbytes:
+            if self._ws is not None:
+                # the old buffer returns to the pool of the stream it was
+                # allocated on; work already enqueued on the current one may
+                # still read it
+                self._ws.record_stream(torch.cuda.current_stream(self.device))
             self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
         return self._ws
 

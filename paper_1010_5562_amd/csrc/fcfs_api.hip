@@ -39,6 +39,8 @@ struct fcfs_handle {
   // back into `stream` with events; default priority like every stream here
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // orders a new stream after the work enqueued on the previous one
+  hipEvent_t ev_switch = nullptr;
   // autotuned choices: forward tile per (precision, K bucket, V bucket) and
   // the persistent batch kernel's tile and corners per work item
   struct Tune {
@@ -1077,7 +1079,8 @@ fcfs_status fcfs_create(fcfs_handle **out, int device, void *hip_stream) {
     hipError_t e2;
     if ((e2 = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking)) ||
         (e2 = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming)) ||
-        (e2 = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming)))
+        (e2 = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming)) ||
+        (e2 = hipEventCreateWithFlags(&h->ev_switch, hipEventDisableTiming)))
       st = hip_fail(h, e2, "side stream");
   }
   if (st) {
@@ -1087,6 +1090,7 @@ fcfs_status fcfs_create(fcfs_handle **out, int device, void *hip_stream) {
     }
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->ev_switch) (void)hipEventDestroy(h->ev_switch);
     if (h->side) (void)hipStreamDestroy(h->side);
     free_tables(h->tab);
     delete h;
@@ -1118,6 +1122,7 @@ fcfs_status fcfs_destroy(fcfs_handle *h) {
   }
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  if (h->ev_switch) (void)hipEventDestroy(h->ev_switch);
   free_tables(h->tab);
   for (auto &t : h->gen_tabs) {
     (void)hipFree(t.w64);
@@ -1131,7 +1136,21 @@ fcfs_status fcfs_destroy(fcfs_handle *h) {
 
 fcfs_status fcfs_set_stream(fcfs_handle *h, void *hip_stream) {
   if (!h) return fail(nullptr, FCFS_ERR_INVALID_ARG, "handle is NULL");
-  h->stream = (hipStream_t)hip_stream;
+  hipStream_t ns = (hipStream_t)hip_stream;
+  if (ns == h->stream) return FCFS_OK;
+  // Everything enqueued on the previous stream (period tables built on first
+  // use, the caller's workspace) completes before work on the new one. A
+  // capturing stream takes no library work, so no order is needed across it.
+  hipError_t e;
+  hipStreamCaptureStatus a = hipStreamCaptureStatusNone, b = hipStreamCaptureStatusNone;
+  if ((e = hipSetDevice(h->device)) || (e = hipStreamIsCapturing(h->stream, &a)) ||
+      (e = hipStreamIsCapturing(ns, &b)))
+    return hip_fail(h, e, "fcfs_set_stream");
+  if (a == hipStreamCaptureStatusNone && b == hipStreamCaptureStatusNone &&
+      ((e = hipEventRecord(h->ev_switch, h->stream)) ||
+       (e = hipStreamWaitEvent(ns, h->ev_switch, 0))))
+    return hip_fail(h, e, "fcfs_set_stream");
+  h->stream = ns;
   return FCFS_OK;
 }
 

@@ -1,5 +1,6 @@
 """Error paths and lifetimes at the C ABI: workspaces that are too small or
-misaligned, a stream the caller is capturing, plans that outlive their
+misaligned, a stream the caller is capturing, a change of stream between
+calls on one handle, plans that outlive their
 handle, general-tile batches past the handle's table cache, and replays that
 recompute from rewritten corners.  Every case calls the library through the
 C ABI (ctypes) on cuda:0; the error cases enqueue nothing on the device."""
@@ -86,6 +87,58 @@ def test_external_capture_is_refused(P):
     F1, _ = P.forward(x, y, s, clip.T, clip.K, clip.L, precision="bf16", handle=h)
     torch.cuda.synchronize()
     assert torch.equal(F0, F1)
+    h.close()
+
+
+def test_stream_switch_orders_the_handle(P):
+    # One handle and one workspace, calls alternating between two streams with
+    # no wait by the caller: a large clip on the first stream, then small ones
+    # on the second and the first again.  The switch orders the new stream
+    # after the old one, so every result equals the same call made alone (the
+    # kernels are deterministic), bit for bit.
+    big = synth.clip(84, 8192, 511, n_polygons=4000)
+    small = synth.clip(85, 2048, 100, n_polygons=200)
+    h = P.Handle()
+    ins = []
+    for c in (big, small):
+        x, y, s, _, _ = P.loops_to_corners(c.xy, c.off)
+        ins.append(tuple(torch.as_tensor(a).cuda() for a in (x, y, s)) + (c,))
+    need = max(P.workspace_size(t[0].numel(), t[3].T, t[3].K, t[3].L, "bf16") for t in ins)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    out = [torch.empty((2 * t[3].K + 1, 2 * t[3].L + 1), dtype=torch.complex64, device="cuda")
+           for t in (ins[0], ins[1], ins[1], ins[0])]
+    area = torch.empty(4, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+
+    def call(i, t, stream):
+        P.check(h.lib.fcfs_set_stream(h.ptr, ctypes.c_void_p(stream.cuda_stream)), h.ptr)
+        x, y, s, c = t
+        cl = P._clip(x, y, s, x.numel(), c.T, c.K, c.L, out[i], area[i:i + 1])
+        P.check(h.lib.fcfs_forward(h.ptr, ctypes.byref(cl), P.PRECISIONS["bf16"],
+                                   ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(need)), h.ptr)
+
+    _say("stream switch: big on s1, small on s2, small on s1, big on s2")
+    for i, (t, st) in enumerate(((ins[0], s1), (ins[1], s2), (ins[1], s1), (ins[0], s2))):
+        call(i, t, st)
+    torch.cuda.synchronize()
+    got = [o.clone() for o in out]
+    for i, t in enumerate((ins[0], ins[1], ins[1], ins[0])):
+        call(i, t, s1)
+        torch.cuda.synchronize()
+        assert torch.equal(got[i], out[i]), i
+    # the binding: its cached workspace grows on one stream while the other
+    # stream's call may still read the old one
+    h2 = P.Handle()
+    res = []
+    for t, st in ((ins[1], s1), (ins[0], s2), (ins[1], s1)):
+        x, y, s, c = t
+        with torch.cuda.stream(st):
+            res.append(P.forward(x, y, s, c.T, c.K, c.L, precision="bf16", handle=h2)[0])
+    torch.cuda.synchronize()
+    assert torch.equal(res[0], got[1]) and torch.equal(res[2], got[1])
+    assert torch.equal(res[1], got[0])
+    h2.close()
     h.close()
 
 
