@@ -1861,15 +1861,18 @@ fcfs_status fcfs_pupil_step_plan(fcfs_handle *h, const int32_t *base_x, const in
 // Batch of general-tile forwards: one workspace slice per clip and one graph.
 // Split-precision batches whose clips all fit the batch kernels run one launch
 // per step over every clip (GBatchLaunch): the split counts are chosen for the
-// whole batch (about one work item per compute unit, at least
+// whole batch (about 11 work items per 16 compute units, at least
 // kGBatchItemMin corners each) and the items are dispatched longest first.
+// The compute units left over run the side stream's guard and axis blocks
+// beside the contraction (which leaves no LDS for them on its own units);
+// one item per unit, or more, was 4-12% slower on a batch of 32 tiles.
 // Other batches capture every clip's single-clip launches in sequence.
 // ---------------------------------------------------------------------------
 }  // extern "C"
 
 namespace {
 constexpr int64_t kGBatchItemMin = 256;
-constexpr int64_t kGBatchItems = kCUs;
+constexpr int64_t kGBatchItems = 11 * kCUs / 16;
 
 struct GBatchLayout {
   bool flat = false;
