@@ -487,6 +487,29 @@ __global__ __launch_bounds__(256, 6) void k_side(const int32_t *__restrict__ x,
                gpart, gspan);
 }
 
+// Adds the guard partials of every used slot over the corner ranges, in range
+// order from an FP64 zero, into range 0 (a thread owns one entry of one slot,
+// so the sum is in place).  It is the sum the epilogue would form, done at the
+// end of the side stream beside the contraction: the epilogue then reads one
+// range, not a chain of g_chunks dependent loads per entry.
+__global__ __launch_bounds__(256, 6) void k_guard_fold(double *__restrict__ gpart, int g_chunks,
+                                                       const unsigned int *__restrict__ gspan) {
+  const int j = blockIdx.x;
+  if (!guard_slot_used(j, (int)*gspan)) return;
+  double *e = gpart + (size_t)j * kGuardD + threadIdx.x;
+  double sum = 0.0;
+#pragma unroll 16
+  for (int c = 0; c < g_chunks; ++c) sum += e[(size_t)c * kGuardSlots * kGuardD];
+  e[0] = sum;
+}
+
+void launch_guard_fold(const FwdPlan &p, void *ws, hipStream_t st) {
+  char *w = (char *)ws;
+  hipLaunchKernelGGL(k_guard_fold, dim3(kGuardSlots), dim3(256), 0, st,
+                     (double *)(w + p.off_guard), p.g_chunks,
+                     (const unsigned int *)(w + p.off_gspan));
+}
+
 hipError_t launch_side(const FwdPlan &p, const int32_t *x, const int32_t *y, const double2 *w64,
                        void *ws, hipStream_t st, bool guard) {
   char *w = (char *)ws;
@@ -499,6 +522,7 @@ hipError_t launch_side(const FwdPlan &p, const int32_t *x, const int32_t *y, con
                        nh, w64, p.g_chunk, p.g_chunks, (const unsigned long long *)(w + p.off_area),
                        p.pre_blocks, p.gscale, p.gscale_alt, p.K, p.L, (double *)(w + p.off_guard),
                        (unsigned int *)(w + p.off_gspan));
+  if (ng > 0) launch_guard_fold(p, ws, st);
   if (p.K + p.L > 0)
     hipLaunchKernelGGL(k_axis_dft, dim3(p.ax_fb_k + p.ax_fb_l, p.ax_chunks), dim3(256), 0, st,
                        hist, w64, p.T, p.shift, p.K, p.L, p.ax_fb_k,
@@ -699,6 +723,7 @@ hipError_t launch_gen_side(const FwdPlan &p, const int32_t *x, const int32_t *y,
                          (const unsigned long long *)(w + p.off_area), p.pre_blocks, p.gscale,
                          p.gscale_alt, p.K, p.L, (double *)(w + p.off_guard),
                          (unsigned int *)(w + p.off_gspan));
+    if (p.K > 0 && p.L > 0) launch_guard_fold(p, ws, st);
     if (p.K + p.L > 0) {
       const int64_t ax_chunk = std::max<int64_t>(1, (p.V + p.ax_chunks - 1) / p.ax_chunks);
       hipLaunchKernelGGL(k_gen_axis_big, dim3(p.ax_fb_k + p.ax_fb_l, p.ax_chunks), dim3(256), 0,
@@ -716,6 +741,7 @@ hipError_t launch_gen_side(const FwdPlan &p, const int32_t *x, const int32_t *y,
                        (const unsigned long long *)(w + p.off_area),
                        p.pre_blocks, p.gscale, p.gscale_alt, p.K, p.L, (double *)(w + p.off_guard),
                        (unsigned int *)(w + p.off_gspan));
+  if (ng > 0) launch_guard_fold(p, ws, st);
   if (p.K + p.L > 0)
     hipLaunchKernelGGL(k_gen_axis_dft, dim3(p.ax_fb_k + p.ax_fb_l, p.ax_chunks), dim3(256), 0, st,
                        hist, wx, wy, p.Mx, p.My, p.K, p.L, p.ax_fb_k, (double2 *)(w + p.off_axis));
@@ -1404,7 +1430,8 @@ hipError_t launch_epilogue(const FwdPlan &p, const void *ws, float *F, int64_t *
                      (const float *)(w + p.off_part), p.nsplit, p.kp, p.lp, p.K, p.L, (double)p.T,
                      (const double2 *)(w + p.off_axis), p.ax_chunks,
                      (const unsigned long long *)(w + p.off_area), p.pre_blocks,
-                     (const double *)(w + p.off_guard), p.g_chunks,
+                     // the side stream folded the guard partials into range 0
+                     (const double *)(w + p.off_guard), 1,
                      (const unsigned int *)(w + p.off_gspan), o, area);
   return hipGetLastError();
 }
