@@ -279,15 +279,18 @@ struct FwdPlan {
 hipError_t launch_prepass(const FwdPlan &p, const int32_t *x, const int32_t *y, const int8_t *s,
                           uint4 *packed, unsigned long long *area_part,
                           unsigned long long *hist, hipStream_t st);
-// histograms + guard region (unless guard is false; its corner-range partials
-// are then folded into range 0), then the axis DFTs
+// histograms + guard region (unless guard is false; with large frequency
+// blocks its corner-range partials are then folded into range 0), then the
+// axis DFTs
 hipError_t launch_side(const FwdPlan &p, const int32_t *x, const int32_t *y, const double2 *w64,
                        void *ws, hipStream_t st, bool guard = true);
 // area_part: the pre-pass area partials, which let a split-bf16 plan route a
 // clip to split-fp16 (route_fp16); nullptr keeps the plan's precision.
 hipError_t launch_contract(const FwdPlan &p, const uint4 *packed, const Tables &t, float *part,
                            hipStream_t st, const unsigned long long *area_part = nullptr);
-// after launch_side or launch_gen_side: reads the folded guard partials
+// after launch_side or launch_gen_side (which fold the guard partials when
+// guard_folded(p); the epilogue then reads range 0 only)
+bool guard_folded(const FwdPlan &p);
 hipError_t launch_epilogue(const FwdPlan &p, const void *ws, float *F, int64_t *area,
                            hipStream_t st);
 // the axes and DC entries only (lattice form)

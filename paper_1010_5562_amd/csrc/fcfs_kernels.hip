@@ -487,25 +487,41 @@ __global__ __launch_bounds__(256, 6) void k_side(const int32_t *__restrict__ x,
                gpart, gspan);
 }
 
-// Adds the guard partials of every used slot over the corner ranges, in range
-// order from an FP64 zero, into range 0 (a thread owns one entry of one slot,
-// so the sum is in place).  It is the sum the epilogue would form, done at the
-// end of the side stream beside the contraction: the epilogue then reads one
-// range, not a chain of g_chunks dependent loads per entry.
+// Adds the guard partials of every used slot over the corner ranges into
+// range 0, in place.  A block takes 64 entries of one slot; wave w sums the
+// w-th quarter of the ranges in range order from an FP64 zero and the four
+// sums are added in wave order (a fixed order; four times shorter chains of
+// dependent loads than one thread per entry).  It runs at the end of the side
+// stream beside the contraction, so the epilogue reads one range.
 __global__ __launch_bounds__(256, 6) void k_guard_fold(double *__restrict__ gpart, int g_chunks,
                                                        const unsigned int *__restrict__ gspan) {
   const int j = blockIdx.x;
   if (!guard_slot_used(j, (int)*gspan)) return;
-  double *e = gpart + (size_t)j * kGuardD + threadIdx.x;
+  __shared__ double red[3][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double *e = gpart + (size_t)j * kGuardD + blockIdx.y * 64 + lane;
+  const int q = (g_chunks + 3) / 4, c0 = w * q, c1 = min(g_chunks, c0 + q);
   double sum = 0.0;
 #pragma unroll 16
-  for (int c = 0; c < g_chunks; ++c) sum += e[(size_t)c * kGuardSlots * kGuardD];
-  e[0] = sum;
+  for (int c = c0; c < c1; ++c) sum += e[(size_t)c * kGuardSlots * kGuardD];
+  if (w > 0) red[w - 1][lane] = sum;
+  __syncthreads();
+  // only wave 0 reads range 0, and it writes after its own reads
+  if (w == 0) e[0] = ((sum + red[0][lane]) + red[1][lane]) + red[2][lane];
+}
+
+// The fold pays where the contraction hides the side stream (large frequency
+// blocks); beside a short contraction (a low-pass band) the side stream is
+// the longer path and the epilogue keeps the sum (0.184 -> 0.188 ms per
+// differentiation step with the fold there, same box).
+bool guard_folded(const FwdPlan &p) {
+  return p.K > 0 && p.L > 0 && (int64_t)(p.K + 1) * (p.L + 1) >= 128 * 128;
 }
 
 void launch_guard_fold(const FwdPlan &p, void *ws, hipStream_t st) {
   char *w = (char *)ws;
-  hipLaunchKernelGGL(k_guard_fold, dim3(kGuardSlots), dim3(256), 0, st,
+  static_assert(kGuardD % 64 == 0, "64 entries per fold block");
+  hipLaunchKernelGGL(k_guard_fold, dim3(kGuardSlots, kGuardD / 64), dim3(256), 0, st,
                      (double *)(w + p.off_guard), p.g_chunks,
                      (const unsigned int *)(w + p.off_gspan));
 }
@@ -522,7 +538,7 @@ hipError_t launch_side(const FwdPlan &p, const int32_t *x, const int32_t *y, con
                        nh, w64, p.g_chunk, p.g_chunks, (const unsigned long long *)(w + p.off_area),
                        p.pre_blocks, p.gscale, p.gscale_alt, p.K, p.L, (double *)(w + p.off_guard),
                        (unsigned int *)(w + p.off_gspan));
-  if (ng > 0) launch_guard_fold(p, ws, st);
+  if (ng > 0 && guard_folded(p)) launch_guard_fold(p, ws, st);
   if (p.K + p.L > 0)
     hipLaunchKernelGGL(k_axis_dft, dim3(p.ax_fb_k + p.ax_fb_l, p.ax_chunks), dim3(256), 0, st,
                        hist, w64, p.T, p.shift, p.K, p.L, p.ax_fb_k,
@@ -723,7 +739,7 @@ hipError_t launch_gen_side(const FwdPlan &p, const int32_t *x, const int32_t *y,
                          (const unsigned long long *)(w + p.off_area), p.pre_blocks, p.gscale,
                          p.gscale_alt, p.K, p.L, (double *)(w + p.off_guard),
                          (unsigned int *)(w + p.off_gspan));
-    if (p.K > 0 && p.L > 0) launch_guard_fold(p, ws, st);
+    if (guard_folded(p)) launch_guard_fold(p, ws, st);
     if (p.K + p.L > 0) {
       const int64_t ax_chunk = std::max<int64_t>(1, (p.V + p.ax_chunks - 1) / p.ax_chunks);
       hipLaunchKernelGGL(k_gen_axis_big, dim3(p.ax_fb_k + p.ax_fb_l, p.ax_chunks), dim3(256), 0,
@@ -741,7 +757,7 @@ hipError_t launch_gen_side(const FwdPlan &p, const int32_t *x, const int32_t *y,
                        (const unsigned long long *)(w + p.off_area),
                        p.pre_blocks, p.gscale, p.gscale_alt, p.K, p.L, (double *)(w + p.off_guard),
                        (unsigned int *)(w + p.off_gspan));
-  if (ng > 0) launch_guard_fold(p, ws, st);
+  if (ng > 0 && guard_folded(p)) launch_guard_fold(p, ws, st);
   if (p.K + p.L > 0)
     hipLaunchKernelGGL(k_gen_axis_dft, dim3(p.ax_fb_k + p.ax_fb_l, p.ax_chunks), dim3(256), 0, st,
                        hist, wx, wy, p.Mx, p.My, p.K, p.L, p.ax_fb_k, (double2 *)(w + p.off_axis));
@@ -1430,8 +1446,8 @@ hipError_t launch_epilogue(const FwdPlan &p, const void *ws, float *F, int64_t *
                      (const float *)(w + p.off_part), p.nsplit, p.kp, p.lp, p.K, p.L, (double)p.T,
                      (const double2 *)(w + p.off_axis), p.ax_chunks,
                      (const unsigned long long *)(w + p.off_area), p.pre_blocks,
-                     // the side stream folded the guard partials into range 0
-                     (const double *)(w + p.off_guard), 1,
+                     // folded: the side stream added the guard ranges into range 0
+                     (const double *)(w + p.off_guard), guard_folded(p) ? 1 : p.g_chunks,
                      (const unsigned int *)(w + p.off_gspan), o, area);
   return hipGetLastError();
 }
