@@ -753,6 +753,7 @@ fcfs_status run_forward(fcfs_handle *h, const fcfs_clip *c, const FwdPlan &p, vo
   }
   if (side) {
     if ((e = hipStreamWaitEvent(h->side, h->ev_fork, 0))) return hip_fail(h, e, "fork");
+    if ((e = fcfs::launch_zero_outside(p, c->F, h->side))) return hip_fail(h, e, "zero launch");
     {
       ProfScope ps(h, kProfAxis, h->side);
       if ((e = fcfs::launch_side(p, c->x, c->y, h->tab.w64, ws, h->side)))
@@ -762,6 +763,8 @@ fcfs_status run_forward(fcfs_handle *h, const fcfs_clip *c, const FwdPlan &p, vo
         (e = hipStreamWaitEvent(h->stream, h->ev_join, 0)))
       return hip_fail(h, e, "join");
   }
+  if (!side && (e = fcfs::launch_zero_outside(p, c->F, h->stream)))
+    return hip_fail(h, e, "zero launch");
   {
     ProfScope ps(h, kProfEpilogue);
     if ((e = fcfs::launch_epilogue(p, ws, c->F, c->area, h->stream)))
@@ -1016,6 +1019,7 @@ fcfs_status run_forward_general(fcfs_handle *h, const fcfs_gclip *c, const FwdPl
   }
   if (side) {
     if ((e = hipStreamWaitEvent(h->side, h->ev_fork, 0))) return hip_fail(h, e, "fork");
+    if ((e = fcfs::launch_zero_outside(p, c->F, h->side))) return hip_fail(h, e, "zero launch");
     {
       ProfScope ps(h, kProfAxis, h->side);
       if ((e = fcfs::launch_gen_side(p, c->x, c->y, tx->w64, ty->w64, ws, h->side)))
@@ -1025,6 +1029,8 @@ fcfs_status run_forward_general(fcfs_handle *h, const fcfs_gclip *c, const FwdPl
         (e = hipStreamWaitEvent(h->stream, h->ev_join, 0)))
       return hip_fail(h, e, "join");
   }
+  if (!side && (e = fcfs::launch_zero_outside(p, c->F, h->stream)))
+    return hip_fail(h, e, "zero launch");
   {
     ProfScope ps(h, kProfEpilogue);
     if ((e = fcfs::launch_epilogue(p, ws, c->F, c->area, h->stream)))

@@ -291,6 +291,9 @@ hipError_t launch_contract(const FwdPlan &p, const uint4 *packed, const Tables &
 // after launch_side or launch_gen_side (which fold the guard partials when
 // guard_folded(p); the epilogue then reads range 0 only)
 bool guard_folded(const FwdPlan &p);
+// the band forward's entries outside the computed band (KO > K or LO > L):
+// zeroed before the epilogue writes the band, on any stream ordered before it
+hipError_t launch_zero_outside(const FwdPlan &p, float *F, hipStream_t st);
 hipError_t launch_epilogue(const FwdPlan &p, const void *ws, float *F, int64_t *area,
                            hipStream_t st);
 // the axes and DC entries only (lattice form)

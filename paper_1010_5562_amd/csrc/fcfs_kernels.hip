@@ -1433,15 +1433,19 @@ __global__ __launch_bounds__(256) void k_zero_grid(float2 *__restrict__ F, int64
     F[i] = make_float2(0.0f, 0.0f);
 }
 
-hipError_t launch_epilogue(const FwdPlan &p, const void *ws, float *F, int64_t *area,
-                           hipStream_t st) {
-  const char *w = (const char *)ws;
-  const OutGrid o{(float2 *)F, p.KO, p.LO, p.r2, p.eg, p.eax, p.eay, p.edc};
+hipError_t launch_zero_outside(const FwdPlan &p, float *F, hipStream_t st) {
   if (p.KO > p.K || p.LO > p.L) {
     const int64_t n = (2 * (int64_t)p.KO + 1) * (2 * (int64_t)p.LO + 1);
     hipLaunchKernelGGL(k_zero_grid, dim3((unsigned)std::min<int64_t>(2048, (n + 255) / 256)),
                        dim3(256), 0, st, (float2 *)F, n);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_epilogue(const FwdPlan &p, const void *ws, float *F, int64_t *area,
+                           hipStream_t st) {
+  const char *w = (const char *)ws;
+  const OutGrid o{(float2 *)F, p.KO, p.LO, p.r2, p.eg, p.eax, p.eay, p.edc};
   hipLaunchKernelGGL(k_epilogue, dim3(epilogue_block_count(p.K, p.L)), dim3(256), 0, st,
                      (const float *)(w + p.off_part), p.nsplit, p.kp, p.lp, p.K, p.L, (double)p.T,
                      (const double2 *)(w + p.off_axis), p.ax_chunks,
