@@ -53,8 +53,12 @@ constexpr int kHaarStack = 3072;
 // overrun it.
 constexpr int kHaarStageCorners = 512;
 constexpr int kHaarStage = kHaarStageCorners;
-// Workgroups of one wave; at 20 KB of LDS each, eight fit on a CU.
-constexpr int kHaarWgPerCU = 8;
+// Workgroups of one wave; at 20 KB of LDS each, eight fit on a CU.  The grid
+// holds twice that many: a workgroup takes tasks blockIdx, blockIdx + grid,
+// ..., so the larger grid hands the tasks out in finer shares as workgroups
+// finish (layout clip, J = 12: 8 per CU 139 us, 16 per CU 129 us, 32 or 64
+// per CU no faster).
+constexpr int kHaarWgPerCU = 16;
 constexpr int kCUs = 256;
 // Levels j < kHaarCoarse (the pyramid's top-left kHaarCoarseSide square,
 // scaling coefficient included) are summed in kHaarReplicas copies of that
@@ -196,8 +200,10 @@ __global__ void k_haar_reset(unsigned long long *__restrict__ U, int64_t n,
 // subtrees; a polygon whose estimated work exceeds kHaarTaskPairs cell-corner
 // pairs is walked by n tasks: every task refines the cells above L0 (only
 // task 0 emits their coefficients), and task t keeps the L0 cells whose hash
-// is t mod n.  The integer sums do not depend on the partition.
-constexpr int kHaarSplitCell = 256;
+// is t mod n.  The integer sums do not depend on the partition.  Split cells
+// of 128 units balance the layout clip's walk better than 256 (148 -> 139 us
+// at 8 workgroups per CU; 512: 168 us; 64: as 128).
+constexpr int kHaarSplitCell = 128;
 constexpr int64_t kHaarTaskPairs = 16384;
 constexpr int kHaarMaxSplit = 64;
 
